@@ -1,0 +1,240 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks one oracle function against something other than itself:
+a closed form, an invariant, brute force on a tiny input, a special case that
+reduces to a textbook result, or the paper's exact-recovery claims.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+from oracle import altgdmin_oracle as O
+from paper_2311_03824_amd import instances as I
+
+
+def _small(n=40, q=12, m=24, r=3, rho=3, seed=7, **kw):
+    inst = I.make_instance(n, q, m, r, rho, seed, **kw)
+    return inst, inst.A64(), inst.Y64
+
+
+# ---------------------------------------------------------------- HardThreshold
+
+def _ht_brute(v, rho):
+    """The unique rho-subset T with |v_j| > |v_l| or (equal and j < l) for all j in T, l not in T."""
+    n = len(v)
+    found = []
+    for T in itertools.combinations(range(n), rho):
+        Ts = set(T)
+        ok = all((abs(v[j]) > abs(v[l])) or (abs(v[j]) == abs(v[l]) and j < l)
+                 for j in Ts for l in range(n) if l not in Ts)
+        if ok:
+            found.append(T)
+    assert len(found) == 1
+    return np.array(found[0], dtype=np.int64)
+
+
+def test_hard_threshold_brute_force_random():
+    rng = np.random.default_rng(1)
+    for trial in range(200):
+        n = rng.integers(1, 9)
+        rho = rng.integers(0, n + 1)
+        # small integer values force many magnitude ties, with both signs and zeros
+        v = rng.integers(-3, 4, size=n).astype(np.float64)
+        dense, idx = O.hard_threshold(v[None, :], rho)
+        T = _ht_brute(v, rho)
+        assert np.array_equal(idx[0], T)
+        ref = np.zeros(n)
+        ref[T] = v[T]
+        assert np.array_equal(dense[0], ref)
+
+
+def test_hard_threshold_hand_ties():
+    v = np.array([[1.0, -3.0, 3.0, 0.0, -1.0, 2.0]])
+    assert O.hard_threshold(v, 1)[1].tolist() == [[1]]           # -3 and 3 tie: lower index
+    assert O.hard_threshold(v, 2)[1].tolist() == [[1, 2]]
+    assert O.hard_threshold(v, 4)[1].tolist() == [[0, 1, 2, 5]]  # 1 and -1 tie at |1|: index 0
+    assert O.hard_threshold(v, 6)[1].tolist() == [[0, 1, 2, 3, 4, 5]]
+    z = np.array([[0.0, -0.0, 0.0]])
+    assert O.hard_threshold(z, 2)[1].tolist() == [[0, 1]]        # -0 equals +0
+    with pytest.raises(ValueError):
+        O.hard_threshold(np.array([[1.0, np.nan]]), 1)
+
+
+# ---------------------------------------------------------------- projector and LS
+
+def test_projector_invariants():
+    inst, A, Y = _small()
+    U = O.qr_pos(np.random.default_rng(3).standard_normal((inst.n, inst.r)))[0]
+    P, G = O.projector_parts(A, U)
+    V = np.random.default_rng(4).standard_normal((inst.q, inst.m))
+    PV = O.project_out(P, G, V)
+    assert np.allclose(O.project_out(P, G, PV), PV, atol=1e-12)          # idempotent
+    PtPV = np.matmul(P.transpose(0, 2, 1), PV[:, :, None])[:, :, 0]
+    assert np.abs(PtPV).max() < 1e-11                                   # annihilates range(P)
+    for k in range(inst.q):                                             # = I - Q Q^T
+        Qk, _ = np.linalg.qr(P[k])
+        assert np.allclose(PV[k], V[k] - Qk @ (Qk.T @ V[k]), atol=1e-12)
+
+
+def test_ls_b_normal_equations_and_lstsq():
+    inst, A, Y = _small()
+    U = O.qr_pos(np.random.default_rng(5).standard_normal((inst.n, inst.r)))[0]
+    S = inst.S_star.T.copy()
+    B = O.ls_b(A, U, Y, S)
+    for k in range(inst.q):
+        AU = A[k] @ U
+        rhs = Y[k] - A[k] @ S[k]
+        assert np.abs(AU.T @ (rhs - AU @ B[k])).max() < 1e-10 * np.abs(AU).sum()
+        ref = np.linalg.lstsq(AU, rhs, rcond=None)[0]
+        assert np.allclose(B[k], ref, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- IHT
+
+def test_iht_step_is_line_search_minimiser():
+    """mu must minimise ||M(s - a g_T) - z||^2 over a (brute-force 1-D search)."""
+    inst, A, Y = _small(q=5)
+    Mop = lambda S: O.apply_A(A, S)
+    MTop = lambda V: O.apply_AT(A, V)
+    trace = []
+    S1, idx1 = O.iht(Y, Mop, MTop, inst.rho, 1, np.zeros((inst.q, inst.n)), trace=trace)
+    S2, idx2 = O.iht(Y, Mop, MTop, inst.rho, 1, S1, idx1, trace=trace)
+    G, mu = trace[1]["G"], trace[1]["mu"]
+    for k in range(inst.q):
+        gT = np.zeros(inst.n)
+        gT[idx1[k]] = G[k, idx1[k]]
+        f = lambda a: np.sum((A[k] @ (S1[k] - a * gT) - Y[k]) ** 2)
+        lo, hi = 0.0, 10 * mu[k] + 1.0
+        for _ in range(200):                                # golden-section search
+            a1 = hi - (hi - lo) / 1.618033988749895
+            a2 = lo + (hi - lo) / 1.618033988749895
+            if f(a1) < f(a2):
+                hi = a2
+            else:
+                lo = a1
+        assert abs((lo + hi) / 2 - mu[k]) <= 1e-7 * mu[k]
+
+
+def test_iht_recovers_sparse_vectors_exactly():
+    """L* = 0 and m >> rho log(n/rho): IHT from 0 is plain compressive sensing and recovers s*."""
+    inst = I.make_instance(120, 20, 60, 1, 4, 11)
+    A = inst.A64()
+    Y = O.apply_A(A, inst.S_star.T)
+    S, idx = O.iht(Y, lambda S: O.apply_A(A, S), lambda V: O.apply_AT(A, V), 4, 40,
+                   np.zeros((20, 120)))
+    assert np.array_equal(idx, inst.supp)
+    assert np.abs(S - inst.S_star.T).max() < 1e-9 * np.abs(inst.S_star).max()
+
+
+def test_iht_scale_invariance():
+    inst, A, Y = _small(q=6)
+    run = lambda c: O.iht(c * Y, lambda S: O.apply_A(c * A, S), lambda V: O.apply_AT(c * A, V),
+                          inst.rho, 5, np.zeros((inst.q, inst.n)))
+    S1, i1 = run(1.0)
+    S2, i2 = run(8.0)        # (M, z) -> (cM, cz) leaves the IHT iterates unchanged
+    assert np.array_equal(i1, i2)
+    assert np.allclose(S1, S2, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("rule", ["literal", "full"])
+def test_other_step_readings_fail_exact_recovery(rule):
+    """Negative test: the printed unsquared ratio diverges; the unrestricted ratio stalls."""
+    inst = I.make_instance(100, 100, 40, 1, 2, 231103824, s_zero=False)
+    A = inst.A64()
+    Y = O.apply_A(A, inst.S_star.T)
+    S, idx = O.iht(Y, lambda S: O.apply_A(A, S), lambda V: O.apply_AT(A, V), 2, 30,
+                   np.zeros((100, 100)), mu_rule=rule)
+    assert np.mean([set(idx[k]) == set(inst.supp[k]) for k in range(100)]) < 0.9
+    S, idx = O.iht(Y, lambda S: O.apply_A(A, S), lambda V: O.apply_AT(A, V), 2, 30,
+                   np.zeros((100, 100)))
+    assert np.array_equal(idx, inst.supp)
+
+
+# ---------------------------------------------------------------- gradient, QR, eta
+
+def test_grad_U_central_differences():
+    inst, A, Y = _small(n=20, q=6, m=12, r=2, rho=2)
+    rng = np.random.default_rng(9)
+    U = rng.standard_normal((inst.n, inst.r))
+    B = rng.standard_normal((inst.q, inst.r))
+    S = inst.S_star.T
+    g = O.grad_U(A, U, B, S, Y)
+    h = 1e-5
+    fd = np.zeros_like(U)
+    for j in range(inst.n):
+        for c in range(inst.r):
+            E = np.zeros_like(U)
+            E[j, c] = h
+            fd[j, c] = (O.cost(A, U + E, B, S, Y) - O.cost(A, U - E, B, S, Y)) / (2 * h)
+    assert np.abs(g - fd / 2).max() <= 1e-6 * np.abs(g).max()     # grad = (1/2) df/dU
+
+
+def test_qr_positive_diagonal():
+    M = np.random.default_rng(2).standard_normal((50, 6))
+    Q, R = O.qr_pos(M)
+    assert np.abs(Q.T @ Q - np.eye(6)).max() < 1e-14
+    assert np.allclose(Q @ R, M, atol=1e-13)
+    assert np.allclose(R, np.triu(R)) and (np.diag(R) > 0).all()
+
+
+def test_eta_normalises_first_step():
+    inst, A, Y = _small(n=60, q=30, m=30, r=2, rho=2)
+    st = O.initialise(A, Y, inst.r, inst.rho)
+    rec = {}
+    st1 = O.gdmin_iteration(A, Y, st, inst.rho, record=rec)
+    assert abs(np.linalg.svd(st1.eta * rec["grad"], compute_uv=False)[0] - O.ETA_C) < 1e-12
+    assert abs(O.spectral_norm(rec["grad"]) - np.linalg.svd(rec["grad"], compute_uv=False)[0]) < 1e-9
+
+
+def test_spectral_init_matches_eigenvectors():
+    L0 = np.random.default_rng(4).standard_normal((30, 20))
+    U0 = O.spectral_init(L0, 3)
+    w, V = np.linalg.eigh(L0 @ L0.T)
+    assert O.subspace_distance(V[:, -3:], U0) < 1e-10
+
+
+# ---------------------------------------------------------------- whole algorithm
+
+def test_exact_recovery_n100():
+    inst = I.make_workload("gauss_n100_q100_m40_r2_rho2")
+    st, hist = O.solve(inst.A64(), inst.Y64, inst.r, inst.rho, t_max=300,
+                       X_star=inst.X_star, err_tol=1e-10)
+    assert hist[-1] < 1e-10 and len(hist) <= 300
+    assert np.array_equal(st.idx, inst.supp)
+
+
+def test_low_rank_only_reduces_to_altgdmin_lr():
+    """S* = 0 with rho = 0: S stays 0 and the method is AltGDmin for LRCCS; exact recovery."""
+    inst = I.make_instance(100, 80, 80, 2, 0, 21, s_zero=True)
+    st, hist = O.solve(inst.A64(), inst.Y64, 2, 0, t_max=200, X_star=inst.X_star, err_tol=1e-10)
+    assert np.all(st.S == 0)
+    assert hist[-1] < 1e-10
+
+
+def test_measurement_scaling_equivariance():
+    inst = I.make_workload("gauss_n100_q100_m40_r2_rho2")
+    A = inst.A64()
+    st1, _ = O.solve(A, inst.Y64, 2, 2, t_max=15)
+    st2, _ = O.solve(A, 4.0 * inst.Y64, 2, 2, t_max=15)
+    assert np.allclose(O.estimate(st2), 4.0 * O.estimate(st1), rtol=1e-9, atol=1e-9)
+
+
+def test_rotation_invariance_of_U0():
+    inst = I.make_workload("gauss_n100_q100_m40_r2_rho2")
+    A = inst.A64()
+    st0 = O.initialise(A, inst.Y64, 2, 2)
+    th = 0.7
+    R = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+    st1, _ = O.solve(A, inst.Y64, 2, 2, t_max=10, U0=st0.U)
+    st2, _ = O.solve(A, inst.Y64, 2, 2, t_max=10, U0=st0.U @ R)
+    assert np.allclose(O.estimate(st1), O.estimate(st2), rtol=1e-9, atol=1e-9)
+
+
+def test_column_permutation_equivariance():
+    inst = I.make_workload("gauss_n100_q100_m40_r2_rho2")
+    A = inst.A64()
+    perm = np.random.default_rng(0).permutation(inst.q)
+    st1, _ = O.solve(A, inst.Y64, 2, 2, t_max=10)
+    st2, _ = O.solve(A[perm], inst.Y64[perm], 2, 2, t_max=10)
+    assert np.allclose(O.estimate(st2), O.estimate(st1)[:, perm], rtol=1e-9, atol=1e-9)
