@@ -1,0 +1,208 @@
+/*
+ * altgdmin.h -- C ABI of the MI355X (gfx950) hot path of AltGDmin-LR+S.
+ *
+ * Method: S. Babu, N. Vaswani, "A Fast Algorithm for Low Rank + Sparse
+ * column-wise Compressive Sensing", arXiv 2311.03824.  Problem statement of
+ * Sec. 1.1: recover X = L + S (n x q), L = U B of rank r and every column of S
+ * holding rho nonzeros, from y_k = A_k x_k, k = 0..q-1, A_k an m x n matrix.
+ * The solver is Alg. 1 (altGDmin-L+S) with Alg. 2 (IHT) inside.
+ *
+ * Conventions shared by every entry point
+ *  - All array pointers are DEVICE pointers unless the argument says "host".
+ *    The library never allocates or frees device memory: the caller owns the
+ *    inputs, the outputs and the workspace, which must outlive every call
+ *    that uses them (and the handle).
+ *  - Work is enqueued on the caller's HIP stream (`stream`, a hipStream_t
+ *    passed as void*; NULL means the legacy default stream).  Calls return as
+ *    soon as the work is enqueued unless they say they synchronise.
+ *  - Layout of A (format ALTGDMIN_A_F32): A_k is column-major with the row
+ *    index fastest: element (i, j) of A_k is A[k*a_stride_k + j*lda + i].
+ *    lda >= m and lda, a_stride_k and the base address must be multiples of 4
+ *    floats (16 bytes).  Rows m..lda-1 are ignored.
+ *    Format ALTGDMIN_A_BF16X2: A_k = hi + lo with hi and lo bfloat16 planes of
+ *    the same layout (uint16 elements; lda, a_stride_k multiples of 8).
+ *  - Y: y_k at Y[k*ldy + i], ldy >= m.
+ *  - U: n x r row-major (U[j*r + c]); B is returned transposed, Bt q x r
+ *    row-major (Bt[k*r + c] = b_k[c]); S as q x rho arrays of row indices
+ *    (int32, ascending within a column) and values (float).
+ *  - Return codes: ALTGDMIN_OK (0); negative values are errors; the positive
+ *    ALTGDMIN_ENOTCONV is a warning.  altgdmin_last_error() gives the text of
+ *    the last error of the calling thread.  Faults inside kernels surface at
+ *    the next call that synchronises.
+ */
+#ifndef ALTGDMIN_H
+#define ALTGDMIN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ALTGDMIN_OK = 0,
+  ALTGDMIN_ENOTCONV = 1,     /* t_max reached before tol_resid (warning) */
+  ALTGDMIN_EINVAL = -1,      /* invalid argument or unsupported size */
+  ALTGDMIN_ENOWS = -2,       /* workspace too small */
+  ALTGDMIN_EHIP = -3,        /* HIP runtime error */
+  ALTGDMIN_ENONFINITE = -4,  /* a NaN/Inf reached the selection, or a Gram matrix was not positive definite */
+  ALTGDMIN_ENOTBUILT = -5    /* no kernel instantiation for these sizes */
+};
+
+enum {
+  ALTGDMIN_A_F32 = 0,        /* FP32 plane */
+  ALTGDMIN_A_BF16X2 = 1      /* BF16 hi plane + BF16 lo plane, A = hi + lo */
+};
+
+/* Problem of Sec. 1.1: sizes, measurement matrices and measurements. */
+typedef struct altgdmin_problem {
+  int32_t n, q, m, r, rho;   /* 1 <= r <= min(m, n), 0 <= rho <= n; rho is the threshold budget (Sec. 2.6) */
+  int32_t a_format;          /* ALTGDMIN_A_* */
+  const void* A;             /* F32: const float*; BF16X2: hi plane, const uint16_t* */
+  const void* A_lo;          /* BF16X2: lo plane; NULL otherwise */
+  int64_t lda;               /* column stride of A_k in elements */
+  int64_t a_stride_k;        /* stride between A_k and A_{k+1} in elements, >= lda*n */
+  const float* Y;            /* q x ldy */
+  int64_t ldy;
+  const float* U_start;      /* optional n x r start block of the subspace iteration (NULL: a fixed disjoint-support basis) */
+} altgdmin_problem;
+
+/* Parameters of Alg. 1 / Sec. 2.6. */
+typedef struct altgdmin_params {
+  int32_t tau0;              /* IHT iterations of the initialisation (paper: 10) */
+  int32_t tau;               /* IHT iterations per GDmin iteration (paper: 3) */
+  int32_t t_max;             /* GDmin iterations (paper: 200) */
+  int32_t power_iters;       /* max subspace iterations for U_0 (top-r left singular vectors of L_0) */
+  int32_t poll_every;        /* altgdmin_solve reads the residual every poll_every iterations */
+  int32_t flags;             /* reserved, 0 */
+  double eta_c;              /* eta = eta_c / ||grad_U f(U_0, B_1, S_1)||_2 (paper: 0.14) */
+  double power_tol;          /* stop the subspace iteration when ||(I - U_p U_p^T) U_{p+1}||_F <= power_tol */
+  double tol_resid;          /* altgdmin_solve stops when ||Y - A(UB+S)||_F / ||Y||_F <= tol_resid (0: never) */
+} altgdmin_params;
+
+/* Fills *p with the paper's defaults (tau0 = 10, tau = 3, t_max = 200, eta_c = 0.14). Host call. */
+void altgdmin_default_params(altgdmin_params* p);
+
+typedef struct altgdmin_handle altgdmin_handle;
+
+/* Host-side status, filled by altgdmin_status (synchronises the stream). */
+typedef struct altgdmin_report {
+  int32_t iterations;        /* GDmin iterations done */
+  int32_t power_iterations;  /* subspace iterations used for U_0 */
+  int32_t error_flags;       /* bit 0: NaN at a selection; bit 1: Gram not positive definite; bit 2: support index out of range */
+  int32_t converged;         /* 1 when the last residual <= tol_resid */
+  double eta;                /* step size (0 before iteration 1) */
+  double resid;              /* ||Y - A(U B + S)||_F / ||Y||_F of the last iteration's consistent pair */
+  double power_sd;           /* last subspace-iteration change */
+} altgdmin_report;
+
+/* Exact device workspace size for a problem (host call, no GPU work). */
+int altgdmin_workspace_bytes(const altgdmin_problem* prob, const altgdmin_params* par, size_t* bytes);
+
+/* Validates, carves the workspace and enqueues the initialisation of Alg. 1
+ * (Sec. 2.3): s_k = IHT(y_k, A_k, rho, tau0, 0), L_0 = [A_k^T (y_k - A_k s_k)],
+ * U_0 = top-r left singular subspace of L_0 by subspace iteration.  *out gets a
+ * small host object; the problem arrays and workspace must outlive it. */
+int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void* workspace,
+                  size_t ws_bytes, void* stream, altgdmin_handle** out);
+
+/* Enqueues `iters` GDmin iterations of Alg. 1 (z_k/M_k from U, warm-started IHT
+ * for s_k, LS for b_k (eq. (bk_LS)), grad_U f, eta at t = 1, U+ = QR(U - eta grad)).
+ * The iteration is captured once as a HIP graph and replayed.  Asynchronous. */
+int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream);
+
+/* Copies the consistent state (U that B and S were fitted with, Bt, S) into
+ * caller buffers (device pointers, torch shapes (n,r), (q,r), (q,rho), (q,rho)).
+ * Any pointer may be NULL.  U_next (optional) receives the already-updated U. */
+int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float* S_val,
+                 float* U_next, void* stream);
+
+/* Synchronises `stream` and reads the device status into *rep (host). */
+int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep);
+
+/* Per-iteration relative residual log, host array of length >= t_max; returns count in *count. Synchronises. */
+int altgdmin_residual_log(altgdmin_handle* h, void* stream, double* host_log, int32_t* count);
+
+/* init + step until tol_resid or t_max, polling every poll_every iterations,
+ * then copies the consistent state out (device pointers, any may be NULL).
+ * Synchronises.  Returns ALTGDMIN_ENOTCONV when t_max is reached first and
+ * tol_resid > 0. */
+int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, void* workspace,
+                   size_t ws_bytes, void* stream, float* U, float* Bt, int32_t* S_idx,
+                   float* S_val, altgdmin_report* rep);
+
+/* Frees the host handle only. */
+int altgdmin_destroy(altgdmin_handle* h);
+
+const char* altgdmin_strerror(int code);
+const char* altgdmin_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * Step-level entry points.  Each runs one step of the path on caller buffers,
+ * with the same kernels the solver uses, so that every step can be checked on
+ * its own.  Stateless; asynchronous on `stream`.
+ * ---------------------------------------------------------------------- */
+
+/* HardThreshold(v, rho) of Alg. 2 on `count` vectors v_c = V[c*ldv + 0..n-1]:
+ * keeps the rho entries of largest |v| (lower index first on ties), writes
+ * their indices ascending to idx[c*rho + t] and values to val[c*rho + t].
+ * flags[c] (optional) gets bit 0 if v_c holds a NaN. */
+int altgdmin_op_select(const float* V, int32_t n, int32_t count, int64_t ldv, int32_t rho,
+                       int32_t* idx, float* val, int32_t* flags, void* stream);
+
+/* P_k = A_k U (m x r, row-major per k at P[k*m*r]) and the Cholesky factor
+ * L_k (lower, r x r row-major FP64 at Lc[k*r*r]) of G_k = P_k^T P_k, the pieces
+ * of (A_k U)^dagger in eq. (bk_LS).  flags[k] gets bit 1 if G_k is not positive definite. */
+int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, double* Lc,
+                   int32_t* flags, void* stream);
+
+/* tau IHT iterations of Alg. 2 per column on caller state.  project = 1:
+ * z_k, M_k of the GDmin loop (needs P, Lc from altgdmin_op_au); project = 0:
+ * M = A_k, z = y_k as in the initialisation.  has_support = 0 starts from
+ * s = 0 (S_idx/S_val ignored on entry).  S_idx/S_val are updated in place.
+ * G_out (optional, q x n) gets the gradient of the last iteration, mu_out
+ * (optional, q) its step size. */
+int altgdmin_op_iht(const altgdmin_problem* prob, int32_t project, const float* P, const double* Lc,
+                    int32_t tau, int32_t has_support, int32_t* S_idx, float* S_val,
+                    float* G_out, double* mu_out, int32_t* flags, void* stream);
+
+/* LS and gradient pieces of one GDmin iteration for the given U (through P,
+ * Lc) and S: b_k = (A_k U)^dagger (y_k - A_k s_k) -> Bt (q x r),
+ * h_k = A_k^T (A_k (U b_k + s_k) - y_k) -> H (q x n), ||r_k||^2 -> rr (q, FP64). */
+int altgdmin_op_lsgrad(const altgdmin_problem* prob, const float* P, const double* Lc,
+                       const int32_t* S_idx, const float* S_val, float* Bt, float* H,
+                       double* rr, int32_t* flags, void* stream);
+
+/* Back-projection of the initialisation: L0t[k*n + j] = (A_k^T (y_k - A_k s_k))_j. */
+int altgdmin_op_backproject(const altgdmin_problem* prob, const int32_t* S_idx, const float* S_val,
+                            float* L0t, void* stream);
+
+/* Device scratch (bytes) that altgdmin_op_grad, altgdmin_op_qr_step and
+ * altgdmin_op_subspace need for sizes (n, q, r).  Host call. */
+int altgdmin_op_scratch_bytes(int32_t n, int32_t q, int32_t r, size_t* bytes);
+
+/* grad_U f = sum_k h_k b_k^T (n x r row-major), summed in a fixed order (Sec. 2.1). */
+int altgdmin_op_grad(const float* H, const float* Bt, int32_t n, int32_t q, int32_t r,
+                     float* grad, void* scratch, size_t scratch_bytes, void* stream);
+
+/* Projected GD step: U_out = Q of the thin QR (positive diagonal R) of
+ * U - eta*grad, by CholeskyQR2 with FP64 Gram and Cholesky.  If *eta_io <= 0
+ * on entry (device double) it is first set to eta_c / ||grad||_2. */
+int altgdmin_op_qr_step(const float* U, const float* grad, int32_t n, int32_t r, double eta_c,
+                        double* eta_io, float* U_out, void* scratch, size_t scratch_bytes,
+                        void* stream);
+
+/* Top-r left singular subspace of L0 (n x q, given as L0t q x n) by subspace
+ * iteration from U_start (n x r), at most `iters` iterations or until the
+ * change drops to tol.  U_out: n x r orthonormal.  iters_out (optional, device
+ * int32) gets the count used. */
+int altgdmin_op_subspace(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start,
+                         int32_t iters, double tol, float* U_out, int32_t* iters_out,
+                         void* scratch, size_t scratch_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ALTGDMIN_H */

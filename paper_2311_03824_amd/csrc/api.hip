@@ -1,0 +1,535 @@
+// C ABI of the AltGDmin-LR+S hot path (declarations and contracts in include/altgdmin.h).
+//
+// Host side only: validation, workspace carving, launch sequencing and the HIP
+// graph of one GDmin iteration.  Every step of the method runs in the kernels
+// of k_column.hip and k_small.hip.
+#include <cstring>
+#include <string>
+
+#include "altgdmin.h"
+#include "launch.h"
+
+using namespace altg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                         \
+  do {                                                                                    \
+    hipError_t e_ = (x);                                                                  \
+    if (e_ != hipSuccess) return fail(ALTGDMIN_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr size_t kMaxLds = 64 * 1024;
+
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    off = (off + kAlign - 1) / kAlign * kAlign;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+int grad_splits(int q) { return q < 16 ? (q < 1 ? 1 : q) : 16; }
+
+int fmt_of(const altgdmin_problem* p) {
+  return p->a_format == ALTGDMIN_A_BF16X2 ? FMT_BF16X2 : FMT_F32;
+}
+
+}  // namespace
+
+struct altgdmin_handle {
+  altgdmin_problem prob;
+  altgdmin_params par;
+  int fmt;
+  float* P;
+  double* Ginv;
+  int* Tidx;
+  float* Tval;
+  float* Bt;
+  float* H;
+  double* colrr;
+  int* colflags;
+  float* gpart;
+  int KS;
+  float* U;
+  float* Uprev;
+  float* Utmp;
+  float* Tpow;
+  Ctl* ctl;
+  double* rlog;
+  int rlog_len;
+  bool have_graph = false;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int t_host = 0;
+};
+
+namespace {
+
+// Lays the workspace out; with base == nullptr it only measures.
+size_t carve(altgdmin_handle* h, void* base) {
+  const altgdmin_problem& p = h->prob;
+  const size_t n = p.n, q = p.q, m = p.m, r = p.r, rho = p.rho;
+  Carver c(base);
+  h->ctl = c.take<Ctl>(1);
+  h->P = c.take<float>(q * m * r);
+  h->Ginv = c.take<double>(q * r * r);
+  h->Tidx = c.take<int>(q * rho);
+  h->Tval = c.take<float>(q * rho);
+  h->Bt = c.take<float>(q * r);
+  h->H = c.take<float>(q * n);
+  h->colrr = c.take<double>(q);
+  h->colflags = c.take<int>(q);
+  h->KS = grad_splits(p.q);
+  h->gpart = c.take<float>((size_t)h->KS * n * r);
+  h->U = c.take<float>(n * r);
+  h->Uprev = c.take<float>(n * r);
+  h->Utmp = c.take<float>(n * r);
+  h->Tpow = c.take<float>(q * r);
+  h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
+  h->rlog = c.take<double>(h->rlog_len);
+  return (c.off + kAlign - 1) / kAlign * kAlign;
+}
+
+int validate(const altgdmin_problem* p, const altgdmin_params* par) {
+  if (!p || !par) return fail(ALTGDMIN_EINVAL, "null problem or params");
+  if (p->n < 1 || p->q < 1 || p->m < 1) return fail(ALTGDMIN_EINVAL, "n, q, m must be >= 1");
+  if (p->r < 1 || p->r > p->m || p->r > p->n) return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n)");
+  if (p->r > kRMax) return fail(ALTGDMIN_ENOTBUILT, "r > 16 has no instantiation");
+  if (p->rho < 0 || p->rho > p->n) return fail(ALTGDMIN_EINVAL, "need 0 <= rho <= n");
+  if (p->m > 256 * kNCMax) return fail(ALTGDMIN_ENOTBUILT, "m > 1024 has no instantiation");
+  if (p->a_format != ALTGDMIN_A_F32 && p->a_format != ALTGDMIN_A_BF16X2)
+    return fail(ALTGDMIN_EINVAL, "unknown a_format");
+  if (!p->A || !p->Y) return fail(ALTGDMIN_EINVAL, "A and Y must be non-null");
+  if (p->a_format == ALTGDMIN_A_BF16X2 && !p->A_lo) return fail(ALTGDMIN_EINVAL, "BF16X2 needs A_lo");
+  if (p->lda < p->m || p->lda % 4 != 0) return fail(ALTGDMIN_EINVAL, "lda must be >= m and a multiple of 4");
+  if (p->a_stride_k < p->lda * (int64_t)p->n || p->a_stride_k % 4 != 0)
+    return fail(ALTGDMIN_EINVAL, "a_stride_k must be >= lda*n and a multiple of 4");
+  const size_t align = p->a_format == ALTGDMIN_A_F32 ? 16 : 8;
+  if (reinterpret_cast<uintptr_t>(p->A) % align != 0 ||
+      (p->A_lo && reinterpret_cast<uintptr_t>(p->A_lo) % align != 0))
+    return fail(ALTGDMIN_EINVAL, "A planes are not aligned to 4 elements");
+  if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
+  if (!au_supported(p->m, p->r)) return fail(ALTGDMIN_ENOTBUILT, "no A_k U instantiation for this (m, r)");
+  if (col_lds_bytes(p->n, p->m, p->r, p->rho, 1) > kMaxLds || au_lds_bytes(p->m, p->r) > kMaxLds)
+    return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 64 KiB of LDS per column workgroup");
+  if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
+      !(par->eta_c >= 0.0))
+    return fail(ALTGDMIN_EINVAL, "invalid params");
+  return ALTGDMIN_OK;
+}
+
+ColArgs col_args(const altgdmin_handle* h) {
+  const altgdmin_problem& p = h->prob;
+  ColArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = p.n; a.q = p.q; a.m = p.m; a.r = p.r; a.rho = p.rho;
+  a.A = p.A; a.Alo = p.A_lo; a.lda = p.lda; a.sA = p.a_stride_k;
+  a.Y = p.Y; a.ldy = p.ldy;
+  a.P = h->P; a.Ginv = h->Ginv; a.Tidx = h->Tidx; a.Tval = h->Tval;
+  a.H = h->H; a.Bt = h->Bt; a.rr = h->colrr; a.flags = h->colflags;
+  return a;
+}
+
+QRArgs qr_args(const altgdmin_handle* h, int mode) {
+  QRArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = h->prob.n; a.r = h->prob.r; a.KS = h->KS; a.mode = mode;
+  a.gpart = h->gpart; a.U = h->U; a.Uprev = h->Uprev; a.Utmp = h->Utmp; a.ctl = h->ctl;
+  a.eta_c = h->par.eta_c; a.power_tol = h->par.power_tol;
+  a.colrr = h->colrr; a.colflags = h->colflags; a.q = h->prob.q;
+  a.rlog = h->rlog; a.rlog_len = h->rlog_len;
+  return a;
+}
+
+// One GDmin iteration of Alg. 1 on stream st.
+int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
+  const altgdmin_problem& p = h->prob;
+  AUArgs au;
+  au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
+  au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
+  au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+  HIPCHK(launch_au(h->fmt, au, st));
+  ColArgs ca = col_args(h);
+  ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
+  HIPCHK(launch_col(h->fmt, ca, st));
+  HIPCHK(launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st));
+  HIPCHK(launch_qr(qr_args(h, QR_GD), st));
+  return ALTGDMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void altgdmin_default_params(altgdmin_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof(*p));
+  p->tau0 = 10;
+  p->tau = 3;
+  p->t_max = 200;
+  p->power_iters = 100;
+  p->poll_every = 10;
+  p->eta_c = 0.14;
+  p->power_tol = 1e-6;
+  p->tol_resid = 0.0;
+}
+
+int altgdmin_workspace_bytes(const altgdmin_problem* prob, const altgdmin_params* par, size_t* bytes) {
+  int rc = validate(prob, par);
+  if (rc) return rc;
+  if (!bytes) return fail(ALTGDMIN_EINVAL, "bytes is null");
+  altgdmin_handle h;
+  h.prob = *prob;
+  h.par = *par;
+  *bytes = carve(&h, nullptr);
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void* workspace, size_t ws_bytes,
+                  void* stream, altgdmin_handle** out) {
+  int rc = validate(prob, par);
+  if (rc) return rc;
+  if (!workspace || !out) return fail(ALTGDMIN_EINVAL, "null workspace or out");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(ALTGDMIN_EINVAL, "workspace must be 256-byte aligned");
+  altgdmin_handle* h = new altgdmin_handle();
+  h->prob = *prob;
+  h->par = *par;
+  h->fmt = fmt_of(prob);
+  const size_t need = carve(h, workspace);
+  if (ws_bytes < need) {
+    delete h;
+    return fail(ALTGDMIN_ENOWS, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const altgdmin_problem& p = h->prob;
+  auto bail = [&](hipError_t e, const char* what) {
+    delete h;
+    return fail(ALTGDMIN_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+  };
+  hipError_t e;
+  if ((e = launch_reset_ctl(h->ctl, 1, st)) != hipSuccess) return bail(e, "reset");
+  if ((e = launch_fill_int(h->colflags, 0, p.q, st)) != hipSuccess) return bail(e, "flags");
+  // s_k = IHT(y_k, A_k, rho, tau0, 0) and L_0 columns A_k^T (y_k - A_k s_k)
+  ColArgs ca = col_args(h);
+  ca.tau = par->tau0; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
+  if ((e = launch_col(h->fmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
+  if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
+  // U_0: top-r left singular subspace of L_0 by subspace iteration
+  if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, (long long)p.n * p.r, st);
+  else e = launch_fill_basis(h->Utmp, p.n, p.r, st);
+  if (e != hipSuccess) return bail(e, "start block");
+  if ((e = launch_qr(qr_args(h, QR_ORTH), st)) != hipSuccess) return bail(e, "orth");
+  for (int it = 0; it < par->power_iters; ++it) {
+    if ((e = launch_ltu(h->H, h->U, p.n, p.q, p.r, h->Tpow, &h->ctl->conv, st)) != hipSuccess) return bail(e, "ltu");
+    if ((e = launch_grad(h->H, h->Tpow, p.n, p.q, p.r, h->KS, h->gpart, &h->ctl->conv, st)) != hipSuccess)
+      return bail(e, "power grad");
+    if ((e = launch_qr(qr_args(h, QR_POWER), st)) != hipSuccess) return bail(e, "power qr");
+  }
+  if ((e = launch_reset_ctl(h->ctl, 0, st)) != hipSuccess) return bail(e, "reset eta");
+  *out = h;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
+  if (!h || iters < 0) return fail(ALTGDMIN_EINVAL, "null handle or negative iters");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  if (h->par.flags & 1) {   // eager launches (no graph)
+    for (int i = 0; i < iters; ++i) {
+      int rc = enqueue_iteration(h, st);
+      if (rc) return rc;
+    }
+    h->t_host += iters;
+    return ALTGDMIN_OK;
+  }
+  if (!h->have_graph) {
+    hipStream_t cs;
+    HIPCHK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    HIPCHK(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = enqueue_iteration(h, cs);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(cs, &g);
+    hipStreamDestroy(cs);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    HIPCHK(hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0));
+    h->graph = g;
+    h->have_graph = true;
+  }
+  for (int i = 0; i < iters; ++i) HIPCHK(hipGraphLaunch(h->exec, st));
+  h->t_host += iters;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float* S_val, float* U_next,
+                 void* stream) {
+  if (!h) return fail(ALTGDMIN_EINVAL, "null handle");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const altgdmin_problem& p = h->prob;
+  const size_t nr = (size_t)p.n * p.r;
+  if (U) HIPCHK(hipMemcpyAsync(U, h->t_host > 0 ? h->Uprev : h->U, nr * 4, hipMemcpyDeviceToDevice, st));
+  if (U_next) HIPCHK(hipMemcpyAsync(U_next, h->U, nr * 4, hipMemcpyDeviceToDevice, st));
+  if (Bt) HIPCHK(hipMemcpyAsync(Bt, h->Bt, (size_t)p.q * p.r * 4, hipMemcpyDeviceToDevice, st));
+  if (S_idx && p.rho > 0) HIPCHK(hipMemcpyAsync(S_idx, h->Tidx, (size_t)p.q * p.rho * 4, hipMemcpyDeviceToDevice, st));
+  if (S_val && p.rho > 0) HIPCHK(hipMemcpyAsync(S_val, h->Tval, (size_t)p.q * p.rho * 4, hipMemcpyDeviceToDevice, st));
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep) {
+  if (!h || !rep) return fail(ALTGDMIN_EINVAL, "null handle or report");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  Ctl c;
+  HIPCHK(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  rep->iterations = c.t;
+  rep->power_iterations = c.power_it;
+  rep->error_flags = c.err;
+  rep->eta = c.eta;
+  rep->resid = c.resid;
+  rep->power_sd = c.power_sd;
+  rep->converged = (h->par.tol_resid > 0.0 && c.t > 0 && c.resid <= h->par.tol_resid) ? 1 : 0;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_residual_log(altgdmin_handle* h, void* stream, double* host_log, int32_t* count) {
+  if (!h || !host_log || !count) return fail(ALTGDMIN_EINVAL, "null argument");
+  altgdmin_report rep;
+  int rc = altgdmin_status(h, stream, &rep);
+  if (rc) return rc;
+  const int cnt = rep.iterations < h->rlog_len ? rep.iterations : h->rlog_len;
+  if (cnt > 0) HIPCHK(hipMemcpy(host_log, h->rlog, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost));
+  *count = cnt;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_destroy(altgdmin_handle* h) {
+  if (!h) return ALTGDMIN_OK;
+  if (h->exec) hipGraphExecDestroy(h->exec);
+  if (h->graph) hipGraphDestroy(h->graph);
+  delete h;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, void* workspace, size_t ws_bytes,
+                   void* stream, float* U, float* Bt, int32_t* S_idx, float* S_val, altgdmin_report* rep) {
+  altgdmin_handle* h = nullptr;
+  int rc = altgdmin_init(prob, par, workspace, ws_bytes, stream, &h);
+  if (rc) return rc;
+  altgdmin_report r;
+  std::memset(&r, 0, sizeof(r));
+  int done = 0;
+  bool conv = false;
+  while (done < par->t_max) {
+    const int k = (par->t_max - done) < par->poll_every ? (par->t_max - done) : par->poll_every;
+    rc = altgdmin_step(h, k, stream);
+    if (rc) { altgdmin_destroy(h); return rc; }
+    done += k;
+    if (par->tol_resid > 0.0) {
+      rc = altgdmin_status(h, stream, &r);
+      if (rc) { altgdmin_destroy(h); return rc; }
+      if (r.error_flags) break;
+      if (r.converged) { conv = true; break; }
+    }
+  }
+  rc = altgdmin_get(h, U, Bt, S_idx, S_val, nullptr, stream);
+  if (!rc) rc = altgdmin_status(h, stream, &r);
+  altgdmin_destroy(h);
+  if (rc) return rc;
+  if (rep) *rep = r;
+  if (r.error_flags) return fail(ALTGDMIN_ENONFINITE, "non-finite value or indefinite Gram matrix during the solve");
+  if (par->tol_resid > 0.0 && !conv) return ALTGDMIN_ENOTCONV;
+  return ALTGDMIN_OK;
+}
+
+const char* altgdmin_strerror(int code) {
+  switch (code) {
+    case ALTGDMIN_OK: return "ok";
+    case ALTGDMIN_ENOTCONV: return "t_max reached before tol_resid";
+    case ALTGDMIN_EINVAL: return "invalid argument";
+    case ALTGDMIN_ENOWS: return "workspace too small";
+    case ALTGDMIN_EHIP: return "HIP runtime error";
+    case ALTGDMIN_ENONFINITE: return "non-finite value or indefinite Gram matrix";
+    case ALTGDMIN_ENOTBUILT: return "no kernel instantiation for these sizes";
+    default: return "unknown error";
+  }
+}
+
+const char* altgdmin_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------ step-level entry points
+
+int altgdmin_op_select(const float* V, int32_t n, int32_t count, int64_t ldv, int32_t rho, int32_t* idx,
+                       float* val, int32_t* flags, void* stream) {
+  if (!V || n < 1 || count < 0 || ldv < n || rho < 0 || rho > n) return fail(ALTGDMIN_EINVAL, "bad select arguments");
+  if (rho > 0 && (!idx || !val)) return fail(ALTGDMIN_EINVAL, "null idx/val");
+  if (select_lds_bytes(n, rho) > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "n too large for the select kernel");
+  if (count == 0) return ALTGDMIN_OK;
+  HIPCHK(launch_select(V, n, count, ldv, rho, idx, val, flags, static_cast<hipStream_t>(stream)));
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, double* Lc, int32_t* flags,
+                   void* stream) {
+  altgdmin_params par;
+  altgdmin_default_params(&par);
+  int rc = validate(prob, &par);
+  if (rc) return rc;
+  if (!U || !P || !Lc) return fail(ALTGDMIN_EINVAL, "null U/P/Ginv");
+  AUArgs au;
+  au.n = prob->n; au.q = prob->q; au.m = prob->m; au.r = prob->r;
+  au.A = prob->A; au.Alo = prob->A_lo; au.lda = prob->lda; au.sA = prob->a_stride_k;
+  au.U = U; au.P = P; au.Ginv = Lc; au.flags = flags;
+  HIPCHK(launch_au(fmt_of(prob), au, static_cast<hipStream_t>(stream)));
+  return ALTGDMIN_OK;
+}
+
+static int op_col(const altgdmin_problem* prob, ColArgs& a, void* stream) {
+  a.n = prob->n; a.q = prob->q; a.m = prob->m; a.r = prob->r; a.rho = prob->rho;
+  a.A = prob->A; a.Alo = prob->A_lo; a.lda = prob->lda; a.sA = prob->a_stride_k;
+  a.Y = prob->Y; a.ldy = prob->ldy;
+  HIPCHK(launch_col(fmt_of(prob), a, static_cast<hipStream_t>(stream)));
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_iht(const altgdmin_problem* prob, int32_t project, const float* P, const double* Lc, int32_t tau,
+                    int32_t has_support, int32_t* S_idx, float* S_val, float* G_out, double* mu_out,
+                    int32_t* flags, void* stream) {
+  altgdmin_params par;
+  altgdmin_default_params(&par);
+  int rc = validate(prob, &par);
+  if (rc) return rc;
+  if (tau < 0 || (project && (!P || !Lc)) || (prob->rho > 0 && (!S_idx || !S_val)))
+    return fail(ALTGDMIN_EINVAL, "bad iht arguments");
+  ColArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.P = P; a.Ginv = Lc; a.Tidx = S_idx; a.Tval = S_val; a.G_out = G_out; a.mu_out = mu_out; a.flags = flags;
+  a.tau = tau; a.project = project ? 1 : 0; a.has_support = has_support ? 1 : 0; a.tail = TAIL_NONE;
+  return op_col(prob, a, stream);
+}
+
+int altgdmin_op_lsgrad(const altgdmin_problem* prob, const float* P, const double* Lc, const int32_t* S_idx,
+                       const float* S_val, float* Bt, float* H, double* rr, int32_t* flags, void* stream) {
+  altgdmin_params par;
+  altgdmin_default_params(&par);
+  int rc = validate(prob, &par);
+  if (rc) return rc;
+  if (!P || !Lc || !Bt || !H || (prob->rho > 0 && (!S_idx || !S_val))) return fail(ALTGDMIN_EINVAL, "bad lsgrad arguments");
+  ColArgs a;
+  std::memset(&a, 0, sizeof(a));
+  // the kernel writes the support back; it is unchanged with tau = 0
+  a.P = P; a.Ginv = Lc; a.Tidx = const_cast<int32_t*>(S_idx); a.Tval = const_cast<float*>(S_val);
+  a.Bt = Bt; a.H = H; a.rr = rr; a.flags = flags;
+  a.tau = 0; a.project = 1; a.has_support = 1; a.tail = TAIL_LSGRAD;
+  return op_col(prob, a, stream);
+}
+
+int altgdmin_op_backproject(const altgdmin_problem* prob, const int32_t* S_idx, const float* S_val, float* L0t,
+                            void* stream) {
+  altgdmin_params par;
+  altgdmin_default_params(&par);
+  int rc = validate(prob, &par);
+  if (rc) return rc;
+  if (!L0t || (prob->rho > 0 && (!S_idx || !S_val))) return fail(ALTGDMIN_EINVAL, "bad backproject arguments");
+  ColArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.Tidx = const_cast<int32_t*>(S_idx); a.Tval = const_cast<float*>(S_val); a.H = L0t;
+  a.tau = 0; a.project = 0; a.has_support = 1; a.tail = TAIL_BACKPROJ;
+  return op_col(prob, a, stream);
+}
+
+// scratch layout of the U-side entry points: Ctl | gpart (KS n r) | Utmp (n r) | T (q r)
+struct OpScratch {
+  Ctl* ctl;
+  float* gpart;
+  float* Utmp;
+  float* T;
+  int KS;
+  size_t bytes;
+};
+
+static OpScratch op_scratch(void* base, int n, int q, int r) {
+  OpScratch s;
+  Carver c(base);
+  s.KS = grad_splits(q);
+  s.ctl = c.take<Ctl>(1);
+  s.gpart = c.take<float>((size_t)s.KS * n * r);
+  s.Utmp = c.take<float>((size_t)n * r);
+  s.T = c.take<float>((size_t)q * r);
+  s.bytes = c.off;
+  return s;
+}
+
+int altgdmin_op_scratch_bytes(int32_t n, int32_t q, int32_t r, size_t* bytes) {
+  if (n < 1 || q < 1 || r < 1 || r > kRMax || !bytes) return fail(ALTGDMIN_EINVAL, "bad sizes");
+  *bytes = op_scratch(nullptr, n, q, r).bytes;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_grad(const float* H, const float* Bt, int32_t n, int32_t q, int32_t r, float* grad, void* scratch,
+                     size_t scratch_bytes, void* stream) {
+  if (!H || !Bt || !grad || !scratch || n < 1 || q < 1 || r < 1 || r > kRMax) return fail(ALTGDMIN_EINVAL, "bad grad arguments");
+  OpScratch s = op_scratch(scratch, n, q, r);
+  if (scratch_bytes < s.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(launch_grad(H, Bt, n, q, r, s.KS, s.gpart, nullptr, st));
+  HIPCHK(launch_sum_partials(s.gpart, s.KS, (long long)n * r, grad, st));
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_qr_step(const float* U, const float* grad, int32_t n, int32_t r, double eta_c, double* eta_io,
+                        float* U_out, void* scratch, size_t scratch_bytes, void* stream) {
+  if (!U || !grad || !eta_io || !U_out || !scratch || n < 1 || r < 1 || r > kRMax || r > n)
+    return fail(ALTGDMIN_EINVAL, "bad qr arguments");
+  OpScratch s = op_scratch(scratch, n, 1, r);
+  if (scratch_bytes < s.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(launch_copy_f(U_out, U, (long long)n * r, st));
+  QRArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n; a.r = r; a.KS = 1; a.mode = QR_GD; a.gpart = grad; a.U = U_out; a.Utmp = s.Utmp;
+  a.eta_c = eta_c; a.eta_io = eta_io;
+  HIPCHK(launch_qr(a, st));
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_subspace(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start, int32_t iters,
+                         double tol, float* U_out, int32_t* iters_out, void* scratch, size_t scratch_bytes,
+                         void* stream) {
+  if (!L0t || !U_out || !scratch || n < 1 || q < 1 || r < 1 || r > kRMax || r > n || iters < 0)
+    return fail(ALTGDMIN_EINVAL, "bad subspace arguments");
+  OpScratch s = op_scratch(scratch, n, q, r);
+  if (scratch_bytes < s.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  HIPCHK(launch_reset_ctl(s.ctl, 1, st));
+  if (U_start) HIPCHK(launch_copy_f(s.Utmp, U_start, (long long)n * r, st));
+  else HIPCHK(launch_fill_basis(s.Utmp, n, r, st));
+  QRArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = n; a.r = r; a.KS = s.KS; a.gpart = s.gpart; a.U = U_out; a.Utmp = s.Utmp; a.ctl = s.ctl;
+  a.power_tol = tol;
+  a.mode = QR_ORTH;
+  HIPCHK(launch_qr(a, st));
+  a.mode = QR_POWER;
+  for (int it = 0; it < iters; ++it) {
+    HIPCHK(launch_ltu(L0t, U_out, n, q, r, s.T, &s.ctl->conv, st));
+    HIPCHK(launch_grad(L0t, s.T, n, q, r, s.KS, s.gpart, &s.ctl->conv, st));
+    HIPCHK(launch_qr(a, st));
+  }
+  if (iters_out) HIPCHK(hipMemcpyAsync(iters_out, &s.ctl->power_it, sizeof(int), hipMemcpyDeviceToDevice, st));
+  return ALTGDMIN_OK;
+}
+
+}  // extern "C"

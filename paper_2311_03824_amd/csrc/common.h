@@ -1,0 +1,240 @@
+// Shared device helpers and argument blocks of the AltGDmin-LR+S kernels (gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace altg {
+
+constexpr int kWaves = 4;            // waves per column workgroup
+constexpr int kThreads = kWaves * 64;
+constexpr int kRMax = 16;            // largest rank r with an instantiation
+constexpr int kNCMax = 4;            // largest number of 256-row chunks per lane (m <= 1024)
+constexpr int kQRThreads = 1024;
+
+// A-operand formats (loader template argument)
+enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2 };
+
+// Device-side control block of one solve.
+struct Ctl {
+  double eta;        // step size of the U update (0 until set at t = 1)
+  double resid;      // ||Y - A(UB+S)||_F / ||Y||_F of the last iteration
+  double power_sd;   // last subspace-iteration change
+  double ynorm2;     // ||Y||_F^2
+  int eta_set;       // 1 once eta is fixed
+  int conv;          // subspace iteration converged
+  int t;             // GDmin iterations done
+  int power_it;      // subspace iterations done
+  int err;           // OR of column error flags
+  int pad[7];
+};
+
+// Column kernel modes
+enum { TAIL_NONE = 0, TAIL_LSGRAD = 1, TAIL_BACKPROJ = 2 };
+
+struct ColArgs {
+  int n, q, m, r, rho;
+  const void* A;        // F32 plane, or BF16 hi plane
+  const void* Alo;      // BF16 lo plane
+  long long lda, sA;    // column stride and column-k stride, in elements
+  const float* Y;
+  long long ldy;
+  const float* P;       // q x m x r (project mode)
+  const double* Ginv;   // q x r x r (project mode)
+  int* Tidx;            // q x rho, in/out
+  float* Tval;          // q x rho, in/out
+  float* G_out;         // optional q x n: gradient of the last IHT iteration
+  double* mu_out;       // optional q: step of the last IHT iteration
+  float* H;             // q x n: h_k (LSGRAD) or l_k (BACKPROJ)
+  float* Bt;            // q x r (LSGRAD)
+  double* rr;           // q: ||r_k||^2 (LSGRAD) or ||y_k||^2 (BACKPROJ)
+  int* flags;           // q, OR-ed
+  int tau, project, has_support, tail;
+};
+
+struct AUArgs {
+  int n, q, m, r;
+  const void* A;
+  const void* Alo;
+  long long lda, sA;
+  const float* U;       // n x r row-major
+  float* P;             // q x m x r
+  double* Ginv;         // q x r x r
+  int* flags;
+};
+
+// ---------------------------------------------------------------- wave reductions
+// Butterfly sums: every lane ends with the same, bitwise identical total.
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o);
+  return x;
+}
+__device__ __forceinline__ int wave_sum(int x) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) x += __shfl_xor(x, o);
+  return x;
+}
+
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+__device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
+
+// ---------------------------------------------------------------- A_k loaders
+// load(j, ch) returns rows 4*ch .. 4*ch+3 of column j of A_k.
+template <int FMT> struct ALoader;
+
+template <> struct ALoader<FMT_F32> {
+  const float* base;
+  long long lda;
+  __device__ ALoader(const ColArgs& a, int k)
+      : base(static_cast<const float*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
+  __device__ ALoader(const AUArgs& a, int k)
+      : base(static_cast<const float*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
+  __device__ __forceinline__ float4 load(int j, int ch) const {
+    return *reinterpret_cast<const float4*>(base + (long long)j * lda + 4 * ch);
+  }
+};
+
+template <> struct ALoader<FMT_BF16X2> {
+  const uint16_t* hi;
+  const uint16_t* lo;
+  long long lda;
+  __device__ ALoader(const ColArgs& a, int k)
+      : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA),
+        lo(static_cast<const uint16_t*>(a.Alo) + (long long)k * a.sA), lda(a.lda) {}
+  __device__ ALoader(const AUArgs& a, int k)
+      : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA),
+        lo(static_cast<const uint16_t*>(a.Alo) + (long long)k * a.sA), lda(a.lda) {}
+  __device__ __forceinline__ float4 load(int j, int ch) const {
+    const uint2 h = *reinterpret_cast<const uint2*>(hi + (long long)j * lda + 4 * ch);
+    const uint2 l = *reinterpret_cast<const uint2*>(lo + (long long)j * lda + 4 * ch);
+    // hi + lo is exact in FP32 (lo is the bf16 rounding of the FP32 remainder)
+    float4 v;
+    v.x = bf16_to_f32(h.x & 0xffffu) + bf16_to_f32(l.x & 0xffffu);
+    v.y = bf16_to_f32(h.x >> 16) + bf16_to_f32(l.x >> 16);
+    v.z = bf16_to_f32(h.y & 0xffffu) + bf16_to_f32(l.y & 0xffffu);
+    v.w = bf16_to_f32(h.y >> 16) + bf16_to_f32(l.y >> 16);
+    return v;
+  }
+};
+
+template <> struct ALoader<FMT_BF16HI> {
+  const uint16_t* hi;
+  long long lda;
+  __device__ ALoader(const ColArgs& a, int k)
+      : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
+  __device__ ALoader(const AUArgs& a, int k)
+      : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
+  __device__ __forceinline__ float4 load(int j, int ch) const {
+    const uint2 h = *reinterpret_cast<const uint2*>(hi + (long long)j * lda + 4 * ch);
+    return make_float4(bf16_to_f32(h.x & 0xffffu), bf16_to_f32(h.x >> 16),
+                       bf16_to_f32(h.y & 0xffffu), bf16_to_f32(h.y >> 16));
+  }
+};
+
+// Zero the components of a 4-row chunk that lie at or beyond row m (nv = valid rows, 0..4).
+__device__ __forceinline__ float4 mask_rows(float4 v, int nv) {
+  v.x = nv > 0 ? v.x : 0.f;
+  v.y = nv > 1 ? v.y : 0.f;
+  v.z = nv > 2 ? v.z : 0.f;
+  v.w = nv > 3 ? v.w : 0.f;
+  return v;
+}
+
+__device__ __forceinline__ float dot4(float4 a, float4 b) {
+  return fmaf(a.w, b.w, fmaf(a.z, b.z, fmaf(a.y, b.y, a.x * b.x)));
+}
+__device__ __forceinline__ float4 axpy4(float s, float4 x, float4 y) {
+  return make_float4(fmaf(s, x.x, y.x), fmaf(s, x.y, y.y), fmaf(s, x.z, y.z), fmaf(s, x.w, y.w));
+}
+__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+  return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+}
+__device__ __forceinline__ float4 sub4(float4 a, float4 b) {
+  return make_float4(a.x - b.x, a.y - b.y, a.z - b.z, a.w - b.w);
+}
+__device__ __forceinline__ float get4(float4 v, int e) {
+  return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
+}
+
+// Lower Cholesky factor L of an SPD r x r FP64 matrix G (row-major), then
+// G^{-1} = L^{-T} L^{-1} into Ginv.  Single thread; L and y (r doubles) are
+// scratch (LDS).  Returns false, and writes the identity, if a pivot is not
+// positive.
+__device__ inline bool chol_inverse(const double* G, double* L, double* Ginv, double* y, int r) {
+  for (int j = 0; j < r; ++j) {
+    double s = G[j * r + j];
+    for (int p = 0; p < j; ++p) s -= L[j * r + p] * L[j * r + p];
+    if (!(s > 0.0)) {
+      for (int i = 0; i < r * r; ++i) Ginv[i] = (i % (r + 1) == 0) ? 1.0 : 0.0;
+      return false;
+    }
+    const double d = sqrt(s);
+    L[j * r + j] = d;
+    for (int i = j + 1; i < r; ++i) {
+      double t = G[i * r + j];
+      for (int p = 0; p < j; ++p) t -= L[i * r + p] * L[j * r + p];
+      L[i * r + j] = t / d;
+    }
+    for (int i = 0; i < j; ++i) L[i * r + j] = 0.0;
+  }
+  // column c of G^{-1}: solve L y = e_c, then L^T x = y
+  for (int c = 0; c < r; ++c) {
+    for (int i = 0; i < r; ++i) {
+      double t = (i == c) ? 1.0 : 0.0;
+      for (int p = 0; p < i; ++p) t -= L[i * r + p] * y[p];
+      y[i] = t / L[i * r + i];
+    }
+    for (int i = r - 1; i >= 0; --i) {
+      double t = y[i];
+      for (int p = i + 1; p < r; ++p) t -= L[p * r + i] * Ginv[p * r + c];
+      Ginv[i * r + c] = t / L[i * r + i];
+    }
+  }
+  return true;
+}
+
+__host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
+
+// LDS layout of the column kernel in bytes; used by the host to size the
+// launch and by the kernel to carve its dynamic shared memory.
+struct ColLayout {
+  size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, total;
+  int mq;
+  __host__ __device__ ColLayout(int n, int m, int r, int rho, int project) {
+    mq = ((m + 3) / 4) * 4;
+    size_t o = 0;
+    ginv = o; o = align16(o + (project ? 8 * (size_t)r * r : 0));
+    P = o;    o = align16(o + (project ? 4 * (size_t)m * r : 0));
+    wpart = o; o = align16(o + 4 * (size_t)kWaves * mq);
+    g = o;    o = align16(o + 4 * (size_t)n);
+    sd = o;   o = align16(o + 4 * (size_t)n);
+    inT = o;  o = align16(o + 4 * (size_t)((n + 31) / 32));
+    Ti = o;   o = align16(o + 4 * (size_t)rho);
+    Tv = o;   o = align16(o + 4 * (size_t)rho);
+    red = o;  o = align16(o + 4 * 4 * kWaves + 8 * 2 * kWaves);
+    total = o;
+  }
+};
+
+// LDS layout of the A_k U kernel.
+struct AULayout {
+  size_t P, gpart, G, L, Gi, y, total;
+  __host__ __device__ AULayout(int m, int r) {
+    size_t o = 0;
+    P = o;     o = align16(o + 4 * (size_t)m * r);
+    gpart = o; o = align16(o + 8 * (size_t)kThreads);
+    G = o;     o = align16(o + 8 * (size_t)r * r);
+    L = o;     o = align16(o + 8 * (size_t)r * r);
+    Gi = o;    o = align16(o + 8 * (size_t)r * r);
+    y = o;     o = align16(o + 8 * (size_t)r);
+    total = o;
+  }
+};
+
+}  // namespace altg

@@ -1,0 +1,574 @@
+// Column kernels of AltGDmin-LR+S for gfx950.
+//
+// One workgroup (4 waves) owns one column k and streams its A_k (m x n,
+// column-major, row index fastest) with coalesced 16-byte loads.  Lane l of
+// every wave holds rows 4*(l + 64c) .. +3 for c < NC, so a column j of A_k is
+// read by one wave as NC contiguous 1 KiB segments.
+//
+//  k_au  : P_k = A_k U (m x r), G_k = P_k^T P_k in FP64, G_k^{-1} by Cholesky
+//          (the pieces of (A_k U)^dagger, eq. (bk_LS)).  U is read with
+//          wave-uniform (scalar) loads; waves split the columns j of A_k and
+//          their partial P_k are summed in LDS in a fixed order.
+//  k_col : tau iterations of IHT (Alg. 2) on column k, then the LS solve for
+//          b_k (eq. (bk_LS)), the residual r_k = A_k(U b_k + s_k) - y_k and
+//          h_k = A_k^T r_k for grad_U f (Sec. 2.1), or the back-projection
+//          A_k^T (y_k - A_k s_k) of the initialisation (Sec. 2.3).
+//
+// One IHT iteration costs one gather of the rho support columns of A_k
+// (A_k s_k), one streaming pass over A_k that forms g_j = A_j^T u and, for the
+// columns j of the current support T, accumulates w = sum_{j in T} g_j A_j
+// (the M g_T of the normalised step) while A_j is still in registers, and a
+// block-wide exact top-rho selection.  In the GDmin loop the projector
+// Pi_k v = v - P_k G_k^{-1} P_k^T v supplies z_k and M_k = Pi_k A_k of Sec. 2.2
+// without forming M_k; since Pi_k is symmetric and idempotent,
+// M_k^T (M_k s - z_k) = A_k^T Pi_k (A_k s - y_k).
+#include "launch.h"
+
+namespace altg {
+
+// ---------------------------------------------------------------- helpers
+
+template <int NC>
+struct Lane {
+  int ch[NC];  // 4-row chunk index held by this lane
+  int nv[NC];  // number of rows of that chunk below m
+  __device__ Lane(int lane, int m) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      ch[c] = lane + 64 * c;
+      const int v = m - 4 * ch[c];
+      nv[c] = v < 0 ? 0 : (v > 4 ? 4 : v);
+    }
+  }
+};
+
+// Sum the per-wave partial vectors of all waves (fixed order 0..W-1); every
+// wave ends with the same total.  Two barriers.
+template <int NC>
+__device__ __forceinline__ void xwave_sum(float4 (&v)[NC], const Lane<NC>& ln, float* wpart, int mq,
+                                          int wave) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (ln.nv[c] > 0) *reinterpret_cast<float4*>(wpart + wave * mq + 4 * ln.ch[c]) = v[c];
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    if (ln.nv[c] > 0) {
+      float4 s = *reinterpret_cast<const float4*>(wpart + 4 * ln.ch[c]);
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) s = add4(s, *reinterpret_cast<const float4*>(wpart + w * mq + 4 * ln.ch[c]));
+      v[c] = s;
+    }
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ double xwave_sum_scalar(double x, double* redd, int lane, int wave) {
+  if (lane == 0) redd[wave] = x;
+  __syncthreads();
+  double s = redd[0];
+#pragma unroll
+  for (int w = 1; w < kWaves; ++w) s += redd[w];
+  __syncthreads();
+  return s;
+}
+
+// out = sum_{t < cnt} coef[t] * A_k[:, idx[t]]  (idx, coef in LDS), all waves get the total.
+template <int FMT, int NC>
+__device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln, const int* idx,
+                                       const float* coef, int cnt, float4 (&out)[NC], float* wpart,
+                                       int mq, int wave) {
+  float4 acc[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll 4
+  for (int t = wave; t < cnt; t += kWaves) {
+    const int j = idx[t];
+    const float cf = coef[t];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      if (ln.nv[c] > 0) acc[c] = axpy4(cf, mask_rows(L.load(j, ln.ch[c]), ln.nv[c]), acc[c]);
+  }
+  xwave_sum<NC>(acc, ln, wpart, mq, wave);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[c] = acc[c];
+}
+
+// v <- v - P_k d with d = G_k^{-1} P_k^T v (FP64 products and solve).  Every
+// wave computes the same result from its own copy of v.  If bl != nullptr,
+// lane i < r receives b_i = -d_i (the LS coefficients when v = A_k s_k - y_k).
+template <int NC>
+__device__ __forceinline__ void project(float4 (&v)[NC], const Lane<NC>& ln, const float* Pl,
+                                        const double* Gi, int r, int lane, double* bl) {
+  double myc = 0.0;
+  for (int rr = 0; rr < r; ++rr) {
+    double part = 0.0;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e < ln.nv[c]) part = fma((double)Pl[(4 * ln.ch[c] + e) * r + rr], (double)get4(v[c], e), part);
+    const double tot = wave_sum(part);
+    if (lane == rr) myc = tot;
+  }
+  double myd = 0.0;
+  for (int jj = 0; jj < r; ++jj) {
+    const double cj = __shfl(myc, jj);
+    if (lane < r) myd = fma(Gi[lane * r + jj], cj, myd);
+  }
+  double acc[NC][4];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[c][e] = (double)get4(v[c], e);
+  for (int rr = 0; rr < r; ++rr) {
+    const double drr = __shfl(myd, rr);
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (e < ln.nv[c]) acc[c][e] = fma(-(double)Pl[(4 * ln.ch[c] + e) * r + rr], drr, acc[c][e]);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    v[c] = make_float4((float)acc[c][0], (float)acc[c][1], (float)acc[c][2], (float)acc[c][3]);
+  if (bl) *bl = -myd;
+}
+
+template <int NC>
+__device__ __forceinline__ double sumsq(const float4 (&v)[NC]) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    s = fma((double)v[c].x, (double)v[c].x, s);
+    s = fma((double)v[c].y, (double)v[c].y, s);
+    s = fma((double)v[c].z, (double)v[c].z, s);
+    s = fma((double)v[c].w, (double)v[c].w, s);
+  }
+  return wave_sum(s);
+}
+
+// Streaming pass over A_k: gl[j] = A_j^T u for every column j; for j in the
+// support bitmap inT (if given) also wacc += gl[j] * A_j and gT2 += gl[j]^2.
+template <int FMT, int NC>
+__device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
+                                           int n, float* gl, const unsigned* inT, float4 (&wacc)[NC],
+                                           double& gT2, int lane, int wave) {
+  constexpr int JU = 4;
+  for (int j0 = wave; j0 < n; j0 += kWaves * JU) {
+    float4 av[JU][NC];
+#pragma unroll
+    for (int ju = 0; ju < JU; ++ju) {
+      const int j = j0 + ju * kWaves;
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+        av[ju][c] = (j < n && ln.nv[c] > 0) ? mask_rows(L.load(j, ln.ch[c]), ln.nv[c])
+                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    float d[JU];
+#pragma unroll
+    for (int ju = 0; ju < JU; ++ju) {
+      float s = 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) s += dot4(av[ju][c], u[c]);
+      d[ju] = s;
+    }
+#pragma unroll
+    for (int ju = 0; ju < JU; ++ju) d[ju] = wave_sum(d[ju]);
+#pragma unroll
+    for (int ju = 0; ju < JU; ++ju) {
+      const int j = j0 + ju * kWaves;
+      if (j < n) {
+        if (lane == 0) gl[j] = d[ju];
+        if (inT && ((inT[j >> 5] >> (j & 31)) & 1u)) {
+#pragma unroll
+          for (int c = 0; c < NC; ++c) wacc[c] = axpy4(d[ju], av[ju][c], wacc[c]);
+          gT2 = fma((double)d[ju], (double)d[ju], gT2);
+        }
+      }
+    }
+  }
+}
+
+// HardThreshold of Alg. 2 on vals[0..n) (LDS): the rho entries of largest
+// |v|, lower index first on ties, written ascending to idx/val (LDS).
+// Exact: the rho-th largest magnitude T is found by a bitwise search on the
+// FP32 magnitude bits (monotone in |v|), ties at T are resolved in index order.
+// Returns the number of NaNs seen (block-uniform).
+__device__ int block_select(const float* vals, int n, int rho, int* idx, float* val, int* redi) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  if (rho <= 0) return 0;
+  unsigned T = 0u;
+  for (int b = 30; b >= 0; --b) {
+    const unsigned cand = T | (1u << b);
+    int cnt = 0;
+    for (int j = tid; j < n; j += kThreads) cnt += ((__float_as_uint(vals[j]) & 0x7fffffffu) >= cand) ? 1 : 0;
+    cnt = wave_sum(cnt);
+    int* buf = redi + (b & 1) * kWaves;
+    if (lane == 0) buf[wave] = cnt;
+    __syncthreads();
+    int tot = 0;
+#pragma unroll
+    for (int w = 0; w < kWaves; ++w) tot += buf[w];
+    if (tot >= rho) T = cand;
+  }
+  int gt = 0, nan = 0;
+  for (int j = tid; j < n; j += kThreads) {
+    const unsigned key = __float_as_uint(vals[j]) & 0x7fffffffu;
+    gt += key > T ? 1 : 0;
+    nan += key > 0x7f800000u ? 1 : 0;
+  }
+  gt = wave_sum(gt);
+  nan = wave_sum(nan);
+  int* buf2 = redi + 2 * kWaves;
+  if (lane == 0) {
+    buf2[wave] = gt;
+    buf2[kWaves + wave] = nan;
+  }
+  __syncthreads();
+  int gtt = 0, nant = 0;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    gtt += buf2[w];
+    nant += buf2[kWaves + w];
+  }
+  const int need_eq = rho - gtt;
+  if (wave == 0) {
+    const unsigned long long lt = (1ull << lane) - 1ull;
+    int base_eq = 0, base_pos = 0;
+    for (int j0 = 0; j0 < n; j0 += 64) {
+      const int j = j0 + lane;
+      const bool valid = j < n;
+      const float x = valid ? vals[j] : 0.f;
+      const unsigned key = __float_as_uint(x) & 0x7fffffffu;
+      const bool eq = valid && key == T;
+      const bool gtb = valid && key > T;
+      const unsigned long long meq = __ballot(eq);
+      const int eq_rank = base_eq + __popcll(meq & lt);
+      const bool sel = gtb || (eq && eq_rank < need_eq);
+      const unsigned long long msel = __ballot(sel);
+      const int pos = base_pos + __popcll(msel & lt);
+      if (sel) {
+        idx[pos] = j;
+        val[pos] = x;
+      }
+      base_eq += __popcll(meq);
+      base_pos += __popcll(msel);
+    }
+  }
+  __syncthreads();
+  return nant;
+}
+
+// ---------------------------------------------------------------- k_col
+
+template <int FMT, int NC>
+__global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  const int n = a.n, m = a.m, r = a.r, rho = a.rho;
+  const ColLayout lay(n, m, r, rho, a.project);
+  double* Gi = reinterpret_cast<double*>(smem + lay.ginv);
+  float* Pl = reinterpret_cast<float*>(smem + lay.P);
+  float* wpart = reinterpret_cast<float*>(smem + lay.wpart);
+  float* gl = reinterpret_cast<float*>(smem + lay.g);
+  float* sd = reinterpret_cast<float*>(smem + lay.sd);
+  unsigned* inT = reinterpret_cast<unsigned*>(smem + lay.inT);
+  int* Ti = reinterpret_cast<int*>(smem + lay.Ti);
+  float* Tv = reinterpret_cast<float*>(smem + lay.Tv);
+  int* redi = reinterpret_cast<int*>(smem + lay.red);
+  double* redd = reinterpret_cast<double*>(smem + lay.red + 16 * kWaves);
+  const int mq = lay.mq;
+  const int nwords = (n + 31) >> 5;
+
+  const ALoader<FMT> L(a, k);
+  const Lane<NC> ln(lane, m);
+
+  float4 yv[NC];
+  {
+    const float* yk = a.Y + (long long)k * a.ldy;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      float t[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t[e] = (e < ln.nv[c]) ? yk[4 * ln.ch[c] + e] : 0.f;
+      yv[c] = make_float4(t[0], t[1], t[2], t[3]);
+    }
+  }
+
+  for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
+  for (int w = tid; w < nwords; w += kThreads) inT[w] = 0u;
+  if (a.project) {
+    const float* Pk = a.P + (long long)k * m * r;
+    for (int t = tid; t < m * r; t += kThreads) Pl[t] = Pk[t];
+    const double* Gk = a.Ginv + (long long)k * r * r;
+    for (int t = tid; t < r * r; t += kThreads) Gi[t] = Gk[t];
+  }
+  __syncthreads();
+  bool hasT = a.has_support != 0;
+  if (hasT) {
+    for (int t = tid; t < rho; t += kThreads) {
+      int j = a.Tidx[(long long)k * rho + t];
+      float v = a.Tval[(long long)k * rho + t];
+      if (j < 0 || j >= n) {   // invalid caller state: flag it and keep every access in bounds
+        if (a.flags) atomicOr(&a.flags[k], 4);
+        j = 0;
+        v = 0.f;
+      }
+      Ti[t] = j;
+      Tv[t] = v;
+      sd[j] = v;
+      atomicOr(&inT[j >> 5], 1u << (j & 31));
+    }
+  }
+  __syncthreads();
+  int nan_seen = 0;
+
+  for (int it = 0; it < a.tau; ++it) {
+    // u = Pi (A_k s - y_k)   (Pi = I in the initialisation)
+    float4 v[NC];
+    gather<FMT, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);
+    if (a.project) project<NC>(v, ln, Pl, Gi, r, lane, nullptr);
+
+    // g = A_k^T u; w = A_k g_T on the current support
+    float4 w[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) w[c] = make_float4(0.f, 0.f, 0.f, 0.f);
+    double gT2 = 0.0;
+    fused_pass<FMT, NC>(L, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
+    __syncthreads();
+    if (hasT) {
+      xwave_sum<NC>(w, ln, wpart, mq, wave);
+      gT2 = xwave_sum_scalar(gT2, redd, lane, wave);
+    } else {
+      // no support yet (s = 0): restrict to the support of HardThreshold(g, rho)
+      nan_seen += block_select(gl, n, rho, Ti, Tv, redi);
+      gather<FMT, NC>(L, ln, Ti, Tv, rho, w, wpart, mq, wave);
+      gT2 = 0.0;
+      for (int t = 0; t < rho; ++t) gT2 = fma((double)Tv[t], (double)Tv[t], gT2);
+    }
+    if (a.project) project<NC>(w, ln, Pl, Gi, r, lane, nullptr);
+    const double ww = sumsq<NC>(w);
+    const double mu = (ww > 0.0 && isfinite(ww) && isfinite(gT2)) ? gT2 / ww : 0.0;
+    const bool last = (it == a.tau - 1);
+    if (last && a.G_out)
+      for (int j = tid; j < n; j += kThreads) a.G_out[(long long)k * n + j] = gl[j];
+    if (last && a.mu_out && tid == 0) a.mu_out[k] = mu;
+    // s - mu g, then HardThreshold
+    for (int j = tid; j < n; j += kThreads) gl[j] = (float)fma(-mu, (double)gl[j], (double)sd[j]);
+    __syncthreads();
+    nan_seen += block_select(gl, n, rho, Ti, Tv, redi);
+    for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
+    for (int wd = tid; wd < nwords; wd += kThreads) inT[wd] = 0u;
+    __syncthreads();
+    for (int t = tid; t < rho; t += kThreads) {
+      const int j = Ti[t];
+      sd[j] = Tv[t];
+      atomicOr(&inT[j >> 5], 1u << (j & 31));
+    }
+    __syncthreads();
+    hasT = true;
+  }
+
+  if (a.tail != TAIL_NONE) {
+    float4 v[NC];
+    gather<FMT, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);   // A_k s_k - y_k
+    if (a.tail == TAIL_LSGRAD) {
+      // b_k = G^{-1} P^T (y - A s); r_k = P b + A s - y = Pi (A s - y)
+      double b = 0.0;
+      project<NC>(v, ln, Pl, Gi, r, lane, &b);
+      const double rr = sumsq<NC>(v);
+      if (wave == 0 && lane < r) a.Bt[(long long)k * r + lane] = (float)b;
+      if (tid == 0 && a.rr) a.rr[k] = rr;
+    } else {
+#pragma unroll
+      for (int c = 0; c < NC; ++c) v[c] = make_float4(-v[c].x, -v[c].y, -v[c].z, -v[c].w);   // y - A s
+      const double yy = sumsq<NC>(yv);
+      if (tid == 0 && a.rr) a.rr[k] = yy;
+    }
+    float4 w[NC];
+    double dummy = 0.0;
+    fused_pass<FMT, NC>(L, ln, v, n, gl, nullptr, w, dummy, lane, wave);
+    __syncthreads();
+    for (int j = tid; j < n; j += kThreads) a.H[(long long)k * n + j] = gl[j];
+  }
+
+  for (int t = tid; t < rho; t += kThreads) {
+    a.Tidx[(long long)k * rho + t] = Ti[t];
+    a.Tval[(long long)k * rho + t] = Tv[t];
+  }
+  if (tid == 0 && nan_seen > 0 && a.flags) a.flags[k] |= 1;
+}
+
+// ---------------------------------------------------------------- k_au
+
+template <int FMT, int NC, int R>
+__global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  const int n = a.n, m = a.m, r = a.r;
+  const AULayout lay(m, r);
+  float* Pl = reinterpret_cast<float*>(smem + lay.P);
+  double* gpart = reinterpret_cast<double*>(smem + lay.gpart);
+  double* Gl = reinterpret_cast<double*>(smem + lay.G);
+  double* Ll = reinterpret_cast<double*>(smem + lay.L);
+  double* Gil = reinterpret_cast<double*>(smem + lay.Gi);
+  double* yl = reinterpret_cast<double*>(smem + lay.y);
+  const ALoader<FMT> L(a, k);
+  const Lane<NC> ln(lane, m);
+
+  float acc[NC][4][R];
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = 0.f;
+
+  const float* U = a.U;
+#pragma unroll 2
+  for (int j = wave; j < n; j += kWaves) {
+    float4 av[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      av[c] = ln.nv[c] > 0 ? mask_rows(L.load(j, ln.ch[c]), ln.nv[c]) : make_float4(0.f, 0.f, 0.f, 0.f);
+    float uj[R];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) uj[rr] = (rr < r) ? U[(long long)j * r + rr] : 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = fmaf(get4(av[c], e), uj[rr], acc[c][e][rr]);
+  }
+  // partial P of the waves summed in wave order
+  for (int w = 0; w < kWaves; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (e < ln.nv[c]) {
+            const int i = 4 * ln.ch[c] + e;
+#pragma unroll
+            for (int rr = 0; rr < R; ++rr)
+              if (rr < r) Pl[i * r + rr] = (w == 0) ? acc[c][e][rr] : Pl[i * r + rr] + acc[c][e][rr];
+          }
+    }
+    __syncthreads();
+  }
+  float* Pk = a.P + (long long)k * m * r;
+  for (int t = tid; t < m * r; t += kThreads) Pk[t] = Pl[t];
+
+  // G = P^T P in FP64: entry e = (ra, rb), ra <= rb; threads split the rows
+  const int E = r * (r + 1) / 2;
+  const int parts = kThreads / E;
+  const int e = tid % E, part = tid / E;
+  int ra = 0, rb = 0;
+  {
+    int base = 0;
+    for (ra = 0; ra < r; ++ra) {
+      const int cnt = r - ra;
+      if (e < base + cnt) { rb = ra + (e - base); break; }
+      base += cnt;
+    }
+  }
+  double s = 0.0;
+  if (part < parts)
+    for (int i = part; i < m; i += parts) s = fma((double)Pl[i * r + ra], (double)Pl[i * r + rb], s);
+  gpart[tid] = s;
+  __syncthreads();
+  if (tid < E) {
+    double t = 0.0;
+    for (int p = 0; p < parts; ++p) t += gpart[p * E + tid];
+    Gl[ra * r + rb] = t;
+    Gl[rb * r + ra] = t;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (!chol_inverse(Gl, Ll, Gil, yl, r) && a.flags) a.flags[k] |= 2;
+  }
+  __syncthreads();
+  double* Gk = a.Ginv + (long long)k * r * r;
+  for (int t = tid; t < r * r; t += kThreads) Gk[t] = Gil[t];
+}
+
+// HardThreshold of one vector per workgroup (the step-level select entry point).
+__global__ __launch_bounds__(kThreads) void k_select(const float* V, int n, long long ldv, int rho, int* idx,
+                                                     float* val, int* flags) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  float* vl = reinterpret_cast<float*>(smem);
+  int* Ti = reinterpret_cast<int*>(smem + align16(4 * (size_t)n));
+  float* Tv = reinterpret_cast<float*>(smem + align16(4 * (size_t)n) + align16(4 * (size_t)rho));
+  int* redi = reinterpret_cast<int*>(smem + align16(4 * (size_t)n) + 2 * align16(4 * (size_t)rho));
+  const int c = blockIdx.x, tid = threadIdx.x;
+  for (int j = tid; j < n; j += kThreads) vl[j] = V[(long long)c * ldv + j];
+  __syncthreads();
+  const int nan = block_select(vl, n, rho, Ti, Tv, redi);
+  for (int t = tid; t < rho; t += kThreads) {
+    idx[(long long)c * rho + t] = Ti[t];
+    val[(long long)c * rho + t] = Tv[t];
+  }
+  if (tid == 0 && flags) flags[c] = nan > 0 ? 1 : 0;
+}
+
+size_t select_lds_bytes(int n, int rho) { return align16(4 * (size_t)n) + 2 * align16(4 * (size_t)rho) + 64; }
+
+hipError_t launch_select(const float* V, int n, int count, long long ldv, int rho, int* idx, float* val,
+                         int* flags, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_select, dim3(count), dim3(kThreads), select_lds_bytes(n, rho), st, V, n, ldv, rho, idx, val,
+                     flags);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- dispatch tables
+
+typedef void (*col_fn)(ColArgs);
+typedef void (*au_fn)(AUArgs);
+
+#define COL_ROW(F) {k_col<F, 1>, k_col<F, 2>, k_col<F, 3>, k_col<F, 4>}
+static const col_fn kColTable[3][kNCMax] = {COL_ROW(FMT_F32), COL_ROW(FMT_BF16X2), COL_ROW(FMT_BF16HI)};
+
+// k_au keeps 4*NC*R accumulators per lane; instantiations above 128 are left out.
+template <int F, int NC, int R>
+constexpr au_fn au_inst() { return (4 * NC * R <= 128) ? k_au<F, NC, (4 * NC * R <= 128 ? R : 2)> : nullptr; }
+#define AU_NC(F, NC) {au_inst<F, NC, 2>(), au_inst<F, NC, 4>(), au_inst<F, NC, 6>(), au_inst<F, NC, 8>(), \
+                      au_inst<F, NC, 10>(), au_inst<F, NC, 12>(), au_inst<F, NC, 14>(), au_inst<F, NC, 16>()}
+#define AU_ROW(F) {AU_NC(F, 1), AU_NC(F, 2), AU_NC(F, 3), AU_NC(F, 4)}
+static const au_fn kAUTable[3][kNCMax][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2), AU_ROW(FMT_BF16HI)};
+
+bool au_supported(int m, int r) {
+  const int nc = (m + 255) / 256;
+  const int R = 2 * ((r + 1) / 2);
+  return nc >= 1 && nc <= kNCMax && r >= 1 && r <= kRMax && 4 * nc * R <= 128;
+}
+
+hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
+  const int nc = (a.m + 255) / 256;
+  const ColLayout lay(a.n, a.m, a.r, a.rho, a.project);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColTable[fmt][nc - 1], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
+  const int nc = (a.m + 255) / 256;
+  const int ri = (a.r + 1) / 2 - 1;
+  const AULayout lay(a.m, a.r);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kAUTable[fmt][nc - 1][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  return hipGetLastError();
+}
+
+size_t col_lds_bytes(int n, int m, int r, int rho, int project) { return ColLayout(n, m, r, rho, project).total; }
+size_t au_lds_bytes(int m, int r) { return AULayout(m, r).total; }
+
+}  // namespace altg

@@ -1,0 +1,389 @@
+// Reductions across columns and the U update of AltGDmin-LR+S for gfx950.
+//
+//  k_grad  : partials of grad_U f = sum_k h_k b_k^T (Sec. 2.1) over KS column
+//            splits, each summed in a fixed order (deterministic, no atomics).
+//            The same kernel forms Z = L_0 (L_0^T U) in the subspace iteration.
+//  k_ltu   : T = L_0^T U for the subspace iteration (one wave per column).
+//  k_qr    : one workgroup: sums the partials, sets eta = eta_c / ||grad||_2 at
+//            t = 1 (Sec. 2.6), forms U - eta grad and re-orthonormalises it by
+//            CholeskyQR2 (FP64 Gram and Cholesky, positive-diagonal R), the QR of
+//            the projected GD step in Alg. 1; also the subspace-iteration
+//            orthonormalisation and the residual monitor.
+#include "launch.h"
+
+namespace altg {
+
+__global__ __launch_bounds__(256) void k_grad(const float* __restrict__ H, const float* __restrict__ B, int n,
+                                              int q, int r, int KS, float* __restrict__ gpart,
+                                              const int* skip) {
+  if (skip && *skip) return;
+  __shared__ float red[kWaves][64][kRMax + 1];
+  const int jl = threadIdx.x & 63, ph = wave_id();
+  const int j = blockIdx.x * 64 + jl, ks = blockIdx.y;
+  const int k0 = (int)((long long)q * ks / KS), k1 = (int)((long long)q * (ks + 1) / KS);
+  float acc[kRMax];
+#pragma unroll
+  for (int c = 0; c < kRMax; ++c) acc[c] = 0.f;
+  for (int k = k0 + ph; k < k1; k += kWaves) {
+    const float h = (j < n) ? H[(long long)k * n + j] : 0.f;
+    const float* Bk = B + (long long)k * r;
+#pragma unroll
+    for (int c = 0; c < kRMax; ++c)
+      if (c < r) acc[c] = fmaf(h, Bk[c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < kRMax; ++c) red[ph][jl][c] = acc[c];
+  __syncthreads();
+  if (ph == 0 && j < n) {
+    for (int c = 0; c < r; ++c) {
+      float s = red[0][jl][c];
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) s += red[w][jl][c];
+      gpart[((long long)ks * n + j) * r + c] = s;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_ltu(const float* __restrict__ L0t, const float* __restrict__ U, int n,
+                                             int q, int r, float* __restrict__ T, const int* skip) {
+  if (skip && *skip) return;
+  const int lane = threadIdx.x & 63;
+  const int k = blockIdx.x * kWaves + wave_id();
+  if (k >= q) return;
+  float acc[kRMax];
+#pragma unroll
+  for (int c = 0; c < kRMax; ++c) acc[c] = 0.f;
+  for (int j = lane; j < n; j += 64) {
+    const float l = L0t[(long long)k * n + j];
+#pragma unroll
+    for (int c = 0; c < kRMax; ++c)
+      if (c < r) acc[c] = fmaf(l, U[(long long)j * r + c], acc[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < kRMax; ++c) {
+    if (c < r) {
+      const float s = wave_sum(acc[c]);
+      if (lane == 0) T[(long long)k * r + c] = s;
+    }
+  }
+}
+
+// C = X^T Y (r x r, FP64) over n rows of the n x r row-major X and Y; block-wide.
+__device__ void block_gram(const float* X, const float* Y, int n, int r, double* sh, double* C) {
+  const int tid = threadIdx.x;
+  const int E = r * r, parts = kQRThreads / E;
+  const int e = tid % E, p = tid / E;
+  double s = 0.0;
+  if (p < parts) {
+    const int ra = e / r, rb = e % r;
+    for (int j = p; j < n; j += parts) s = fma((double)X[(long long)j * r + ra], (double)Y[(long long)j * r + rb], s);
+  }
+  sh[tid] = s;
+  __syncthreads();
+  if (tid < E) {
+    double t = 0.0;
+    for (int pp = 0; pp < parts; ++pp) t += sh[pp * E + tid];
+    C[tid] = t;
+  }
+  __syncthreads();
+}
+
+// Largest eigenvalue of a symmetric r x r matrix (cyclic Jacobi, single thread, in place).
+__device__ double jacobi_max_eig(double* W, int r) {
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int a = 0; a < r; ++a) {
+      diag += W[a * r + a] * W[a * r + a];
+      for (int b = a + 1; b < r; ++b) off += W[a * r + b] * W[a * r + b];
+    }
+    if (off <= 1e-30 * diag || off == 0.0) break;
+    for (int p = 0; p < r; ++p) {
+      for (int q = p + 1; q < r; ++q) {
+        const double apq = W[p * r + q];
+        if (apq == 0.0) continue;
+        const double theta = (W[q * r + q] - W[p * r + p]) / (2.0 * apq);
+        const double t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < r; ++k) {   // columns p, q
+          const double wkp = W[k * r + p], wkq = W[k * r + q];
+          W[k * r + p] = c * wkp - s * wkq;
+          W[k * r + q] = s * wkp + c * wkq;
+        }
+        for (int k = 0; k < r; ++k) {   // rows p, q
+          const double wpk = W[p * r + k], wqk = W[q * r + k];
+          W[p * r + k] = c * wpk - s * wqk;
+          W[q * r + k] = s * wpk + c * wqk;
+        }
+      }
+    }
+  }
+  double lam = W[0];
+  for (int a = 1; a < r; ++a) lam = fmax(lam, W[a * r + a]);
+  return lam;
+}
+
+// X (n x r, in place) <- X R^{-1} where X^T X = R^T R (R upper, positive diagonal).
+// Returns false if the Gram matrix is not positive definite.
+__device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W, double* Lf, int* okflag) {
+  const int tid = threadIdx.x;
+  block_gram(X, X, n, r, sh, W);
+  if (tid == 0) {
+    int ok = 1;
+    for (int j = 0; j < r && ok; ++j) {
+      double s = W[j * r + j];
+      for (int p = 0; p < j; ++p) s -= Lf[j * r + p] * Lf[j * r + p];
+      if (!(s > 0.0)) { ok = 0; break; }
+      const double d = sqrt(s);
+      Lf[j * r + j] = d;
+      for (int i = j + 1; i < r; ++i) {
+        double t = W[i * r + j];
+        for (int p = 0; p < j; ++p) t -= Lf[i * r + p] * Lf[j * r + p];
+        Lf[i * r + j] = t / d;
+      }
+    }
+    *okflag = ok;
+  }
+  __syncthreads();
+  if (!*okflag) return false;
+  // row x of X: solve x_new R = x, R[a][c] = Lf[c][a]
+  for (int j = tid; j < n; j += kQRThreads) {
+    double xn[kRMax];
+#pragma unroll
+    for (int c = 0; c < kRMax; ++c) {
+      if (c < r) {
+        double t = (double)X[(long long)j * r + c];
+#pragma unroll
+        for (int a = 0; a < kRMax; ++a)
+          if (a < c) t -= xn[a] * Lf[c * r + a];
+        xn[c] = t / Lf[c * r + c];
+      } else {
+        xn[c] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < kRMax; ++c)
+      if (c < r) X[(long long)j * r + c] = (float)xn[c];
+  }
+  __syncthreads();
+  return true;
+}
+
+__global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
+  __shared__ double sh[kQRThreads];
+  __shared__ double W[kRMax * kRMax], Lf[kRMax * kRMax];
+  __shared__ double eta_s;
+  __shared__ int okflag;
+  const int tid = threadIdx.x;
+  const int n = a.n, r = a.r, nr = n * r;
+  if (a.mode == QR_POWER && a.ctl && a.ctl->conv) return;
+
+  if (a.mode != QR_ORTH) {
+    for (int idx = tid; idx < nr; idx += kQRThreads) {
+      float s = a.gpart[idx];
+      for (int ks = 1; ks < a.KS; ++ks) s += a.gpart[(long long)ks * nr + idx];
+      a.Utmp[idx] = s;
+      if (a.grad_out) a.grad_out[idx] = s;
+    }
+    __syncthreads();
+  }
+  if (a.mode == QR_GD) {
+    const bool have = a.ctl ? (a.ctl->eta_set != 0) : (*a.eta_io > 0.0);
+    if (!have) {
+      block_gram(a.Utmp, a.Utmp, n, r, sh, W);
+      if (tid == 0) {
+        const double lam = jacobi_max_eig(W, r);
+        const double eta = lam > 0.0 ? a.eta_c / sqrt(lam) : 0.0;
+        eta_s = eta;
+        if (a.ctl) {
+          a.ctl->eta = eta;
+          a.ctl->eta_set = 1;
+        } else {
+          *a.eta_io = eta;
+        }
+      }
+    } else if (tid == 0) {
+      eta_s = a.ctl ? a.ctl->eta : *a.eta_io;
+    }
+    __syncthreads();
+    const double eta = eta_s;
+    for (int idx = tid; idx < nr; idx += kQRThreads)
+      a.Utmp[idx] = (float)fma(-eta, (double)a.Utmp[idx], (double)a.U[idx]);
+    __syncthreads();
+  }
+  // CholeskyQR2
+  bool ok = block_cholqr_pass(a.Utmp, n, r, sh, W, Lf, &okflag);
+  if (ok) ok = block_cholqr_pass(a.Utmp, n, r, sh, W, Lf, &okflag);
+  if (!ok) {
+    if (tid == 0 && a.ctl) a.ctl->err |= 2;
+    return;
+  }
+  if (a.mode == QR_POWER) {
+    block_gram(a.U, a.Utmp, n, r, sh, W);   // U_old^T U_new
+    if (tid == 0) {
+      double f = 0.0;
+      for (int e = 0; e < r * r; ++e) f += W[e] * W[e];
+      const double sd = sqrt(fmax(0.0, (double)r - f));
+      a.ctl->power_sd = sd;
+      a.ctl->power_it += 1;
+      if (sd <= a.power_tol) a.ctl->conv = 1;
+    }
+  }
+  for (int idx = tid; idx < nr; idx += kQRThreads) {
+    if (a.mode == QR_GD && a.Uprev) a.Uprev[idx] = a.U[idx];
+    a.U[idx] = a.Utmp[idx];
+  }
+  if (a.mode == QR_GD && a.ctl) {
+    double s = 0.0;
+    int fl = 0;
+    for (int k = tid; k < a.q; k += kQRThreads) {
+      s += a.colrr[k];
+      fl |= a.colflags[k];
+    }
+    sh[tid] = s;
+    __syncthreads();
+    for (int st = kQRThreads / 2; st > 0; st >>= 1) {
+      if (tid < st) sh[tid] += sh[tid + st];
+      __syncthreads();
+    }
+    if (fl) atomicOr(&a.ctl->err, fl);
+    if (tid == 0) {
+      const double resid = a.ctl->ynorm2 > 0.0 ? sqrt(sh[0] / a.ctl->ynorm2) : sqrt(sh[0]);
+      const int t = a.ctl->t;
+      if (a.rlog && t < a.rlog_len) a.rlog[t] = resid;
+      a.ctl->resid = resid;
+      a.ctl->t = t + 1;
+    }
+  }
+}
+
+// ||Y||_F^2 from the per-column values, fixed order.
+__global__ __launch_bounds__(kQRThreads) void k_sum_ctl(const double* colrr, int q, Ctl* ctl) {
+  __shared__ double sh[kQRThreads];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int k = tid; k < q; k += kQRThreads) s += colrr[k];
+  sh[tid] = s;
+  __syncthreads();
+  for (int st = kQRThreads / 2; st > 0; st >>= 1) {
+    if (tid < st) sh[tid] += sh[tid + st];
+    __syncthreads();
+  }
+  if (tid == 0) ctl->ynorm2 = sh[0];
+}
+
+__global__ void k_reset_ctl(Ctl* ctl, int full) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->eta = 0.0;
+    ctl->eta_set = 0;
+    ctl->t = 0;
+    ctl->resid = 0.0;
+    if (full) {
+      ctl->power_sd = 0.0;
+      ctl->ynorm2 = 0.0;
+      ctl->conv = 0;
+      ctl->power_it = 0;
+      ctl->err = 0;
+    }
+  }
+}
+
+__global__ void k_fill_int(int* p, int v, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// U[j][c] = 1 if j % r == c else 0: an orthogonal start block with disjoint supports.
+__global__ void k_fill_basis(float* U, int n, int r) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * r; i += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(i / r), c = (int)(i % r);
+    U[i] = (j % r == c) ? 1.f : 0.f;
+  }
+}
+
+__global__ void k_copy_f(float* dst, const float* src, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_copy_i(int* dst, const int* src, long long count) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+
+__global__ void k_sum_partials(const float* gpart, int KS, long long nr, float* out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nr; i += (long long)gridDim.x * blockDim.x) {
+    float s = gpart[i];
+    for (int ks = 1; ks < KS; ++ks) s += gpart[(long long)ks * nr + i];
+    out[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline int grid_for(long long count, int block) {
+  long long g = (count + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > 4096) g = 4096;
+  return (int)g;
+}
+
+hipError_t launch_grad(const float* H, const float* B, int n, int q, int r, int KS, float* gpart,
+                       const int* skip, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_grad, dim3((n + 63) / 64, KS), dim3(256), 0, st, H, B, n, q, r, KS, gpart, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_ltu(const float* L0t, const float* U, int n, int q, int r, float* T, const int* skip,
+                      hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_ltu, dim3((q + kWaves - 1) / kWaves), dim3(256), 0, st, L0t, U, n, q, r, T, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr(const QRArgs& a, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_qr, dim3(1), dim3(kQRThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_ctl(const double* colrr, int q, Ctl* ctl, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_sum_ctl, dim3(1), dim3(kQRThreads), 0, st, colrr, q, ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_ctl(Ctl* ctl, int full, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, st, ctl, full);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int* p, int v, long long count, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_fill_int, dim3(grid_for(count, 256)), dim3(256), 0, st, p, v, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_basis(float* U, int n, int r, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_fill_basis, dim3(grid_for((long long)n * r, 256)), dim3(256), 0, st, U, n, r);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_copy_f, dim3(grid_for(count, 256)), dim3(256), 0, st, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_sum_partials(const float* gpart, int KS, long long nr, float* out, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_sum_partials, dim3(grid_for(nr, 256)), dim3(256), 0, st, gpart, KS, nr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_i(int* dst, const int* src, long long count, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_copy_i, dim3(grid_for(count, 256)), dim3(256), 0, st, dst, src, count);
+  return hipGetLastError();
+}
+
+}  // namespace altg

@@ -1,0 +1,47 @@
+// Launchers of the AltGDmin-LR+S kernels (host side, internal to the library).
+#pragma once
+#include "common.h"
+
+namespace altg {
+
+enum { QR_GD = 0, QR_POWER = 1, QR_ORTH = 2 };
+
+struct QRArgs {
+  int n, r, KS, mode;
+  const float* gpart;      // KS x n x r partial sums (GD: gradient, POWER: L0 L0^T U)
+  float* U;                // n x r, in/out
+  float* Uprev;            // n x r, GD: receives the U the step started from
+  float* Utmp;             // n x r scratch; ORTH: the block to orthonormalise
+  Ctl* ctl;
+  double eta_c, power_tol;
+  const double* colrr;     // q residual norms^2 of the iteration (GD)
+  const int* colflags;     // q column flags (GD)
+  int q;
+  double* rlog;            // residual log (GD)
+  int rlog_len;
+  float* grad_out;         // optional copy of the summed partials
+  double* eta_io;          // op entry: eta in/out (<= 0: compute), used instead of ctl when ctl == nullptr
+};
+
+hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);
+hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
+bool au_supported(int m, int r);
+size_t col_lds_bytes(int n, int m, int r, int rho, int project);
+size_t au_lds_bytes(int m, int r);
+size_t select_lds_bytes(int n, int rho);
+hipError_t launch_select(const float* V, int n, int count, long long ldv, int rho, int* idx, float* val,
+                         int* flags, hipStream_t st);
+hipError_t launch_sum_partials(const float* gpart, int KS, long long nr, float* out, hipStream_t st);
+hipError_t launch_grad(const float* H, const float* B, int n, int q, int r, int KS, float* gpart,
+                       const int* skip, hipStream_t st);
+hipError_t launch_ltu(const float* L0t, const float* U, int n, int q, int r, float* T, const int* skip,
+                      hipStream_t st);
+hipError_t launch_qr(const QRArgs& a, hipStream_t st);
+hipError_t launch_sum_ctl(const double* colrr, int q, Ctl* ctl, hipStream_t st);
+hipError_t launch_reset_ctl(Ctl* ctl, int full, hipStream_t st);
+hipError_t launch_fill_int(int* p, int v, long long count, hipStream_t st);
+hipError_t launch_fill_basis(float* U, int n, int r, hipStream_t st);
+hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStream_t st);
+hipError_t launch_copy_i(int* dst, const int* src, long long count, hipStream_t st);
+
+}  // namespace altg

@@ -24,6 +24,7 @@ def gpu_available() -> bool:
 @pytest.fixture(scope="session")
 def lib():
     """The HIP library through its Python binding; fails loudly if it is not built."""
+    import torch  # noqa: F401  (torch's HIP runtime must be loaded before the library)
     from paper_2311_03824_amd import altgdmin
     altgdmin.load()
     return altgdmin

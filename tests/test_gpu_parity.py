@@ -1,0 +1,363 @@
+"""Parity of every step of the HIP path against the FP64 oracle (through the C ABI).
+
+Inputs come from the seeded generator only; the oracle never sees a value the
+GPU produced.  Tolerances:
+  * the selection (HardThreshold) is compared bit-exactly on identical FP32 input;
+  * FP32 dot products of L terms accumulated serially per lane, then by a
+    wave/waves tree, are bounded elementwise by (L_serial + 8) * 2^-24 * sum|terms|
+    (the gamma_L bound of recursive summation), written per test;
+  * normwise relative errors of FP32 results are checked at 1e-5;
+  * subspaces agree to ||(I - U1 U1^T) U2||_F <= 1e-5 (FP32 path).
+"""
+import numpy as np
+import pytest
+
+from oracle import altgdmin_oracle as O
+from paper_2311_03824_amd import instances as I
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as _t
+    if not _t.cuda.is_available():
+        pytest.fail("GPU tests need a ROCm GPU")
+    return _t
+
+
+def dev(torch, x, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def problem(lib, torch, inst, bf16=False):
+    A = dev(torch, inst.At)
+    Y = dev(torch, inst.Y32)
+    keep = [A, Y]
+    if bf16:
+        hi = dev(torch, inst.A_hi.view(np.int16))
+        lo = dev(torch, inst.A_lo.view(np.int16))
+        keep += [hi, lo]
+        p = lib.make_problem(hi, Y, inst.r, inst.rho, A_lo=lo, m=inst.m)
+    else:
+        p = lib.make_problem(A, Y, inst.r, inst.rho, m=inst.m)
+    return p, keep
+
+
+# Shapes: several 256-row chunks and column blocks plus ragged tails (m % 4 != 0, n % 64 != 0).
+SHAPES = [
+    dict(n=100, q=24, m=40, r=2, rho=2),
+    dict(n=301, q=37, m=150, r=3, rho=7),       # m % 4 = 2
+    dict(n=517, q=20, m=333, r=5, rho=11),      # two chunks, ragged
+    dict(n=260, q=16, m=701, r=8, rho=9),       # three chunks
+]
+
+
+# ---------------------------------------------------------------- a7: HardThreshold
+
+@pytest.mark.parametrize("n,rho", [(1, 1), (7, 0), (64, 5), (100, 2), (1000, 50), (1537, 300), (2048, 2048)])
+def test_select_bitexact(lib, torch, n, rho):
+    rng = np.random.default_rng(n * 31 + rho)
+    count = 9
+    V = rng.standard_normal((count, n)).astype(np.float32)
+    V[1] = np.round(V[1] * 2)                          # many exact ties, both signs, zeros
+    V[2] = 0.0
+    V[3, 1::2] = -V[3, 0::2][: len(V[3, 1::2])]      # +-x pairs tie in magnitude
+    V[4] = np.float32(1.0)
+    V[5, : n // 2] = -0.0
+    idx = torch.zeros((count, max(rho, 1)), dtype=torch.int32, device="cuda")
+    val = torch.zeros((count, max(rho, 1)), dtype=torch.float32, device="cuda")
+    flags = torch.zeros(count, dtype=torch.int32, device="cuda")
+    lib.altgdmin_op_select(dev(torch, V), rho, idx, val, flags)
+    torch.cuda.synchronize()
+    dense, ref = O.hard_threshold(V.astype(np.float64), rho)
+    assert np.array_equal(host(idx)[:, :rho], ref)
+    refv = dense[np.arange(count)[:, None], ref]
+    assert np.array_equal(host(val)[:, :rho].astype(np.float64), refv)
+    assert not host(flags).any()
+
+
+def test_select_flags_nan(lib, torch):
+    V = np.ones((2, 50), np.float32)
+    V[1, 7] = np.nan
+    idx = torch.zeros((2, 3), dtype=torch.int32, device="cuda")
+    val = torch.zeros((2, 3), dtype=torch.float32, device="cuda")
+    flags = torch.zeros(2, dtype=torch.int32, device="cuda")
+    lib.altgdmin_op_select(dev(torch, V), 3, idx, val, flags)
+    torch.cuda.synchronize()
+    assert host(flags).tolist() == [0, 1]
+
+
+# ---------------------------------------------------------------- a4, a5: A_k U, Gram, inverse
+
+def _rand_U(n, r, seed):
+    return O.qr_pos(np.random.default_rng(seed).standard_normal((n, r)))[0].astype(np.float32)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("bf16", [False, True])
+def test_au_gram(lib, torch, shape, bf16):
+    inst = I.make_instance(**shape, seed=5, bf16_planes=True)
+    p, keep = problem(lib, torch, inst, bf16)
+    q, m, r, n = inst.q, inst.m, inst.r, inst.n
+    U = _rand_U(n, r, 1)
+    P = torch.zeros((q, m, r), dtype=torch.float32, device="cuda")
+    Gi = torch.zeros((q, r, r), dtype=torch.float64, device="cuda")
+    fl = torch.zeros(q, dtype=torch.int32, device="cuda")
+    lib.altgdmin_op_au(p, dev(torch, U), P, Gi, fl)
+    torch.cuda.synchronize()
+    A = inst.A64()
+    P_ref, G_ref = O.projector_parts(A, U.astype(np.float64))
+    bound = (n / 4 + 8) * U32 * np.matmul(np.abs(A), np.abs(U.astype(np.float64)))
+    Pg = host(P)
+    assert (np.abs(Pg - P_ref) <= bound).all()
+    assert np.linalg.norm(Pg - P_ref) <= 1e-5 * np.linalg.norm(P_ref)
+    # inverse Gram in FP64 from the kernel's own P: tight
+    Pg64 = Pg.astype(np.float64)
+    Gi_own = np.linalg.inv(np.matmul(Pg64.transpose(0, 2, 1), Pg64))
+    assert np.allclose(host(Gi), Gi_own, rtol=1e-9, atol=1e-12 * np.abs(Gi_own).max())
+    assert np.linalg.norm(host(Gi) - np.linalg.inv(G_ref)) <= 1e-4 * np.linalg.norm(np.linalg.inv(G_ref))
+    assert not host(fl).any()
+
+
+# ---------------------------------------------------------------- a1, a6: IHT
+
+def _supports_match(gpu_idx, ref_idx):
+    return np.array([np.array_equal(a, b) for a, b in zip(gpu_idx, ref_idx)])
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_init_iht_matches_oracle(lib, torch, shape):
+    """Alg. 1 initialisation IHT (M = A_k, z = y_k, from s = 0): supports exact, values close."""
+    inst = I.make_instance(**shape, seed=9)
+    p, keep = problem(lib, torch, inst)
+    q, n, rho = inst.q, inst.n, inst.rho
+    A = inst.A64()
+    Y = inst.Y32.astype(np.float64)
+    for tau in (1, 2, 10):
+        Si = torch.zeros((q, rho), dtype=torch.int32, device="cuda")
+        Sv = torch.zeros((q, rho), dtype=torch.float32, device="cuda")
+        G = torch.zeros((q, n), dtype=torch.float32, device="cuda")
+        mu = torch.zeros(q, dtype=torch.float64, device="cuda")
+        lib.altgdmin_op_iht(p, False, None, None, tau, False, Si, Sv, G, mu)
+        torch.cuda.synchronize()
+        trace = []
+        S_ref, idx_ref = O.iht(Y, lambda S: O.apply_A(A, S), lambda V: O.apply_AT(A, V), rho, tau,
+                               np.zeros((q, n)), trace=trace)
+        same = _supports_match(host(Si), idx_ref)
+        assert same.mean() >= 0.9, same.mean()
+        g_ref = trace[-1]["G"]
+        # gradient of the last iteration (columns whose support path agreed)
+        if tau == 1:
+            assert same.all()
+            gg = host(G)
+            assert np.linalg.norm(gg - g_ref) <= 1e-5 * np.linalg.norm(g_ref)
+            assert np.allclose(host(mu), trace[-1]["mu"], rtol=1e-4)
+        vals = host(Sv).astype(np.float64)
+        ref_vals = S_ref[np.arange(q)[:, None], idx_ref]
+        err = np.abs(vals - ref_vals)[same]
+        assert err.max() <= 1e-4 * max(1.0, np.abs(ref_vals).max())
+
+
+def _oracle_state_after(inst, iters):
+    A = inst.A64()
+    Y = inst.Y32.astype(np.float64)
+    st = O.initialise(A, Y, inst.r, inst.rho)
+    for _ in range(iters):
+        st = O.gdmin_iteration(A, Y, st, inst.rho)
+    return A, Y, st
+
+
+@pytest.mark.parametrize("shape", SHAPES[:3])
+def test_projected_iht_and_lsgrad_teacher_forced(lib, torch, shape):
+    """One GDmin iteration's column work from the oracle's own (U, S), cast to FP32."""
+    inst = I.make_instance(**shape, seed=13)
+    p, keep = problem(lib, torch, inst)
+    q, n, m, r, rho = inst.q, inst.n, inst.m, inst.r, inst.rho
+    A, Y, st = _oracle_state_after(inst, 2)
+    U32_ = st.U.astype(np.float32)
+    S32 = st.S.astype(np.float32)
+    idx0 = st.idx
+    P = torch.zeros((q, m, r), dtype=torch.float32, device="cuda")
+    Gi = torch.zeros((q, r, r), dtype=torch.float64, device="cuda")
+    lib.altgdmin_op_au(p, dev(torch, U32_), P, Gi)
+    Si = dev(torch, idx0.astype(np.int32))
+    Sv = dev(torch, S32[np.arange(q)[:, None], idx0])
+    lib.altgdmin_op_iht(p, True, P, Gi, 3, True, Si, Sv)
+    Bt = torch.zeros((q, r), dtype=torch.float32, device="cuda")
+    H = torch.zeros((q, n), dtype=torch.float32, device="cuda")
+    rr = torch.zeros(q, dtype=torch.float64, device="cuda")
+    lib.altgdmin_op_lsgrad(p, P, Gi, Si, Sv, Bt, H, rr)
+    torch.cuda.synchronize()
+    # oracle on the same FP32-cast state
+    st32 = O.State(U=U32_.astype(np.float64), S=S32.astype(np.float64), idx=idx0, eta=1.0)
+    rec = {}
+    O.gdmin_iteration(A, Y, st32, rho, record=rec)
+    same = _supports_match(host(Si), rec["idx"])
+    assert same.mean() >= 0.95
+    sv = host(Sv).astype(np.float64)
+    ref_v = rec["S"][np.arange(q)[:, None], rec["idx"]]
+    assert np.abs(sv - ref_v)[same].max() <= 1e-4 * max(1.0, np.abs(ref_v).max())
+    Bg = host(Bt).astype(np.float64)
+    assert np.linalg.norm(Bg[same] - rec["B"][same]) <= 1e-4 * np.linalg.norm(rec["B"][same])
+    # h_k and the residual of the same (U, b_k, s_k) on the columns that agreed
+    X = rec["B"] @ st32.U.T + rec["S"]
+    Rres = O.apply_A(A, X) - Y
+    H_ref = O.apply_AT(A, Rres)
+    Hg = host(H).astype(np.float64)
+    scale = np.linalg.norm(O.apply_AT(np.abs(A), np.abs(Rres))[same])
+    assert np.linalg.norm(Hg[same] - H_ref[same]) <= 1e-4 * scale
+    assert np.allclose(host(rr)[same], np.sum(Rres ** 2, axis=1)[same], rtol=1e-3, atol=1e-9 * np.sum(Y ** 2))
+
+
+def test_backprojection(lib, torch):
+    inst = I.make_instance(n=301, q=37, m=150, r=3, rho=7, seed=21)
+    p, keep = problem(lib, torch, inst)
+    q, n, rho = inst.q, inst.n, inst.rho
+    idx = inst.supp.astype(np.int32)
+    vals = np.random.default_rng(1).standard_normal((q, rho)).astype(np.float32)
+    L0t = torch.zeros((q, n), dtype=torch.float32, device="cuda")
+    lib.altgdmin_op_backproject(p, dev(torch, idx), dev(torch, vals), L0t)
+    torch.cuda.synchronize()
+    A = inst.A64()
+    S = np.zeros((q, n))
+    S[np.arange(q)[:, None], idx] = vals
+    ref = O.backprojection(A, inst.Y32.astype(np.float64), S).T
+    assert np.linalg.norm(host(L0t) - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+# ---------------------------------------------------------------- a9, a10, a11: gradient, eta, QR
+
+@pytest.mark.parametrize("n,q,r", [(100, 100, 2), (1000, 1000, 10), (777, 13, 16)])
+def test_grad_reduce(lib, torch, n, q, r):
+    rng = np.random.default_rng(n + q)
+    H = rng.standard_normal((q, n)).astype(np.float32)
+    B = rng.standard_normal((q, r)).astype(np.float32)
+    g = torch.zeros((n, r), dtype=torch.float32, device="cuda")
+    lib.altgdmin_op_grad(dev(torch, H), dev(torch, B), g)
+    torch.cuda.synchronize()
+    ref = H.astype(np.float64).T @ B.astype(np.float64)
+    bound = (q / 16 / 4 + 24) * U32 * (np.abs(H.astype(np.float64)).T @ np.abs(B.astype(np.float64)))
+    assert (np.abs(host(g) - ref) <= bound).all()
+
+
+@pytest.mark.parametrize("n,r", [(100, 2), (1000, 10), (3000, 16)])
+def test_qr_step_and_eta(lib, torch, n, r):
+    rng = np.random.default_rng(n)
+    U = O.qr_pos(rng.standard_normal((n, r)))[0].astype(np.float32)
+    grad = (rng.standard_normal((n, r)) * 50).astype(np.float32)
+    eta = torch.zeros(1, dtype=torch.float64, device="cuda")
+    Uo = torch.zeros((n, r), dtype=torch.float32, device="cuda")
+    lib.altgdmin_op_qr_step(dev(torch, U), dev(torch, grad), 0.14, eta, Uo)
+    torch.cuda.synchronize()
+    g64 = grad.astype(np.float64)
+    eta_ref = 0.14 / O.spectral_norm(g64)
+    assert abs(host(eta)[0] - eta_ref) <= 1e-12 * eta_ref
+    Q_ref, _ = O.qr_pos(U.astype(np.float64) - eta_ref * g64)
+    Ug = host(Uo).astype(np.float64)
+    assert np.abs(Ug - Q_ref).max() <= 1e-5
+    assert np.abs(Ug.T @ Ug - np.eye(r)).max() <= 1e-5
+    # fixed eta on entry is used as given
+    eta2 = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    lib.altgdmin_op_qr_step(dev(torch, U), dev(torch, grad), 0.14, eta2, Uo)
+    torch.cuda.synchronize()
+    Q2, _ = O.qr_pos(U.astype(np.float64) - 1e-3 * g64)
+    assert np.abs(host(Uo) - Q2).max() <= 1e-5
+
+
+def test_subspace_iteration(lib, torch):
+    rng = np.random.default_rng(3)
+    n, q, r = 400, 300, 4
+    Ut = O.qr_pos(rng.standard_normal((n, r)))[0]
+    L0 = Ut @ np.diag([40.0, 30.0, 20.0, 10.0]) @ rng.standard_normal((r, q)) / np.sqrt(q) * 10
+    L0 += rng.standard_normal((n, q)) * 0.5
+    L0t = L0.T.astype(np.float32)
+    Uo = torch.zeros((n, r), dtype=torch.float32, device="cuda")
+    its = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Us = rng.standard_normal((n, r)).astype(np.float32)
+    lib.altgdmin_op_subspace(dev(torch, L0t), r, dev(torch, Us), 200, 1e-7, Uo, its)
+    torch.cuda.synchronize()
+    U_ref = O.spectral_init(L0t.T.astype(np.float64), r)
+    assert O.subspace_distance(U_ref, host(Uo).astype(np.float64)) <= 1e-5
+    assert 1 <= host(its)[0] < 200
+
+
+# ---------------------------------------------------------------- whole path
+
+def _solve(lib, torch, inst, t_max, bf16=False, flags=0, tol=0.0):
+    par = lib.default_params(t_max=t_max, flags=flags, tol_resid=tol, poll_every=10)
+    A_hi = inst.A_hi if bf16 else None
+    A_lo = inst.A_lo if bf16 else None
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=A_hi, A_lo=A_lo)
+    s.init().step(t_max)
+    out = s.get()
+    out["status"] = s.status()
+    out["log"] = s.residual_log()
+    s.close()
+    return out
+
+
+@pytest.mark.parametrize("shape,iters", [(dict(n=100, q=100, m=40, r=2, rho=2), 120),
+                                         (dict(n=301, q=64, m=150, r=3, rho=7), 60)])
+def test_solve_matches_oracle(lib, torch, shape, iters):
+    inst = I.make_instance(**shape, seed=231103824)
+    out = _solve(lib, torch, inst, iters)
+    A = inst.A64()
+    Y = inst.Y32.astype(np.float64)
+    st, hist = O.solve(A, Y, inst.r, inst.rho, t_max=iters, X_star=inst.X_star)
+    assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    err_gpu = O.rel_error(X_gpu, inst.X_star)
+    err_orc = hist[-1]
+    assert err_gpu <= max(1e-5, 10 * err_orc)
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+    assert out["status"]["iterations"] == iters and out["status"]["error_flags"] == 0
+    assert abs(out["status"]["eta"] - st.eta) <= 1e-3 * st.eta
+
+
+def test_bf16_split_equals_fp32(lib, torch):
+    """hi + lo is the canonical A exactly, so the BF16-split form reproduces the FP32 form bitwise."""
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=4, bf16_planes=True)
+    a = _solve(lib, torch, inst, 20)
+    b = _solve(lib, torch, inst, 20, bf16=True)
+    for key in ("U", "Bt", "S_idx", "S_val"):
+        assert np.array_equal(a[key], b[key])
+
+
+def test_deterministic_and_graph_equals_eager(lib, torch):
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=8)
+    a = _solve(lib, torch, inst, 15)
+    b = _solve(lib, torch, inst, 15)
+    c = _solve(lib, torch, inst, 15, flags=lib.FLAG_EAGER)
+    for key in ("U", "Bt", "S_idx", "S_val"):
+        assert np.array_equal(a[key], b[key])
+        assert np.array_equal(a[key], c[key])
+    assert np.array_equal(a["log"], c["log"])
+
+
+def test_solve_entry_point_tolerance_stop(lib, torch):
+    inst = I.make_instance(n=100, q=100, m=40, r=2, rho=2, seed=231103824)
+    par = lib.default_params(t_max=300, tol_resid=1e-5, poll_every=5)
+    A = dev(torch, inst.At)
+    Y = dev(torch, inst.Y32)
+    p = lib.make_problem(A, Y, inst.r, inst.rho, m=inst.m)
+    ws = torch.empty(lib.altgdmin_workspace_bytes(p, par), dtype=torch.uint8, device="cuda")
+    U = torch.zeros((inst.n, inst.r), dtype=torch.float32, device="cuda")
+    Bt = torch.zeros((inst.q, inst.r), dtype=torch.float32, device="cuda")
+    Si = torch.zeros((inst.q, inst.rho), dtype=torch.int32, device="cuda")
+    Sv = torch.zeros((inst.q, inst.rho), dtype=torch.float32, device="cuda")
+    rc, rep = lib.altgdmin_solve(p, par, ws, U, Bt, Si, Sv)
+    assert rc == 0 and rep["converged"] == 1 and rep["resid"] <= 1e-5
+    assert rep["iterations"] % 5 == 0 and rep["iterations"] < 300
+    assert np.array_equal(host(Si), inst.supp)
