@@ -132,6 +132,13 @@ int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, voi
                    size_t ws_bytes, void* stream, float* U, float* Bt, int32_t* S_idx,
                    float* S_val, altgdmin_report* rep);
 
+/* Measurement hook: runs `iters` GDmin iterations with eager launches and a
+ * HIP event pair around each of the four kernels of an iteration (A_k U,
+ * column kernel, gradient reduction, U update), on `stream`.  ms_out (host,
+ * 4 doubles) receives the average duration of each kernel in milliseconds.
+ * Advances the solve like altgdmin_step.  Synchronises. */
+int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out);
+
 /* Frees the host handle only. */
 int altgdmin_destroy(altgdmin_handle* h);
 

@@ -66,6 +66,7 @@ _SIGS = {
     "altgdmin_residual_log": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_solve": (c_i32, [c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_destroy": (c_i32, [c_vp]),
+    "altgdmin_profile_iteration": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "altgdmin_strerror": (ctypes.c_char_p, [c_i32]),
     "altgdmin_last_error": (ctypes.c_char_p, []),
     "altgdmin_op_select": (c_i32, [c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp]),
@@ -194,6 +195,16 @@ def altgdmin_residual_log(h, t_max: int, stream=None) -> np.ndarray:
     cnt = c_i32(0)
     _check(_lib.altgdmin_residual_log(h, stream_ptr(stream), buf, ctypes.byref(cnt)))
     return np.array(buf[: cnt.value])
+
+
+KERNELS = ("k_au", "k_col", "k_grad", "k_qr")
+
+
+def altgdmin_profile_iteration(h, iters: int, stream=None) -> dict:
+    """Average per-kernel milliseconds of `iters` eager GDmin iterations (HIP events on the launch stream)."""
+    ms = (c_f64 * 4)()
+    _check(_lib.altgdmin_profile_iteration(h, iters, stream_ptr(stream), ms))
+    return dict(zip(KERNELS, list(ms)))
 
 
 def altgdmin_destroy(h) -> None:
@@ -328,6 +339,9 @@ class Solver:
 
     def status(self, stream=None) -> dict:
         return altgdmin_status(self.h, stream)
+
+    def profile_iteration(self, iters: int) -> dict:
+        return altgdmin_profile_iteration(self.h, iters)
 
     def residual_log(self) -> np.ndarray:
         return altgdmin_residual_log(self.h, max(1, self.par.t_max))

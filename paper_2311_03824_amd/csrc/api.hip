@@ -274,6 +274,45 @@ int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
   return ALTGDMIN_OK;
 }
 
+int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out) {
+  if (!h || iters < 1 || !ms_out) return fail(ALTGDMIN_EINVAL, "bad profile arguments");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const altgdmin_problem& p = h->prob;
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  double acc[4] = {0, 0, 0, 0};
+  int rc = ALTGDMIN_OK;
+  for (int it = 0; it < iters && rc == ALTGDMIN_OK; ++it) {
+    AUArgs au;
+    au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
+    au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
+    au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+    ColArgs ca = col_args(h);
+    ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
+    hipError_t e = hipEventRecord(ev[0], st);
+    if (e == hipSuccess) e = launch_au(h->fmt, au, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], st);
+    if (e == hipSuccess) e = launch_col(h->fmt, ca, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[2], st);
+    if (e == hipSuccess) e = launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[3], st);
+    if (e == hipSuccess) e = launch_qr(qr_args(h, QR_GD), st);
+    if (e == hipSuccess) e = hipEventRecord(ev[4], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      acc[k] += ms;
+    }
+    if (e != hipSuccess) rc = fail(ALTGDMIN_EHIP, std::string("profile: ") + hipGetErrorString(e));
+  }
+  for (int i = 0; i < 5; ++i) hipEventDestroy(ev[i]);
+  if (rc) return rc;
+  for (int k = 0; k < 4; ++k) ms_out[k] = acc[k] / iters;
+  h->t_host += iters;
+  return ALTGDMIN_OK;
+}
+
 int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float* S_val, float* U_next,
                  void* stream) {
   if (!h) return fail(ALTGDMIN_EINVAL, "null handle");
