@@ -80,6 +80,49 @@ __device__ __forceinline__ int wave_sum(int x) {
   return x;
 }
 
+// DPP sums: quad swaps, half-row and row mirrors give every lane its 16-lane
+// row sum; the four row sums are read with readlane and added in a fixed
+// order, so every lane gets the same, bitwise identical total.
+__device__ __forceinline__ float row_sum_dpp(float x) {
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0xB1, 0xF, 0xF, false));   // quad [1,0,3,2]
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x4E, 0xF, 0xF, false));   // quad [2,3,0,1]
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x141, 0xF, 0xF, false));  // row half mirror
+  x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x140, 0xF, 0xF, false));  // row mirror
+  return x;
+}
+__device__ __forceinline__ float wave_sum_dpp(float x) {
+  x = row_sum_dpp(x);
+  const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+  const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+  const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+  const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+  return (a + b) + (c + d);
+}
+__device__ __forceinline__ double dpp_f64(double x, int ctrl_sel) {
+  const long long v = __double_as_longlong(x);
+  int lo = (int)(v & 0xffffffffll), hi = (int)(v >> 32);
+  switch (ctrl_sel) {
+    case 0: lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false); hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false); break;
+    case 1: lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false); hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false); break;
+    case 2: lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false); hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false); break;
+    default: lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false); hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false); break;
+  }
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double x) {
+  x += dpp_f64(x, 0);
+  x += dpp_f64(x, 1);
+  x += dpp_f64(x, 2);
+  x += dpp_f64(x, 3);
+  return (readlane_f64(x, 0) + readlane_f64(x, 16)) + (readlane_f64(x, 32) + readlane_f64(x, 48));
+}
+
 __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
@@ -204,7 +247,7 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 // LDS layout of the column kernel in bytes; used by the host to size the
 // launch and by the kernel to carve its dynamic shared memory.
 struct ColLayout {
-  size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, total;
+  size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, hist, cbuf, total;
   int mq;
   __host__ __device__ ColLayout(int n, int m, int r, int rho, int project) {
     mq = ((m + 3) / 4) * 4;
@@ -217,7 +260,9 @@ struct ColLayout {
     inT = o;  o = align16(o + 4 * (size_t)((n + 31) / 32));
     Ti = o;   o = align16(o + 4 * (size_t)rho);
     Tv = o;   o = align16(o + 4 * (size_t)rho);
-    red = o;  o = align16(o + 4 * 4 * kWaves + 8 * 2 * kWaves);
+    red = o;  o = align16(o + 8 * 2 * kWaves);
+    hist = o; o = align16(o + 4 * (256 + 8));
+    cbuf = o; o = align16(o + 8 * kRMax);
     total = o;
   }
 };

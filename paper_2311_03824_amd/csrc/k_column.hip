@@ -30,12 +30,15 @@ namespace altg {
 
 template <int NC>
 struct Lane {
-  int ch[NC];  // 4-row chunk index held by this lane
-  int nv[NC];  // number of rows of that chunk below m
+  int ch[NC];   // 4-row chunk index held by this lane
+  int chc[NC];  // the same, clamped to the last chunk that holds a row below m (always a legal address)
+  int nv[NC];   // number of rows of that chunk below m (0 when the chunk lies beyond m)
   __device__ Lane(int lane, int m) {
+    const int chmax = (m - 1) >> 2;
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       ch[c] = lane + 64 * c;
+      chc[c] = ch[c] < chmax ? ch[c] : chmax;
       const int v = m - 4 * ch[c];
       nv[c] = v < 0 ? 0 : (v > 4 ? 4 : v);
     }
@@ -74,55 +77,70 @@ __device__ __forceinline__ double xwave_sum_scalar(double x, double* redd, int l
 }
 
 // out = sum_{t < cnt} coef[t] * A_k[:, idx[t]]  (idx, coef in LDS), all waves get the total.
+// Each wave keeps up to 4 support columns in flight.
 template <int FMT, int NC>
 __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln, const int* idx,
                                        const float* coef, int cnt, float4 (&out)[NC], float* wpart,
                                        int mq, int wave) {
+  constexpr int GU = 4;
   float4 acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-#pragma unroll 4
-  for (int t = wave; t < cnt; t += kWaves) {
-    const int j = idx[t];
-    const float cf = coef[t];
+  for (int t0 = wave; t0 < cnt; t0 += kWaves * GU) {
+    // every load is issued before any is used: clamped, always legal addresses,
+    // invalid rows and slots are zeroed afterwards
+    float4 av[GU][NC];
+    float cf[GU];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      if (ln.nv[c] > 0) acc[c] = axpy4(cf, mask_rows(L.load(j, ln.ch[c]), ln.nv[c]), acc[c]);
+    for (int g = 0; g < GU; ++g) {
+      const int t = t0 + g * kWaves;
+      const int j = idx[t < cnt ? t : t0];
+      cf[g] = t < cnt ? coef[t] : 0.f;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) av[g][c] = L.load(j, ln.chc[c]);
+    }
+#pragma unroll
+    for (int g = 0; g < GU; ++g) {
+      const bool ok = t0 + g * kWaves < cnt;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc[c] = axpy4(cf[g], mask_rows(av[g][c], ok ? ln.nv[c] : 0), acc[c]);
+    }
   }
   xwave_sum<NC>(acc, ln, wpart, mq, wave);
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[c] = acc[c];
 }
 
-// v <- v - P_k d with d = G_k^{-1} P_k^T v (FP64 products and solve).  Every
-// wave computes the same result from its own copy of v.  If bl != nullptr,
-// lane i < r receives b_i = -d_i (the LS coefficients when v = A_k s_k - y_k).
+// v <- v - P_k d with d = G_k^{-1} P_k^T v (FP64 products and solve).  The r
+// reductions of P_k^T v are split across the waves and exchanged through cbuf
+// (LDS, r doubles); every wave then applies the same d to its own copy of v.
+// If bl != nullptr, lane i < r receives b_i = -d_i (the LS coefficients when
+// v = A_k s_k - y_k).  One barrier; cbuf may be rewritten only after another.
 template <int NC>
 __device__ __forceinline__ void project(float4 (&v)[NC], const Lane<NC>& ln, const float* Pl,
-                                        const double* Gi, int r, int lane, double* bl) {
-  double myc = 0.0;
-  for (int rr = 0; rr < r; ++rr) {
+                                        const double* Gi, int r, int lane, int wave, double* cbuf,
+                                        double* bl) {
+  for (int rr = wave; rr < r; rr += kWaves) {
     double part = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
         if (e < ln.nv[c]) part = fma((double)Pl[(4 * ln.ch[c] + e) * r + rr], (double)get4(v[c], e), part);
-    const double tot = wave_sum(part);
-    if (lane == rr) myc = tot;
+    const double tot = wave_sum_dpp(part);
+    if (lane == 0) cbuf[rr] = tot;
   }
+  __syncthreads();
   double myd = 0.0;
-  for (int jj = 0; jj < r; ++jj) {
-    const double cj = __shfl(myc, jj);
-    if (lane < r) myd = fma(Gi[lane * r + jj], cj, myd);
-  }
+  if (lane < r)
+    for (int jj = 0; jj < r; ++jj) myd = fma(Gi[lane * r + jj], cbuf[jj], myd);
   double acc[NC][4];
 #pragma unroll
   for (int c = 0; c < NC; ++c)
 #pragma unroll
     for (int e = 0; e < 4; ++e) acc[c][e] = (double)get4(v[c], e);
   for (int rr = 0; rr < r; ++rr) {
-    const double drr = __shfl(myd, rr);
+    const double drr = readlane_f64(myd, __builtin_amdgcn_readfirstlane(rr));
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -145,36 +163,45 @@ __device__ __forceinline__ double sumsq(const float4 (&v)[NC]) {
     s = fma((double)v[c].z, (double)v[c].z, s);
     s = fma((double)v[c].w, (double)v[c].w, s);
   }
-  return wave_sum(s);
+  return wave_sum_dpp(s);
 }
 
 // Streaming pass over A_k: gl[j] = A_j^T u for every column j; for j in the
 // support bitmap inT (if given) also wacc += gl[j] * A_j and gT2 += gl[j]^2.
+// Wave w takes columns j = w, w + 4, ...; groups of JU columns are loaded one
+// group ahead of the one being reduced.
 template <int FMT, int NC>
 __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
                                            int n, float* gl, const unsigned* inT, float4 (&wacc)[NC],
                                            double& gT2, int lane, int wave) {
-  constexpr int JU = 4;
-  for (int j0 = wave; j0 < n; j0 += kWaves * JU) {
-    float4 av[JU][NC];
+  constexpr int JU = 2;
+  constexpr int step = kWaves * JU;
+  // loads are unconditional (column clamped to n-1, chunk clamped to a legal
+  // one) so that a whole group is in flight at once; consume() masks them
+  auto load = [&](int j0, float4 (&av)[JU][NC]) {
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
       const int j = j0 + ju * kWaves;
+      const int jc = j < n ? j : n - 1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
-        av[ju][c] = (j < n && ln.nv[c] > 0) ? mask_rows(L.load(j, ln.ch[c]), ln.nv[c])
-                                            : make_float4(0.f, 0.f, 0.f, 0.f);
+      for (int c = 0; c < NC; ++c) av[ju][c] = L.load(jc, ln.chc[c]);
     }
+  };
+  auto consume = [&](int j0, float4 (&av)[JU][NC]) {
     float d[JU];
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
+      const bool ok = j0 + ju * kWaves < n;
       float s = 0.f;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) s += dot4(av[ju][c], u[c]);
+      for (int c = 0; c < NC; ++c) {
+        av[ju][c] = mask_rows(av[ju][c], ok ? ln.nv[c] : 0);
+        s += dot4(av[ju][c], u[c]);
+      }
       d[ju] = s;
     }
 #pragma unroll
-    for (int ju = 0; ju < JU; ++ju) d[ju] = wave_sum(d[ju]);
+    for (int ju = 0; ju < JU; ++ju) d[ju] = wave_sum_dpp(d[ju]);
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
       const int j = j0 + ju * kWaves;
@@ -187,52 +214,75 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
         }
       }
     }
+  };
+  float4 a0[JU][NC], a1[JU][NC];
+  int j0 = wave;
+  load(j0, a0);
+  for (;;) {
+    const int j1 = j0 + step;
+    if (j1 < n) load(j1, a1);
+    consume(j0, a0);
+    if (j1 >= n) break;
+    const int j2 = j1 + step;
+    if (j2 < n) load(j2, a0);
+    consume(j1, a1);
+    if (j2 >= n) break;
+    j0 = j2;
   }
 }
 
 // HardThreshold of Alg. 2 on vals[0..n) (LDS): the rho entries of largest
 // |v|, lower index first on ties, written ascending to idx/val (LDS).
-// Exact: the rho-th largest magnitude T is found by a bitwise search on the
-// FP32 magnitude bits (monotone in |v|), ties at T are resolved in index order.
-// Returns the number of NaNs seen (block-uniform).
-__device__ int block_select(const float* vals, int n, int rho, int* idx, float* val, int* redi) {
+// Exact: the rho-th largest magnitude T is found by a radix select on the FP32
+// magnitude bits (monotone in |v|), one byte per round from the top, with a
+// 256-bin LDS histogram; ties at T are then resolved in index order by one
+// wave.  hist: 256 + 8 ints of LDS.  Returns the number of NaNs (block-uniform).
+__device__ int block_select(const float* vals, int n, int rho, int* idx, float* val, int* hist) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   if (rho <= 0) return 0;
-  unsigned T = 0u;
-  for (int b = 30; b >= 0; --b) {
-    const unsigned cand = T | (1u << b);
-    int cnt = 0;
-    for (int j = tid; j < n; j += kThreads) cnt += ((__float_as_uint(vals[j]) & 0x7fffffffu) >= cand) ? 1 : 0;
-    cnt = wave_sum(cnt);
-    int* buf = redi + (b & 1) * kWaves;
-    if (lane == 0) buf[wave] = cnt;
+  int* ctl = hist + 256;   // [0] digit, [1] rank left, [2] NaN count
+  unsigned prefix = 0u, pmask = 0u;
+  int remaining = rho;
+  for (int d = 3; d >= 0; --d) {
+    const int shift = 8 * d;
+    for (int b = tid; b < 256; b += kThreads) hist[b] = 0;
+    if (d == 3 && tid == 0) ctl[2] = 0;
     __syncthreads();
-    int tot = 0;
+    int nanc = 0;
+    for (int j = tid; j < n; j += kThreads) {
+      const unsigned key = __float_as_uint(vals[j]) & 0x7fffffffu;
+      if (d == 3) nanc += key > 0x7f800000u ? 1 : 0;
+      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1);
+    }
+    if (d == 3 && nanc) atomicAdd(&ctl[2], nanc);
+    __syncthreads();
+    if (wave == 0) {
+      const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+      const int lsum = h0 + h1 + h2 + h3;
+      int incl = lsum;   // inclusive suffix sum over lanes >= lane
 #pragma unroll
-    for (int w = 0; w < kWaves; ++w) tot += buf[w];
-    if (tot >= rho) T = cand;
-  }
-  int gt = 0, nan = 0;
-  for (int j = tid; j < n; j += kThreads) {
-    const unsigned key = __float_as_uint(vals[j]) & 0x7fffffffu;
-    gt += key > T ? 1 : 0;
-    nan += key > 0x7f800000u ? 1 : 0;
-  }
-  gt = wave_sum(gt);
-  nan = wave_sum(nan);
-  int* buf2 = redi + 2 * kWaves;
-  if (lane == 0) {
-    buf2[wave] = gt;
-    buf2[kWaves + wave] = nan;
-  }
-  __syncthreads();
-  int gtt = 0, nant = 0;
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_down(incl, o);
+        if (lane + o < 64) incl += t;
+      }
+      int acc = incl - lsum;   // elements in bins above 4*lane+3
+      const int hb[4] = {h3, h2, h1, h0};
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
-    gtt += buf2[w];
-    nant += buf2[kWaves + w];
+      for (int q = 0; q < 4; ++q) {
+        if (acc < remaining && remaining <= acc + hb[q]) {
+          ctl[0] = 4 * lane + 3 - q;
+          ctl[1] = remaining - acc;
+        }
+        acc += hb[q];
+      }
+    }
+    __syncthreads();
+    remaining = ctl[1];
+    prefix |= (unsigned)ctl[0] << shift;
+    pmask |= 255u << shift;
   }
-  const int need_eq = rho - gtt;
+  const unsigned T = prefix;
+  const int need_eq = remaining;
   if (wave == 0) {
     const unsigned long long lt = (1ull << lane) - 1ull;
     int base_eq = 0, base_pos = 0;
@@ -257,13 +307,13 @@ __device__ int block_select(const float* vals, int n, int rho, int* idx, float* 
     }
   }
   __syncthreads();
-  return nant;
+  return ctl[2];
 }
 
 // ---------------------------------------------------------------- k_col
 
 template <int FMT, int NC>
-__global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col(ColArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
@@ -277,8 +327,9 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
   unsigned* inT = reinterpret_cast<unsigned*>(smem + lay.inT);
   int* Ti = reinterpret_cast<int*>(smem + lay.Ti);
   float* Tv = reinterpret_cast<float*>(smem + lay.Tv);
-  int* redi = reinterpret_cast<int*>(smem + lay.red);
-  double* redd = reinterpret_cast<double*>(smem + lay.red + 16 * kWaves);
+  double* redd = reinterpret_cast<double*>(smem + lay.red);
+  int* hist = reinterpret_cast<int*>(smem + lay.hist);
+  double* cbuf = reinterpret_cast<double*>(smem + lay.cbuf);
   const int mq = lay.mq;
   const int nwords = (n + 31) >> 5;
 
@@ -331,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     gather<FMT, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);
-    if (a.project) project<NC>(v, ln, Pl, Gi, r, lane, nullptr);
+    if (a.project) project<NC>(v, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
 
     // g = A_k^T u; w = A_k g_T on the current support
     float4 w[NC];
@@ -345,12 +396,12 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
       gT2 = xwave_sum_scalar(gT2, redd, lane, wave);
     } else {
       // no support yet (s = 0): restrict to the support of HardThreshold(g, rho)
-      nan_seen += block_select(gl, n, rho, Ti, Tv, redi);
+      nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
       gather<FMT, NC>(L, ln, Ti, Tv, rho, w, wpart, mq, wave);
       gT2 = 0.0;
       for (int t = 0; t < rho; ++t) gT2 = fma((double)Tv[t], (double)Tv[t], gT2);
     }
-    if (a.project) project<NC>(w, ln, Pl, Gi, r, lane, nullptr);
+    if (a.project) project<NC>(w, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
     const double ww = sumsq<NC>(w);
     const double mu = (ww > 0.0 && isfinite(ww) && isfinite(gT2)) ? gT2 / ww : 0.0;
     const bool last = (it == a.tau - 1);
@@ -360,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     // s - mu g, then HardThreshold
     for (int j = tid; j < n; j += kThreads) gl[j] = (float)fma(-mu, (double)gl[j], (double)sd[j]);
     __syncthreads();
-    nan_seen += block_select(gl, n, rho, Ti, Tv, redi);
+    nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
     for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
     for (int wd = tid; wd < nwords; wd += kThreads) inT[wd] = 0u;
     __syncthreads();
@@ -381,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_col(ColArgs a) {
     if (a.tail == TAIL_LSGRAD) {
       // b_k = G^{-1} P^T (y - A s); r_k = P b + A s - y = Pi (A s - y)
       double b = 0.0;
-      project<NC>(v, ln, Pl, Gi, r, lane, &b);
+      project<NC>(v, ln, Pl, Gi, r, lane, wave, cbuf, &b);
       const double rr = sumsq<NC>(v);
       if (wave == 0 && lane < r) a.Bt[(long long)k * r + lane] = (float)b;
       if (tid == 0 && a.rr) a.rr[k] = rr;
@@ -431,22 +482,35 @@ __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = 0.f;
 
+  // software pipeline: column j+4 of A_k and row j+4 of U are requested
+  // before the 4*NC*R FMAs of column j are issued
   const float* U = a.U;
-#pragma unroll 2
+  float4 av[NC];
+  float uj[R];
+  auto fetch = [&](int j, float4 (&a4)[NC], float (&u)[R]) {
+    const int jc = j < n ? j : n - 1;   // clamped: always a legal address
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a4[c] = L.load(jc, ln.chc[c]);
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) u[rr] = (rr < r) ? U[(long long)jc * r + rr] : 0.f;
+  };
+  fetch(wave, av, uj);
   for (int j = wave; j < n; j += kWaves) {
-    float4 av[NC];
+    float4 bv[NC];
+    float un[R];
+    fetch(j + kWaves, bv, un);
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
-      av[c] = ln.nv[c] > 0 ? mask_rows(L.load(j, ln.ch[c]), ln.nv[c]) : make_float4(0.f, 0.f, 0.f, 0.f);
-    float uj[R];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) uj[rr] = (rr < r) ? U[(long long)j * r + rr] : 0.f;
+    for (int c = 0; c < NC; ++c) av[c] = mask_rows(av[c], ln.nv[c]);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
         for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = fmaf(get4(av[c], e), uj[rr], acc[c][e][rr]);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) av[c] = bv[c];
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) uj[rr] = un[rr];
   }
   // partial P of the waves summed in wave order
   for (int w = 0; w < kWaves; ++w) {
@@ -507,11 +571,11 @@ __global__ __launch_bounds__(kThreads) void k_select(const float* V, int n, long
   float* vl = reinterpret_cast<float*>(smem);
   int* Ti = reinterpret_cast<int*>(smem + align16(4 * (size_t)n));
   float* Tv = reinterpret_cast<float*>(smem + align16(4 * (size_t)n) + align16(4 * (size_t)rho));
-  int* redi = reinterpret_cast<int*>(smem + align16(4 * (size_t)n) + 2 * align16(4 * (size_t)rho));
+  int* hist = reinterpret_cast<int*>(smem + align16(4 * (size_t)n) + 2 * align16(4 * (size_t)rho));
   const int c = blockIdx.x, tid = threadIdx.x;
   for (int j = tid; j < n; j += kThreads) vl[j] = V[(long long)c * ldv + j];
   __syncthreads();
-  const int nan = block_select(vl, n, rho, Ti, Tv, redi);
+  const int nan = block_select(vl, n, rho, Ti, Tv, hist);
   for (int t = tid; t < rho; t += kThreads) {
     idx[(long long)c * rho + t] = Ti[t];
     val[(long long)c * rho + t] = Tv[t];
@@ -519,7 +583,7 @@ __global__ __launch_bounds__(kThreads) void k_select(const float* V, int n, long
   if (tid == 0 && flags) flags[c] = nan > 0 ? 1 : 0;
 }
 
-size_t select_lds_bytes(int n, int rho) { return align16(4 * (size_t)n) + 2 * align16(4 * (size_t)rho) + 64; }
+size_t select_lds_bytes(int n, int rho) { return align16(4 * (size_t)n) + 2 * align16(4 * (size_t)rho) + 4 * (256 + 8); }
 
 hipError_t launch_select(const float* V, int n, int count, long long ldv, int rho, int* idx, float* val,
                          int* flags, hipStream_t st) {

@@ -168,7 +168,9 @@ __device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W,
   return true;
 }
 
+// The n x r block lives in LDS when it fits (a.lds != 0), else in a.Utmp.
 __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   __shared__ double sh[kQRThreads];
   __shared__ double W[kRMax * kRMax], Lf[kRMax * kRMax];
   __shared__ double eta_s;
@@ -176,20 +178,23 @@ __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
   const int tid = threadIdx.x;
   const int n = a.n, r = a.r, nr = n * r;
   if (a.mode == QR_POWER && a.ctl && a.ctl->conv) return;
+  float* X = a.lds ? reinterpret_cast<float*>(dsm) : a.Utmp;
 
   if (a.mode != QR_ORTH) {
     for (int idx = tid; idx < nr; idx += kQRThreads) {
       float s = a.gpart[idx];
       for (int ks = 1; ks < a.KS; ++ks) s += a.gpart[(long long)ks * nr + idx];
-      a.Utmp[idx] = s;
+      X[idx] = s;
       if (a.grad_out) a.grad_out[idx] = s;
     }
-    __syncthreads();
+  } else if (a.lds) {
+    for (int idx = tid; idx < nr; idx += kQRThreads) X[idx] = a.Utmp[idx];
   }
+  __syncthreads();
   if (a.mode == QR_GD) {
     const bool have = a.ctl ? (a.ctl->eta_set != 0) : (*a.eta_io > 0.0);
     if (!have) {
-      block_gram(a.Utmp, a.Utmp, n, r, sh, W);
+      block_gram(X, X, n, r, sh, W);
       if (tid == 0) {
         const double lam = jacobi_max_eig(W, r);
         const double eta = lam > 0.0 ? a.eta_c / sqrt(lam) : 0.0;
@@ -206,19 +211,18 @@ __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
     }
     __syncthreads();
     const double eta = eta_s;
-    for (int idx = tid; idx < nr; idx += kQRThreads)
-      a.Utmp[idx] = (float)fma(-eta, (double)a.Utmp[idx], (double)a.U[idx]);
+    for (int idx = tid; idx < nr; idx += kQRThreads) X[idx] = (float)fma(-eta, (double)X[idx], (double)a.U[idx]);
     __syncthreads();
   }
   // CholeskyQR2
-  bool ok = block_cholqr_pass(a.Utmp, n, r, sh, W, Lf, &okflag);
-  if (ok) ok = block_cholqr_pass(a.Utmp, n, r, sh, W, Lf, &okflag);
+  bool ok = block_cholqr_pass(X, n, r, sh, W, Lf, &okflag);
+  if (ok) ok = block_cholqr_pass(X, n, r, sh, W, Lf, &okflag);
   if (!ok) {
     if (tid == 0 && a.ctl) a.ctl->err |= 2;
     return;
   }
   if (a.mode == QR_POWER) {
-    block_gram(a.U, a.Utmp, n, r, sh, W);   // U_old^T U_new
+    block_gram(a.U, X, n, r, sh, W);   // U_old^T U_new
     if (tid == 0) {
       double f = 0.0;
       for (int e = 0; e < r * r; ++e) f += W[e] * W[e];
@@ -230,7 +234,7 @@ __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
   }
   for (int idx = tid; idx < nr; idx += kQRThreads) {
     if (a.mode == QR_GD && a.Uprev) a.Uprev[idx] = a.U[idx];
-    a.U[idx] = a.Utmp[idx];
+    a.U[idx] = X[idx];
   }
   if (a.mode == QR_GD && a.ctl) {
     double s = 0.0;
@@ -338,9 +342,12 @@ hipError_t launch_ltu(const float* L0t, const float* U, int n, int q, int r, flo
   return hipGetLastError();
 }
 
-hipError_t launch_qr(const QRArgs& a, hipStream_t st) {
+hipError_t launch_qr(const QRArgs& a_in, hipStream_t st) {
+  QRArgs a = a_in;
+  const size_t bytes = (size_t)a.n * a.r * sizeof(float);
+  a.lds = bytes <= kQRLdsMax ? 1 : 0;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(k_qr, dim3(1), dim3(kQRThreads), 0, st, a);
+  hipLaunchKernelGGL(k_qr, dim3(1), dim3(kQRThreads), a.lds ? bytes : 0, st, a);
   return hipGetLastError();
 }
 

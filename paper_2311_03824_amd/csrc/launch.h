@@ -21,7 +21,10 @@ struct QRArgs {
   int rlog_len;
   float* grad_out;         // optional copy of the summed partials
   double* eta_io;          // op entry: eta in/out (<= 0: compute), used instead of ctl when ctl == nullptr
+  int lds;                 // set by launch_qr: the n x r block is staged in LDS
 };
+
+constexpr size_t kQRLdsMax = 48 * 1024;   // dynamic LDS for the n x r block of k_qr
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
