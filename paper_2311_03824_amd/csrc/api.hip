@@ -42,7 +42,9 @@ struct Carver {
   }
 };
 
-int grad_splits(int q) { return q < 16 ? (q < 1 ? 1 : q) : 16; }
+// column splits of the gradient reduction: enough workgroups to fill the
+// chip for small n, one split when every split would hold few columns
+int grad_splits(int q) { return q >= 512 ? 4 : (q >= 64 ? 2 : 1); }
 
 int fmt_of(const altgdmin_problem* p) {
   return p->a_format == ALTGDMIN_A_BF16X2 ? FMT_BF16X2 : FMT_F32;

@@ -482,35 +482,44 @@ __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = 0.f;
 
-  // software pipeline: column j+4 of A_k and row j+4 of U are requested
-  // before the 4*NC*R FMAs of column j are issued
+  // software pipeline, two columns deep: columns j+4 and j+8 of A_k and the
+  // matching rows of U are in flight while the 4*NC*R FMAs of column j are
+  // issued.  Row j of U is fetched by lanes 0..r-1 with one vector load (in-order
+  // vmcnt tracking, unlike scalar loads) and broadcast with readlane.
   const float* U = a.U;
-  float4 av[NC];
-  float uj[R];
-  auto fetch = [&](int j, float4 (&a4)[NC], float (&u)[R]) {
+  auto fetch = [&](int j, float4 (&a4)[NC], float& uv) {
     const int jc = j < n ? j : n - 1;   // clamped: always a legal address
 #pragma unroll
     for (int c = 0; c < NC; ++c) a4[c] = L.load(jc, ln.chc[c]);
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) u[rr] = (rr < r) ? U[(long long)jc * r + rr] : 0.f;
+    uv = U[(long long)jc * r + (lane < r ? lane : 0)];
   };
-  fetch(wave, av, uj);
-  for (int j = wave; j < n; j += kWaves) {
-    float4 bv[NC];
-    float un[R];
-    fetch(j + kWaves, bv, un);
+  auto fma_col = [&](float4 (&a4)[NC], float uv) {
+    float u[R];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) av[c] = mask_rows(av[c], ln.nv[c]);
+    for (int rr = 0; rr < R; ++rr)
+      u[rr] = rr < r ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uv), rr)) : 0.f;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) a4[c] = mask_rows(a4[c], ln.nv[c]);
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
       for (int e = 0; e < 4; ++e)
 #pragma unroll
-        for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = fmaf(get4(av[c], e), uj[rr], acc[c][e][rr]);
-#pragma unroll
-    for (int c = 0; c < NC; ++c) av[c] = bv[c];
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) uj[rr] = un[rr];
+        for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = fmaf(get4(a4[c], e), u[rr], acc[c][e][rr]);
+  };
+  float4 b0[NC], b1[NC], b2[NC];
+  float u0, u1, u2;
+  fetch(wave, b0, u0);
+  fetch(wave + kWaves, b1, u1);
+  for (int j = wave; j < n; j += 3 * kWaves) {
+    fetch(j + 2 * kWaves, b2, u2);
+    fma_col(b0, u0);
+    if (j + kWaves >= n) break;
+    fetch(j + 3 * kWaves, b0, u0);
+    fma_col(b1, u1);
+    if (j + 2 * kWaves >= n) break;
+    fetch(j + 4 * kWaves, b1, u1);
+    fma_col(b2, u2);
   }
   // partial P of the waves summed in wave order
   for (int w = 0; w < kWaves; ++w) {

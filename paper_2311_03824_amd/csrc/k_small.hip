@@ -13,35 +13,55 @@
 
 namespace altg {
 
-__global__ __launch_bounds__(256) void k_grad(const float* __restrict__ H, const float* __restrict__ B, int n,
-                                              int q, int r, int KS, float* __restrict__ gpart,
-                                              const int* skip) {
+// One workgroup of 16 waves per block of 64 rows j; wave w sums the columns
+// k = w, w + 16, ... of its split; the 16 wave partials are added in wave order.
+// Row k of B is fetched by lanes 0..r-1 with one vector load and broadcast with
+// readlane, so that loads of later columns stay in flight.
+constexpr int kGradWaves = 16;
+__global__ __launch_bounds__(kGradWaves * 64) void k_grad(const float* __restrict__ H, const float* __restrict__ B,
+                                                          int n, int q, int r, int KS, float* __restrict__ gpart,
+                                                          const int* skip) {
   if (skip && *skip) return;
-  __shared__ float red[kWaves][64][kRMax + 1];
-  const int jl = threadIdx.x & 63, ph = wave_id();
-  const int j = blockIdx.x * 64 + jl, ks = blockIdx.y;
+  __shared__ float red[kGradWaves / 2][64][kRMax + 1];
+  const int lane = threadIdx.x & 63, ph = wave_id();
+  const int j = blockIdx.x * 64 + lane, ks = blockIdx.y;
+  const int jc = j < n ? j : n - 1;
   const int k0 = (int)((long long)q * ks / KS), k1 = (int)((long long)q * (ks + 1) / KS);
   float acc[kRMax];
 #pragma unroll
   for (int c = 0; c < kRMax; ++c) acc[c] = 0.f;
-  for (int k = k0 + ph; k < k1; k += kWaves) {
-    const float h = (j < n) ? H[(long long)k * n + j] : 0.f;
-    const float* Bk = B + (long long)k * r;
+  constexpr int KU = 4;
+  for (int kb = k0 + ph; kb < k1; kb += kGradWaves * KU) {
+    float h[KU], bv[KU];
 #pragma unroll
-    for (int c = 0; c < kRMax; ++c)
-      if (c < r) acc[c] = fmaf(h, Bk[c], acc[c]);
-  }
+    for (int u = 0; u < KU; ++u) {
+      const int k = kb + u * kGradWaves;
+      const int kc = k < k1 ? k : k0;
+      h[u] = H[(long long)kc * n + jc];
+      bv[u] = B[(long long)kc * r + (lane < r ? lane : 0)];
+    }
 #pragma unroll
-  for (int c = 0; c < kRMax; ++c) red[ph][jl][c] = acc[c];
-  __syncthreads();
-  if (ph == 0 && j < n) {
-    for (int c = 0; c < r; ++c) {
-      float s = red[0][jl][c];
+    for (int u = 0; u < KU; ++u) {
+      const bool ok = kb + u * kGradWaves < k1;
+      const float hu = ok ? h[u] : 0.f;
 #pragma unroll
-      for (int w = 1; w < kWaves; ++w) s += red[w][jl][c];
-      gpart[((long long)ks * n + j) * r + c] = s;
+      for (int c = 0; c < kRMax; ++c)
+        if (c < r) acc[c] = fmaf(hu, __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bv[u]), c)), acc[c]);
     }
   }
+  // pairwise tree over the waves in a fixed order: (w, w + h) for h = 8, 4, 2, 1
+  for (int h = kGradWaves / 2; h >= 1; h >>= 1) {
+    if (ph >= h && ph < 2 * h)
+#pragma unroll
+      for (int c = 0; c < kRMax; ++c) red[ph - h][lane][c] = acc[c];
+    __syncthreads();
+    if (ph < h)
+#pragma unroll
+      for (int c = 0; c < kRMax; ++c) acc[c] += red[ph][lane][c];
+    __syncthreads();
+  }
+  if (ph == 0 && j < n)
+    for (int c = 0; c < r; ++c) gpart[((long long)ks * n + j) * r + c] = acc[c];
 }
 
 __global__ __launch_bounds__(256) void k_ltu(const float* __restrict__ L0t, const float* __restrict__ U, int n,
@@ -122,30 +142,47 @@ __device__ double jacobi_max_eig(double* W, int r) {
   return lam;
 }
 
+// In-place lower Cholesky factor of the SPD r x r matrix W (row-major LDS) by
+// one wave, right-looking: column j is scaled by lane-parallel divisions and
+// the trailing submatrix is updated by all lanes.  Writes 1/L_jj to rdiag.
+// Returns false (wave-uniform) if a pivot is not positive.
+__device__ bool wave_cholesky(double* W, double* rdiag, int r) {
+  const int lane = threadIdx.x & 63;
+  for (int j = 0; j < r; ++j) {
+    const double piv = W[j * r + j];
+    if (!(piv > 0.0)) return false;
+    const double d = sqrt(piv);
+    const double inv = 1.0 / d;
+    if (lane == 0) {
+      W[j * r + j] = d;
+      rdiag[j] = inv;
+    }
+    if (lane > j && lane < r) W[lane * r + j] *= inv;
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    const int t = r - j - 1;                      // trailing size
+    for (int e = lane; e < t * t; e += 64) {
+      const int i = j + 1 + e / t, k = j + 1 + e % t;
+      if (k <= i) W[i * r + k] -= W[i * r + j] * W[k * r + j];
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return true;
+}
+
 // X (n x r, in place) <- X R^{-1} where X^T X = R^T R (R upper, positive diagonal).
 // Returns false if the Gram matrix is not positive definite.
-__device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W, double* Lf, int* okflag) {
+__device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W, double* rdiag, int* okflag) {
   const int tid = threadIdx.x;
   block_gram(X, X, n, r, sh, W);
-  if (tid == 0) {
-    int ok = 1;
-    for (int j = 0; j < r && ok; ++j) {
-      double s = W[j * r + j];
-      for (int p = 0; p < j; ++p) s -= Lf[j * r + p] * Lf[j * r + p];
-      if (!(s > 0.0)) { ok = 0; break; }
-      const double d = sqrt(s);
-      Lf[j * r + j] = d;
-      for (int i = j + 1; i < r; ++i) {
-        double t = W[i * r + j];
-        for (int p = 0; p < j; ++p) t -= Lf[i * r + p] * Lf[j * r + p];
-        Lf[i * r + j] = t / d;
-      }
-    }
-    *okflag = ok;
+  if (tid < 64) {
+    const bool ok = wave_cholesky(W, rdiag, r);
+    if (tid == 0) *okflag = ok ? 1 : 0;
   }
   __syncthreads();
   if (!*okflag) return false;
-  // row x of X: solve x_new R = x, R[a][c] = Lf[c][a]
+  // row x of X: solve x_new R = x, R[a][c] = L[c][a]
   for (int j = tid; j < n; j += kQRThreads) {
     double xn[kRMax];
 #pragma unroll
@@ -154,8 +191,8 @@ __device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W,
         double t = (double)X[(long long)j * r + c];
 #pragma unroll
         for (int a = 0; a < kRMax; ++a)
-          if (a < c) t -= xn[a] * Lf[c * r + a];
-        xn[c] = t / Lf[c * r + c];
+          if (a < c) t -= xn[a] * W[c * r + a];
+        xn[c] = t * rdiag[c];
       } else {
         xn[c] = 0.0;
       }
@@ -172,7 +209,7 @@ __device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W,
 __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
   __shared__ double sh[kQRThreads];
-  __shared__ double W[kRMax * kRMax], Lf[kRMax * kRMax];
+  __shared__ double W[kRMax * kRMax], Lf[kRMax];
   __shared__ double eta_s;
   __shared__ int okflag;
   const int tid = threadIdx.x;
@@ -331,7 +368,7 @@ static inline int grid_for(long long count, int block) {
 hipError_t launch_grad(const float* H, const float* B, int n, int q, int r, int KS, float* gpart,
                        const int* skip, hipStream_t st) {
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(k_grad, dim3((n + 63) / 64, KS), dim3(256), 0, st, H, B, n, q, r, KS, gpart, skip);
+  hipLaunchKernelGGL(k_grad, dim3((n + 63) / 64, KS), dim3(kGradWaves * 64), 0, st, H, B, n, q, r, KS, gpart, skip);
   return hipGetLastError();
 }
 
