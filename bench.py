@@ -68,6 +68,45 @@ def committed_traffic(kernel_src: str, profile: str):
     return None
 
 
+def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
+    """Wall time of altgdmin_solve until ||Y - A(UB+S)||/||Y|| <= target, per form of A, and the final error.
+
+    fp32: FP32 plane.  bf16x2: BF16 hi plane alone until the residual stalls (resid_t >=
+    0.9 resid_{t-1}) or 200 iterations, then hi + lo.  Same instance, same GPU.
+    """
+    out = {}
+    n, q, m, r, rho = inst.n, inst.q, inst.m, inst.r, inst.rho
+    A_hi = torch.from_numpy(np.ascontiguousarray(inst.A_hi).view(np.int16)).cuda()
+    A_lo = torch.from_numpy(np.ascontiguousarray(inst.A_lo).view(np.int16)).cuda()
+    forms = {
+        "fp32": (lib.make_problem(fp32_solver.A, fp32_solver.Y, r, rho, m=m), {}),
+        "bf16x2": (lib.make_problem(A_hi, fp32_solver.Y, r, rho, A_lo=A_lo, m=m),
+                   {"bf16_hi_max": 200, "bf16_stall": 0.9}),
+    }
+    for name, (prob, extra) in forms.items():
+        par = lib.default_params(t_max=400, tol_resid=target, poll_every=5, **extra)
+        ws = torch.empty(lib.altgdmin_workspace_bytes(prob, par), dtype=torch.uint8, device="cuda")
+        U = torch.empty((n, r), dtype=torch.float32, device="cuda")
+        Bt = torch.empty((q, r), dtype=torch.float32, device="cuda")
+        Si = torch.empty((q, rho), dtype=torch.int32, device="cuda")
+        Sv = torch.empty((q, rho), dtype=torch.float32, device="cuda")
+        lib.altgdmin_solve(prob, par, ws, U, Bt, Si, Sv)           # warm-up (graph capture, caches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, rep = lib.altgdmin_solve(prob, par, ws, U, Bt, Si, Sv)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        X = U.cpu().numpy().astype(np.float64) @ Bt.cpu().numpy().T.astype(np.float64)
+        X[Si.cpu().numpy(), np.arange(q)[:, None]] += Sv.cpu().numpy()
+        err = float(np.linalg.norm(X - inst.X_star) / np.linalg.norm(inst.X_star))
+        out[name] = {"ms_to_target": round(ms, 2), "iterations": rep["iterations"], "converged": rep["converged"],
+                     "final_rel_residual": rep["resid"], "final_rel_error_vs_Xstar": err,
+                     "refine_iteration": rep["refine_iteration"]}
+    out["target_rel_residual"] = target
+    out["bf16x2_speedup_vs_fp32"] = round(out["fp32"]["ms_to_target"] / out["bf16x2"]["ms_to_target"], 3)
+    return out
+
+
 def cpu_baseline(inst_args, q_sample: int, iters: int):
     """FP64 oracle on the first q_sample columns: init + `iters` GDmin iterations, extrapolated to the workload."""
     import numpy as np
@@ -115,6 +154,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-q", type=int, default=100)
     ap.add_argument("--profile-iters", type=int, default=20)
+    ap.add_argument("--no-forms", action="store_true", help="skip the time-to-equal-error comparison of the A forms")
+    ap.add_argument("--target-resid", type=float, default=1e-6)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run torch's copy kernel on a 1.6 GB FP32 buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -147,7 +188,7 @@ def main() -> int:
     n, q, m, r, rho = cfg["n"], cfg["q"], cfg["m"], cfg["r"], cfg["rho"]
     log(f"generating {WORKLOAD} (seed {cfg['seed']})")
     t0 = time.perf_counter()
-    inst = I.make_instance(**cfg, bf16_planes=(args.form == "bf16x2"))
+    inst = I.make_instance(**cfg, bf16_planes=True)
     log(f"generated in {time.perf_counter() - t0:.1f} s; uploading")
     par = lib.default_params(t_max=args.iters)
     solver = lib.Solver(inst.At if args.form == "fp32" else None, inst.Y32, m, r, rho, par,
@@ -230,6 +271,9 @@ def main() -> int:
         "final_rel_residual": st["resid"],
         "eta": st["eta"],
     }
+    if not args.no_forms:
+        result["forms_time_to_target"] = forms_time_to_target(lib, torch, np, inst, args.target_resid, solver)
+        log("forms: " + json.dumps(result["forms_time_to_target"]))
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on {args.cpu_sample_q} columns")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_q, 2)

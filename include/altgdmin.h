@@ -79,6 +79,10 @@ typedef struct altgdmin_params {
   double eta_c;              /* eta = eta_c / ||grad_U f(U_0, B_1, S_1)||_2 (paper: 0.14) */
   double power_tol;          /* stop the subspace iteration when ||(I - U_p U_p^T) U_{p+1}||_F <= power_tol */
   double tol_resid;          /* altgdmin_solve stops when ||Y - A(UB+S)||_F / ||Y||_F <= tol_resid (0: never) */
+  int32_t bf16_hi_max;       /* BF16X2 only: the initialisation and up to this many GDmin iterations read
+                                the hi plane alone (2 bytes per element); 0 disables the hi-only phase */
+  int32_t pad0;
+  double bf16_stall;         /* BF16X2 hi-only phase ends early once resid_t >= bf16_stall * resid_{t-1} */
 } altgdmin_params;
 
 /* Fills *p with the paper's defaults (tau0 = 10, tau = 3, t_max = 200, eta_c = 0.14). Host call. */
@@ -92,6 +96,8 @@ typedef struct altgdmin_report {
   int32_t power_iterations;  /* subspace iterations used for U_0 */
   int32_t error_flags;       /* bit 0: NaN at a selection; bit 1: Gram not positive definite; bit 2: support index out of range */
   int32_t converged;         /* 1 when the last residual <= tol_resid */
+  int32_t refine_iteration;  /* BF16X2: first GDmin iteration that read hi + lo (-1: still hi-only or no hi-only phase) */
+  int32_t pad0;
   double eta;                /* step size (0 before iteration 1) */
   double resid;              /* ||Y - A(U B + S)||_F / ||Y||_F of the last iteration's consistent pair */
   double power_sd;           /* last subspace-iteration change */

@@ -37,12 +37,13 @@ class Problem(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("tau0", c_i32), ("tau", c_i32), ("t_max", c_i32), ("power_iters", c_i32),
                 ("poll_every", c_i32), ("flags", c_i32), ("eta_c", c_f64), ("power_tol", c_f64),
-                ("tol_resid", c_f64)]
+                ("tol_resid", c_f64), ("bf16_hi_max", c_i32), ("pad0", c_i32), ("bf16_stall", c_f64)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("iterations", c_i32), ("power_iterations", c_i32), ("error_flags", c_i32),
-                ("converged", c_i32), ("eta", c_f64), ("resid", c_f64), ("power_sd", c_f64)]
+                ("converged", c_i32), ("refine_iteration", c_i32), ("pad0", c_i32), ("eta", c_f64),
+                ("resid", c_f64), ("power_sd", c_f64)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -300,7 +301,7 @@ class Solver:
         torch = _torch()
         load()
         if A_hi is not None:
-            self.A = torch.from_numpy(A_hi.view(np.int16)).to(device)
+            self.A = torch.from_numpy(np.ascontiguousarray(A_hi).view(np.int16)).to(device)
             self.A_lo = torch.from_numpy(A_lo.view(np.int16)).to(device)
         else:
             self.A = torch.from_numpy(np.ascontiguousarray(At, dtype=np.float32)).to(device)

@@ -73,6 +73,7 @@ struct altgdmin_handle {
   Ctl* ctl;
   double* rlog;
   int rlog_len;
+  bool hi_phase = false;   // BF16X2 with a hi-only phase
   bool have_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -129,7 +130,7 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (col_lds_bytes(p->n, p->m, p->r, p->rho, 1) > kMaxLds || au_lds_bytes(p->m, p->r) > kMaxLds)
     return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 64 KiB of LDS per column workgroup");
   if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
-      !(par->eta_c >= 0.0))
+      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0)
     return fail(ALTGDMIN_EINVAL, "invalid params");
   return ALTGDMIN_OK;
 }
@@ -154,6 +155,8 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
   a.eta_c = h->par.eta_c; a.power_tol = h->par.power_tol;
   a.colrr = h->colrr; a.colflags = h->colflags; a.q = h->prob.q;
   a.rlog = h->rlog; a.rlog_len = h->rlog_len;
+  a.hi_max = h->par.bf16_hi_max;
+  a.stall = h->par.bf16_stall;
   return a;
 }
 
@@ -164,9 +167,18 @@ int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
   au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
   au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
   au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
-  HIPCHK(launch_au(h->fmt, au, st));
+  au.gate = nullptr; au.gate_want = 0;
   ColArgs ca = col_args(h);
   ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
+  if (h->hi_phase) {
+    // both variants are in the graph; the phase flag in the control block picks one
+    au.gate = &h->ctl->phase; ca.gate = &h->ctl->phase;
+    au.gate_want = 0; ca.gate_want = 0;
+    HIPCHK(launch_au(FMT_BF16HI, au, st));
+    HIPCHK(launch_col(FMT_BF16HI, ca, st));
+    au.gate_want = 1; ca.gate_want = 1;
+  }
+  HIPCHK(launch_au(h->fmt, au, st));
   HIPCHK(launch_col(h->fmt, ca, st));
   HIPCHK(launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st));
   HIPCHK(launch_qr(qr_args(h, QR_GD), st));
@@ -188,6 +200,8 @@ void altgdmin_default_params(altgdmin_params* p) {
   p->eta_c = 0.14;
   p->power_tol = 1e-6;
   p->tol_resid = 0.0;
+  p->bf16_hi_max = 0;
+  p->bf16_stall = 0.9;
 }
 
 int altgdmin_workspace_bytes(const altgdmin_problem* prob, const altgdmin_params* par, size_t* bytes) {
@@ -211,6 +225,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->prob = *prob;
   h->par = *par;
   h->fmt = fmt_of(prob);
+  h->hi_phase = (h->fmt == FMT_BF16X2 && par->bf16_hi_max > 0);
   const size_t need = carve(h, workspace);
   if (ws_bytes < need) {
     delete h;
@@ -224,11 +239,13 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   };
   hipError_t e;
   if ((e = launch_reset_ctl(h->ctl, 1, st)) != hipSuccess) return bail(e, "reset");
+  if ((e = launch_set_phase(h->ctl, h->hi_phase ? 0 : 1, st)) != hipSuccess) return bail(e, "phase");
   if ((e = launch_fill_int(h->colflags, 0, p.q, st)) != hipSuccess) return bail(e, "flags");
-  // s_k = IHT(y_k, A_k, rho, tau0, 0) and L_0 columns A_k^T (y_k - A_k s_k)
+  // s_k = IHT(y_k, A_k, rho, tau0, 0) and L_0 columns A_k^T (y_k - A_k s_k); the
+  // hi plane alone when a BF16X2 solve starts with a hi-only phase
   ColArgs ca = col_args(h);
   ca.tau = par->tau0; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
-  if ((e = launch_col(h->fmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
+  if ((e = launch_col(h->hi_phase ? FMT_BF16HI : h->fmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
   if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
   // U_0: top-r left singular subspace of L_0 by subspace iteration
   if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, (long long)p.n * p.r, st);
@@ -289,6 +306,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
     au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+    au.gate = nullptr; au.gate_want = 0;
     ColArgs ca = col_args(h);
     ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
     hipError_t e = hipEventRecord(ev[0], st);
@@ -342,6 +360,7 @@ int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep) {
   rep->resid = c.resid;
   rep->power_sd = c.power_sd;
   rep->converged = (h->par.tol_resid > 0.0 && c.t > 0 && c.resid <= h->par.tol_resid) ? 1 : 0;
+  rep->refine_iteration = h->hi_phase ? c.refine_t : -1;
   return ALTGDMIN_OK;
 }
 
@@ -433,6 +452,7 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
   au.n = prob->n; au.q = prob->q; au.m = prob->m; au.r = prob->r;
   au.A = prob->A; au.Alo = prob->A_lo; au.lda = prob->lda; au.sA = prob->a_stride_k;
   au.U = U; au.P = P; au.Ginv = Lc; au.flags = flags;
+  au.gate = nullptr; au.gate_want = 0;
   HIPCHK(launch_au(fmt_of(prob), au, static_cast<hipStream_t>(stream)));
   return ALTGDMIN_OK;
 }

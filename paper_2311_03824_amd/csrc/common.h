@@ -25,7 +25,10 @@ struct Ctl {
   int t;             // GDmin iterations done
   int power_it;      // subspace iterations done
   int err;           // OR of column error flags
-  int pad[7];
+  int phase;         // BF16X2 solves: 0 while the hi plane alone is read, 1 once hi + lo are read
+  int refine_t;      // first iteration with phase 1 (-1 before)
+  int pad[5];
+  double prev_resid; // residual of the previous iteration (stall test of the hi-only phase)
 };
 
 // Column kernel modes
@@ -49,6 +52,8 @@ struct ColArgs {
   double* rr;           // q: ||r_k||^2 (LSGRAD) or ||y_k||^2 (BACKPROJ)
   int* flags;           // q, OR-ed
   int tau, project, has_support, tail;
+  const int* gate;      // if non-null, the kernel runs only when *gate == gate_want
+  int gate_want;
 };
 
 struct AUArgs {
@@ -60,6 +65,8 @@ struct AUArgs {
   float* P;             // q x m x r
   double* Ginv;         // q x r x r
   int* flags;
+  const int* gate;      // if non-null, the kernel runs only when *gate == gate_want
+  int gate_want;
 };
 
 // ---------------------------------------------------------------- wave reductions

@@ -314,6 +314,7 @@ __device__ int block_select(const float* vals, int n, int rho, int* idx, float* 
 
 template <int FMT, int NC>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col(ColArgs a) {
+  if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
@@ -460,6 +461,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
 
 template <int FMT, int NC, int R>
 __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
+  if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();

@@ -293,6 +293,12 @@ __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
       if (a.rlog && t < a.rlog_len) a.rlog[t] = resid;
       a.ctl->resid = resid;
       a.ctl->t = t + 1;
+      // BF16X2 hi-only phase: switch to hi + lo when the residual stalls or the budget is spent
+      if (a.ctl->phase == 0 && (t + 1 >= a.hi_max || (t > 0 && resid >= a.stall * a.ctl->prev_resid))) {
+        a.ctl->phase = 1;
+        a.ctl->refine_t = t + 1;
+      }
+      a.ctl->prev_resid = resid;
     }
   }
 }
@@ -312,12 +318,20 @@ __global__ __launch_bounds__(kQRThreads) void k_sum_ctl(const double* colrr, int
   if (tid == 0) ctl->ynorm2 = sh[0];
 }
 
+__global__ void k_set_phase(Ctl* ctl, int phase) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->phase = phase;
+    ctl->refine_t = phase ? 0 : -1;
+  }
+}
+
 __global__ void k_reset_ctl(Ctl* ctl, int full) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl->eta = 0.0;
     ctl->eta_set = 0;
     ctl->t = 0;
     ctl->resid = 0.0;
+    ctl->prev_resid = 0.0;
     if (full) {
       ctl->power_sd = 0.0;
       ctl->ynorm2 = 0.0;
@@ -397,6 +411,12 @@ hipError_t launch_sum_ctl(const double* colrr, int q, Ctl* ctl, hipStream_t st) 
 hipError_t launch_reset_ctl(Ctl* ctl, int full, hipStream_t st) {
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(k_reset_ctl, dim3(1), dim3(64), 0, st, ctl, full);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_phase(Ctl* ctl, int phase, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_set_phase, dim3(1), dim3(64), 0, st, ctl, phase);
   return hipGetLastError();
 }
 

@@ -22,6 +22,8 @@ struct QRArgs {
   float* grad_out;         // optional copy of the summed partials
   double* eta_io;          // op entry: eta in/out (<= 0: compute), used instead of ctl when ctl == nullptr
   int lds;                 // set by launch_qr: the n x r block is staged in LDS
+  int hi_max;              // BF16X2 hi-only budget (iterations)
+  double stall;            // BF16X2 stall ratio
 };
 
 constexpr size_t kQRLdsMax = 48 * 1024;   // dynamic LDS for the n x r block of k_qr
@@ -42,6 +44,7 @@ hipError_t launch_ltu(const float* L0t, const float* U, int n, int q, int r, flo
 hipError_t launch_qr(const QRArgs& a, hipStream_t st);
 hipError_t launch_sum_ctl(const double* colrr, int q, Ctl* ctl, hipStream_t st);
 hipError_t launch_reset_ctl(Ctl* ctl, int full, hipStream_t st);
+hipError_t launch_set_phase(Ctl* ctl, int phase, hipStream_t st);
 hipError_t launch_fill_int(int* p, int v, long long count, hipStream_t st);
 hipError_t launch_fill_basis(float* U, int n, int r, hipStream_t st);
 hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStream_t st);

@@ -98,6 +98,11 @@ class Instance:
     def X_star(self) -> np.ndarray:
         return self.U_star @ self.B_star + self.S_star
 
+    def A64_hi(self) -> np.ndarray:
+        """The bf16 hi plane alone as FP64 (q, m, n) arrays: the matrix a hi-only pass reads."""
+        hi = (self.A_hi[:, :, : self.m].astype(np.uint32) << 16).view(np.float32)
+        return np.ascontiguousarray(hi.transpose(0, 2, 1), dtype=np.float64)
+
     def A64(self, ks=None) -> np.ndarray:
         """A_k as FP64 (len(ks), m, n) arrays (exact widening of the canonical FP32 values)."""
         At = self.At if ks is None else self.At[ks]

@@ -361,3 +361,53 @@ def test_solve_entry_point_tolerance_stop(lib, torch):
     assert rc == 0 and rep["converged"] == 1 and rep["resid"] <= 1e-5
     assert rep["iterations"] % 5 == 0 and rep["iterations"] < 300
     assert np.array_equal(host(Si), inst.supp)
+
+
+# ---------------------------------------------------------------- a13(b): BF16 hi-only phase + refinement
+
+def test_bf16_hi_phase_then_refinement(lib, torch):
+    """Hi plane alone first, then hi + lo.
+
+    Before refinement the GPU solves the problem with A rounded to bf16: it must match
+    the oracle run on that same rounded A (SD <= 1e-5); its distance to the exact
+    problem's solution is the method's error from the rounding (reported, loose bound).
+    After refinement it must match the oracle of the exact problem (SD <= 1e-5).
+    """
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=231103824, bf16_planes=True)
+    Y = inst.Y32.astype(np.float64)
+    hi_iters = 40
+    st_hi, _ = O.solve(inst.A64_hi(), Y, inst.r, inst.rho, t_max=hi_iters)
+    st, _ = O.solve(inst.A64(), Y, inst.r, inst.rho, t_max=80, X_star=inst.X_star)
+    # hi-only for exactly hi_iters iterations (stall ratio 2 never triggers)
+    par = lib.default_params(t_max=hi_iters, bf16_hi_max=hi_iters, bf16_stall=2.0)
+    s = lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=inst.A_hi, A_lo=inst.A_lo)
+    s.init().step(hi_iters)
+    before = s.get()
+    U_b = before["U"].astype(np.float64)
+    assert O.subspace_distance(st_hi.U_fit, U_b) <= 1e-5
+    assert np.array_equal(before["S_idx"], st_hi.idx)
+    sd_rounding = O.subspace_distance(st.U_fit, U_b)
+    print(f"hi-only phase: SD to the exact problem's oracle = {sd_rounding:.3e}")
+    assert sd_rounding <= 0.05
+    s.step(40)      # the phase switched after hi_iters: the rest reads hi + lo
+    after = s.get()
+    rep = s.status()
+    s.close()
+    assert rep["refine_iteration"] == hi_iters
+    sd_after = O.subspace_distance(st.U_fit, after["U"].astype(np.float64))
+    assert sd_after <= 1e-5, sd_after
+    assert np.array_equal(after["S_idx"], st.idx)
+
+
+def test_bf16_stall_rule_switches(lib, torch):
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=5, bf16_planes=True)
+    par = lib.default_params(t_max=120, bf16_hi_max=120, bf16_stall=0.9)
+    s = lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=inst.A_hi, A_lo=inst.A_lo)
+    s.init().step(120)
+    rep = s.status()
+    log = s.residual_log()
+    s.close()
+    t = rep["refine_iteration"]
+    assert 1 <= t < 120
+    assert log[t - 1] >= 0.9 * log[t - 2]        # the stall that triggered the switch
+    assert log[-1] <= 1e-5 * 10                   # hi + lo reaches the FP32 floor afterwards
