@@ -107,6 +107,47 @@ def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
     return out
 
 
+def philox_form(lib, torch, np, cfg, target):
+    """Philox form: A regenerated in the kernels from its counter definition, never read from HBM.
+
+    Same sizes and seed; the instance's A is the Philox matrix.  Compared with the FP32 plane
+    holding the very same values (the iterates are bitwise identical), so the difference is the
+    cost of regenerating A against streaming it.
+    """
+    from paper_2311_03824_amd import instances as I
+    t0 = time.perf_counter()
+    inst = I.make_instance(**cfg, a_form="philox")
+    log(f"philox instance generated in {time.perf_counter() - t0:.1f} s")
+    n, q, m, r, rho = inst.n, inst.q, inst.m, inst.r, inst.rho
+    out = {}
+    for name in ("fp32_plane", "philox"):
+        par = lib.default_params(t_max=T_ITERS)
+        if name == "philox":
+            s = lib.Solver(None, inst.Y32, m, r, rho, par, philox_seed=inst.a_seed, normal_table=inst.table, n=n)
+        else:
+            s = lib.Solver(inst.At, inst.Y32, m, r, rho, par)
+        s.init().step(T_ITERS)
+        torch.cuda.synchronize()
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record()
+        s.init()
+        e1.record()
+        s.step(T_ITERS)
+        e2.record()
+        torch.cuda.synchronize()
+        kms = s.profile_iteration(5)
+        st = s.status()
+        out[name] = {"init_ms": round(e0.elapsed_time(e1), 3), "gdmin_iter_ms": round(e1.elapsed_time(e2) / T_ITERS, 4),
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "final_rel_residual": st["resid"]}
+        s.close()
+        del s
+    out["philox_speedup_vs_fp32_plane"] = round(out["fp32_plane"]["gdmin_iter_ms"] / out["philox"]["gdmin_iter_ms"], 3)
+    # ALU figure of the philox column kernel: elements generated per launch / launch time
+    elems = q * n * 4 * ((m + 3) // 4) * (par.tau + 1) + q * 4 * ((m + 3) // 4) * rho * (par.tau + 1)
+    out["philox_k_col_Gelem_per_s"] = round(elems / (out["philox"]["kernels_ms"]["k_col"] * 1e-3) / 1e9, 1)
+    return out
+
+
 def cpu_baseline(inst_args, q_sample: int, iters: int):
     """FP64 oracle on the first q_sample columns: init + `iters` GDmin iterations, extrapolated to the workload."""
     import numpy as np
@@ -274,6 +315,8 @@ def main() -> int:
     if not args.no_forms:
         result["forms_time_to_target"] = forms_time_to_target(lib, torch, np, inst, args.target_resid, solver)
         log("forms: " + json.dumps(result["forms_time_to_target"]))
+        result["philox_form"] = philox_form(lib, torch, np, cfg, args.target_resid)
+        log("philox: " + json.dumps(result["philox_form"]))
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on {args.cpu_sample_q} columns")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_q, 2)

@@ -52,8 +52,13 @@ enum {
 
 enum {
   ALTGDMIN_A_F32 = 0,        /* FP32 plane */
-  ALTGDMIN_A_BF16X2 = 1      /* BF16 hi plane + BF16 lo plane, A = hi + lo */
+  ALTGDMIN_A_BF16X2 = 1,     /* BF16 hi plane + BF16 lo plane, A = hi + lo */
+  ALTGDMIN_A_PHILOX = 2      /* regenerated in the kernels from a counter; never stored (see altgdmin_op_philox_fill) */
 };
+
+/* Entries of the normal table of the Philox form: |z| = -Phi^{-1}(v) at
+ * v = 2^(e-33) (1 + s/64), e = 0..31, s = 0..63 (index e*64 + s), then two zeros. */
+#define ALTGDMIN_NORMAL_TABLE_SIZE (32 * 64 + 2)
 
 /* Problem of Sec. 1.1: sizes, measurement matrices and measurements. */
 typedef struct altgdmin_problem {
@@ -66,6 +71,8 @@ typedef struct altgdmin_problem {
   const float* Y;            /* q x ldy */
   int64_t ldy;
   const float* U_start;      /* optional n x r start block of the subspace iteration (NULL: a fixed disjoint-support basis) */
+  uint64_t a_seed;           /* PHILOX: 64-bit key of A */
+  const float* normal_table; /* PHILOX: device array of ALTGDMIN_NORMAL_TABLE_SIZE FP32 */
 } altgdmin_problem;
 
 /* Parameters of Alg. 1 / Sec. 2.6. */
@@ -163,6 +170,18 @@ const char* altgdmin_last_error(void);
  * flags[c] (optional) gets bit 0 if v_c holds a NaN. */
 int altgdmin_op_select(const float* V, int32_t n, int32_t count, int64_t ldv, int32_t rho,
                        int32_t* idx, float* val, int32_t* flags, void* stream);
+
+/* The Philox form of A written out in the FP32 layout (A[k*n*lda + j*lda + i],
+ * rows i < m): element (i, j) of A_k is output word i % 4 of Philox4x32-10
+ * (Salmon et al., SC'11) at counter (i / 4, j, k, 0) with key (seed low word,
+ * seed high word), made a normal deviate by the table transform: with
+ * v = (2 (x & 0x7fffffff) + 1) * 2^-33 (FP32), idx = 64 * (exponent(v) + 33) +
+ * top 6 mantissa bits of v, t = low 17 mantissa bits * 2^-17,
+ * |z| = T[idx] + (T[idx+1] - T[idx]) * t (each operation rounded to FP32), sign
+ * from the top bit of x.  The kernels of the PHILOX format compute exactly these
+ * values in registers.  For tests and for callers that want the matrix. */
+int altgdmin_op_philox_fill(uint64_t seed, const float* normal_table, int32_t q, int32_t n, int32_t m,
+                            int64_t lda, float* A, void* stream);
 
 /* P_k = A_k U (m x r, row-major per k at P[k*m*r]) and the Cholesky factor
  * L_k (lower, r x r row-major FP64 at Lc[k*r*r]) of G_k = P_k^T P_k, the pieces

@@ -23,6 +23,7 @@ ALTGDMIN_OK = 0
 ALTGDMIN_ENOTCONV = 1
 ALTGDMIN_A_F32 = 0
 ALTGDMIN_A_BF16X2 = 1
+ALTGDMIN_A_PHILOX = 2
 FLAG_EAGER = 1      # params.flags bit 0: launch the iteration's kernels without a HIP graph
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -31,7 +32,8 @@ c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_doubl
 class Problem(ctypes.Structure):
     _fields_ = [("n", c_i32), ("q", c_i32), ("m", c_i32), ("r", c_i32), ("rho", c_i32),
                 ("a_format", c_i32), ("A", c_vp), ("A_lo", c_vp), ("lda", c_i64),
-                ("a_stride_k", c_i64), ("Y", c_vp), ("ldy", c_i64), ("U_start", c_vp)]
+                ("a_stride_k", c_i64), ("Y", c_vp), ("ldy", c_i64), ("U_start", c_vp),
+                ("a_seed", ctypes.c_uint64), ("normal_table", c_vp)]
 
 
 class Params(ctypes.Structure):
@@ -72,6 +74,7 @@ _SIGS = {
     "altgdmin_last_error": (ctypes.c_char_p, []),
     "altgdmin_op_select": (c_i32, [c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_au": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "altgdmin_op_philox_fill": (c_i32, [ctypes.c_uint64, c_vp, c_i32, c_i32, c_i32, c_i64, c_vp, c_vp]),
     "altgdmin_op_iht": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_lsgrad": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_backproject": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -145,15 +148,25 @@ def default_params(**kw) -> Params:
     return p
 
 
-def make_problem(A, Y, r: int, rho: int, A_lo=None, U_start=None, m: Optional[int] = None) -> Problem:
-    """A: (q, n, lda) float32 (or int16/uint16 bf16 hi plane with A_lo), Y: (q, ldy) float32."""
-    q, n, lda = A.shape
+def make_problem(A, Y, r: int, rho: int, A_lo=None, U_start=None, m: Optional[int] = None,
+                 philox_seed: Optional[int] = None, normal_table=None, n: Optional[int] = None) -> Problem:
+    """A: (q, n, lda) float32 (or int16/uint16 bf16 hi plane with A_lo), Y: (q, ldy) float32.
+
+    Philox form: A=None, philox_seed and normal_table (device FP32) given, n given.
+    """
     p = Problem()
+    if philox_seed is not None:
+        q = Y.shape[0]
+        p.a_format = ALTGDMIN_A_PHILOX
+        p.a_seed, p.normal_table = int(philox_seed), ptr(normal_table)
+        p.lda = p.a_stride_k = 0
+    else:
+        q, n, lda = A.shape
+        p.a_format = ALTGDMIN_A_BF16X2 if A_lo is not None else ALTGDMIN_A_F32
+        p.A, p.A_lo = ptr(A), ptr(A_lo)
+        p.lda, p.a_stride_k = lda, n * lda
     p.n, p.q, p.r, p.rho = n, q, r, rho
     p.m = int(m) if m is not None else int(Y.shape[1])
-    p.a_format = ALTGDMIN_A_BF16X2 if A_lo is not None else ALTGDMIN_A_F32
-    p.A, p.A_lo = ptr(A), ptr(A_lo)
-    p.lda, p.a_stride_k = lda, n * lda
     p.Y, p.ldy = ptr(Y), Y.shape[1]
     p.U_start = ptr(U_start)
     return p
@@ -229,6 +242,12 @@ def altgdmin_op_select(V, rho: int, idx, val, flags=None, stream=None) -> None:
     _check(_lib.altgdmin_op_select(ptr(V), n, count, n, rho, ptr(idx), ptr(val), ptr(flags), stream_ptr(stream)))
 
 
+def altgdmin_op_philox_fill(seed: int, normal_table, q: int, n: int, m: int, A, stream=None) -> None:
+    """Write the Philox form of A (q, n, lda) FP32 into the device tensor A."""
+    load()
+    _check(_lib.altgdmin_op_philox_fill(int(seed), ptr(normal_table), q, n, m, A.shape[2], ptr(A), stream_ptr(stream)))
+
+
 def altgdmin_op_au(prob: Problem, U, P, Ginv, flags=None, stream=None) -> None:
     load()
     _check(_lib.altgdmin_op_au(ctypes.byref(prob), ptr(U), ptr(P), ptr(Ginv), ptr(flags), stream_ptr(stream)))
@@ -297,10 +316,15 @@ class Solver:
 
     def __init__(self, At: np.ndarray, Y: np.ndarray, m: int, r: int, rho: int, params: Optional[Params] = None,
                  A_hi: Optional[np.ndarray] = None, A_lo: Optional[np.ndarray] = None,
-                 U_start: Optional[np.ndarray] = None, device="cuda"):
+                 U_start: Optional[np.ndarray] = None, device="cuda", philox_seed: Optional[int] = None,
+                 normal_table: Optional[np.ndarray] = None, n: Optional[int] = None):
         torch = _torch()
         load()
-        if A_hi is not None:
+        self.table = None
+        if philox_seed is not None:
+            self.A = self.A_lo = None
+            self.table = torch.from_numpy(np.ascontiguousarray(normal_table, dtype=np.float32)).to(device)
+        elif A_hi is not None:
             self.A = torch.from_numpy(np.ascontiguousarray(A_hi).view(np.int16)).to(device)
             self.A_lo = torch.from_numpy(A_lo.view(np.int16)).to(device)
         else:
@@ -308,9 +332,13 @@ class Solver:
             self.A_lo = None
         self.Y = torch.from_numpy(np.ascontiguousarray(Y, dtype=np.float32)).to(device)
         self.U_start = None if U_start is None else torch.from_numpy(np.ascontiguousarray(U_start, dtype=np.float32)).to(device)
-        self.q, self.n, _ = self.A.shape
+        if philox_seed is not None:
+            self.q, self.n = self.Y.shape[0], int(n)
+        else:
+            self.q, self.n, _ = self.A.shape
         self.m, self.r, self.rho = m, r, rho
-        self.prob = make_problem(self.A, self.Y, r, rho, A_lo=self.A_lo, U_start=self.U_start, m=m)
+        self.prob = make_problem(self.A, self.Y, r, rho, A_lo=self.A_lo, U_start=self.U_start, m=m,
+                                 philox_seed=philox_seed, normal_table=self.table, n=self.n)
         self.par = params if params is not None else default_params()
         nb = altgdmin_workspace_bytes(self.prob, self.par)
         self.ws = torch.empty(nb, dtype=torch.uint8, device=device)

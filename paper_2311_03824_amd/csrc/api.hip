@@ -47,7 +47,7 @@ struct Carver {
 int grad_splits(int q) { return q >= 512 ? 4 : (q >= 64 ? 2 : 1); }
 
 int fmt_of(const altgdmin_problem* p) {
-  return p->a_format == ALTGDMIN_A_BF16X2 ? FMT_BF16X2 : FMT_F32;
+  return p->a_format == ALTGDMIN_A_BF16X2 ? FMT_BF16X2 : (p->a_format == ALTGDMIN_A_PHILOX ? FMT_PHILOX : FMT_F32);
 }
 
 }  // namespace
@@ -114,20 +114,26 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (p->r > kRMax) return fail(ALTGDMIN_ENOTBUILT, "r > 16 has no instantiation");
   if (p->rho < 0 || p->rho > p->n) return fail(ALTGDMIN_EINVAL, "need 0 <= rho <= n");
   if (p->m > 256 * kNCMax) return fail(ALTGDMIN_ENOTBUILT, "m > 1024 has no instantiation");
-  if (p->a_format != ALTGDMIN_A_F32 && p->a_format != ALTGDMIN_A_BF16X2)
+  if (p->a_format != ALTGDMIN_A_F32 && p->a_format != ALTGDMIN_A_BF16X2 && p->a_format != ALTGDMIN_A_PHILOX)
     return fail(ALTGDMIN_EINVAL, "unknown a_format");
-  if (!p->A || !p->Y) return fail(ALTGDMIN_EINVAL, "A and Y must be non-null");
-  if (p->a_format == ALTGDMIN_A_BF16X2 && !p->A_lo) return fail(ALTGDMIN_EINVAL, "BF16X2 needs A_lo");
-  if (p->lda < p->m || p->lda % 4 != 0) return fail(ALTGDMIN_EINVAL, "lda must be >= m and a multiple of 4");
-  if (p->a_stride_k < p->lda * (int64_t)p->n || p->a_stride_k % 4 != 0)
-    return fail(ALTGDMIN_EINVAL, "a_stride_k must be >= lda*n and a multiple of 4");
-  const size_t align = p->a_format == ALTGDMIN_A_F32 ? 16 : 8;
-  if (reinterpret_cast<uintptr_t>(p->A) % align != 0 ||
-      (p->A_lo && reinterpret_cast<uintptr_t>(p->A_lo) % align != 0))
-    return fail(ALTGDMIN_EINVAL, "A planes are not aligned to 4 elements");
+  if (!p->Y) return fail(ALTGDMIN_EINVAL, "Y must be non-null");
+  if (p->a_format == ALTGDMIN_A_PHILOX) {
+    if (!p->normal_table) return fail(ALTGDMIN_EINVAL, "PHILOX needs the normal table");
+  } else {
+    if (!p->A) return fail(ALTGDMIN_EINVAL, "A must be non-null");
+    if (p->a_format == ALTGDMIN_A_BF16X2 && !p->A_lo) return fail(ALTGDMIN_EINVAL, "BF16X2 needs A_lo");
+    if (p->lda < p->m || p->lda % 4 != 0) return fail(ALTGDMIN_EINVAL, "lda must be >= m and a multiple of 4");
+    if (p->a_stride_k < p->lda * (int64_t)p->n || p->a_stride_k % 4 != 0)
+      return fail(ALTGDMIN_EINVAL, "a_stride_k must be >= lda*n and a multiple of 4");
+    const size_t align = p->a_format == ALTGDMIN_A_F32 ? 16 : 8;
+    if (reinterpret_cast<uintptr_t>(p->A) % align != 0 ||
+        (p->A_lo && reinterpret_cast<uintptr_t>(p->A_lo) % align != 0))
+      return fail(ALTGDMIN_EINVAL, "A planes are not aligned to 4 elements");
+  }
   if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
   if (!au_supported(p->m, p->r)) return fail(ALTGDMIN_ENOTBUILT, "no A_k U instantiation for this (m, r)");
-  if (col_lds_bytes(p->n, p->m, p->r, p->rho, 1) > kMaxLds || au_lds_bytes(p->m, p->r) > kMaxLds)
+  const int phx = p->a_format == ALTGDMIN_A_PHILOX;
+  if (col_lds_bytes(p->n, p->m, p->r, p->rho, 1, phx) > kMaxLds || au_lds_bytes(p->m, p->r, phx) > kMaxLds)
     return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 64 KiB of LDS per column workgroup");
   if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
       !(par->eta_c >= 0.0) || par->bf16_hi_max < 0)
@@ -144,6 +150,7 @@ ColArgs col_args(const altgdmin_handle* h) {
   a.Y = p.Y; a.ldy = p.ldy;
   a.P = h->P; a.Ginv = h->Ginv; a.Tidx = h->Tidx; a.Tval = h->Tval;
   a.H = h->H; a.Bt = h->Bt; a.rr = h->colrr; a.flags = h->colflags;
+  a.seed = p.a_seed; a.table = p.normal_table;
   return a;
 }
 
@@ -168,6 +175,7 @@ int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
   au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
   au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
   au.gate = nullptr; au.gate_want = 0;
+  au.seed = p.a_seed; au.table = p.normal_table;
   ColArgs ca = col_args(h);
   ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
   if (h->hi_phase) {
@@ -307,6 +315,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
     au.gate = nullptr; au.gate_want = 0;
+    au.seed = p.a_seed; au.table = p.normal_table;
     ColArgs ca = col_args(h);
     ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
     hipError_t e = hipEventRecord(ev[0], st);
@@ -453,12 +462,14 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
   au.A = prob->A; au.Alo = prob->A_lo; au.lda = prob->lda; au.sA = prob->a_stride_k;
   au.U = U; au.P = P; au.Ginv = Lc; au.flags = flags;
   au.gate = nullptr; au.gate_want = 0;
+  au.seed = prob->a_seed; au.table = prob->normal_table;
   HIPCHK(launch_au(fmt_of(prob), au, static_cast<hipStream_t>(stream)));
   return ALTGDMIN_OK;
 }
 
 static int op_col(const altgdmin_problem* prob, ColArgs& a, void* stream) {
   a.n = prob->n; a.q = prob->q; a.m = prob->m; a.r = prob->r; a.rho = prob->rho;
+  a.seed = prob->a_seed; a.table = prob->normal_table;
   a.A = prob->A; a.Alo = prob->A_lo; a.lda = prob->lda; a.sA = prob->a_stride_k;
   a.Y = prob->Y; a.ldy = prob->ldy;
   HIPCHK(launch_col(fmt_of(prob), a, static_cast<hipStream_t>(stream)));
@@ -509,6 +520,13 @@ int altgdmin_op_backproject(const altgdmin_problem* prob, const int32_t* S_idx, 
   a.Tidx = const_cast<int32_t*>(S_idx); a.Tval = const_cast<float*>(S_val); a.H = L0t;
   a.tau = 0; a.project = 0; a.has_support = 1; a.tail = TAIL_BACKPROJ;
   return op_col(prob, a, stream);
+}
+
+int altgdmin_op_philox_fill(uint64_t seed, const float* normal_table, int32_t q, int32_t n, int32_t m, int64_t lda,
+                            float* A, void* stream) {
+  if (!normal_table || !A || q < 1 || n < 1 || m < 1 || lda < m) return fail(ALTGDMIN_EINVAL, "bad philox fill arguments");
+  HIPCHK(launch_philox_fill(seed, normal_table, q, n, m, lda, A, static_cast<hipStream_t>(stream)));
+  return ALTGDMIN_OK;
 }
 
 // scratch layout of the U-side entry points: Ctl | gpart (KS n r) | Utmp (n r) | T (q r)

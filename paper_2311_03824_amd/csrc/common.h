@@ -12,7 +12,8 @@ constexpr int kNCMax = 4;            // largest number of 256-row chunks per lan
 constexpr int kQRThreads = 1024;
 
 // A-operand formats (loader template argument)
-enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2 };
+enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2, FMT_PHILOX = 3 };
+constexpr int kNormalTable = 32 * 64 + 2;   // entries of the normal table of the Philox form
 
 // Device-side control block of one solve.
 struct Ctl {
@@ -54,6 +55,8 @@ struct ColArgs {
   int tau, project, has_support, tail;
   const int* gate;      // if non-null, the kernel runs only when *gate == gate_want
   int gate_want;
+  unsigned long long seed;  // Philox form: key of A
+  const float* table;       // Philox form: normal table (kNormalTable FP32)
 };
 
 struct AUArgs {
@@ -67,6 +70,8 @@ struct AUArgs {
   int* flags;
   const int* gate;      // if non-null, the kernel runs only when *gate == gate_want
   int gate_want;
+  unsigned long long seed;  // Philox form: key of A
+  const float* table;       // Philox form: normal table (kNormalTable FP32)
 };
 
 // ---------------------------------------------------------------- wave reductions
@@ -187,6 +192,60 @@ template <> struct ALoader<FMT_BF16HI> {
   }
 };
 
+// Philox form: element (i, j) of A_k is word i % 4 of Philox4x32-10 (Salmon et
+// al., SC'11) at counter (i / 4, j, k, 0) with key (seed low, seed high),
+// turned into a normal deviate by the inverse-CDF table in LDS: with
+// v = (2 (x & 0x7fffffff) + 1) 2^-33, idx from the exponent and the top six
+// mantissa bits of v, t from the other 17, |z| = T[idx] + (T[idx+1] - T[idx]) t
+// and the sign from the top bit of x.  Every operation is a correctly rounded
+// conversion or a non-contracted add/sub/mul, so the host definition gives the
+// same bits.
+__device__ __forceinline__ void philox4x32_10(uint32_t (&c)[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    // one 32 x 32 -> 64-bit multiply per product (v_mad_u64_u32) gives both halves
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0, n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = (uint32_t)p1;
+    c[2] = n2;
+    c[3] = (uint32_t)p0;
+  }
+}
+
+__device__ __forceinline__ float word_to_normal(uint32_t x, const float* tab) {
+#pragma clang fp contract(off)   // the definition rounds after the multiply and after the add
+  const uint32_t w = x & 0x7fffffffu;
+  const float v = (float)(2u * w + 1u) * 0x1p-33f;
+  const uint32_t bits = __float_as_uint(v);
+  const int idx = ((int)(bits >> 23) - (127 - 33)) * 64 + (int)((bits & 0x7fffffu) >> 17);
+  const float t = (float)(bits & 0x1ffffu) * 0x1p-17f;
+  const float lo = tab[idx], hi = tab[idx + 1];
+  const float d = hi - lo;
+  const float z = lo + d * t;
+  return (x >> 31) ? -z : z;
+}
+
+template <> struct ALoader<FMT_PHILOX> {
+  uint32_t k0, k1, col;
+  const float* tab;   // LDS copy of the normal table, set by the kernel
+  __device__ ALoader(const ColArgs& a, int k)
+      : k0((uint32_t)a.seed), k1((uint32_t)(a.seed >> 32)), col((uint32_t)k), tab(nullptr) {}
+  __device__ ALoader(const AUArgs& a, int k)
+      : k0((uint32_t)a.seed), k1((uint32_t)(a.seed >> 32)), col((uint32_t)k), tab(nullptr) {}
+  __device__ __forceinline__ float4 load(int j, int ch) const {
+    uint32_t c[4] = {(uint32_t)ch, (uint32_t)j, col, 0u};
+    philox4x32_10(c, k0, k1);
+    return make_float4(word_to_normal(c[0], tab), word_to_normal(c[1], tab), word_to_normal(c[2], tab),
+                       word_to_normal(c[3], tab));
+  }
+};
+
 // Zero the components of a 4-row chunk that lie at or beyond row m (nv = valid rows, 0..4).
 __device__ __forceinline__ float4 mask_rows(float4 v, int nv) {
   v.x = nv > 0 ? v.x : 0.f;
@@ -254,9 +313,9 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 // LDS layout of the column kernel in bytes; used by the host to size the
 // launch and by the kernel to carve its dynamic shared memory.
 struct ColLayout {
-  size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, hist, cbuf, total;
+  size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, hist, cbuf, tab, total;
   int mq;
-  __host__ __device__ ColLayout(int n, int m, int r, int rho, int project) {
+  __host__ __device__ ColLayout(int n, int m, int r, int rho, int project, int philox = 0) {
     mq = ((m + 3) / 4) * 4;
     size_t o = 0;
     ginv = o; o = align16(o + (project ? 8 * (size_t)r * r : 0));
@@ -270,14 +329,15 @@ struct ColLayout {
     red = o;  o = align16(o + 8 * 2 * kWaves);
     hist = o; o = align16(o + 4 * (256 + 8));
     cbuf = o; o = align16(o + 8 * kRMax);
+    tab = o;  o = align16(o + (philox ? 4 * (size_t)kNormalTable : 0));
     total = o;
   }
 };
 
 // LDS layout of the A_k U kernel.
 struct AULayout {
-  size_t P, gpart, G, L, Gi, y, total;
-  __host__ __device__ AULayout(int m, int r) {
+  size_t P, gpart, G, L, Gi, y, tab, total;
+  __host__ __device__ AULayout(int m, int r, int philox = 0) {
     size_t o = 0;
     P = o;     o = align16(o + 4 * (size_t)m * r);
     gpart = o; o = align16(o + 8 * (size_t)kThreads);
@@ -285,6 +345,7 @@ struct AULayout {
     L = o;     o = align16(o + 8 * (size_t)r * r);
     Gi = o;    o = align16(o + 8 * (size_t)r * r);
     y = o;     o = align16(o + 8 * (size_t)r);
+    tab = o;   o = align16(o + (philox ? 4 * (size_t)kNormalTable : 0));
     total = o;
   }
 };

@@ -319,7 +319,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
   const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r, rho = a.rho;
-  const ColLayout lay(n, m, r, rho, a.project);
+  const ColLayout lay(n, m, r, rho, a.project, FMT == FMT_PHILOX);
   double* Gi = reinterpret_cast<double*>(smem + lay.ginv);
   float* Pl = reinterpret_cast<float*>(smem + lay.P);
   float* wpart = reinterpret_cast<float*>(smem + lay.wpart);
@@ -334,7 +334,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
   const int mq = lay.mq;
   const int nwords = (n + 31) >> 5;
 
-  const ALoader<FMT> L(a, k);
+  ALoader<FMT> L(a, k);
+  if constexpr (FMT == FMT_PHILOX) {
+    float* tab = reinterpret_cast<float*>(smem + lay.tab);
+    for (int t = tid; t < kNormalTable; t += kThreads) tab[t] = a.table[t];
+    L.tab = tab;   // read only after the barrier that ends the LDS set-up below
+  }
   const Lane<NC> ln(lane, m);
 
   float4 yv[NC];
@@ -466,14 +471,20 @@ __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
   const int k = blockIdx.x;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r;
-  const AULayout lay(m, r);
+  const AULayout lay(m, r, FMT == FMT_PHILOX);
   float* Pl = reinterpret_cast<float*>(smem + lay.P);
   double* gpart = reinterpret_cast<double*>(smem + lay.gpart);
   double* Gl = reinterpret_cast<double*>(smem + lay.G);
   double* Ll = reinterpret_cast<double*>(smem + lay.L);
   double* Gil = reinterpret_cast<double*>(smem + lay.Gi);
   double* yl = reinterpret_cast<double*>(smem + lay.y);
-  const ALoader<FMT> L(a, k);
+  ALoader<FMT> L(a, k);
+  if constexpr (FMT == FMT_PHILOX) {
+    float* tab = reinterpret_cast<float*>(smem + lay.tab);
+    for (int t = tid; t < kNormalTable; t += kThreads) tab[t] = a.table[t];
+    L.tab = tab;
+    __syncthreads();
+  }
   const Lane<NC> ln(lane, m);
 
   float acc[NC][4][R];
@@ -610,7 +621,8 @@ typedef void (*col_fn)(ColArgs);
 typedef void (*au_fn)(AUArgs);
 
 #define COL_ROW(F) {k_col<F, 1>, k_col<F, 2>, k_col<F, 3>, k_col<F, 4>}
-static const col_fn kColTable[3][kNCMax] = {COL_ROW(FMT_F32), COL_ROW(FMT_BF16X2), COL_ROW(FMT_BF16HI)};
+static const col_fn kColTable[4][kNCMax] = {COL_ROW(FMT_F32), COL_ROW(FMT_BF16X2), COL_ROW(FMT_BF16HI),
+                                            COL_ROW(FMT_PHILOX)};
 
 // k_au keeps 4*NC*R accumulators per lane; instantiations above 128 are left out.
 template <int F, int NC, int R>
@@ -618,7 +630,8 @@ constexpr au_fn au_inst() { return (4 * NC * R <= 128) ? k_au<F, NC, (4 * NC * R
 #define AU_NC(F, NC) {au_inst<F, NC, 2>(), au_inst<F, NC, 4>(), au_inst<F, NC, 6>(), au_inst<F, NC, 8>(), \
                       au_inst<F, NC, 10>(), au_inst<F, NC, 12>(), au_inst<F, NC, 14>(), au_inst<F, NC, 16>()}
 #define AU_ROW(F) {AU_NC(F, 1), AU_NC(F, 2), AU_NC(F, 3), AU_NC(F, 4)}
-static const au_fn kAUTable[3][kNCMax][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2), AU_ROW(FMT_BF16HI)};
+static const au_fn kAUTable[4][kNCMax][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2), AU_ROW(FMT_BF16HI),
+                                                     AU_ROW(FMT_PHILOX)};
 
 bool au_supported(int m, int r) {
   const int nc = (m + 255) / 256;
@@ -628,7 +641,7 @@ bool au_supported(int m, int r) {
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
   const int nc = (a.m + 255) / 256;
-  const ColLayout lay(a.n, a.m, a.r, a.rho, a.project);
+  const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColTable[fmt][nc - 1], dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
@@ -637,13 +650,46 @@ hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
   const int nc = (a.m + 255) / 256;
   const int ri = (a.r + 1) / 2 - 1;
-  const AULayout lay(a.m, a.r);
+  const AULayout lay(a.m, a.r, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kAUTable[fmt][nc - 1][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
 }
 
-size_t col_lds_bytes(int n, int m, int r, int rho, int project) { return ColLayout(n, m, r, rho, project).total; }
-size_t au_lds_bytes(int m, int r) { return AULayout(m, r).total; }
+size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox) {
+  return ColLayout(n, m, r, rho, project, philox).total;
+}
+size_t au_lds_bytes(int m, int r, int philox) { return AULayout(m, r, philox).total; }
+
+// Materialises the Philox form of A into the FP32 layout (one thread per 4-row chunk).
+__global__ __launch_bounds__(256) void k_philox_fill(unsigned long long seed, const float* table, int q, int n, int m,
+                                                     long long lda, float* A) {
+  __shared__ float tab[kNormalTable];
+  for (int t = threadIdx.x; t < kNormalTable; t += blockDim.x) tab[t] = table[t];
+  __syncthreads();
+  const int nch = (m + 3) / 4;
+  const long long total = (long long)q * n * nch;
+  AUArgs dummy;
+  dummy.seed = seed;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x) {
+    const int ch = (int)(e % nch);
+    const int j = (int)((e / nch) % n);
+    const int k = (int)(e / ((long long)nch * n));
+    ALoader<FMT_PHILOX> L(dummy, k);
+    L.tab = tab;
+    const float4 v = L.load(j, ch);
+    float* dst = A + (long long)k * n * lda + (long long)j * lda + 4 * ch;
+    const float vv[4] = {v.x, v.y, v.z, v.w};
+    for (int c = 0; c < 4; ++c)
+      if (4 * ch + c < m) dst[c] = vv[c];
+  }
+}
+
+hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,
+                              hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_philox_fill, dim3(1024), dim3(256), 0, st, seed, table, q, n, m, lda, A);
+  return hipGetLastError();
+}
 
 }  // namespace altg

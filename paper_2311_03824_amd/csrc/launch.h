@@ -31,8 +31,10 @@ constexpr size_t kQRLdsMax = 48 * 1024;   // dynamic LDS for the n x r block of 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
 bool au_supported(int m, int r);
-size_t col_lds_bytes(int n, int m, int r, int rho, int project);
-size_t au_lds_bytes(int m, int r);
+size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox);
+size_t au_lds_bytes(int m, int r, int philox);
+hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,
+                              hipStream_t st);
 size_t select_lds_bytes(int n, int rho);
 hipError_t launch_select(const float* V, int n, int count, long long ldv, int rho, int* idx, float* val,
                          int* flags, hipStream_t st);

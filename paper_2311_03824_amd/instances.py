@@ -67,6 +67,78 @@ def split_bf16(a: np.ndarray):
     return hi_bits, lo_bits, canon
 
 
+# ---------------------------------------------------------------- Philox form of A
+# A_k entries regenerated from a counter: Philox4x32-10 (Salmon, Moraes, Dror,
+# Shaw, SC'11) with key = (seed low word, seed high word) and counter
+# (chunk, j, k, 0), where chunk = i // 4 indexes 4 consecutive rows of column j;
+# output word i % 4 gives element (i, j) of A_k.  A 32-bit word x becomes a normal
+# deviate by an inverse-CDF table, log-spaced in v = (2 (x & 0x7fffffff) + 1) 2^-33
+# (v in (0, 1/2], the smaller of u and 1 - u for u uniform on (0, 1)):
+# |z| = T[idx] + (T[idx+1] - T[idx]) t with idx from the exponent and the top 6
+# mantissa bits of v and t from the remaining 17 bits, and sign(z) = top bit of x.
+# Only correctly rounded FP32 conversions, subtractions, multiplications and
+# additions are used, so every implementation of this definition gives the same bits.
+
+PHILOX_M0, PHILOX_M1 = 0xD2511F53, 0xCD9E8D57
+PHILOX_W0, PHILOX_W1 = 0x9E3779B9, 0xBB67AE85
+NORMAL_TABLE_EXPONENTS = 32          # v in [2^-33, 2^-1); v = 1/2 maps to the last two entries
+NORMAL_TABLE_SUB = 64                # 6 mantissa bits per exponent
+
+
+def philox4x32_10(c0, c1, c2, c3, k0: int, k1: int):
+    """Philox4x32 with 10 rounds on arrays of counter words; returns four uint32 arrays."""
+    m = np.uint64(0xFFFFFFFF)
+    c = [np.asarray(x).astype(np.uint64) for x in (c0, c1, c2, c3)]
+    M0, M1 = np.uint64(PHILOX_M0), np.uint64(PHILOX_M1)
+    for rnd in range(10):
+        if rnd > 0:
+            k0 = (k0 + PHILOX_W0) & 0xFFFFFFFF
+            k1 = (k1 + PHILOX_W1) & 0xFFFFFFFF
+        p0 = M0 * c[0]
+        p1 = M1 * c[2]
+        c = [(p1 >> np.uint64(32)) ^ c[1] ^ np.uint64(k0), p1 & m, (p0 >> np.uint64(32)) ^ c[3] ^ np.uint64(k1), p0 & m]
+    return [x.astype(np.uint32) for x in c]
+
+
+def normal_table() -> np.ndarray:
+    """|z| = -ndtri(v) at v = 2^(e-33) (1 + s/64), e = 0..31, s = 0..63, then two entries for
+    v = 1/2 (z = 0); FP32 values of the FP64 ndtri, 32 * 64 + 2 entries."""
+    from scipy.special import ndtri
+    e = np.arange(NORMAL_TABLE_EXPONENTS)[:, None]
+    s_ = np.arange(NORMAL_TABLE_SUB)[None, :]
+    v = np.ldexp(1.0 + s_ / NORMAL_TABLE_SUB, e - 33).ravel()
+    t = -ndtri(np.concatenate([v, [0.5, 0.5]]))
+    return np.abs(t).astype(np.float32)
+
+
+def words_to_normal(x: np.ndarray, table: np.ndarray) -> np.ndarray:
+    """The table transform of uint32 words x into FP32 normal deviates."""
+    x = np.asarray(x, dtype=np.uint32)
+    w = (x & np.uint32(0x7FFFFFFF)).astype(np.uint64)
+    v = (np.uint64(2) * w + np.uint64(1)).astype(np.float32) * np.float32(2.0 ** -33)
+    bits = v.view(np.uint32)
+    e_idx = (bits >> np.uint32(23)).astype(np.int64) - (127 - 33)
+    mant = bits & np.uint32(0x7FFFFF)
+    idx = e_idx * NORMAL_TABLE_SUB + (mant >> np.uint32(17)).astype(np.int64)
+    t = (mant & np.uint32(0x1FFFF)).astype(np.float32) * np.float32(2.0 ** -17)
+    lo = table[idx]
+    hi = table[idx + 1]
+    z = lo + (hi - lo) * t
+    return np.where(x >> np.uint32(31) != 0, -z, z).astype(np.float32)
+
+
+def philox_A(seed: int, k_range, n: int, m: int, lda: int, table: np.ndarray) -> np.ndarray:
+    """A_k^T (len(k_range), n, lda) FP32 for the Philox form; rows m..lda-1 are zero."""
+    ks = np.asarray(list(k_range), dtype=np.uint64)
+    nch = (m + 3) // 4
+    K, J, C = np.meshgrid(ks, np.arange(n, dtype=np.uint64), np.arange(nch, dtype=np.uint64), indexing="ij")
+    w = philox4x32_10(C, J, K, np.zeros_like(C), seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF)
+    z = np.stack([words_to_normal(wi, table) for wi in w], axis=-1).reshape(len(ks), n, nch * 4)
+    out = np.zeros((len(ks), n, lda), np.float32)
+    out[:, :, :m] = z[:, :, :m]
+    return out
+
+
 def round_up(x: int, mult: int) -> int:
     return (x + mult - 1) // mult * mult
 
@@ -89,6 +161,8 @@ class Instance:
     U_start: np.ndarray   # (n, r) float32, Gaussian start block for subspace iteration
     A_hi: Optional[np.ndarray] = None  # (q, n, lda) uint16 bf16 hi plane
     A_lo: Optional[np.ndarray] = None  # (q, n, lda) uint16 bf16 lo plane
+    a_seed: Optional[int] = None       # Philox form: the 64-bit key of A
+    table: Optional[np.ndarray] = None # Philox form: the normal table
 
     @property
     def lda(self) -> int:
@@ -116,12 +190,14 @@ def _rng(seed: int, tag: int) -> np.random.Generator:
 def make_instance(n: int, q: int, m: int, r: int, rho: int, seed: int,
                   s_dist: str = "normal", s_scale: float = 10.0,
                   s_zero: bool = False, lda_mult: int = 8,
-                  bf16_planes: bool = False, chunk: int = 64) -> Instance:
+                  bf16_planes: bool = False, chunk: int = 64, a_form: str = "gauss") -> Instance:
     """Draw one seeded instance.
 
     s_dist: "normal" draws S* values N(0, s_scale^2); "uniform" draws
     U[-s_scale, s_scale] (the S1 law of Sec. 3); "pm_powers" draws from
     {+-1, +-10, +-100} (the S2 law of Sec. 3).  s_zero=True gives S* = 0.
+    a_form="philox" draws A from the Philox definition above (key derived from the
+    seed) instead of the canonical bf16 hi + lo of a NumPy Gaussian draw.
     """
     if not (1 <= r <= min(m, n)) or not (0 <= rho <= n) or min(n, q, m) < 1:
         raise ValueError("invalid sizes")
@@ -150,18 +226,39 @@ def make_instance(n: int, q: int, m: int, r: int, rho: int, seed: int,
         S_star[supp, np.arange(q)[:, None]] = vals
     X_star = U_star @ B_star + S_star
 
+    a_seed = table = None
+    if a_form == "philox":
+        a_seed = int(_rng(seed, _TAG_A).integers(0, 2**63))
+        table = normal_table()
+    elif a_form != "gauss":
+        raise ValueError(a_form)
     # A: canonical hi + lo of an FP32 Gaussian draw, drawn column by column (k)
     ra = _rng(seed, _TAG_A)
     At = np.zeros((q, n, lda), np.float32)
     A_hi = np.zeros((q, n, lda), np.uint16) if bf16_planes else None
     A_lo = np.zeros((q, n, lda), np.uint16) if bf16_planes else None
     Y64 = np.empty((q, m))
-    for k0 in range(0, q, chunk):
+    starts = list(range(0, q, chunk))
+    philox_chunks = None
+    if a_form == "philox":
+        # independent column ranges, generated in parallel (NumPy releases the GIL in its loops)
+        import concurrent.futures as cf
+        import os as _os
+        workers = max(1, min(16, len(_os.sched_getaffinity(0))))
+        with cf.ThreadPoolExecutor(max_workers=workers) as ex:
+            philox_chunks = list(ex.map(
+                lambda k0: philox_A(a_seed, range(k0, min(q, k0 + chunk)), n, m, m, table), starts))
+    for ci, k0 in enumerate(starts):
         k1 = min(q, k0 + chunk)
-        a = ra.standard_normal((k1 - k0, n, m), dtype=np.float32)
-        hb, lb, canon = split_bf16(a)
+        if a_form == "philox":
+            canon = philox_chunks[ci]
+            philox_chunks[ci] = None
+            hb = lb = None
+        else:
+            a = ra.standard_normal((k1 - k0, n, m), dtype=np.float32)
+            hb, lb, canon = split_bf16(a)
         At[k0:k1, :, :m] = canon
-        if bf16_planes:
+        if bf16_planes and hb is not None:
             A_hi[k0:k1, :, :m] = hb
             A_lo[k0:k1, :, :m] = lb
         # y_k = A_k x*_k in FP64 (A_k^T stored row-major, so y_k = x*_k^T At_k)
@@ -169,7 +266,8 @@ def make_instance(n: int, q: int, m: int, r: int, rho: int, seed: int,
     U_start = _rng(seed, _TAG_START).standard_normal((n, r)).astype(np.float32)
     return Instance(n=n, q=q, m=m, r=r, rho=rho, seed=seed, At=At,
                     Y32=Y64.astype(np.float32), Y64=Y64, U_star=U_star, B_star=B_star,
-                    S_star=S_star, supp=supp, U_start=U_start, A_hi=A_hi, A_lo=A_lo)
+                    S_star=S_star, supp=supp, U_start=U_start, A_hi=A_hi, A_lo=A_lo,
+                    a_seed=a_seed, table=table)
 
 
 def make_workload(name: str, **kw) -> Instance:

@@ -411,3 +411,47 @@ def test_bf16_stall_rule_switches(lib, torch):
     assert 1 <= t < 120
     assert log[t - 1] >= 0.9 * log[t - 2]        # the stall that triggered the switch
     assert log[-1] <= 1e-5 * 10                   # hi + lo reaches the FP32 floor afterwards
+
+
+# ---------------------------------------------------------------- a13(c): Philox regeneration
+
+@pytest.mark.parametrize("q,n,m", [(3, 50, 37), (20, 301, 150), (4, 1000, 400)])
+def test_philox_device_generator_bitexact(lib, torch, q, n, m):
+    seed = 0x1234_5678_9ABC_DEF0 + q
+    T = I.normal_table()
+    lda = ((m + 7) // 8) * 8
+    A = torch.zeros((q, n, lda), dtype=torch.float32, device="cuda")
+    lib.altgdmin_op_philox_fill(seed, dev(torch, T), q, n, m, A)
+    torch.cuda.synchronize()
+    ref = I.philox_A(seed, range(q), n, m, lda, T)
+    assert np.array_equal(host(A).view(np.uint32), ref.view(np.uint32))
+
+
+def test_philox_form_equals_fp32_plane(lib, torch):
+    """The kernels regenerate exactly the values the FP32 plane holds: identical solves."""
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=19, a_form="philox")
+    par = lib.default_params(t_max=25)
+    a = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par)
+    a.init().step(25)
+    ra = a.get()
+    a.close()
+    b = lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, philox_seed=inst.a_seed,
+                   normal_table=inst.table, n=inst.n)
+    b.init().step(25)
+    rb = b.get()
+    b.close()
+    for key in ("U", "Bt", "S_idx", "S_val"):
+        assert np.array_equal(ra[key], rb[key])
+
+
+def test_philox_solve_matches_oracle(lib, torch):
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=23, a_form="philox")
+    par = lib.default_params(t_max=60)
+    s = lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, philox_seed=inst.a_seed,
+                   normal_table=inst.table, n=inst.n)
+    s.init().step(60)
+    out = s.get()
+    s.close()
+    st, hist = O.solve(inst.A64(), inst.Y32.astype(np.float64), inst.r, inst.rho, t_max=60, X_star=inst.X_star)
+    assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
