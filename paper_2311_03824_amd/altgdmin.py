@@ -70,6 +70,8 @@ _SIGS = {
     "altgdmin_solve": (c_i32, [c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_destroy": (c_i32, [c_vp]),
     "altgdmin_profile_iteration": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
+    "altgdmin_group_bytes": (c_i32, [c_vp, c_i32, c_vp]),
+    "altgdmin_step_many": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_sz, c_vp]),
     "altgdmin_strerror": (ctypes.c_char_p, [c_i32]),
     "altgdmin_last_error": (ctypes.c_char_p, []),
     "altgdmin_op_select": (c_i32, [c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp]),
@@ -209,6 +211,26 @@ def altgdmin_residual_log(h, t_max: int, stream=None) -> np.ndarray:
     cnt = c_i32(0)
     _check(_lib.altgdmin_residual_log(h, stream_ptr(stream), buf, ctypes.byref(cnt)))
     return np.array(buf[: cnt.value])
+
+
+def _handle_array(hs):
+    arr = (c_vp * len(hs))()
+    for i, h in enumerate(hs):
+        arr[i] = h.value if isinstance(h, c_vp) else h
+    return arr
+
+
+def altgdmin_group_bytes(hs) -> int:
+    load()
+    b = c_sz(0)
+    _check(_lib.altgdmin_group_bytes(_handle_array(hs), len(hs), ctypes.byref(b)))
+    return b.value
+
+
+def altgdmin_step_many(hs, iters: int, group_ws, stream=None) -> None:
+    """One batched launch sequence per iteration over all handles (serving)."""
+    _check(_lib.altgdmin_step_many(_handle_array(hs), len(hs), iters, ptr(group_ws),
+                                   group_ws.numel() * group_ws.element_size(), stream_ptr(stream)))
 
 
 KERNELS = ("k_au", "k_col", "k_grad", "k_qr")

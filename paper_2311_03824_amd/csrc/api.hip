@@ -3,8 +3,10 @@
 // Host side only: validation, workspace carving, launch sequencing and the HIP
 // graph of one GDmin iteration.  Every step of the method runs in the kernels
 // of k_column.hip and k_small.hip.
+#include <algorithm>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "altgdmin.h"
 #include "launch.h"
@@ -437,6 +439,138 @@ const char* altgdmin_strerror(int code) {
 }
 
 const char* altgdmin_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ serving: batched iterations
+
+namespace {
+
+struct GroupPlan {
+  std::vector<AUArgs> au;
+  std::vector<ColArgs> col;
+  std::vector<GradArgs> grad;
+  std::vector<QRArgs> qr;
+  std::vector<int2> au_map[4], col_map[4];
+  std::vector<int4> grad_map;
+  size_t au_lds[4] = {0, 0, 0, 0}, col_lds[4] = {0, 0, 0, 0}, qr_lds = 0;
+  int rmax[4] = {0, 0, 0, 0}, ncmax[4] = {0, 0, 0, 0};
+  // byte offsets in the group workspace
+  size_t o_au, o_col, o_grad, o_qr, o_aum[4], o_colm[4], o_gm, total;
+};
+
+int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
+  if (!hs || count < 1) return fail(ALTGDMIN_EINVAL, "no handles");
+  for (int i = 0; i < count; ++i) {
+    altgdmin_handle* h = hs[i];
+    if (!h) return fail(ALTGDMIN_EINVAL, "null handle");
+    if (h->hi_phase) return fail(ALTGDMIN_EINVAL, "a BF16X2 problem with a hi-only phase cannot be batched");
+    const altgdmin_problem& p = h->prob;
+    AUArgs au;
+    std::memset(&au, 0, sizeof(au));
+    au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
+    au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
+    au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+    au.seed = p.a_seed; au.table = p.normal_table;
+    g.au.push_back(au);
+    ColArgs ca = col_args(h);
+    ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
+    g.col.push_back(ca);
+    GradArgs ga;
+    ga.H = h->H; ga.B = h->Bt; ga.n = p.n; ga.q = p.q; ga.r = p.r; ga.KS = h->KS; ga.gpart = h->gpart;
+    g.grad.push_back(ga);
+    QRArgs qa = qr_args(h, QR_GD);
+    qa.lds = (size_t)p.n * p.r * sizeof(float) <= kQRLdsMax ? 1 : 0;
+    if (qa.lds) g.qr_lds = std::max(g.qr_lds, (size_t)p.n * p.r * sizeof(float));
+    g.qr.push_back(qa);
+    const int f = h->fmt, phx = f == FMT_PHILOX;
+    for (int k = 0; k < p.q; ++k) {
+      g.au_map[f].push_back(make_int2(i, k));
+      g.col_map[f].push_back(make_int2(i, k));
+    }
+    for (int jb = 0; jb < (p.n + 63) / 64; ++jb)
+      for (int ks = 0; ks < h->KS; ++ks) g.grad_map.push_back(make_int4(i, jb, ks, 0));
+    g.au_lds[f] = std::max(g.au_lds[f], AULayout(p.m, p.r, phx).total);
+    g.col_lds[f] = std::max(g.col_lds[f], ColLayout(p.n, p.m, p.r, p.rho, 1, phx).total);
+    g.rmax[f] = std::max(g.rmax[f], p.r);
+    g.ncmax[f] = std::max(g.ncmax[f], (p.m + 255) / 256);
+  }
+  size_t o = 0;
+  auto take = [&](size_t bytes) { o = (o + kAlign - 1) / kAlign * kAlign; size_t r = o; o += bytes; return r; };
+  g.o_au = take(g.au.size() * sizeof(AUArgs));
+  g.o_col = take(g.col.size() * sizeof(ColArgs));
+  g.o_grad = take(g.grad.size() * sizeof(GradArgs));
+  g.o_qr = take(g.qr.size() * sizeof(QRArgs));
+  for (int f = 0; f < 4; ++f) {
+    g.o_aum[f] = take(g.au_map[f].size() * sizeof(int2));
+    g.o_colm[f] = take(g.col_map[f].size() * sizeof(int2));
+  }
+  g.o_gm = take(g.grad_map.size() * sizeof(int4));
+  g.total = (o + kAlign - 1) / kAlign * kAlign;
+  return ALTGDMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int altgdmin_group_bytes(altgdmin_handle* const* hs, int32_t count, size_t* bytes) {
+  if (!bytes) return fail(ALTGDMIN_EINVAL, "bytes is null");
+  GroupPlan g;
+  int rc = plan_group(hs, count, g);
+  if (rc) return rc;
+  *bytes = g.total;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters, void* group_ws, size_t group_bytes,
+                       void* stream) {
+  if (iters < 0 || !group_ws || reinterpret_cast<uintptr_t>(group_ws) % kAlign != 0)
+    return fail(ALTGDMIN_EINVAL, "bad step_many arguments");
+  GroupPlan g;
+  int rc = plan_group(hs, count, g);
+  if (rc) return rc;
+  if (group_bytes < g.total) return fail(ALTGDMIN_ENOWS, "group workspace too small: need " + std::to_string(g.total));
+  for (int f = 0; f < 4; ++f)
+    if (g.au_lds[f] > kMaxLds || g.col_lds[f] > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
+  std::vector<char> buf(g.total, 0);
+  auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(buf.data() + off, src, bytes); };
+  put(g.o_au, g.au.data(), g.au.size() * sizeof(AUArgs));
+  put(g.o_col, g.col.data(), g.col.size() * sizeof(ColArgs));
+  put(g.o_grad, g.grad.data(), g.grad.size() * sizeof(GradArgs));
+  put(g.o_qr, g.qr.data(), g.qr.size() * sizeof(QRArgs));
+  for (int f = 0; f < 4; ++f) {
+    put(g.o_aum[f], g.au_map[f].data(), g.au_map[f].size() * sizeof(int2));
+    put(g.o_colm[f], g.col_map[f].data(), g.col_map[f].size() * sizeof(int2));
+  }
+  put(g.o_gm, g.grad_map.data(), g.grad_map.size() * sizeof(int4));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* dev = static_cast<char*>(group_ws);
+  HIPCHK(hipMemcpyAsync(dev, buf.data(), g.total, hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));   // the host staging buffer is released on return
+  const AUArgs* au_tab = reinterpret_cast<const AUArgs*>(dev + g.o_au);
+  const ColArgs* col_tab = reinterpret_cast<const ColArgs*>(dev + g.o_col);
+  const GradArgs* grad_tab = reinterpret_cast<const GradArgs*>(dev + g.o_grad);
+  const QRArgs* qr_tab = reinterpret_cast<const QRArgs*>(dev + g.o_qr);
+  for (int it = 0; it < iters; ++it) {
+    for (int f = 0; f < 4; ++f)
+      if (!g.au_map[f].empty())
+        HIPCHK(launch_au_grp(f, g.rmax[f], au_tab, reinterpret_cast<const int2*>(dev + g.o_aum[f]),
+                             (int)g.au_map[f].size(), g.au_lds[f], st));
+    for (int f = 0; f < 4; ++f)
+      if (!g.col_map[f].empty())
+        HIPCHK(launch_col_grp(f, g.ncmax[f], col_tab, reinterpret_cast<const int2*>(dev + g.o_colm[f]),
+                              (int)g.col_map[f].size(), g.col_lds[f], st));
+    HIPCHK(launch_grad_grp(grad_tab, reinterpret_cast<const int4*>(dev + g.o_gm), (int)g.grad_map.size(), st));
+    HIPCHK(launch_qr_grp(qr_tab, count, g.qr_lds, st));
+  }
+  for (int i = 0; i < count; ++i) hs[i]->t_host += iters;
+  return ALTGDMIN_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
 
 // ------------------------------------------------------------------ step-level entry points
 

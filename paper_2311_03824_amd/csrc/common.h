@@ -272,39 +272,47 @@ __device__ __forceinline__ float get4(float4 v, int e) {
 }
 
 // Lower Cholesky factor L of an SPD r x r FP64 matrix G (row-major), then
-// G^{-1} = L^{-T} L^{-1} into Ginv.  Single thread; L and y (r doubles) are
-// scratch (LDS).  Returns false, and writes the identity, if a pivot is not
-// positive.
-__device__ inline bool chol_inverse(const double* G, double* L, double* Ginv, double* y, int r) {
+// G^{-1} = L^{-T} L^{-1} into Ginv, for an SPD r x r matrix G (r <= 64), by the
+// whole workgroup (every thread calls it).  Cholesky G = L L^T column by column:
+// thread j + 1 + t computes L[j + 1 + t][j]; then thread c solves L y = e_c and
+// L^T x = y for column c of G^{-1} (y in Y, column c at Y[i * r + c]).  G, L,
+// Ginv, Y live in LDS.  Returns false, with the identity in Ginv, if a pivot is
+// not positive; the result is the same on every thread.
+__device__ inline bool block_chol_inverse(const double* G, double* L, double* Ginv, double* Y, int r) {
+  const int tid = threadIdx.x;
   for (int j = 0; j < r; ++j) {
     double s = G[j * r + j];
     for (int p = 0; p < j; ++p) s -= L[j * r + p] * L[j * r + p];
-    if (!(s > 0.0)) {
-      for (int i = 0; i < r * r; ++i) Ginv[i] = (i % (r + 1) == 0) ? 1.0 : 0.0;
+    if (!(s > 0.0)) {   // every thread computed the same s
+      for (int i = tid; i < r * r; i += blockDim.x) Ginv[i] = (i % (r + 1) == 0) ? 1.0 : 0.0;
+      __syncthreads();
       return false;
     }
     const double d = sqrt(s);
-    L[j * r + j] = d;
-    for (int i = j + 1; i < r; ++i) {
+    const int i = j + 1 + tid;
+    if (i < r) {
       double t = G[i * r + j];
       for (int p = 0; p < j; ++p) t -= L[i * r + p] * L[j * r + p];
       L[i * r + j] = t / d;
     }
-    for (int i = 0; i < j; ++i) L[i * r + j] = 0.0;
+    if (tid == 0) L[j * r + j] = d;
+    if (tid < j) L[tid * r + j] = 0.0;
+    __syncthreads();
   }
-  // column c of G^{-1}: solve L y = e_c, then L^T x = y
-  for (int c = 0; c < r; ++c) {
-    for (int i = 0; i < r; ++i) {
+  if (tid < r) {
+    const int c = tid;
+    for (int i = c; i < r; ++i) {           // rows above c of y are zero
       double t = (i == c) ? 1.0 : 0.0;
-      for (int p = 0; p < i; ++p) t -= L[i * r + p] * y[p];
-      y[i] = t / L[i * r + i];
+      for (int p = c; p < i; ++p) t -= L[i * r + p] * Y[p * r + c];
+      Y[i * r + c] = t / L[i * r + i];
     }
     for (int i = r - 1; i >= 0; --i) {
-      double t = y[i];
+      double t = i >= c ? Y[i * r + c] : 0.0;
       for (int p = i + 1; p < r; ++p) t -= L[p * r + i] * Ginv[p * r + c];
       Ginv[i * r + c] = t / L[i * r + i];
     }
   }
+  __syncthreads();
   return true;
 }
 
@@ -312,14 +320,17 @@ __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(
 
 // LDS layout of the column kernel in bytes; used by the host to size the
 // launch and by the kernel to carve its dynamic shared memory.
+constexpr size_t kPInLdsMax = 32 * 1024;   // P_k is staged in LDS up to this size
+
 struct ColLayout {
   size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, hist, cbuf, tab, total;
-  int mq;
+  int mq, p_in_lds;
   __host__ __device__ ColLayout(int n, int m, int r, int rho, int project, int philox = 0) {
     mq = ((m + 3) / 4) * 4;
+    p_in_lds = 4 * (size_t)m * r <= kPInLdsMax;
     size_t o = 0;
     ginv = o; o = align16(o + (project ? 8 * (size_t)r * r : 0));
-    P = o;    o = align16(o + (project ? 4 * (size_t)m * r : 0));
+    P = o;    o = align16(o + (project && p_in_lds ? 4 * (size_t)m * r : 0));
     wpart = o; o = align16(o + 4 * (size_t)kWaves * mq);
     g = o;    o = align16(o + 4 * (size_t)n);
     sd = o;   o = align16(o + 4 * (size_t)n);
@@ -337,14 +348,19 @@ struct ColLayout {
 // LDS layout of the A_k U kernel.
 struct AULayout {
   size_t P, gpart, G, L, Gi, y, tab, total;
+  int p_in_lds, mp;
   __host__ __device__ AULayout(int m, int r, int philox = 0) {
+    mp = ((m + 3) / 4) * 4 + 4;                     // LDS row stride of the column-major P
+    p_in_lds = 4 * (size_t)mp * r <= kPInLdsMax;
+    const size_t ust = 4 * (size_t)kWaves * 64 * ((((r + 1) / 2 * 2) + 3) / 4 * 4);   // staged rows of U
+    const size_t pb = p_in_lds ? 4 * (size_t)mp * r : 0;
     size_t o = 0;
-    P = o;     o = align16(o + 4 * (size_t)m * r);
-    gpart = o; o = align16(o + 8 * (size_t)kThreads);
+    P = o;     o = align16(o + (pb > ust ? pb : ust));
+    gpart = o; o = align16(o + 4 * 8 * (size_t)kThreads);
     G = o;     o = align16(o + 8 * (size_t)r * r);
     L = o;     o = align16(o + 8 * (size_t)r * r);
     Gi = o;    o = align16(o + 8 * (size_t)r * r);
-    y = o;     o = align16(o + 8 * (size_t)r);
+    y = o;     o = align16(o + 8 * (size_t)r * r);
     tab = o;   o = align16(o + (philox ? 4 * (size_t)kNormalTable : 0));
     total = o;
   }

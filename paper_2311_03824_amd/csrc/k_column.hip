@@ -313,15 +313,13 @@ __device__ int block_select(const float* vals, int n, int rho, int* idx, float* 
 // ---------------------------------------------------------------- k_col
 
 template <int FMT, int NC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col(ColArgs a) {
-  if (a.gate && *a.gate != a.gate_want) return;
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int k = blockIdx.x;
+__device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char* smem) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r, rho = a.rho;
   const ColLayout lay(n, m, r, rho, a.project, FMT == FMT_PHILOX);
   double* Gi = reinterpret_cast<double*>(smem + lay.ginv);
-  float* Pl = reinterpret_cast<float*>(smem + lay.P);
+  // P_k in LDS when it fits, else read from the workspace copy in global memory
+  float* Pl = lay.p_in_lds ? reinterpret_cast<float*>(smem + lay.P) : const_cast<float*>(a.P + (long long)k * m * r);
   float* wpart = reinterpret_cast<float*>(smem + lay.wpart);
   float* gl = reinterpret_cast<float*>(smem + lay.g);
   float* sd = reinterpret_cast<float*>(smem + lay.sd);
@@ -358,7 +356,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
   for (int w = tid; w < nwords; w += kThreads) inT[w] = 0u;
   if (a.project) {
     const float* Pk = a.P + (long long)k * m * r;
-    for (int t = tid; t < m * r; t += kThreads) Pl[t] = Pk[t];
+    if (lay.p_in_lds)
+      for (int t = tid; t < m * r; t += kThreads) Pl[t] = Pk[t];
     const double* Gk = a.Ginv + (long long)k * r * r;
     for (int t = tid; t < r * r; t += kThreads) Gi[t] = Gk[t];
   }
@@ -462,17 +461,37 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
   if (tid == 0 && nan_seen > 0 && a.flags) a.flags[k] |= 1;
 }
 
-// ---------------------------------------------------------------- k_au
-
-template <int FMT, int NC, int R>
-__global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
+template <int FMT, int NC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col(ColArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  const int k = blockIdx.x;
+  col_body<FMT, NC>(a, blockIdx.x, smem);
+}
+
+// Several problems in one launch: block b works on column map[b].y of problem map[b].x.
+template <int FMT, int NC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col_grp(
+    const ColArgs* tab, const int2* map) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int2 mp = map[blockIdx.x];
+  const ColArgs a = tab[mp.x];
+  col_body<FMT, NC>(a, mp.y, smem);
+}
+
+// ---------------------------------------------------------------- k_au
+
+// One column k of A_k U.  Waves split the 256-row chunks of A_k first and the
+// columns j second: with nch = ceil(m / 256) chunks, wave w takes chunk w / js
+// and columns j = w % js, w % js + js, ... where js = 4 / nch (1 when nch > 2);
+// each lane holds 4 rows x R accumulators.  Partial P_k of the waves sharing a
+// chunk are added in a fixed order (in LDS when P_k fits, else in global memory).
+template <int FMT, int R>
+__device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* smem) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r;
   const AULayout lay(m, r, FMT == FMT_PHILOX);
-  float* Pl = reinterpret_cast<float*>(smem + lay.P);
+  float* Pk = a.P + (long long)k * m * r;
+  float* Pp = lay.p_in_lds ? reinterpret_cast<float*>(smem + lay.P) : Pk;
   double* gpart = reinterpret_cast<double*>(smem + lay.gpart);
   double* Gl = reinterpret_cast<double*>(smem + lay.G);
   double* Ll = reinterpret_cast<double*>(smem + lay.L);
@@ -485,105 +504,183 @@ __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
     L.tab = tab;
     __syncthreads();
   }
-  const Lane<NC> ln(lane, m);
+  const int nch = (m + 255) >> 8;
+  const int js = nch == 1 ? 4 : (nch == 2 ? 2 : 1);
+  const int cs = wave / js, jw = wave % js;
+  const bool active = cs < nch;
+  const int ch = lane + 64 * cs;
+  const int chmax = (m - 1) >> 2;
+  const int chc = ch < chmax ? ch : chmax;
+  const int nvr = m - 4 * ch;
+  const int nv = nvr < 0 ? 0 : (nvr > 4 ? 4 : nvr);
 
-  float acc[NC][4][R];
+  float acc[4][R];
 #pragma unroll
-  for (int c = 0; c < NC; ++c)
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int rr = 0; rr < R; ++rr) acc[e][rr] = 0.f;
+
+  // software pipeline, AUD columns deep: the A_k loads of the next AUD columns
+  // of this wave are in flight while the 4R FMAs of the current column are
+  // issued.  The rows of U this wave needs are staged 64 at a time in its own
+  // LDS slice (lane t loads the row of the wave's t-th next column) and read back
+  // as broadcast 16-byte LDS loads, so the FMAs take plain register operands.
+  constexpr int AUD = 4;
+  constexpr int RP = (R + 3) / 4 * 4;
+  float* Uw = reinterpret_cast<float*>(smem + lay.P) + wave * 64 * RP;   // shares the P region
+  const float* U = a.U;
+  auto fetch = [&](int j, float4& a4) {
+    const int jc = j < n ? j : n - 1;   // clamped: always a legal address
+    a4 = L.load(jc, chc);
+  };
+  float un[RP];
+  auto load_rows = [&](int t0) {        // rows of columns jw + js (t0 + t), t = lane
+    const int jrow = jw + js * (t0 + lane);
+    const int jr = jrow < n ? jrow : n - 1;
+#pragma unroll
+    for (int rr = 0; rr < RP; ++rr) un[rr] = U[(long long)jr * r + (rr < r ? rr : 0)];
+  };
+  auto store_rows = [&](int t0) {
+    const int jrow = jw + js * (t0 + lane);
+#pragma unroll
+    for (int rr = 0; rr < RP; ++rr) Uw[lane * RP + rr] = (jrow < n && rr < r) ? un[rr] : 0.f;
+  };
+  auto fma_col = [&](float4 a4, int t) {  // t: slot of the column in the staged block
+    float u[RP];
+#pragma unroll
+    for (int q4 = 0; q4 < RP / 4; ++q4) {
+      const float4 w4 = *reinterpret_cast<const float4*>(Uw + t * RP + 4 * q4);
+      u[4 * q4] = w4.x; u[4 * q4 + 1] = w4.y; u[4 * q4 + 2] = w4.z; u[4 * q4 + 3] = w4.w;
+    }
+    a4 = mask_rows(a4, nv);
 #pragma unroll
     for (int e = 0; e < 4; ++e)
 #pragma unroll
-      for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = 0.f;
-
-  // software pipeline, two columns deep: columns j+4 and j+8 of A_k and the
-  // matching rows of U are in flight while the 4*NC*R FMAs of column j are
-  // issued.  Row j of U is fetched by lanes 0..r-1 with one vector load (in-order
-  // vmcnt tracking, unlike scalar loads) and broadcast with readlane.
-  const float* U = a.U;
-  auto fetch = [&](int j, float4 (&a4)[NC], float& uv) {
-    const int jc = j < n ? j : n - 1;   // clamped: always a legal address
-#pragma unroll
-    for (int c = 0; c < NC; ++c) a4[c] = L.load(jc, ln.chc[c]);
-    uv = U[(long long)jc * r + (lane < r ? lane : 0)];
+      for (int rr = 0; rr < R; ++rr) acc[e][rr] = fmaf(get4(a4, e), u[rr], acc[e][rr]);
   };
-  auto fma_col = [&](float4 (&a4)[NC], float uv) {
-    float u[R];
+  if (active) {
+    float4 buf[AUD];
 #pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-      u[rr] = rr < r ? __int_as_float(__builtin_amdgcn_readlane(__float_as_int(uv), rr)) : 0.f;
+    for (int d = 0; d < AUD; ++d) fetch(jw + d * js, buf[d]);
+    int cnt = 0;                        // columns of this wave done so far
+    for (int j = jw; j < n; j += AUD * js) {
 #pragma unroll
-    for (int c = 0; c < NC; ++c) a4[c] = mask_rows(a4[c], ln.nv[c]);
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-#pragma unroll
-        for (int rr = 0; rr < R; ++rr) acc[c][e][rr] = fmaf(get4(a4[c], e), u[rr], acc[c][e][rr]);
-  };
-  float4 b0[NC], b1[NC], b2[NC];
-  float u0, u1, u2;
-  fetch(wave, b0, u0);
-  fetch(wave + kWaves, b1, u1);
-  for (int j = wave; j < n; j += 3 * kWaves) {
-    fetch(j + 2 * kWaves, b2, u2);
-    fma_col(b0, u0);
-    if (j + kWaves >= n) break;
-    fetch(j + 3 * kWaves, b0, u0);
-    fma_col(b1, u1);
-    if (j + 2 * kWaves >= n) break;
-    fetch(j + 4 * kWaves, b1, u1);
-    fma_col(b2, u2);
+      for (int d = 0; d < AUD; ++d) {
+        const int jj = j + d * js;
+        if (jj < n) {
+          if ((cnt & 63) == 0) {         // wave-local: the LDS accesses of one wave complete in order
+            __builtin_amdgcn_wave_barrier();
+            load_rows(cnt);
+            store_rows(cnt);
+            __builtin_amdgcn_wave_barrier();
+          }
+          const float4 cur = buf[d];
+          fetch(jj + AUD * js, buf[d]);
+          fma_col(cur, cnt & 63);
+          ++cnt;
+        }
+      }
+    }
   }
-  // partial P of the waves summed in wave order
-  for (int w = 0; w < kWaves; ++w) {
-    if (wave == w) {
+  __syncthreads();   // the staged rows of U share LDS with P
+
+  // partial P of the waves sharing a chunk, added in column-split order.  In
+  // LDS, P is column-major with row stride mp (lane-contiguous 16-byte stores);
+  // in global memory it is row-major m x r.
+  const int mp = lay.mp;
+  for (int s = 0; s < js; ++s) {
+    if (active && jw == s && nv > 0) {
+      if (lay.p_in_lds) {
 #pragma unroll
-      for (int c = 0; c < NC; ++c)
+        for (int rr = 0; rr < R; ++rr)
+          if (rr < r) {
+            float4* dst = reinterpret_cast<float4*>(Pp + rr * mp + 4 * ch);
+            float4 v = make_float4(acc[0][rr], acc[1][rr], acc[2][rr], acc[3][rr]);
+            if (s > 0) {
+              const float4 o = *dst;
+              v = make_float4(o.x + v.x, o.y + v.y, o.z + v.z, o.w + v.w);
+            }
+            *dst = v;
+          }
+      } else {
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          if (e < ln.nv[c]) {
-            const int i = 4 * ln.ch[c] + e;
+          if (e < nv) {
+            const int i = 4 * ch + e;
 #pragma unroll
             for (int rr = 0; rr < R; ++rr)
-              if (rr < r) Pl[i * r + rr] = (w == 0) ? acc[c][e][rr] : Pl[i * r + rr] + acc[c][e][rr];
+              if (rr < r) Pp[i * r + rr] = (s == 0) ? acc[e][rr] : Pp[i * r + rr] + acc[e][rr];
           }
+      }
     }
     __syncthreads();
   }
-  float* Pk = a.P + (long long)k * m * r;
-  for (int t = tid; t < m * r; t += kThreads) Pk[t] = Pl[t];
+  if (lay.p_in_lds)
+    for (int t = tid; t < m * r; t += kThreads) {
+      const int i = t / r, rr = t - i * r;
+      Pk[t] = Pp[rr * mp + i];
+    }
+  auto pval = [&](int i, int c) -> double {
+    return (double)(lay.p_in_lds ? Pp[c * mp + i] : Pp[i * r + c]);
+  };
 
-  // G = P^T P in FP64: entry e = (ra, rb), ra <= rb; threads split the rows
-  const int E = r * (r + 1) / 2;
-  const int parts = kThreads / E;
-  const int e = tid % E, part = tid / E;
-  int ra = 0, rb = 0;
+  // G = P^T P in FP64.  Thread (blk, part) accumulates the 2 x 2 block
+  // (2ba .. 2ba+1) x (2bb .. 2bb+1), ba <= bb, over rows part, part + parts, ...;
+  // the parts are then added in order.  Columns beyond r read as zero.
+  const int RB = (r + 1) >> 1;
+  const int nb = RB * (RB + 1) / 2;
+  const int parts = kThreads / nb;
   {
-    int base = 0;
-    for (ra = 0; ra < r; ++ra) {
-      const int cnt = r - ra;
-      if (e < base + cnt) { rb = ra + (e - base); break; }
-      base += cnt;
+    const int blk = tid % nb, part = tid / nb;
+    int ba = 0, base = 0;
+    while (blk >= base + (RB - ba)) { base += RB - ba; ++ba; }
+    const int bb = ba + (blk - base);
+    const int c0 = 2 * ba, c1 = 2 * ba + 1, d0 = 2 * bb, d1 = 2 * bb + 1;
+    double g00 = 0.0, g01 = 0.0, g10 = 0.0, g11 = 0.0;
+    if (part < parts)
+      for (int i = part; i < m; i += parts) {
+        const double x0 = pval(i, c0), x1 = c1 < r ? pval(i, c1) : 0.0;
+        const double y0 = pval(i, d0), y1 = d1 < r ? pval(i, d1) : 0.0;
+        g00 = fma(x0, y0, g00); g01 = fma(x0, y1, g01);
+        g10 = fma(x1, y0, g10); g11 = fma(x1, y1, g11);
+      }
+    gpart[4 * tid] = g00; gpart[4 * tid + 1] = g01; gpart[4 * tid + 2] = g10; gpart[4 * tid + 3] = g11;
+  }
+  __syncthreads();
+  if (tid < 4 * nb) {
+    const int blk = tid >> 2, w = tid & 3;
+    int ba = 0, base = 0;
+    while (blk >= base + (RB - ba)) { base += RB - ba; ++ba; }
+    const int bb = ba + (blk - base);
+    const int ra = 2 * ba + (w >> 1), rb = 2 * bb + (w & 1);
+    double t = 0.0;
+    for (int p = 0; p < parts; ++p) t += gpart[4 * (p * nb + blk) + w];
+    if (ra < r && rb < r) {
+      Gl[ra * r + rb] = t;
+      Gl[rb * r + ra] = t;
     }
   }
-  double s = 0.0;
-  if (part < parts)
-    for (int i = part; i < m; i += parts) s = fma((double)Pl[i * r + ra], (double)Pl[i * r + rb], s);
-  gpart[tid] = s;
   __syncthreads();
-  if (tid < E) {
-    double t = 0.0;
-    for (int p = 0; p < parts; ++p) t += gpart[p * E + tid];
-    Gl[ra * r + rb] = t;
-    Gl[rb * r + ra] = t;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    if (!chol_inverse(Gl, Ll, Gil, yl, r) && a.flags) a.flags[k] |= 2;
-  }
-  __syncthreads();
+  const bool spd = block_chol_inverse(Gl, Ll, Gil, yl, r);
+  if (!spd && tid == 0 && a.flags) a.flags[k] |= 2;
   double* Gk = a.Ginv + (long long)k * r * r;
   for (int t = tid; t < r * r; t += kThreads) Gk[t] = Gil[t];
+}
+
+template <int FMT, int R>
+__global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
+  if (a.gate && *a.gate != a.gate_want) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  au_body<FMT, R>(a, blockIdx.x, smem);
+}
+
+// Several problems in one launch: block b works on column map[b].y of problem map[b].x.
+template <int FMT, int R>
+__global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const int2* map) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int2 mp = map[blockIdx.x];
+  const AUArgs a = tab[mp.x];
+  au_body<FMT, R>(a, mp.y, smem);
 }
 
 // HardThreshold of one vector per workgroup (the step-level select entry point).
@@ -619,25 +716,23 @@ hipError_t launch_select(const float* V, int n, int count, long long ldv, int rh
 
 typedef void (*col_fn)(ColArgs);
 typedef void (*au_fn)(AUArgs);
+typedef void (*colg_fn)(const ColArgs*, const int2*);
+typedef void (*aug_fn)(const AUArgs*, const int2*);
 
 #define COL_ROW(F) {k_col<F, 1>, k_col<F, 2>, k_col<F, 3>, k_col<F, 4>}
 static const col_fn kColTable[4][kNCMax] = {COL_ROW(FMT_F32), COL_ROW(FMT_BF16X2), COL_ROW(FMT_BF16HI),
                                             COL_ROW(FMT_PHILOX)};
+#define COLG_ROW(F) {k_col_grp<F, 1>, k_col_grp<F, 2>, k_col_grp<F, 3>, k_col_grp<F, 4>}
+static const colg_fn kColGrpTable[4][kNCMax] = {COLG_ROW(FMT_F32), COLG_ROW(FMT_BF16X2), COLG_ROW(FMT_BF16HI),
+                                                COLG_ROW(FMT_PHILOX)};
+#define AU_ROW(F) {k_au<F, 2>, k_au<F, 4>, k_au<F, 6>, k_au<F, 8>, k_au<F, 10>, k_au<F, 12>, k_au<F, 14>, k_au<F, 16>}
+static const au_fn kAUTable[4][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2), AU_ROW(FMT_BF16HI), AU_ROW(FMT_PHILOX)};
+#define AUG_ROW(F) {k_au_grp<F, 2>, k_au_grp<F, 4>, k_au_grp<F, 6>, k_au_grp<F, 8>, k_au_grp<F, 10>, k_au_grp<F, 12>, \
+                    k_au_grp<F, 14>, k_au_grp<F, 16>}
+static const aug_fn kAUGrpTable[4][kRMax / 2] = {AUG_ROW(FMT_F32), AUG_ROW(FMT_BF16X2), AUG_ROW(FMT_BF16HI),
+                                                 AUG_ROW(FMT_PHILOX)};
 
-// k_au keeps 4*NC*R accumulators per lane; instantiations above 128 are left out.
-template <int F, int NC, int R>
-constexpr au_fn au_inst() { return (4 * NC * R <= 128) ? k_au<F, NC, (4 * NC * R <= 128 ? R : 2)> : nullptr; }
-#define AU_NC(F, NC) {au_inst<F, NC, 2>(), au_inst<F, NC, 4>(), au_inst<F, NC, 6>(), au_inst<F, NC, 8>(), \
-                      au_inst<F, NC, 10>(), au_inst<F, NC, 12>(), au_inst<F, NC, 14>(), au_inst<F, NC, 16>()}
-#define AU_ROW(F) {AU_NC(F, 1), AU_NC(F, 2), AU_NC(F, 3), AU_NC(F, 4)}
-static const au_fn kAUTable[4][kNCMax][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2), AU_ROW(FMT_BF16HI),
-                                                     AU_ROW(FMT_PHILOX)};
-
-bool au_supported(int m, int r) {
-  const int nc = (m + 255) / 256;
-  const int R = 2 * ((r + 1) / 2);
-  return nc >= 1 && nc <= kNCMax && r >= 1 && r <= kRMax && 4 * nc * R <= 128;
-}
+bool au_supported(int m, int r) { return m >= 1 && m <= 256 * kNCMax && r >= 1 && r <= kRMax; }
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
   const int nc = (a.m + 255) / 256;
@@ -648,11 +743,23 @@ hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
-  const int nc = (a.m + 255) / 256;
   const int ri = (a.r + 1) / 2 - 1;
   const AULayout lay(a.m, a.r, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUTable[fmt][nc - 1][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  hipLaunchKernelGGL(kAUTable[fmt][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_grp(int fmt, int nc, const ColArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColGrpTable[fmt][nc - 1], dim3(blocks), dim3(kThreads), lds, st, tab, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st) {
+  const int ri = (rmax + 1) / 2 - 1;
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kAUGrpTable[fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab, map);
   return hipGetLastError();
 }
 

@@ -14,17 +14,14 @@
 namespace altg {
 
 // One workgroup of 16 waves per block of 64 rows j; wave w sums the columns
-// k = w, w + 16, ... of its split; the 16 wave partials are added in wave order.
-// Row k of B is fetched by lanes 0..r-1 with one vector load and broadcast with
-// readlane, so that loads of later columns stay in flight.
-constexpr int kGradWaves = 16;
-__global__ __launch_bounds__(kGradWaves * 64) void k_grad(const float* __restrict__ H, const float* __restrict__ B,
-                                                          int n, int q, int r, int KS, float* __restrict__ gpart,
-                                                          const int* skip) {
-  if (skip && *skip) return;
-  __shared__ float red[kGradWaves / 2][64][kRMax + 1];
+// k = w, w + 16, ... of its split; the 16 wave partials are added in a fixed
+// pairwise order.  Row k of B is fetched by lanes 0..r-1 with one vector load
+// and broadcast with readlane, so that loads of later columns stay in flight.
+__device__ __forceinline__ void grad_body(const float* __restrict__ H, const float* __restrict__ B, int n, int q, int r,
+                                          int KS, float* __restrict__ gpart, int jblock, int ks,
+                                          float (*red)[64][kRMax + 1]) {
   const int lane = threadIdx.x & 63, ph = wave_id();
-  const int j = blockIdx.x * 64 + lane, ks = blockIdx.y;
+  const int j = jblock * 64 + lane;
   const int jc = j < n ? j : n - 1;
   const int k0 = (int)((long long)q * ks / KS), k1 = (int)((long long)q * (ks + 1) / KS);
   float acc[kRMax];
@@ -50,18 +47,34 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_grad(const float* __restric
     }
   }
   // pairwise tree over the waves in a fixed order: (w, w + h) for h = 8, 4, 2, 1
-  for (int h = kGradWaves / 2; h >= 1; h >>= 1) {
-    if (ph >= h && ph < 2 * h)
+  for (int hh = kGradWaves / 2; hh >= 1; hh >>= 1) {
+    if (ph >= hh && ph < 2 * hh)
 #pragma unroll
-      for (int c = 0; c < kRMax; ++c) red[ph - h][lane][c] = acc[c];
+      for (int c = 0; c < kRMax; ++c) red[ph - hh][lane][c] = acc[c];
     __syncthreads();
-    if (ph < h)
+    if (ph < hh)
 #pragma unroll
       for (int c = 0; c < kRMax; ++c) acc[c] += red[ph][lane][c];
     __syncthreads();
   }
   if (ph == 0 && j < n)
     for (int c = 0; c < r; ++c) gpart[((long long)ks * n + j) * r + c] = acc[c];
+}
+
+__global__ __launch_bounds__(kGradWaves * 64) void k_grad(const float* __restrict__ H, const float* __restrict__ B,
+                                                          int n, int q, int r, int KS, float* __restrict__ gpart,
+                                                          const int* skip) {
+  if (skip && *skip) return;
+  __shared__ float red[kGradWaves / 2][64][kRMax + 1];
+  grad_body(H, B, n, q, r, KS, gpart, blockIdx.x, blockIdx.y, red);
+}
+
+// Several problems in one launch: block b is (problem, row block, split) = map[b].
+__global__ __launch_bounds__(kGradWaves * 64) void k_grad_grp(const GradArgs* tab, const int4* map) {
+  __shared__ float red[kGradWaves / 2][64][kRMax + 1];
+  const int4 mp = map[blockIdx.x];
+  const GradArgs a = tab[mp.x];
+  grad_body(a.H, a.B, a.n, a.q, a.r, a.KS, a.gpart, mp.y, mp.z, red);
 }
 
 __global__ __launch_bounds__(256) void k_ltu(const float* __restrict__ L0t, const float* __restrict__ U, int n,
@@ -206,12 +219,19 @@ __device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W,
 }
 
 // The n x r block lives in LDS when it fits (a.lds != 0), else in a.Utmp.
-__global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
-  __shared__ double sh[kQRThreads];
-  __shared__ double W[kRMax * kRMax], Lf[kRMax];
-  __shared__ double eta_s;
-  __shared__ int okflag;
+struct QRShared {
+  double sh[kQRThreads];
+  double W[kRMax * kRMax], Lf[kRMax];
+  double eta_s;
+  int okflag;
+};
+
+__device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
+  double* sh = S.sh;
+  double* W = S.W;
+  double* Lf = S.Lf;
+  double& eta_s = S.eta_s;
+  int& okflag = S.okflag;
   const int tid = threadIdx.x;
   const int n = a.n, r = a.r, nr = n * r;
   if (a.mode == QR_POWER && a.ctl && a.ctl->conv) return;
@@ -301,6 +321,20 @@ __global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
       a.ctl->prev_resid = resid;
     }
   }
+}
+
+__global__ __launch_bounds__(kQRThreads) void k_qr(QRArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
+  __shared__ QRShared S;
+  qr_body(a, dsm, S);
+}
+
+// Several problems in one launch: block b updates the U of problem b.
+__global__ __launch_bounds__(kQRThreads) void k_qr_grp(const QRArgs* tab) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char dsm[];
+  __shared__ QRShared S;
+  const QRArgs a = tab[blockIdx.x];
+  qr_body(a, dsm, S);
 }
 
 // ||Y||_F^2 from the per-column values, fixed order.
@@ -399,6 +433,18 @@ hipError_t launch_qr(const QRArgs& a_in, hipStream_t st) {
   a.lds = bytes <= kQRLdsMax ? 1 : 0;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(k_qr, dim3(1), dim3(kQRThreads), a.lds ? bytes : 0, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_grp(const GradArgs* tab, const int4* map, int blocks, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_grad_grp, dim3(blocks), dim3(kGradWaves * 64), 0, st, tab, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_qr_grp(const QRArgs* tab, int count, size_t lds, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_qr_grp, dim3(count), dim3(kQRThreads), lds, st, tab);
   return hipGetLastError();
 }
 

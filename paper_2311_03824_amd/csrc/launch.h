@@ -27,10 +27,20 @@ struct QRArgs {
 };
 
 constexpr size_t kQRLdsMax = 48 * 1024;   // dynamic LDS for the n x r block of k_qr
+constexpr int kGradWaves = 16;             // waves of a gradient-reduction workgroup
+
+struct GradArgs {
+  const float* H;
+  const float* B;
+  int n, q, r, KS;
+  float* gpart;
+};
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
 bool au_supported(int m, int r);
+hipError_t launch_col_grp(int fmt, int nc, const ColArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st);
 size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox);
 size_t au_lds_bytes(int m, int r, int philox);
 hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,
@@ -44,6 +54,8 @@ hipError_t launch_grad(const float* H, const float* B, int n, int q, int r, int 
 hipError_t launch_ltu(const float* L0t, const float* U, int n, int q, int r, float* T, const int* skip,
                       hipStream_t st);
 hipError_t launch_qr(const QRArgs& a, hipStream_t st);
+hipError_t launch_grad_grp(const GradArgs* tab, const int4* map, int blocks, hipStream_t st);
+hipError_t launch_qr_grp(const QRArgs* tab, int count, size_t lds, hipStream_t st);
 hipError_t launch_sum_ctl(const double* colrr, int q, Ctl* ctl, hipStream_t st);
 hipError_t launch_reset_ctl(Ctl* ctl, int full, hipStream_t st);
 hipError_t launch_set_phase(Ctl* ctl, int phase, hipStream_t st);

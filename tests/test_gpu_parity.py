@@ -59,6 +59,7 @@ SHAPES = [
     dict(n=301, q=37, m=150, r=3, rho=7),       # m % 4 = 2
     dict(n=517, q=20, m=333, r=5, rho=11),      # two chunks, ragged
     dict(n=260, q=16, m=701, r=8, rho=9),       # three chunks
+    dict(n=1100, q=6, m=1020, r=16, rho=20),    # four chunks, P_k too large for LDS
 ]
 
 
@@ -455,3 +456,42 @@ def test_philox_solve_matches_oracle(lib, torch):
     st, hist = O.solve(inst.A64(), inst.Y32.astype(np.float64), inst.r, inst.rho, t_max=60, X_star=inst.X_star)
     assert np.array_equal(out["S_idx"], st.idx)
     assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+
+
+# ---------------------------------------------------------------- serving: batched launches
+
+def test_step_many_equals_solo(lib, torch):
+    """Each problem gives the same result alone and batched with others of other sizes and formats."""
+    specs = [dict(n=300, q=40, m=120, r=2, rho=5, seed=1, bf16=False),
+             dict(n=257, q=33, m=700, r=16, rho=3, seed=2, bf16=True),     # 3 chunks, P_k in global memory
+             dict(n=640, q=70, m=250, r=5, rho=20, seed=3, bf16=False)]
+    insts = [I.make_instance(n=s["n"], q=s["q"], m=s["m"], r=s["r"], rho=s["rho"], seed=s["seed"],
+                             bf16_planes=s["bf16"]) for s in specs]
+    iters = 25
+
+    def solver(inst, bf16):
+        par = lib.default_params(t_max=iters)
+        if bf16:
+            return lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=inst.A_hi, A_lo=inst.A_lo)
+        return lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par)
+
+    solo = []
+    for inst, sp in zip(insts, specs):
+        s = solver(inst, sp["bf16"])
+        s.init().step(iters)
+        solo.append(s.get())
+        s.close()
+    group = [solver(inst, sp["bf16"]) for inst, sp in zip(insts, specs)]
+    for s in group:
+        s.init()
+    hs = [s.h for s in group]
+    gws = torch.empty(lib.altgdmin_group_bytes(hs) + 256, dtype=torch.uint8, device="cuda")
+    for _ in range(5):
+        lib.altgdmin_step_many(hs, iters // 5, gws)
+    mixed = [s.get() for s in group]
+    for s in group:
+        assert s.status()["iterations"] == iters
+        s.close()
+    for a, b in zip(solo, mixed):
+        for key in ("U", "Bt", "S_idx", "S_val"):
+            assert np.array_equal(a[key], b[key]), key
