@@ -1,0 +1,155 @@
+"""Host-side checks of the C ABI (no GPU work): the library loads, exports every
+function include/altgdmin.h declares, the ctypes structs of the binding have the
+C layout, and the host-only entry points validate their arguments as documented.
+"""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "altgdmin.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = set(re.findall(r"\b(altgdmin_[a-z0-9_]+)\s*\(", text))
+    return sorted(names)
+
+
+def test_header_declares_the_binding_functions(lib):
+    declared = set(_declared_functions())
+    assert declared == set(lib.EXPORTED), (declared ^ set(lib.EXPORTED))
+
+
+def test_library_exports_every_declared_symbol(lib):
+    so = lib.load()
+    missing = [f for f in _declared_functions() if not hasattr(so, f)]
+    assert not missing, missing
+
+
+_PROBE = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "altgdmin.h"
+#define F(T, f) printf(#T " " #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("altgdmin_problem sizeof %zu\n", sizeof(altgdmin_problem));
+  printf("altgdmin_params sizeof %zu\n", sizeof(altgdmin_params));
+  printf("altgdmin_report sizeof %zu\n", sizeof(altgdmin_report));
+  %FIELDS%
+  return 0;
+}
+"""
+
+
+@pytest.mark.skipif(shutil.which("gcc") is None, reason="needs a C compiler")
+def test_struct_layouts_match_c(lib, tmp_path):
+    structs = {"altgdmin_problem": lib.Problem, "altgdmin_params": lib.Params, "altgdmin_report": lib.Report}
+    fields = "\n  ".join(f"F({c}, {f})" for c, py in structs.items() for f, _ in py._fields_)
+    src = tmp_path / "probe.c"
+    src.write_text(_PROBE.replace("%FIELDS%", fields))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-I", os.path.dirname(HEADER), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for c, py in structs.items():
+        assert got[(c, "sizeof")] == ctypes.sizeof(py), c
+        for f, _ in py._fields_:
+            assert got[(c, f)] == getattr(py, f).offset, (c, f)
+
+
+def _problem(lib, **kw):
+    """A problem whose device pointers are placeholders: only validated, never dereferenced."""
+    p = lib.Problem()
+    p.n, p.q, p.m, p.r, p.rho = 1000, 1000, 400, 10, 50
+    p.a_format = lib.ALTGDMIN_A_F32
+    p.A, p.Y = 1 << 20, 1 << 24
+    p.lda, p.a_stride_k, p.ldy = 400, 400 * 1000, 400
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ws(lib, p, par=None):
+    so = lib.load()
+    par = par or lib.default_params()
+    b = ctypes.c_size_t(0)
+    rc = so.altgdmin_workspace_bytes(ctypes.byref(p), ctypes.byref(par), ctypes.byref(b))
+    return rc, b.value, so.altgdmin_last_error().decode()
+
+
+def test_default_params_are_the_papers(lib):
+    par = lib.default_params()
+    assert (par.tau0, par.tau, par.t_max) == (10, 3, 200)
+    assert par.eta_c == pytest.approx(0.14)
+    assert par.tol_resid == 0.0 and par.flags == 0
+
+
+def test_workspace_bytes_accepts_the_benchmark_problem(lib):
+    rc, b, _ = _ws(lib, _problem(lib))
+    assert rc == 0 and b > 0
+    rc2, b2, _ = _ws(lib, _problem(lib, q=2000))
+    assert rc2 == 0 and b2 > b          # per-column state grows with q
+    assert b % 256 == 0
+
+
+@pytest.mark.parametrize("kw, code", [
+    (dict(r=17), -5),                   # no instantiation above r = 16
+    (dict(m=1025, lda=1028, a_stride_k=1028 * 1000, ldy=1025), -5),
+    (dict(r=0), -1),
+    (dict(r=12, m=10, lda=12, ldy=12, a_stride_k=12000), -1),   # r > m
+    (dict(rho=1001), -1),
+    (dict(rho=-1), -1),
+    (dict(lda=402), -1),                # not a multiple of 4
+    (dict(lda=396), -1),                # lda < m
+    (dict(a_stride_k=400 * 999), -1),   # A_k overlap
+    (dict(ldy=399), -1),
+    (dict(A=None), -1),
+    (dict(Y=None), -1),
+    (dict(A=(1 << 20) + 4), -1),        # base not 16-byte aligned
+    (dict(a_format=7), -1),
+    (dict(a_format=1), -1),             # BF16X2 without the lo plane
+    (dict(a_format=2), -1),             # PHILOX without the normal table
+])
+def test_workspace_bytes_rejects_invalid_problems(lib, kw, code):
+    rc, _, msg = _ws(lib, _problem(lib, **kw))
+    assert rc == code
+    assert msg
+
+
+def test_workspace_bytes_rejects_invalid_params(lib):
+    for field, value in [("tau", -1), ("t_max", -1), ("poll_every", 0), ("eta_c", -0.1), ("bf16_hi_max", -2)]:
+        par = lib.default_params(**{field: value})
+        rc, _, _ = _ws(lib, _problem(lib), par)
+        assert rc == -1, field
+
+
+def test_philox_problem_needs_no_A(lib):
+    p = _problem(lib, a_format=2, A=None, lda=0, a_stride_k=0)
+    p.normal_table = 1 << 22
+    rc, b, _ = _ws(lib, p)
+    assert rc == 0 and b > 0
+
+
+def test_strerror_covers_every_code(lib):
+    so = lib.load()
+    texts = {c: so.altgdmin_strerror(c).decode() for c in (0, 1, -1, -2, -3, -4, -5)}
+    assert all(texts.values())
+    assert len(set(texts.values())) == len(texts)
+
+
+def test_op_scratch_bytes_is_host_only(lib):
+    so = lib.load()
+    b = ctypes.c_size_t(0)
+    assert so.altgdmin_op_scratch_bytes(1000, 1000, 10, ctypes.byref(b)) == 0
+    assert b.value >= 4 * 1000 * 10
+    assert so.altgdmin_op_scratch_bytes(0, 1000, 10, ctypes.byref(b)) < 0
