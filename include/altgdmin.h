@@ -198,6 +198,22 @@ int altgdmin_op_select(const float* V, int32_t n, int32_t count, int64_t ldv, in
 int altgdmin_op_philox_fill(uint64_t seed, const float* normal_table, int32_t q, int32_t n, int32_t m,
                             int64_t lda, float* A, void* stream);
 
+/* Synthetic measurement matrices (input generation, not a step of Alg. 1): the
+ * draw a of element (i, j) of A_k is the value altgdmin_op_philox_fill writes; the
+ * stored matrix is the canonical A = hi + lo, hi = bf16_RN(a), lo = bf16_RN(a - hi)
+ * (round to nearest even), exact in FP32.  a_format ALTGDMIN_A_F32 writes hi + lo
+ * as FP32 into A; ALTGDMIN_A_BF16X2 writes the hi plane into A and the lo plane
+ * into A_lo (uint16).  Layout A[k*n*lda + j*lda + i]; rows m..lda-1 are written
+ * as zeros; lda a multiple of 4.  Asynchronous on `stream`. */
+int altgdmin_op_make_a(uint64_t seed, const float* normal_table, int32_t q, int32_t n, int32_t m,
+                       int64_t lda, int32_t a_format, void* A, void* A_lo, void* stream);
+
+/* Measurements of the model of Sec. 1.1, y_k = A_k x_k (noise-free), for the A
+ * of `prob` in any format (prob->Y is ignored).  Xt: q x n FP64 row-major
+ * (x_k at Xt[k*n]); Y: y_k at Y[k*ldy + i] in FP32.  Each y_k[i] is accumulated
+ * in FP64 over j = 0..n-1 in order and rounded once.  Asynchronous. */
+int altgdmin_op_measure(const altgdmin_problem* prob, const double* Xt, float* Y, void* stream);
+
 /* P_k = A_k U (m x r, row-major per k at P[k*m*r]) and the Cholesky factor
  * L_k (lower, r x r row-major FP64 at Lc[k*r*r]) of G_k = P_k^T P_k, the pieces
  * of (A_k U)^dagger in eq. (bk_LS).  flags[k] gets bit 1 if G_k is not positive definite. */

@@ -77,6 +77,8 @@ _SIGS = {
     "altgdmin_op_select": (c_i32, [c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_au": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_philox_fill": (c_i32, [ctypes.c_uint64, c_vp, c_i32, c_i32, c_i32, c_i64, c_vp, c_vp]),
+    "altgdmin_op_make_a": (c_i32, [ctypes.c_uint64, c_vp, c_i32, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp]),
+    "altgdmin_op_measure": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_iht": (c_i32, [c_vp, c_i32, c_vp, c_vp, c_i32, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_lsgrad": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_backproject": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp]),
@@ -268,6 +270,21 @@ def altgdmin_op_philox_fill(seed: int, normal_table, q: int, n: int, m: int, A, 
     """Write the Philox form of A (q, n, lda) FP32 into the device tensor A."""
     load()
     _check(_lib.altgdmin_op_philox_fill(int(seed), ptr(normal_table), q, n, m, A.shape[2], ptr(A), stream_ptr(stream)))
+
+
+def altgdmin_op_make_a(seed: int, normal_table, q: int, n: int, m: int, A, A_lo=None, stream=None) -> None:
+    """Write the canonical synthetic A: FP32 (q, n, lda) into A, or, with A_lo given,
+    the BF16 hi plane into A and the lo plane into A_lo (int16/uint16 (q, n, lda))."""
+    load()
+    fmt = ALTGDMIN_A_BF16X2 if A_lo is not None else ALTGDMIN_A_F32
+    _check(_lib.altgdmin_op_make_a(int(seed), ptr(normal_table), q, n, m, A.shape[2], fmt, ptr(A), ptr(A_lo),
+                                   stream_ptr(stream)))
+
+
+def altgdmin_op_measure(prob: Problem, Xt, Y, stream=None) -> None:
+    """Y[k, :m] = A_k x_k with FP64 accumulation; Xt (q, n) float64 on the device."""
+    load()
+    _check(_lib.altgdmin_op_measure(ctypes.byref(prob), ptr(Xt), ptr(Y), stream_ptr(stream)))
 
 
 def altgdmin_op_au(prob: Problem, U, P, Ginv, flags=None, stream=None) -> None:

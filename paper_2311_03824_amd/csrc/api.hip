@@ -663,6 +663,48 @@ int altgdmin_op_philox_fill(uint64_t seed, const float* normal_table, int32_t q,
   return ALTGDMIN_OK;
 }
 
+int altgdmin_op_make_a(uint64_t seed, const float* normal_table, int32_t q, int32_t n, int32_t m, int64_t lda,
+                       int32_t a_format, void* A, void* A_lo, void* stream) {
+  if (!normal_table || !A || q < 1 || n < 1 || m < 1 || lda < m || lda % 4 != 0)
+    return fail(ALTGDMIN_EINVAL, "bad make_a arguments");
+  if (a_format == ALTGDMIN_A_F32) {
+    if (reinterpret_cast<uintptr_t>(A) % 16 != 0) return fail(ALTGDMIN_EINVAL, "A not 16-byte aligned");
+    HIPCHK(launch_make_a(seed, normal_table, q, n, m, lda, FMT_F32, static_cast<float*>(A), nullptr, nullptr,
+                         static_cast<hipStream_t>(stream)));
+  } else if (a_format == ALTGDMIN_A_BF16X2) {
+    if (!A_lo || reinterpret_cast<uintptr_t>(A) % 8 != 0 || reinterpret_cast<uintptr_t>(A_lo) % 8 != 0)
+      return fail(ALTGDMIN_EINVAL, "BF16X2 needs two 8-byte aligned planes");
+    HIPCHK(launch_make_a(seed, normal_table, q, n, m, lda, FMT_BF16X2, nullptr, static_cast<uint16_t*>(A),
+                         static_cast<uint16_t*>(A_lo), static_cast<hipStream_t>(stream)));
+  } else {
+    return fail(ALTGDMIN_EINVAL, "make_a writes the F32 or BF16X2 format");
+  }
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_measure(const altgdmin_problem* prob, const double* Xt, float* Y, void* stream) {
+  if (!prob || !Xt || !Y) return fail(ALTGDMIN_EINVAL, "bad measure arguments");
+  const altgdmin_problem& p = *prob;
+  if (p.n < 1 || p.q < 1 || p.m < 1 || p.ldy < p.m) return fail(ALTGDMIN_EINVAL, "bad measure sizes");
+  MeasureArgs a;
+  a.n = p.n; a.q = p.q; a.m = p.m;
+  a.A = p.A; a.Alo = p.A_lo; a.lda = p.lda; a.sA = p.a_stride_k;
+  a.Xt = Xt; a.Y = Y; a.ldy = p.ldy; a.seed = p.a_seed; a.table = p.normal_table;
+  int fmt;
+  if (p.a_format == ALTGDMIN_A_PHILOX) {
+    if (!p.normal_table) return fail(ALTGDMIN_EINVAL, "PHILOX needs the normal table");
+    fmt = FMT_PHILOX;
+  } else {
+    if (!p.A || p.lda < p.m || p.lda % 4 != 0 || p.a_stride_k < p.lda * (int64_t)p.n)
+      return fail(ALTGDMIN_EINVAL, "bad A layout");
+    if (p.a_format == ALTGDMIN_A_F32) fmt = FMT_F32;
+    else if (p.a_format == ALTGDMIN_A_BF16X2 && p.A_lo) fmt = FMT_BF16X2;
+    else return fail(ALTGDMIN_EINVAL, "unknown a_format or missing lo plane");
+  }
+  HIPCHK(launch_measure(fmt, a, static_cast<hipStream_t>(stream)));
+  return ALTGDMIN_OK;
+}
+
 // scratch layout of the U-side entry points: Ctl | gpart (KS n r) | Utmp (n r) | T (q r)
 struct OpScratch {
   Ctl* ctl;

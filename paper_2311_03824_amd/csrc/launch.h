@@ -64,4 +64,20 @@ hipError_t launch_fill_basis(float* U, int n, int r, hipStream_t st);
 hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStream_t st);
 hipError_t launch_copy_i(int* dst, const int* src, long long count, hipStream_t st);
 
+// synthetic instances on the device
+struct MeasureArgs {
+  int n, q, m;
+  const void* A;
+  const void* Alo;
+  long long lda, sA;
+  const double* Xt;   // q x n, x_k at Xt[k * n]
+  float* Y;
+  long long ldy;
+  unsigned long long seed;
+  const float* table;
+};
+hipError_t launch_make_a(unsigned long long seed, const float* table, int q, int n, int m, long long lda, int fmt,
+                         float* A32, uint16_t* hi, uint16_t* lo, hipStream_t st);
+hipError_t launch_measure(int fmt, const MeasureArgs& a, hipStream_t st);
+
 }  // namespace altg

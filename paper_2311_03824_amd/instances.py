@@ -274,3 +274,90 @@ def make_workload(name: str, **kw) -> Instance:
     cfg = dict(WORKLOADS[name])
     cfg.update(kw)
     return make_instance(**cfg)
+
+
+# ---------------------------------------------------------------- serving workload
+# A stream of independent problems of mixed sizes (the serving set-up): per
+# request n ~ logU[256, 2048], q ~ logU[128, 1024], r ~ logU[2, 16] rounded,
+# m = round(n U[0.3, 0.5]), rho = round(n U[0.01, 0.05]); the stored form of A
+# alternates between the FP32 plane and the BF16 hi/lo pair.  U*, B*, S* follow
+# the laws of make_instance; A is the canonical hi + lo of the Philox draw with a
+# per-request key, so the device can write it without a host copy.
+
+_TAG_SERVE = 7
+
+
+@dataclasses.dataclass
+class ServeRequest:
+    idx: int
+    n: int
+    q: int
+    m: int
+    r: int
+    rho: int
+    a_format: str          # "f32" or "bf16x2"
+    seed: int              # seed of this request's U*, B*, S* and A key
+    arrival: float = 0.0   # seconds after the start of the run
+
+    @property
+    def lda(self) -> int:
+        return round_up(self.m, 8)
+
+    @property
+    def a_seed(self) -> int:
+        return int(_rng(self.seed, _TAG_A).integers(0, 2**63))
+
+    def a_bytes(self) -> int:
+        """Device bytes of the stored A (4 per element in both forms)."""
+        return 4 * self.q * self.n * self.lda
+
+
+def _log_uniform(rng: np.random.Generator, lo: float, hi: float) -> float:
+    return float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+
+
+def serving_requests(count: int, seed: int, n_range=(256, 2048), q_range=(128, 1024),
+                     r_range=(2, 16)) -> list:
+    """Sizes and seeds of `count` requests (arrival times zero)."""
+    rng = _rng(seed, _TAG_SERVE)
+    out = []
+    for i in range(count):
+        n = int(round(_log_uniform(rng, *n_range)))
+        q = int(round(_log_uniform(rng, *q_range)))
+        r = int(round(_log_uniform(rng, *r_range)))
+        m = int(round(n * rng.uniform(0.3, 0.5)))
+        rho = int(round(n * rng.uniform(0.01, 0.05)))
+        r = max(1, min(r, m, n))
+        out.append(ServeRequest(idx=i, n=n, q=q, m=m, r=r, rho=rho,
+                                a_format="f32" if i % 2 == 0 else "bf16x2",
+                                seed=int(seed) * 1000003 + i))
+    return out
+
+
+def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
+    """Arrival times (seconds) of a Poisson process of the given rate (requests/s)."""
+    gaps = _rng(seed, _TAG_SERVE + 1).exponential(1.0 / rate, count)
+    return np.cumsum(gaps) - gaps[0]
+
+
+def request_truth(req: ServeRequest, s_scale: float = 10.0) -> dict:
+    """U* (n, r), B* (r, q), the support (q, rho) and values, and Xt = X*^T (q, n) FP64."""
+    n, q, r, rho = req.n, req.q, req.r, req.rho
+    G = _rng(req.seed, _TAG_U).standard_normal((n, r))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    U_star = Q * d
+    B_star = _rng(req.seed, _TAG_B).standard_normal((r, q))
+    keys = _rng(req.seed, _TAG_SUPP).random((q, n))
+    supp = np.sort(np.argpartition(keys, rho - 1, axis=1)[:, :rho], axis=1) if rho > 0 else np.zeros((q, 0), np.int64)
+    vals = _rng(req.seed, _TAG_SVAL).standard_normal((q, rho)) * s_scale
+    Xt = (U_star @ B_star).T.copy()
+    if rho > 0:
+        Xt[np.arange(q)[:, None], supp] += vals
+    return dict(U_star=U_star, B_star=B_star, supp=supp, vals=vals, Xt=Xt)
+
+
+def canonical_philox_A(a_seed: int, k_range, n: int, m: int, lda: int, table: np.ndarray):
+    """(hi_bits, lo_bits, canonical FP32) of the Philox draw, each (len(k_range), n, lda)."""
+    return split_bf16(philox_A(a_seed, k_range, n, m, lda, table))

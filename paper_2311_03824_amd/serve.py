@@ -1,0 +1,267 @@
+"""Serving loop: many independent AltGDmin-LR+S problems on one GPU.
+
+Requests arrive over time (a Poisson process); each one brings its sizes and
+the seed of its data.  The scheduler
+
+  * admits waiting requests in arrival order while the sum of their device
+    footprints (stored A, Y, X*, and the exact workspace of
+    altgdmin_workspace_bytes) stays within an HBM budget; a request larger than
+    the whole budget is rejected;
+  * on admission, writes the request's A and y on the device
+    (altgdmin_op_make_a, altgdmin_op_measure) and enqueues the initialisation of
+    Alg. 1 (altgdmin_init);
+  * advances every admitted problem together, `poll_every` GDmin iterations per
+    round, with altgdmin_step_many (the column, gradient and QR kernels of all
+    problems share launches);
+  * after each round reads each problem's relative residual and retires those
+    at or below `tol` or at `max_iters` iterations, recording the latency
+    (completion minus arrival) and the error against X*.
+
+The scheduling logic is host-only and takes an executor object, so it can be
+exercised without a GPU; GpuExecutor is the one that drives the library.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Callable, List, Optional
+
+import numpy as np
+
+from . import instances as inst
+
+
+@dataclasses.dataclass
+class Outcome:
+    idx: int
+    arrival: float
+    admitted: float
+    done: float
+    iterations: int
+    resid: float
+    converged: bool
+    error: float            # ||X - X*||_F / ||X*||_F of the consistent pair
+    rejected: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+@dataclasses.dataclass
+class ServeReport:
+    outcomes: List[Outcome]
+    makespan: float
+    budget_bytes: int
+    peak_bytes: int
+    rounds: int
+
+    def summary(self, err_bound: float = 1e-6) -> dict:
+        done = [o for o in self.outcomes if not o.rejected]
+        lat = np.array([o.latency for o in done]) if done else np.zeros(1)
+        conv = [o for o in done if o.converged]
+        return {
+            "requests": len(self.outcomes),
+            "completed": len(done),
+            "rejected": len(self.outcomes) - len(done),
+            "solves_per_s": len(done) / self.makespan if self.makespan > 0 else 0.0,
+            "p50_latency_s": float(np.percentile(lat, 50)),
+            "p99_latency_s": float(np.percentile(lat, 99)),
+            "converged_fraction": len(conv) / max(1, len(done)),
+            "max_error_converged": max((o.error for o in conv), default=float("nan")),
+            "error_violations": sum(1 for o in conv if not (o.error <= err_bound)),
+            "mean_iterations": float(np.mean([o.iterations for o in done])) if done else 0.0,
+            "makespan_s": self.makespan,
+            "budget_gib": self.budget_bytes / 2**30,
+            "peak_admitted_gib": self.peak_bytes / 2**30,
+            "rounds": self.rounds,
+        }
+
+
+class Scheduler:
+    """FIFO admission by footprint, batched stepping, retire on residual or cap."""
+
+    def __init__(self, executor, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
+                 max_iters: int = 300, clock: Callable[[], float] = time.perf_counter,
+                 sleep: Callable[[float], None] = time.sleep):
+        if poll_every < 1 or max_iters < 1:
+            raise ValueError("poll_every and max_iters must be >= 1")
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.poll_every = poll_every
+        self.tol = tol
+        self.max_iters = max_iters
+        self.clock = clock
+        self.sleep = sleep
+
+    def run(self, requests) -> ServeReport:
+        pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.idx)))
+        waiting = collections.deque()
+        active = []                     # (request, job, footprint, admitted_at)
+        outcomes = []
+        used = peak = 0
+        rounds = 0
+        t0 = self.clock()
+        now = lambda: self.clock() - t0  # noqa: E731
+        while pending or waiting or active:
+            t = now()
+            while pending and pending[0].arrival <= t:
+                waiting.append(pending.popleft())
+            while waiting:
+                req = waiting[0]
+                fp = self.ex.footprint(req)
+                if fp > self.budget:
+                    waiting.popleft()
+                    outcomes.append(Outcome(req.idx, req.arrival, t, t, 0, float("nan"), False,
+                                            float("nan"), rejected=True))
+                    continue
+                if used + fp > self.budget:
+                    break
+                waiting.popleft()
+                job = self.ex.start(req)
+                used += fp
+                peak = max(peak, used)
+                active.append((req, job, fp, now()))
+            if not active:
+                if pending:
+                    self.sleep(max(0.0, pending[0].arrival - now()))
+                continue
+            self.ex.step([a[1] for a in active], self.poll_every)
+            rounds += 1
+            status = self.ex.poll([a[1] for a in active])
+            keep = []
+            for (req, job, fp, adm), st in zip(active, status):
+                iters, resid = st
+                conv = resid <= self.tol
+                if conv or iters >= self.max_iters:
+                    err = self.ex.finish(job)
+                    outcomes.append(Outcome(req.idx, req.arrival, adm, now(), iters, resid, conv, err))
+                    used -= fp
+                else:
+                    keep.append((req, job, fp, adm))
+            active = keep
+        makespan = max((o.done for o in outcomes), default=0.0) - min((o.arrival for o in outcomes), default=0.0)
+        outcomes.sort(key=lambda o: o.idx)
+        return ServeReport(outcomes, makespan, self.budget, peak, rounds)
+
+
+class GpuExecutor:
+    """Runs requests through the HIP library (one stream, torch for device memory)."""
+
+    def __init__(self, tol: float = 1e-7, max_iters: int = 300, device: str = "cuda"):
+        import torch
+        from . import altgdmin as lib
+        if not torch.cuda.is_available():
+            raise RuntimeError("GpuExecutor needs a ROCm GPU")
+        lib.load()
+        self.torch, self.lib, self.device = torch, lib, device
+        self.table = torch.from_numpy(inst.normal_table()).to(device)
+        self.params = lib.default_params(tol_resid=tol, t_max=max_iters)
+        self.group_ws = None
+        self._ws_cache = {}
+
+    # -- sizes
+    def _problem_for_size(self, req):
+        p = self.lib.Problem()
+        p.n, p.q, p.m, p.r, p.rho = req.n, req.q, req.m, req.r, req.rho
+        p.a_format = self.lib.ALTGDMIN_A_F32 if req.a_format == "f32" else self.lib.ALTGDMIN_A_BF16X2
+        # placeholder addresses: only the layout is validated by the size query
+        p.A, p.A_lo, p.Y = 1 << 20, 1 << 21, 1 << 24
+        p.lda, p.a_stride_k, p.ldy = req.lda, req.lda * req.n, req.m
+        return p
+
+    def workspace_bytes(self, req) -> int:
+        key = (req.n, req.q, req.m, req.r, req.rho, req.a_format)
+        if key not in self._ws_cache:
+            self._ws_cache[key] = self.lib.altgdmin_workspace_bytes(self._problem_for_size(req), self.params)
+        return self._ws_cache[key]
+
+    def footprint(self, req) -> int:
+        return req.a_bytes() + 4 * req.q * req.m + 8 * req.q * req.n + self.workspace_bytes(req)
+
+    # -- lifecycle
+    def start(self, req):
+        torch, lib = self.torch, self.lib
+        truth = inst.request_truth(req)
+        Xt = torch.from_numpy(truth["Xt"]).to(self.device, non_blocking=False)
+        shape = (req.q, req.n, req.lda)
+        if req.a_format == "f32":
+            A, A_lo = torch.empty(shape, dtype=torch.float32, device=self.device), None
+        else:
+            A = torch.empty(shape, dtype=torch.int16, device=self.device)
+            A_lo = torch.empty(shape, dtype=torch.int16, device=self.device)
+        Y = torch.empty((req.q, req.m), dtype=torch.float32, device=self.device)
+        lib.altgdmin_op_make_a(req.a_seed, self.table, req.q, req.n, req.m, A, A_lo)
+        prob = lib.make_problem(A, Y, req.r, req.rho, A_lo=A_lo, m=req.m)
+        lib.altgdmin_op_measure(prob, Xt, Y)
+        ws = torch.empty(self.workspace_bytes(req), dtype=torch.uint8, device=self.device)
+        h = lib.altgdmin_init(prob, self.params, ws)
+        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, ws=ws, prob=prob, h=h)
+
+    def step(self, jobs, iters: int) -> None:
+        hs = [j["h"] for j in jobs]
+        need = self.lib.altgdmin_group_bytes(hs)
+        if self.group_ws is None or self.group_ws.numel() < need:
+            self.group_ws = self.torch.empty(max(need, 1 << 20), dtype=self.torch.uint8, device=self.device)
+        self.lib.altgdmin_step_many(hs, iters, self.group_ws)
+
+    def poll(self, jobs):
+        out = []
+        for j in jobs:
+            st = self.lib.altgdmin_status(j["h"])
+            out.append((int(st["iterations"]), float(st["resid"])))
+        return out
+
+    def finish(self, job) -> float:
+        torch, req = self.torch, job["req"]
+        U = torch.empty((req.n, req.r), dtype=torch.float32, device=self.device)
+        Bt = torch.empty((req.q, req.r), dtype=torch.float32, device=self.device)
+        rho = max(req.rho, 1)
+        Si = torch.zeros((req.q, rho), dtype=torch.int32, device=self.device)
+        Sv = torch.zeros((req.q, rho), dtype=torch.float32, device=self.device)
+        self.lib.altgdmin_get(job["h"], U, Bt, Si if req.rho else None, Sv if req.rho else None)
+        # error of the consistent pair in FP64 (measurement harness, not the method)
+        Xt = Bt.double() @ U.double().T
+        if req.rho:
+            Xt.scatter_add_(1, Si.long(), Sv.double())
+        err = float(torch.linalg.norm(Xt - job["Xt"]) / torch.linalg.norm(job["Xt"]))
+        self.lib.altgdmin_destroy(job["h"])
+        job.clear()
+        return err
+
+
+def calibrate_rate(executor, requests, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
+                   max_iters: int = 300) -> float:
+    """Closed-loop throughput (all requests present at t = 0), in solves/s."""
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in requests]
+    rep = Scheduler(executor, budget_bytes, poll_every, tol, max_iters).run(reqs)
+    return rep.summary()["solves_per_s"]
+
+
+def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, load: float = 0.8,
+          rate: Optional[float] = None, poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
+          calibration_count: Optional[int] = None, log=None) -> dict:
+    """Serve `count` seeded requests on the GPU and return the summary.
+
+    Without an explicit `rate`, the arrival rate is `load` times the closed-loop
+    throughput of the first `calibration_count` requests (default: all of them).
+    """
+    ex = GpuExecutor(tol=tol, max_iters=max_iters)
+    reqs = inst.serving_requests(count, seed)
+    budget = int(budget_gib * 2**30)
+    sat = None
+    if rate is None:
+        cal = reqs[: calibration_count or count]
+        sat = calibrate_rate(ex, cal, budget, poll_every, tol, max_iters)
+        rate = load * sat
+        if log:
+            log(f"closed-loop throughput {sat:.2f} solves/s over {len(cal)} requests; arrival rate {rate:.2f}/s")
+    arr = inst.poisson_arrivals(count, rate, seed)
+    for r, a in zip(reqs, arr):
+        r.arrival = float(a)
+    rep = Scheduler(ex, budget, poll_every, tol, max_iters).run(reqs)
+    out = rep.summary()
+    out.update({"arrival_rate_per_s": rate, "closed_loop_solves_per_s": sat, "load": load if sat else None,
+                "tol_resid": tol, "max_iters": max_iters, "poll_every": poll_every, "seed": seed})
+    return out
