@@ -156,14 +156,19 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
 int altgdmin_group_bytes(altgdmin_handle* const* hs, int32_t count, size_t* bytes);
 
 /* Serving: `iters` GDmin iterations of every handle in hs[0..count), with the
- * column work of all problems batched into shared launches (per A format: one
- * A_k U launch and one column-kernel launch over the columns of every problem;
- * then one gradient-reduction launch and one U-update launch with a workgroup
- * per problem).  Each problem keeps its own U/B/S state in its workspace and
- * follows exactly the arithmetic of altgdmin_step.  group_ws (device,
- * 256-byte aligned, >= altgdmin_group_bytes) holds the launch tables; it is
- * filled from the host and the stream is synchronised once per call.  Handles
- * of a BF16X2 problem with a hi-only phase are rejected (EINVAL). */
+ * column work of all problems batched into shared launches (per A format and
+ * kernel instantiation -- ceil(m / 256) for the column kernel, r rounded up to
+ * even for A_k U -- one A_k U launch and one column-kernel launch over the
+ * columns of those problems; then one gradient-reduction launch and one
+ * U-update launch with a workgroup per problem).  Each problem keeps its own
+ * U/B/S state in its workspace and follows exactly the arithmetic of
+ * altgdmin_step.  A problem whose params have tol_resid > 0 is frozen from the
+ * iteration after its residual first reaches tol_resid: its kernels skip it, so
+ * its state, report.iterations and report.resid stay those of the first
+ * iteration that met the tolerance.  group_ws (device, 256-byte aligned,
+ * >= altgdmin_group_bytes) holds the launch tables; it is filled from the host
+ * and the stream is synchronised once per call.  Handles of a BF16X2 problem
+ * with a hi-only phase are rejected (EINVAL). */
 int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters, void* group_ws,
                        size_t group_bytes, void* stream);
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstring>
 #include <string>
+#include <map>
 #include <vector>
 
 #include "altgdmin.h"
@@ -446,17 +447,25 @@ const char* altgdmin_last_error(void) { return g_last_error.c_str(); }
 
 namespace {
 
+// Launch buckets of a group: problems of one A format whose column kernels share
+// an instantiation (NC = ceil(m / 256) for the column kernel, R = r rounded up to
+// even for the A_k U kernel), so no problem runs a wider instantiation than its own.
+struct Bucket {
+  int fmt, inst;
+  std::vector<int2> map;
+  size_t lds = 0, off = 0;
+};
+
 struct GroupPlan {
   std::vector<AUArgs> au;
   std::vector<ColArgs> col;
   std::vector<GradArgs> grad;
   std::vector<QRArgs> qr;
-  std::vector<int2> au_map[4], col_map[4];
+  std::map<int, Bucket> au_b, col_b;   // key fmt * 64 + inst
   std::vector<int4> grad_map;
-  size_t au_lds[4] = {0, 0, 0, 0}, col_lds[4] = {0, 0, 0, 0}, qr_lds = 0;
-  int rmax[4] = {0, 0, 0, 0}, ncmax[4] = {0, 0, 0, 0};
+  size_t qr_lds = 0;
   // byte offsets in the group workspace
-  size_t o_au, o_col, o_grad, o_qr, o_aum[4], o_colm[4], o_gm, total;
+  size_t o_au, o_col, o_grad, o_qr, o_gm, total;
 };
 
 int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
@@ -472,28 +481,39 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
     au.seed = p.a_seed; au.table = p.normal_table;
+    // with tol_resid > 0 a problem whose residual reached it is frozen (every kernel skips it)
+    const int* done = h->par.tol_resid > 0.0 ? &h->ctl->done : nullptr;
+    au.gate = done; au.gate_want = 0;
     g.au.push_back(au);
     ColArgs ca = col_args(h);
     ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
+    ca.gate = done; ca.gate_want = 0;
     g.col.push_back(ca);
     GradArgs ga;
     ga.H = h->H; ga.B = h->Bt; ga.n = p.n; ga.q = p.q; ga.r = p.r; ga.KS = h->KS; ga.gpart = h->gpart;
+    ga.skip = done;
     g.grad.push_back(ga);
     QRArgs qa = qr_args(h, QR_GD);
+    qa.tol = h->par.tol_resid;
+    qa.gate_done = done ? 1 : 0;
     qa.lds = (size_t)p.n * p.r * sizeof(float) <= kQRLdsMax ? 1 : 0;
     if (qa.lds) g.qr_lds = std::max(g.qr_lds, (size_t)p.n * p.r * sizeof(float));
     g.qr.push_back(qa);
     const int f = h->fmt, phx = f == FMT_PHILOX;
+    const int nc = (p.m + 255) / 256, rr = (p.r + 1) / 2 * 2;
+    Bucket& ab = g.au_b[f * 64 + rr];
+    Bucket& cb = g.col_b[f * 64 + nc];
+    ab.fmt = cb.fmt = f;
+    ab.inst = rr;
+    cb.inst = nc;
     for (int k = 0; k < p.q; ++k) {
-      g.au_map[f].push_back(make_int2(i, k));
-      g.col_map[f].push_back(make_int2(i, k));
+      ab.map.push_back(make_int2(i, k));
+      cb.map.push_back(make_int2(i, k));
     }
     for (int jb = 0; jb < (p.n + 63) / 64; ++jb)
       for (int ks = 0; ks < h->KS; ++ks) g.grad_map.push_back(make_int4(i, jb, ks, 0));
-    g.au_lds[f] = std::max(g.au_lds[f], AULayout(p.m, p.r, phx).total);
-    g.col_lds[f] = std::max(g.col_lds[f], ColLayout(p.n, p.m, p.r, p.rho, 1, phx).total);
-    g.rmax[f] = std::max(g.rmax[f], p.r);
-    g.ncmax[f] = std::max(g.ncmax[f], (p.m + 255) / 256);
+    ab.lds = std::max(ab.lds, AULayout(p.m, p.r, phx).total);
+    cb.lds = std::max(cb.lds, ColLayout(p.n, p.m, p.r, p.rho, 1, phx).total);
   }
   size_t o = 0;
   auto take = [&](size_t bytes) { o = (o + kAlign - 1) / kAlign * kAlign; size_t r = o; o += bytes; return r; };
@@ -501,10 +521,8 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
   g.o_col = take(g.col.size() * sizeof(ColArgs));
   g.o_grad = take(g.grad.size() * sizeof(GradArgs));
   g.o_qr = take(g.qr.size() * sizeof(QRArgs));
-  for (int f = 0; f < 4; ++f) {
-    g.o_aum[f] = take(g.au_map[f].size() * sizeof(int2));
-    g.o_colm[f] = take(g.col_map[f].size() * sizeof(int2));
-  }
+  for (auto& kv : g.au_b) kv.second.off = take(kv.second.map.size() * sizeof(int2));
+  for (auto& kv : g.col_b) kv.second.off = take(kv.second.map.size() * sizeof(int2));
   g.o_gm = take(g.grad_map.size() * sizeof(int4));
   g.total = (o + kAlign - 1) / kAlign * kAlign;
   return ALTGDMIN_OK;
@@ -531,18 +549,18 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
   int rc = plan_group(hs, count, g);
   if (rc) return rc;
   if (group_bytes < g.total) return fail(ALTGDMIN_ENOWS, "group workspace too small: need " + std::to_string(g.total));
-  for (int f = 0; f < 4; ++f)
-    if (g.au_lds[f] > kMaxLds || g.col_lds[f] > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
+  for (const auto& kv : g.au_b)
+    if (kv.second.lds > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
+  for (const auto& kv : g.col_b)
+    if (kv.second.lds > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
   std::vector<char> buf(g.total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(buf.data() + off, src, bytes); };
   put(g.o_au, g.au.data(), g.au.size() * sizeof(AUArgs));
   put(g.o_col, g.col.data(), g.col.size() * sizeof(ColArgs));
   put(g.o_grad, g.grad.data(), g.grad.size() * sizeof(GradArgs));
   put(g.o_qr, g.qr.data(), g.qr.size() * sizeof(QRArgs));
-  for (int f = 0; f < 4; ++f) {
-    put(g.o_aum[f], g.au_map[f].data(), g.au_map[f].size() * sizeof(int2));
-    put(g.o_colm[f], g.col_map[f].data(), g.col_map[f].size() * sizeof(int2));
-  }
+  for (const auto& kv : g.au_b) put(kv.second.off, kv.second.map.data(), kv.second.map.size() * sizeof(int2));
+  for (const auto& kv : g.col_b) put(kv.second.off, kv.second.map.data(), kv.second.map.size() * sizeof(int2));
   put(g.o_gm, g.grad_map.data(), g.grad_map.size() * sizeof(int4));
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* dev = static_cast<char*>(group_ws);
@@ -553,14 +571,16 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
   const GradArgs* grad_tab = reinterpret_cast<const GradArgs*>(dev + g.o_grad);
   const QRArgs* qr_tab = reinterpret_cast<const QRArgs*>(dev + g.o_qr);
   for (int it = 0; it < iters; ++it) {
-    for (int f = 0; f < 4; ++f)
-      if (!g.au_map[f].empty())
-        HIPCHK(launch_au_grp(f, g.rmax[f], au_tab, reinterpret_cast<const int2*>(dev + g.o_aum[f]),
-                             (int)g.au_map[f].size(), g.au_lds[f], st));
-    for (int f = 0; f < 4; ++f)
-      if (!g.col_map[f].empty())
-        HIPCHK(launch_col_grp(f, g.ncmax[f], col_tab, reinterpret_cast<const int2*>(dev + g.o_colm[f]),
-                              (int)g.col_map[f].size(), g.col_lds[f], st));
+    for (const auto& kv : g.au_b) {
+      const Bucket& b = kv.second;
+      HIPCHK(launch_au_grp(b.fmt, b.inst, au_tab, reinterpret_cast<const int2*>(dev + b.off), (int)b.map.size(),
+                           b.lds, st));
+    }
+    for (const auto& kv : g.col_b) {
+      const Bucket& b = kv.second;
+      HIPCHK(launch_col_grp(b.fmt, b.inst, col_tab, reinterpret_cast<const int2*>(dev + b.off), (int)b.map.size(),
+                            b.lds, st));
+    }
     HIPCHK(launch_grad_grp(grad_tab, reinterpret_cast<const int4*>(dev + g.o_gm), (int)g.grad_map.size(), st));
     HIPCHK(launch_qr_grp(qr_tab, count, g.qr_lds, st));
   }

@@ -28,7 +28,8 @@ struct Ctl {
   int err;           // OR of column error flags
   int phase;         // BF16X2 solves: 0 while the hi plane alone is read, 1 once hi + lo are read
   int refine_t;      // first iteration with phase 1 (-1 before)
-  int pad[5];
+  int done;          // batched stepping: the residual reached tol_resid; the problem is not advanced further
+  int pad[4];
   double prev_resid; // residual of the previous iteration (stall test of the hi-only phase)
 };
 

@@ -475,6 +475,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const ColArgs a = tab[mp.x];
+  if (a.gate && *a.gate != a.gate_want) return;
   col_body<FMT, NC>(a, mp.y, smem);
 }
 
@@ -680,6 +681,7 @@ __global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const in
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
+  if (a.gate && *a.gate != a.gate_want) return;
   au_body<FMT, R>(a, mp.y, smem);
 }
 

@@ -74,6 +74,7 @@ __global__ __launch_bounds__(kGradWaves * 64) void k_grad_grp(const GradArgs* ta
   __shared__ float red[kGradWaves / 2][64][kRMax + 1];
   const int4 mp = map[blockIdx.x];
   const GradArgs a = tab[mp.x];
+  if (a.skip && *a.skip) return;
   grad_body(a.H, a.B, a.n, a.q, a.r, a.KS, a.gpart, mp.y, mp.z, red);
 }
 
@@ -235,6 +236,7 @@ __device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
   const int tid = threadIdx.x;
   const int n = a.n, r = a.r, nr = n * r;
   if (a.mode == QR_POWER && a.ctl && a.ctl->conv) return;
+  if (a.mode == QR_GD && a.gate_done && a.ctl && a.ctl->done) return;
   float* X = a.lds ? reinterpret_cast<float*>(dsm) : a.Utmp;
 
   if (a.mode != QR_ORTH) {
@@ -319,6 +321,7 @@ __device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
         a.ctl->refine_t = t + 1;
       }
       a.ctl->prev_resid = resid;
+      if (a.gate_done && a.tol > 0.0 && resid <= a.tol) a.ctl->done = 1;
     }
   }
 }
@@ -366,6 +369,7 @@ __global__ void k_reset_ctl(Ctl* ctl, int full) {
     ctl->t = 0;
     ctl->resid = 0.0;
     ctl->prev_resid = 0.0;
+    ctl->done = 0;
     if (full) {
       ctl->power_sd = 0.0;
       ctl->ynorm2 = 0.0;

@@ -24,6 +24,8 @@ struct QRArgs {
   int lds;                 // set by launch_qr: the n x r block is staged in LDS
   int hi_max;              // BF16X2 hi-only budget (iterations)
   double stall;            // BF16X2 stall ratio
+  double tol;              // GD with gate_done: set ctl->done once resid <= tol
+  int gate_done;           // GD: skip the update when ctl->done is set (batched stepping)
 };
 
 constexpr size_t kQRLdsMax = 48 * 1024;   // dynamic LDS for the n x r block of k_qr
@@ -34,6 +36,7 @@ struct GradArgs {
   const float* B;
   int n, q, r, KS;
   float* gpart;
+  const int* skip;   // if non-null and *skip != 0, the workgroup does nothing
 };
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);

@@ -23,7 +23,9 @@ exercised without a GPU; GpuExecutor is the one that drives the library.
 from __future__ import annotations
 
 import collections
+import concurrent.futures
 import dataclasses
+import itertools
 import time
 from typing import Callable, List, Optional
 
@@ -56,6 +58,7 @@ class ServeReport:
     budget_bytes: int
     peak_bytes: int
     rounds: int
+    host_seconds: dict = dataclasses.field(default_factory=dict)
 
     def summary(self, err_bound: float = 1e-6) -> dict:
         done = [o for o in self.outcomes if not o.rejected]
@@ -76,6 +79,7 @@ class ServeReport:
             "budget_gib": self.budget_bytes / 2**30,
             "peak_admitted_gib": self.peak_bytes / 2**30,
             "rounds": self.rounds,
+            "host_seconds": {k: round(v, 4) for k, v in self.host_seconds.items()},
         }
 
 
@@ -84,7 +88,7 @@ class Scheduler:
 
     def __init__(self, executor, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
                  max_iters: int = 300, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep):
+                 sleep: Callable[[float], None] = time.sleep, prefetch: int = 16):
         if poll_every < 1 or max_iters < 1:
             raise ValueError("poll_every and max_iters must be >= 1")
         self.ex = executor
@@ -94,6 +98,7 @@ class Scheduler:
         self.max_iters = max_iters
         self.clock = clock
         self.sleep = sleep
+        self.prefetch = prefetch
 
     def run(self, requests) -> ServeReport:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.idx)))
@@ -102,12 +107,24 @@ class Scheduler:
         outcomes = []
         used = peak = 0
         rounds = 0
+        spent = collections.Counter()     # wall time inside each executor call
+        prepare = getattr(self.ex, "prepare", None)
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
+
+        def timed(name, fn, *args):
+            a = self.clock()
+            out = fn(*args)
+            spent[name] += self.clock() - a
+            return out
+
         while pending or waiting or active:
             t = now()
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
+            if prepare is not None:          # host-side payloads of the next few, made in the background
+                for req in itertools.islice(waiting, self.prefetch):
+                    prepare(req)
             while waiting:
                 req = waiting[0]
                 fp = self.ex.footprint(req)
@@ -119,7 +136,7 @@ class Scheduler:
                 if used + fp > self.budget:
                     break
                 waiting.popleft()
-                job = self.ex.start(req)
+                job = timed("start", self.ex.start, req)
                 used += fp
                 peak = max(peak, used)
                 active.append((req, job, fp, now()))
@@ -127,15 +144,15 @@ class Scheduler:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
-            self.ex.step([a[1] for a in active], self.poll_every)
+            timed("step", self.ex.step, [a[1] for a in active], self.poll_every)
             rounds += 1
-            status = self.ex.poll([a[1] for a in active])
+            status = timed("poll", self.ex.poll, [a[1] for a in active])
             keep = []
             for (req, job, fp, adm), st in zip(active, status):
                 iters, resid = st
                 conv = resid <= self.tol
                 if conv or iters >= self.max_iters:
-                    err = self.ex.finish(job)
+                    err = timed("finish", self.ex.finish, job)
                     outcomes.append(Outcome(req.idx, req.arrival, adm, now(), iters, resid, conv, err))
                     used -= fp
                 else:
@@ -143,7 +160,7 @@ class Scheduler:
             active = keep
         makespan = max((o.done for o in outcomes), default=0.0) - min((o.arrival for o in outcomes), default=0.0)
         outcomes.sort(key=lambda o: o.idx)
-        return ServeReport(outcomes, makespan, self.budget, peak, rounds)
+        return ServeReport(outcomes, makespan, self.budget, peak, rounds, dict(spent))
 
 
 class GpuExecutor:
@@ -160,6 +177,17 @@ class GpuExecutor:
         self.params = lib.default_params(tol_resid=tol, t_max=max_iters)
         self.group_ws = None
         self._ws_cache = {}
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=4)
+        self._truth = {}
+
+    def _make_truth(self, req):
+        Xt = self.torch.from_numpy(inst.request_truth(req)["Xt"])
+        return Xt.pin_memory()
+
+    def prepare(self, req) -> None:
+        """Start drawing X* of a request on a host thread (pinned for the upload)."""
+        if req.idx not in self._truth:
+            self._truth[req.idx] = self._pool.submit(self._make_truth, req)
 
     # -- sizes
     def _problem_for_size(self, req):
@@ -183,8 +211,9 @@ class GpuExecutor:
     # -- lifecycle
     def start(self, req):
         torch, lib = self.torch, self.lib
-        truth = inst.request_truth(req)
-        Xt = torch.from_numpy(truth["Xt"]).to(self.device, non_blocking=False)
+        fut = self._truth.pop(req.idx, None)
+        Xt_host = fut.result() if fut is not None else self._make_truth(req)
+        Xt = Xt_host.to(self.device, non_blocking=True)
         shape = (req.q, req.n, req.lda)
         if req.a_format == "f32":
             A, A_lo = torch.empty(shape, dtype=torch.float32, device=self.device), None
@@ -197,7 +226,7 @@ class GpuExecutor:
         lib.altgdmin_op_measure(prob, Xt, Y)
         ws = torch.empty(self.workspace_bytes(req), dtype=torch.uint8, device=self.device)
         h = lib.altgdmin_init(prob, self.params, ws)
-        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, ws=ws, prob=prob, h=h)
+        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, Xt_host=Xt_host, ws=ws, prob=prob, h=h)
 
     def step(self, jobs, iters: int) -> None:
         hs = [j["h"] for j in jobs]

@@ -495,3 +495,41 @@ def test_step_many_equals_solo(lib, torch):
     for a, b in zip(solo, mixed):
         for key in ("U", "Bt", "S_idx", "S_val"):
             assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.gpu
+def test_step_many_freezes_at_tolerance(lib, torch):
+    """With tol_resid > 0, batched stepping stops advancing a problem after the first
+    iteration whose residual meets the tolerance; its state equals a solo run of
+    exactly that many iterations, while a problem that has not converged goes on."""
+    a = I.make_instance(n=300, q=40, m=120, r=2, rho=5, seed=11)
+    b = I.make_instance(n=400, q=50, m=150, r=3, rho=6, seed=12)
+    tol = 1e-4
+    # solo reference: the residual log tells where the tolerance is first met
+    s = lib.Solver(a.At, a.Y32, a.m, a.r, a.rho, lib.default_params(t_max=80))
+    s.init().step(80)
+    log = lib.altgdmin_residual_log(s.h, 80)
+    s.close()
+    t_conv = int(np.argmax(log <= tol)) + 1
+    assert log[t_conv - 1] <= tol and np.all(log[: t_conv - 1] > tol) and t_conv < 60
+    ref = lib.Solver(a.At, a.Y32, a.m, a.r, a.rho, lib.default_params(t_max=80))
+    ref.init().step(t_conv)
+    want = ref.get()
+    ref.close()
+
+    group = [lib.Solver(a.At, a.Y32, a.m, a.r, a.rho, lib.default_params(t_max=80, tol_resid=tol)),
+             lib.Solver(b.At, b.Y32, b.m, b.r, b.rho, lib.default_params(t_max=80, tol_resid=1e-30))]
+    for g in group:
+        g.init()
+    hs = [g.h for g in group]
+    gws = torch.empty(lib.altgdmin_group_bytes(hs) + 256, dtype=torch.uint8, device="cuda")
+    for _ in range(6):
+        lib.altgdmin_step_many(hs, 10, gws)
+    st = group[0].status()
+    assert st["iterations"] == t_conv and st["resid"] == log[t_conv - 1]
+    got = group[0].get()
+    for key in ("U", "Bt", "S_idx", "S_val"):
+        assert np.array_equal(want[key], got[key]), key
+    assert group[1].status()["iterations"] == 60
+    for g in group:
+        g.close()
