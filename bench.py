@@ -8,8 +8,11 @@ T = 200 GDmin iterations (replays of the captured iteration graph).
 ``value`` is GDmin iterations per second over whole solves, init included.
 
 Also printed: the per-kernel average durations (HIP events on the launch
-stream), the roofline of the dominant kernel (the column kernel), and the FP64
-CPU oracle timed on a bounded sample of the same workload.
+stream), the roofline of the dominant kernel (the column kernel), the A forms
+(BF16 hi/lo planes, Philox regeneration) at equal error, a mixed-size serving
+run (Poisson arrivals at 0.8 x the closed-loop rate; solves/s and latency
+percentiles), and the FP64 CPU oracle timed on a bounded sample of the same
+workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--form fp32|bf16x2]
 """
@@ -197,6 +200,9 @@ def main() -> int:
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true", help="skip the time-to-equal-error comparison of the A forms")
     ap.add_argument("--target-resid", type=float, default=1e-6)
+    ap.add_argument("--serve-requests", type=int, default=128,
+                    help="requests of the mixed-size serving run (0: skip); arrival rate = 0.8 x closed-loop rate")
+    ap.add_argument("--serve-budget-gib", type=float, default=32.0, help="HBM admission budget of the serving run")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run torch's copy kernel on a 1.6 GB FP32 buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -317,6 +323,11 @@ def main() -> int:
         log("forms: " + json.dumps(result["forms_time_to_target"]))
         result["philox_form"] = philox_form(lib, torch, np, cfg, args.target_resid)
         log("philox: " + json.dumps(result["philox_form"]))
+    if args.serve_requests > 0:
+        from paper_2311_03824_amd import serve
+        log(f"serving {args.serve_requests} mixed-size requests (budget {args.serve_budget_gib} GiB)")
+        result["serving"] = serve.serve(count=args.serve_requests, budget_gib=args.serve_budget_gib, log=log)
+        log("serving: " + json.dumps(result["serving"]))
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on {args.cpu_sample_q} columns")
         result["cpu_baseline"] = cpu_baseline(cfg, args.cpu_sample_q, 2)
