@@ -361,3 +361,70 @@ def request_truth(req: ServeRequest, s_scale: float = 10.0) -> dict:
 def canonical_philox_A(a_seed: int, k_range, n: int, m: int, lda: int, table: np.ndarray):
     """(hi_bits, lo_bits, canonical FP32) of the Philox draw, each (len(k_range), n, lda)."""
     return split_bf16(philox_A(a_seed, k_range, n, m, lda, table))
+
+
+# ---------------------------------------------------------------- partial Fourier form
+# Frames of N1 x N2 complex pixels (x_k flattened row-major, n = N1 N2); A_k keeps
+# m distinct rows of the unitary 2D DFT, the frequency indices of frame k drawn
+# uniformly without replacement and stored ascending (index u = u1 N2 + u2).
+# U* is the Q factor (real positive diagonal R) of an n x r complex Gaussian; B*
+# is i.i.d. CN(0, 1); S* holds rho entries per column at uniformly drawn rows with
+# CN(0, s_var) values.  y_k = rows mask_k of the unitary 2D DFT of x*_k.
+
+_TAG_MASK = 9
+
+
+@dataclasses.dataclass
+class FourierInstance:
+    N1: int
+    N2: int
+    q: int
+    m: int
+    r: int
+    rho: int
+    seed: int
+    mask: np.ndarray      # (q, m) int64, ascending frequency indices of each frame
+    Y: np.ndarray         # (q, m) complex128
+    U_star: np.ndarray    # (n, r) complex128, orthonormal columns
+    B_star: np.ndarray    # (r, q) complex128
+    S_star: np.ndarray    # (n, q) complex128
+    supp: np.ndarray      # (q, rho) int64
+
+    @property
+    def n(self) -> int:
+        return self.N1 * self.N2
+
+    @property
+    def X_star(self) -> np.ndarray:
+        return self.U_star @ self.B_star + self.S_star
+
+
+def _complex_normal(rng: np.random.Generator, shape, var: float) -> np.ndarray:
+    s = np.sqrt(var / 2.0)
+    return rng.standard_normal(shape) * s + 1j * (rng.standard_normal(shape) * s)
+
+
+def make_fourier_instance(N1: int, N2: int, q: int, m: int, r: int, rho: int, seed: int,
+                          s_var: float = 25.0, s_zero: bool = False) -> FourierInstance:
+    n = N1 * N2
+    if not (1 <= r <= min(m, n)) or not (0 <= rho <= n) or not (1 <= m <= n) or q < 1:
+        raise ValueError("invalid sizes")
+    G = _complex_normal(_rng(seed, _TAG_U), (n, r), 1.0)
+    Q, R = np.linalg.qr(G)
+    d = np.diag(R)
+    ph = np.where(np.abs(d) > 0, d / np.where(np.abs(d) > 0, np.abs(d), 1.0), 1.0)
+    U_star = Q * ph
+    B_star = _complex_normal(_rng(seed, _TAG_B), (r, q), 1.0)
+    keys = _rng(seed, _TAG_SUPP).random((q, n))
+    supp = np.sort(np.argsort(keys, axis=1, kind="stable")[:, :rho], axis=1)
+    vals = _complex_normal(_rng(seed, _TAG_SVAL), (q, rho), s_var)
+    S_star = np.zeros((n, q), np.complex128)
+    if not s_zero and rho > 0:
+        S_star[supp, np.arange(q)[:, None]] = vals
+    mkeys = _rng(seed, _TAG_MASK).random((q, n))
+    mask = np.sort(np.argsort(mkeys, axis=1, kind="stable")[:, :m], axis=1)
+    X = (U_star @ B_star + S_star).T.reshape(q, N1, N2)
+    F = np.fft.fft2(X, norm="ortho").reshape(q, n)
+    Y = F[np.arange(q)[:, None], mask]
+    return FourierInstance(N1=N1, N2=N2, q=q, m=m, r=r, rho=rho, seed=seed, mask=mask, Y=Y,
+                           U_star=U_star, B_star=B_star, S_star=S_star, supp=supp)
