@@ -25,6 +25,16 @@
  *  - U: n x r row-major (U[j*r + c]); B is returned transposed, Bt q x r
  *    row-major (Bt[k*r + c] = b_k[c]); S as q x rho arrays of row indices
  *    (int32, ascending within a column) and values (float).
+ *  - Partial Fourier form (a_format ALTGDMIN_A_PFOURIER): A_k x = (F x)[mask_k]
+ *    with F the unitary 2D DFT, (F x)[u1, u2] = (n1 n2)^(-1/2) sum x[j1, j2]
+ *    exp(-2 pi i (u1 j1 / n1 + u2 j2 / n2)); A is never stored (A, A_lo, lda
+ *    and a_stride_k are ignored).  Y, U, Bt and S_val hold complex64 values
+ *    (interleaved re, im float pairs; ldy counts complex elements), so every
+ *    float* output of such a problem receives twice the float count of the
+ *    real form.  Limits: n1 = n2 = 96, m <= 2048, r <= 8, rho <= 256.  Every
+ *    transpose of Alg. 1 and Alg. 2 becomes a conjugate transpose and
+ *    HardThreshold ranks by the modulus, computed as the FP32 key
+ *    fl(fl(re*re) + fl(im*im)) (lower index first on equal keys).
  *  - Return codes: ALTGDMIN_OK (0); negative values are errors; the positive
  *    ALTGDMIN_ENOTCONV is a warning.  altgdmin_last_error() gives the text of
  *    the last error of the calling thread.  Faults inside kernels surface at
@@ -53,7 +63,8 @@ enum {
 enum {
   ALTGDMIN_A_F32 = 0,        /* FP32 plane */
   ALTGDMIN_A_BF16X2 = 1,     /* BF16 hi plane + BF16 lo plane, A = hi + lo */
-  ALTGDMIN_A_PHILOX = 2      /* regenerated in the kernels from a counter; never stored (see altgdmin_op_philox_fill) */
+  ALTGDMIN_A_PHILOX = 2,     /* regenerated in the kernels from a counter; never stored (see altgdmin_op_philox_fill) */
+  ALTGDMIN_A_PFOURIER = 3    /* partial Fourier: rows fourier_mask[k] of the unitary 2D DFT of n1 x n2 complex frames */
 };
 
 /* Entries of the normal table of the Philox form: |z| = -Phi^{-1}(v) at
@@ -70,9 +81,12 @@ typedef struct altgdmin_problem {
   int64_t a_stride_k;        /* stride between A_k and A_{k+1} in elements, >= lda*n */
   const float* Y;            /* q x ldy */
   int64_t ldy;
-  const float* U_start;      /* optional n x r start block of the subspace iteration (NULL: a fixed disjoint-support basis) */
+  const float* U_start;      /* optional n x r start block of the subspace iteration (NULL: a fixed disjoint-support
+                                basis); complex64 pairs for PFOURIER */
   uint64_t a_seed;           /* PHILOX: 64-bit key of A */
   const float* normal_table; /* PHILOX: device array of ALTGDMIN_NORMAL_TABLE_SIZE FP32 */
+  int32_t n1, n2;            /* PFOURIER: frame size, n = n1 * n2 (x_k flattened row-major); built for 96 x 96 */
+  const int32_t* fourier_mask; /* PFOURIER: q x m frequency indices u = u1 * n2 + u2, ascending per frame */
 } altgdmin_problem;
 
 /* Parameters of Alg. 1 / Sec. 2.6. */

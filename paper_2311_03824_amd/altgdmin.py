@@ -24,6 +24,7 @@ ALTGDMIN_ENOTCONV = 1
 ALTGDMIN_A_F32 = 0
 ALTGDMIN_A_BF16X2 = 1
 ALTGDMIN_A_PHILOX = 2
+ALTGDMIN_A_PFOURIER = 3
 FLAG_EAGER = 1      # params.flags bit 0: launch the iteration's kernels without a HIP graph
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
@@ -33,7 +34,8 @@ class Problem(ctypes.Structure):
     _fields_ = [("n", c_i32), ("q", c_i32), ("m", c_i32), ("r", c_i32), ("rho", c_i32),
                 ("a_format", c_i32), ("A", c_vp), ("A_lo", c_vp), ("lda", c_i64),
                 ("a_stride_k", c_i64), ("Y", c_vp), ("ldy", c_i64), ("U_start", c_vp),
-                ("a_seed", ctypes.c_uint64), ("normal_table", c_vp)]
+                ("a_seed", ctypes.c_uint64), ("normal_table", c_vp), ("n1", c_i32), ("n2", c_i32),
+                ("fourier_mask", c_vp)]
 
 
 class Params(ctypes.Structure):
@@ -149,6 +151,20 @@ def default_params(**kw) -> Params:
     _lib.altgdmin_default_params(ctypes.byref(p))
     for k, v in kw.items():
         setattr(p, k, v)
+    return p
+
+
+def make_fourier_problem(mask, Y, n1: int, n2: int, r: int, rho: int, U_start=None) -> Problem:
+    """Partial Fourier form: mask (q, m) int32 and Y (q, m) complex64 device tensors
+    (Y may also be a (q, m, 2) float32 view); frames of n1 x n2."""
+    p = Problem()
+    q, m = mask.shape[0], mask.shape[1]
+    p.a_format = ALTGDMIN_A_PFOURIER
+    p.n, p.q, p.m, p.r, p.rho = n1 * n2, q, m, r, rho
+    p.n1, p.n2 = n1, n2
+    p.fourier_mask = ptr(mask)
+    p.Y, p.ldy = ptr(Y), Y.shape[1]
+    p.U_start = ptr(U_start)
     return p
 
 
@@ -413,6 +429,64 @@ class Solver:
 
     def residual_log(self) -> np.ndarray:
         return altgdmin_residual_log(self.h, max(1, self.par.t_max))
+
+    def close(self):
+        if self.h is not None:
+            altgdmin_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class FourierSolver:
+    """Owns the device copies of one partial Fourier problem (complex64) and its workspace."""
+
+    def __init__(self, mask: np.ndarray, Y: np.ndarray, n1: int, n2: int, r: int, rho: int,
+                 params: Optional[Params] = None, U_start: Optional[np.ndarray] = None, device="cuda"):
+        torch = _torch()
+        load()
+        self.mask = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.int32)).to(device)
+        self.Y = torch.from_numpy(np.ascontiguousarray(Y, dtype=np.complex64)).to(device)
+        self.U_start = (None if U_start is None else
+                        torch.from_numpy(np.ascontiguousarray(U_start, dtype=np.complex64)).to(device))
+        self.q, self.m = mask.shape
+        self.n, self.r, self.rho = n1 * n2, r, rho
+        self.prob = make_fourier_problem(self.mask, self.Y, n1, n2, r, rho, self.U_start)
+        self.par = params if params is not None else default_params()
+        self.ws = torch.empty(altgdmin_workspace_bytes(self.prob, self.par), dtype=torch.uint8, device=device)
+        self.h = None
+
+    def init(self, stream=None):
+        if self.h is not None:
+            altgdmin_destroy(self.h)
+        self.h = altgdmin_init(self.prob, self.par, self.ws, stream)
+        return self
+
+    def step(self, iters: int, stream=None):
+        altgdmin_step(self.h, iters, stream)
+        return self
+
+    def get(self, stream=None):
+        torch = _torch()
+        U = torch.empty((self.n, self.r), dtype=torch.complex64, device="cuda")
+        Un = torch.empty_like(U)
+        Bt = torch.empty((self.q, self.r), dtype=torch.complex64, device="cuda")
+        Si = torch.zeros((self.q, max(self.rho, 1)), dtype=torch.int32, device="cuda")
+        Sv = torch.zeros((self.q, max(self.rho, 1)), dtype=torch.complex64, device="cuda")
+        altgdmin_get(self.h, U, Bt, Si if self.rho else None, Sv if self.rho else None, Un, stream)
+        torch.cuda.synchronize()
+        return dict(U=U.cpu().numpy(), U_next=Un.cpu().numpy(), Bt=Bt.cpu().numpy(),
+                    S_idx=Si.cpu().numpy()[:, : self.rho], S_val=Sv.cpu().numpy()[:, : self.rho])
+
+    def status(self, stream=None) -> dict:
+        return altgdmin_status(self.h, stream)
+
+    def profile_iteration(self, iters: int) -> dict:
+        return altgdmin_profile_iteration(self.h, iters)
 
     def close(self):
         if self.h is not None:

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libaltgdmin.so")
 ARCH = os.environ.get("ALTGDMIN_ARCH", "gfx950")
-SOURCES = ["k_column.hip", "k_small.hip", "k_gen.hip", "api.hip"]
+SOURCES = ["k_column.hip", "k_small.hip", "k_gen.hip", "k_fourier.hip", "api.hip"]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -50,7 +50,12 @@ struct Carver {
 int grad_splits(int q) { return q >= 512 ? 4 : (q >= 64 ? 2 : 1); }
 
 int fmt_of(const altgdmin_problem* p) {
-  return p->a_format == ALTGDMIN_A_BF16X2 ? FMT_BF16X2 : (p->a_format == ALTGDMIN_A_PHILOX ? FMT_PHILOX : FMT_F32);
+  switch (p->a_format) {
+    case ALTGDMIN_A_BF16X2: return FMT_BF16X2;
+    case ALTGDMIN_A_PHILOX: return FMT_PHILOX;
+    case ALTGDMIN_A_PFOURIER: return FMT_PFOURIER;
+    default: return FMT_F32;
+  }
 }
 
 }  // namespace
@@ -76,6 +81,10 @@ struct altgdmin_handle {
   Ctl* ctl;
   double* rlog;
   int rlog_len;
+  // partial Fourier form: complex buffers (float pairs); Tval, Bt, H, gpart (the
+  // gradient or L_0 L_0^H U), U, Uprev, Utmp and Tpow hold complex values there
+  float* FU = nullptr;     // n x r: the 2D DFT of U's columns
+  float* tw = nullptr;     // 96 twiddles
   bool hi_phase = false;   // BF16X2 with a hi-only phase
   bool have_graph = false;
   hipGraph_t graph = nullptr;
@@ -85,8 +94,36 @@ struct altgdmin_handle {
 
 namespace {
 
+// Workspace of the partial Fourier form (complex values as float pairs).
+size_t carve_fourier(altgdmin_handle* h, void* base) {
+  const altgdmin_problem& p = h->prob;
+  const size_t n = p.n, q = p.q, r = p.r, rho = p.rho;
+  Carver c(base);
+  h->ctl = c.take<Ctl>(1);
+  h->P = nullptr;
+  h->Ginv = nullptr;
+  h->Tidx = c.take<int>(q * rho);
+  h->Tval = c.take<float>(2 * q * rho);
+  h->Bt = c.take<float>(2 * q * r);
+  h->H = c.take<float>(2 * q * n);
+  h->colrr = c.take<double>(q);
+  h->colflags = c.take<int>(q);
+  h->KS = 1;
+  h->gpart = c.take<float>(2 * n * r);
+  h->FU = c.take<float>(2 * n * r);
+  h->U = c.take<float>(2 * n * r);
+  h->Uprev = c.take<float>(2 * n * r);
+  h->Utmp = c.take<float>(2 * n * r);
+  h->Tpow = c.take<float>(2 * q * r);
+  h->tw = c.take<float>(2 * kFN);
+  h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
+  h->rlog = c.take<double>(h->rlog_len);
+  return (c.off + kAlign - 1) / kAlign * kAlign;
+}
+
 // Lays the workspace out; with base == nullptr it only measures.
 size_t carve(altgdmin_handle* h, void* base) {
+  if (h->prob.a_format == ALTGDMIN_A_PFOURIER) return carve_fourier(h, base);
   const altgdmin_problem& p = h->prob;
   const size_t n = p.n, q = p.q, m = p.m, r = p.r, rho = p.rho;
   Carver c(base);
@@ -114,8 +151,23 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (!p || !par) return fail(ALTGDMIN_EINVAL, "null problem or params");
   if (p->n < 1 || p->q < 1 || p->m < 1) return fail(ALTGDMIN_EINVAL, "n, q, m must be >= 1");
   if (p->r < 1 || p->r > p->m || p->r > p->n) return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n)");
-  if (p->r > kRMax) return fail(ALTGDMIN_ENOTBUILT, "r > 16 has no instantiation");
   if (p->rho < 0 || p->rho > p->n) return fail(ALTGDMIN_EINVAL, "need 0 <= rho <= n");
+  if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
+      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0)
+    return fail(ALTGDMIN_EINVAL, "invalid params");
+  if (p->a_format == ALTGDMIN_A_PFOURIER) {
+    if (p->n1 < 1 || p->n2 < 1 || (int64_t)p->n1 * p->n2 != p->n) return fail(ALTGDMIN_EINVAL, "need n = n1 * n2");
+    if (p->n1 != kFN || p->n2 != kFN) return fail(ALTGDMIN_ENOTBUILT, "the Fourier kernels are built for 96 x 96 frames");
+    if (p->m > p->n) return fail(ALTGDMIN_EINVAL, "need m <= n");
+    if (p->m > 2 * kFThreads) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: m > 2048 has no instantiation");
+    if (p->r > kFRMax) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: r > 8 has no instantiation");
+    if (p->rho > kFRhoMax) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: rho > 256 has no instantiation");
+    if (!p->fourier_mask || !p->Y) return fail(ALTGDMIN_EINVAL, "Fourier form needs the mask and Y");
+    if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
+    if (reinterpret_cast<uintptr_t>(p->Y) % 8 != 0) return fail(ALTGDMIN_EINVAL, "Y must be 8-byte aligned");
+    return ALTGDMIN_OK;
+  }
+  if (p->r > kRMax) return fail(ALTGDMIN_ENOTBUILT, "r > 16 has no instantiation");
   if (p->m > 256 * kNCMax) return fail(ALTGDMIN_ENOTBUILT, "m > 1024 has no instantiation");
   if (p->a_format != ALTGDMIN_A_F32 && p->a_format != ALTGDMIN_A_BF16X2 && p->a_format != ALTGDMIN_A_PHILOX)
     return fail(ALTGDMIN_EINVAL, "unknown a_format");
@@ -138,9 +190,6 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   const int phx = p->a_format == ALTGDMIN_A_PHILOX;
   if (col_lds_bytes(p->n, p->m, p->r, p->rho, 1, phx) > kMaxLds || au_lds_bytes(p->m, p->r, phx) > kMaxLds)
     return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 64 KiB of LDS per column workgroup");
-  if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
-      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0)
-    return fail(ALTGDMIN_EINVAL, "invalid params");
   return ALTGDMIN_OK;
 }
 
@@ -170,8 +219,65 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
   return a;
 }
 
+FColArgs fcol_args(const altgdmin_handle* h, int mode) {
+  const altgdmin_problem& p = h->prob;
+  FColArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = p.n; a.q = p.q; a.m = p.m; a.r = p.r; a.rho = p.rho;
+  a.mode = mode;
+  a.tau = mode == FCOL_GD ? h->par.tau : h->par.tau0;
+  a.mask = p.fourier_mask;
+  a.Y = static_cast<const float2*>(static_cast<const void*>(p.Y));
+  a.ldy = p.ldy;
+  a.FU = reinterpret_cast<const float2*>(h->FU);
+  a.tw = reinterpret_cast<const float2*>(h->tw);
+  a.Sidx = h->Tidx;
+  a.Sval = reinterpret_cast<float2*>(h->Tval);
+  a.Bt = reinterpret_cast<float2*>(h->Bt);
+  a.H = reinterpret_cast<float2*>(h->H);
+  a.colrr = h->colrr;
+  a.flags = h->colflags;
+  return a;
+}
+
+FQRArgs fqr_args(const altgdmin_handle* h, int mode) {
+  FQRArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.n = h->prob.n; a.r = h->prob.r; a.q = h->prob.q; a.mode = mode;
+  a.G = reinterpret_cast<const float2*>(h->gpart);
+  a.U = reinterpret_cast<float2*>(h->U);
+  a.Uprev = reinterpret_cast<float2*>(h->Uprev);
+  a.Utmp = reinterpret_cast<float2*>(h->Utmp);
+  a.ctl = h->ctl;
+  a.eta_c = h->par.eta_c;
+  a.power_tol = h->par.power_tol;
+  a.colrr = h->colrr;
+  a.colflags = h->colflags;
+  a.rlog = h->rlog;
+  a.rlog_len = h->rlog_len;
+  return a;
+}
+
+#define F2(p) reinterpret_cast<float2*>(p)
+#define CF2(p) reinterpret_cast<const float2*>(p)
+
+// The four launches of one GDmin iteration of the partial Fourier form.
+hipError_t fourier_launch(altgdmin_handle* h, int which, hipStream_t st) {
+  const altgdmin_problem& p = h->prob;
+  switch (which) {
+    case 0: return launch_fu(CF2(h->U), p.r, CF2(h->tw), F2(h->FU), st);
+    case 1: return launch_fcol(fcol_args(h, FCOL_GD), st);
+    case 2: return launch_fgrad(CF2(h->H), CF2(h->Bt), p.n, p.q, p.r, F2(h->gpart), nullptr, st);
+    default: return launch_fqr(fqr_args(h, QR_GD), st);
+  }
+}
+
 // One GDmin iteration of Alg. 1 on stream st.
 int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
+  if (h->fmt == FMT_PFOURIER) {
+    for (int w = 0; w < 4; ++w) HIPCHK(fourier_launch(h, w, st));
+    return ALTGDMIN_OK;
+  }
   const altgdmin_problem& p = h->prob;
   AUArgs au;
   au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
@@ -252,6 +358,26 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   if ((e = launch_reset_ctl(h->ctl, 1, st)) != hipSuccess) return bail(e, "reset");
   if ((e = launch_set_phase(h->ctl, h->hi_phase ? 0 : 1, st)) != hipSuccess) return bail(e, "phase");
   if ((e = launch_fill_int(h->colflags, 0, p.q, st)) != hipSuccess) return bail(e, "flags");
+  if (h->fmt == FMT_PFOURIER) {
+    // s_k = IHT(y_k, A_k, rho, tau0, 0), L_0 = [A_k^H (y_k - A_k s_k)], U_0 by subspace iteration
+    if ((e = launch_ftwiddle(F2(h->tw), st)) != hipSuccess) return bail(e, "twiddles");
+    if ((e = launch_fcol(fcol_args(h, FCOL_INIT), st)) != hipSuccess) return bail(e, "init column kernel");
+    if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
+    if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, 2LL * p.n * p.r, st);
+    else e = launch_fbasis(F2(h->Utmp), p.n, p.r, st);
+    if (e != hipSuccess) return bail(e, "start block");
+    if ((e = launch_fqr(fqr_args(h, QR_ORTH), st)) != hipSuccess) return bail(e, "orth");
+    for (int it = 0; it < par->power_iters; ++it) {
+      if ((e = launch_fltu(CF2(h->H), CF2(h->U), p.n, p.q, p.r, F2(h->Tpow), &h->ctl->conv, st)) != hipSuccess)
+        return bail(e, "ltu");
+      if ((e = launch_fgrad(CF2(h->H), CF2(h->Tpow), p.n, p.q, p.r, F2(h->gpart), &h->ctl->conv, st)) != hipSuccess)
+        return bail(e, "power grad");
+      if ((e = launch_fqr(fqr_args(h, QR_POWER), st)) != hipSuccess) return bail(e, "power qr");
+    }
+    if ((e = launch_reset_ctl(h->ctl, 0, st)) != hipSuccess) return bail(e, "reset eta");
+    *out = h;
+    return ALTGDMIN_OK;
+  }
   // s_k = IHT(y_k, A_k, rho, tau0, 0) and L_0 columns A_k^T (y_k - A_k s_k); the
   // hi plane alone when a BF16X2 solve starts with a hi-only phase
   ColArgs ca = col_args(h);
@@ -312,7 +438,22 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
   for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
   double acc[4] = {0, 0, 0, 0};
   int rc = ALTGDMIN_OK;
-  for (int it = 0; it < iters && rc == ALTGDMIN_OK; ++it) {
+  for (int it = 0; it < iters && rc == ALTGDMIN_OK && h->fmt == FMT_PFOURIER; ++it) {
+    hipError_t e = hipSuccess;
+    for (int w = 0; w < 4 && e == hipSuccess; ++w) {
+      e = hipEventRecord(ev[w], st);
+      if (e == hipSuccess) e = fourier_launch(h, w, st);
+    }
+    if (e == hipSuccess) e = hipEventRecord(ev[4], st);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[4]);
+    for (int k = 0; k < 4 && e == hipSuccess; ++k) {
+      float ms = 0.f;
+      e = hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      acc[k] += ms;
+    }
+    if (e != hipSuccess) rc = fail(ALTGDMIN_EHIP, std::string("profile: ") + hipGetErrorString(e));
+  }
+  for (int it = 0; it < iters && rc == ALTGDMIN_OK && h->fmt != FMT_PFOURIER; ++it) {
     AUArgs au;
     au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
     au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
@@ -351,11 +492,12 @@ int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float*
   hipStream_t st = static_cast<hipStream_t>(stream);
   const altgdmin_problem& p = h->prob;
   const size_t nr = (size_t)p.n * p.r;
-  if (U) HIPCHK(hipMemcpyAsync(U, h->t_host > 0 ? h->Uprev : h->U, nr * 4, hipMemcpyDeviceToDevice, st));
-  if (U_next) HIPCHK(hipMemcpyAsync(U_next, h->U, nr * 4, hipMemcpyDeviceToDevice, st));
-  if (Bt) HIPCHK(hipMemcpyAsync(Bt, h->Bt, (size_t)p.q * p.r * 4, hipMemcpyDeviceToDevice, st));
+  const size_t w = h->fmt == FMT_PFOURIER ? 8 : 4;   // bytes per value: complex64 in the Fourier form
+  if (U) HIPCHK(hipMemcpyAsync(U, h->t_host > 0 ? h->Uprev : h->U, nr * w, hipMemcpyDeviceToDevice, st));
+  if (U_next) HIPCHK(hipMemcpyAsync(U_next, h->U, nr * w, hipMemcpyDeviceToDevice, st));
+  if (Bt) HIPCHK(hipMemcpyAsync(Bt, h->Bt, (size_t)p.q * p.r * w, hipMemcpyDeviceToDevice, st));
   if (S_idx && p.rho > 0) HIPCHK(hipMemcpyAsync(S_idx, h->Tidx, (size_t)p.q * p.rho * 4, hipMemcpyDeviceToDevice, st));
-  if (S_val && p.rho > 0) HIPCHK(hipMemcpyAsync(S_val, h->Tval, (size_t)p.q * p.rho * 4, hipMemcpyDeviceToDevice, st));
+  if (S_val && p.rho > 0) HIPCHK(hipMemcpyAsync(S_val, h->Tval, (size_t)p.q * p.rho * w, hipMemcpyDeviceToDevice, st));
   return ALTGDMIN_OK;
 }
 
@@ -474,6 +616,7 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     altgdmin_handle* h = hs[i];
     if (!h) return fail(ALTGDMIN_EINVAL, "null handle");
     if (h->hi_phase) return fail(ALTGDMIN_EINVAL, "a BF16X2 problem with a hi-only phase cannot be batched");
+    if (h->fmt == FMT_PFOURIER) return fail(ALTGDMIN_EINVAL, "batched stepping takes the real A formats only");
     const altgdmin_problem& p = h->prob;
     AUArgs au;
     std::memset(&au, 0, sizeof(au));

@@ -12,7 +12,7 @@ constexpr int kNCMax = 4;            // largest number of 256-row chunks per lan
 constexpr int kQRThreads = 1024;
 
 // A-operand formats (loader template argument)
-enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2, FMT_PHILOX = 3 };
+enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2, FMT_PHILOX = 3, FMT_PFOURIER = 4 };
 constexpr int kNormalTable = 32 * 64 + 2;   // entries of the normal table of the Philox form
 
 // Device-side control block of one solve.

@@ -1,0 +1,974 @@
+// Partial Fourier form of the measurement operators (gfx950).
+//
+// A_k keeps the rows mask_k of the unitary 2D DFT of 96 x 96 complex frames
+// (x_k flattened row-major; frequency index u = u1 * 96 + u2), so
+// A_k x = (F x)[mask_k] and A_k^H v = F^H (v scattered to mask_k).  All data are
+// complex64 (float2 = re, im); every transpose of the real path is a conjugate
+// transpose and HardThreshold ranks by modulus.  Per GDmin iteration of Alg. 1:
+//
+//   k_fu   : F U (the DFT of each column of U), one workgroup per column of U;
+//   k_fcol : per column k (one 1024-thread workgroup): P_k = (F U)[mask_k],
+//            G_k = P_k^H P_k and its inverse in FP64, the projected IHT of
+//            Alg. 2 (tau iterations, three 2D FFTs each), b_k by least squares
+//            (eq. (bk_LS)), r_k and h_k = A_k^H r_k;
+//   k_fgrad: grad_U f = sum_k h_k b_k^H in fixed column order;
+//   k_fqr  : eta at t = 1, U - eta grad, CholeskyQR2 with a real positive
+//            diagonal, the residual.
+// The initialisation uses k_fcol with M = A_k (IHT from 0, then the columns of
+// L_0 = [A_k^H (y_k - A_k s_k)]) and the subspace iteration k_fltu / k_fgrad /
+// k_fqr.
+//
+// 2D FFT.  A frame lives in LDS as 96 rows of 97 complex values (one pad column
+// keeps the column pass free of bank conflicts).  Each 96-point transform is
+// done by a group of 32 lanes: lane l holds elements l, l + 32, l + 64; a
+// radix-3 butterfly with twiddles W96^(l k2) is followed by a 32-point radix-2
+// decimation-in-frequency transform across the lanes (ds_swizzle exchanges), so
+// lane l ends with outputs 3 bitrev5(l) + k2.  Rows first, then columns; the
+// unitary scale 1/96 is applied in the column pass.
+#include "common.h"
+#include "launch.h"
+
+namespace altg {
+
+namespace {
+
+__device__ __forceinline__ float2 c_add(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ float2 c_sub(float2 a, float2 b) { return make_float2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ float2 c_mul(float2 a, float2 b) {
+  return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ float2 c_scale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+
+// |v|^2 as the ranking key: two products and one sum, each rounded to FP32.
+__device__ __forceinline__ float c_abs2_key(float2 v) {
+#pragma clang fp contract(off)
+  const float a = v.x * v.x;
+  const float b = v.y * v.y;
+  return a + b;
+}
+
+__device__ __forceinline__ int fpos(int j) { return j + j / kFN; }   // element j -> padded grid slot
+
+template <int H>
+__device__ __forceinline__ float2 swz_xor(float2 v) {
+  // ds_swizzle bit mode inside groups of 32 lanes: partner = lane ^ H
+  constexpr int pat = (H << 10) | 0x1f;
+  return make_float2(__int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v.x), pat)),
+                     __int_as_float(__builtin_amdgcn_ds_swizzle(__float_as_int(v.y), pat)));
+}
+
+template <bool INV>
+__device__ __forceinline__ float2 twid(const float2* tw, int e) {   // W96^e (conjugated for the inverse)
+  const float2 w = tw[e];
+  return INV ? make_float2(w.x, -w.y) : w;
+}
+
+template <bool INV, int H>
+__device__ __forceinline__ void dif_stage(float2 (&v)[3], int l, const float2* tw) {
+  const bool up = (l & H) != 0;
+  const float2 w = twid<INV>(tw, 3 * ((l & (H - 1)) * (16 / H)));   // W32^((l mod H) 16 / H)
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float2 t = swz_xor<H>(v[a]);
+    v[a] = up ? c_mul(c_sub(t, v[a]), w) : c_add(v[a], t);
+  }
+}
+
+// 96-point DFT by the 32 lanes of a group: in v[a] = x[l + 32 a], out v[a] = X[3 bitrev5(l) + a].
+template <bool INV>
+__device__ __forceinline__ void fft96(float2 (&v)[3], int l, const float2* tw) {
+  const float2 w1 = twid<INV>(tw, 32), w2 = twid<INV>(tw, 64);   // W3, W3^2
+  const float2 x0 = v[0], x1 = v[1], x2 = v[2];
+  v[0] = c_add(c_add(x0, x1), x2);
+  v[1] = c_mul(c_add(c_add(x0, c_mul(x1, w1)), c_mul(x2, w2)), twid<INV>(tw, l));
+  v[2] = c_mul(c_add(c_add(x0, c_mul(x1, w2)), c_mul(x2, w1)), twid<INV>(tw, 2 * l));
+  dif_stage<INV, 16>(v, l, tw);
+  dif_stage<INV, 8>(v, l, tw);
+  dif_stage<INV, 4>(v, l, tw);
+  dif_stage<INV, 2>(v, l, tw);
+  dif_stage<INV, 1>(v, l, tw);
+}
+
+// Unitary 2D DFT (INV: its inverse) of the frame in `grid`, in place.  All 1024
+// threads call it; it ends with a barrier.
+template <bool INV>
+__device__ __attribute__((noinline)) void fft2_grid(float2* grid, const float2* tw) {
+  const int g = threadIdx.x >> 5, l = threadIdx.x & 31;
+  const int k1 = (int)(__builtin_bitreverse32((unsigned)l) >> 27);
+  for (int rr = 0; rr < 3; ++rr) {
+    float2* row = grid + (g + 32 * rr) * kFP;
+    float2 v[3] = {row[l], row[l + 32], row[l + 64]};
+    fft96<INV>(v, l, tw);
+    row[3 * k1] = v[0];
+    row[3 * k1 + 1] = v[1];
+    row[3 * k1 + 2] = v[2];
+  }
+  __syncthreads();
+  const float s = 1.0f / kFN;
+  for (int cc = 0; cc < 3; ++cc) {
+    float2* col = grid + g + 32 * cc;
+    float2 v[3] = {col[l * kFP], col[(l + 32) * kFP], col[(l + 64) * kFP]};
+    fft96<INV>(v, l, tw);
+    col[(3 * k1) * kFP] = c_scale(v[0], s);
+    col[(3 * k1 + 1) * kFP] = c_scale(v[1], s);
+    col[(3 * k1 + 2) * kFP] = c_scale(v[2], s);
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ void zero_grid(float2* grid) {
+  for (int t = threadIdx.x; t < kFGrid; t += kFThreads) grid[t] = make_float2(0.f, 0.f);
+}
+
+// Sum over the workgroup of NV doubles per thread, in a fixed order (DPP inside
+// each wave, then the 16 wave totals in wave order).  out[0..NV) in LDS; ends
+// with a barrier.  red holds kFWaves * NV doubles.
+template <int NV>
+__device__ void fblock_sum(double (&v)[NV], double* red, double* out) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum_dpp(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) red[wave * NV + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double s = 0.0;
+    for (int w = 0; w < kFWaves; ++w) s += red[w * NV + threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// Exclusive prefix sum of one int per thread over the workgroup in thread order;
+// *total gets the sum.  tmp holds kFWaves + 1 ints.
+__device__ int fblock_exscan(int v, int* tmp, int* total) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  int incl = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int t = __shfl_up(incl, o);
+    if (lane >= o) incl += t;
+  }
+  if (lane == 63) tmp[wave] = incl;
+  __syncthreads();
+  int base = 0, all = 0;
+  for (int w = 0; w < kFWaves; ++w) {
+    const int t = tmp[w];
+    base += w < wave ? t : 0;
+    all += t;
+  }
+  *total = all;
+  __syncthreads();
+  return base + incl - v;
+}
+
+// HardThreshold support of n complex values: the rho largest keys |v|^2 (FP32,
+// as c_abs2_key), lower index first on ties, written ascending to idx[0..rho).
+// Thread t owns the contiguous elements [t c, t c + c), c = ceil(n / 1024).
+// Byte-wise radix selection with a 256-bin LDS histogram.  Returns the number of
+// NaN keys seen.  hist holds 256 + 8 ints, tmp kFWaves + 1 ints.
+template <class Val>
+__device__ int fselect(Val val, int n, int rho, int* idx, int* hist, int* tmp) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  const int per = (n + kFThreads - 1) / kFThreads;
+  const int j0 = tid * per;
+  const int j1 = min(n, j0 + per);
+  int* ctl = hist + 256;
+  unsigned prefix = 0u, pmask = 0u;
+  int remaining = rho;
+  int nanc = 0;
+  for (int d = 3; d >= 0; --d) {
+    const int shift = 8 * d;
+    for (int b = tid; b < 256; b += kFThreads) hist[b] = 0;
+    if (d == 3 && tid == 0) ctl[2] = 0;
+    __syncthreads();
+    for (int j = j0; j < j1; ++j) {
+      const unsigned key = __float_as_uint(c_abs2_key(val(j)));
+      if (d == 3) nanc += key > 0x7f800000u ? 1 : 0;
+      if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1);
+    }
+    if (d == 3 && nanc) atomicAdd(&ctl[2], nanc);
+    __syncthreads();
+    if (wave == 0) {
+      const int h0 = hist[4 * lane], h1 = hist[4 * lane + 1], h2 = hist[4 * lane + 2], h3 = hist[4 * lane + 3];
+      const int lsum = h0 + h1 + h2 + h3;
+      int incl = lsum;   // inclusive suffix sum over lanes >= lane
+#pragma unroll
+      for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_down(incl, o);
+        if (lane + o < 64) incl += t;
+      }
+      int acc = incl - lsum;
+      const int hb[4] = {h3, h2, h1, h0};
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (acc < remaining && remaining <= acc + hb[q]) {
+          ctl[0] = 4 * lane + 3 - q;
+          ctl[1] = remaining - acc;
+        }
+        acc += hb[q];
+      }
+    }
+    __syncthreads();
+    remaining = ctl[1];
+    prefix |= (unsigned)ctl[0] << shift;
+    pmask |= 255u << shift;
+    __syncthreads();
+  }
+  const unsigned T = prefix;
+  int ngt = 0, neq = 0;
+  for (int j = j0; j < j1; ++j) {
+    const unsigned key = __float_as_uint(c_abs2_key(val(j)));
+    ngt += key > T ? 1 : 0;
+    neq += key == T ? 1 : 0;
+  }
+  int tot;
+  const int eq_base = fblock_exscan(neq, tmp, &tot);
+  const int take_eq = max(0, min(neq, remaining - eq_base));
+  const int nsel = ngt + take_eq;
+  const int pos0 = fblock_exscan(nsel, tmp, &tot);
+  int pos = pos0, eqs = 0;
+  for (int j = j0; j < j1; ++j) {
+    const unsigned key = __float_as_uint(c_abs2_key(val(j)));
+    bool sel = key > T;
+    if (key == T) {
+      sel = eqs < take_eq;
+      ++eqs;
+    }
+    if (sel && pos < rho) idx[pos++] = j;
+  }
+  const int nan_total = ctl[2];
+  __syncthreads();
+  return nan_total;
+}
+
+// G^{-1} of a Hermitian positive definite r x r matrix (complex FP64, row-major
+// double2 = re, im), by the workgroup: Cholesky G = L L^H (real positive
+// diagonal) column by column, thread j + 1 + t computing L[j + 1 + t][j]; then
+// thread c solves L y = e_c and L^H x = y for column c.  Returns false (identity
+// in Ginv) if a pivot is not positive.
+__device__ bool fblock_chol_inverse(const double2* G, double2* L, double2* Ginv, double2* Y, int r) {
+  const int tid = threadIdx.x;
+  for (int j = 0; j < r; ++j) {
+    double s = G[j * r + j].x;
+    for (int p = 0; p < j; ++p) s -= L[j * r + p].x * L[j * r + p].x + L[j * r + p].y * L[j * r + p].y;
+    if (!(s > 0.0)) {
+      for (int i = tid; i < r * r; i += kFThreads) Ginv[i] = make_double2((i % (r + 1) == 0) ? 1.0 : 0.0, 0.0);
+      __syncthreads();
+      return false;
+    }
+    const double d = sqrt(s);
+    const int i = j + 1 + tid;
+    if (i < r) {
+      double tr = G[i * r + j].x, ti = G[i * r + j].y;
+      for (int p = 0; p < j; ++p) {   // t -= L[i][p] conj(L[j][p])
+        const double2 a = L[i * r + p], b = L[j * r + p];
+        tr -= a.x * b.x + a.y * b.y;
+        ti -= a.y * b.x - a.x * b.y;
+      }
+      L[i * r + j] = make_double2(tr / d, ti / d);
+    }
+    if (tid == 0) L[j * r + j] = make_double2(d, 0.0);
+    if (tid < j) L[tid * r + j] = make_double2(0.0, 0.0);
+    __syncthreads();
+  }
+  if (tid < r) {
+    const int c = tid;
+    for (int i = c; i < r; ++i) {
+      double tr = (i == c) ? 1.0 : 0.0, ti = 0.0;
+      for (int p = c; p < i; ++p) {   // t -= L[i][p] y[p]
+        const double2 a = L[i * r + p], y = Y[p * r + c];
+        tr -= a.x * y.x - a.y * y.y;
+        ti -= a.x * y.y + a.y * y.x;
+      }
+      const double dd = L[i * r + i].x;
+      Y[i * r + c] = make_double2(tr / dd, ti / dd);
+    }
+    for (int i = r - 1; i >= 0; --i) {
+      double tr = i >= c ? Y[i * r + c].x : 0.0, ti = i >= c ? Y[i * r + c].y : 0.0;
+      for (int p = i + 1; p < r; ++p) {   // t -= conj(L[p][i]) x[p]
+        const double2 a = L[p * r + i], x = Ginv[p * r + c];
+        tr -= a.x * x.x + a.y * x.y;
+        ti -= a.x * x.y - a.y * x.x;
+      }
+      const double dd = L[i * r + i].x;
+      Ginv[i * r + c] = make_double2(tr / dd, ti / dd);
+    }
+  }
+  __syncthreads();
+  return true;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- k_fcol
+
+// LDS layout of the column kernel (bytes)
+struct FColLayout {
+  size_t gridA, gridB, tw, red, gi, dsum, sidx, sval, gT, hist, tmp, total;
+  __host__ __device__ FColLayout(int rho, int r) {
+    size_t o = 0;
+    gridA = o; o = align16(o + 8 * (size_t)kFGrid);
+    gridB = o; o = align16(o + 8 * (size_t)kFGrid);
+    tw = o;    o = align16(o + 8 * (size_t)kFN);
+    red = o;   o = align16(o + 8 * (size_t)kFWaves * 2 * kFRMax);
+    gi = o;    o = align16(o + 16 * (size_t)r * r);
+    dsum = o;  o = align16(o + 8 * (size_t)2 * kFRMax);
+    sidx = o;  o = align16(o + 4 * (size_t)rho);
+    sval = o;  o = align16(o + 8 * (size_t)rho);
+    gT = o;    o = align16(o + 8 * (size_t)rho);
+    hist = o;  o = align16(o + 4 * (size_t)(256 + 8));
+    tmp = o;   o = align16(o + 4 * (size_t)(kFWaves + 1));
+    total = o;
+  }
+};
+
+size_t fcol_lds_bytes(int rho, int r) { return FColLayout(rho, r).total; }
+
+template <int R>
+__global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const int tid = threadIdx.x, k = blockIdx.x;
+  const int n = a.n, m = a.m, r = a.r, rho = a.rho;
+  const bool gd = a.mode == FCOL_GD;
+  const FColLayout lay(rho, r);
+  float2* gA = reinterpret_cast<float2*>(smem + lay.gridA);
+  float2* gB = reinterpret_cast<float2*>(smem + lay.gridB);
+  float2* tw = reinterpret_cast<float2*>(smem + lay.tw);
+  double* red = reinterpret_cast<double*>(smem + lay.red);
+  double2* Gi = reinterpret_cast<double2*>(smem + lay.gi);
+  double* dsum = reinterpret_cast<double*>(smem + lay.dsum);
+  int* sidx = reinterpret_cast<int*>(smem + lay.sidx);
+  float2* sval = reinterpret_cast<float2*>(smem + lay.sval);
+  float2* gT = reinterpret_cast<float2*>(smem + lay.gT);
+  int* hist = reinterpret_cast<int*>(smem + lay.hist);
+  int* tmp = reinterpret_cast<int*>(smem + lay.tmp);
+
+  for (int t = tid; t < kFN; t += kFThreads) tw[t] = a.tw[t];
+  // the measurement rows i = tid, tid + 1024 of this thread, in registers
+  int mi[2];
+  bool ok[2];
+  float2 yv[2];
+  int flags = 0;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int i = tid + kFThreads * e;
+    const int raw = i < m ? a.mask[(long long)k * m + i] : 0;
+    const bool inr = raw >= 0 && raw < n;
+    if (i < m && !inr) flags |= 4;   // a frequency index out of range: the row is left out
+    ok[e] = i < m && inr;
+    mi[e] = ok[e] ? raw : 0;
+    yv[e] = ok[e] ? a.Y[(long long)k * a.ldy + i] : make_float2(0.f, 0.f);
+  }
+  // row i of P_k = row mask_k[i] of F U (read from the L2-resident F U when used)
+  auto Prow = [&](int e, float2 (&p)[R]) {
+    const float2* src = a.FU + (long long)mi[e] * r;
+#pragma unroll
+    for (int c = 0; c < R; ++c) p[c] = (ok[e] && c < r) ? src[c] : make_float2(0.f, 0.f);
+  };
+  if (gd)
+    for (int e = tid; e < rho; e += kFThreads) {
+      sidx[e] = a.Sidx[(long long)k * rho + e];
+      sval[e] = a.Sval[(long long)k * rho + e];
+    }
+  __syncthreads();
+
+  // G_k = P_k^H P_k (FP64) and its inverse
+  if (gd) {
+    double2* Gl = reinterpret_cast<double2*>(gB);              // scratch: gridB is free here
+    double2* Ll = Gl + kFRMax * kFRMax;
+    double2* Yl = Ll + kFRMax * kFRMax;
+#pragma unroll
+    for (int ra = 0; ra < R; ++ra) {
+      if (ra < r) {   // row ra of G: conj(P[i][ra]) P[i][c], summed over the rows i
+        double v[2 * R];
+#pragma unroll
+        for (int c = 0; c < 2 * R; ++c) v[c] = 0.0;
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          float2 p[R];
+          Prow(e, p);
+#pragma unroll
+          for (int c = 0; c < R; ++c) {
+            const float2 pa = p[ra], pc = p[c];
+            v[2 * c] += (double)pa.x * pc.x + (double)pa.y * pc.y;
+            v[2 * c + 1] += (double)pa.x * pc.y - (double)pa.y * pc.x;
+          }
+        }
+        fblock_sum<2 * R>(v, red, dsum);
+        if (tid < r) Gl[ra * r + tid] = make_double2(dsum[2 * tid], dsum[2 * tid + 1]);
+        __syncthreads();
+      }
+    }
+    if (!fblock_chol_inverse(Gl, Ll, Gi, Yl, r)) flags |= 2;
+  }
+
+  // v <- v - P_k G_k^{-1} P_k^H v for the two rows of this thread
+  auto project = [&](float2 (&v)[2]) {
+    double c[2 * R];
+#pragma unroll
+    for (int cc = 0; cc < 2 * R; ++cc) c[cc] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {   // conj(P[i][cc]) v[i]
+      float2 p[R];
+      Prow(e, p);
+#pragma unroll
+      for (int cc = 0; cc < R; ++cc) {
+        c[2 * cc] += (double)p[cc].x * v[e].x + (double)p[cc].y * v[e].y;
+        c[2 * cc + 1] += (double)p[cc].x * v[e].y - (double)p[cc].y * v[e].x;
+      }
+    }
+    fblock_sum<2 * R>(c, red, dsum);
+    float2 d[R];
+#pragma unroll
+    for (int ra = 0; ra < R; ++ra) {
+      double dr = 0.0, di = 0.0;
+      if (ra < r)
+        for (int cb = 0; cb < r; ++cb) {
+          const double2 g = Gi[ra * r + cb];
+          const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
+          dr += g.x * xr - g.y * xi;
+          di += g.x * xi + g.y * xr;
+        }
+      d[ra] = make_float2((float)dr, (float)di);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      float2 p[R];
+      Prow(e, p);
+      float2 s = v[e];
+#pragma unroll
+      for (int ra = 0; ra < R; ++ra) s = c_sub(s, c_mul(p[ra], d[ra]));
+      v[e] = ok[e] ? s : make_float2(0.f, 0.f);
+    }
+  };
+
+  auto sum_sq = [&](float2 (&v)[2]) -> double {
+    double s[1] = {0.0};
+#pragma unroll
+    for (int e = 0; e < 2; ++e) s[0] += (double)v[e].x * v[e].x + (double)v[e].y * v[e].y;
+    fblock_sum<1>(s, red, dsum);
+    return dsum[0];
+  };
+
+  // A_k s (the sparse s in sidx/sval) into grid B, gathered at this thread's rows
+  auto apply_sparse = [&](const int* id, const float2* vl, int cnt, float2 (&out)[2]) {
+    zero_grid(gB);
+    __syncthreads();
+    for (int e = tid; e < cnt; e += kFThreads) gB[fpos(id[e])] = vl[e];
+    __syncthreads();
+    fft2_grid<false>(gB, tw);
+#pragma unroll
+    for (int e = 0; e < 2; ++e) out[e] = ok[e] ? gB[fpos(mi[e])] : make_float2(0.f, 0.f);
+    __syncthreads();
+  };
+  // A_k^H v into grid A
+  auto apply_adj = [&](float2 (&v)[2]) {
+    zero_grid(gA);
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 2; ++e)
+      if (ok[e]) gA[fpos(mi[e])] = v[e];
+    __syncthreads();
+    fft2_grid<true>(gA, tw);
+  };
+
+  bool have = gd;
+  const int tau = rho > 0 ? a.tau : 0;
+  for (int it = 0; it < tau; ++it) {
+    // u = M s - z: A s - y (projected in the GD iterations)
+    float2 u[2];
+    if (have) {
+      apply_sparse(sidx, sval, rho, u);
+    } else {
+      u[0] = u[1] = make_float2(0.f, 0.f);
+    }
+#pragma unroll
+    for (int e = 0; e < 2; ++e) u[e] = ok[e] ? c_sub(u[e], yv[e]) : make_float2(0.f, 0.f);
+    if (gd) project(u);
+    // g = M^H u = A^H u (u lies in the range of the projector)
+    apply_adj(u);
+    // T: the current support, or that of HardThreshold(g) when s = 0
+    if (!have) {
+      flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
+      for (int e = tid; e < rho; e += kFThreads) sval[e] = make_float2(0.f, 0.f);
+      __syncthreads();
+    }
+    for (int e = tid; e < rho; e += kFThreads) gT[e] = gA[fpos(sidx[e])];
+    double gg;
+    {
+      double s[1] = {0.0};
+      for (int e = tid; e < rho; e += kFThreads) s[0] += (double)gT[e].x * gT[e].x + (double)gT[e].y * gT[e].y;
+      fblock_sum<1>(s, red, dsum);
+      gg = dsum[0];
+    }
+    // w = M g_T
+    float2 w[2];
+    apply_sparse(sidx, gT, rho, w);
+    if (gd) project(w);
+    const double ww = sum_sq(w);
+    const bool okmu = ww > 0.0 && isfinite(ww) && isfinite(gg);
+    const float mu = okmu ? (float)(gg / ww) : 0.f;
+    // v = s - mu g in grid A, then HardThreshold
+    for (int t = tid; t < kFGrid; t += kFThreads) gA[t] = c_scale(gA[t], -mu);
+    __syncthreads();
+    for (int e = tid; e < rho; e += kFThreads) gA[fpos(sidx[e])] = c_add(gA[fpos(sidx[e])], sval[e]);
+    __syncthreads();
+    flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
+    for (int e = tid; e < rho; e += kFThreads) sval[e] = gA[fpos(sidx[e])];
+    __syncthreads();
+    have = true;
+  }
+
+  // A_k s_k and e_k = y_k - A_k s_k
+  float2 ev[2];
+  if (rho > 0) {
+    apply_sparse(sidx, sval, rho, ev);
+  } else {
+    ev[0] = ev[1] = make_float2(0.f, 0.f);
+  }
+#pragma unroll
+  for (int e = 0; e < 2; ++e) ev[e] = ok[e] ? c_sub(yv[e], ev[e]) : make_float2(0.f, 0.f);
+
+  float2* Hk = a.H + (long long)k * n;
+  if (gd) {
+    // b_k = G_k^{-1} P_k^H e_k; r_k = P_k b_k - e_k; h_k = A_k^H r_k
+    double c[2 * R];
+#pragma unroll
+    for (int cc = 0; cc < 2 * R; ++cc) c[cc] = 0.0;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      float2 p[R];
+      Prow(e, p);
+#pragma unroll
+      for (int cc = 0; cc < R; ++cc) {
+        c[2 * cc] += (double)p[cc].x * ev[e].x + (double)p[cc].y * ev[e].y;
+        c[2 * cc + 1] += (double)p[cc].x * ev[e].y - (double)p[cc].y * ev[e].x;
+      }
+    }
+    fblock_sum<2 * R>(c, red, dsum);
+    float2 b[R];
+#pragma unroll
+    for (int ra = 0; ra < R; ++ra) {
+      double br = 0.0, bi = 0.0;
+      if (ra < r)
+        for (int cb = 0; cb < r; ++cb) {
+          const double2 g = Gi[ra * r + cb];
+          const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
+          br += g.x * xr - g.y * xi;
+          bi += g.x * xi + g.y * xr;
+        }
+      b[ra] = make_float2((float)br, (float)bi);
+    }
+    if (tid < r) {
+      float2 bo = b[0];
+#pragma unroll
+      for (int ra = 0; ra < R; ++ra)
+        if (ra == tid) bo = b[ra];
+      a.Bt[(long long)k * r + tid] = bo;
+    }
+    float2 rv[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      float2 p[R];
+      Prow(e, p);
+      float2 s = make_float2(-ev[e].x, -ev[e].y);
+#pragma unroll
+      for (int ra = 0; ra < R; ++ra) s = c_add(s, c_mul(p[ra], b[ra]));
+      rv[e] = ok[e] ? s : make_float2(0.f, 0.f);
+    }
+    const double rr = sum_sq(rv);
+    if (tid == 0) a.colrr[k] = rr;
+    apply_adj(rv);
+  } else {
+    // initialisation: ||y_k||^2 and the column A_k^H (y_k - A_k s_k) of L_0
+    const double yy = sum_sq(yv);
+    if (tid == 0) a.colrr[k] = yy;
+    apply_adj(ev);
+  }
+  for (int j = tid; j < n; j += kFThreads) Hk[j] = gA[fpos(j)];
+  for (int e = tid; e < rho; e += kFThreads) {
+    a.Sidx[(long long)k * rho + e] = sidx[e];
+    a.Sval[(long long)k * rho + e] = sval[e];
+  }
+  if (flags) atomicOr(&a.flags[k], flags);
+}
+
+// ---------------------------------------------------------------- U side
+
+// F U: column c of U (n x r, row-major) transformed by workgroup c.
+__global__ __launch_bounds__(kFThreads) void k_fu(const float2* U, int r, const float2* twg, float2* FU) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  float2* grid = reinterpret_cast<float2*>(smem);
+  float2* tw = grid + kFGrid;
+  const int c = blockIdx.x, tid = threadIdx.x;
+  for (int t = tid; t < kFN; t += kFThreads) tw[t] = twg[t];
+  zero_grid(grid);
+  __syncthreads();
+  for (int j = tid; j < kFN * kFN; j += kFThreads) grid[fpos(j)] = U[(long long)j * r + c];
+  __syncthreads();
+  fft2_grid<false>(grid, tw);
+  for (int u = tid; u < kFN * kFN; u += kFThreads) FU[(long long)u * r + c] = grid[fpos(u)];
+}
+
+// Tc[k][c] = sum_j H[k][j] conj(U[j][c]) (so that L_0 (L_0^H U) = sum_k h_k conj(Tc[k]) ^ T).
+template <int R>
+__global__ __launch_bounds__(kFThreads) void k_fltu(const float2* H, const float2* U, int n, int r, float2* Tc,
+                                                    const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double red[kFWaves * 2 * kFRMax];
+  __shared__ double out[2 * kFRMax];
+  const int k = blockIdx.x, tid = threadIdx.x;
+  double v[2 * R];
+#pragma unroll
+  for (int i = 0; i < 2 * R; ++i) v[i] = 0.0;
+  for (int j = tid; j < n; j += kFThreads) {
+    const float2 h = H[(long long)k * n + j];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (c < r) {
+        const float2 u = U[(long long)j * r + c];
+        v[2 * c] += (double)h.x * u.x + (double)h.y * u.y;
+        v[2 * c + 1] += (double)h.y * u.x - (double)h.x * u.y;
+      }
+  }
+  fblock_sum<2 * R>(v, red, out);
+  if (tid < r) Tc[(long long)k * r + tid] = make_float2((float)out[2 * tid], (float)out[2 * tid + 1]);
+}
+
+// Gsum[j][c] = sum_k H[k][j] conj(B[k][c]), k in order (grad_U f with B = B_t;
+// L_0 (L_0^H U) with B = Tc).  One thread per row j.
+template <int R>
+__global__ __launch_bounds__(256) void k_fgrad(const float2* H, const float2* B, int n, int q, int r, float2* Gsum,
+                                               const int* skip) {
+  if (skip && *skip) return;
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= n) return;
+  float2 acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = make_float2(0.f, 0.f);
+  for (int k = 0; k < q; ++k) {
+    const float2 h = H[(long long)k * n + j];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (c < r) {
+        const float2 b = B[(long long)k * r + c];
+        acc[c].x = fmaf(h.x, b.x, fmaf(h.y, b.y, acc[c].x));
+        acc[c].y = fmaf(h.y, b.x, fmaf(-h.x, b.y, acc[c].y));
+      }
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    if (c < r) Gsum[(long long)j * r + c] = acc[c];
+}
+
+namespace {
+
+// Largest eigenvalue of a real symmetric N x N matrix (row-major, destroyed) by
+// cyclic Jacobi rotations; one thread.
+__device__ double jacobi_lmax(double* A, int N) {
+  for (int sweep = 0; sweep < 40; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j) {
+        tot += A[i * N + j] * A[i * N + j];
+        if (i != j) off += A[i * N + j] * A[i * N + j];
+      }
+    if (off <= 1e-30 * tot) break;
+    for (int p = 0; p < N - 1; ++p)
+      for (int q = p + 1; q < N; ++q) {
+        const double apq = A[p * N + q];
+        if (apq == 0.0) continue;
+        const double theta = (A[q * N + q] - A[p * N + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+        for (int k = 0; k < N; ++k) {
+          const double akp = A[k * N + p], akq = A[k * N + q];
+          A[k * N + p] = cs * akp - sn * akq;
+          A[k * N + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < N; ++k) {
+          const double apk = A[p * N + k], aqk = A[q * N + k];
+          A[p * N + k] = cs * apk - sn * aqk;
+          A[q * N + k] = sn * apk + cs * aqk;
+        }
+      }
+  }
+  double l = A[0];
+  for (int i = 1; i < N; ++i) l = fmax(l, A[i * N + i]);
+  return l;
+}
+
+// W (r x r, complex FP64) = X^H Y over the n rows (workgroup sum, fixed order).
+template <int R>
+__device__ void fgram(const float2* X, const float2* Y, int n, int r, double* red, double* out, double2* W) {
+  const int tid = threadIdx.x;
+  for (int ra = 0; ra < r; ++ra) {
+    double v[2 * R];
+#pragma unroll
+    for (int i = 0; i < 2 * R; ++i) v[i] = 0.0;
+    for (int j = tid; j < n; j += kFThreads) {
+      const float2 x = X[(long long)j * r + ra];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (c < r) {
+          const float2 y = Y[(long long)j * r + c];
+          v[2 * c] += (double)x.x * y.x + (double)x.y * y.y;
+          v[2 * c + 1] += (double)x.x * y.y - (double)x.y * y.x;
+        }
+    }
+    fblock_sum<2 * R>(v, red, out);
+    if (tid < r) W[ra * r + tid] = make_double2(out[2 * tid], out[2 * tid + 1]);
+    __syncthreads();
+  }
+}
+
+// One CholeskyQR pass on X (n x r in global memory): X <- X R^{-1}, R = L^H from
+// X^H X = L L^H.  Returns false if X^H X is not positive definite.
+template <int R>
+__device__ bool fcholqr_pass(float2* X, int n, int r, double* red, double* out, double2* W, double2* Lm, int* okf) {
+  const int tid = threadIdx.x;
+  fgram<R>(X, X, n, r, red, out, W);
+  if (tid == 0) {
+    int ok = 1;
+    for (int j = 0; j < r && ok; ++j) {
+      double s = W[j * r + j].x;
+      for (int p = 0; p < j; ++p) s -= Lm[j * r + p].x * Lm[j * r + p].x + Lm[j * r + p].y * Lm[j * r + p].y;
+      if (!(s > 0.0)) { ok = 0; break; }
+      const double d = sqrt(s);
+      Lm[j * r + j] = make_double2(d, 0.0);
+      for (int i = j + 1; i < r; ++i) {
+        double tr = W[i * r + j].x, ti = W[i * r + j].y;
+        for (int p = 0; p < j; ++p) {
+          const double2 a = Lm[i * r + p], b = Lm[j * r + p];
+          tr -= a.x * b.x + a.y * b.y;
+          ti -= a.y * b.x - a.x * b.y;
+        }
+        Lm[i * r + j] = make_double2(tr / d, ti / d);
+      }
+    }
+    *okf = ok;
+  }
+  __syncthreads();
+  if (!*okf) return false;
+  // row x <- x R^{-1}: q[c] = (x[c] - sum_{p<c} q[p] R[p][c]) / R[c][c], R[p][c] = conj(L[c][p])
+  for (int j = tid; j < n; j += kFThreads) {
+    float2 x[R];
+    double2 qd[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c) x[c] = c < r ? X[(long long)j * r + c] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      double tr = x[c].x, ti = x[c].y;
+#pragma unroll
+      for (int p = 0; p < c; ++p) {   // q[p] * conj(L[c][p])
+        const double2 l = c < r ? Lm[c * r + p] : make_double2(0.0, 0.0);
+        tr -= qd[p].x * l.x + qd[p].y * l.y;
+        ti -= qd[p].y * l.x - qd[p].x * l.y;
+      }
+      const double d = c < r ? Lm[c * r + c].x : 1.0;
+      qd[c] = make_double2(tr / d, ti / d);
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (c < r) X[(long long)j * r + c] = make_float2((float)qd[c].x, (float)qd[c].y);
+  }
+  __syncthreads();
+  return true;
+}
+
+}  // namespace
+
+// GD: U <- QR(U - eta grad) (eta fixed at t = 1), residual, log.  POWER: U <- QR(Z),
+// subspace change.  ORTH: U <- QR(Utmp).  One workgroup.
+template <int R>
+__global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
+  __shared__ double red[kFWaves * 2 * kFRMax];
+  __shared__ double out[2 * kFRMax];
+  __shared__ double2 W[kFRMax * kFRMax];
+  __shared__ double2 Lm[kFRMax * kFRMax];
+  __shared__ double Mr[4 * kFRMax * kFRMax];
+  __shared__ double eta_s;
+  __shared__ int okf;
+  const int tid = threadIdx.x, n = a.n, r = a.r, nr = n * r;
+  if (a.mode == QR_POWER && a.ctl->conv) return;
+  float2* X = a.Utmp;
+  if (a.mode == QR_GD) {
+    if (!a.ctl->eta_set) {
+      fgram<R>(a.G, a.G, n, r, red, out, W);
+      if (tid == 0) {
+        // Hermitian W = A + iB -> real symmetric [[A, -B], [B, A]] (same eigenvalues, doubled)
+        const int N = 2 * r;
+        for (int i = 0; i < r; ++i)
+          for (int j = 0; j < r; ++j) {
+            const double2 w = W[i * r + j];
+            Mr[i * N + j] = w.x;
+            Mr[(i + r) * N + j + r] = w.x;
+            Mr[i * N + j + r] = -w.y;
+            Mr[(i + r) * N + j] = w.y;
+          }
+        const double lam = jacobi_lmax(Mr, N);
+        const double eta = lam > 0.0 ? a.eta_c / sqrt(lam) : 0.0;
+        a.ctl->eta = eta;
+        a.ctl->eta_set = 1;
+        eta_s = eta;
+      }
+    } else if (tid == 0) {
+      eta_s = a.ctl->eta;
+    }
+    __syncthreads();
+    const double eta = eta_s;
+    for (int t = tid; t < nr; t += kFThreads) {
+      const float2 u = a.U[t], g = a.G[t];
+      X[t] = make_float2((float)fma(-eta, (double)g.x, (double)u.x), (float)fma(-eta, (double)g.y, (double)u.y));
+    }
+    __syncthreads();
+  } else if (a.mode == QR_POWER) {
+    for (int t = tid; t < nr; t += kFThreads) X[t] = a.G[t];
+    __syncthreads();
+  }
+  bool ok = fcholqr_pass<R>(X, n, r, red, out, W, Lm, &okf);
+  if (ok) ok = fcholqr_pass<R>(X, n, r, red, out, W, Lm, &okf);
+  if (!ok) {
+    if (tid == 0) a.ctl->err |= 2;
+    return;
+  }
+  if (a.mode == QR_POWER) {
+    fgram<R>(a.U, X, n, r, red, out, W);   // U_old^H U_new
+    if (tid == 0) {
+      double f = 0.0;
+      for (int e = 0; e < r * r; ++e) f += W[e].x * W[e].x + W[e].y * W[e].y;
+      const double sd = sqrt(fmax(0.0, (double)r - f));
+      a.ctl->power_sd = sd;
+      a.ctl->power_it += 1;
+      if (sd <= a.power_tol) a.ctl->conv = 1;
+    }
+  }
+  for (int t = tid; t < nr; t += kFThreads) {
+    if (a.mode == QR_GD) a.Uprev[t] = a.U[t];
+    a.U[t] = X[t];
+  }
+  if (a.mode == QR_GD) {
+    double s[1] = {0.0};
+    int fl = 0;
+    for (int k = tid; k < a.q; k += kFThreads) {
+      s[0] += a.colrr[k];
+      fl |= a.colflags[k];
+    }
+    // fixed-order sum: per-thread partials in thread order
+    fblock_sum<1>(s, red, out);
+    if (fl) atomicOr(&a.ctl->err, fl);
+    if (tid == 0) {
+      const double ss = out[0];
+      const double resid = a.ctl->ynorm2 > 0.0 ? sqrt(ss / a.ctl->ynorm2) : sqrt(ss);
+      const int t = a.ctl->t;
+      if (a.rlog && t < a.rlog_len) a.rlog[t] = resid;
+      a.ctl->resid = resid;
+      a.ctl->t = t + 1;
+      a.ctl->prev_resid = resid;
+    }
+  }
+}
+
+__global__ void k_ftwiddle(float2* tw) {
+  const int t = threadIdx.x;
+  if (t < kFN) {
+    double s, c;
+    sincospi(-2.0 * t / kFN, &s, &c);
+    tw[t] = make_float2((float)c, (float)s);
+  }
+}
+
+__global__ void k_fbasis(float2* U, int n, int r) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * r;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int j = (int)(i / r), c = (int)(i % r);
+    U[i] = make_float2((j % r == c) ? 1.f : 0.f, 0.f);
+  }
+}
+
+// ---------------------------------------------------------------- launchers
+
+#define FR_SWITCH(R_, CALL)  \
+  switch (R_) {              \
+    case 2: CALL(2); break;  \
+    case 4: CALL(4); break;  \
+    case 6: CALL(6); break;  \
+    default: CALL(8); break; \
+  }
+
+static int fr_bucket(int r) { return r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 6 ? 6 : 8)); }
+
+hipError_t launch_fcol(const FColArgs& a, hipStream_t st) {
+  const size_t lds = fcol_lds_bytes(a.rho, a.r);
+  (void)hipGetLastError();
+#define FCOL_CALL(RR)                                                                                       \
+  {                                                                                                         \
+    static bool attr_set = false;   /* the LDS limit is raised once, before any graph capture */           \
+    if (!attr_set) {                                                                                        \
+      hipError_t e = hipFuncSetAttribute((const void*)k_fcol<RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                         (int)(163840));                                                    \
+      if (e != hipSuccess) return e;                                                                        \
+      attr_set = true;                                                                                      \
+    }                                                                                                       \
+    hipLaunchKernelGGL(k_fcol<RR>, dim3(a.q), dim3(kFThreads), lds, st, a);                                 \
+  }
+  FR_SWITCH(fr_bucket(a.r), FCOL_CALL)
+#undef FCOL_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_fu(const float2* U, int r, const float2* tw, float2* FU, hipStream_t st) {
+  const size_t lds = 8 * (size_t)(kFGrid + kFN);
+  (void)hipGetLastError();
+  static bool attr_set = false;   // raised once, before any graph capture
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_fu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_fu, dim3(r), dim3(kFThreads), lds, st, U, r, tw, FU);
+  return hipGetLastError();
+}
+
+hipError_t launch_fltu(const float2* H, const float2* U, int n, int q, int r, float2* Tc, const int* skip,
+                       hipStream_t st) {
+  (void)hipGetLastError();
+#define FLTU_CALL(RR) hipLaunchKernelGGL(k_fltu<RR>, dim3(q), dim3(kFThreads), 0, st, H, U, n, r, Tc, skip)
+  FR_SWITCH(fr_bucket(r), FLTU_CALL)
+#undef FLTU_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_fgrad(const float2* H, const float2* B, int n, int q, int r, float2* Gsum, const int* skip,
+                        hipStream_t st) {
+  (void)hipGetLastError();
+#define FGRAD_CALL(RR) \
+  hipLaunchKernelGGL(k_fgrad<RR>, dim3((n + 255) / 256), dim3(256), 0, st, H, B, n, q, r, Gsum, skip)
+  FR_SWITCH(fr_bucket(r), FGRAD_CALL)
+#undef FGRAD_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_fqr(const FQRArgs& a, hipStream_t st) {
+  (void)hipGetLastError();
+#define FQR_CALL(RR) hipLaunchKernelGGL(k_fqr<RR>, dim3(1), dim3(kFThreads), 0, st, a)
+  FR_SWITCH(fr_bucket(a.r), FQR_CALL)
+#undef FQR_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_ftwiddle(float2* tw, hipStream_t st) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_ftwiddle, dim3(1), dim3(128), 0, st, tw);
+  return hipGetLastError();
+}
+
+hipError_t launch_fbasis(float2* U, int n, int r, hipStream_t st) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_fbasis, dim3(64), dim3(256), 0, st, U, n, r);
+  return hipGetLastError();
+}
+
+}  // namespace altg

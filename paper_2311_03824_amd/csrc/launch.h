@@ -67,6 +67,56 @@ hipError_t launch_fill_basis(float* U, int n, int r, hipStream_t st);
 hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStream_t st);
 hipError_t launch_copy_i(int* dst, const int* src, long long count, hipStream_t st);
 
+// partial Fourier form (96 x 96 complex frames)
+constexpr int kFN = 96;                // 1D transform size
+constexpr int kFP = 97;                // LDS row stride of a frame (complex elements)
+constexpr int kFGrid = kFN * kFP;      // complex elements of a padded frame
+constexpr int kFThreads = 1024;        // workgroup of the Fourier kernels
+constexpr int kFWaves = kFThreads / 64;
+constexpr int kFRMax = 8;              // largest rank of the Fourier kernels
+constexpr int kFRhoMax = 256;          // largest rho of the Fourier column kernel
+enum { FCOL_INIT = 0, FCOL_GD = 1 };
+
+struct FColArgs {
+  int n, q, m, r, rho, tau, mode;
+  const int* mask;       // q x m frequency indices, ascending per frame
+  const float2* Y;       // y_k at Y[k * ldy]
+  long long ldy;
+  const float2* FU;      // n x r, the 2D DFT of U's columns (GD)
+  const float2* tw;      // 96 twiddles exp(-2 pi i t / 96)
+  int* Sidx;             // q x rho, in (GD) / out
+  float2* Sval;          // q x rho
+  float2* Bt;            // q x r (GD)
+  float2* H;             // q x n: L_0 columns (init) or A_k^H r_k (GD)
+  double* colrr;         // q: ||y_k||^2 (init) or ||r_k||^2 (GD)
+  int* flags;            // q
+};
+
+struct FQRArgs {
+  int n, r, q, mode;
+  const float2* G;       // n x r: grad_U f (GD) or L_0 L_0^H U (POWER)
+  float2* U;
+  float2* Uprev;
+  float2* Utmp;
+  Ctl* ctl;
+  double eta_c, power_tol;
+  const double* colrr;
+  const int* colflags;
+  double* rlog;
+  int rlog_len;
+};
+
+size_t fcol_lds_bytes(int rho, int r);
+hipError_t launch_fcol(const FColArgs& a, hipStream_t st);
+hipError_t launch_fu(const float2* U, int r, const float2* tw, float2* FU, hipStream_t st);
+hipError_t launch_fltu(const float2* H, const float2* U, int n, int q, int r, float2* Tc, const int* skip,
+                       hipStream_t st);
+hipError_t launch_fgrad(const float2* H, const float2* B, int n, int q, int r, float2* Gsum, const int* skip,
+                        hipStream_t st);
+hipError_t launch_fqr(const FQRArgs& a, hipStream_t st);
+hipError_t launch_ftwiddle(float2* tw, hipStream_t st);
+hipError_t launch_fbasis(float2* U, int n, int r, hipStream_t st);
+
 // synthetic instances on the device
 struct MeasureArgs {
   int n, q, m;

@@ -153,3 +153,24 @@ def test_op_scratch_bytes_is_host_only(lib):
     assert so.altgdmin_op_scratch_bytes(1000, 1000, 10, ctypes.byref(b)) == 0
     assert b.value >= 4 * 1000 * 10
     assert so.altgdmin_op_scratch_bytes(0, 1000, 10, ctypes.byref(b)) < 0
+
+
+def _fourier_problem(lib, **kw):
+    p = lib.Problem()
+    p.n, p.q, p.m, p.r, p.rho = 96 * 96, 64, 1536, 6, 184
+    p.n1 = p.n2 = 96
+    p.a_format = lib.ALTGDMIN_A_PFOURIER
+    p.fourier_mask, p.Y, p.ldy = 1 << 20, 1 << 24, 1536
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def test_fourier_workspace_and_limits(lib):
+    rc, b, _ = _ws(lib, _fourier_problem(lib))
+    assert rc == 0 and b >= 8 * 64 * 96 * 96     # holds the q x n complex back-projections
+    for kw, code in [(dict(n1=64, n2=144), -5), (dict(n2=95), -1), (dict(r=9), -5), (dict(rho=257), -5),
+                     (dict(m=2049, ldy=2049), -5), (dict(fourier_mask=None), -1), (dict(ldy=100), -1),
+                     (dict(m=9217), -1)]:
+        rc, _, msg = _ws(lib, _fourier_problem(lib, **kw))
+        assert rc == code, (kw, msg)
