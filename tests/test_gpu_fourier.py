@@ -1,12 +1,13 @@
 """Parity of the partial Fourier form (complex64 HIP path) against the complex FP64 oracle.
 
-Frames of 96 x 96; the GPU computes its 2D DFTs in FP32.  Tolerances:
-  * supports: identical on at least 95 % of the columns after the
-    initialisation IHT and after the GDmin iterations (the rest sit within FP32
-    resolution of a tie in modulus), values to 1e-4 relative on the shared ones;
-  * subspaces: ||(I - U1 U1^H) U2||_F <= 1e-4 after a few iterations from the
-    same U_0;
-  * the estimate X = U B + S: normwise relative difference <= 1e-4.
+Frames of 96 x 96; the GPU computes its 2D DFTs in FP32 (rounding error of a
+96-point transform about log2(96) 2^-24 relative).  Tolerances, each about ten
+times what these seeded instances show:
+  * supports: identical on every column after the initialisation IHT and after
+    the GDmin iterations; values to 1e-6 relative;
+  * subspaces: ||(I - U1 U1^H) U2||_F <= 5e-5 after a few iterations from the
+    same U_0 (about 5e-6 observed: the FP32 rounding of n r = 55 296 entries);
+  * the estimate X = U B + S: normwise relative difference <= 1e-6; eta to 1e-6.
 """
 import numpy as np
 import pytest
@@ -27,10 +28,6 @@ def torch():
     return _t
 
 
-def _support_agreement(a, b):
-    return np.mean([np.array_equal(x, y) for x, y in zip(a, b)])
-
-
 def _estimate(out):
     X = out["U"].astype(np.complex128) @ out["Bt"].T.astype(np.complex128)
     q = X.shape[1]
@@ -49,12 +46,10 @@ def test_init_iht_matches_oracle(lib, torch, q, m, r, rho):
     st = s.status()
     s.close()
     assert st["error_flags"] == 0
-    agree = _support_agreement(out["S_idx"], idx_ref)
-    assert agree >= 0.95, agree
+    assert np.array_equal(out["S_idx"], idx_ref)
     for k in range(q):
-        if np.array_equal(out["S_idx"][k], idx_ref[k]):
-            ref = S_ref[k, idx_ref[k]]
-            assert np.linalg.norm(out["S_val"][k] - ref) <= 1e-4 * np.linalg.norm(ref)
+        ref = S_ref[k, idx_ref[k]]
+        assert np.linalg.norm(out["S_val"][k] - ref) <= 1e-6 * np.linalg.norm(ref)
 
 
 @pytest.mark.parametrize("q,m,r,rho,iters", [(16, 1536, 6, 184, 4), (10, 1000, 4, 60, 3), (64, 1536, 6, 184, 2)])
@@ -73,12 +68,12 @@ def test_gdmin_trajectory_matches_oracle(lib, torch, q, m, r, rho, iters):
     rep = s.status()
     s.close()
     assert rep["iterations"] == iters and rep["error_flags"] == 0
-    assert rep["eta"] == pytest.approx(st.eta, rel=1e-4)
-    assert F.subspace_distance(out["U"].astype(np.complex128), st.U_fit) <= 1e-4
-    assert _support_agreement(out["S_idx"], st.idx) >= 0.95
+    assert rep["eta"] == pytest.approx(st.eta, rel=1e-6)
+    assert F.subspace_distance(out["U"].astype(np.complex128), st.U_fit) <= 5e-5
+    assert np.array_equal(out["S_idx"], st.idx)
     X_ref = F.estimate(st)
     X = _estimate(out)
-    assert np.linalg.norm(X - X_ref) <= 1e-4 * np.linalg.norm(X_ref)
+    assert np.linalg.norm(X - X_ref) <= 1e-6 * np.linalg.norm(X_ref)
     # the residual the kernels report is that of the consistent pair
     Bt = out["Bt"].astype(np.complex128)
     S = np.zeros((q, N * N), np.complex128)
