@@ -54,14 +54,22 @@ def au_kernel_bytes(n, q, m, r, a_bytes=4.0):
     return q * (m * n * a_bytes + 4 * m * r + 8 * r * r) + 4 * n * r
 
 
-def committed_traffic(kernel_src: str, profile: str):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
-    kernel source changed since the counters were taken (hash recorded in the summary)."""
+def source_hash(paths) -> str:
+    """First 16 hex digits of the SHA-256 of the concatenated sources of a kernel."""
     import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()[:16]
+
+
+def committed_traffic(kernel_srcs, profile: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or None when the
+    kernel sources changed since the counters were taken (hash recorded in the summary)."""
     import re
     try:
         txt = open(profile).read()
-        sha = hashlib.sha256(open(kernel_src, "rb").read()).hexdigest()[:16]
+        sha = source_hash(kernel_srcs)
         m_sha = re.search(r"source_sha256_16 \([^)]*\): ([0-9a-f]{16})", txt)
         m_tr = re.search(r"traffic_bytes_per_launch k_col: ([0-9]+)", txt)
         if m_sha and m_tr and m_sha.group(1) == sha:
@@ -338,7 +346,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "achieved": round(col_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(col_gbs / HBM_PEAK_GBS, 4),
                      "traffic": committed_traffic(
-                         os.path.join(ROOT, "paper_2311_03824_amd", "csrc", "k_column.hip"),
+                         [os.path.join(ROOT, "paper_2311_03824_amd", "csrc", f) for f in ("k_column.hip", "common.h")],
                          os.path.join(ROOT, "profiles", f"k_col_{WORKLOAD}_fp32.md")) if args.form == "fp32" else None,
                      "kernel": "k_col", "bytes_per_launch": int(col_bytes), "avg_ms": round(kms["k_col"], 4)},
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
