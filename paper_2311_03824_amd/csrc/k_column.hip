@@ -169,12 +169,13 @@ __device__ __forceinline__ double sumsq(const float4 (&v)[NC]) {
 // Streaming pass over A_k: gl[j] = A_j^T u for every column j; for j in the
 // support bitmap inT (if given) also wacc += gl[j] * A_j and gT2 += gl[j]^2.
 // Wave w takes columns j = w, w + 4, ...; groups of JU columns are loaded one
-// group ahead of the one being reduced.
+// group ahead of the one being reduced.  JU keeps about 4-6 float4 loads per
+// lane in flight (measured best: JU = 3 for one 256-row chunk, 1 for more).
 template <int FMT, int NC>
 __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
                                            int n, float* gl, const unsigned* inT, float4 (&wacc)[NC],
                                            double& gT2, int lane, int wave) {
-  constexpr int JU = 2;
+  constexpr int JU = NC == 1 ? 3 : 1;
   constexpr int step = kWaves * JU;
   // loads are unconditional (column clamped to n-1, chunk clamped to a legal
   // one) so that a whole group is in flight at once; consume() masks them
@@ -526,7 +527,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   // issued.  The rows of U this wave needs are staged 64 at a time in its own
   // LDS slice (lane t loads the row of the wave's t-th next column) and read back
   // as broadcast 16-byte LDS loads, so the FMAs take plain register operands.
-  constexpr int AUD = 4;
+  constexpr int AUD = 2;
   constexpr int RP = (R + 3) / 4 * 4;
   float* Uw = reinterpret_cast<float*>(smem + lay.P) + wave * 64 * RP;   // shares the P region
   const float* U = a.U;
