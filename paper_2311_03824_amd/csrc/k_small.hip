@@ -103,21 +103,33 @@ __global__ __launch_bounds__(256) void k_ltu(const float* __restrict__ L0t, cons
 }
 
 // C = X^T Y (r x r, FP64) over n rows of the n x r row-major X and Y; block-wide.
-__device__ void block_gram(const float* X, const float* Y, int n, int r, double* sh, double* C) {
-  const int tid = threadIdx.x;
-  const int E = r * r, parts = kQRThreads / E;
-  const int e = tid % E, p = tid / E;
-  double s = 0.0;
-  if (p < parts) {
-    const int ra = e / r, rb = e % r;
-    for (int j = p; j < n; j += parts) s = fma((double)X[(long long)j * r + ra], (double)Y[(long long)j * r + rb], s);
-  }
-  sh[tid] = s;
-  __syncthreads();
-  if (tid < E) {
-    double t = 0.0;
-    for (int pp = 0; pp < parts; ++pp) t += sh[pp * E + tid];
-    C[tid] = t;
+__device__ void block_gram(const float* X, const float* Y, int n, int r, double* C, bool sym) {
+  // C = X^T Y (r x r, FP64) over the n rows of X and Y (row-major n x r).  Wave
+  // w computes the entries e = w, w + 16, ... (with sym, the entries a <= b only,
+  // mirrored); its lanes stride over the rows and the 64 lane sums are added by
+  // the fixed DPP tree, so the result does not depend on timing.
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int E = sym ? r * (r + 1) / 2 : r * r;
+  for (int e = wave; e < E; e += kQRThreads / 64) {
+    int ra = 0, rb = 0;
+    if (sym) {
+      int base = 0;
+      while (e >= base + (r - ra)) {
+        base += r - ra;
+        ++ra;
+      }
+      rb = ra + (e - base);
+    } else {
+      ra = e / r;
+      rb = e - ra * r;
+    }
+    double s = 0.0;
+    for (int j = lane; j < n; j += 64) s = fma((double)X[(long long)j * r + ra], (double)Y[(long long)j * r + rb], s);
+    s = wave_sum_dpp(s);
+    if (lane == 0) {
+      C[ra * r + rb] = s;
+      if (sym) C[rb * r + ra] = s;
+    }
   }
   __syncthreads();
 }
@@ -187,9 +199,9 @@ __device__ bool wave_cholesky(double* W, double* rdiag, int r) {
 
 // X (n x r, in place) <- X R^{-1} where X^T X = R^T R (R upper, positive diagonal).
 // Returns false if the Gram matrix is not positive definite.
-__device__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W, double* rdiag, int* okflag) {
+__device__ __forceinline__ bool block_cholqr_pass(float* X, int n, int r, double* sh, double* W, double* rdiag, int* okflag) {
   const int tid = threadIdx.x;
-  block_gram(X, X, n, r, sh, W);
+  block_gram(X, X, n, r, W, true);
   if (tid < 64) {
     const bool ok = wave_cholesky(W, rdiag, r);
     if (tid == 0) *okflag = ok ? 1 : 0;
@@ -227,7 +239,7 @@ struct QRShared {
   int okflag;
 };
 
-__device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
+__device__ __forceinline__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
   double* sh = S.sh;
   double* W = S.W;
   double* Lf = S.Lf;
@@ -240,11 +252,27 @@ __device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
   float* X = a.lds ? reinterpret_cast<float*>(dsm) : a.Utmp;
 
   if (a.mode != QR_ORTH) {
-    for (int idx = tid; idx < nr; idx += kQRThreads) {
-      float s = a.gpart[idx];
-      for (int ks = 1; ks < a.KS; ++ks) s += a.gpart[(long long)ks * nr + idx];
-      X[idx] = s;
-      if (a.grad_out) a.grad_out[idx] = s;
+    if ((nr & 3) == 0) {   // float4 loads; the same per-element order as below
+      const int nr4 = nr >> 2;
+      for (int i4 = tid; i4 < nr4; i4 += kQRThreads) {
+        float4 s = reinterpret_cast<const float4*>(a.gpart)[i4];
+        for (int ks = 1; ks < a.KS; ++ks) {
+          const float4 t = reinterpret_cast<const float4*>(a.gpart + (long long)ks * nr)[i4];
+          s.x += t.x; s.y += t.y; s.z += t.z; s.w += t.w;
+        }
+        reinterpret_cast<float4*>(X)[i4] = s;
+        if (a.grad_out) {
+          a.grad_out[4 * i4] = s.x; a.grad_out[4 * i4 + 1] = s.y;
+          a.grad_out[4 * i4 + 2] = s.z; a.grad_out[4 * i4 + 3] = s.w;
+        }
+      }
+    } else {
+      for (int idx = tid; idx < nr; idx += kQRThreads) {
+        float s = a.gpart[idx];
+        for (int ks = 1; ks < a.KS; ++ks) s += a.gpart[(long long)ks * nr + idx];
+        X[idx] = s;
+        if (a.grad_out) a.grad_out[idx] = s;
+      }
     }
   } else if (a.lds) {
     for (int idx = tid; idx < nr; idx += kQRThreads) X[idx] = a.Utmp[idx];
@@ -253,7 +281,7 @@ __device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
   if (a.mode == QR_GD) {
     const bool have = a.ctl ? (a.ctl->eta_set != 0) : (*a.eta_io > 0.0);
     if (!have) {
-      block_gram(X, X, n, r, sh, W);
+      block_gram(X, X, n, r, W, true);
       if (tid == 0) {
         const double lam = jacobi_max_eig(W, r);
         const double eta = lam > 0.0 ? a.eta_c / sqrt(lam) : 0.0;
@@ -281,7 +309,7 @@ __device__ void qr_body(const QRArgs& a, unsigned char* dsm, QRShared& S) {
     return;
   }
   if (a.mode == QR_POWER) {
-    block_gram(a.U, X, n, r, sh, W);   // U_old^T U_new
+    block_gram(a.U, X, n, r, W, false);   // U_old^T U_new
     if (tid == 0) {
       double f = 0.0;
       for (int e = 0; e < r * r; ++e) f += W[e] * W[e];
