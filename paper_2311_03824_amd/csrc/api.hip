@@ -85,6 +85,8 @@ struct altgdmin_handle {
   // gradient or L_0 L_0^H U), U, Uprev, Utmp and Tpow hold complex values there
   float* FU = nullptr;     // n x r: the 2D DFT of U's columns
   float* tw = nullptr;     // 96 twiddles
+  double* fpart = nullptr; // per-256-row-block partial Grams of the GD update
+  double* frinv = nullptr; // R1^{-1}, R2^{-1} of the GD update
   bool hi_phase = false;   // BF16X2 with a hi-only phase
   bool have_graph = false;
   hipGraph_t graph = nullptr;
@@ -116,6 +118,8 @@ size_t carve_fourier(altgdmin_handle* h, void* base) {
   h->Utmp = c.take<float>(2 * n * r);
   h->Tpow = c.take<float>(2 * q * r);
   h->tw = c.take<float>(2 * kFN);
+  h->fpart = c.take<double>(2 * 3 * r * r * ((n + 255) / 256));
+  h->frinv = c.take<double>(2 * 2 * r * r);
   h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
   h->rlog = c.take<double>(h->rlog_len);
   return (c.off + kAlign - 1) / kAlign * kAlign;
@@ -255,6 +259,9 @@ FQRArgs fqr_args(const altgdmin_handle* h, int mode) {
   a.colflags = h->colflags;
   a.rlog = h->rlog;
   a.rlog_len = h->rlog_len;
+  a.part = reinterpret_cast<double2*>(h->fpart);
+  a.rinv = reinterpret_cast<double2*>(h->frinv);
+  a.nb = (h->prob.n + 255) / 256;
   return a;
 }
 
@@ -267,8 +274,10 @@ hipError_t fourier_launch(altgdmin_handle* h, int which, hipStream_t st) {
   switch (which) {
     case 0: return launch_fu(CF2(h->U), p.r, CF2(h->tw), F2(h->FU), st);
     case 1: return launch_fcol(fcol_args(h, FCOL_GD), st);
-    case 2: return launch_fgrad(CF2(h->H), CF2(h->Bt), p.n, p.q, p.r, F2(h->gpart), nullptr, st);
-    default: return launch_fqr(fqr_args(h, QR_GD), st);
+    case 2:
+      return launch_fgrad_gd(CF2(h->H), CF2(h->Bt), CF2(h->U), p.n, p.q, p.r, F2(h->gpart),
+                             reinterpret_cast<double2*>(h->fpart), st);
+    default: return launch_fqr_gd(fqr_args(h, QR_GD), st);
   }
 }
 

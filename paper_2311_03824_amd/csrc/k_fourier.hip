@@ -700,28 +700,44 @@ __device__ double jacobi_lmax(double* A, int N) {
   return l;
 }
 
-// W (r x r, complex FP64) = X^H Y over the n rows (workgroup sum, fixed order).
+// W (r x r, complex FP64) = X^H Y over the n rows.  Wave w computes the entries
+// e = w, w + 16, ... (with sym, the entries a <= b only, the others by
+// conjugation); its lanes stride over the rows and the lane sums are added by
+// the fixed DPP tree.  Ends with a barrier.
 template <int R>
-__device__ void fgram(const float2* X, const float2* Y, int n, int r, double* red, double* out, double2* W) {
-  const int tid = threadIdx.x;
-  for (int ra = 0; ra < r; ++ra) {
-    double v[2 * R];
-#pragma unroll
-    for (int i = 0; i < 2 * R; ++i) v[i] = 0.0;
-    for (int j = tid; j < n; j += kFThreads) {
-      const float2 x = X[(long long)j * r + ra];
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-        if (c < r) {
-          const float2 y = Y[(long long)j * r + c];
-          v[2 * c] += (double)x.x * y.x + (double)x.y * y.y;
-          v[2 * c + 1] += (double)x.x * y.y - (double)x.y * y.x;
-        }
+__device__ void fgram(const float2* X, const float2* Y, int n, int r, double* red, double* out, double2* W,
+                      bool sym = true) {
+  (void)red;
+  (void)out;
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int E = sym ? r * (r + 1) / 2 : r * r;
+  for (int e = wave; e < E; e += kFWaves) {
+    int ra = 0, rb = 0;
+    if (sym) {
+      int base = 0;
+      while (e >= base + (r - ra)) {
+        base += r - ra;
+        ++ra;
+      }
+      rb = ra + (e - base);
+    } else {
+      ra = e / r;
+      rb = e - ra * r;
     }
-    fblock_sum<2 * R>(v, red, out);
-    if (tid < r) W[ra * r + tid] = make_double2(out[2 * tid], out[2 * tid + 1]);
-    __syncthreads();
+    double sr = 0.0, si = 0.0;
+    for (int j = lane; j < n; j += 64) {   // conj(X[j][ra]) Y[j][rb]
+      const float2 x = X[(long long)j * r + ra], y = Y[(long long)j * r + rb];
+      sr = fma((double)x.x, (double)y.x, fma((double)x.y, (double)y.y, sr));
+      si = fma((double)x.x, (double)y.y, fma(-(double)x.y, (double)y.x, si));
+    }
+    sr = wave_sum_dpp(sr);
+    si = wave_sum_dpp(si);
+    if (lane == 0) {
+      W[ra * r + rb] = make_double2(sr, si);
+      if (sym) W[rb * r + ra] = make_double2(sr, -si);
+    }
   }
+  __syncthreads();
 }
 
 // One CholeskyQR pass on X (n x r in global memory): X <- X R^{-1}, R = L^H from
@@ -835,7 +851,7 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
     return;
   }
   if (a.mode == QR_POWER) {
-    fgram<R>(a.U, X, n, r, red, out, W);   // U_old^H U_new
+    fgram<R>(a.U, X, n, r, red, out, W, false);   // U_old^H U_new
     if (tid == 0) {
       double f = 0.0;
       for (int e = 0; e < r * r; ++e) f += W[e].x * W[e].x + W[e].y * W[e].y;
@@ -886,6 +902,288 @@ __global__ void k_fbasis(float2* U, int n, int r) {
     const int j = (int)(i / r), c = (int)(i % r);
     U[i] = make_float2((j % r == c) ? 1.f : 0.f, 0.f);
   }
+}
+
+// ---------------------------------------------------------------- GD update over many workgroups
+//
+// The projected GD step U+ = QR(U - eta grad) of Alg. 1 for the Fourier form,
+// split so that the n x r arrays are streamed by many CUs:
+//   k_fgrad_gd : rows of grad (as k_fgrad) and, per 256-row block, the partial
+//                Grams U^H U, U^H G, G^H G (wave per entry, lanes over rows);
+//   k_fqr_a    : one workgroup: sums the partials in block order, eta at t = 1,
+//                the Gram of X = U - eta G by expansion, its Cholesky factor and
+//                R1^{-1}; the residual and the iteration counter;
+//   k_fqr_b    : X = (U - eta G) R1^{-1} row by row, partial Grams of X;
+//   k_fqr_c    : one workgroup: R2^{-1} from the Gram of X;
+//   k_fqr_d    : U_prev = U, U = X R2^{-1}.
+// CholeskyQR2 as in k_fqr, with the first Gram taken from the expansion
+// U^H U - eta (U^H G + G^H U) + eta^2 G^H G of the unrounded U - eta G.
+
+namespace {
+
+// Partial Gram of the 256 LDS rows Xl, Yl (rows x r complex): dst[a * r + b] =
+// sum_rows conj(X[a]) Y[b]; waves take entries w, w + 4, ...; with sym only
+// a <= b are summed and the rest mirrored.
+__device__ void rows_gram(const float2* Xl, const float2* Yl, int r, bool sym, double2* dst) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int E = sym ? r * (r + 1) / 2 : r * r;
+  for (int e = wave; e < E; e += 4) {
+    int ra = 0, rb = 0;
+    if (sym) {
+      int base = 0;
+      while (e >= base + (r - ra)) {
+        base += r - ra;
+        ++ra;
+      }
+      rb = ra + (e - base);
+    } else {
+      ra = e / r;
+      rb = e - ra * r;
+    }
+    double sr = 0.0, si = 0.0;
+    for (int j = lane; j < 256; j += 64) {
+      const float2 x = Xl[j * r + ra], y = Yl[j * r + rb];
+      sr = fma((double)x.x, (double)y.x, fma((double)x.y, (double)y.y, sr));
+      si = fma((double)x.x, (double)y.y, fma(-(double)x.y, (double)y.x, si));
+    }
+    sr = wave_sum_dpp(sr);
+    si = wave_sum_dpp(si);
+    if (lane == 0) {
+      dst[ra * r + rb] = make_double2(sr, si);
+      if (sym) dst[rb * r + ra] = make_double2(sr, -si);
+    }
+  }
+}
+
+// Cholesky W = L L^H (complex r x r, thread 0) and Rinv = (L^H)^{-1} (upper
+// triangular) written to dst; false if a pivot is not positive.
+__device__ bool chol_rinv_c(const double2* W, double2* L, double2* dst, int r) {
+  for (int j = 0; j < r; ++j) {
+    double s = W[j * r + j].x;
+    for (int p = 0; p < j; ++p) s -= L[j * r + p].x * L[j * r + p].x + L[j * r + p].y * L[j * r + p].y;
+    if (!(s > 0.0)) return false;
+    const double d = sqrt(s);
+    L[j * r + j] = make_double2(d, 0.0);
+    for (int i = j + 1; i < r; ++i) {
+      double tr = W[i * r + j].x, ti = W[i * r + j].y;
+      for (int p = 0; p < j; ++p) {   // - L[i][p] conj(L[j][p])
+        const double2 a = L[i * r + p], b = L[j * r + p];
+        tr -= a.x * b.x + a.y * b.y;
+        ti -= a.y * b.x - a.x * b.y;
+      }
+      L[i * r + j] = make_double2(tr / d, ti / d);
+    }
+  }
+  // M = L^{-1} (lower) column by column; Rinv = M^H: Rinv[a][c] = conj(M[c][a])
+  for (int c = 0; c < r; ++c)
+    for (int i = 0; i < r; ++i) {
+      double mr = 0.0, mi = 0.0;
+      if (i >= c) {
+        mr = (i == c) ? 1.0 : 0.0;
+        for (int p = c; p < i; ++p) {   // - L[i][p] M[p][c]
+          const double2 a = L[i * r + p], m = dst[c * r + p];   // dst holds M^H so far: M[p][c] = conj(dst[c][p])
+          const double pr = m.x, pi = -m.y;
+          mr -= a.x * pr - a.y * pi;
+          mi -= a.x * pi + a.y * pr;
+        }
+        const double dd = L[i * r + i].x;
+        mr /= dd;
+        mi /= dd;
+      }
+      dst[c * r + i] = make_double2(mr, -mi);   // Rinv[c][i] = conj(M[i][c])
+    }
+  return true;
+}
+
+}  // namespace
+
+template <int R>
+__global__ __launch_bounds__(256) void k_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q, int r,
+                                                  float2* Gsum, double2* part) {
+  __shared__ float2 Ul[256 * kFRMax], Gl[256 * kFRMax];
+  const int tid = threadIdx.x, j = blockIdx.x * 256 + tid;
+  float2 acc[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) acc[c] = make_float2(0.f, 0.f);
+  if (j < n)
+    for (int k = 0; k < q; ++k) {
+      const float2 h = H[(long long)k * n + j];
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (c < r) {
+          const float2 b = B[(long long)k * r + c];
+          acc[c].x = fmaf(h.x, b.x, fmaf(h.y, b.y, acc[c].x));
+          acc[c].y = fmaf(h.y, b.x, fmaf(-h.x, b.y, acc[c].y));
+        }
+    }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    if (c < r) {
+      const bool in = j < n;
+      if (in) Gsum[(long long)j * r + c] = acc[c];
+      Gl[tid * r + c] = in ? acc[c] : make_float2(0.f, 0.f);
+      Ul[tid * r + c] = in ? U[(long long)j * r + c] : make_float2(0.f, 0.f);
+    }
+  __syncthreads();
+  double2* slot = part + (long long)blockIdx.x * 3 * r * r;
+  rows_gram(Ul, Ul, r, true, slot);
+  rows_gram(Ul, Gl, r, false, slot + r * r);
+  rows_gram(Gl, Gl, r, true, slot + 2 * r * r);
+}
+
+__global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
+  __shared__ double2 S[3 * kFRMax * kFRMax], Lm[kFRMax * kFRMax];
+  __shared__ double Mr[4 * kFRMax * kFRMax];
+  __shared__ double red[4];
+  __shared__ double eta_s;
+  const int tid = threadIdx.x, r = a.r, rr = r * r;
+  for (int e = tid; e < 3 * rr; e += 256) {
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < a.nb; ++b) {
+      const double2 v = a.part[(long long)b * 3 * rr + e];
+      sr += v.x;
+      si += v.y;
+    }
+    S[e] = make_double2(sr, si);
+  }
+  __syncthreads();
+  const double2* UU = S;
+  const double2* UG = S + rr;
+  const double2* GG = S + 2 * rr;
+  if (tid == 0) {
+    double eta;
+    if (!a.ctl->eta_set) {
+      const int N = 2 * r;   // Hermitian GG = A + iB -> real symmetric [[A, -B], [B, A]]
+      for (int i = 0; i < r; ++i)
+        for (int jj = 0; jj < r; ++jj) {
+          const double2 w = GG[i * r + jj];
+          Mr[i * N + jj] = w.x;
+          Mr[(i + r) * N + jj + r] = w.x;
+          Mr[i * N + jj + r] = -w.y;
+          Mr[(i + r) * N + jj] = w.y;
+        }
+      const double lam = jacobi_lmax(Mr, N);
+      eta = lam > 0.0 ? a.eta_c / sqrt(lam) : 0.0;
+      a.ctl->eta = eta;
+      a.ctl->eta_set = 1;
+    } else {
+      eta = a.ctl->eta;
+    }
+    eta_s = eta;
+    // Gram of X = U - eta G: UU - eta (UG + UG^H) + eta^2 GG
+    double2* W = reinterpret_cast<double2*>(Mr);
+    for (int i = 0; i < r; ++i)
+      for (int jj = 0; jj < r; ++jj) {
+        const double2 uu = UU[i * r + jj], ug = UG[i * r + jj], gu = UG[jj * r + i], gg = GG[i * r + jj];
+        W[i * r + jj] = make_double2(uu.x - eta * (ug.x + gu.x) + eta * eta * gg.x,
+                                     uu.y - eta * (ug.y - gu.y) + eta * eta * gg.y);
+      }
+    if (!chol_rinv_c(W, Lm, a.rinv, r)) {
+      a.ctl->err |= 2;
+      for (int e = 0; e < rr; ++e) a.rinv[e] = make_double2((e % (r + 1) == 0) ? 1.0 : 0.0, 0.0);
+    }
+  }
+  // the residual of the iteration (colrr in column order) and the counters
+  double s = 0.0;
+  int fl = 0;
+  for (int k = tid; k < a.q; k += 256) {
+    s += a.colrr[k];
+    fl |= a.colflags[k];
+  }
+  s = wave_sum_dpp(s);
+  if ((tid & 63) == 0) red[tid >> 6] = s;
+  if (fl) atomicOr(&a.ctl->err, fl);
+  __syncthreads();
+  if (tid == 0) {
+    const double ss = (red[0] + red[1]) + (red[2] + red[3]);
+    const double resid = a.ctl->ynorm2 > 0.0 ? sqrt(ss / a.ctl->ynorm2) : sqrt(ss);
+    const int t = a.ctl->t;
+    if (a.rlog && t < a.rlog_len) a.rlog[t] = resid;
+    a.ctl->resid = resid;
+    a.ctl->t = t + 1;
+    a.ctl->prev_resid = resid;
+  }
+}
+
+// X = (U - eta G) R1^{-1} (FP64 per row, stored FP32) and the partial Grams of X.
+template <int R>
+__global__ __launch_bounds__(256) void k_fqr_b(FQRArgs a) {
+  __shared__ float2 Xl[256 * kFRMax];
+  const int tid = threadIdx.x, j = blockIdx.x * 256 + tid, r = a.r;
+  const double eta = a.ctl->eta;
+  double2 x[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    x[c] = make_double2(0.0, 0.0);
+    if (c < r && j < a.n) {
+      const float2 u = a.U[(long long)j * r + c], g = a.G[(long long)j * r + c];
+      x[c] = make_double2(fma(-eta, (double)g.x, (double)u.x), fma(-eta, (double)g.y, (double)u.y));
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    if (c < r) {
+      double tr = 0.0, ti = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < R; ++aa)
+        if (aa <= c) {   // x[aa] Rinv[aa][c]
+          const double2 m = a.rinv[aa * r + c];
+          tr += x[aa].x * m.x - x[aa].y * m.y;
+          ti += x[aa].x * m.y + x[aa].y * m.x;
+        }
+      const float2 v = make_float2((float)tr, (float)ti);
+      if (j < a.n) a.Utmp[(long long)j * r + c] = v;
+      Xl[tid * r + c] = j < a.n ? v : make_float2(0.f, 0.f);
+    }
+  __syncthreads();
+  rows_gram(Xl, Xl, r, true, a.part + (long long)blockIdx.x * r * r);
+}
+
+__global__ __launch_bounds__(256) void k_fqr_c(FQRArgs a) {
+  __shared__ double2 W[kFRMax * kFRMax], Lm[kFRMax * kFRMax];
+  const int tid = threadIdx.x, rr = a.r * a.r;
+  for (int e = tid; e < rr; e += 256) {
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < a.nb; ++b) {
+      const double2 v = a.part[(long long)b * rr + e];
+      sr += v.x;
+      si += v.y;
+    }
+    W[e] = make_double2(sr, si);
+  }
+  __syncthreads();
+  if (tid == 0 && !chol_rinv_c(W, Lm, a.rinv + rr, a.r)) {
+    a.ctl->err |= 2;
+    for (int e = 0; e < rr; ++e) a.rinv[rr + e] = make_double2((e % (a.r + 1) == 0) ? 1.0 : 0.0, 0.0);
+  }
+}
+
+// U_prev = U; U = X R2^{-1}.
+template <int R>
+__global__ __launch_bounds__(256) void k_fqr_d(FQRArgs a) {
+  const int j = blockIdx.x * 256 + threadIdx.x, r = a.r;
+  if (j >= a.n) return;
+  const double2* Ri = a.rinv + r * r;
+  double2 x[R];
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    const float2 v = c < r ? a.Utmp[(long long)j * r + c] : make_float2(0.f, 0.f);
+    x[c] = make_double2(v.x, v.y);
+  }
+#pragma unroll
+  for (int c = 0; c < R; ++c)
+    if (c < r) {
+      double tr = 0.0, ti = 0.0;
+#pragma unroll
+      for (int aa = 0; aa < R; ++aa)
+        if (aa <= c) {
+          const double2 m = Ri[aa * r + c];
+          tr += x[aa].x * m.x - x[aa].y * m.y;
+          ti += x[aa].x * m.y + x[aa].y * m.x;
+        }
+      a.Uprev[(long long)j * r + c] = a.U[(long long)j * r + c];
+      a.U[(long long)j * r + c] = make_float2((float)tr, (float)ti);
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -956,6 +1254,30 @@ hipError_t launch_fqr(const FQRArgs& a, hipStream_t st) {
 #define FQR_CALL(RR) hipLaunchKernelGGL(k_fqr<RR>, dim3(1), dim3(kFThreads), 0, st, a)
   FR_SWITCH(fr_bucket(a.r), FQR_CALL)
 #undef FQR_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q, int r, float2* Gsum,
+                           double2* part, hipStream_t st) {
+  (void)hipGetLastError();
+#define FGD_CALL(RR) \
+  hipLaunchKernelGGL(k_fgrad_gd<RR>, dim3((n + 255) / 256), dim3(256), 0, st, H, B, U, n, q, r, Gsum, part)
+  FR_SWITCH(fr_bucket(r), FGD_CALL)
+#undef FGD_CALL
+  return hipGetLastError();
+}
+
+hipError_t launch_fqr_gd(const FQRArgs& a, hipStream_t st) {
+  const int nb = (a.n + 255) / 256;
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_fqr_a, dim3(1), dim3(256), 0, st, a);
+#define FQB_CALL(RR) hipLaunchKernelGGL(k_fqr_b<RR>, dim3(nb), dim3(256), 0, st, a)
+  FR_SWITCH(fr_bucket(a.r), FQB_CALL)
+#undef FQB_CALL
+  hipLaunchKernelGGL(k_fqr_c, dim3(1), dim3(256), 0, st, a);
+#define FQD_CALL(RR) hipLaunchKernelGGL(k_fqr_d<RR>, dim3(nb), dim3(256), 0, st, a)
+  FR_SWITCH(fr_bucket(a.r), FQD_CALL)
+#undef FQD_CALL
   return hipGetLastError();
 }
 
