@@ -312,9 +312,9 @@ struct FColLayout {
     gridA = o; o = align16(o + 8 * (size_t)kFGrid);
     gridB = o; o = align16(o + 8 * (size_t)kFGrid);
     tw = o;    o = align16(o + 8 * (size_t)kFN);
-    red = o;   o = align16(o + 8 * (size_t)kFWaves * 2 * kFRMax);
+    red = o;   o = align16(o + 8 * (size_t)kFWaves * (2 * kFRMax + 2));
     gi = o;    o = align16(o + 16 * (size_t)r * r);
-    dsum = o;  o = align16(o + 8 * (size_t)2 * kFRMax);
+    dsum = o;  o = align16(o + 8 * (size_t)(2 * kFRMax + 2));
     sidx = o;  o = align16(o + 4 * (size_t)rho);
     sval = o;  o = align16(o + 8 * (size_t)rho);
     gT = o;    o = align16(o + 8 * (size_t)rho);
@@ -374,33 +374,51 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     }
   __syncthreads();
 
-  // G_k = P_k^H P_k (FP64) and its inverse
+  // G_k = P_k^H P_k (FP64) and its inverse.  The rows of P_k are staged in the
+  // two grids (free at this point); wave w sums the entries w, w + 16, ... of
+  // the upper triangle with its lanes over the rows (fixed DPP order).
   if (gd) {
-    double2* Gl = reinterpret_cast<double2*>(gB);              // scratch: gridB is free here
-    double2* Ll = Gl + kFRMax * kFRMax;
-    double2* Yl = Ll + kFRMax * kFRMax;
+    constexpr int PS = R + 1;   // LDS row stride of P_k (complex values)
+    float2* Pl = gA;
 #pragma unroll
-    for (int ra = 0; ra < R; ++ra) {
-      if (ra < r) {   // row ra of G: conj(P[i][ra]) P[i][c], summed over the rows i
-        double v[2 * R];
+    for (int e = 0; e < 2; ++e) {
+      const int i = tid + kFThreads * e;
+      if (i < m) {
+        float2 p[R];
+        Prow(e, p);
 #pragma unroll
-        for (int c = 0; c < 2 * R; ++c) v[c] = 0.0;
-#pragma unroll
-        for (int e = 0; e < 2; ++e) {
-          float2 p[R];
-          Prow(e, p);
-#pragma unroll
-          for (int c = 0; c < R; ++c) {
-            const float2 pa = p[ra], pc = p[c];
-            v[2 * c] += (double)pa.x * pc.x + (double)pa.y * pc.y;
-            v[2 * c + 1] += (double)pa.x * pc.y - (double)pa.y * pc.x;
-          }
-        }
-        fblock_sum<2 * R>(v, red, dsum);
-        if (tid < r) Gl[ra * r + tid] = make_double2(dsum[2 * tid], dsum[2 * tid + 1]);
-        __syncthreads();
+        for (int c = 0; c < R; ++c) Pl[i * PS + c] = p[c];
       }
     }
+    __syncthreads();
+    double2* Gl = reinterpret_cast<double2*>(red);   // r x r
+    {
+      const int lane = tid & 63, wave = wave_id();
+      const int E = r * (r + 1) / 2;
+      for (int e = wave; e < E; e += kFWaves) {
+        int ra = 0, base = 0;
+        while (e >= base + (r - ra)) {
+          base += r - ra;
+          ++ra;
+        }
+        const int rb = ra + (e - base);
+        double sr = 0.0, si = 0.0;
+        for (int i = lane; i < m; i += 64) {   // conj(P[i][ra]) P[i][rb]
+          const float2 pa = Pl[i * PS + ra], pb = Pl[i * PS + rb];
+          sr = fma((double)pa.x, (double)pb.x, fma((double)pa.y, (double)pb.y, sr));
+          si = fma((double)pa.x, (double)pb.y, fma(-(double)pa.y, (double)pb.x, si));
+        }
+        sr = wave_sum_dpp(sr);
+        si = wave_sum_dpp(si);
+        if (lane == 0) {
+          Gl[ra * r + rb] = make_double2(sr, si);
+          Gl[rb * r + ra] = make_double2(sr, -si);
+        }
+      }
+    }
+    __syncthreads();
+    double2* Ll = reinterpret_cast<double2*>(gB);   // the staged rows are no longer needed
+    double2* Yl = Ll + kFRMax * kFRMax;
     if (!fblock_chol_inverse(Gl, Ll, Gi, Yl, r)) flags |= 2;
   }
 
@@ -495,19 +513,54 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
       for (int e = tid; e < rho; e += kFThreads) sval[e] = make_float2(0.f, 0.f);
       __syncthreads();
     }
-    for (int e = tid; e < rho; e += kFThreads) gT[e] = gA[fpos(sidx[e])];
-    double gg;
-    {
-      double s[1] = {0.0};
-      for (int e = tid; e < rho; e += kFThreads) s[0] += (double)gT[e].x * gT[e].x + (double)gT[e].y * gT[e].y;
-      fblock_sum<1>(s, red, dsum);
-      gg = dsum[0];
+    double gg_part = 0.0;
+    for (int e = tid; e < rho; e += kFThreads) {
+      const float2 g = gA[fpos(sidx[e])];
+      gT[e] = g;
+      gg_part += (double)g.x * g.x + (double)g.y * g.y;
     }
-    // w = M g_T
+    // w = M g_T: only ||w||^2 is needed.  With the projector, ||Pi w||^2 =
+    // ||w||^2 - Re(c^H G^{-1} c) with c = P_k^H w, one reduction together with
+    // ||g_T||^2.
     float2 w[2];
     apply_sparse(sidx, gT, rho, w);
-    if (gd) project(w);
-    const double ww = sum_sq(w);
+    double gg, ww;
+    {
+      double v[2 * R + 2];
+#pragma unroll
+      for (int cc = 0; cc < 2 * R + 2; ++cc) v[cc] = 0.0;
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        v[2 * R] += (double)w[e].x * w[e].x + (double)w[e].y * w[e].y;
+        if (gd) {
+          float2 p[R];
+          Prow(e, p);
+#pragma unroll
+          for (int cc = 0; cc < R; ++cc) {
+            v[2 * cc] += (double)p[cc].x * w[e].x + (double)p[cc].y * w[e].y;
+            v[2 * cc + 1] += (double)p[cc].x * w[e].y - (double)p[cc].y * w[e].x;
+          }
+        }
+      }
+      v[2 * R + 1] = gg_part;
+      fblock_sum<2 * R + 2>(v, red, dsum);
+      gg = dsum[2 * R + 1];
+      ww = dsum[2 * R];
+      if (gd) {
+        double q = 0.0;   // Re(c^H G^{-1} c)
+        for (int ra = 0; ra < r; ++ra) {
+          double dr = 0.0, di = 0.0;
+          for (int cb = 0; cb < r; ++cb) {
+            const double2 g = Gi[ra * r + cb];
+            const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
+            dr += g.x * xr - g.y * xi;
+            di += g.x * xi + g.y * xr;
+          }
+          q += dsum[2 * ra] * dr + dsum[2 * ra + 1] * di;
+        }
+        ww = fmax(ww - q, 0.0);
+      }
+    }
     const bool okmu = ww > 0.0 && isfinite(ww) && isfinite(gg);
     const float mu = okmu ? (float)(gg / ww) : 0.f;
     // v = s - mu g in grid A, then HardThreshold
@@ -534,9 +587,9 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
   float2* Hk = a.H + (long long)k * n;
   if (gd) {
     // b_k = G_k^{-1} P_k^H e_k; r_k = P_k b_k - e_k; h_k = A_k^H r_k
-    double c[2 * R];
+    double c[2 * R + 1];
 #pragma unroll
-    for (int cc = 0; cc < 2 * R; ++cc) c[cc] = 0.0;
+    for (int cc = 0; cc < 2 * R + 1; ++cc) c[cc] = 0.0;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       float2 p[R];
@@ -546,8 +599,9 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
         c[2 * cc] += (double)p[cc].x * ev[e].x + (double)p[cc].y * ev[e].y;
         c[2 * cc + 1] += (double)p[cc].x * ev[e].y - (double)p[cc].y * ev[e].x;
       }
+      c[2 * R] += (double)ev[e].x * ev[e].x + (double)ev[e].y * ev[e].y;
     }
-    fblock_sum<2 * R>(c, red, dsum);
+    fblock_sum<2 * R + 1>(c, red, dsum);
     float2 b[R];
 #pragma unroll
     for (int ra = 0; ra < R; ++ra) {
@@ -568,6 +622,21 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
         if (ra == tid) bo = b[ra];
       a.Bt[(long long)k * r + tid] = bo;
     }
+    // ||r_k||^2 = ||e_k||^2 - Re(c^H b_k), since G_k b_k = c = P_k^H e_k
+    double cb_re = 0.0;
+    for (int ra = 0; ra < r; ++ra) {
+      double br = 0.0, bi = 0.0;
+      for (int cb = 0; cb < r; ++cb) {
+        const double2 g = Gi[ra * r + cb];
+        const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
+        br += g.x * xr - g.y * xi;
+        bi += g.x * xi + g.y * xr;
+      }
+      cb_re += dsum[2 * ra] * br + dsum[2 * ra + 1] * bi;
+    }
+    const double rr = fmax(dsum[2 * R] - cb_re, 0.0);
+    if (tid == 0) a.colrr[k] = rr;
+    __syncthreads();   // dsum is read above by every thread
     float2 rv[2];
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
@@ -578,8 +647,6 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
       for (int ra = 0; ra < R; ++ra) s = c_add(s, c_mul(p[ra], b[ra]));
       rv[e] = ok[e] ? s : make_float2(0.f, 0.f);
     }
-    const double rr = sum_sq(rv);
-    if (tid == 0) a.colrr[k] = rr;
     apply_adj(rv);
   } else {
     // initialisation: ||y_k||^2 and the column A_k^H (y_k - A_k s_k) of L_0
