@@ -243,6 +243,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=128,
                     help="requests of the mixed-size serving run (0: skip); arrival rate = 0.8 x closed-loop rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0, help="HBM admission budget of the serving run")
+    ap.add_argument("--only", choices=["fourier", "serve"],
+                    help="run only the Fourier form or only the serving run and print its JSON (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run torch's copy kernel on a 1.6 GB FP32 buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -271,6 +273,14 @@ def main() -> int:
                           "copy_calibration_bytes_written": dst.numel() * 4, "launches": 3}), flush=True)
         return 0
     lib.load()
+    if args.only == "fourier":
+        print(json.dumps({"fourier_form": fourier_form(lib, torch, np)}), flush=True)
+        return 0
+    if args.only == "serve":
+        from paper_2311_03824_amd import serve
+        out = serve.serve(count=args.serve_requests, budget_gib=args.serve_budget_gib, log=log)
+        print(json.dumps({"serving": out}), flush=True)
+        return 0
     cfg = dict(I.WORKLOADS[WORKLOAD])
     n, q, m, r, rho = cfg["n"], cfg["q"], cfg["m"], cfg["r"], cfg["rho"]
     log(f"generating {WORKLOAD} (seed {cfg['seed']})")
