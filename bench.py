@@ -149,7 +149,8 @@ def philox_form(lib, torch, np, cfg, target):
         kms = s.profile_iteration(5)
         st = s.status()
         out[name] = {"init_ms": round(e0.elapsed_time(e1), 3), "gdmin_iter_ms": round(e1.elapsed_time(e2) / T_ITERS, 4),
-                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "final_rel_residual": st["resid"]}
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+        "tuning": tuning, "final_rel_residual": st["resid"]}
         s.close()
         del s
     out["philox_speedup_vs_fp32_plane"] = round(out["fp32_plane"]["gdmin_iter_ms"] / out["philox"]["gdmin_iter_ms"], 3)
@@ -189,6 +190,77 @@ def fourier_form(lib, torch, np, iters: int = 200):
             "kernels_ms": {"k_fu": round(kms["k_au"], 4), "k_fcol": round(kms["k_col"], 4),
                            "k_fgrad": round(kms["k_grad"], 4), "k_fqr": round(kms["k_qr"], 4)},
             "final_rel_residual": rep["resid"], "rel_error_vs_Xstar": err}
+
+
+def small_configs(lib, torch, np):
+    """The exact-recovery shape (n = q = 100) and the FP32 throughput shape (n = q = 600):
+    GPU solves beside the FP64 oracle on the same instances."""
+    from oracle import altgdmin_oracle as O
+    from paper_2311_03824_amd import instances as I
+    out = {}
+    # n = q = 100, m = 40, r = 2, rho = 2: oracle to 1e-10 (<= 300 iterations), GPU FP32 300 iterations
+    cfg = dict(I.WORKLOADS["gauss_n100_q100_m40_r2_rho2"])
+    inst = I.make_instance(**cfg)
+    A, Y = inst.A64(), inst.Y64
+    t0 = time.perf_counter()
+    st, hist = O.solve(A, Y, inst.r, inst.rho, t_max=300, X_star=inst.X_star, err_tol=1e-10)
+    t_orc = time.perf_counter() - t0
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, lib.default_params(t_max=300))
+    s.init().step(300)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.init().step(300)
+    e1.record()
+    torch.cuda.synchronize()
+    g = s.get()
+    X = g["U"].astype(np.float64) @ g["Bt"].T.astype(np.float64)
+    X[g["S_idx"], np.arange(inst.q)[:, None]] += g["S_val"]
+    log_r = lib.altgdmin_residual_log(s.h, 300)
+    s.close()
+    out["gauss_n100_q100_m40_r2_rho2"] = {
+        "oracle_fp64": {"iterations_to_1e-10": len(hist), "final_rel_error": hist[-1], "solve_s": round(t_orc, 3)},
+        "gpu_fp32": {"iterations": 300, "solve_ms": round(e0.elapsed_time(e1), 3),
+                     "final_rel_error_vs_Xstar": float(np.linalg.norm(X - inst.X_star) / np.linalg.norm(inst.X_star)),
+                     "first_iteration_resid_below_1e-6": int(np.argmax(log_r <= 1e-6)) + 1 if (log_r <= 1e-6).any() else None},
+    }
+    # n = q = 600, m = 250, r = 4, rho = 30: 200 fixed iterations
+    cfg = dict(I.WORKLOADS["gauss_n600_q600_m250_r4_rho30"])
+    inst = I.make_instance(**cfg)
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, lib.default_params(t_max=T_ITERS))
+    s.init().step(T_ITERS)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s.init().step(T_ITERS)
+    e1.record()
+    torch.cuda.synchronize()
+    g = s.get()
+    X = g["U"].astype(np.float64) @ g["Bt"].T.astype(np.float64)
+    X[g["S_idx"], np.arange(inst.q)[:, None]] += g["S_val"]
+    kms = s.profile_iteration(20)
+    s.close()
+    col_bytes = column_kernel_bytes(inst.n, inst.q, inst.m, inst.r, inst.rho, 3)
+    col_gbs = col_bytes / (kms["k_col"] * 1e-3) / 1e9
+    A = inst.A64()
+    Yd = inst.Y32.astype(np.float64)
+    t0 = time.perf_counter()
+    st = O.initialise(A, Yd, inst.r, inst.rho)
+    t1 = time.perf_counter()
+    for _ in range(2):
+        st = O.gdmin_iteration(A, Yd, st, inst.rho)
+    t2 = time.perf_counter()
+    orc_iter = (t2 - t1) / 2
+    out["gauss_n600_q600_m250_r4_rho30"] = {
+        "gpu_fp32": {"gdmin_iters_per_s": round(T_ITERS / (e0.elapsed_time(e1) * 1e-3), 1),
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+        "tuning": tuning,
+                     "k_col_GBps": round(col_gbs, 1), "k_col_roofline_frac": round(col_gbs / HBM_PEAK_GBS, 4),
+                     "final_rel_error_vs_Xstar": float(np.linalg.norm(X - inst.X_star) / np.linalg.norm(inst.X_star))},
+        "oracle_fp64": {"init_s": round(t1 - t0, 3), "s_per_iteration": round(orc_iter, 4),
+                        "iters_per_s_whole_solve": round(T_ITERS / ((t1 - t0) + T_ITERS * orc_iter), 3)},
+    }
+    return out
 
 
 def cpu_baseline(inst_args, q_sample: int, iters: int):
@@ -236,6 +308,8 @@ def main() -> int:
     ap.add_argument("--form", choices=["fp32", "bf16x2"], default="fp32")
     ap.add_argument("--iters", type=int, default=T_ITERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="run the default loads-in-flight instantiations instead of the autotuned ones")
     ap.add_argument("--cpu-sample-q", type=int, default=100)
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true", help="skip the time-to-equal-error comparison of the A forms")
@@ -287,7 +361,7 @@ def main() -> int:
     t0 = time.perf_counter()
     inst = I.make_instance(**cfg, bf16_planes=True)
     log(f"generated in {time.perf_counter() - t0:.1f} s; uploading")
-    par = lib.default_params(t_max=args.iters)
+    par = lib.default_params(t_max=args.iters, flags=0 if args.no_autotune else lib.FLAG_AUTOTUNE)
     solver = lib.Solver(inst.At if args.form == "fp32" else None, inst.Y32, m, r, rho, par,
                         A_hi=inst.A_hi if args.form == "bf16x2" else None,
                         A_lo=inst.A_lo if args.form == "bf16x2" else None)
@@ -297,6 +371,11 @@ def main() -> int:
         solver.init()
         solver.step(args.iters)
 
+    t0 = time.perf_counter()
+    solver.init()      # the first init of a shape runs the autotuner; later inits reuse its choice
+    torch.cuda.synchronize()
+    tuning = lib.altgdmin_tuning(solver.h)
+    log(f"first init {time.perf_counter() - t0:.2f} s, tuning {tuning}")
     for w in range(args.warmup):
         one_solve()
         torch.cuda.synchronize()
@@ -360,6 +439,7 @@ def main() -> int:
                          os.path.join(ROOT, "profiles", f"k_col_{WORKLOAD}_fp32.md")) if args.form == "fp32" else None,
                      "kernel": "k_col", "bytes_per_launch": int(col_bytes), "avg_ms": round(kms["k_col"], 4)},
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+        "tuning": tuning,
         "k_au_GBps": round(au_gbs, 1),
         "init_ms": round(init_ms, 3),
         "gdmin_iter_ms": round(iters_ms / args.iters, 4),
@@ -375,6 +455,8 @@ def main() -> int:
         log("philox: " + json.dumps(result["philox_form"]))
         result["fourier_form"] = fourier_form(lib, torch, np)
         log("fourier: " + json.dumps(result["fourier_form"]))
+        result["other_configs"] = small_configs(lib, torch, np)
+        log("other configs: " + json.dumps(result["other_configs"]))
     if args.serve_requests > 0:
         from paper_2311_03824_amd import serve
         log(f"serving {args.serve_requests} mixed-size requests (budget {args.serve_budget_gib} GiB)")

@@ -67,6 +67,11 @@ enum {
   ALTGDMIN_A_PFOURIER = 3    /* partial Fourier: rows fourier_mask[k] of the unitary 2D DFT of n1 x n2 complex frames */
 };
 
+/* altgdmin_params.flags bits */
+#define ALTGDMIN_FLAG_EAGER 1      /* launch each iteration's kernels directly instead of replaying a HIP graph */
+#define ALTGDMIN_FLAG_AUTOTUNE 2   /* FP32 / BF16X2 planes: altgdmin_init times the loads-in-flight variants of the
+                                      streaming kernels on the problem and keeps the fastest (see altgdmin_tuning) */
+
 /* Entries of the normal table of the Philox form: |z| = -Phi^{-1}(v) at
  * v = 2^(e-33) (1 + s/64), e = 0..31, s = 0..63 (index e*64 + s), then two zeros. */
 #define ALTGDMIN_NORMAL_TABLE_SIZE (32 * 64 + 2)
@@ -96,7 +101,7 @@ typedef struct altgdmin_params {
   int32_t t_max;             /* GDmin iterations (paper: 200) */
   int32_t power_iters;       /* max subspace iterations for U_0 (top-r left singular vectors of L_0) */
   int32_t poll_every;        /* altgdmin_solve reads the residual every poll_every iterations */
-  int32_t flags;             /* reserved, 0 */
+  int32_t flags;             /* ALTGDMIN_FLAG_* bits, 0 by default */
   double eta_c;              /* eta = eta_c / ||grad_U f(U_0, B_1, S_1)||_2 (paper: 0.14) */
   double power_tol;          /* stop the subspace iteration when ||(I - U_p U_p^T) U_{p+1}||_F <= power_tol */
   double tol_resid;          /* altgdmin_solve stops when ||Y - A(UB+S)||_F / ||Y||_F <= tol_resid (0: never) */
@@ -165,6 +170,17 @@ int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, voi
  * 4 doubles) receives the average duration of each kernel in milliseconds.
  * Advances the solve like altgdmin_step.  Synchronises. */
 int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out);
+
+/* Autotuner (with ALTGDMIN_FLAG_AUTOTUNE): the column-kernel unroll JU (columns
+ * per load group, 1..3) and the A_k U pipeline depth AUD (1, 2 or 4) chosen for
+ * this handle; 0 means the default instantiation.  The choice is made once per
+ * (GPU architecture, A format, n, q, m, r, rho) in a process by timing each
+ * variant three times on the problem's own data (A_k U from a fixed orthonormal
+ * U; one IHT iteration plus the back-projection for the column kernel) before
+ * the initialisation; with the environment variable ALTGDMIN_TUNE_CACHE naming
+ * a file, choices are read from and appended to it as JSON lines keyed by the
+ * architecture.  Every variant computes the same bits.  Host call. */
+int altgdmin_tuning(altgdmin_handle* h, int32_t* col_unroll, int32_t* au_depth);
 
 /* Device bytes of the launch tables altgdmin_step_many needs for these handles (host call). */
 int altgdmin_group_bytes(altgdmin_handle* const* hs, int32_t count, size_t* bytes);

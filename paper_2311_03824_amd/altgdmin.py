@@ -26,6 +26,7 @@ ALTGDMIN_A_BF16X2 = 1
 ALTGDMIN_A_PHILOX = 2
 ALTGDMIN_A_PFOURIER = 3
 FLAG_EAGER = 1      # params.flags bit 0: launch the iteration's kernels without a HIP graph
+FLAG_AUTOTUNE = 2   # params.flags bit 1: time the streaming-kernel variants at init and keep the fastest
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 
@@ -76,6 +77,7 @@ _SIGS = {
     "altgdmin_step_many": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_sz, c_vp]),
     "altgdmin_strerror": (ctypes.c_char_p, [c_i32]),
     "altgdmin_last_error": (ctypes.c_char_p, []),
+    "altgdmin_tuning": (c_i32, [c_vp, c_vp, c_vp]),
     "altgdmin_op_select": (c_i32, [c_vp, c_i32, c_i32, c_i64, c_i32, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_au": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_op_philox_fill": (c_i32, [ctypes.c_uint64, c_vp, c_i32, c_i32, c_i32, c_i64, c_vp, c_vp]),
@@ -259,6 +261,13 @@ def altgdmin_profile_iteration(h, iters: int, stream=None) -> dict:
     ms = (c_f64 * 4)()
     _check(_lib.altgdmin_profile_iteration(h, iters, stream_ptr(stream), ms))
     return dict(zip(KERNELS, list(ms)))
+
+
+def altgdmin_tuning(h) -> dict:
+    """The autotuned column-kernel unroll and A_k U depth of a handle (0: defaults)."""
+    ju, aud = c_i32(0), c_i32(0)
+    _check(_lib.altgdmin_tuning(h, ctypes.byref(ju), ctypes.byref(aud)))
+    return {"col_unroll": ju.value, "au_depth": aud.value}
 
 
 def altgdmin_destroy(h) -> None:

@@ -19,7 +19,16 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libaltgdmin.so")
 ARCH = os.environ.get("ALTGDMIN_ARCH", "gfx950")
-SOURCES = ["k_column.hip", "k_small.hip", "k_gen.hip", "k_fourier.hip", "api.hip"]
+# (source, extra flags, object): k_column.hip is compiled twice, the second time
+# for the autotuned kernel variants only, so the two halves build in parallel.
+SOURCES = [
+    ("k_column.hip", ["-DALTG_PART=1"], "k_column.o"),
+    ("k_column.hip", ["-DALTG_PART=2"], "k_column_tuned.o"),
+    ("k_small.hip", [], "k_small.o"),
+    ("k_gen.hip", [], "k_gen.o"),
+    ("k_fourier.hip", [], "k_fourier.o"),
+    ("api.hip", [], "api.o"),
+]
 
 HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",
@@ -36,9 +45,10 @@ def _hipcc() -> str:
     return h
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(spec) -> str:
+    src, extra, obj_name = spec
+    obj = os.path.join(BUILD, obj_name)
+    cmd = [_hipcc(), *HIPCC_FLAGS, *extra, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stderr}")

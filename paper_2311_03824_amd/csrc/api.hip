@@ -4,9 +4,13 @@
 // graph of one GDmin iteration.  Every step of the method runs in the kernels
 // of k_column.hip and k_small.hip.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
-#include <string>
 #include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "altgdmin.h"
@@ -87,6 +91,8 @@ struct altgdmin_handle {
   float* tw = nullptr;     // 96 twiddles
   double* fpart = nullptr; // per-256-row-block partial Grams of the GD update
   double* frinv = nullptr; // R1^{-1}, R2^{-1} of the GD update
+  int col_unroll = 0;      // autotuned JU of the column kernel (0: the default instantiation)
+  int au_depth = 0;        // autotuned AUD of the A_k U kernel (0: the default instantiation)
   bool hi_phase = false;   // BF16X2 with a hi-only phase
   bool have_graph = false;
   hipGraph_t graph = nullptr;
@@ -157,7 +163,7 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (p->r < 1 || p->r > p->m || p->r > p->n) return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n)");
   if (p->rho < 0 || p->rho > p->n) return fail(ALTGDMIN_EINVAL, "need 0 <= rho <= n");
   if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
-      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0)
+      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0 || (par->flags & ~(ALTGDMIN_FLAG_EAGER | ALTGDMIN_FLAG_AUTOTUNE)))
     return fail(ALTGDMIN_EINVAL, "invalid params");
   if (p->a_format == ALTGDMIN_A_PFOURIER) {
     if (p->n1 < 1 || p->n2 < 1 || (int64_t)p->n1 * p->n2 != p->n) return fail(ALTGDMIN_EINVAL, "need n = n1 * n2");
@@ -221,6 +227,134 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
   a.hi_max = h->par.bf16_hi_max;
   a.stall = h->par.bf16_stall;
   return a;
+}
+
+// The column and A_k U launches of a solve, through the autotuned variant when
+// one was chosen for this problem's format.
+hipError_t col_launch(const altgdmin_handle* h, int fmt, const ColArgs& a, hipStream_t st) {
+  if (h->col_unroll && fmt == h->fmt) return launch_col_tuned(fmt, h->col_unroll, a, st);
+  return launch_col(fmt, a, st);
+}
+hipError_t au_launch(const altgdmin_handle* h, int fmt, const AUArgs& a, hipStream_t st) {
+  if (h->au_depth && fmt == h->fmt) return launch_au_tuned(fmt, h->au_depth, a, st);
+  return launch_au(fmt, a, st);
+}
+
+// ---- autotuner: the loads in flight of the two streaming kernels, per
+// (A format, n, q, m, r, rho), chosen by timing the variants on the problem's own
+// data; kept for the process and, with ALTGDMIN_TUNE_CACHE=<file>, in a JSON-lines
+// file keyed by the GPU architecture.
+using TuneKey = std::tuple<std::string, int, int, int, int, int, int>;
+std::mutex g_tune_mu;
+std::map<TuneKey, std::pair<int, int>> g_tune;
+bool g_tune_loaded = false;
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+  std::string a = prop.gcnArchName;
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+void tune_cache_load(const std::string& arch) {
+  g_tune_loaded = true;
+  const char* path = std::getenv("ALTGDMIN_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return;
+  char line[512];
+  while (std::fgets(line, sizeof line, f)) {
+    char a[64] = {0};
+    int fmt, n, q, m, r, rho, ju, aud;
+    if (std::sscanf(line,
+                    "{\"arch\": \"%63[^\"]\", \"fmt\": %d, \"n\": %d, \"q\": %d, \"m\": %d, \"r\": %d, "
+                    "\"rho\": %d, \"col_unroll\": %d, \"au_depth\": %d",
+                    a, &fmt, &n, &q, &m, &r, &rho, &ju, &aud) == 9 &&
+        arch == a)
+      g_tune[TuneKey(arch, fmt, n, q, m, r, rho)] = {ju, aud};
+  }
+  std::fclose(f);
+}
+
+void tune_cache_append(const TuneKey& k, int ju, int aud, float col_ms, float au_ms) {
+  const char* path = std::getenv("ALTGDMIN_TUNE_CACHE");
+  if (!path) return;
+  FILE* f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f,
+               "{\"arch\": \"%s\", \"fmt\": %d, \"n\": %d, \"q\": %d, \"m\": %d, \"r\": %d, \"rho\": %d, "
+               "\"col_unroll\": %d, \"au_depth\": %d, \"col_ms\": %.4f, \"au_ms\": %.4f}\n",
+               std::get<0>(k).c_str(), std::get<1>(k), std::get<2>(k), std::get<3>(k), std::get<4>(k), std::get<5>(k),
+               std::get<6>(k), ju, aud, col_ms, au_ms);
+  std::fclose(f);
+}
+
+ColArgs col_args(const altgdmin_handle* h);
+
+int autotune(altgdmin_handle* h, hipStream_t st) {
+  const altgdmin_problem& p = h->prob;
+  const std::string arch = device_arch();
+  const TuneKey key(arch, h->fmt, p.n, p.q, p.m, p.r, p.rho);
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_loaded) tune_cache_load(arch);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) {
+      h->col_unroll = it->second.first;
+      h->au_depth = it->second.second;
+      return ALTGDMIN_OK;
+    }
+  }
+  // the variants run on the problem's own A and y: A_k U from a fixed orthonormal
+  // U, and the column kernel as one IHT iteration from s = 0 plus the
+  // back-projection; every buffer they write is rewritten by the initialisation
+  HIPCHK(launch_fill_basis(h->Utmp, p.n, p.r, st));
+  AUArgs au;
+  std::memset(&au, 0, sizeof(au));
+  au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
+  au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
+  au.U = h->Utmp; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+  ColArgs ca = col_args(h);
+  ca.tau = 1; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto timed = [&](auto launch, float* ms) -> hipError_t {
+    hipError_t e = launch();   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, st);
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch();
+    if (e == hipSuccess) e = hipEventRecord(e1, st);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    *ms /= 3.f;
+    return e;
+  };
+  int best_aud = 0, best_ju = 0;
+  float best_au = 1e30f, best_col = 1e30f;
+  hipError_t e = hipSuccess;
+  for (int aud : {1, 2, 4}) {
+    float ms = 0.f;
+    e = timed([&] { return launch_au_tuned(h->fmt, aud, au, st); }, &ms);
+    if (e != hipSuccess) break;
+    if (ms < best_au) { best_au = ms; best_aud = aud; }
+  }
+  for (int ju = 1; ju <= 3 && e == hipSuccess; ++ju) {
+    float ms = 0.f;
+    e = timed([&] { return launch_col_tuned(h->fmt, ju, ca, st); }, &ms);
+    if (e != hipSuccess) break;
+    if (ms < best_col) { best_col = ms; best_ju = ju; }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("autotune: ") + hipGetErrorString(e));
+  h->col_unroll = best_ju;
+  h->au_depth = best_aud;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune[key] = {best_ju, best_aud};
+  tune_cache_append(key, best_ju, best_aud, best_col, best_au);
+  return ALTGDMIN_OK;
 }
 
 FColArgs fcol_args(const altgdmin_handle* h, int mode) {
@@ -304,8 +438,8 @@ int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
     HIPCHK(launch_col(FMT_BF16HI, ca, st));
     au.gate_want = 1; ca.gate_want = 1;
   }
-  HIPCHK(launch_au(h->fmt, au, st));
-  HIPCHK(launch_col(h->fmt, ca, st));
+  HIPCHK(au_launch(h, h->fmt, au, st));
+  HIPCHK(col_launch(h, h->fmt, ca, st));
   HIPCHK(launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st));
   HIPCHK(launch_qr(qr_args(h, QR_GD), st));
   return ALTGDMIN_OK;
@@ -363,6 +497,13 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
     delete h;
     return fail(ALTGDMIN_EHIP, std::string(what) + ": " + hipGetErrorString(e));
   };
+  if ((par->flags & ALTGDMIN_FLAG_AUTOTUNE) && !h->hi_phase && (h->fmt == FMT_F32 || h->fmt == FMT_BF16X2)) {
+    const int trc = autotune(h, st);
+    if (trc) {
+      delete h;
+      return trc;
+    }
+  }
   hipError_t e;
   if ((e = launch_reset_ctl(h->ctl, 1, st)) != hipSuccess) return bail(e, "reset");
   if ((e = launch_set_phase(h->ctl, h->hi_phase ? 0 : 1, st)) != hipSuccess) return bail(e, "phase");
@@ -391,7 +532,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   // hi plane alone when a BF16X2 solve starts with a hi-only phase
   ColArgs ca = col_args(h);
   ca.tau = par->tau0; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
-  if ((e = launch_col(h->hi_phase ? FMT_BF16HI : h->fmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
+  if ((e = col_launch(h, h->hi_phase ? FMT_BF16HI : h->fmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
   if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
   // U_0: top-r left singular subspace of L_0 by subspace iteration
   if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, (long long)p.n * p.r, st);
@@ -412,7 +553,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
 int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
   if (!h || iters < 0) return fail(ALTGDMIN_EINVAL, "null handle or negative iters");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  if (h->par.flags & 1) {   // eager launches (no graph)
+  if (h->par.flags & ALTGDMIN_FLAG_EAGER) {   // eager launches (no graph)
     for (int i = 0; i < iters; ++i) {
       int rc = enqueue_iteration(h, st);
       if (rc) return rc;
@@ -472,9 +613,9 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     ColArgs ca = col_args(h);
     ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
     hipError_t e = hipEventRecord(ev[0], st);
-    if (e == hipSuccess) e = launch_au(h->fmt, au, st);
+    if (e == hipSuccess) e = au_launch(h, h->fmt, au, st);
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-    if (e == hipSuccess) e = launch_col(h->fmt, ca, st);
+    if (e == hipSuccess) e = col_launch(h, h->fmt, ca, st);
     if (e == hipSuccess) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess) e = launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st);
     if (e == hipSuccess) e = hipEventRecord(ev[3], st);
@@ -591,6 +732,13 @@ const char* altgdmin_strerror(int code) {
 }
 
 const char* altgdmin_last_error(void) { return g_last_error.c_str(); }
+
+int altgdmin_tuning(altgdmin_handle* h, int32_t* col_unroll, int32_t* au_depth) {
+  if (!h) return fail(ALTGDMIN_EINVAL, "null handle");
+  if (col_unroll) *col_unroll = h->col_unroll;
+  if (au_depth) *au_depth = h->au_depth;
+  return ALTGDMIN_OK;
+}
 
 }  // extern "C"
 

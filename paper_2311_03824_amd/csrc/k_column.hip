@@ -171,11 +171,15 @@ __device__ __forceinline__ double sumsq(const float4 (&v)[NC]) {
 // Wave w takes columns j = w, w + 4, ...; groups of JU columns are loaded one
 // group ahead of the one being reduced.  JU keeps about 4-6 float4 loads per
 // lane in flight (measured best: JU = 3 for one 256-row chunk, 1 for more).
-template <int FMT, int NC>
+// The order in which a wave visits the columns does not depend on JU, so every
+// JU gives the same bits.
+// default loads in flight (autotuned variants pass another JU)
+constexpr int default_ju(int nc) { return nc == 1 ? 3 : 1; }
+
+template <int FMT, int NC, int JU>
 __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
                                            int n, float* gl, const unsigned* inT, float4 (&wacc)[NC],
                                            double& gT2, int lane, int wave) {
-  constexpr int JU = NC == 1 ? 3 : 1;
   constexpr int step = kWaves * JU;
   // loads are unconditional (column clamped to n-1, chunk clamped to a legal
   // one) so that a whole group is in flight at once; consume() masks them
@@ -238,7 +242,7 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
 // magnitude bits (monotone in |v|), one byte per round from the top, with a
 // 256-bin LDS histogram; ties at T are then resolved in index order by one
 // wave.  hist: 256 + 8 ints of LDS.  Returns the number of NaNs (block-uniform).
-__device__ int block_select(const float* vals, int n, int rho, int* idx, float* val, int* hist) {
+static __device__ int block_select(const float* vals, int n, int rho, int* idx, float* val, int* hist) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   if (rho <= 0) return 0;
   int* ctl = hist + 256;   // [0] digit, [1] rank left, [2] NaN count
@@ -313,7 +317,7 @@ __device__ int block_select(const float* vals, int n, int rho, int* idx, float* 
 
 // ---------------------------------------------------------------- k_col
 
-template <int FMT, int NC>
+template <int FMT, int NC, int JU>
 __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char* smem) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r, rho = a.rho;
@@ -395,7 +399,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
 #pragma unroll
     for (int c = 0; c < NC; ++c) w[c] = make_float4(0.f, 0.f, 0.f, 0.f);
     double gT2 = 0.0;
-    fused_pass<FMT, NC>(L, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
+    fused_pass<FMT, NC, JU>(L, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
     __syncthreads();
     if (hasT) {
       xwave_sum<NC>(w, ln, wpart, mq, wave);
@@ -450,7 +454,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     }
     float4 w[NC];
     double dummy = 0.0;
-    fused_pass<FMT, NC>(L, ln, v, n, gl, nullptr, w, dummy, lane, wave);
+    fused_pass<FMT, NC, JU>(L, ln, v, n, gl, nullptr, w, dummy, lane, wave);
     __syncthreads();
     for (int j = tid; j < n; j += kThreads) a.H[(long long)k * n + j] = gl[j];
   }
@@ -462,11 +466,11 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   if (tid == 0 && nan_seen > 0 && a.flags) a.flags[k] |= 1;
 }
 
-template <int FMT, int NC>
+template <int FMT, int NC, int JU = default_ju(NC)>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col(ColArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  col_body<FMT, NC>(a, blockIdx.x, smem);
+  col_body<FMT, NC, JU>(a, blockIdx.x, smem);
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
@@ -477,7 +481,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
   const int2 mp = map[blockIdx.x];
   const ColArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  col_body<FMT, NC>(a, mp.y, smem);
+  col_body<FMT, NC, default_ju(NC)>(a, mp.y, smem);
 }
 
 // ---------------------------------------------------------------- k_au
@@ -487,7 +491,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
 // and columns j = w % js, w % js + js, ... where js = 4 / nch (1 when nch > 2);
 // each lane holds 4 rows x R accumulators.  Partial P_k of the waves sharing a
 // chunk are added in a fixed order (in LDS when P_k fits, else in global memory).
-template <int FMT, int R>
+template <int FMT, int R, int AUD>
 __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* smem) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r;
@@ -527,7 +531,6 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   // issued.  The rows of U this wave needs are staged 64 at a time in its own
   // LDS slice (lane t loads the row of the wave's t-th next column) and read back
   // as broadcast 16-byte LDS loads, so the FMAs take plain register operands.
-  constexpr int AUD = 2;
   constexpr int RP = (R + 3) / 4 * 4;
   float* Uw = reinterpret_cast<float*>(smem + lay.P) + wave * 64 * RP;   // shares the P region
   const float* U = a.U;
@@ -669,11 +672,13 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   for (int t = tid; t < r * r; t += kThreads) Gk[t] = Gil[t];
 }
 
-template <int FMT, int R>
+constexpr int kDefaultAUD = 2;   // A_k loads of the next AUD columns in flight per wave (autotuned variants differ)
+
+template <int FMT, int R, int AUD = kDefaultAUD>
 __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  au_body<FMT, R>(a, blockIdx.x, smem);
+  au_body<FMT, R, AUD>(a, blockIdx.x, smem);
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
@@ -683,9 +688,10 @@ __global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const in
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  au_body<FMT, R>(a, mp.y, smem);
+  au_body<FMT, R, kDefaultAUD>(a, mp.y, smem);
 }
 
+#if !defined(ALTG_PART) || ALTG_PART == 1
 // HardThreshold of one vector per workgroup (the step-level select entry point).
 __global__ __launch_bounds__(kThreads) void k_select(const float* V, int n, long long ldv, int rho, int* idx,
                                                      float* val, int* flags) {
@@ -801,5 +807,48 @@ hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q
   hipLaunchKernelGGL(k_philox_fill, dim3(1024), dim3(256), 0, st, seed, table, q, n, m, lda, A);
   return hipGetLastError();
 }
+
+#endif  // part 1
+
+#if ALTG_PART == 2
+// Autotuned variants of the plane formats: k_col with JU in {1, 2, 3} and k_au
+// with AUD in {1, 2, 4}.  Every variant gives the same bits as the default one.
+typedef void (*col_fn2)(ColArgs);
+typedef void (*au_fn2)(AUArgs);
+#define COLT_NC(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 3>}
+#define COLT_F(F) {COLT_NC(F, 1), COLT_NC(F, 2), COLT_NC(F, 3), COLT_NC(F, 4)}
+static const col_fn2 kColTuned[2][kNCMax][3] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2)};
+#define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 4>}
+#define AUT_F(F) {AUT_R(F, 2), AUT_R(F, 4), AUT_R(F, 6), AUT_R(F, 8), AUT_R(F, 10), AUT_R(F, 12), AUT_R(F, 14), AUT_R(F, 16)}
+static const au_fn2 kAUTuned[2][kRMax / 2][3] = {AUT_F(FMT_F32), AUT_F(FMT_BF16X2)};
+
+static int tuned_slot(int v, const int (&vals)[3]) {
+  for (int i = 0; i < 3; ++i)
+    if (vals[i] == v) return i;
+  return -1;
+}
+
+hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
+  static const int kJU[3] = {1, 2, 3};
+  const int slot = tuned_slot(ju, kJU);
+  if ((fmt != FMT_F32 && fmt != FMT_BF16X2) || slot < 0) return hipErrorInvalidValue;
+  const int nc = (a.m + 255) / 256;
+  const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, 0);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColTuned[fmt == FMT_F32 ? 0 : 1][nc - 1][slot], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st) {
+  static const int kAUD[3] = {1, 2, 4};
+  const int slot = tuned_slot(aud, kAUD);
+  if ((fmt != FMT_F32 && fmt != FMT_BF16X2) || slot < 0) return hipErrorInvalidValue;
+  const int ri = (a.r + 1) / 2 - 1;
+  const AULayout lay(a.m, a.r, 0);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kAUTuned[fmt == FMT_F32 ? 0 : 1][ri][slot], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  return hipGetLastError();
+}
+#endif  // ALTG_PART == 2
 
 }  // namespace altg

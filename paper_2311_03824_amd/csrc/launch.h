@@ -40,6 +40,9 @@ struct GradArgs {
 };
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);
+// autotuned variants (FP32 and BF16X2 planes): JU in {1, 2, 3}, AUD in {1, 2, 4}
+hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st);
+hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st);
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
 bool au_supported(int m, int r);
 hipError_t launch_col_grp(int fmt, int nc, const ColArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st);

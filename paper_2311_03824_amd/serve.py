@@ -88,7 +88,8 @@ class Scheduler:
 
     def __init__(self, executor, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
                  max_iters: int = 300, clock: Callable[[], float] = time.perf_counter,
-                 sleep: Callable[[float], None] = time.sleep, prefetch: int = 16):
+                 sleep: Callable[[float], None] = time.sleep, prefetch: int = 16,
+                 max_active: Optional[int] = None):
         if poll_every < 1 or max_iters < 1:
             raise ValueError("poll_every and max_iters must be >= 1")
         self.ex = executor
@@ -99,6 +100,7 @@ class Scheduler:
         self.clock = clock
         self.sleep = sleep
         self.prefetch = prefetch
+        self.max_active = max_active   # None: limited by the budget only; 1: one request at a time
 
     def run(self, requests) -> ServeReport:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.idx)))
@@ -134,6 +136,8 @@ class Scheduler:
                                             float("nan"), rejected=True))
                     continue
                 if used + fp > self.budget:
+                    break
+                if self.max_active is not None and len(active) >= self.max_active:
                     break
                 waiting.popleft()
                 job = timed("start", self.ex.start, req)
@@ -261,16 +265,17 @@ class GpuExecutor:
 
 
 def calibrate_rate(executor, requests, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
-                   max_iters: int = 300) -> float:
-    """Closed-loop throughput (all requests present at t = 0), in solves/s."""
+                   max_iters: int = 300, max_active: Optional[int] = None) -> float:
+    """Closed-loop throughput (all requests present at t = 0), in solves/s.  With
+    max_active = 1 the requests are solved one after the other (no batching)."""
     reqs = [dataclasses.replace(r, arrival=0.0) for r in requests]
-    rep = Scheduler(executor, budget_bytes, poll_every, tol, max_iters).run(reqs)
+    rep = Scheduler(executor, budget_bytes, poll_every, tol, max_iters, max_active=max_active).run(reqs)
     return rep.summary()["solves_per_s"]
 
 
 def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, load: float = 0.8,
           rate: Optional[float] = None, poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
-          calibration_count: Optional[int] = None, log=None) -> dict:
+          calibration_count: Optional[int] = None, sequential: bool = True, log=None) -> dict:
     """Serve `count` seeded requests on the GPU and return the summary.
 
     Without an explicit `rate`, the arrival rate is `load` times the closed-loop
@@ -293,4 +298,11 @@ def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, loa
     out = rep.summary()
     out.update({"arrival_rate_per_s": rate, "closed_loop_solves_per_s": sat, "load": load if sat else None,
                 "tol_resid": tol, "max_iters": max_iters, "poll_every": poll_every, "seed": seed})
+    if sequential and sat:
+        # the same requests solved one at a time through the same executor (no batching)
+        seq = calibrate_rate(ex, reqs[: calibration_count or count], budget, poll_every, tol, max_iters, max_active=1)
+        out["sequential_solves_per_s"] = seq
+        out["batching_speedup"] = sat / seq if seq > 0 else None
+        if log:
+            log(f"one request at a time: {seq:.2f} solves/s (batching speedup {sat / seq:.2f}x)")
     return out

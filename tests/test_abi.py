@@ -127,7 +127,7 @@ def test_workspace_bytes_rejects_invalid_problems(lib, kw, code):
 
 
 def test_workspace_bytes_rejects_invalid_params(lib):
-    for field, value in [("tau", -1), ("t_max", -1), ("poll_every", 0), ("eta_c", -0.1), ("bf16_hi_max", -2)]:
+    for field, value in [("tau", -1), ("t_max", -1), ("poll_every", 0), ("eta_c", -0.1), ("bf16_hi_max", -2), ("flags", 4)]:
         par = lib.default_params(**{field: value})
         rc, _, _ = _ws(lib, _problem(lib), par)
         assert rc == -1, field

@@ -9,6 +9,8 @@ GPU produced.  Tolerances:
   * normwise relative errors of FP32 results are checked at 1e-5;
   * subspaces agree to ||(I - U1 U1^T) U2||_F <= 1e-5 (FP32 path).
 """
+import json
+
 import numpy as np
 import pytest
 
@@ -303,6 +305,7 @@ def _solve(lib, torch, inst, t_max, bf16=False, flags=0, tol=0.0):
     out = s.get()
     out["status"] = s.status()
     out["log"] = s.residual_log()
+    out["tuning"] = lib.altgdmin_tuning(s.h)
     s.close()
     return out
 
@@ -345,6 +348,27 @@ def test_deterministic_and_graph_equals_eager(lib, torch):
         assert np.array_equal(a[key], b[key])
         assert np.array_equal(a[key], c[key])
     assert np.array_equal(a["log"], c["log"])
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatch, bf16):
+    """The loads-in-flight variants the autotuner picks among compute the same bits."""
+    cache = tmp_path / "tune.jsonl"
+    monkeypatch.setenv("ALTGDMIN_TUNE_CACHE", str(cache))
+    inst = I.make_instance(n=517, q=40, m=333 + 4 * bf16, r=5, rho=11, seed=12, bf16_planes=bf16)
+    a = _solve(lib, torch, inst, 12, bf16=bf16)
+    b = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE)
+    c = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE | lib.FLAG_EAGER)
+    assert a["tuning"] == {"col_unroll": 0, "au_depth": 0}
+    assert b["tuning"]["col_unroll"] in (1, 2, 3) and b["tuning"]["au_depth"] in (1, 2, 4)
+    assert c["tuning"] == b["tuning"]              # the second init reuses the process-wide choice
+    for key in ("U", "Bt", "S_idx", "S_val"):
+        assert np.array_equal(a[key], b[key]), key
+        assert np.array_equal(a[key], c[key]), key
+    assert np.array_equal(a["log"], b["log"])
+    rec = [json.loads(x) for x in cache.read_text().splitlines()]
+    assert len(rec) == 1 and rec[0]["m"] == inst.m and rec[0]["fmt"] == int(bf16)
+    assert (rec[0]["col_unroll"], rec[0]["au_depth"]) == (b["tuning"]["col_unroll"], b["tuning"]["au_depth"])
 
 
 def test_solve_entry_point_tolerance_stop(lib, torch):

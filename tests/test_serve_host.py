@@ -161,3 +161,12 @@ def test_scheduler_batches_concurrent_requests():
 def test_scheduler_rejects_bad_arguments():
     with pytest.raises(ValueError):
         Scheduler(None, 1, poll_every=0)
+
+
+def test_scheduler_one_at_a_time():
+    clk = Clock()
+    reqs = _reqs(5)
+    ex = MockExecutor(clk, {r.idx: 20 for r in reqs})
+    rep = Scheduler(ex, 1 << 50, poll_every=10, clock=clk, sleep=clk.sleep, max_active=1).run(reqs)
+    assert ex.rounds == [1] * 10 and ex.max_in_use == max(r.a_bytes() for r in reqs)
+    assert rep.summary()["completed"] == 5
