@@ -83,16 +83,21 @@ def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
     """Wall time of altgdmin_solve until ||Y - A(UB+S)||/||Y|| <= target, per form of A, and the final error.
 
     fp32: FP32 plane.  bf16x2: BF16 hi plane alone until the residual stalls (resid_t >=
-    0.9 resid_{t-1}) or 200 iterations, then hi + lo.  Same instance, same GPU.
+    0.9 resid_{t-1}) or 200 iterations, then hi + lo.  bf16_mixed: hi + lo for every
+    product that forms a residual, the hi plane alone for the transposed products and
+    the IHT step lengths.  Same instance, same GPU.
     """
     out = {}
     n, q, m, r, rho = inst.n, inst.q, inst.m, inst.r, inst.rho
     A_hi = torch.from_numpy(np.ascontiguousarray(inst.A_hi).view(np.int16)).cuda()
     A_lo = torch.from_numpy(np.ascontiguousarray(inst.A_lo).view(np.int16)).cuda()
+    tune = lib.FLAG_AUTOTUNE
     forms = {
-        "fp32": (lib.make_problem(fp32_solver.A, fp32_solver.Y, r, rho, m=m), {}),
+        "fp32": (lib.make_problem(fp32_solver.A, fp32_solver.Y, r, rho, m=m), {"flags": tune}),
         "bf16x2": (lib.make_problem(A_hi, fp32_solver.Y, r, rho, A_lo=A_lo, m=m),
                    {"bf16_hi_max": 200, "bf16_stall": 0.9}),
+        "bf16_mixed": (lib.make_problem(A_hi, fp32_solver.Y, r, rho, A_lo=A_lo, m=m),
+                       {"flags": tune | lib.FLAG_BF16_MIXED}),
     }
     for name, (prob, extra) in forms.items():
         par = lib.default_params(t_max=400, tol_resid=target, poll_every=5, **extra)
@@ -115,6 +120,7 @@ def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
                      "refine_iteration": rep["refine_iteration"]}
     out["target_rel_residual"] = target
     out["bf16x2_speedup_vs_fp32"] = round(out["fp32"]["ms_to_target"] / out["bf16x2"]["ms_to_target"], 3)
+    out["bf16_mixed_speedup_vs_fp32"] = round(out["fp32"]["ms_to_target"] / out["bf16_mixed"]["ms_to_target"], 3)
     return out
 
 
@@ -149,8 +155,7 @@ def philox_form(lib, torch, np, cfg, target):
         kms = s.profile_iteration(5)
         st = s.status()
         out[name] = {"init_ms": round(e0.elapsed_time(e1), 3), "gdmin_iter_ms": round(e1.elapsed_time(e2) / T_ITERS, 4),
-                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
-        "tuning": tuning, "final_rel_residual": st["resid"]}
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "final_rel_residual": st["resid"]}
         s.close()
         del s
     out["philox_speedup_vs_fp32_plane"] = round(out["fp32_plane"]["gdmin_iter_ms"] / out["philox"]["gdmin_iter_ms"], 3)
@@ -227,7 +232,8 @@ def small_configs(lib, torch, np):
     # n = q = 600, m = 250, r = 4, rho = 30: 200 fixed iterations
     cfg = dict(I.WORKLOADS["gauss_n600_q600_m250_r4_rho30"])
     inst = I.make_instance(**cfg)
-    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, lib.default_params(t_max=T_ITERS))
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho,
+                   lib.default_params(t_max=T_ITERS, flags=lib.FLAG_AUTOTUNE))
     s.init().step(T_ITERS)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -239,6 +245,7 @@ def small_configs(lib, torch, np):
     X = g["U"].astype(np.float64) @ g["Bt"].T.astype(np.float64)
     X[g["S_idx"], np.arange(inst.q)[:, None]] += g["S_val"]
     kms = s.profile_iteration(20)
+    tuning = lib.altgdmin_tuning(s.h)
     s.close()
     col_bytes = column_kernel_bytes(inst.n, inst.q, inst.m, inst.r, inst.rho, 3)
     col_gbs = col_bytes / (kms["k_col"] * 1e-3) / 1e9
@@ -253,8 +260,7 @@ def small_configs(lib, torch, np):
     orc_iter = (t2 - t1) / 2
     out["gauss_n600_q600_m250_r4_rho30"] = {
         "gpu_fp32": {"gdmin_iters_per_s": round(T_ITERS / (e0.elapsed_time(e1) * 1e-3), 1),
-                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
-        "tuning": tuning,
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "tuning": tuning,
                      "k_col_GBps": round(col_gbs, 1), "k_col_roofline_frac": round(col_gbs / HBM_PEAK_GBS, 4),
                      "final_rel_error_vs_Xstar": float(np.linalg.norm(X - inst.X_star) / np.linalg.norm(inst.X_star))},
         "oracle_fp64": {"init_s": round(t1 - t0, 3), "s_per_iteration": round(orc_iter, 4),

@@ -71,6 +71,13 @@ enum {
 #define ALTGDMIN_FLAG_EAGER 1      /* launch each iteration's kernels directly instead of replaying a HIP graph */
 #define ALTGDMIN_FLAG_AUTOTUNE 2   /* FP32 / BF16X2 planes: altgdmin_init times the loads-in-flight variants of the
                                       streaming kernels on the problem and keeps the fastest (see altgdmin_tuning) */
+#define ALTGDMIN_FLAG_BF16_MIXED 4 /* BF16X2 planes, mixed form: every product that forms a residual (A_k U and the
+                                      support gathers A_k s_k) reads hi + lo, i.e. A exactly; the streaming
+                                      transposed products A_k^T v (IHT gradients, h_k of grad_U f, the
+                                      back-projection L_0) and the IHT step-length product read the hi plane
+                                      alone, at half the bytes.  The exact iterate X* stays a fixed point; the
+                                      search directions carry the 2^-9 relative error of the hi plane.  Needs
+                                      bf16_hi_max = 0. */
 
 /* Entries of the normal table of the Philox form: |z| = -Phi^{-1}(v) at
  * v = 2^(e-33) (1 + s/64), e = 0..31, s = 0..63 (index e*64 + s), then two zeros. */

@@ -33,6 +33,13 @@ design notes as well):
     before any use) and is skipped.
   * The output pairs U with the B and S fitted to it ("consistent pair").
   * mu = 0 when ||M g|| is 0 or not finite; eta = 0 when grad_U f = 0.
+
+Mixed-precision variant (not in the paper; an option of the GPU path whose
+A_k is stored as a BF16 hi + lo pair): every function that takes ``A_t`` uses
+it in place of A for the transposed products A_k^T v (the IHT gradient, h_k of
+grad_U f, the back-projection L_0) and for the IHT step-length product M g_T,
+while every product that forms a residual (A_k U, A_k s_k) keeps A.  With
+A_t = A (the default) this is the paper's algorithm unchanged.
 """
 from __future__ import annotations
 
@@ -72,7 +79,7 @@ def hard_threshold(V: np.ndarray, rho: int):
 
 def iht(z: np.ndarray, Mop: Callable, MTop: Callable, rho: int, tau: int,
         S0: np.ndarray, idx0: Optional[np.ndarray] = None, mu_rule: str = "support",
-        trace: Optional[list] = None):
+        trace: Optional[list] = None, Dop: Optional[Callable] = None):
     """IHT(z, M, rho, tau, s) of Alg. 2 for all columns at once.
 
     For t = 1..tau: gradient g of L(s) = ||M s - z||^2 (factor 2 dropped),
@@ -87,6 +94,8 @@ def iht(z: np.ndarray, Mop: Callable, MTop: Callable, rho: int, tau: int,
     of unsquared norms; both are kept for negative tests only.
 
     Mop maps (q, n) -> (q, m) column by column; MTop maps (q, m) -> (q, n).
+    Dop, if given, replaces Mop in the step-length product M g_T only (the
+    mixed-precision variant); the residual M s - z always uses Mop.
     Returns the dense (q, n) result and its kept indices (q, rho), ascending.
     """
     S = np.array(S0, dtype=np.float64, copy=True)
@@ -104,7 +113,7 @@ def iht(z: np.ndarray, Mop: Callable, MTop: Callable, rho: int, tau: int,
             D = G
         else:
             raise ValueError(mu_rule)
-        W = Mop(D)                          # M * (restricted) gradient
+        W = (Dop or Mop)(D)                 # M * (restricted) gradient
         gg = np.einsum("kn,kn->k", D, D)
         ww = np.einsum("km,km->k", W, W)
         if mu_rule == "literal":
@@ -155,11 +164,12 @@ def ls_b(A: np.ndarray, U: np.ndarray, Y: np.ndarray, S: np.ndarray) -> np.ndarr
     return pinv_apply(P, G, Y - apply_A(A, S))
 
 
-def grad_U(A: np.ndarray, U: np.ndarray, B: np.ndarray, S: np.ndarray, Y: np.ndarray) -> np.ndarray:
+def grad_U(A: np.ndarray, U: np.ndarray, B: np.ndarray, S: np.ndarray, Y: np.ndarray,
+           A_t: Optional[np.ndarray] = None) -> np.ndarray:
     """Sec. 2.1: grad_U f = sum_k A_k^T (A_k (U b_k + s_k) - y_k) b_k^T, an (n, r) matrix."""
     X = B @ U.T + S                                    # rows are (U b_k + s_k)^T
     Rres = apply_A(A, X) - Y                           # r_k = A_k (U b_k + s_k) - y_k
-    H = apply_AT(A, Rres)                              # rows h_k^T = (A_k^T r_k)^T
+    H = apply_AT(A if A_t is None else A_t, Rres)      # rows h_k^T = (A_k^T r_k)^T
     return H.T @ B
 
 
@@ -196,16 +206,18 @@ def rel_error(X: np.ndarray, X_star: np.ndarray) -> float:
 # Alg. 1
 # ---------------------------------------------------------------------------
 
-def init_sparse(A: np.ndarray, Y: np.ndarray, rho: int, tau0: int = TAU0, mu_rule="support"):
+def init_sparse(A: np.ndarray, Y: np.ndarray, rho: int, tau0: int = TAU0, mu_rule="support",
+                A_t: Optional[np.ndarray] = None):
     """Alg. 1 initialisation, first step: s_k = IHT(y_k, A_k, rho, tau0, 0).  Returns (S, idx)."""
     q, m, n = A.shape
-    return iht(Y, lambda S: apply_A(A, S), lambda V: apply_AT(A, V), rho, tau0,
-               np.zeros((q, n)), mu_rule=mu_rule)
+    At = A if A_t is None else A_t
+    return iht(Y, lambda S: apply_A(A, S), lambda V: apply_AT(At, V), rho, tau0,
+               np.zeros((q, n)), mu_rule=mu_rule, Dop=lambda S: apply_A(At, S))
 
 
-def backprojection(A: np.ndarray, Y: np.ndarray, S: np.ndarray) -> np.ndarray:
+def backprojection(A: np.ndarray, Y: np.ndarray, S: np.ndarray, A_t: Optional[np.ndarray] = None) -> np.ndarray:
     """Alg. 1 / Sec. 2.3: L_0 = [A_k^T (y_k - A_k s_k)]_k, an n x q matrix."""
-    return apply_AT(A, Y - apply_A(A, S)).T
+    return apply_AT(A if A_t is None else A_t, Y - apply_A(A, S)).T
 
 
 def spectral_init(L0: np.ndarray, r: int) -> np.ndarray:
@@ -225,16 +237,16 @@ class State:
     t: int = 0
 
 
-def initialise(A, Y, r, rho, tau0=TAU0, mu_rule="support") -> State:
+def initialise(A, Y, r, rho, tau0=TAU0, mu_rule="support", A_t=None) -> State:
     """Initialisation block of Alg. 1 (Sec. 2.3): sparse part first with B = 0, then spectral init."""
-    S, idx = init_sparse(A, Y, rho, tau0, mu_rule)
-    L0 = backprojection(A, Y, S)
+    S, idx = init_sparse(A, Y, rho, tau0, mu_rule, A_t)
+    L0 = backprojection(A, Y, S, A_t)
     U0 = spectral_init(L0, r)
     return State(U=U0, S=S, idx=idx)
 
 
 def gdmin_iteration(A, Y, st: State, rho: int, tau: int = TAU, eta_c: float = ETA_C,
-                    mu_rule="support", record: Optional[dict] = None) -> State:
+                    mu_rule="support", record: Optional[dict] = None, A_t=None) -> State:
     """One GDmin iteration of Alg. 1.
 
     z_k, M_k from the current U; warm-started IHT for s_k; LS for b_k
@@ -242,13 +254,15 @@ def gdmin_iteration(A, Y, st: State, rho: int, tau: int = TAU, eta_c: float = ET
     projected GD step U+ = QR(U - eta grad).
     """
     U = st.U
+    At = A if A_t is None else A_t
     P, G = projector_parts(A, U)                             # A_k U and its Gram
     Z = project_out(P, G, Y)                                 # z_k
     Mop = lambda S: project_out(P, G, apply_A(A, S))         # s -> M_k s
-    MTop = lambda V: apply_AT(A, project_out(P, G, V))       # v -> M_k^T v (projector is symmetric)
-    S, idx = iht(Z, Mop, MTop, rho, tau, st.S, st.idx, mu_rule=mu_rule)
+    MTop = lambda V: apply_AT(At, project_out(P, G, V))      # v -> M_k^T v (projector is symmetric)
+    Dop = lambda S: project_out(P, G, apply_A(At, S))        # step-length product
+    S, idx = iht(Z, Mop, MTop, rho, tau, st.S, st.idx, mu_rule=mu_rule, Dop=Dop)
     B = pinv_apply(P, G, Y - apply_A(A, S))                  # b_k
-    grad = grad_U(A, U, B, S, Y)
+    grad = grad_U(A, U, B, S, Y, A_t)
     eta = st.eta
     if eta is None:
         nrm = spectral_norm(grad)
@@ -266,14 +280,15 @@ def estimate(st: State) -> np.ndarray:
 
 def solve(A, Y, r, rho, t_max: int = T_MAX, tau0: int = TAU0, tau: int = TAU,
           eta_c: float = ETA_C, X_star: Optional[np.ndarray] = None,
-          err_tol: Optional[float] = None, mu_rule="support", U0: Optional[np.ndarray] = None):
+          err_tol: Optional[float] = None, mu_rule="support", U0: Optional[np.ndarray] = None,
+          A_t: Optional[np.ndarray] = None):
     """Alg. 1 end to end.  Returns (state, history of Error(X*, X_t) when X_star is given)."""
-    st = initialise(A, Y, r, rho, tau0, mu_rule)
+    st = initialise(A, Y, r, rho, tau0, mu_rule, A_t)
     if U0 is not None:
         st.U = np.array(U0, dtype=np.float64)
     hist = []
     for _ in range(t_max):
-        st = gdmin_iteration(A, Y, st, rho, tau, eta_c, mu_rule)
+        st = gdmin_iteration(A, Y, st, rho, tau, eta_c, mu_rule, A_t=A_t)
         if X_star is not None:
             hist.append(rel_error(estimate(st), X_star))
             if err_tol is not None and hist[-1] < err_tol:

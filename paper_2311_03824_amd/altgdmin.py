@@ -27,6 +27,7 @@ ALTGDMIN_A_PHILOX = 2
 ALTGDMIN_A_PFOURIER = 3
 FLAG_EAGER = 1      # params.flags bit 0: launch the iteration's kernels without a HIP graph
 FLAG_AUTOTUNE = 2   # params.flags bit 1: time the streaming-kernel variants at init and keep the fastest
+FLAG_BF16_MIXED = 4  # params.flags bit 2: BF16X2 planes, hi plane alone for the transposed products
 
 c_i32, c_i64, c_f64, c_vp, c_sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
 

@@ -93,6 +93,7 @@ struct altgdmin_handle {
   double* frinv = nullptr; // R1^{-1}, R2^{-1} of the GD update
   int col_unroll = 0;      // autotuned JU of the column kernel (0: the default instantiation)
   int au_depth = 0;        // autotuned AUD of the A_k U kernel (0: the default instantiation)
+  int colfmt = 0;          // format of the column kernel: fmt, or the mixed BF16 form
   bool hi_phase = false;   // BF16X2 with a hi-only phase
   bool have_graph = false;
   hipGraph_t graph = nullptr;
@@ -163,8 +164,11 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (p->r < 1 || p->r > p->m || p->r > p->n) return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n)");
   if (p->rho < 0 || p->rho > p->n) return fail(ALTGDMIN_EINVAL, "need 0 <= rho <= n");
   if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
-      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0 || (par->flags & ~(ALTGDMIN_FLAG_EAGER | ALTGDMIN_FLAG_AUTOTUNE)))
+      !(par->eta_c >= 0.0) || par->bf16_hi_max < 0 ||
+      (par->flags & ~(ALTGDMIN_FLAG_EAGER | ALTGDMIN_FLAG_AUTOTUNE | ALTGDMIN_FLAG_BF16_MIXED)))
     return fail(ALTGDMIN_EINVAL, "invalid params");
+  if ((par->flags & ALTGDMIN_FLAG_BF16_MIXED) && (p->a_format != ALTGDMIN_A_BF16X2 || par->bf16_hi_max > 0))
+    return fail(ALTGDMIN_EINVAL, "the mixed BF16 form needs BF16X2 planes and no hi-only phase");
   if (p->a_format == ALTGDMIN_A_PFOURIER) {
     if (p->n1 < 1 || p->n2 < 1 || (int64_t)p->n1 * p->n2 != p->n) return fail(ALTGDMIN_EINVAL, "need n = n1 * n2");
     if (p->n1 != kFN || p->n2 != kFN) return fail(ALTGDMIN_ENOTBUILT, "the Fourier kernels are built for 96 x 96 frames");
@@ -232,7 +236,7 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
 // The column and A_k U launches of a solve, through the autotuned variant when
 // one was chosen for this problem's format.
 hipError_t col_launch(const altgdmin_handle* h, int fmt, const ColArgs& a, hipStream_t st) {
-  if (h->col_unroll && fmt == h->fmt) return launch_col_tuned(fmt, h->col_unroll, a, st);
+  if (h->col_unroll && fmt == h->colfmt) return launch_col_tuned(fmt, h->col_unroll, a, st);
   return launch_col(fmt, a, st);
 }
 hipError_t au_launch(const altgdmin_handle* h, int fmt, const AUArgs& a, hipStream_t st) {
@@ -296,7 +300,7 @@ ColArgs col_args(const altgdmin_handle* h);
 int autotune(altgdmin_handle* h, hipStream_t st) {
   const altgdmin_problem& p = h->prob;
   const std::string arch = device_arch();
-  const TuneKey key(arch, h->fmt, p.n, p.q, p.m, p.r, p.rho);
+  const TuneKey key(arch, h->colfmt, p.n, p.q, p.m, p.r, p.rho);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_loaded) tune_cache_load(arch);
@@ -342,7 +346,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   }
   for (int ju = 1; ju <= 3 && e == hipSuccess; ++ju) {
     float ms = 0.f;
-    e = timed([&] { return launch_col_tuned(h->fmt, ju, ca, st); }, &ms);
+    e = timed([&] { return launch_col_tuned(h->colfmt, ju, ca, st); }, &ms);
     if (e != hipSuccess) break;
     if (ms < best_col) { best_col = ms; best_ju = ju; }
   }
@@ -439,7 +443,7 @@ int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
     au.gate_want = 1; ca.gate_want = 1;
   }
   HIPCHK(au_launch(h, h->fmt, au, st));
-  HIPCHK(col_launch(h, h->fmt, ca, st));
+  HIPCHK(col_launch(h, h->colfmt, ca, st));
   HIPCHK(launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st));
   HIPCHK(launch_qr(qr_args(h, QR_GD), st));
   return ALTGDMIN_OK;
@@ -486,6 +490,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->par = *par;
   h->fmt = fmt_of(prob);
   h->hi_phase = (h->fmt == FMT_BF16X2 && par->bf16_hi_max > 0);
+  h->colfmt = (par->flags & ALTGDMIN_FLAG_BF16_MIXED) ? FMT_BF16MIX : h->fmt;
   const size_t need = carve(h, workspace);
   if (ws_bytes < need) {
     delete h;
@@ -532,7 +537,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   // hi plane alone when a BF16X2 solve starts with a hi-only phase
   ColArgs ca = col_args(h);
   ca.tau = par->tau0; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
-  if ((e = col_launch(h, h->hi_phase ? FMT_BF16HI : h->fmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
+  if ((e = col_launch(h, h->hi_phase ? FMT_BF16HI : h->colfmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
   if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
   // U_0: top-r left singular subspace of L_0 by subspace iteration
   if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, (long long)p.n * p.r, st);
@@ -615,7 +620,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     hipError_t e = hipEventRecord(ev[0], st);
     if (e == hipSuccess) e = au_launch(h, h->fmt, au, st);
     if (e == hipSuccess) e = hipEventRecord(ev[1], st);
-    if (e == hipSuccess) e = col_launch(h, h->fmt, ca, st);
+    if (e == hipSuccess) e = col_launch(h, h->colfmt, ca, st);
     if (e == hipSuccess) e = hipEventRecord(ev[2], st);
     if (e == hipSuccess) e = launch_grad(h->H, h->Bt, p.n, p.q, p.r, h->KS, h->gpart, nullptr, st);
     if (e == hipSuccess) e = hipEventRecord(ev[3], st);
@@ -799,11 +804,12 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     qa.lds = (size_t)p.n * p.r * sizeof(float) <= kQRLdsMax ? 1 : 0;
     if (qa.lds) g.qr_lds = std::max(g.qr_lds, (size_t)p.n * p.r * sizeof(float));
     g.qr.push_back(qa);
-    const int f = h->fmt, phx = f == FMT_PHILOX;
+    const int f = h->fmt, cf = h->colfmt, phx = f == FMT_PHILOX;
     const int nc = (p.m + 255) / 256, rr = (p.r + 1) / 2 * 2;
     Bucket& ab = g.au_b[f * 64 + rr];
-    Bucket& cb = g.col_b[f * 64 + nc];
-    ab.fmt = cb.fmt = f;
+    Bucket& cb = g.col_b[cf * 64 + nc];
+    ab.fmt = f;
+    cb.fmt = cf;
     ab.inst = rr;
     cb.inst = nc;
     for (int k = 0; k < p.q; ++k) {

@@ -12,7 +12,15 @@ constexpr int kNCMax = 4;            // largest number of 256-row chunks per lan
 constexpr int kQRThreads = 1024;
 
 // A-operand formats (loader template argument)
-enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2, FMT_PHILOX = 3, FMT_PFOURIER = 4 };
+enum { FMT_F32 = 0, FMT_BF16X2 = 1, FMT_BF16HI = 2, FMT_PHILOX = 3, FMT_BF16MIX = 4, FMT_PFOURIER = 5 };
+
+// The column kernel reads A_k in two roles: the gathers that form A_k s_k (and
+// so every residual) and the streaming passes (A_k^T u, and the step-length
+// product A_k g_T on the support).  The mixed BF16 form takes the exact
+// hi + lo planes for the first and the hi plane alone for the second; every
+// other format reads the same view in both roles.
+constexpr int gather_fmt(int f) { return f == FMT_BF16MIX ? FMT_BF16X2 : f; }
+constexpr int stream_fmt(int f) { return f == FMT_BF16MIX ? FMT_BF16HI : f; }
 constexpr int kNormalTable = 32 * 64 + 2;   // entries of the normal table of the Philox form
 
 // Device-side control block of one solve.
@@ -165,9 +173,13 @@ template <> struct ALoader<FMT_F32> {
       : base(static_cast<const float*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
   __device__ ALoader(const AUArgs& a, int k)
       : base(static_cast<const float*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
-  __device__ __forceinline__ float4 load(int j, int ch) const {
-    return ld_stream(base + (long long)j * lda + 4 * ch);
-  }
+  // fetch() issues the loads of 4 rows of column j; expand() turns them into
+  // FP32.  Pipelined loops keep raw_t in flight and expand at the point of use,
+  // so that a conversion never waits for loads issued after it.
+  typedef float4 raw_t;
+  __device__ __forceinline__ raw_t fetch(int j, int ch) const { return ld_stream(base + (long long)j * lda + 4 * ch); }
+  __device__ static __forceinline__ float4 expand(raw_t v) { return v; }
+  __device__ __forceinline__ float4 load(int j, int ch) const { return fetch(j, ch); }
 };
 
 template <> struct ALoader<FMT_BF16X2> {
@@ -180,17 +192,22 @@ template <> struct ALoader<FMT_BF16X2> {
   __device__ ALoader(const AUArgs& a, int k)
       : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA),
         lo(static_cast<const uint16_t*>(a.Alo) + (long long)k * a.sA), lda(a.lda) {}
-  __device__ __forceinline__ float4 load(int j, int ch) const {
+  typedef uint4 raw_t;   // (hi pair, lo pair)
+  __device__ __forceinline__ raw_t fetch(int j, int ch) const {
     const uint2 h = ld_stream(hi + (long long)j * lda + 4 * ch);
     const uint2 l = ld_stream(lo + (long long)j * lda + 4 * ch);
-    // hi + lo is exact in FP32 (lo is the bf16 rounding of the FP32 remainder)
-    float4 v;
-    v.x = bf16_to_f32(h.x & 0xffffu) + bf16_to_f32(l.x & 0xffffu);
-    v.y = bf16_to_f32(h.x >> 16) + bf16_to_f32(l.x >> 16);
-    v.z = bf16_to_f32(h.y & 0xffffu) + bf16_to_f32(l.y & 0xffffu);
-    v.w = bf16_to_f32(h.y >> 16) + bf16_to_f32(l.y >> 16);
-    return v;
+    return make_uint4(h.x, h.y, l.x, l.y);
   }
+  __device__ static __forceinline__ float4 expand(raw_t v) {
+    // hi + lo is exact in FP32 (lo is the bf16 rounding of the FP32 remainder)
+    float4 o;
+    o.x = bf16_to_f32(v.x & 0xffffu) + bf16_to_f32(v.z & 0xffffu);
+    o.y = bf16_to_f32(v.x >> 16) + bf16_to_f32(v.z >> 16);
+    o.z = bf16_to_f32(v.y & 0xffffu) + bf16_to_f32(v.w & 0xffffu);
+    o.w = bf16_to_f32(v.y >> 16) + bf16_to_f32(v.w >> 16);
+    return o;
+  }
+  __device__ __forceinline__ float4 load(int j, int ch) const { return expand(fetch(j, ch)); }
 };
 
 template <> struct ALoader<FMT_BF16HI> {
@@ -200,11 +217,13 @@ template <> struct ALoader<FMT_BF16HI> {
       : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
   __device__ ALoader(const AUArgs& a, int k)
       : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
-  __device__ __forceinline__ float4 load(int j, int ch) const {
-    const uint2 h = ld_stream(hi + (long long)j * lda + 4 * ch);
+  typedef uint2 raw_t;
+  __device__ __forceinline__ raw_t fetch(int j, int ch) const { return ld_stream(hi + (long long)j * lda + 4 * ch); }
+  __device__ static __forceinline__ float4 expand(raw_t h) {
     return make_float4(bf16_to_f32(h.x & 0xffffu), bf16_to_f32(h.x >> 16),
                        bf16_to_f32(h.y & 0xffffu), bf16_to_f32(h.y >> 16));
   }
+  __device__ __forceinline__ float4 load(int j, int ch) const { return expand(fetch(j, ch)); }
 };
 
 // Philox form: element (i, j) of A_k is word i % 4 of Philox4x32-10 (Salmon et
@@ -253,12 +272,15 @@ template <> struct ALoader<FMT_PHILOX> {
       : k0((uint32_t)a.seed), k1((uint32_t)(a.seed >> 32)), col((uint32_t)k), tab(nullptr) {}
   __device__ ALoader(const AUArgs& a, int k)
       : k0((uint32_t)a.seed), k1((uint32_t)(a.seed >> 32)), col((uint32_t)k), tab(nullptr) {}
-  __device__ __forceinline__ float4 load(int j, int ch) const {
+  typedef float4 raw_t;   // generated, not loaded: fetch() does the work
+  __device__ __forceinline__ raw_t fetch(int j, int ch) const {
     uint32_t c[4] = {(uint32_t)ch, (uint32_t)j, col, 0u};
     philox4x32_10(c, k0, k1);
     return make_float4(word_to_normal(c[0], tab), word_to_normal(c[1], tab), word_to_normal(c[2], tab),
                        word_to_normal(c[3], tab));
   }
+  __device__ static __forceinline__ float4 expand(raw_t v) { return v; }
+  __device__ __forceinline__ float4 load(int j, int ch) const { return fetch(j, ch); }
 };
 
 // Zero the components of a 4-row chunk that lie at or beyond row m (nv = valid rows, 0..4).

@@ -89,7 +89,7 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
   for (int t0 = wave; t0 < cnt; t0 += kWaves * GU) {
     // every load is issued before any is used: clamped, always legal addresses,
     // invalid rows and slots are zeroed afterwards
-    float4 av[GU][NC];
+    typename ALoader<FMT>::raw_t av[GU][NC];
     float cf[GU];
 #pragma unroll
     for (int g = 0; g < GU; ++g) {
@@ -97,13 +97,14 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
       const int j = idx[t < cnt ? t : t0];
       cf[g] = t < cnt ? coef[t] : 0.f;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) av[g][c] = L.load(j, ln.chc[c]);
+      for (int c = 0; c < NC; ++c) av[g][c] = L.fetch(j, ln.chc[c]);
     }
 #pragma unroll
     for (int g = 0; g < GU; ++g) {
       const bool ok = t0 + g * kWaves < cnt;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) acc[c] = axpy4(cf[g], mask_rows(av[g][c], ok ? ln.nv[c] : 0), acc[c]);
+      for (int c = 0; c < NC; ++c)
+        acc[c] = axpy4(cf[g], mask_rows(ALoader<FMT>::expand(av[g][c]), ok ? ln.nv[c] : 0), acc[c]);
     }
   }
   xwave_sum<NC>(acc, ln, wpart, mq, wave);
@@ -183,16 +184,18 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
   constexpr int step = kWaves * JU;
   // loads are unconditional (column clamped to n-1, chunk clamped to a legal
   // one) so that a whole group is in flight at once; consume() masks them
-  auto load = [&](int j0, float4 (&av)[JU][NC]) {
+  typedef typename ALoader<FMT>::raw_t raw_t;
+  auto load = [&](int j0, raw_t (&ar)[JU][NC]) {
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
       const int j = j0 + ju * kWaves;
       const int jc = j < n ? j : n - 1;
 #pragma unroll
-      for (int c = 0; c < NC; ++c) av[ju][c] = L.load(jc, ln.chc[c]);
+      for (int c = 0; c < NC; ++c) ar[ju][c] = L.fetch(jc, ln.chc[c]);
     }
   };
-  auto consume = [&](int j0, float4 (&av)[JU][NC]) {
+  auto consume = [&](int j0, const raw_t (&ar)[JU][NC]) {
+    float4 av[JU][NC];
     float d[JU];
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
@@ -200,7 +203,7 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
       float s = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        av[ju][c] = mask_rows(av[ju][c], ok ? ln.nv[c] : 0);
+        av[ju][c] = mask_rows(ALoader<FMT>::expand(ar[ju][c]), ok ? ln.nv[c] : 0);
         s += dot4(av[ju][c], u[c]);
       }
       d[ju] = s;
@@ -220,20 +223,23 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
       }
     }
   };
-  float4 a0[JU][NC], a1[JU][NC];
-  int j0 = wave;
-  load(j0, a0);
-  for (;;) {
-    const int j1 = j0 + step;
-    if (j1 < n) load(j1, a1);
+  // Two groups in flight: the next group is loaded before the current one is
+  // reduced.  The loop has one exit and loads without a condition (past the
+  // end they re-read column n - 1 and are dropped): with a load under a branch,
+  // or a second exit, the compiler waits for the newer loads as well before
+  // the older group is reduced, and the two groups no longer overlap.
+  const int groups = wave < n ? (n - wave + step - 1) / step : 0;
+  raw_t a0[JU][NC], a1[JU][NC];
+  load(wave, a0);
+  int g = 0;
+  for (; g + 1 < groups; g += 2) {
+    const int j0 = wave + g * step;
+    load(j0 + step, a1);
     consume(j0, a0);
-    if (j1 >= n) break;
-    const int j2 = j1 + step;
-    if (j2 < n) load(j2, a0);
-    consume(j1, a1);
-    if (j2 >= n) break;
-    j0 = j2;
+    load(j0 + 2 * step, a0);
+    consume(j0 + step, a1);
   }
+  if (g < groups) consume(wave + g * step, a0);
 }
 
 // HardThreshold of Alg. 2 on vals[0..n) (LDS): the rho entries of largest
@@ -337,11 +343,14 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   const int mq = lay.mq;
   const int nwords = (n + 31) >> 5;
 
-  ALoader<FMT> L(a, k);
+  constexpr int GF = gather_fmt(FMT), SF = stream_fmt(FMT);
+  ALoader<GF> L(a, k);    // A_k s_k: exact
+  ALoader<SF> Ls(a, k);   // A_k^T u and the step length: the streaming view
   if constexpr (FMT == FMT_PHILOX) {
     float* tab = reinterpret_cast<float*>(smem + lay.tab);
     for (int t = tid; t < kNormalTable; t += kThreads) tab[t] = a.table[t];
     L.tab = tab;   // read only after the barrier that ends the LDS set-up below
+    Ls.tab = tab;
   }
   const Lane<NC> ln(lane, m);
 
@@ -389,7 +398,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   for (int it = 0; it < a.tau; ++it) {
     // u = Pi (A_k s - y_k)   (Pi = I in the initialisation)
     float4 v[NC];
-    gather<FMT, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
+    gather<GF, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);
     if (a.project) project<NC>(v, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
@@ -399,7 +408,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
 #pragma unroll
     for (int c = 0; c < NC; ++c) w[c] = make_float4(0.f, 0.f, 0.f, 0.f);
     double gT2 = 0.0;
-    fused_pass<FMT, NC, JU>(L, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
+    fused_pass<SF, NC, JU>(Ls, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
     __syncthreads();
     if (hasT) {
       xwave_sum<NC>(w, ln, wpart, mq, wave);
@@ -407,7 +416,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     } else {
       // no support yet (s = 0): restrict to the support of HardThreshold(g, rho)
       nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
-      gather<FMT, NC>(L, ln, Ti, Tv, rho, w, wpart, mq, wave);
+      gather<SF, NC>(Ls, ln, Ti, Tv, rho, w, wpart, mq, wave);
       gT2 = 0.0;
       for (int t = 0; t < rho; ++t) gT2 = fma((double)Tv[t], (double)Tv[t], gT2);
     }
@@ -436,7 +445,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
 
   if (a.tail != TAIL_NONE) {
     float4 v[NC];
-    gather<FMT, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
+    gather<GF, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);   // A_k s_k - y_k
     if (a.tail == TAIL_LSGRAD) {
@@ -454,7 +463,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     }
     float4 w[NC];
     double dummy = 0.0;
-    fused_pass<FMT, NC, JU>(L, ln, v, n, gl, nullptr, w, dummy, lane, wave);
+    fused_pass<SF, NC, JU>(Ls, ln, v, n, gl, nullptr, w, dummy, lane, wave);
     __syncthreads();
     for (int j = tid; j < n; j += kThreads) a.H[(long long)k * n + j] = gl[j];
   }
@@ -466,8 +475,18 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   if (tid == 0 && nan_seen > 0 && a.flags) a.flags[k] |= 1;
 }
 
+// Minimum waves per SIMD asked of the register allocator: four (at most 128
+// VGPRs) where the column pass fits in them without spilling, fewer where the
+// format's conversion (BF16 pairs, the Philox rounds) needs more registers.
+constexpr int col_min_waves(int fmt, int nc, int ju) {
+  // e: the loads in flight per lane, in units of one FP32 float4 column chunk
+  // (the hi plane alone is half of one, the two BF16 planes one more)
+  const int e = stream_fmt(fmt) == FMT_BF16HI ? (ju + 1) / 2 : ju + (fmt == FMT_BF16X2);
+  return nc > 2 || fmt == FMT_PHILOX ? (nc > 2 ? 1 : 2) : nc == 1 ? 4 : (e >= 3 ? 2 : (e == 2 ? 3 : 4));
+}
+
 template <int FMT, int NC, int JU = default_ju(NC)>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col(ColArgs a) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(col_min_waves(FMT, NC, JU), 8))) void k_col(ColArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   col_body<FMT, NC, JU>(a, blockIdx.x, smem);
@@ -475,7 +494,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
 template <int FMT, int NC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(NC <= 2 ? 4 : 1, 8))) void k_col_grp(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(col_min_waves(FMT, NC, default_ju(NC)), 8))) void k_col_grp(
     const ColArgs* tab, const int2* map) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
@@ -534,9 +553,10 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   constexpr int RP = (R + 3) / 4 * 4;
   float* Uw = reinterpret_cast<float*>(smem + lay.P) + wave * 64 * RP;   // shares the P region
   const float* U = a.U;
-  auto fetch = [&](int j, float4& a4) {
+  typedef typename ALoader<FMT>::raw_t raw_t;
+  auto fetch = [&](int j, raw_t& a4) {
     const int jc = j < n ? j : n - 1;   // clamped: always a legal address
-    a4 = L.load(jc, chc);
+    a4 = L.fetch(jc, chc);
   };
   float un[RP];
   auto load_rows = [&](int t0) {        // rows of columns jw + js (t0 + t), t = lane
@@ -563,27 +583,40 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
 #pragma unroll
       for (int rr = 0; rr < R; ++rr) acc[e][rr] = fmaf(get4(a4, e), u[rr], acc[e][rr]);
   };
+  auto stage = [&](int t) {             // wave-local: the LDS accesses of one wave complete in order
+    __builtin_amdgcn_wave_barrier();
+    load_rows(t);
+    store_rows(t);
+    __builtin_amdgcn_wave_barrier();
+  };
   if (active) {
-    float4 buf[AUD];
+    // t-th column of this wave: j = jw + t js.  AUD + 1 slots in rotation: the
+    // slot refilled at step t is the one consumed at step t - 1, so that no
+    // register holding a load in flight is ever copied (a copy would wait for
+    // it).  Refills in the main loop are not under a condition (past the end
+    // they re-read column n - 1 and are dropped).
+    constexpr int NB = AUD + 1;
+    const int cols = jw < n ? (n - jw + js - 1) / js : 0;
+    raw_t buf[NB];
 #pragma unroll
     for (int d = 0; d < AUD; ++d) fetch(jw + d * js, buf[d]);
-    int cnt = 0;                        // columns of this wave done so far
-    for (int j = jw; j < n; j += AUD * js) {
+    int t = 0;
+    for (; t + NB <= cols; t += NB) {
 #pragma unroll
-      for (int d = 0; d < AUD; ++d) {
-        const int jj = j + d * js;
-        if (jj < n) {
-          if ((cnt & 63) == 0) {         // wave-local: the LDS accesses of one wave complete in order
-            __builtin_amdgcn_wave_barrier();
-            load_rows(cnt);
-            store_rows(cnt);
-            __builtin_amdgcn_wave_barrier();
-          }
-          const float4 cur = buf[d];
-          fetch(jj + AUD * js, buf[d]);
-          fma_col(cur, cnt & 63);
-          ++cnt;
-        }
+      for (int d = 0; d < NB; ++d) {
+        const int tt = t + d;
+        if ((tt & 63) == 0) stage(tt);
+        fetch(jw + (tt + AUD) * js, buf[(d + AUD) % NB]);
+        fma_col(ALoader<FMT>::expand(buf[d]), tt & 63);
+      }
+    }
+#pragma unroll
+    for (int d = 0; d < NB; ++d) {
+      const int tt = t + d;
+      if (tt < cols) {
+        if ((tt & 63) == 0) stage(tt);
+        if (d + AUD < NB) fetch(jw + (tt + AUD) * js, buf[d + AUD]);
+        fma_col(ALoader<FMT>::expand(buf[d]), tt & 63);
       }
     }
   }
@@ -729,11 +762,11 @@ typedef void (*colg_fn)(const ColArgs*, const int2*);
 typedef void (*aug_fn)(const AUArgs*, const int2*);
 
 #define COL_ROW(F) {k_col<F, 1>, k_col<F, 2>, k_col<F, 3>, k_col<F, 4>}
-static const col_fn kColTable[4][kNCMax] = {COL_ROW(FMT_F32), COL_ROW(FMT_BF16X2), COL_ROW(FMT_BF16HI),
-                                            COL_ROW(FMT_PHILOX)};
+static const col_fn kColTable[5][kNCMax] = {COL_ROW(FMT_F32), COL_ROW(FMT_BF16X2), COL_ROW(FMT_BF16HI),
+                                            COL_ROW(FMT_PHILOX), COL_ROW(FMT_BF16MIX)};
 #define COLG_ROW(F) {k_col_grp<F, 1>, k_col_grp<F, 2>, k_col_grp<F, 3>, k_col_grp<F, 4>}
-static const colg_fn kColGrpTable[4][kNCMax] = {COLG_ROW(FMT_F32), COLG_ROW(FMT_BF16X2), COLG_ROW(FMT_BF16HI),
-                                                COLG_ROW(FMT_PHILOX)};
+static const colg_fn kColGrpTable[5][kNCMax] = {COLG_ROW(FMT_F32), COLG_ROW(FMT_BF16X2), COLG_ROW(FMT_BF16HI),
+                                                COLG_ROW(FMT_PHILOX), COLG_ROW(FMT_BF16MIX)};
 #define AU_ROW(F) {k_au<F, 2>, k_au<F, 4>, k_au<F, 6>, k_au<F, 8>, k_au<F, 10>, k_au<F, 12>, k_au<F, 14>, k_au<F, 16>}
 static const au_fn kAUTable[4][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2), AU_ROW(FMT_BF16HI), AU_ROW(FMT_PHILOX)};
 #define AUG_ROW(F) {k_au_grp<F, 2>, k_au_grp<F, 4>, k_au_grp<F, 6>, k_au_grp<F, 8>, k_au_grp<F, 10>, k_au_grp<F, 12>, \
@@ -744,6 +777,7 @@ static const aug_fn kAUGrpTable[4][kRMax / 2] = {AUG_ROW(FMT_F32), AUG_ROW(FMT_B
 bool au_supported(int m, int r) { return m >= 1 && m <= 256 * kNCMax && r >= 1 && r <= kRMax; }
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
+  if (fmt < FMT_F32 || fmt > FMT_BF16MIX) return hipErrorInvalidValue;
   const int nc = (a.m + 255) / 256;
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
@@ -752,6 +786,7 @@ hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
+  if (fmt < FMT_F32 || fmt > FMT_PHILOX) return hipErrorInvalidValue;   // A_k U is exact in every form
   const int ri = (a.r + 1) / 2 - 1;
   const AULayout lay(a.m, a.r, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
@@ -760,12 +795,14 @@ hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_col_grp(int fmt, int nc, const ColArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st) {
+  if (fmt < FMT_F32 || fmt > FMT_BF16MIX) return hipErrorInvalidValue;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColGrpTable[fmt][nc - 1], dim3(blocks), dim3(kThreads), lds, st, tab, map);
   return hipGetLastError();
 }
 
 hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st) {
+  if (fmt < FMT_F32 || fmt > FMT_PHILOX) return hipErrorInvalidValue;
   const int ri = (rmax + 1) / 2 - 1;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kAUGrpTable[fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab, map);
@@ -811,13 +848,13 @@ hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q
 #endif  // part 1
 
 #if ALTG_PART == 2
-// Autotuned variants of the plane formats: k_col with JU in {1, 2, 3} and k_au
-// with AUD in {1, 2, 4}.  Every variant gives the same bits as the default one.
+// Autotuned variants of the plane formats: k_col with JU in {1, 2, 3} (FP32,
+// BF16X2 and the mixed BF16 form) and k_au with AUD in {1, 2, 4} (FP32, BF16X2).  Every variant gives the same bits as the default one.
 typedef void (*col_fn2)(ColArgs);
 typedef void (*au_fn2)(AUArgs);
 #define COLT_NC(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 3>}
 #define COLT_F(F) {COLT_NC(F, 1), COLT_NC(F, 2), COLT_NC(F, 3), COLT_NC(F, 4)}
-static const col_fn2 kColTuned[2][kNCMax][3] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2)};
+static const col_fn2 kColTuned[3][kNCMax][3] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2), COLT_F(FMT_BF16MIX)};
 #define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 4>}
 #define AUT_F(F) {AUT_R(F, 2), AUT_R(F, 4), AUT_R(F, 6), AUT_R(F, 8), AUT_R(F, 10), AUT_R(F, 12), AUT_R(F, 14), AUT_R(F, 16)}
 static const au_fn2 kAUTuned[2][kRMax / 2][3] = {AUT_F(FMT_F32), AUT_F(FMT_BF16X2)};
@@ -831,11 +868,12 @@ static int tuned_slot(int v, const int (&vals)[3]) {
 hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
   static const int kJU[3] = {1, 2, 3};
   const int slot = tuned_slot(ju, kJU);
-  if ((fmt != FMT_F32 && fmt != FMT_BF16X2) || slot < 0) return hipErrorInvalidValue;
+  const int row = fmt == FMT_F32 ? 0 : fmt == FMT_BF16X2 ? 1 : fmt == FMT_BF16MIX ? 2 : -1;
+  if (row < 0 || slot < 0) return hipErrorInvalidValue;
   const int nc = (a.m + 255) / 256;
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, 0);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kColTuned[fmt == FMT_F32 ? 0 : 1][nc - 1][slot], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  hipLaunchKernelGGL(kColTuned[row][nc - 1][slot], dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
 }
 

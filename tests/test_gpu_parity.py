@@ -330,6 +330,34 @@ def test_solve_matches_oracle(lib, torch, shape, iters):
     assert abs(out["status"]["eta"] - st.eta) <= 1e-3 * st.eta
 
 
+@pytest.mark.parametrize("shape,iters", [(dict(n=100, q=100, m=40, r=2, rho=2), 120),
+                                         (dict(n=301, q=64, m=150, r=3, rho=7), 60),
+                                         (dict(n=400, q=64, m=300, r=3, rho=8), 40)])   # two row chunks
+def test_mixed_bf16_solve_matches_oracle(lib, torch, shape, iters):
+    """Mixed BF16 form: residual products with hi + lo, transposed products and IHT step
+    lengths with the hi plane, against the FP64 oracle of that variant (A_t = hi plane)."""
+    inst = I.make_instance(**shape, seed=231103824, bf16_planes=True)
+    out = _solve(lib, torch, inst, iters, bf16=True, flags=lib.FLAG_BF16_MIXED)
+    st, hist = O.solve(inst.A64(), inst.Y32.astype(np.float64), inst.r, inst.rho, t_max=iters,
+                       X_star=inst.X_star, A_t=inst.A64_hi())
+    assert out["status"]["iterations"] == iters and out["status"]["error_flags"] == 0
+    assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+    assert abs(out["status"]["eta"] - st.eta) <= 1e-3 * st.eta
+
+
+def test_mixed_bf16_rejects_a_hi_phase_and_plain_planes(lib, torch):
+    inst = I.make_instance(n=100, q=8, m=40, r=2, rho=2, seed=3, bf16_planes=True)
+    with pytest.raises(lib.AltGDminError):
+        lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho,
+                   lib.default_params(flags=lib.FLAG_BF16_MIXED, bf16_hi_max=5), A_hi=inst.A_hi, A_lo=inst.A_lo)
+    with pytest.raises(lib.AltGDminError):
+        lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, lib.default_params(flags=lib.FLAG_BF16_MIXED))
+
+
 def test_bf16_split_equals_fp32(lib, torch):
     """hi + lo is the canonical A exactly, so the BF16-split form reproduces the FP32 form bitwise."""
     inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=4, bf16_planes=True)
@@ -488,24 +516,25 @@ def test_step_many_equals_solo(lib, torch):
     """Each problem gives the same result alone and batched with others of other sizes and formats."""
     specs = [dict(n=300, q=40, m=120, r=2, rho=5, seed=1, bf16=False),
              dict(n=257, q=33, m=700, r=16, rho=3, seed=2, bf16=True),     # 3 chunks, P_k in global memory
-             dict(n=640, q=70, m=250, r=5, rho=20, seed=3, bf16=False)]
+             dict(n=640, q=70, m=250, r=5, rho=20, seed=3, bf16=False),
+             dict(n=300, q=40, m=120, r=2, rho=5, seed=4, bf16=True, mixed=True)]   # mixed BF16 form
     insts = [I.make_instance(n=s["n"], q=s["q"], m=s["m"], r=s["r"], rho=s["rho"], seed=s["seed"],
                              bf16_planes=s["bf16"]) for s in specs]
     iters = 25
 
-    def solver(inst, bf16):
-        par = lib.default_params(t_max=iters)
-        if bf16:
+    def solver(inst, sp):
+        par = lib.default_params(t_max=iters, flags=lib.FLAG_BF16_MIXED if sp.get("mixed") else 0)
+        if sp["bf16"]:
             return lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=inst.A_hi, A_lo=inst.A_lo)
         return lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par)
 
     solo = []
     for inst, sp in zip(insts, specs):
-        s = solver(inst, sp["bf16"])
+        s = solver(inst, sp)
         s.init().step(iters)
         solo.append(s.get())
         s.close()
-    group = [solver(inst, sp["bf16"]) for inst, sp in zip(insts, specs)]
+    group = [solver(inst, sp) for inst, sp in zip(insts, specs)]
     for s in group:
         s.init()
     hs = [s.h for s in group]

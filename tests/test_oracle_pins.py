@@ -238,3 +238,47 @@ def test_column_permutation_equivariance():
     st1, _ = O.solve(A, inst.Y64, 2, 2, t_max=10)
     st2, _ = O.solve(A[perm], inst.Y64[perm], 2, 2, t_max=10)
     assert np.allclose(O.estimate(st2), O.estimate(st1)[:, perm], rtol=1e-9, atol=1e-9)
+
+
+# ---------------------------------------------------------------- mixed-precision variant
+# A_t (here the bf16 hi plane of A) replaces A in the transposed products and the
+# IHT step length only; the products that form residuals keep A.
+
+
+def _truth_state(inst):
+    return O.State(U=inst.U_star.copy(), S=inst.S_star.T.copy(), idx=inst.supp.copy(), eta=0.1)
+
+
+def test_mixed_variant_with_A_t_equal_A_is_the_plain_method():
+    inst, A, Y = _small(bf16_planes=True)
+    a, ha = O.solve(A, Y, inst.r, inst.rho, t_max=5, X_star=inst.X_star)
+    b, hb = O.solve(A, Y, inst.r, inst.rho, t_max=5, X_star=inst.X_star, A_t=A)
+    assert np.array_equal(a.U, b.U) and np.array_equal(a.idx, b.idx) and ha == hb
+
+
+def test_mixed_variant_keeps_the_exact_fixed_point():
+    """Noise-free data: from (U*, S*) one mixed iteration returns X* to rounding, because
+    every residual is formed with the exact A; taking the hi plane for the residuals as
+    well (the planted mistake) moves the iterate by about the bf16 relative error."""
+    inst = I.make_instance(120, 30, 60, 3, 4, 17, bf16_planes=True)
+    A, Y, Ahi = inst.A64(), inst.Y64, inst.A64_hi()
+    assert 1e-4 < np.abs(A - Ahi).max() / np.abs(A).max() < 1e-2      # the planes differ
+    st = O.gdmin_iteration(A, Y, _truth_state(inst), inst.rho, A_t=Ahi)
+    assert O.rel_error(O.estimate(st), inst.X_star) < 1e-12
+    assert O.subspace_distance(st.U, inst.U_star) < 1e-12
+    assert np.array_equal(st.idx, inst.supp)
+    bad = O.gdmin_iteration(Ahi, Y, _truth_state(inst), inst.rho)
+    assert O.rel_error(O.estimate(bad), inst.X_star) > 1e-5
+
+
+def test_mixed_variant_recovers_exactly_n100():
+    """The paper's exact-recovery size with A_t = bf16 hi plane: Error < 1e-10 as in the
+    plain method, within a few more iterations; the hi plane alone stalls far above."""
+    inst = I.make_workload("gauss_n100_q100_m40_r2_rho2", bf16_planes=True)
+    A, Y, Ahi = inst.A64(), inst.Y64, inst.A64_hi()
+    _, h_plain = O.solve(A, Y, inst.r, inst.rho, t_max=300, X_star=inst.X_star, err_tol=1e-10)
+    st, h_mix = O.solve(A, Y, inst.r, inst.rho, t_max=300, X_star=inst.X_star, err_tol=1e-10, A_t=Ahi)
+    assert h_mix[-1] < 1e-10 and len(h_mix) <= len(h_plain) + 10
+    assert np.array_equal(st.idx, inst.supp)
+    _, h_hi = O.solve(Ahi, Y, inst.r, inst.rho, t_max=len(h_mix), X_star=inst.X_star)
+    assert min(h_hi) > 1e-5
