@@ -18,7 +18,8 @@
  *  - Layout of A (format ALTGDMIN_A_F32): A_k is column-major with the row
  *    index fastest: element (i, j) of A_k is A[k*a_stride_k + j*lda + i].
  *    lda >= m and lda, a_stride_k and the base address must be multiples of 4
- *    floats (16 bytes).  Rows m..lda-1 are ignored.
+ *    floats (16 bytes).  Rows m..lda-1 do not change any result but are read, so
+ *    they must hold finite values (zeros, as altgdmin_op_make_a writes them).
  *    Format ALTGDMIN_A_BF16X2: A_k = hi + lo with hi and lo bfloat16 planes of
  *    the same layout (uint16 elements; lda, a_stride_k multiples of 8).
  *  - Y: y_k at Y[k*ldy + i], ldy >= m.
@@ -179,7 +180,7 @@ int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, voi
 int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out);
 
 /* Autotuner (with ALTGDMIN_FLAG_AUTOTUNE): the column-kernel unroll JU (columns
- * per load group, 1..3) and the A_k U pipeline depth AUD (1, 2 or 4) chosen for
+ * per load group, 1, 2 or 4) and the A_k U pipeline depth AUD (1, 2 or 4) chosen for
  * this handle; 0 means the default instantiation.  The choice is made once per
  * (GPU architecture, A format, n, q, m, r, rho) in a process by timing each
  * variant three times on the problem's own data (A_k U from a fixed orthonormal

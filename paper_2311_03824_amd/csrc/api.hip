@@ -344,7 +344,8 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     if (e != hipSuccess) break;
     if (ms < best_au) { best_au = ms; best_aud = aud; }
   }
-  for (int ju = 1; ju <= 3 && e == hipSuccess; ++ju) {
+  for (int ju : {1, 2, 4}) {
+    if (e != hipSuccess) break;
     float ms = 0.f;
     e = timed([&] { return launch_col_tuned(h->colfmt, ju, ca, st); }, &ms);
     if (e != hipSuccess) break;

@@ -167,15 +167,58 @@ __device__ __forceinline__ double sumsq(const float4 (&v)[NC]) {
   return wave_sum_dpp(s);
 }
 
+// Totals over the 64 lanes of JU per-lane partial sums at once (JU = 1, 2, 4):
+// on return lane i < JU holds the total of x[i].  The lanes are paired in one
+// fixed order for every JU -- l ^ 1 and l ^ 2 (quad permutations), rotations
+// by 4 and 8 within each row of 16, then rows r ^ 1 and halves (permlane
+// swaps) -- and with JU > 1 each lane carries the column it will end with from
+// the first step on, so a column's total has the same bits for every JU.
+template <int JU>
+__device__ __forceinline__ float col_totals(const float (&x)[JU], int lane) {
+  static_assert(JU == 1 || JU == 2 || JU == 4, "JU must be 1, 2 or 4");
+  auto dpp = [](float v, int ctrl) -> float {
+    switch (ctrl) {   // constant after inlining
+      case 0xB1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
+      case 0x4E: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
+      case 0x124: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false));
+      default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false));
+    }
+  };
+  float v;
+  if constexpr (JU == 1) {
+    v = x[0] + dpp(x[0], 0xB1);
+    v = v + dpp(v, 0x4E);
+  } else if constexpr (JU == 2) {
+    const bool odd = lane & 1;
+    const float a = odd ? x[1] : x[0], b = odd ? x[0] : x[1];
+    v = a + dpp(b, 0xB1);            // lane parity p: column p
+    v = v + dpp(v, 0x4E);
+  } else {
+    const bool odd = lane & 1, two = lane & 2;
+    const float a = odd ? x[1] : x[0], b = odd ? x[0] : x[1];
+    const float c = odd ? x[3] : x[2], d = odd ? x[2] : x[3];
+    const float ab = a + dpp(b, 0xB1);   // even lanes: column 0, odd: column 1
+    const float cd = c + dpp(d, 0xB1);   // even lanes: column 2, odd: column 3
+    const float e = two ? cd : ab, f = two ? ab : cd;
+    v = e + dpp(f, 0x4E);                // lane & 3: column
+  }
+  v = v + dpp(v, 0x124);                 // row_ror:4
+  v = v + dpp(v, 0x128);                 // row_ror:8
+  const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  v = __uint_as_float(p[0]) + __uint_as_float(p[1]);     // rows r and r ^ 1
+  const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
+  return __uint_as_float(h[0]) + __uint_as_float(h[1]);  // lanes l and l ^ 32
+}
+
 // Streaming pass over A_k: gl[j] = A_j^T u for every column j; for j in the
 // support bitmap inT (if given) also wacc += gl[j] * A_j and gT2 += gl[j]^2.
 // Wave w takes columns j = w, w + 4, ...; groups of JU columns are loaded one
-// group ahead of the one being reduced.  JU keeps about 4-6 float4 loads per
-// lane in flight (measured best: JU = 3 for one 256-row chunk, 1 for more).
-// The order in which a wave visits the columns does not depend on JU, so every
-// JU gives the same bits.
+// group ahead of the one being reduced, and reduced together (col_totals).
+// u must be zero on rows >= m (and A finite there): the products are then not
+// masked.  The order in which a wave visits the columns and every column's
+// reduction tree do not depend on JU, so every JU gives the same bits.
 // default loads in flight (autotuned variants pass another JU)
-constexpr int default_ju(int nc) { return nc == 1 ? 3 : 1; }
+constexpr int default_ju(int nc) { return nc == 1 ? 4 : 2; }
 
 template <int FMT, int NC, int JU>
 __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
@@ -183,7 +226,7 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
                                            double& gT2, int lane, int wave) {
   constexpr int step = kWaves * JU;
   // loads are unconditional (column clamped to n-1, chunk clamped to a legal
-  // one) so that a whole group is in flight at once; consume() masks them
+  // one) so that a whole group is in flight at once; consume() drops them
   typedef typename ALoader<FMT>::raw_t raw_t;
   auto load = [&](int j0, raw_t (&ar)[JU][NC]) {
 #pragma unroll
@@ -199,26 +242,26 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
     float d[JU];
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
-      const bool ok = j0 + ju * kWaves < n;
       float s = 0.f;
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
-        av[ju][c] = mask_rows(ALoader<FMT>::expand(ar[ju][c]), ok ? ln.nv[c] : 0);
+        av[ju][c] = ALoader<FMT>::expand(ar[ju][c]);
         s += dot4(av[ju][c], u[c]);
       }
       d[ju] = s;
     }
+    const float tot = col_totals<JU>(d, lane);
+    const int jl = j0 + lane * kWaves;
+    if (lane < JU && jl < n) gl[jl] = tot;
+    if (inT) {
 #pragma unroll
-    for (int ju = 0; ju < JU; ++ju) d[ju] = wave_sum_dpp(d[ju]);
+      for (int ju = 0; ju < JU; ++ju) {
+        const int j = j0 + ju * kWaves;
+        if (j < n && ((inT[j >> 5] >> (j & 31)) & 1u)) {
+          const float dj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), ju));
 #pragma unroll
-    for (int ju = 0; ju < JU; ++ju) {
-      const int j = j0 + ju * kWaves;
-      if (j < n) {
-        if (lane == 0) gl[j] = d[ju];
-        if (inT && ((inT[j >> 5] >> (j & 31)) & 1u)) {
-#pragma unroll
-          for (int c = 0; c < NC; ++c) wacc[c] = axpy4(d[ju], av[ju][c], wacc[c]);
-          gT2 = fma((double)d[ju], (double)d[ju], gT2);
+          for (int c = 0; c < NC; ++c) wacc[c] = axpy4(dj, mask_rows(av[ju][c], ln.nv[c]), wacc[c]);
+          gT2 = fma((double)dj, (double)dj, gT2);
         }
       }
     }
@@ -475,14 +518,15 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   if (tid == 0 && nan_seen > 0 && a.flags) a.flags[k] |= 1;
 }
 
-// Minimum waves per SIMD asked of the register allocator: four (at most 128
-// VGPRs) where the column pass fits in them without spilling, fewer where the
-// format's conversion (BF16 pairs, the Philox rounds) needs more registers.
+// Minimum waves per SIMD asked of the register allocator (4 waves: at most 128
+// VGPRs): as many as the column pass fits without spilling.  The loads in
+// flight grow with NC and JU; the two BF16 planes and the Philox rounds need
+// more registers than one FP32 or hi plane.
 constexpr int col_min_waves(int fmt, int nc, int ju) {
-  // e: the loads in flight per lane, in units of one FP32 float4 column chunk
-  // (the hi plane alone is half of one, the two BF16 planes one more)
-  const int e = stream_fmt(fmt) == FMT_BF16HI ? (ju + 1) / 2 : ju + (fmt == FMT_BF16X2);
-  return nc > 2 || fmt == FMT_PHILOX ? (nc > 2 ? 1 : 2) : nc == 1 ? 4 : (e >= 3 ? 2 : (e == 2 ? 3 : 4));
+  if (fmt == FMT_PHILOX) return nc <= 2 ? 2 : 1;
+  if (nc == 1) return 4;
+  if (nc == 2) return ju == 1 ? 4 : (ju == 2 ? (fmt == FMT_BF16X2 ? 3 : 4) : (fmt == FMT_BF16X2 ? 2 : 3));
+  return ju == 4 ? 1 : 2;
 }
 
 template <int FMT, int NC, int JU = default_ju(NC)>
@@ -848,11 +892,11 @@ hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q
 #endif  // part 1
 
 #if ALTG_PART == 2
-// Autotuned variants of the plane formats: k_col with JU in {1, 2, 3} (FP32,
+// Autotuned variants of the plane formats: k_col with JU in {1, 2, 4} (FP32,
 // BF16X2 and the mixed BF16 form) and k_au with AUD in {1, 2, 4} (FP32, BF16X2).  Every variant gives the same bits as the default one.
 typedef void (*col_fn2)(ColArgs);
 typedef void (*au_fn2)(AUArgs);
-#define COLT_NC(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 3>}
+#define COLT_NC(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 4>}
 #define COLT_F(F) {COLT_NC(F, 1), COLT_NC(F, 2), COLT_NC(F, 3), COLT_NC(F, 4)}
 static const col_fn2 kColTuned[3][kNCMax][3] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2), COLT_F(FMT_BF16MIX)};
 #define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 4>}
@@ -866,7 +910,7 @@ static int tuned_slot(int v, const int (&vals)[3]) {
 }
 
 hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
-  static const int kJU[3] = {1, 2, 3};
+  static const int kJU[3] = {1, 2, 4};
   const int slot = tuned_slot(ju, kJU);
   const int row = fmt == FMT_F32 ? 0 : fmt == FMT_BF16X2 ? 1 : fmt == FMT_BF16MIX ? 2 : -1;
   if (row < 0 || slot < 0) return hipErrorInvalidValue;

@@ -388,7 +388,7 @@ def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatc
     b = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE)
     c = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE | lib.FLAG_EAGER)
     assert a["tuning"] == {"col_unroll": 0, "au_depth": 0}
-    assert b["tuning"]["col_unroll"] in (1, 2, 3) and b["tuning"]["au_depth"] in (1, 2, 4)
+    assert b["tuning"]["col_unroll"] in (1, 2, 4) and b["tuning"]["au_depth"] in (1, 2, 4)
     assert c["tuning"] == b["tuning"]              # the second init reuses the process-wide choice
     for key in ("U", "Bt", "S_idx", "S_val"):
         assert np.array_equal(a[key], b[key]), key
