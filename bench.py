@@ -36,15 +36,18 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def column_kernel_bytes(n, q, m, r, rho, tau, a_bytes=4.0):
+def column_kernel_bytes(n, q, m, r, rho, tau, a_bytes=4.0, gather_bytes=None):
     """Algorithmic HBM bytes of one launch of the column kernel (tau IHT iterations + LS/gradient tail).
 
     Per column: (tau + 1) streaming passes over A_k (m n elements), (tau + 1)
     gathers of the rho support columns (rho m elements), y_k, P_k (m r FP32),
     G_k^{-1} (r^2 FP64), the support in and out (2 rho (4 + 4) bytes), h_k
-    (n FP32), b_k (r FP32) and ||r_k||^2.
+    (n FP32), b_k (r FP32) and ||r_k||^2.  a_bytes: bytes per element of the
+    streaming passes; gather_bytes: of the support gathers (default a_bytes;
+    the mixed BF16 form streams 2 bytes and gathers 4).
     """
-    per_col = ((tau + 1) * m * n * a_bytes + (tau + 1) * rho * m * a_bytes + 4 * m + 4 * m * r
+    gb = a_bytes if gather_bytes is None else gather_bytes
+    per_col = ((tau + 1) * m * n * a_bytes + (tau + 1) * rho * m * gb + 4 * m + 4 * m * r
                + 8 * r * r + 16 * rho + 4 * n + 4 * r + 8)
     return per_col * q
 
@@ -80,7 +83,9 @@ def committed_traffic(kernel_srcs, profile: str):
 
 
 def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
-    """Wall time of altgdmin_solve until ||Y - A(UB+S)||/||Y|| <= target, per form of A, and the final error.
+    """Wall time of altgdmin_solve until ||Y - A(UB+S)||/||Y|| <= target (median of five solves,
+    each from scratch: initialisation, graph capture, iterations, polls), per form of A, and the
+    final error.
 
     fp32: FP32 plane.  bf16x2: BF16 hi plane alone until the residual stalls (resid_t >=
     0.9 resid_{t-1}) or 200 iterations, then hi + lo.  bf16_mixed: hi + lo for every
@@ -92,8 +97,9 @@ def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
     A_hi = torch.from_numpy(np.ascontiguousarray(inst.A_hi).view(np.int16)).cuda()
     A_lo = torch.from_numpy(np.ascontiguousarray(inst.A_lo).view(np.int16)).cuda()
     tune = lib.FLAG_AUTOTUNE
+    A32 = torch.from_numpy(np.ascontiguousarray(inst.At)).cuda()
     forms = {
-        "fp32": (lib.make_problem(fp32_solver.A, fp32_solver.Y, r, rho, m=m), {"flags": tune}),
+        "fp32": (lib.make_problem(A32, fp32_solver.Y, r, rho, m=m), {"flags": tune}),
         "bf16x2": (lib.make_problem(A_hi, fp32_solver.Y, r, rho, A_lo=A_lo, m=m),
                    {"bf16_hi_max": 200, "bf16_stall": 0.9}),
         "bf16_mixed": (lib.make_problem(A_hi, fp32_solver.Y, r, rho, A_lo=A_lo, m=m),
@@ -106,12 +112,15 @@ def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
         Bt = torch.empty((q, r), dtype=torch.float32, device="cuda")
         Si = torch.empty((q, rho), dtype=torch.int32, device="cuda")
         Sv = torch.empty((q, rho), dtype=torch.float32, device="cuda")
-        lib.altgdmin_solve(prob, par, ws, U, Bt, Si, Sv)           # warm-up (graph capture, caches)
+        lib.altgdmin_solve(prob, par, ws, U, Bt, Si, Sv)           # warm-up (autotuner, caches)
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rc, rep = lib.altgdmin_solve(prob, par, ws, U, Bt, Si, Sv)
-        torch.cuda.synchronize()
-        ms = (time.perf_counter() - t0) * 1e3
+        times = []
+        for _ in range(5):                                           # median of five whole solves
+            t0 = time.perf_counter()
+            rc, rep = lib.altgdmin_solve(prob, par, ws, U, Bt, Si, Sv)
+            torch.cuda.synchronize()
+            times.append((time.perf_counter() - t0) * 1e3)
+        ms = float(np.median(times))
         X = U.cpu().numpy().astype(np.float64) @ Bt.cpu().numpy().T.astype(np.float64)
         X[Si.cpu().numpy(), np.arange(q)[:, None]] += Sv.cpu().numpy()
         err = float(np.linalg.norm(X - inst.X_star) / np.linalg.norm(inst.X_star))
@@ -311,7 +320,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--form", choices=["fp32", "bf16x2"], default="fp32")
+    ap.add_argument("--form", choices=["fp32", "bf16x2", "bf16_mixed"], default="fp32",
+                    help="A form of the timed solves: FP32 plane, BF16 hi + lo, or the mixed BF16 form")
     ap.add_argument("--iters", type=int, default=T_ITERS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
@@ -367,10 +377,11 @@ def main() -> int:
     t0 = time.perf_counter()
     inst = I.make_instance(**cfg, bf16_planes=True)
     log(f"generated in {time.perf_counter() - t0:.1f} s; uploading")
-    par = lib.default_params(t_max=args.iters, flags=0 if args.no_autotune else lib.FLAG_AUTOTUNE)
-    solver = lib.Solver(inst.At if args.form == "fp32" else None, inst.Y32, m, r, rho, par,
-                        A_hi=inst.A_hi if args.form == "bf16x2" else None,
-                        A_lo=inst.A_lo if args.form == "bf16x2" else None)
+    flags = (0 if args.no_autotune else lib.FLAG_AUTOTUNE) | (lib.FLAG_BF16_MIXED if args.form == "bf16_mixed" else 0)
+    par = lib.default_params(t_max=args.iters, flags=flags)
+    planes = args.form != "fp32"
+    solver = lib.Solver(None if planes else inst.At, inst.Y32, m, r, rho, par,
+                        A_hi=inst.A_hi if planes else None, A_lo=inst.A_lo if planes else None)
     torch.cuda.synchronize()
 
     def one_solve():
@@ -416,9 +427,9 @@ def main() -> int:
     # per-kernel durations (eager launches bracketed by events on the launch stream)
     kms = solver.profile_iteration(args.profile_iters)
     log("per-kernel ms: " + ", ".join(f"{k}={v:.4f}" for k, v in kms.items()))
-    a_bytes = 4.0
-    col_bytes = column_kernel_bytes(n, q, m, r, rho, par.tau, a_bytes)
-    au_bytes = au_kernel_bytes(n, q, m, r, a_bytes)
+    a_bytes = 2.0 if args.form == "bf16_mixed" else 4.0
+    col_bytes = column_kernel_bytes(n, q, m, r, rho, par.tau, a_bytes, gather_bytes=4.0)
+    au_bytes = au_kernel_bytes(n, q, m, r, 4.0)
     col_gbs = col_bytes / (kms["k_col"] * 1e-3) / 1e9
     au_gbs = au_bytes / (kms["k_au"] * 1e-3) / 1e9
 
@@ -434,7 +445,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if args.form == "fp32" else "bf16x2->f32",
+        "dtype": {"fp32": "f32", "bf16x2": "bf16x2->f32", "bf16_mixed": "bf16x2(mixed)->f32"}[args.form],
         "data": "synthetic",
         "config": {"workload": f"{WORKLOAD} ({args.form} A resident in HBM)", "n": n, "q": q, "m": m,
                    "r": r, "rho": rho, "tau0": par.tau0, "tau": par.tau, "gdmin_iters_per_step": args.iters},
@@ -442,7 +453,7 @@ def main() -> int:
                      "frac": round(col_gbs / HBM_PEAK_GBS, 4),
                      "traffic": committed_traffic(
                          [os.path.join(ROOT, "paper_2311_03824_amd", "csrc", f) for f in ("k_column.hip", "common.h")],
-                         os.path.join(ROOT, "profiles", f"k_col_{WORKLOAD}_fp32.md")) if args.form == "fp32" else None,
+                         os.path.join(ROOT, "profiles", f"k_col_{WORKLOAD}_{args.form}.md")),
                      "kernel": "k_col", "bytes_per_launch": int(col_bytes), "avg_ms": round(kms["k_col"], 4)},
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "tuning": tuning,

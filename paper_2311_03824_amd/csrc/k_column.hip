@@ -238,13 +238,23 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
     }
   };
   auto consume = [&](int j0, const raw_t (&ar)[JU][NC]) {
+    // support bits of columns j0 .. j0 + 4 (JU - 1) (at most 44 bits from
+    // j0 - j0 % 32): two bitmap words, read before the reduction hides their latency
+    unsigned long long tb = 0ull;
+    if (inT) {
+      const int wb = j0 >> 5;
+      const unsigned w0 = inT[wb];
+      const unsigned w1 = 32 * (wb + 1) < n ? inT[wb + 1] : 0u;
+      tb = (((unsigned long long)w1 << 32) | w0) >> (j0 & 31);
+    }
     float4 av[JU][NC];
     float d[JU];
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
-      float s = 0.f;
+      av[ju][0] = ALoader<FMT>::expand(ar[ju][0]);
+      float s = dot4(av[ju][0], u[0]);
 #pragma unroll
-      for (int c = 0; c < NC; ++c) {
+      for (int c = 1; c < NC; ++c) {
         av[ju][c] = ALoader<FMT>::expand(ar[ju][c]);
         s += dot4(av[ju][c], u[c]);
       }
@@ -257,7 +267,7 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
 #pragma unroll
       for (int ju = 0; ju < JU; ++ju) {
         const int j = j0 + ju * kWaves;
-        if (j < n && ((inT[j >> 5] >> (j & 31)) & 1u)) {
+        if (j < n && ((tb >> (kWaves * ju)) & 1ull)) {
           const float dj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), ju));
 #pragma unroll
           for (int c = 0; c < NC; ++c) wacc[c] = axpy4(dj, mask_rows(av[ju][c], ln.nv[c]), wacc[c]);
