@@ -133,6 +133,33 @@ def forms_time_to_target(lib, torch, np, inst, target, fp32_solver):
     return out
 
 
+def forms_throughput(lib, torch, np, inst, steps: int, iters: int):
+    """Whole-solve throughput (init + `iters` GDmin iterations, `steps` solves) of the BF16
+    forms on the benchmark instance, timed like the headline FP32 line."""
+    out = {}
+    n, q, m, r, rho = inst.n, inst.q, inst.m, inst.r, inst.rho
+    for name, extra in (("bf16_mixed", {"flags": lib.FLAG_AUTOTUNE | lib.FLAG_BF16_MIXED}),
+                        ("bf16x2_exact", {"flags": lib.FLAG_AUTOTUNE})):
+        s = lib.Solver(None, inst.Y32, m, r, rho, lib.default_params(t_max=iters, **extra),
+                       A_hi=inst.A_hi, A_lo=inst.A_lo)
+        s.init().step(iters)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(steps):
+            s.init()
+            s.step(iters)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        kms = s.profile_iteration(10)
+        out[name] = {"iters_per_s": round(steps * iters / (ms * 1e-3), 2), "ms_per_solve": round(ms / steps, 3),
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()}, "tuning": lib.altgdmin_tuning(s.h),
+                     "final_rel_residual": s.status()["resid"]}
+        s.close()
+    return out
+
+
 def philox_form(lib, torch, np, cfg, target):
     """Philox form: A regenerated in the kernels from its counter definition, never read from HBM.
 
@@ -468,6 +495,8 @@ def main() -> int:
     if not args.no_forms:
         result["forms_time_to_target"] = forms_time_to_target(lib, torch, np, inst, args.target_resid, solver)
         log("forms: " + json.dumps(result["forms_time_to_target"]))
+        result["forms_throughput"] = forms_throughput(lib, torch, np, inst, args.steps, args.iters)
+        log("forms throughput: " + json.dumps(result["forms_throughput"]))
         result["philox_form"] = philox_form(lib, torch, np, cfg, args.target_resid)
         log("philox: " + json.dumps(result["philox_form"]))
         result["fourier_form"] = fourier_form(lib, torch, np)

@@ -168,9 +168,13 @@ class Scheduler:
 
 
 class GpuExecutor:
-    """Runs requests through the HIP library (one stream, torch for device memory)."""
+    """Runs requests through the HIP library (one stream, torch for device memory).
 
-    def __init__(self, tol: float = 1e-7, max_iters: int = 300, device: str = "cuda"):
+    BF16 requests run the mixed form (hi plane for the transposed products,
+    hi + lo for every residual) unless bf16_mixed is False.
+    """
+
+    def __init__(self, tol: float = 1e-7, max_iters: int = 300, device: str = "cuda", bf16_mixed: bool = True):
         import torch
         from . import altgdmin as lib
         if not torch.cuda.is_available():
@@ -179,6 +183,9 @@ class GpuExecutor:
         self.torch, self.lib, self.device = torch, lib, device
         self.table = torch.from_numpy(inst.normal_table()).to(device)
         self.params = lib.default_params(tol_resid=tol, t_max=max_iters)
+        self.params_bf16 = lib.default_params(tol_resid=tol, t_max=max_iters,
+                                              flags=lib.FLAG_BF16_MIXED if bf16_mixed else 0)
+        self.bf16_mixed = bf16_mixed
         self.group_ws = None
         self._ws_cache = {}
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=4)
@@ -229,7 +236,7 @@ class GpuExecutor:
         prob = lib.make_problem(A, Y, req.r, req.rho, A_lo=A_lo, m=req.m)
         lib.altgdmin_op_measure(prob, Xt, Y)
         ws = torch.empty(self.workspace_bytes(req), dtype=torch.uint8, device=self.device)
-        h = lib.altgdmin_init(prob, self.params, ws)
+        h = lib.altgdmin_init(prob, self.params if req.a_format == "f32" else self.params_bf16, ws)
         return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, Xt_host=Xt_host, ws=ws, prob=prob, h=h)
 
     def step(self, jobs, iters: int) -> None:
@@ -275,13 +282,14 @@ def calibrate_rate(executor, requests, budget_bytes: int, poll_every: int = 10, 
 
 def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, load: float = 0.8,
           rate: Optional[float] = None, poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
-          calibration_count: Optional[int] = None, sequential: bool = True, log=None) -> dict:
+          calibration_count: Optional[int] = None, sequential: bool = True, bf16_mixed: bool = True,
+          log=None) -> dict:
     """Serve `count` seeded requests on the GPU and return the summary.
 
     Without an explicit `rate`, the arrival rate is `load` times the closed-loop
     throughput of the first `calibration_count` requests (default: all of them).
     """
-    ex = GpuExecutor(tol=tol, max_iters=max_iters)
+    ex = GpuExecutor(tol=tol, max_iters=max_iters, bf16_mixed=bf16_mixed)
     reqs = inst.serving_requests(count, seed)
     budget = int(budget_gib * 2**30)
     sat = None
@@ -297,7 +305,8 @@ def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, loa
     rep = Scheduler(ex, budget, poll_every, tol, max_iters).run(reqs)
     out = rep.summary()
     out.update({"arrival_rate_per_s": rate, "closed_loop_solves_per_s": sat, "load": load if sat else None,
-                "tol_resid": tol, "max_iters": max_iters, "poll_every": poll_every, "seed": seed})
+                "tol_resid": tol, "max_iters": max_iters, "poll_every": poll_every, "seed": seed,
+                "bf16_form": "mixed" if bf16_mixed else "hi+lo"})
     if sequential and sat:
         # the same requests solved one at a time through the same executor (no batching)
         seq = calibrate_rate(ex, reqs[: calibration_count or count], budget, poll_every, tol, max_iters, max_active=1)
