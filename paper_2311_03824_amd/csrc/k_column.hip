@@ -77,12 +77,13 @@ __device__ __forceinline__ double xwave_sum_scalar(double x, double* redd, int l
 }
 
 // out = sum_{t < cnt} coef[t] * A_k[:, idx[t]]  (idx, coef in LDS), all waves get the total.
-// Each wave keeps up to 4 support columns in flight.
+// Each wave keeps up to 8 support columns in flight when A_k has at most 256 rows
+// (4 otherwise, and in the Philox form, where they are generated, not loaded).
 template <int FMT, int NC>
 __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln, const int* idx,
                                        const float* coef, int cnt, float4 (&out)[NC], float* wpart,
                                        int mq, int wave) {
-  constexpr int GU = 4;
+  constexpr int GU = (NC == 1 && FMT != FMT_PHILOX) ? 8 : 4;   // support columns in flight per wave
   float4 acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);

@@ -918,14 +918,30 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
     return;
   }
   if (a.mode == QR_POWER) {
+    // subspace change ||U_new - U_old (U_old^H U_new)||_F from the residual entries
+    // (r - ||U_old^H U_new||_F^2 cancels below angles of ~3e-4 in FP32)
     fgram<R>(a.U, X, n, r, red, out, W, false);   // U_old^H U_new
+    double acc[1] = {0.0};
+    for (int t = tid; t < nr; t += kFThreads) {
+      const int i = t / r, c = t - (t / r) * r;
+      double dx = (double)X[t].x, dy = (double)X[t].y;
+      for (int e = 0; e < r; ++e) {
+        const float2 u = a.U[(long long)i * r + e];
+        const double2 w = W[e * r + c];
+        dx -= (double)u.x * w.x - (double)u.y * w.y;
+        dy -= (double)u.x * w.y + (double)u.y * w.x;
+      }
+      acc[0] += dx * dx + dy * dy;
+    }
+    fblock_sum<1>(acc, red, out);
     if (tid == 0) {
-      double f = 0.0;
-      for (int e = 0; e < r * r; ++e) f += W[e].x * W[e].x + W[e].y * W[e].y;
-      const double sd = sqrt(fmax(0.0, (double)r - f));
+      const double sd = sqrt(out[0]);
+      const double prev = a.ctl->power_sd;   // 0 before the first step
       a.ctl->power_sd = sd;
       a.ctl->power_it += 1;
-      if (sd <= a.power_tol) a.ctl->conv = 1;
+      // converged at power_tol, or once the change has stopped shrinking (by less
+      // than 10 % in a step) below 1e-3: the FP32 iterate's rounding floor
+      if (sd <= a.power_tol || (sd <= 1e-3 && prev > 0.0 && sd >= 0.9 * prev)) a.ctl->conv = 1;
     }
   }
   for (int t = tid; t < nr; t += kFThreads) {

@@ -309,14 +309,29 @@ __device__ __forceinline__ void qr_body(const QRArgs& a, unsigned char* dsm, QRS
     return;
   }
   if (a.mode == QR_POWER) {
+    // subspace change ||U_new - U_old (U_old^T U_new)||_F, summed directly from the
+    // residual entries (r - ||U_old^T U_new||_F^2 cancels below angles of ~3e-4 in FP32)
     block_gram(a.U, X, n, r, W, false);   // U_old^T U_new
+    double acc = 0.0;
+    for (int idx = tid; idx < nr; idx += kQRThreads) {
+      const int i = idx / r, c = idx - (idx / r) * r;
+      double d = (double)X[idx];
+      for (int e = 0; e < r; ++e) d = fma(-(double)a.U[(long long)i * r + e], W[e * r + c], d);
+      acc = fma(d, d, acc);
+    }
+    acc = wave_sum_dpp(acc);
+    if ((tid & 63) == 0) sh[tid >> 6] = acc;
+    __syncthreads();
     if (tid == 0) {
       double f = 0.0;
-      for (int e = 0; e < r * r; ++e) f += W[e] * W[e];
-      const double sd = sqrt(fmax(0.0, (double)r - f));
+      for (int w = 0; w < kQRThreads / 64; ++w) f += sh[w];
+      const double sd = sqrt(f);
+      const double prev = a.ctl->power_sd;   // 0 before the first step
       a.ctl->power_sd = sd;
       a.ctl->power_it += 1;
-      if (sd <= a.power_tol) a.ctl->conv = 1;
+      // converged at power_tol, or once the change has stopped shrinking (by less
+      // than 10 % in a step) below 1e-3: the FP32 iterate's rounding floor
+      if (sd <= a.power_tol || (sd <= 1e-3 && prev > 0.0 && sd >= 0.9 * prev)) a.ctl->conv = 1;
     }
   }
   for (int idx = tid; idx < nr; idx += kQRThreads) {

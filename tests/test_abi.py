@@ -106,6 +106,9 @@ def test_workspace_bytes_accepts_the_benchmark_problem(lib):
     (dict(r=17), -5),                   # no instantiation above r = 16
     (dict(m=1025, lda=1028, a_stride_k=1028 * 1000, ldy=1025), -5),
     (dict(r=0), -1),
+    (dict(q=0), -1),                    # empty problem
+    (dict(n=0), -1),
+    (dict(m=0, lda=4, ldy=4, a_stride_k=4000), -1),
     (dict(r=12, m=10, lda=12, ldy=12, a_stride_k=12000), -1),   # r > m
     (dict(rho=1001), -1),
     (dict(rho=-1), -1),

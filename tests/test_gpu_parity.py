@@ -586,3 +586,49 @@ def test_step_many_freezes_at_tolerance(lib, torch):
     assert group[1].status()["iterations"] == 60
     for g in group:
         g.close()
+
+
+# ---------------------------------------------------------------- degenerate shapes
+
+@pytest.mark.parametrize("shape,iters", [
+    (dict(n=3, q=2, m=5, r=1, rho=1), 4),       # fewer columns j than waves per workgroup
+    (dict(n=64, q=1, m=20, r=1, rho=0), 4),     # one column, no sparse part
+])
+def test_degenerate_shapes_match_oracle(lib, torch, shape, iters):
+    inst = I.make_instance(**shape, seed=77)
+    out = _solve(lib, torch, inst, iters)
+    st, _ = O.solve(inst.A64(), inst.Y32.astype(np.float64), inst.r, inst.rho, t_max=iters)
+    assert out["status"]["error_flags"] == 0
+    if inst.rho:
+        assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    if inst.rho:
+        X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [dict(n=10, q=4, m=1, r=1, rho=0),    # m = 1: Pi_k = 0, nothing left to fit
+                                   dict(n=5, q=7, m=8, r=5, rho=0),    # r = n: U spans everything
+                                   dict(n=20, q=3, m=30, r=2, rho=20)])  # rho = n: S dense, U not identifiable
+def test_degenerate_first_iteration_matches_oracle(lib, torch, shape):
+    """Cases where U is not determined by the data (grad_U f vanishes up to rounding, or
+    S can absorb any column), so later iterates follow rounding: the first iteration's
+    fit X = U_0 B_1 + S_1 is compared.  The subspace iteration runs its 100 steps
+    (power_tol = 0), so U_0 is the top-r subspace of L_0 to FP32 accuracy, as the
+    oracle's exact SVD."""
+    inst = I.make_instance(**shape, seed=77)
+    par = lib.default_params(t_max=1, power_iters=100, power_tol=0.0)
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par)
+    s.init().step(1)
+    out = s.get()
+    out["status"] = s.status()
+    s.close()
+    st, _ = O.solve(inst.A64(), inst.Y32.astype(np.float64), inst.r, inst.rho, t_max=1)
+    assert out["status"]["error_flags"] == 0
+    if inst.rho:
+        assert np.array_equal(out["S_idx"], st.idx)
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    if inst.rho:
+        X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-4
