@@ -922,16 +922,24 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
     // (r - ||U_old^H U_new||_F^2 cancels below angles of ~3e-4 in FP32)
     fgram<R>(a.U, X, n, r, red, out, W, false);   // U_old^H U_new
     double acc[1] = {0.0};
-    for (int t = tid; t < nr; t += kFThreads) {
-      const int i = t / r, c = t - (t / r) * r;
-      double dx = (double)X[t].x, dy = (double)X[t].y;
-      for (int e = 0; e < r; ++e) {
-        const float2 u = a.U[(long long)i * r + e];
-        const double2 w = W[e * r + c];
-        dx -= (double)u.x * w.x - (double)u.y * w.y;
-        dy -= (double)u.x * w.y + (double)u.y * w.x;
-      }
-      acc[0] += dx * dx + dy * dy;
+    for (int i = tid; i < n; i += kFThreads) {   // one row per thread: U_old row in registers
+      float2 u[R];
+#pragma unroll
+      for (int e = 0; e < R; ++e) u[e] = e < r ? a.U[(long long)i * r + e] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int c = 0; c < R; ++c)
+        if (c < r) {
+          const float2 xv = X[(long long)i * r + c];
+          double dx = (double)xv.x, dy = (double)xv.y;
+#pragma unroll
+          for (int e = 0; e < R; ++e)
+            if (e < r) {
+              const double2 w = W[e * r + c];
+              dx -= (double)u[e].x * w.x - (double)u[e].y * w.y;
+              dy -= (double)u[e].x * w.y + (double)u[e].y * w.x;
+            }
+          acc[0] += dx * dx + dy * dy;
+        }
     }
     fblock_sum<1>(acc, red, out);
     if (tid == 0) {

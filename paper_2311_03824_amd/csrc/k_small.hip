@@ -313,11 +313,17 @@ __device__ __forceinline__ void qr_body(const QRArgs& a, unsigned char* dsm, QRS
     // residual entries (r - ||U_old^T U_new||_F^2 cancels below angles of ~3e-4 in FP32)
     block_gram(a.U, X, n, r, W, false);   // U_old^T U_new
     double acc = 0.0;
-    for (int idx = tid; idx < nr; idx += kQRThreads) {
-      const int i = idx / r, c = idx - (idx / r) * r;
-      double d = (double)X[idx];
-      for (int e = 0; e < r; ++e) d = fma(-(double)a.U[(long long)i * r + e], W[e * r + c], d);
-      acc = fma(d, d, acc);
+    for (int i = tid; i < n; i += kQRThreads) {   // one row per thread: U_old row in registers
+      float u[kRMax];
+#pragma unroll
+      for (int e = 0; e < kRMax; ++e) u[e] = e < r ? a.U[(long long)i * r + e] : 0.f;
+      for (int c = 0; c < r; ++c) {
+        double d = (double)X[(long long)i * r + c];
+#pragma unroll
+        for (int e = 0; e < kRMax; ++e)
+          if (e < r) d = fma(-(double)u[e], W[e * r + c], d);
+        acc = fma(d, d, acc);
+      }
     }
     acc = wave_sum_dpp(acc);
     if ((tid & 63) == 0) sh[tid >> 6] = acc;
