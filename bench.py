@@ -160,6 +160,37 @@ def forms_throughput(lib, torch, np, inst, steps: int, iters: int):
     return out
 
 
+def shard_config(lib, torch, np, shards: int = 8):
+    """One GPU's share of the headline workload sharded by columns over `shards` GPUs:
+    n = 1000, m = 400, r = 10, rho = 50 and q = 1000 / shards columns (FP32 and the mixed
+    BF16 form).  The all-reduce of the n x r gradient that sharding adds is not included."""
+    from paper_2311_03824_amd import instances as I
+    cfg = dict(I.WORKLOADS[WORKLOAD])
+    cfg["q"] = cfg["q"] // shards
+    inst = I.make_instance(**cfg, bf16_planes=True)
+    out = {"q": inst.q, "shards": shards}
+    for name, flags, planes in (("fp32", lib.FLAG_AUTOTUNE, False),
+                                ("bf16_mixed", lib.FLAG_AUTOTUNE | lib.FLAG_BF16_MIXED, True)):
+        s = lib.Solver(None if planes else inst.At, inst.Y32, inst.m, inst.r, inst.rho,
+                       lib.default_params(t_max=T_ITERS, flags=flags),
+                       A_hi=inst.A_hi if planes else None, A_lo=inst.A_lo if planes else None)
+        s.init().step(T_ITERS)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s.init().step(T_ITERS)
+        e1.record()
+        torch.cuda.synchronize()
+        kms = s.profile_iteration(20)
+        col_bytes = column_kernel_bytes(inst.n, inst.q, inst.m, inst.r, inst.rho, 3, 2.0 if planes else 4.0, 4.0)
+        out[name] = {"gdmin_iters_per_s": round(T_ITERS / (e0.elapsed_time(e1) * 1e-3), 1),
+                     "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+                     "k_col_GBps": round(col_bytes / (kms["k_col"] * 1e-3) / 1e9, 1),
+                     "final_rel_residual": s.status()["resid"]}
+        s.close()
+    return out
+
+
 def philox_form(lib, torch, np, cfg, target):
     """Philox form: A regenerated in the kernels from its counter definition, never read from HBM.
 
@@ -503,6 +534,8 @@ def main() -> int:
         log("fourier: " + json.dumps(result["fourier_form"]))
         result["other_configs"] = small_configs(lib, torch, np)
         log("other configs: " + json.dumps(result["other_configs"]))
+        result["shard_of_8"] = shard_config(lib, torch, np, 8)
+        log("one GPU's share of 8: " + json.dumps(result["shard_of_8"]))
     if args.serve_requests > 0:
         from paper_2311_03824_amd import serve
         log(f"serving {args.serve_requests} mixed-size requests (budget {args.serve_budget_gib} GiB)")

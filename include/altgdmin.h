@@ -182,14 +182,16 @@ int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, voi
 int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out);
 
 /* Autotuner (with ALTGDMIN_FLAG_AUTOTUNE): the column-kernel unroll JU (columns
- * per load group, 1, 2 or 4) and the A_k U pipeline depth AUD (1, 2 or 4) chosen for
+ * per load group, 1, 2, 4 or 8) and the A_k U pipeline depth AUD (1, 2, 4 or 8) chosen for
  * this handle; 0 means the default instantiation.  The choice is made once per
  * (GPU architecture, A format, n, q, m, r, rho) in a process by timing each
  * variant three times on the problem's own data (A_k U from a fixed orthonormal
  * U; one IHT iteration plus the back-projection for the column kernel) before
  * the initialisation; with the environment variable ALTGDMIN_TUNE_CACHE naming
  * a file, choices are read from and appended to it as JSON lines keyed by the
- * architecture.  Every variant computes the same bits.  Host call. */
+ * architecture.  ALTGDMIN_TUNE_FORCE="JU,AUD" takes the given variants without
+ * timing (JU = 8 falls back to 4 above 512 rows).  Every variant computes the
+ * same bits.  Host call. */
 int altgdmin_tuning(altgdmin_handle* h, int32_t* col_unroll, int32_t* au_depth);
 
 /* Device bytes of the launch tables altgdmin_step_many needs for these handles (host call). */

@@ -299,6 +299,17 @@ ColArgs col_args(const altgdmin_handle* h);
 
 int autotune(altgdmin_handle* h, hipStream_t st) {
   const altgdmin_problem& p = h->prob;
+  // ALTGDMIN_TUNE_FORCE="JU,AUD" skips the timing and takes these variants (tests)
+  if (const char* force = std::getenv("ALTGDMIN_TUNE_FORCE")) {
+    int ju = 0, aud = 0;
+    if (std::sscanf(force, "%d,%d", &ju, &aud) != 2 || (ju != 1 && ju != 2 && ju != 4 && ju != 8) ||
+        (aud != 1 && aud != 2 && aud != 4 && aud != 8))
+      return fail(ALTGDMIN_EINVAL, "ALTGDMIN_TUNE_FORCE must be JU,AUD with JU, AUD in {1, 2, 4, 8}");
+    if (ju == 8 && p.m > 512) ju = 4;   // JU = 8 is built for at most two row chunks
+    h->col_unroll = ju;
+    h->au_depth = aud;
+    return ALTGDMIN_OK;
+  }
   const std::string arch = device_arch();
   const TuneKey key(arch, h->colfmt, p.n, p.q, p.m, p.r, p.rho);
   {
@@ -338,16 +349,20 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   int best_aud = 0, best_ju = 0;
   float best_au = 1e30f, best_col = 1e30f;
   hipError_t e = hipSuccess;
-  for (int aud : {1, 2, 4}) {
+  for (int aud : {1, 2, 4, 8}) {
     float ms = 0.f;
     e = timed([&] { return launch_au_tuned(h->fmt, aud, au, st); }, &ms);
     if (e != hipSuccess) break;
     if (ms < best_au) { best_au = ms; best_aud = aud; }
   }
-  for (int ju : {1, 2, 4}) {
+  for (int ju : {1, 2, 4, 8}) {
     if (e != hipSuccess) break;
     float ms = 0.f;
     e = timed([&] { return launch_col_tuned(h->colfmt, ju, ca, st); }, &ms);
+    if (e == hipErrorNotSupported) {   // no such instantiation for this row count: not a candidate
+      e = hipSuccess;
+      continue;
+    }
     if (e != hipSuccess) break;
     if (ms < best_col) { best_col = ms; best_ju = ju; }
   }

@@ -168,43 +168,65 @@ __device__ __forceinline__ double sumsq(const float4 (&v)[NC]) {
   return wave_sum_dpp(s);
 }
 
-// Totals over the 64 lanes of JU per-lane partial sums at once (JU = 1, 2, 4):
-// on return lane i < JU holds the total of x[i].  The lanes are paired in one
-// fixed order for every JU -- l ^ 1 and l ^ 2 (quad permutations), rotations
-// by 4 and 8 within each row of 16, then rows r ^ 1 and halves (permlane
-// swaps) -- and with JU > 1 each lane carries the column it will end with from
-// the first step on, so a column's total has the same bits for every JU.
+// Totals over the 64 lanes of JU per-lane partial sums at once (JU = 1, 2, 4, 8):
+// on return lane i < JU holds the total of x[i].  A butterfly: lanes l and
+// l ^ 1, l ^ 2 (quad permutations), l ^ 4, l ^ 8 (row shifts restricted to the
+// banks whose partner lies that way), then rows r ^ 1 and the two halves
+// (permlane swaps).  Both lanes of a pair add the same two numbers, so a
+// column's total has the same bits in every lane; with JU > 1 each lane
+// carries, from the first step on, the column it ends with, so every JU gives
+// the same bits.
+template <int SH>
+__device__ __forceinline__ float lanes_xor(float v) {   // value of lane l ^ SH (SH = 4 or 8)
+  static_assert(SH == 4 || SH == 8, "row butterflies by 4 and 8 only");
+  const int iv = __float_as_int(v);
+  int t = __builtin_amdgcn_update_dpp(iv, iv, 0x100 + SH, 0xF, SH == 4 ? 0x5 : 0x3, false);   // row_shl
+  t = __builtin_amdgcn_update_dpp(t, iv, 0x110 + SH, 0xF, SH == 4 ? 0xA : 0xC, false);       // row_shr
+  return __int_as_float(t);
+}
+
 template <int JU>
 __device__ __forceinline__ float col_totals(const float (&x)[JU], int lane) {
-  static_assert(JU == 1 || JU == 2 || JU == 4, "JU must be 1, 2 or 4");
-  auto dpp = [](float v, int ctrl) -> float {
-    switch (ctrl) {   // constant after inlining
-      case 0xB1: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));
-      case 0x4E: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
-      case 0x124: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xF, 0xF, false));
-      default: return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xF, 0xF, false));
-    }
+  static_assert(JU == 1 || JU == 2 || JU == 4 || JU == 8, "JU must be 1, 2, 4 or 8");
+  auto qp = [](float v, int ctrl) -> float {
+    return ctrl == 0xB1 ? __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false))
+                        : __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));
   };
   float v;
   if constexpr (JU == 1) {
-    v = x[0] + dpp(x[0], 0xB1);
-    v = v + dpp(v, 0x4E);
+    v = x[0] + qp(x[0], 0xB1);
+    v = v + qp(v, 0x4E);
+    v = v + lanes_xor<4>(v);
   } else if constexpr (JU == 2) {
     const bool odd = lane & 1;
     const float a = odd ? x[1] : x[0], b = odd ? x[0] : x[1];
-    v = a + dpp(b, 0xB1);            // lane parity p: column p
-    v = v + dpp(v, 0x4E);
-  } else {
+    v = a + qp(b, 0xB1);                 // lane parity p: column p
+    v = v + qp(v, 0x4E);
+    v = v + lanes_xor<4>(v);
+  } else if constexpr (JU == 4) {
     const bool odd = lane & 1, two = lane & 2;
     const float a = odd ? x[1] : x[0], b = odd ? x[0] : x[1];
     const float c = odd ? x[3] : x[2], d = odd ? x[2] : x[3];
-    const float ab = a + dpp(b, 0xB1);   // even lanes: column 0, odd: column 1
-    const float cd = c + dpp(d, 0xB1);   // even lanes: column 2, odd: column 3
+    const float ab = a + qp(b, 0xB1);    // even lanes: column 0, odd: column 1
+    const float cd = c + qp(d, 0xB1);    // even lanes: column 2, odd: column 3
     const float e = two ? cd : ab, f = two ? ab : cd;
-    v = e + dpp(f, 0x4E);                // lane & 3: column
+    v = e + qp(f, 0x4E);                 // lane & 3: column
+    v = v + lanes_xor<4>(v);
+  } else {
+    const bool odd = lane & 1, two = lane & 2, four = lane & 4;
+    float h[4];
+#pragma unroll
+    for (int pq = 0; pq < 4; ++pq) {     // pairs (2pq, 2pq + 1): lane parity picks the column kept
+      const float a = odd ? x[2 * pq + 1] : x[2 * pq], b = odd ? x[2 * pq] : x[2 * pq + 1];
+      h[pq] = a + qp(b, 0xB1);
+    }
+    const float e0 = two ? h[1] : h[0], f0 = two ? h[0] : h[1];   // columns 0..3
+    const float e1 = two ? h[3] : h[2], f1 = two ? h[2] : h[3];   // columns 4..7
+    const float g0 = e0 + qp(f0, 0x4E), g1 = e1 + qp(f1, 0x4E);
+    const float k = four ? g1 : g0, gv = four ? g0 : g1;
+    v = k + lanes_xor<4>(gv);            // lane & 7: column
   }
-  v = v + dpp(v, 0x124);                 // row_ror:4
-  v = v + dpp(v, 0x128);                 // row_ror:8
+  v = v + lanes_xor<8>(v);
   const auto p = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), false, false);
   v = __uint_as_float(p[0]) + __uint_as_float(p[1]);     // rows r and r ^ 1
   const auto h = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), false, false);
@@ -239,7 +261,7 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
     }
   };
   auto consume = [&](int j0, const raw_t (&ar)[JU][NC]) {
-    // support bits of columns j0 .. j0 + 4 (JU - 1) (at most 44 bits from
+    // support bits of columns j0 .. j0 + 4 (JU - 1) (at most 60 bits from
     // j0 - j0 % 32): two bitmap words, read before the reduction hides their latency
     unsigned long long tb = 0ull;
     if (inT) {
@@ -534,6 +556,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
 // flight grow with NC and JU; the two BF16 planes and the Philox rounds need
 // more registers than one FP32 or hi plane.
 constexpr int col_min_waves(int fmt, int nc, int ju) {
+  if (ju == 8) return nc == 1 ? 2 : 1;
   if (fmt == FMT_PHILOX) return nc <= 2 ? 2 : 1;
   if (nc == 1) return 4;
   if (nc == 2) return ju == 1 ? 4 : (ju == 2 ? (fmt == FMT_BF16X2 ? 3 : 4) : (fmt == FMT_BF16X2 ? 2 : 3));
@@ -903,29 +926,35 @@ hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q
 #endif  // part 1
 
 #if ALTG_PART == 2
-// Autotuned variants of the plane formats: k_col with JU in {1, 2, 4} (FP32,
-// BF16X2 and the mixed BF16 form) and k_au with AUD in {1, 2, 4} (FP32, BF16X2).  Every variant gives the same bits as the default one.
+// Autotuned variants of the plane formats: k_col with JU in {1, 2, 4, 8} (FP32,
+// BF16X2 and the mixed BF16 form) and k_au with AUD in {1, 2, 4, 8} (FP32,
+// BF16X2).  JU = 8 and AUD = 8 keep many loads in flight per wave at one or two
+// waves per SIMD: for problems with few columns, where each CU holds one or two
+// column workgroups.  Every variant gives the same bits as the default one.
 typedef void (*col_fn2)(ColArgs);
 typedef void (*au_fn2)(AUArgs);
-#define COLT_NC(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 4>}
-#define COLT_F(F) {COLT_NC(F, 1), COLT_NC(F, 2), COLT_NC(F, 3), COLT_NC(F, 4)}
-static const col_fn2 kColTuned[3][kNCMax][3] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2), COLT_F(FMT_BF16MIX)};
-#define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 4>}
+// JU = 8 for at most two row chunks (its loads need every register at more)
+#define COLT_NC(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 4>, k_col<F, NC, 8>}
+#define COLT_NC4(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 4>, nullptr}
+#define COLT_F(F) {COLT_NC(F, 1), COLT_NC(F, 2), COLT_NC4(F, 3), COLT_NC4(F, 4)}
+static const col_fn2 kColTuned[3][kNCMax][4] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2), COLT_F(FMT_BF16MIX)};
+#define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 4>, k_au<F, R, 8>}
 #define AUT_F(F) {AUT_R(F, 2), AUT_R(F, 4), AUT_R(F, 6), AUT_R(F, 8), AUT_R(F, 10), AUT_R(F, 12), AUT_R(F, 14), AUT_R(F, 16)}
-static const au_fn2 kAUTuned[2][kRMax / 2][3] = {AUT_F(FMT_F32), AUT_F(FMT_BF16X2)};
+static const au_fn2 kAUTuned[2][kRMax / 2][4] = {AUT_F(FMT_F32), AUT_F(FMT_BF16X2)};
 
-static int tuned_slot(int v, const int (&vals)[3]) {
-  for (int i = 0; i < 3; ++i)
+static int tuned_slot(int v, const int (&vals)[4]) {
+  for (int i = 0; i < 4; ++i)
     if (vals[i] == v) return i;
   return -1;
 }
 
 hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
-  static const int kJU[3] = {1, 2, 4};
+  static const int kJU[4] = {1, 2, 4, 8};
   const int slot = tuned_slot(ju, kJU);
   const int row = fmt == FMT_F32 ? 0 : fmt == FMT_BF16X2 ? 1 : fmt == FMT_BF16MIX ? 2 : -1;
   if (row < 0 || slot < 0) return hipErrorInvalidValue;
   const int nc = (a.m + 255) / 256;
+  if (!kColTuned[row][nc - 1][slot]) return hipErrorNotSupported;   // variant not built
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, 0);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColTuned[row][nc - 1][slot], dim3(a.q), dim3(kThreads), lay.total, st, a);
@@ -933,7 +962,7 @@ hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st) {
-  static const int kAUD[3] = {1, 2, 4};
+  static const int kAUD[4] = {1, 2, 4, 8};
   const int slot = tuned_slot(aud, kAUD);
   if ((fmt != FMT_F32 && fmt != FMT_BF16X2) || slot < 0) return hipErrorInvalidValue;
   const int ri = (a.r + 1) / 2 - 1;

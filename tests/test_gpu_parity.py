@@ -388,7 +388,7 @@ def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatc
     b = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE)
     c = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE | lib.FLAG_EAGER)
     assert a["tuning"] == {"col_unroll": 0, "au_depth": 0}
-    assert b["tuning"]["col_unroll"] in (1, 2, 4) and b["tuning"]["au_depth"] in (1, 2, 4)
+    assert b["tuning"]["col_unroll"] in (1, 2, 4, 8) and b["tuning"]["au_depth"] in (1, 2, 4, 8)
     assert c["tuning"] == b["tuning"]              # the second init reuses the process-wide choice
     for key in ("U", "Bt", "S_idx", "S_val"):
         assert np.array_equal(a[key], b[key]), key
@@ -397,6 +397,23 @@ def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatc
     rec = [json.loads(x) for x in cache.read_text().splitlines()]
     assert len(rec) == 1 and rec[0]["m"] == inst.m and rec[0]["fmt"] == int(bf16)
     assert (rec[0]["col_unroll"], rec[0]["au_depth"]) == (b["tuning"]["col_unroll"], b["tuning"]["au_depth"])
+
+
+@pytest.mark.parametrize("shape", [dict(n=517, q=24, m=333, r=5, rho=11),    # two row chunks
+                                   dict(n=300, q=20, m=200, r=3, rho=6),     # one row chunk
+                                   dict(n=260, q=8, m=701, r=8, rho=9)])     # three row chunks
+def test_every_tuned_variant_is_bitwise_the_default(lib, torch, monkeypatch, shape):
+    """Each column-pass unroll JU and A_k U depth AUD, forced in turn, gives the bits of
+    the default instantiation (FP32 plane and the mixed BF16 form)."""
+    inst = I.make_instance(**shape, seed=21, bf16_planes=True)
+    for bf16, extra in ((False, 0), (True, lib.FLAG_BF16_MIXED)):
+        monkeypatch.delenv("ALTGDMIN_TUNE_FORCE", raising=False)
+        ref = _solve(lib, torch, inst, 6, bf16=bf16, flags=extra)
+        for ju, aud in ((1, 1), (2, 2), (4, 4), (8, 8), (1, 8), (8, 1)):
+            monkeypatch.setenv("ALTGDMIN_TUNE_FORCE", f"{ju},{aud}")
+            out = _solve(lib, torch, inst, 6, bf16=bf16, flags=extra | lib.FLAG_AUTOTUNE)
+            for key in ("U", "Bt", "S_idx", "S_val"):
+                assert np.array_equal(ref[key], out[key]), (bf16, ju, aud, key)
 
 
 def test_solve_entry_point_tolerance_stop(lib, torch):
