@@ -186,7 +186,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
  * this handle; 0 means the default instantiation.  The choice is made once per
  * (GPU architecture, A format, n, q, m, r, rho) in a process by timing each
  * variant three times on the problem's own data (A_k U from a fixed orthonormal
- * U; one IHT iteration plus the back-projection for the column kernel) before
+ * U; the column kernel as in a GDmin iteration, from an empty support) before
  * the initialisation; with the environment variable ALTGDMIN_TUNE_CACHE naming
  * a file, choices are read from and appended to it as JSON lines keyed by the
  * architecture.  ALTGDMIN_TUNE_FORCE="JU,AUD" takes the given variants without

@@ -323,16 +323,19 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     }
   }
   // the variants run on the problem's own A and y: A_k U from a fixed orthonormal
-  // U, and the column kernel as one IHT iteration from s = 0 plus the
-  // back-projection; every buffer they write is rewritten by the initialisation
+  // U, then the column kernel as in a GDmin iteration; every buffer they write
+  // is rewritten by the initialisation or the first iteration
   HIPCHK(launch_fill_basis(h->Utmp, p.n, p.r, st));
   AUArgs au;
   std::memset(&au, 0, sizeof(au));
   au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
   au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
   au.U = h->Utmp; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+  // the column kernel in its GDmin configuration (projection by the P_k, G_k^{-1}
+  // the A_k U runs just wrote, tau IHT iterations, the LS / gradient tail), from
+  // an empty support
   ColArgs ca = col_args(h);
-  ca.tau = 1; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
+  ca.tau = h->par.tau; ca.project = 1; ca.has_support = 0; ca.tail = TAIL_LSGRAD;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
