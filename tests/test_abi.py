@@ -104,6 +104,7 @@ def test_workspace_bytes_accepts_the_benchmark_problem(lib):
 
 @pytest.mark.parametrize("kw, code", [
     (dict(r=17), -5),                   # no instantiation above r = 16
+    (dict(n=5600, m=1024, r=16, lda=1024, ldy=1024, a_stride_k=1024 * 5600), -5),   # LDS of a column workgroup
     (dict(m=1025, lda=1028, a_stride_k=1028 * 1000, ldy=1025), -5),
     (dict(r=0), -1),
     (dict(q=0), -1),                    # empty problem

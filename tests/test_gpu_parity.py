@@ -649,3 +649,26 @@ def test_degenerate_first_iteration_matches_oracle(lib, torch, shape):
     if inst.rho:
         X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
     assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-4
+
+
+def test_largest_supported_shape_matches_oracle(lib, torch):
+    """Largest instantiation along every axis at once: m = 1024 rows (four row chunks,
+    P_k in global memory), r = 16, and n = 5500 columns, just under the 64 KiB of LDS
+    a column workgroup may take (n = 5600 is rejected, see test_abi)."""
+    inst = I.make_instance(n=5500, q=20, m=1024, r=16, rho=50, seed=41)
+    A, Y = inst.A64(), inst.Y32.astype(np.float64)
+    st = O.initialise(A, Y, inst.r, inst.rho)
+    U0 = st.U.copy()   # L_0 is 5500 x 20 with r = 16: its 16th gap is small, so start from the exact U_0
+    for _ in range(3):
+        st = O.gdmin_iteration(A, Y, st, inst.rho)
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, lib.default_params(t_max=3), U_start=U0)
+    s.init().step(3)
+    out = s.get()
+    out["status"] = s.status()
+    s.close()
+    assert out["status"]["error_flags"] == 0
+    assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
