@@ -209,8 +209,10 @@ int altgdmin_group_bytes(altgdmin_handle* const* hs, int32_t count, size_t* byte
  * its state, report.iterations and report.resid stay those of the first
  * iteration that met the tolerance.  group_ws (device, 256-byte aligned,
  * >= altgdmin_group_bytes) holds the launch tables; it is filled from the host
- * and the stream is synchronised once per call.  Handles of a BF16X2 problem
- * with a hi-only phase are rejected (EINVAL). */
+ * and the stream is synchronised once per call.  The batched launches use the
+ * default loads-in-flight instantiations (an autotuned choice applies to
+ * altgdmin_step / altgdmin_solve; every variant gives the same bits).  Handles
+ * of a BF16X2 problem with a hi-only phase are rejected (EINVAL). */
 int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters, void* group_ws,
                        size_t group_bytes, void* stream);
 
