@@ -27,7 +27,7 @@ __device__ __forceinline__ void grad_body(const float* __restrict__ H, const flo
   float acc[kRMax];
 #pragma unroll
   for (int c = 0; c < kRMax; ++c) acc[c] = 0.f;
-  constexpr int KU = 4;
+  constexpr int KU = 16;   // loads in flight per wave; the order of the k terms does not depend on it
   for (int kb = k0 + ph; kb < k1; kb += kGradWaves * KU) {
     float h[KU], bv[KU];
 #pragma unroll
