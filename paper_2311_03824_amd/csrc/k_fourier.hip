@@ -11,7 +11,7 @@
 //            G_k = P_k^H P_k and its inverse in FP64, the projected IHT of
 //            Alg. 2 (tau iterations, three 2D FFTs each), b_k by least squares
 //            (eq. (bk_LS)), r_k and h_k = A_k^H r_k;
-//   k_fgrad: grad_U f = sum_k h_k b_k^H in fixed column order;
+//   k_fgrad: grad_U f = sum_k h_k b_k^H, four column splits in a fixed order;
 //   k_fqr  : eta at t = 1, U - eta grad, CholeskyQR2 with a real positive
 //            diagonal, the residual.
 // The initialisation uses k_fcol with M = A_k (IHT from 0, then the columns of
@@ -704,30 +704,79 @@ __global__ __launch_bounds__(kFThreads) void k_fltu(const float2* H, const float
   if (tid < r) Tc[(long long)k * r + tid] = make_float2((float)out[2 * tid], (float)out[2 * tid + 1]);
 }
 
-// Gsum[j][c] = sum_k H[k][j] conj(B[k][c]), k in order (grad_U f with B = B_t;
-// L_0 (L_0^H U) with B = Tc).  One thread per row j.
+// Rows of Gsum[j][c] = sum_k H[k][j] conj(B[k][c]) (grad_U f with B = B_t;
+// L_0 (L_0^H U) with B = Tc) for the 256 rows j of block blockIdx.x, by 1024
+// threads: thread t takes row t % 256 and the k range of split s = t / 256 (the
+// four quarters of 0 .. q - 1, each summed in order); the splits are added as
+// (s0 + s2) + (s1 + s3) through buf (2 x 256 x R float2 of LDS).  Threads of
+// split 0 return true and hold the row in acc.
+constexpr int kFGradSplits = 4;
+
 template <int R>
-__global__ __launch_bounds__(256) void k_fgrad(const float2* H, const float2* B, int n, int q, int r, float2* Gsum,
-                                               const int* skip) {
-  if (skip && *skip) return;
-  const int j = blockIdx.x * 256 + threadIdx.x;
-  if (j >= n) return;
-  float2 acc[R];
+__device__ bool fgrad_rows(const float2* H, const float2* B, int n, int q, int r, float2 (&acc)[R], float2* buf) {
+  const int tid = threadIdx.x, row = tid & 255, sp = tid >> 8;
+  const int j = blockIdx.x * 256 + row;
+  const int jc = j < n ? j : n - 1;
+  const int k0 = q * sp / kFGradSplits, k1 = q * (sp + 1) / kFGradSplits;
 #pragma unroll
   for (int c = 0; c < R; ++c) acc[c] = make_float2(0.f, 0.f);
-  for (int k = 0; k < q; ++k) {
-    const float2 h = H[(long long)k * n + j];
+  constexpr int KU = 8;   // loads in flight per thread; the k order of the sum does not depend on it
+  for (int kb = k0; kb < k1; kb += KU) {
+    float2 h[KU];
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      const int k = kb + u < k1 ? kb + u : k0;
+      h[u] = H[(long long)k * n + jc];
+    }
+#pragma unroll
+    for (int u = 0; u < KU; ++u) {
+      if (kb + u < k1) {
+        const int k = kb + u;
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+          if (c < r) {
+            const float2 b = B[(long long)k * r + c];
+            acc[c].x = fmaf(h[u].x, b.x, fmaf(h[u].y, b.y, acc[c].x));
+            acc[c].y = fmaf(h[u].y, b.x, fmaf(-h[u].x, b.y, acc[c].y));
+          }
+      }
+    }
+  }
+  auto put = [&](int slot) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) buf[(slot * 256 + row) * R + c] = acc[c];
+  };
+  auto add = [&](int slot) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+      const float2 o = buf[(slot * 256 + row) * R + c];
+      acc[c].x += o.x;
+      acc[c].y += o.y;
+    }
+  };
+  if (sp >= 2) put(sp - 2);
+  __syncthreads();
+  if (sp < 2) add(sp);
+  __syncthreads();
+  if (sp == 1) put(0);
+  __syncthreads();
+  if (sp == 0) add(0);
+  __syncthreads();   // buf is free again
+  return sp == 0;
+}
+
+template <int R>
+__global__ __launch_bounds__(kFThreads) void k_fgrad(const float2* H, const float2* B, int n, int q, int r,
+                                                     float2* Gsum, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ float2 buf[2 * 256 * R];
+  float2 acc[R];
+  const bool mine = fgrad_rows<R>(H, B, n, q, r, acc, buf);
+  const int j = blockIdx.x * 256 + (threadIdx.x & 255);
+  if (mine && j < n)
 #pragma unroll
     for (int c = 0; c < R; ++c)
-      if (c < r) {
-        const float2 b = B[(long long)k * r + c];
-        acc[c].x = fmaf(h.x, b.x, fmaf(h.y, b.y, acc[c].x));
-        acc[c].y = fmaf(h.y, b.x, fmaf(-h.x, b.y, acc[c].y));
-      }
-  }
-#pragma unroll
-  for (int c = 0; c < R; ++c)
-    if (c < r) Gsum[(long long)j * r + c] = acc[c];
+      if (c < r) Gsum[(long long)j * r + c] = acc[c];
 }
 
 namespace {
@@ -767,71 +816,204 @@ __device__ double jacobi_lmax(double* A, int N) {
   return l;
 }
 
-// W (r x r, complex FP64) = X^H Y over the n rows.  Wave w computes the entries
-// e = w, w + 16, ... (with sym, the entries a <= b only, the others by
-// conjugation); its lanes stride over the rows and the lane sums are added by
-// the fixed DPP tree.  Ends with a barrier.
+// W (r x r, complex FP64) = X^H Y over the n rows of the row-major n x r X and Y
+// (global memory).  Whole rows are staged through LDS 256 at a time (coalesced
+// copies; the next chunk is loaded into registers while the current one is
+// summed), so each element is read from memory once.  Wave w computes the
+// entries e = w, w + 16, ... (with sym, the entries a <= b only, the others by
+// conjugation); per entry the lanes stride over the rows j = lane, lane + 64, ...
+// in order and the lane sums are added by the fixed DPP tree.  stage holds
+// 2 x 256 x kFRMax float2.  Ends with a barrier.  (Not inlined: inlined at its
+// three call sites it pushed k_fqr<6> past 128 VGPRs.)
 template <int R>
-__device__ void fgram(const float2* X, const float2* Y, int n, int r, double* red, double* out, double2* W,
-                      bool sym = true) {
-  (void)red;
-  (void)out;
-  const int lane = threadIdx.x & 63, wave = wave_id();
+__device__ __noinline__ void fgram(const float2* X, const float2* Y, int n, int r, float2* stage, double2* W,
+                                   bool sym = true) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
+  constexpr int CH = 256;
+  constexpr int kEW = (kFRMax * kFRMax + kFWaves - 1) / kFWaves;   // entries of one wave, at most
+  const bool same = X == Y;
+  float2* Xs = stage;
+  float2* Ys = same ? stage : stage + CH * kFRMax;
   const int E = sym ? r * (r + 1) / 2 : r * r;
-  for (int e = wave; e < E; e += kFWaves) {
-    int ra = 0, rb = 0;
-    if (sym) {
-      int base = 0;
-      while (e >= base + (r - ra)) {
-        base += r - ra;
-        ++ra;
+  int ra[kEW], rb[kEW];
+  double sr[kEW], si[kEW];
+#pragma unroll
+  for (int t = 0; t < kEW; ++t) {
+    const int e = wave + t * kFWaves;
+    int a = 0, b = 0;
+    if (e < E) {
+      if (sym) {
+        int base = 0;
+        while (e >= base + (r - a)) {
+          base += r - a;
+          ++a;
+        }
+        b = a + (e - base);
+      } else {
+        a = e / r;
+        b = e - a * r;
       }
-      rb = ra + (e - base);
-    } else {
-      ra = e / r;
-      rb = e - ra * r;
     }
-    double sr = 0.0, si = 0.0;
-    for (int j = lane; j < n; j += 64) {   // conj(X[j][ra]) Y[j][rb]
-      const float2 x = X[(long long)j * r + ra], y = Y[(long long)j * r + rb];
-      sr = fma((double)x.x, (double)y.x, fma((double)x.y, (double)y.y, sr));
-      si = fma((double)x.x, (double)y.y, fma(-(double)x.y, (double)y.x, si));
+    ra[t] = a;
+    rb[t] = b;
+    sr[t] = 0.0;
+    si[t] = 0.0;
+  }
+  const int nch = (n + CH - 1) / CH;
+  float2 xv[2], yv[2];   // this thread's share of a chunk: at most 256 x 8 / 1024 = 2 elements
+  auto fetch = [&](int c) {
+    const long long o = (long long)c * CH * r;
+    const int cnt = min(CH, n - c * CH) * r;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + u * kFThreads;
+      if (i < cnt) {
+        xv[u] = X[o + i];
+        if (!same) yv[u] = Y[o + i];
+      }
     }
-    sr = wave_sum_dpp(sr);
-    si = wave_sum_dpp(si);
-    if (lane == 0) {
-      W[ra * r + rb] = make_double2(sr, si);
-      if (sym) W[rb * r + ra] = make_double2(sr, -si);
+  };
+  fetch(0);
+  for (int c = 0; c < nch; ++c) {
+    const int rows = min(CH, n - c * CH);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int i = tid + u * kFThreads;
+      if (i < rows * r) {
+        Xs[i] = xv[u];
+        if (!same) Ys[i] = yv[u];
+      }
+    }
+    __syncthreads();
+    if (c + 1 < nch) fetch(c + 1);
+#pragma unroll
+    for (int t = 0; t < kEW; ++t) {
+      if (wave + t * kFWaves < E) {
+        for (int jl = lane; jl < rows; jl += 64) {   // conj(X[j][ra]) Y[j][rb]
+          const float2 x = Xs[jl * r + ra[t]], y = Ys[jl * r + rb[t]];
+          sr[t] = fma((double)x.x, (double)y.x, fma((double)x.y, (double)y.y, sr[t]));
+          si[t] = fma((double)x.x, (double)y.y, fma(-(double)x.y, (double)y.x, si[t]));
+        }
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < kEW; ++t) {
+    if (wave + t * kFWaves < E) {
+      const double vr = wave_sum_dpp(sr[t]);
+      const double vi = wave_sum_dpp(si[t]);
+      if (lane == 0) {
+        W[ra[t] * r + rb[t]] = make_double2(vr, vi);
+        if (sym) W[rb[t] * r + ra[t]] = make_double2(vr, -vi);
+      }
     }
   }
   __syncthreads();
 }
 
+// Cholesky W = L L^H of a Hermitian positive definite r x r matrix (complex FP64,
+// row-major in LDS), real positive diagonal, by one wave in LDS, right-looking:
+// the lower triangle of W is copied to L; at step j column j is scaled by
+// lane-parallel products with 1 / L_jj and the trailing lower triangle is
+// updated by all lanes.  Returns false (wave-uniform) if a pivot is not
+// positive.  All 64 lanes call it; the LDS accesses of one wave complete in order.
+__device__ bool wave_chol_c(const double2* W, double2* L, int r) {
+  const int lane = threadIdx.x & 63;
+  for (int e = lane; e < r * r; e += 64)
+    if (e % r <= e / r) L[e] = W[e];
+  __builtin_amdgcn_s_waitcnt(0);
+  __builtin_amdgcn_wave_barrier();
+  for (int j = 0; j < r; ++j) {
+    const double piv = L[j * r + j].x;
+    if (!(piv > 0.0)) return false;
+    const double d = sqrt(piv);
+    const double inv = 1.0 / d;
+    if (lane == j) {
+      L[j * r + j] = make_double2(d, 0.0);
+    } else if (lane > j && lane < r) {
+      const double2 v = L[lane * r + j];
+      L[lane * r + j] = make_double2(v.x * inv, v.y * inv);
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+    const int t = r - j - 1;   // trailing size
+    for (int e = lane; e < t * t; e += 64) {
+      const int i = j + 1 + e / t, k = j + 1 + e % t;
+      if (k <= i) {   // L[i][k] -= L[i][j] conj(L[k][j])
+        const double2 a = L[i * r + j], b = L[k * r + j], w = L[i * r + k];
+        L[i * r + k] = make_double2(w.x - (a.x * b.x + a.y * b.y), w.y - (a.y * b.x - a.x * b.y));
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+    __builtin_amdgcn_wave_barrier();
+  }
+  return true;
+}
+
+// Rinv = (L^H)^{-1} (upper triangular, complex FP64) from the factor of
+// wave_chol_c, by one wave: lane c solves L m = e_c by forward substitution (the
+// rows of L read from LDS) and writes Rinv[c][i] = conj(m[i]) to dst (r x r,
+// row-major).  All 64 lanes of the wave that factored call it.
+template <int R>
+__device__ void wave_rinv_c(const double2* L, double2* dst, int r) {
+  const int c = threadIdx.x & 63;
+  if (c < r) {
+    double2 mc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      double mr = 0.0, mi = 0.0;
+      if (i < r && i >= c) {
+        mr = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+        for (int p = 0; p < R; ++p)
+          if (p >= c && p < i) {   // - L[i][p] m[p]
+            const double2 a = L[i * r + p];
+            mr -= a.x * mc[p].x - a.y * mc[p].y;
+            mi -= a.x * mc[p].y + a.y * mc[p].x;
+          }
+        const double dd = L[i * r + i].x;
+        mr /= dd;
+        mi /= dd;
+      }
+      mc[i] = make_double2(mr, mi);
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (i < r) dst[c * r + i] = make_double2(mc[i].x, -mc[i].y);
+  }
+}
+
+// dst[0 .. count) = src[0 .. count) (complex values, 16-byte aligned arrays) by the
+// workgroup with 16-byte accesses, 8 in flight per thread.
+__device__ __forceinline__ void block_copy_c(float2* dst, const float2* src, int count) {
+  const int tid = threadIdx.x;
+  const int n4 = count >> 1;   // two complex values per float4
+  typedef float f32x4_c __attribute__((ext_vector_type(4)));
+  const f32x4_c* s4 = reinterpret_cast<const f32x4_c*>(src);
+  f32x4_c* d4 = reinterpret_cast<f32x4_c*>(dst);
+  constexpr int U = 8;
+  int i = tid;
+  for (; i + (U - 1) * kFThreads < n4; i += U * kFThreads) {
+    f32x4_c v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = s4[i + u * kFThreads];
+#pragma unroll
+    for (int u = 0; u < U; ++u) d4[i + u * kFThreads] = v[u];
+  }
+  for (; i < n4; i += kFThreads) d4[i] = s4[i];
+  if ((count & 1) && tid == 0) dst[count - 1] = src[count - 1];
+}
+
 // One CholeskyQR pass on X (n x r in global memory): X <- X R^{-1}, R = L^H from
 // X^H X = L L^H.  Returns false if X^H X is not positive definite.
 template <int R>
-__device__ bool fcholqr_pass(float2* X, int n, int r, double* red, double* out, double2* W, double2* Lm, int* okf) {
+__device__ bool fcholqr_pass(float2* X, int n, int r, float2* stage, double2* W, double2* Lm, int* okf) {
   const int tid = threadIdx.x;
-  fgram<R>(X, X, n, r, red, out, W);
-  if (tid == 0) {
-    int ok = 1;
-    for (int j = 0; j < r && ok; ++j) {
-      double s = W[j * r + j].x;
-      for (int p = 0; p < j; ++p) s -= Lm[j * r + p].x * Lm[j * r + p].x + Lm[j * r + p].y * Lm[j * r + p].y;
-      if (!(s > 0.0)) { ok = 0; break; }
-      const double d = sqrt(s);
-      Lm[j * r + j] = make_double2(d, 0.0);
-      for (int i = j + 1; i < r; ++i) {
-        double tr = W[i * r + j].x, ti = W[i * r + j].y;
-        for (int p = 0; p < j; ++p) {
-          const double2 a = Lm[i * r + p], b = Lm[j * r + p];
-          tr -= a.x * b.x + a.y * b.y;
-          ti -= a.y * b.x - a.x * b.y;
-        }
-        Lm[i * r + j] = make_double2(tr / d, ti / d);
-      }
-    }
-    *okf = ok;
+  fgram<R>(X, X, n, r, stage, W);
+  if (tid < 64) {
+    const bool ok = wave_chol_c(W, Lm, r);
+    if (tid == 0) *okf = ok ? 1 : 0;
   }
   __syncthreads();
   if (!*okf) return false;
@@ -867,6 +1049,7 @@ __device__ bool fcholqr_pass(float2* X, int n, int r, double* red, double* out, 
 // subspace change.  ORTH: U <- QR(Utmp).  One workgroup.
 template <int R>
 __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
+  __shared__ float2 stage[2 * 256 * kFRMax];   // rows staged by fgram
   __shared__ double red[kFWaves * 2 * kFRMax];
   __shared__ double out[2 * kFRMax];
   __shared__ double2 W[kFRMax * kFRMax];
@@ -879,7 +1062,7 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
   float2* X = a.Utmp;
   if (a.mode == QR_GD) {
     if (!a.ctl->eta_set) {
-      fgram<R>(a.G, a.G, n, r, red, out, W);
+      fgram<R>(a.G, a.G, n, r, stage, W);
       if (tid == 0) {
         // Hermitian W = A + iB -> real symmetric [[A, -B], [B, A]] (same eigenvalues, doubled)
         const int N = 2 * r;
@@ -908,11 +1091,11 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
     }
     __syncthreads();
   } else if (a.mode == QR_POWER) {
-    for (int t = tid; t < nr; t += kFThreads) X[t] = a.G[t];
+    block_copy_c(X, a.G, nr);
     __syncthreads();
   }
-  bool ok = fcholqr_pass<R>(X, n, r, red, out, W, Lm, &okf);
-  if (ok) ok = fcholqr_pass<R>(X, n, r, red, out, W, Lm, &okf);
+  bool ok = fcholqr_pass<R>(X, n, r, stage, W, Lm, &okf);
+  if (ok) ok = fcholqr_pass<R>(X, n, r, stage, W, Lm, &okf);
   if (!ok) {
     if (tid == 0) a.ctl->err |= 2;
     return;
@@ -920,7 +1103,7 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
   if (a.mode == QR_POWER) {
     // subspace change ||U_new - U_old (U_old^H U_new)||_F from the residual entries
     // (r - ||U_old^H U_new||_F^2 cancels below angles of ~3e-4 in FP32)
-    fgram<R>(a.U, X, n, r, red, out, W, false);   // U_old^H U_new
+    fgram<R>(a.U, X, n, r, stage, W, false);   // U_old^H U_new
     double acc[1] = {0.0};
     for (int i = tid; i < n; i += kFThreads) {   // one row per thread: U_old row in registers
       float2 u[R];
@@ -952,10 +1135,11 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
       if (sd <= a.power_tol || (sd <= 1e-3 && prev > 0.0 && sd >= 0.9 * prev)) a.ctl->conv = 1;
     }
   }
-  for (int t = tid; t < nr; t += kFThreads) {
-    if (a.mode == QR_GD) a.Uprev[t] = a.U[t];
-    a.U[t] = X[t];
+  if (a.mode == QR_GD) {
+    block_copy_c(a.Uprev, a.U, nr);
+    __syncthreads();
   }
+  block_copy_c(a.U, X, nr);
   if (a.mode == QR_GD) {
     double s[1] = {0.0};
     int fl = 0;
@@ -999,11 +1183,12 @@ __global__ void k_fbasis(float2* U, int n, int r) {
 //
 // The projected GD step U+ = QR(U - eta grad) of Alg. 1 for the Fourier form,
 // split so that the n x r arrays are streamed by many CUs:
-//   k_fgrad_gd : rows of grad (as k_fgrad) and, per 256-row block, the partial
-//                Grams U^H U, U^H G, G^H G (wave per entry, lanes over rows);
+//   k_fgrad_gd : rows of grad (as k_fgrad, four column splits) and, per 256-row
+//                block, the partial Grams U^H U, U^H G, G^H G (wave per entry,
+//                lanes over rows);
 //   k_fqr_a    : one workgroup: sums the partials in block order, eta at t = 1,
 //                the Gram of X = U - eta G by expansion, its Cholesky factor and
-//                R1^{-1}; the residual and the iteration counter;
+//                R1^{-1} (one wave); the residual and the iteration counter;
 //   k_fqr_b    : X = (U - eta G) R1^{-1} row by row, partial Grams of X;
 //   k_fqr_c    : one workgroup: R2^{-1} from the Gram of X;
 //   k_fqr_d    : U_prev = U, U = X R2^{-1}.
@@ -1013,12 +1198,12 @@ __global__ void k_fbasis(float2* U, int n, int r) {
 namespace {
 
 // Partial Gram of the 256 LDS rows Xl, Yl (rows x r complex): dst[a * r + b] =
-// sum_rows conj(X[a]) Y[b]; waves take entries w, w + 4, ...; with sym only
-// a <= b are summed and the rest mirrored.
+// sum_rows conj(X[a]) Y[b]; the workgroup's waves take entries w, w + waves, ...;
+// with sym only a <= b are summed and the rest mirrored.
 __device__ void rows_gram(const float2* Xl, const float2* Yl, int r, bool sym, double2* dst) {
-  const int lane = threadIdx.x & 63, wave = wave_id();
+  const int lane = threadIdx.x & 63, wave = wave_id(), waves = blockDim.x >> 6;
   const int E = sym ? r * (r + 1) / 2 : r * r;
-  for (int e = wave; e < E; e += 4) {
+  for (int e = wave; e < E; e += waves) {
     int ra = 0, rb = 0;
     if (sym) {
       int base = 0;
@@ -1046,75 +1231,27 @@ __device__ void rows_gram(const float2* Xl, const float2* Yl, int r, bool sym, d
   }
 }
 
-// Cholesky W = L L^H (complex r x r, thread 0) and Rinv = (L^H)^{-1} (upper
-// triangular) written to dst; false if a pivot is not positive.
-__device__ bool chol_rinv_c(const double2* W, double2* L, double2* dst, int r) {
-  for (int j = 0; j < r; ++j) {
-    double s = W[j * r + j].x;
-    for (int p = 0; p < j; ++p) s -= L[j * r + p].x * L[j * r + p].x + L[j * r + p].y * L[j * r + p].y;
-    if (!(s > 0.0)) return false;
-    const double d = sqrt(s);
-    L[j * r + j] = make_double2(d, 0.0);
-    for (int i = j + 1; i < r; ++i) {
-      double tr = W[i * r + j].x, ti = W[i * r + j].y;
-      for (int p = 0; p < j; ++p) {   // - L[i][p] conj(L[j][p])
-        const double2 a = L[i * r + p], b = L[j * r + p];
-        tr -= a.x * b.x + a.y * b.y;
-        ti -= a.y * b.x - a.x * b.y;
-      }
-      L[i * r + j] = make_double2(tr / d, ti / d);
-    }
-  }
-  // M = L^{-1} (lower) column by column; Rinv = M^H: Rinv[a][c] = conj(M[c][a])
-  for (int c = 0; c < r; ++c)
-    for (int i = 0; i < r; ++i) {
-      double mr = 0.0, mi = 0.0;
-      if (i >= c) {
-        mr = (i == c) ? 1.0 : 0.0;
-        for (int p = c; p < i; ++p) {   // - L[i][p] M[p][c]
-          const double2 a = L[i * r + p], m = dst[c * r + p];   // dst holds M^H so far: M[p][c] = conj(dst[c][p])
-          const double pr = m.x, pi = -m.y;
-          mr -= a.x * pr - a.y * pi;
-          mi -= a.x * pi + a.y * pr;
-        }
-        const double dd = L[i * r + i].x;
-        mr /= dd;
-        mi /= dd;
-      }
-      dst[c * r + i] = make_double2(mr, -mi);   // Rinv[c][i] = conj(M[i][c])
-    }
-  return true;
-}
-
 }  // namespace
 
 template <int R>
-__global__ __launch_bounds__(256) void k_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q, int r,
-                                                  float2* Gsum, double2* part) {
-  __shared__ float2 Ul[256 * kFRMax], Gl[256 * kFRMax];
-  const int tid = threadIdx.x, j = blockIdx.x * 256 + tid;
+__global__ __launch_bounds__(kFThreads) void k_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q,
+                                                        int r, float2* Gsum, double2* part) {
+  __shared__ float2 sm[2 * 256 * R];   // the split sums first, then U and grad rows
+  float2* Ul = sm;
+  float2* Gl = sm + 256 * R;
   float2 acc[R];
+  const bool mine = fgrad_rows<R>(H, B, n, q, r, acc, sm);
+  const int tid = threadIdx.x, j = blockIdx.x * 256 + (tid & 255);
+  if (mine) {
 #pragma unroll
-  for (int c = 0; c < R; ++c) acc[c] = make_float2(0.f, 0.f);
-  if (j < n)
-    for (int k = 0; k < q; ++k) {
-      const float2 h = H[(long long)k * n + j];
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-        if (c < r) {
-          const float2 b = B[(long long)k * r + c];
-          acc[c].x = fmaf(h.x, b.x, fmaf(h.y, b.y, acc[c].x));
-          acc[c].y = fmaf(h.y, b.x, fmaf(-h.x, b.y, acc[c].y));
-        }
-    }
-#pragma unroll
-  for (int c = 0; c < R; ++c)
-    if (c < r) {
-      const bool in = j < n;
-      if (in) Gsum[(long long)j * r + c] = acc[c];
-      Gl[tid * r + c] = in ? acc[c] : make_float2(0.f, 0.f);
-      Ul[tid * r + c] = in ? U[(long long)j * r + c] : make_float2(0.f, 0.f);
-    }
+    for (int c = 0; c < R; ++c)
+      if (c < r) {
+        const bool in = j < n;
+        if (in) Gsum[(long long)j * r + c] = acc[c];
+        Gl[tid * r + c] = in ? acc[c] : make_float2(0.f, 0.f);
+        Ul[tid * r + c] = in ? U[(long long)j * r + c] : make_float2(0.f, 0.f);
+      }
+  }
   __syncthreads();
   double2* slot = part + (long long)blockIdx.x * 3 * r * r;
   rows_gram(Ul, Ul, r, true, slot);
@@ -1128,6 +1265,7 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
   __shared__ double red[4];
   __shared__ double eta_s;
   const int tid = threadIdx.x, r = a.r, rr = r * r;
+  double2* W = reinterpret_cast<double2*>(Mr);
   for (int e = tid; e < 3 * rr; e += 256) {
     double sr = 0.0, si = 0.0;
     for (int b = 0; b < a.nb; ++b) {
@@ -1162,14 +1300,18 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
     }
     eta_s = eta;
     // Gram of X = U - eta G: UU - eta (UG + UG^H) + eta^2 GG
-    double2* W = reinterpret_cast<double2*>(Mr);
     for (int i = 0; i < r; ++i)
       for (int jj = 0; jj < r; ++jj) {
         const double2 uu = UU[i * r + jj], ug = UG[i * r + jj], gu = UG[jj * r + i], gg = GG[i * r + jj];
         W[i * r + jj] = make_double2(uu.x - eta * (ug.x + gu.x) + eta * eta * gg.x,
                                      uu.y - eta * (ug.y - gu.y) + eta * eta * gg.y);
       }
-    if (!chol_rinv_c(W, Lm, a.rinv, r)) {
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const bool ok = wave_chol_c(W, Lm, r);
+    if (ok) wave_rinv_c<kFRMax>(Lm, a.rinv, r);
+    if (!ok && tid == 0) {
       a.ctl->err |= 2;
       for (int e = 0; e < rr; ++e) a.rinv[e] = make_double2((e % (r + 1) == 0) ? 1.0 : 0.0, 0.0);
     }
@@ -1243,9 +1385,13 @@ __global__ __launch_bounds__(256) void k_fqr_c(FQRArgs a) {
     W[e] = make_double2(sr, si);
   }
   __syncthreads();
-  if (tid == 0 && !chol_rinv_c(W, Lm, a.rinv + rr, a.r)) {
-    a.ctl->err |= 2;
-    for (int e = 0; e < rr; ++e) a.rinv[rr + e] = make_double2((e % (a.r + 1) == 0) ? 1.0 : 0.0, 0.0);
+  if (tid < 64) {
+    const bool ok = wave_chol_c(W, Lm, a.r);
+    if (ok) wave_rinv_c<kFRMax>(Lm, a.rinv + rr, a.r);
+    if (!ok && tid == 0) {
+      a.ctl->err |= 2;
+      for (int e = 0; e < rr; ++e) a.rinv[rr + e] = make_double2((e % (a.r + 1) == 0) ? 1.0 : 0.0, 0.0);
+    }
   }
 }
 
@@ -1334,7 +1480,7 @@ hipError_t launch_fgrad(const float2* H, const float2* B, int n, int q, int r, f
                         hipStream_t st) {
   (void)hipGetLastError();
 #define FGRAD_CALL(RR) \
-  hipLaunchKernelGGL(k_fgrad<RR>, dim3((n + 255) / 256), dim3(256), 0, st, H, B, n, q, r, Gsum, skip)
+  hipLaunchKernelGGL(k_fgrad<RR>, dim3((n + 255) / 256), dim3(kFThreads), 0, st, H, B, n, q, r, Gsum, skip)
   FR_SWITCH(fr_bucket(r), FGRAD_CALL)
 #undef FGRAD_CALL
   return hipGetLastError();
@@ -1352,7 +1498,7 @@ hipError_t launch_fgrad_gd(const float2* H, const float2* B, const float2* U, in
                            double2* part, hipStream_t st) {
   (void)hipGetLastError();
 #define FGD_CALL(RR) \
-  hipLaunchKernelGGL(k_fgrad_gd<RR>, dim3((n + 255) / 256), dim3(256), 0, st, H, B, U, n, q, r, Gsum, part)
+  hipLaunchKernelGGL(k_fgrad_gd<RR>, dim3((n + 255) / 256), dim3(kFThreads), 0, st, H, B, U, n, q, r, Gsum, part)
   FR_SWITCH(fr_bucket(r), FGD_CALL)
 #undef FGD_CALL
   return hipGetLastError();
