@@ -107,12 +107,14 @@ typedef struct altgdmin_params {
   int32_t tau0;              /* IHT iterations of the initialisation (paper: 10) */
   int32_t tau;               /* IHT iterations per GDmin iteration (paper: 3) */
   int32_t t_max;             /* GDmin iterations (paper: 200) */
-  int32_t power_iters;       /* max subspace iterations for U_0 (top-r left singular vectors of L_0) */
+  int32_t power_iters;       /* max subspace iterations for U_0 (top-r left singular vectors of L_0); the
+                                change shrinks by (sigma_{r+1} / sigma_r)^2 of L_0 per step, so a small gap
+                                (ratio near 1) needs more than the default 100 */
   int32_t poll_every;        /* altgdmin_solve reads the residual every poll_every iterations */
   int32_t flags;             /* ALTGDMIN_FLAG_* bits, 0 by default */
   double eta_c;              /* eta = eta_c / ||grad_U f(U_0, B_1, S_1)||_2 (paper: 0.14) */
   double power_tol;          /* stop the subspace iteration when ||(I - U_p U_p^T) U_{p+1}||_F <= power_tol,
-                                or when that change, below 1e-3, shrank by less than 10 % in a step (the
+                                or when that change, below 1e-3, shrank by less than 1 % in a step (the
                                 FP32 rounding floor of the iterate) */
   double tol_resid;          /* altgdmin_solve stops when ||Y - A(UB+S)||_F / ||Y||_F <= tol_resid (0: never) */
   int32_t bf16_hi_max;       /* BF16X2 only: the initialisation and up to this many GDmin iterations read

@@ -294,6 +294,27 @@ def test_subspace_iteration(lib, torch):
     assert 1 <= host(its)[0] < 200
 
 
+def test_subspace_iteration_small_gap(lib, torch):
+    """A slow iteration is not a stall: with (sigma_5 / sigma_4)^2 = 0.92 the change
+    shrinks by 8 % a step for ~150 steps; the stop rule must let it reach the FP32
+    floor instead of stopping as soon as the change is below 1e-3 (about 1e-2 from
+    the SVD subspace)."""
+    rng = np.random.default_rng(11)
+    n, q, r = 400, 300, 4
+    Uf = O.qr_pos(rng.standard_normal((n, 12)))[0]
+    Vf = O.qr_pos(rng.standard_normal((q, 12)))[0]
+    sv = np.array([40.0, 30.0, 20.0, 10.0, 10.0 * np.sqrt(0.92), 8.0, 6.0, 4.0, 2.0, 1.0, 0.5, 0.25])
+    L0 = Uf @ np.diag(sv) @ Vf.T
+    L0t = L0.T.astype(np.float32)
+    Uo = torch.zeros((n, r), dtype=torch.float32, device="cuda")
+    its = torch.zeros(1, dtype=torch.int32, device="cuda")
+    Us = rng.standard_normal((n, r)).astype(np.float32)
+    lib.altgdmin_op_subspace(dev(torch, L0t), r, dev(torch, Us), 400, 1e-7, Uo, its)
+    torch.cuda.synchronize()
+    assert O.subspace_distance(Uf[:, :r], host(Uo).astype(np.float64)) <= 1e-4
+    assert 1 <= host(its)[0] < 400
+
+
 # ---------------------------------------------------------------- whole path
 
 def _solve(lib, torch, inst, t_max, bf16=False, flags=0, tol=0.0):
