@@ -433,7 +433,7 @@ hipError_t fourier_launch(altgdmin_handle* h, int which, hipStream_t st) {
     case 1: return launch_fcol(fcol_args(h, FCOL_GD), st);
     case 2:
       return launch_fgrad_gd(CF2(h->H), CF2(h->Bt), CF2(h->U), p.n, p.q, p.r, F2(h->gpart),
-                             reinterpret_cast<double2*>(h->fpart), st);
+                             reinterpret_cast<double2*>(h->fpart), nullptr, st);
     default: return launch_fqr_gd(fqr_args(h, QR_GD), st);
   }
 }
@@ -544,9 +544,12 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
     for (int it = 0; it < par->power_iters; ++it) {
       if ((e = launch_fltu(CF2(h->H), CF2(h->U), p.n, p.q, p.r, F2(h->Tpow), &h->ctl->conv, st)) != hipSuccess)
         return bail(e, "ltu");
-      if ((e = launch_fgrad(CF2(h->H), CF2(h->Tpow), p.n, p.q, p.r, F2(h->gpart), &h->ctl->conv, st)) != hipSuccess)
+      // L_0 (L_0^H U) with its per-block partial Grams, then CholeskyQR2 and the
+      // subspace change over many workgroups
+      if ((e = launch_fgrad_gd(CF2(h->H), CF2(h->Tpow), CF2(h->U), p.n, p.q, p.r, F2(h->gpart),
+                               reinterpret_cast<double2*>(h->fpart), &h->ctl->conv, st)) != hipSuccess)
         return bail(e, "power grad");
-      if ((e = launch_fqr(fqr_args(h, QR_POWER), st)) != hipSuccess) return bail(e, "power qr");
+      if ((e = launch_fqr_gd(fqr_args(h, QR_POWER), st)) != hipSuccess) return bail(e, "power qr");
     }
     if ((e = launch_reset_ctl(h->ctl, 0, st)) != hipSuccess) return bail(e, "reset eta");
     *out = h;

@@ -11,12 +11,13 @@
 //            G_k = P_k^H P_k and its inverse in FP64, the projected IHT of
 //            Alg. 2 (tau iterations, three 2D FFTs each), b_k by least squares
 //            (eq. (bk_LS)), r_k and h_k = A_k^H r_k;
-//   k_fgrad: grad_U f = sum_k h_k b_k^H, four column splits in a fixed order;
-//   k_fqr  : eta at t = 1, U - eta grad, CholeskyQR2 with a real positive
-//            diagonal, the residual.
+//   k_fgrad_gd: grad_U f = sum_k h_k b_k^H (four column splits in a fixed order)
+//            and per-block partial Grams;
+//   k_fqr_a .. k_fqr_d: eta at t = 1, U - eta grad, CholeskyQR2 with a real
+//            positive diagonal over many workgroups, the residual.
 // The initialisation uses k_fcol with M = A_k (IHT from 0, then the columns of
-// L_0 = [A_k^H (y_k - A_k s_k)]) and the subspace iteration k_fltu / k_fgrad /
-// k_fqr.
+// L_0 = [A_k^H (y_k - A_k s_k)]), k_fqr for the orthonormal start block, and the
+// subspace iteration k_fltu / k_fgrad_gd / k_fqr_a .. k_fqr_f.
 //
 // 2D FFT.  A frame lives in LDS as 96 rows of 97 complex values (one pad column
 // keeps the column pass free of bank conflicts).  Each 96-point transform is
@@ -765,20 +766,6 @@ __device__ bool fgrad_rows(const float2* H, const float2* B, int n, int q, int r
   return sp == 0;
 }
 
-template <int R>
-__global__ __launch_bounds__(kFThreads) void k_fgrad(const float2* H, const float2* B, int n, int q, int r,
-                                                     float2* Gsum, const int* skip) {
-  if (skip && *skip) return;
-  __shared__ float2 buf[2 * 256 * R];
-  float2 acc[R];
-  const bool mine = fgrad_rows<R>(H, B, n, q, r, acc, buf);
-  const int j = blockIdx.x * 256 + (threadIdx.x & 255);
-  if (mine && j < n)
-#pragma unroll
-    for (int c = 0; c < R; ++c)
-      if (c < r) Gsum[(long long)j * r + c] = acc[c];
-}
-
 namespace {
 
 // Largest eigenvalue of a real symmetric N x N matrix (row-major, destroyed) by
@@ -1045,123 +1032,24 @@ __device__ bool fcholqr_pass(float2* X, int n, int r, float2* stage, double2* W,
 
 }  // namespace
 
-// GD: U <- QR(U - eta grad) (eta fixed at t = 1), residual, log.  POWER: U <- QR(Z),
-// subspace change.  ORTH: U <- QR(Utmp).  One workgroup.
+// U <- QR(Utmp) (CholeskyQR2, real positive diagonal): the orthonormal start of
+// the subspace iteration.  One workgroup.  (The GD update and the subspace steps
+// run over many workgroups: k_fqr_a .. k_fqr_f.)
 template <int R>
 __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
   __shared__ float2 stage[2 * 256 * kFRMax];   // rows staged by fgram
-  __shared__ double red[kFWaves * 2 * kFRMax];
-  __shared__ double out[2 * kFRMax];
   __shared__ double2 W[kFRMax * kFRMax];
   __shared__ double2 Lm[kFRMax * kFRMax];
-  __shared__ double Mr[4 * kFRMax * kFRMax];
-  __shared__ double eta_s;
   __shared__ int okf;
   const int tid = threadIdx.x, n = a.n, r = a.r, nr = n * r;
-  if (a.mode == QR_POWER && a.ctl->conv) return;
   float2* X = a.Utmp;
-  if (a.mode == QR_GD) {
-    if (!a.ctl->eta_set) {
-      fgram<R>(a.G, a.G, n, r, stage, W);
-      if (tid == 0) {
-        // Hermitian W = A + iB -> real symmetric [[A, -B], [B, A]] (same eigenvalues, doubled)
-        const int N = 2 * r;
-        for (int i = 0; i < r; ++i)
-          for (int j = 0; j < r; ++j) {
-            const double2 w = W[i * r + j];
-            Mr[i * N + j] = w.x;
-            Mr[(i + r) * N + j + r] = w.x;
-            Mr[i * N + j + r] = -w.y;
-            Mr[(i + r) * N + j] = w.y;
-          }
-        const double lam = jacobi_lmax(Mr, N);
-        const double eta = lam > 0.0 ? a.eta_c / sqrt(lam) : 0.0;
-        a.ctl->eta = eta;
-        a.ctl->eta_set = 1;
-        eta_s = eta;
-      }
-    } else if (tid == 0) {
-      eta_s = a.ctl->eta;
-    }
-    __syncthreads();
-    const double eta = eta_s;
-    for (int t = tid; t < nr; t += kFThreads) {
-      const float2 u = a.U[t], g = a.G[t];
-      X[t] = make_float2((float)fma(-eta, (double)g.x, (double)u.x), (float)fma(-eta, (double)g.y, (double)u.y));
-    }
-    __syncthreads();
-  } else if (a.mode == QR_POWER) {
-    block_copy_c(X, a.G, nr);
-    __syncthreads();
-  }
   bool ok = fcholqr_pass<R>(X, n, r, stage, W, Lm, &okf);
   if (ok) ok = fcholqr_pass<R>(X, n, r, stage, W, Lm, &okf);
   if (!ok) {
     if (tid == 0) a.ctl->err |= 2;
     return;
   }
-  if (a.mode == QR_POWER) {
-    // subspace change ||U_new - U_old (U_old^H U_new)||_F from the residual entries
-    // (r - ||U_old^H U_new||_F^2 cancels below angles of ~3e-4 in FP32)
-    fgram<R>(a.U, X, n, r, stage, W, false);   // U_old^H U_new
-    double acc[1] = {0.0};
-    for (int i = tid; i < n; i += kFThreads) {   // one row per thread: U_old row in registers
-      float2 u[R];
-#pragma unroll
-      for (int e = 0; e < R; ++e) u[e] = e < r ? a.U[(long long)i * r + e] : make_float2(0.f, 0.f);
-#pragma unroll
-      for (int c = 0; c < R; ++c)
-        if (c < r) {
-          const float2 xv = X[(long long)i * r + c];
-          double dx = (double)xv.x, dy = (double)xv.y;
-#pragma unroll
-          for (int e = 0; e < R; ++e)
-            if (e < r) {
-              const double2 w = W[e * r + c];
-              dx -= (double)u[e].x * w.x - (double)u[e].y * w.y;
-              dy -= (double)u[e].x * w.y + (double)u[e].y * w.x;
-            }
-          acc[0] += dx * dx + dy * dy;
-        }
-    }
-    fblock_sum<1>(acc, red, out);
-    if (tid == 0) {
-      const double sd = sqrt(out[0]);
-      const double prev = a.ctl->power_sd;   // 0 before the first step
-      a.ctl->power_sd = sd;
-      a.ctl->power_it += 1;
-      // converged at power_tol, or once the change has stopped shrinking below 1e-3
-      // (by less than 1 % in a step): the FP32 iterate's rounding floor.  A change
-      // that still shrinks by a steady factor above 0.9 is a slow iteration (a
-      // small gap sigma_{r+1} / sigma_r of L_0), not the floor, and goes on.
-      if (sd <= a.power_tol || (sd <= 1e-3 && prev > 0.0 && sd >= 0.99 * prev)) a.ctl->conv = 1;
-    }
-  }
-  if (a.mode == QR_GD) {
-    block_copy_c(a.Uprev, a.U, nr);
-    __syncthreads();
-  }
   block_copy_c(a.U, X, nr);
-  if (a.mode == QR_GD) {
-    double s[1] = {0.0};
-    int fl = 0;
-    for (int k = tid; k < a.q; k += kFThreads) {
-      s[0] += a.colrr[k];
-      fl |= a.colflags[k];
-    }
-    // fixed-order sum: per-thread partials in thread order
-    fblock_sum<1>(s, red, out);
-    if (fl) atomicOr(&a.ctl->err, fl);
-    if (tid == 0) {
-      const double ss = out[0];
-      const double resid = a.ctl->ynorm2 > 0.0 ? sqrt(ss / a.ctl->ynorm2) : sqrt(ss);
-      const int t = a.ctl->t;
-      if (a.rlog && t < a.rlog_len) a.rlog[t] = resid;
-      a.ctl->resid = resid;
-      a.ctl->t = t + 1;
-      a.ctl->prev_resid = resid;
-    }
-  }
 }
 
 __global__ void k_ftwiddle(float2* tw) {
@@ -1185,9 +1073,9 @@ __global__ void k_fbasis(float2* U, int n, int r) {
 //
 // The projected GD step U+ = QR(U - eta grad) of Alg. 1 for the Fourier form,
 // split so that the n x r arrays are streamed by many CUs:
-//   k_fgrad_gd : rows of grad (as k_fgrad, four column splits) and, per 256-row
-//                block, the partial Grams U^H U, U^H G, G^H G (wave per entry,
-//                lanes over rows);
+//   k_fgrad_gd : rows of grad (four column splits per 1024-thread workgroup,
+//                added in a fixed order) and, per 256-row block, the partial
+//                Grams U^H U, U^H G, G^H G (wave per entry, lanes over rows);
 //   k_fqr_a    : one workgroup: sums the partials in block order, eta at t = 1,
 //                the Gram of X = U - eta G by expansion, its Cholesky factor and
 //                R1^{-1} (one wave); the residual and the iteration counter;
@@ -1196,6 +1084,14 @@ __global__ void k_fbasis(float2* U, int n, int r) {
 //   k_fqr_d    : U_prev = U, U = X R2^{-1}.
 // CholeskyQR2 as in k_fqr, with the first Gram taken from the expansion
 // U^H U - eta (U^H G + G^H U) + eta^2 G^H G of the unrounded U - eta G.
+//
+// The initialisation's subspace iteration (mode QR_POWER) runs the same chain
+// on G = L_0 (L_0^H U): k_fqr_a takes the first Gram as G^H G, k_fqr_b forms
+// X = G R1^{-1}, and k_fqr_d adds per-block partial Grams U_prev^H U; then
+//   k_fqr_e    : W = U_prev^H U from the partials, per-block sums of
+//                |U - U_prev W|^2 over the rows (the subspace change);
+//   k_fqr_f    : one thread: the change, the step counter and the stop rule.
+// Every kernel of the chain returns at once after the stop rule has fired.
 
 namespace {
 
@@ -1237,7 +1133,8 @@ __device__ void rows_gram(const float2* Xl, const float2* Yl, int r, bool sym, d
 
 template <int R>
 __global__ __launch_bounds__(kFThreads) void k_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q,
-                                                        int r, float2* Gsum, double2* part) {
+                                                        int r, float2* Gsum, double2* part, const int* skip) {
+  if (skip && *skip) return;
   __shared__ float2 sm[2 * 256 * R];   // the split sums first, then U and grad rows
   float2* Ul = sm;
   float2* Gl = sm + 256 * R;
@@ -1266,6 +1163,7 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
   __shared__ double Mr[4 * kFRMax * kFRMax];
   __shared__ double red[4];
   __shared__ double eta_s;
+  if (a.mode == QR_POWER && a.ctl->conv) return;
   const int tid = threadIdx.x, r = a.r, rr = r * r;
   double2* W = reinterpret_cast<double2*>(Mr);
   for (int e = tid; e < 3 * rr; e += 256) {
@@ -1281,7 +1179,9 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
   const double2* UU = S;
   const double2* UG = S + rr;
   const double2* GG = S + 2 * rr;
-  if (tid == 0) {
+  if (tid == 0 && a.mode == QR_POWER) {
+    for (int e = 0; e < rr; ++e) W[e] = GG[e];   // X = G: its Gram
+  } else if (tid == 0) {
     double eta;
     if (!a.ctl->eta_set) {
       const int N = 2 * r;   // Hermitian GG = A + iB -> real symmetric [[A, -B], [B, A]]
@@ -1318,6 +1218,7 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
       for (int e = 0; e < rr; ++e) a.rinv[e] = make_double2((e % (r + 1) == 0) ? 1.0 : 0.0, 0.0);
     }
   }
+  if (a.mode == QR_POWER) return;
   // the residual of the iteration (colrr in column order) and the counters
   double s = 0.0;
   int fl = 0;
@@ -1344,14 +1245,16 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
 template <int R>
 __global__ __launch_bounds__(256) void k_fqr_b(FQRArgs a) {
   __shared__ float2 Xl[256 * kFRMax];
+  if (a.mode == QR_POWER && a.ctl->conv) return;
   const int tid = threadIdx.x, j = blockIdx.x * 256 + tid, r = a.r;
-  const double eta = a.ctl->eta;
+  const bool power = a.mode == QR_POWER;
+  const double eta = power ? -1.0 : a.ctl->eta;   // POWER: X = G
   double2 x[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) {
     x[c] = make_double2(0.0, 0.0);
     if (c < r && j < a.n) {
-      const float2 u = a.U[(long long)j * r + c], g = a.G[(long long)j * r + c];
+      const float2 u = power ? make_float2(0.f, 0.f) : a.U[(long long)j * r + c], g = a.G[(long long)j * r + c];
       x[c] = make_double2(fma(-eta, (double)g.x, (double)u.x), fma(-eta, (double)g.y, (double)u.y));
     }
   }
@@ -1376,6 +1279,7 @@ __global__ __launch_bounds__(256) void k_fqr_b(FQRArgs a) {
 
 __global__ __launch_bounds__(256) void k_fqr_c(FQRArgs a) {
   __shared__ double2 W[kFRMax * kFRMax], Lm[kFRMax * kFRMax];
+  if (a.mode == QR_POWER && a.ctl->conv) return;
   const int tid = threadIdx.x, rr = a.r * a.r;
   for (int e = tid; e < rr; e += 256) {
     double sr = 0.0, si = 0.0;
@@ -1397,16 +1301,19 @@ __global__ __launch_bounds__(256) void k_fqr_c(FQRArgs a) {
   }
 }
 
-// U_prev = U; U = X R2^{-1}.
+// U_prev = U; U = X R2^{-1}.  POWER: also the per-block partial Grams U_prev^H U.
 template <int R>
 __global__ __launch_bounds__(256) void k_fqr_d(FQRArgs a) {
-  const int j = blockIdx.x * 256 + threadIdx.x, r = a.r;
-  if (j >= a.n) return;
+  __shared__ float2 Ol[256 * R], Nl[256 * R];
+  const bool power = a.mode == QR_POWER;
+  if (power && a.ctl->conv) return;
+  const int tid = threadIdx.x, j = blockIdx.x * 256 + tid, r = a.r;
+  const bool in = j < a.n;
   const double2* Ri = a.rinv + r * r;
   double2 x[R];
 #pragma unroll
   for (int c = 0; c < R; ++c) {
-    const float2 v = c < r ? a.Utmp[(long long)j * r + c] : make_float2(0.f, 0.f);
+    const float2 v = (in && c < r) ? a.Utmp[(long long)j * r + c] : make_float2(0.f, 0.f);
     x[c] = make_double2(v.x, v.y);
   }
 #pragma unroll
@@ -1420,9 +1327,81 @@ __global__ __launch_bounds__(256) void k_fqr_d(FQRArgs a) {
           tr += x[aa].x * m.x - x[aa].y * m.y;
           ti += x[aa].x * m.y + x[aa].y * m.x;
         }
-      a.Uprev[(long long)j * r + c] = a.U[(long long)j * r + c];
-      a.U[(long long)j * r + c] = make_float2((float)tr, (float)ti);
+      const float2 un = make_float2((float)tr, (float)ti);
+      const float2 uo = in ? a.U[(long long)j * r + c] : make_float2(0.f, 0.f);
+      if (in) {
+        a.Uprev[(long long)j * r + c] = uo;
+        a.U[(long long)j * r + c] = un;
+      }
+      if (power) {
+        Ol[tid * r + c] = uo;
+        Nl[tid * r + c] = in ? un : make_float2(0.f, 0.f);
+      }
     }
+  if (!power) return;
+  __syncthreads();
+  rows_gram(Ol, Nl, r, false, a.part + (long long)blockIdx.x * r * r);
+}
+
+// POWER: W = U_prev^H U summed from the per-block partials (in block order, by
+// every workgroup), then the block's sum of |U[j] - U_prev[j] W|^2 over its rows
+// (FP64 per row, the 256 row sums added by the fixed DPP tree and the 4 wave
+// totals in order) into part[nb r^2 + block].x.
+template <int R>
+__global__ __launch_bounds__(256) void k_fqr_e(FQRArgs a) {
+  __shared__ double2 Wl[kFRMax * kFRMax];
+  __shared__ double wsum[4];
+  if (a.ctl->conv) return;
+  const int tid = threadIdx.x, j = blockIdx.x * 256 + tid, r = a.r, rr = r * r;
+  for (int e = tid; e < rr; e += 256) {
+    double sr = 0.0, si = 0.0;
+    for (int b = 0; b < a.nb; ++b) {
+      const double2 v = a.part[(long long)b * rr + e];
+      sr += v.x;
+      si += v.y;
+    }
+    Wl[e] = make_double2(sr, si);
+  }
+  __syncthreads();
+  double acc = 0.0;
+  if (j < a.n) {
+    float2 u[R];
+#pragma unroll
+    for (int e = 0; e < R; ++e) u[e] = e < r ? a.Uprev[(long long)j * r + e] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (c < r) {
+        const float2 xv = a.U[(long long)j * r + c];
+        double dx = (double)xv.x, dy = (double)xv.y;
+#pragma unroll
+        for (int e = 0; e < R; ++e)
+          if (e < r) {
+            const double2 w = Wl[e * r + c];
+            dx -= (double)u[e].x * w.x - (double)u[e].y * w.y;
+            dy -= (double)u[e].x * w.y + (double)u[e].y * w.x;
+          }
+        acc += dx * dx + dy * dy;
+      }
+  }
+  acc = wave_sum_dpp(acc);
+  if ((tid & 63) == 0) wsum[tid >> 6] = acc;
+  __syncthreads();
+  if (tid == 0) a.part[(long long)a.nb * rr + blockIdx.x] = make_double2((wsum[0] + wsum[1]) + (wsum[2] + wsum[3]), 0.0);
+}
+
+// POWER: the subspace change from the block sums (in block order), the step
+// counter and the stop rule.
+__global__ void k_fqr_f(FQRArgs a) {
+  if (threadIdx.x != 0 || a.ctl->conv) return;
+  double f = 0.0;
+  for (int b = 0; b < a.nb; ++b) f += a.part[(long long)a.nb * a.r * a.r + b].x;
+  const double sd = sqrt(f);
+  const double prev = a.ctl->power_sd;   // 0 before the first step
+  a.ctl->power_sd = sd;
+  a.ctl->power_it += 1;
+  // as in k_fqr: converged at power_tol, or once the change has stopped
+  // shrinking below 1e-3 (by less than 1 % in a step)
+  if (sd <= a.power_tol || (sd <= 1e-3 && prev > 0.0 && sd >= 0.99 * prev)) a.ctl->conv = 1;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -1478,16 +1457,6 @@ hipError_t launch_fltu(const float2* H, const float2* U, int n, int q, int r, fl
   return hipGetLastError();
 }
 
-hipError_t launch_fgrad(const float2* H, const float2* B, int n, int q, int r, float2* Gsum, const int* skip,
-                        hipStream_t st) {
-  (void)hipGetLastError();
-#define FGRAD_CALL(RR) \
-  hipLaunchKernelGGL(k_fgrad<RR>, dim3((n + 255) / 256), dim3(kFThreads), 0, st, H, B, n, q, r, Gsum, skip)
-  FR_SWITCH(fr_bucket(r), FGRAD_CALL)
-#undef FGRAD_CALL
-  return hipGetLastError();
-}
-
 hipError_t launch_fqr(const FQRArgs& a, hipStream_t st) {
   (void)hipGetLastError();
 #define FQR_CALL(RR) hipLaunchKernelGGL(k_fqr<RR>, dim3(1), dim3(kFThreads), 0, st, a)
@@ -1497,10 +1466,10 @@ hipError_t launch_fqr(const FQRArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q, int r, float2* Gsum,
-                           double2* part, hipStream_t st) {
+                           double2* part, const int* skip, hipStream_t st) {
   (void)hipGetLastError();
 #define FGD_CALL(RR) \
-  hipLaunchKernelGGL(k_fgrad_gd<RR>, dim3((n + 255) / 256), dim3(kFThreads), 0, st, H, B, U, n, q, r, Gsum, part)
+  hipLaunchKernelGGL(k_fgrad_gd<RR>, dim3((n + 255) / 256), dim3(kFThreads), 0, st, H, B, U, n, q, r, Gsum, part, skip)
   FR_SWITCH(fr_bucket(r), FGD_CALL)
 #undef FGD_CALL
   return hipGetLastError();
@@ -1517,6 +1486,12 @@ hipError_t launch_fqr_gd(const FQRArgs& a, hipStream_t st) {
 #define FQD_CALL(RR) hipLaunchKernelGGL(k_fqr_d<RR>, dim3(nb), dim3(256), 0, st, a)
   FR_SWITCH(fr_bucket(a.r), FQD_CALL)
 #undef FQD_CALL
+  if (a.mode == QR_POWER) {
+#define FQE_CALL(RR) hipLaunchKernelGGL(k_fqr_e<RR>, dim3(nb), dim3(256), 0, st, a)
+    FR_SWITCH(fr_bucket(a.r), FQE_CALL)
+#undef FQE_CALL
+    hipLaunchKernelGGL(k_fqr_f, dim3(1), dim3(64), 0, st, a);
+  }
   return hipGetLastError();
 }
 

@@ -107,21 +107,20 @@ struct FQRArgs {
   const int* colflags;
   double* rlog;
   int rlog_len;
-  double2* part;         // GD over many workgroups: per-block partial Grams (nb x 3 r^2)
+  double2* part;         // over many workgroups: per-block partial Grams (nb x 3 r^2); POWER also
+                         // the per-block change sums after nb r^2
   double2* rinv;         // R1^{-1}, R2^{-1} (2 r^2)
   int nb;                // 256-row blocks of n
 };
 
 size_t fcol_lds_bytes(int rho, int r);
 hipError_t launch_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q, int r, float2* Gsum,
-                           double2* part, hipStream_t st);
+                           double2* part, const int* skip, hipStream_t st);
 hipError_t launch_fqr_gd(const FQRArgs& a, hipStream_t st);
 hipError_t launch_fcol(const FColArgs& a, hipStream_t st);
 hipError_t launch_fu(const float2* U, int r, const float2* tw, float2* FU, hipStream_t st);
 hipError_t launch_fltu(const float2* H, const float2* U, int n, int q, int r, float2* Tc, const int* skip,
                        hipStream_t st);
-hipError_t launch_fgrad(const float2* H, const float2* B, int n, int q, int r, float2* Gsum, const int* skip,
-                        hipStream_t st);
 hipError_t launch_fqr(const FQRArgs& a, hipStream_t st);
 hipError_t launch_ftwiddle(float2* tw, hipStream_t st);
 hipError_t launch_fbasis(float2* U, int n, int r, hipStream_t st);
