@@ -1095,6 +1095,28 @@ __global__ void k_fbasis(float2* U, int n, int r) {
 
 namespace {
 
+// sum over b = 0 .. nb - 1 of p[b * stride], in that order; the loads go out 8 at a time.
+__device__ __forceinline__ double2 sum_blocks(const double2* p, long long stride, int nb) {
+  double sr = 0.0, si = 0.0;
+  int b = 0;
+  for (; b + 8 <= nb; b += 8) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(long long)(b + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      sr += v[u].x;
+      si += v[u].y;
+    }
+  }
+  for (; b < nb; ++b) {
+    const double2 v = p[(long long)b * stride];
+    sr += v.x;
+    si += v.y;
+  }
+  return make_double2(sr, si);
+}
+
 // Partial Gram of the 256 LDS rows Xl, Yl (rows x r complex): dst[a * r + b] =
 // sum_rows conj(X[a]) Y[b]; the workgroup's waves take entries w, w + waves, ...;
 // with sym only a <= b are summed and the rest mirrored.
@@ -1166,15 +1188,7 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
   if (a.mode == QR_POWER && a.ctl->conv) return;
   const int tid = threadIdx.x, r = a.r, rr = r * r;
   double2* W = reinterpret_cast<double2*>(Mr);
-  for (int e = tid; e < 3 * rr; e += 256) {
-    double sr = 0.0, si = 0.0;
-    for (int b = 0; b < a.nb; ++b) {
-      const double2 v = a.part[(long long)b * 3 * rr + e];
-      sr += v.x;
-      si += v.y;
-    }
-    S[e] = make_double2(sr, si);
-  }
+  for (int e = tid; e < 3 * rr; e += 256) S[e] = sum_blocks(a.part + e, 3 * rr, a.nb);
   __syncthreads();
   const double2* UU = S;
   const double2* UG = S + rr;
@@ -1281,15 +1295,7 @@ __global__ __launch_bounds__(256) void k_fqr_c(FQRArgs a) {
   __shared__ double2 W[kFRMax * kFRMax], Lm[kFRMax * kFRMax];
   if (a.mode == QR_POWER && a.ctl->conv) return;
   const int tid = threadIdx.x, rr = a.r * a.r;
-  for (int e = tid; e < rr; e += 256) {
-    double sr = 0.0, si = 0.0;
-    for (int b = 0; b < a.nb; ++b) {
-      const double2 v = a.part[(long long)b * rr + e];
-      sr += v.x;
-      si += v.y;
-    }
-    W[e] = make_double2(sr, si);
-  }
+  for (int e = tid; e < rr; e += 256) W[e] = sum_blocks(a.part + e, rr, a.nb);
   __syncthreads();
   if (tid < 64) {
     const bool ok = wave_chol_c(W, Lm, a.r);
@@ -1353,15 +1359,7 @@ __global__ __launch_bounds__(256) void k_fqr_e(FQRArgs a) {
   __shared__ double wsum[4];
   if (a.ctl->conv) return;
   const int tid = threadIdx.x, j = blockIdx.x * 256 + tid, r = a.r, rr = r * r;
-  for (int e = tid; e < rr; e += 256) {
-    double sr = 0.0, si = 0.0;
-    for (int b = 0; b < a.nb; ++b) {
-      const double2 v = a.part[(long long)b * rr + e];
-      sr += v.x;
-      si += v.y;
-    }
-    Wl[e] = make_double2(sr, si);
-  }
+  for (int e = tid; e < rr; e += 256) Wl[e] = sum_blocks(a.part + e, rr, a.nb);
   __syncthreads();
   double acc = 0.0;
   if (j < a.n) {
@@ -1393,8 +1391,7 @@ __global__ __launch_bounds__(256) void k_fqr_e(FQRArgs a) {
 // counter and the stop rule.
 __global__ void k_fqr_f(FQRArgs a) {
   if (threadIdx.x != 0 || a.ctl->conv) return;
-  double f = 0.0;
-  for (int b = 0; b < a.nb; ++b) f += a.part[(long long)a.nb * a.r * a.r + b].x;
+  const double f = sum_blocks(a.part + (long long)a.nb * a.r * a.r, 1, a.nb).x;
   const double sd = sqrt(f);
   const double prev = a.ctl->power_sd;   // 0 before the first step
   a.ctl->power_sd = sd;
