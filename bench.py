@@ -426,7 +426,7 @@ def main() -> int:
         return 0
     if args.only == "serve":
         from paper_2311_03824_amd import serve
-        out = serve.serve(count=args.serve_requests, budget_gib=args.serve_budget_gib, log=log)
+        out = serve.serve(count=args.serve_requests, budget_gib=args.serve_budget_gib, sweep=(0.5, 1.0, 1.2), log=log)
         print(json.dumps({"serving": out}), flush=True)
         return 0
     cfg = dict(I.WORKLOADS[WORKLOAD])
@@ -539,7 +539,8 @@ def main() -> int:
     if args.serve_requests > 0:
         from paper_2311_03824_amd import serve
         log(f"serving {args.serve_requests} mixed-size requests (budget {args.serve_budget_gib} GiB)")
-        result["serving"] = serve.serve(count=args.serve_requests, budget_gib=args.serve_budget_gib, log=log)
+        result["serving"] = serve.serve(count=args.serve_requests, budget_gib=args.serve_budget_gib,
+                                        sweep=(0.5, 1.0, 1.2), log=log)
         log("serving: " + json.dumps(result["serving"]))
     if not args.no_cpu_baseline:
         log(f"timing the FP64 oracle on {args.cpu_sample_q} columns")

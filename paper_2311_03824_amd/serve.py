@@ -27,7 +27,7 @@ import concurrent.futures
 import dataclasses
 import itertools
 import time
-from typing import Callable, List, Optional
+from typing import Callable, Dict, List, Optional, Sequence
 
 import numpy as np
 
@@ -280,14 +280,37 @@ def calibrate_rate(executor, requests, budget_bytes: int, poll_every: int = 10, 
     return rep.summary()["solves_per_s"]
 
 
+def load_sweep(executor, requests, saturated: float, loads: Sequence[float], budget_bytes: int, seed: int,
+               poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
+               clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
+               log=None) -> Dict[str, dict]:
+    """The same requests under seeded Poisson arrivals at each load x the closed-loop
+    throughput `saturated`; per load: the rate, solves/s, p50 / p99 latency and the
+    converged fraction."""
+    out = {}
+    for ld in loads:
+        rate = ld * saturated
+        arr = inst.poisson_arrivals(len(requests), rate, seed)
+        reqs = [dataclasses.replace(r, arrival=float(a)) for r, a in zip(requests, arr)]
+        s = Scheduler(executor, budget_bytes, poll_every, tol, max_iters, clock=clock, sleep=sleep).run(reqs).summary()
+        out[f"{ld:g}"] = {"arrival_rate_per_s": rate, "solves_per_s": s["solves_per_s"],
+                          "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
+                          "converged_fraction": s["converged_fraction"], "error_violations": s["error_violations"]}
+        if log:
+            log(f"load {ld:g}: arrivals {rate:.2f}/s, {s['solves_per_s']:.2f} solves/s, "
+                f"p50 {s['p50_latency_s']:.3f} s, p99 {s['p99_latency_s']:.3f} s")
+    return out
+
+
 def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, load: float = 0.8,
           rate: Optional[float] = None, poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
           calibration_count: Optional[int] = None, sequential: bool = True, bf16_mixed: bool = True,
-          log=None) -> dict:
+          sweep: Sequence[float] = (), log=None) -> dict:
     """Serve `count` seeded requests on the GPU and return the summary.
 
     Without an explicit `rate`, the arrival rate is `load` times the closed-loop
-    throughput of the first `calibration_count` requests (default: all of them).
+    throughput of the first `calibration_count` requests (default: all of them);
+    `sweep` adds runs at those other multiples of it.
     """
     ex = GpuExecutor(tol=tol, max_iters=max_iters, bf16_mixed=bf16_mixed)
     reqs = inst.serving_requests(count, seed)
@@ -314,4 +337,6 @@ def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, loa
         out["batching_speedup"] = sat / seq if seq > 0 else None
         if log:
             log(f"one request at a time: {seq:.2f} solves/s (batching speedup {sat / seq:.2f}x)")
+    if sweep and sat:
+        out["load_sweep"] = load_sweep(ex, reqs, sat, sweep, budget, seed, poll_every, tol, max_iters, log=log)
     return out

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2311_03824_amd import instances as inst
-from paper_2311_03824_amd.serve import Scheduler
+from paper_2311_03824_amd.serve import Scheduler, load_sweep
 
 
 class Clock:
@@ -170,3 +170,19 @@ def test_scheduler_one_at_a_time():
     rep = Scheduler(ex, 1 << 50, poll_every=10, clock=clk, sleep=clk.sleep, max_active=1).run(reqs)
     assert ex.rounds == [1] * 10 and ex.max_in_use == max(r.a_bytes() for r in reqs)
     assert rep.summary()["completed"] == 5
+
+
+def test_load_sweep_runs_each_load_on_the_same_requests():
+    clk = Clock()
+    reqs = _reqs(12)
+    ex = MockExecutor(clk, {r.idx: 20 for r in reqs}, cost=0.01)
+    sw = load_sweep(ex, reqs, saturated=50.0, loads=(0.5, 1.2), budget_bytes=1 << 50, seed=9,
+                    clock=clk, sleep=clk.sleep)
+    assert list(sw) == ["0.5", "1.2"]
+    assert sw["0.5"]["arrival_rate_per_s"] == pytest.approx(25.0)
+    assert sw["1.2"]["arrival_rate_per_s"] == pytest.approx(60.0)
+    for v in sw.values():
+        assert v["converged_fraction"] == 1.0 and v["error_violations"] == 0
+        assert 0.0 < v["p50_latency_s"] <= v["p99_latency_s"]
+    # the caller's requests keep their own arrival times
+    assert all(r.arrival == 0.0 for r in reqs)
