@@ -369,8 +369,8 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     if (e != hipSuccess) break;
     if (ms < best_col) { best_col = ms; best_ju = ju; }
   }
-  hipEventDestroy(e0);
-  hipEventDestroy(e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("autotune: ") + hipGetErrorString(e));
   h->col_unroll = best_ju;
   h->au_depth = best_aud;
@@ -595,7 +595,7 @@ int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
     int rc = enqueue_iteration(h, cs);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
-    hipStreamDestroy(cs);
+    (void)hipStreamDestroy(cs);
     if (rc) return rc;
     if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("capture: ") + hipGetErrorString(e));
     HIPCHK(hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0));
@@ -656,7 +656,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     }
     if (e != hipSuccess) rc = fail(ALTGDMIN_EHIP, std::string("profile: ") + hipGetErrorString(e));
   }
-  for (int i = 0; i < 5; ++i) hipEventDestroy(ev[i]);
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) ms_out[k] = acc[k] / iters;
   h->t_host += iters;
@@ -708,8 +708,8 @@ int altgdmin_residual_log(altgdmin_handle* h, void* stream, double* host_log, in
 
 int altgdmin_destroy(altgdmin_handle* h) {
   if (!h) return ALTGDMIN_OK;
-  if (h->exec) hipGraphExecDestroy(h->exec);
-  if (h->graph) hipGraphDestroy(h->graph);
+  if (h->exec) (void)hipGraphExecDestroy(h->exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
   delete h;
   return ALTGDMIN_OK;
 }
