@@ -36,6 +36,11 @@
  *    transpose of Alg. 1 and Alg. 2 becomes a conjugate transpose and
  *    HardThreshold ranks by the modulus, computed as the FP32 key
  *    fl(fl(re*re) + fl(im*im)) (lower index first on equal keys).
+ *  - Threads: a handle keeps host state (iteration count, the captured graph),
+ *    so calls on one handle must not overlap; different handles may be used
+ *    from different host threads at once (the process-wide autotuning cache is
+ *    locked).  Work enqueued on one handle from different streams must be
+ *    ordered by the caller.
  *  - Return codes: ALTGDMIN_OK (0); negative values are errors; the positive
  *    ALTGDMIN_ENOTCONV is a warning.  altgdmin_last_error() gives the text of
  *    the last error of the calling thread.  Faults inside kernels surface at
