@@ -362,11 +362,19 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     mi[e] = ok[e] ? raw : 0;
     yv[e] = ok[e] ? a.Y[(long long)k * a.ldy + i] : make_float2(0.f, 0.f);
   }
-  // row i of P_k = row mask_k[i] of F U (read from the L2-resident F U when used)
-  auto Prow = [&](int e, float2 (&p)[R]) {
+  // rows i of P_k = rows mask_k[i] of F U, read once into registers (the GD
+  // steps use them about a dozen times; each re-read from L2 was a round trip
+  // on the critical path).  At R = 6, 8 this costs a few spilled registers.
+  float2 Pc[2][R];
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
     const float2* src = a.FU + (long long)mi[e] * r;
 #pragma unroll
-    for (int c = 0; c < R; ++c) p[c] = (ok[e] && c < r) ? src[c] : make_float2(0.f, 0.f);
+    for (int c = 0; c < R; ++c) Pc[e][c] = (gd && ok[e] && c < r) ? src[c] : make_float2(0.f, 0.f);
+  }
+  auto Prow = [&](int e, float2 (&p)[R]) {
+#pragma unroll
+    for (int c = 0; c < R; ++c) p[c] = Pc[e][c];
   };
   if (gd)
     for (int e = tid; e < rho; e += kFThreads) {
