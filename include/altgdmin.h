@@ -279,7 +279,10 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
 /* tau IHT iterations of Alg. 2 per column on caller state.  project = 1:
  * z_k, M_k of the GDmin loop (needs P, Lc from altgdmin_op_au); project = 0:
  * M = A_k, z = y_k as in the initialisation.  has_support = 0 starts from
- * s = 0 (S_idx/S_val ignored on entry).  S_idx/S_val are updated in place.
+ * s = 0 (S_idx/S_val ignored on entry); so does a start whose rho values are
+ * all zero (the step size then takes its support from HardThreshold(g), as
+ * for s = 0).  S_idx/S_val are updated in place; with tau = 0 and no start
+ * they become indices 0 .. rho - 1 with zero values.
  * G_out (optional, q x n) gets the gradient of the last iteration, mu_out
  * (optional, q) its step size. */
 int altgdmin_op_iht(const altgdmin_problem* prob, int32_t project, const float* P, const double* Lc,

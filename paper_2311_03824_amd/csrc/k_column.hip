@@ -452,8 +452,8 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     for (int t = tid; t < r * r; t += kThreads) Gi[t] = Gk[t];
   }
   __syncthreads();
-  bool hasT = a.has_support != 0;
-  if (hasT) {
+  int nz = 0;
+  if (a.has_support) {
     for (int t = tid; t < rho; t += kThreads) {
       int j = a.Tidx[(long long)k * rho + t];
       float v = a.Tval[(long long)k * rho + t];
@@ -466,9 +466,17 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
       Tv[t] = v;
       sd[j] = v;
       atomicOr(&inT[j >> 5], 1u << (j & 31));
+      nz |= v != 0.f;
+    }
+  } else {
+    for (int t = tid; t < rho; t += kThreads) {   // s = 0 on the support 0 .. rho - 1 (kept if tau = 0)
+      Ti[t] = t;
+      Tv[t] = 0.f;
     }
   }
-  __syncthreads();
+  // a start whose values are all zero (an initialisation with tau0 = 0) is s = 0
+  // with no support yet: T then comes from HardThreshold(g), as for no start
+  bool hasT = xwave_sum_scalar(__ballot(nz != 0) != 0ull ? 1.0 : 0.0, redd, lane, wave) > 0.0;
   int nan_seen = 0;
 
   for (int it = 0; it < a.tau; ++it) {

@@ -141,6 +141,20 @@ __device__ void fblock_sum(double (&v)[NV], double* red, double* out) {
   __syncthreads();
 }
 
+// Whether any thread of the workgroup has f != 0 (every thread calls it; a
+// barrier on entry and on exit).  slot holds kFWaves ints of LDS.
+__device__ bool fblock_any(int f, int* slot) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  const bool any = __ballot(f != 0) != 0ull;
+  if (lane == 0) slot[wave] = any ? 1 : 0;
+  __syncthreads();
+  int r = 0;
+#pragma unroll
+  for (int w = 0; w < kFWaves; ++w) r |= slot[w];
+  __syncthreads();
+  return r != 0;
+}
+
 // Exclusive prefix sum of one int per thread over the workgroup in thread order;
 // *total gets the sum.  tmp holds kFWaves + 1 ints.
 __device__ int fblock_exscan(int v, int* tmp, int* total) {
@@ -376,12 +390,26 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
 #pragma unroll
     for (int c = 0; c < R; ++c) p[c] = Pc[e][c];
   };
-  if (gd)
-    for (int e = tid; e < rho; e += kFThreads) {
-      sidx[e] = a.Sidx[(long long)k * rho + e];
-      sval[e] = a.Sval[(long long)k * rho + e];
+  int nz = 0;
+  for (int e = tid; e < rho; e += kFThreads) {
+    int j = e;   // s = 0 on the support 0 .. rho - 1 when there is no start (kept if tau = 0)
+    float2 v = make_float2(0.f, 0.f);
+    if (gd) {
+      j = a.Sidx[(long long)k * rho + e];
+      v = a.Sval[(long long)k * rho + e];
+      if (j < 0 || j >= n) {   // invalid caller state: flag it and keep every access in bounds
+        flags |= 4;
+        j = 0;
+        v = make_float2(0.f, 0.f);
+      }
     }
-  __syncthreads();
+    sidx[e] = j;
+    sval[e] = v;
+    nz |= v.x != 0.f || v.y != 0.f;
+  }
+  // a start whose values are all zero (an initialisation with tau0 = 0) is s = 0
+  // with no support yet: T then comes from HardThreshold(g), as for no start
+  const bool start = fblock_any(nz, tmp);
 
   // G_k = P_k^H P_k (FP64) and its inverse.  The rows of P_k are staged in the
   // two grids (free at this point); wave w sums the entries w, w + 16, ... of
@@ -501,18 +529,21 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     fft2_grid<true>(gA, tw);
   };
 
-  bool have = gd;
+  // A_k s at this thread's rows.  When a HardThreshold step keeps the support
+  // T, the new s is s - mu g_T, so A_k s moves by -mu A_k g_T = -mu w, which is
+  // already at hand: the next transform of s is skipped (equal up to rounding
+  // order).  mark is a bitmap of T over n, kept in grid B between transforms.
+  float2 as[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+  bool have = start, known = !start;   // without a start s = 0, so A_k s = 0
+  unsigned* mark = reinterpret_cast<unsigned*>(gB);
+  const int words = (n + 31) >> 5;
   const int tau = rho > 0 ? a.tau : 0;
   for (int it = 0; it < tau; ++it) {
     // u = M s - z: A s - y (projected in the GD iterations)
     float2 u[2];
-    if (have) {
-      apply_sparse(sidx, sval, rho, u);
-    } else {
-      u[0] = u[1] = make_float2(0.f, 0.f);
-    }
+    if (!known) apply_sparse(sidx, sval, rho, as);
 #pragma unroll
-    for (int e = 0; e < 2; ++e) u[e] = ok[e] ? c_sub(u[e], yv[e]) : make_float2(0.f, 0.f);
+    for (int e = 0; e < 2; ++e) u[e] = ok[e] ? c_sub(as[e], yv[e]) : make_float2(0.f, 0.f);
     if (gd) project(u);
     // g = M^H u = A^H u (u lies in the range of the projector)
     apply_adj(u);
@@ -574,24 +605,33 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     const float mu = okmu ? (float)(gg / ww) : 0.f;
     // v = s - mu g in grid A, then HardThreshold
     for (int t = tid; t < kFGrid; t += kFThreads) gA[t] = c_scale(gA[t], -mu);
+    for (int t = tid; t < words; t += kFThreads) mark[t] = 0u;
     __syncthreads();
-    for (int e = tid; e < rho; e += kFThreads) gA[fpos(sidx[e])] = c_add(gA[fpos(sidx[e])], sval[e]);
+    for (int e = tid; e < rho; e += kFThreads) {
+      const int j = sidx[e];
+      gA[fpos(j)] = c_add(gA[fpos(j)], sval[e]);
+      atomicOr(&mark[j >> 5], 1u << (j & 31));
+    }
     __syncthreads();
     flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
-    for (int e = tid; e < rho; e += kFThreads) sval[e] = gA[fpos(sidx[e])];
-    __syncthreads();
+    int moved = 0;
+    for (int e = tid; e < rho; e += kFThreads) {
+      const int j = sidx[e];
+      sval[e] = gA[fpos(j)];
+      moved |= ((mark[j >> 5] >> (j & 31)) & 1u) ^ 1u;
+    }
+    known = !fblock_any(moved, tmp);
+    if (known && mu != 0.f)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) as[e] = c_sub(as[e], c_scale(w[e], mu));
     have = true;
   }
 
   // A_k s_k and e_k = y_k - A_k s_k
   float2 ev[2];
-  if (rho > 0) {
-    apply_sparse(sidx, sval, rho, ev);
-  } else {
-    ev[0] = ev[1] = make_float2(0.f, 0.f);
-  }
+  if (rho > 0 && !known) apply_sparse(sidx, sval, rho, as);
 #pragma unroll
-  for (int e = 0; e < 2; ++e) ev[e] = ok[e] ? c_sub(yv[e], ev[e]) : make_float2(0.f, 0.f);
+  for (int e = 0; e < 2; ++e) ev[e] = ok[e] ? c_sub(yv[e], as[e]) : make_float2(0.f, 0.f);
 
   float2* Hk = a.H + (long long)k * n;
   if (gd) {

@@ -83,6 +83,30 @@ def test_gdmin_trajectory_matches_oracle(lib, torch, q, m, r, rho, iters):
     assert rep["resid"] == pytest.approx(np.linalg.norm(R) / np.linalg.norm(inst.Y), rel=1e-3)
 
 
+def test_tau0_zero_trajectory_matches_oracle(lib, torch):
+    """tau0 = 0: S_0 = 0 with no support, and the first GDmin IHT takes its step-size
+    support from HardThreshold(g), as the oracle's IHT does from s = 0."""
+    q, m, r, rho, iters = 10, 1000, 4, 60, 3
+    inst = I.make_fourier_instance(N, N, q, m, r, rho, seed=7 + q)
+    op = F.PartialFourier(N, N, inst.mask)
+    st = F.initialise(op, inst.Y, r, rho, tau0=0)
+    assert st.idx is None and not st.S.any()
+    U0 = st.U.copy()
+    for _ in range(iters):
+        st = F.gdmin_iteration(op, inst.Y, st, rho)
+    s = lib.FourierSolver(inst.mask, inst.Y, N, N, r, rho,
+                          lib.default_params(power_iters=2, t_max=iters, tau0=0), U_start=U0).init()
+    s.step(iters)
+    out = s.get()
+    rep = s.status()
+    s.close()
+    assert rep["iterations"] == iters and rep["error_flags"] == 0
+    assert F.subspace_distance(out["U"].astype(np.complex128), st.U_fit) <= 5e-5
+    assert np.array_equal(out["S_idx"], st.idx)
+    X_ref = F.estimate(st)
+    assert np.linalg.norm(_estimate(out) - X_ref) <= 1e-6 * np.linalg.norm(X_ref)
+
+
 @pytest.mark.parametrize("q,m,r,rho", [(12, 1536, 6, 184), (16, 900, 8, 60), (3, 800, 2, 20)])
 def test_subspace_iteration_reaches_the_svd_subspace(lib, torch, q, m, r, rho):
     """The initialisation's subspace iteration (complex CholeskyQR2 of L_0 L_0^H U in

@@ -317,8 +317,8 @@ def test_subspace_iteration_small_gap(lib, torch):
 
 # ---------------------------------------------------------------- whole path
 
-def _solve(lib, torch, inst, t_max, bf16=False, flags=0, tol=0.0):
-    par = lib.default_params(t_max=t_max, flags=flags, tol_resid=tol, poll_every=10)
+def _solve(lib, torch, inst, t_max, bf16=False, flags=0, tol=0.0, **extra):
+    par = lib.default_params(t_max=t_max, flags=flags, tol_resid=tol, poll_every=10, **extra)
     A_hi = inst.A_hi if bf16 else None
     A_lo = inst.A_lo if bf16 else None
     s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=A_hi, A_lo=A_lo)
@@ -644,6 +644,56 @@ def test_degenerate_shapes_match_oracle(lib, torch, shape, iters):
     if inst.rho:
         X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
     assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+
+
+def test_tau0_zero_solve_matches_oracle(lib, torch):
+    """tau0 = 0: the initialisation leaves S_0 = 0 with no support (L_0 = A^T y), and the
+    first GDmin IHT takes its step-size support from HardThreshold(g), as the oracle's
+    IHT does from s = 0.  L_0 then carries S and its r-th singular gap is slight
+    ((sigma_4 / sigma_3)^2 = 0.987 here), so the subspace iteration starts at the
+    oracle's U_0 (exact SVD), which two steps keep."""
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=231103824)
+    iters = 3
+    A = inst.A64()
+    Y = inst.Y32.astype(np.float64)
+    st = O.initialise(A, Y, inst.r, inst.rho, tau0=0)
+    assert st.idx is None and not st.S.any()
+    U0 = st.U.copy()
+    for _ in range(iters):
+        st = O.gdmin_iteration(A, Y, st, inst.rho)
+    par = lib.default_params(t_max=iters, tau0=0, power_iters=2)
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par, U_start=U0)
+    s.init().step(iters)
+    out = s.get()
+    rep = s.status()
+    s.close()
+    assert rep["error_flags"] == 0 and rep["iterations"] == iters
+    assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+
+
+def test_iht_zero_start_is_no_start(lib, torch):
+    """tau = 0 from no start writes the support 0 .. rho - 1 with zero values; IHT from that
+    all-zero start is bitwise IHT from no start."""
+    inst = I.make_instance(n=301, q=64, m=150, r=3, rho=7, seed=5)
+    p, keep = problem(lib, torch, inst)
+    q, rho = inst.q, inst.rho
+    Si = torch.full((q, rho), -1, dtype=torch.int32, device="cuda")
+    Sv = torch.full((q, rho), 7.0, dtype=torch.float32, device="cuda")
+    lib.altgdmin_op_iht(p, False, None, None, 0, False, Si, Sv)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Si), np.tile(np.arange(rho, dtype=np.int32), (q, 1)))
+    assert not host(Sv).any()
+    Si2 = torch.zeros((q, rho), dtype=torch.int32, device="cuda")
+    Sv2 = torch.zeros((q, rho), dtype=torch.float32, device="cuda")
+    lib.altgdmin_op_iht(p, False, None, None, 2, True, Si, Sv)
+    lib.altgdmin_op_iht(p, False, None, None, 2, False, Si2, Sv2)
+    torch.cuda.synchronize()
+    assert np.array_equal(host(Si), host(Si2))
+    assert np.array_equal(host(Sv), host(Sv2))
 
 
 @pytest.mark.parametrize("shape", [dict(n=10, q=4, m=1, r=1, rho=0),    # m = 1: Pi_k = 0, nothing left to fit
