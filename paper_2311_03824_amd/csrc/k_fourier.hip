@@ -141,6 +141,46 @@ __device__ void fblock_sum(double (&v)[NV], double* red, double* out) {
   __syncthreads();
 }
 
+// Whether HardThreshold keeps the support marked in the bitmap `mark`: it does
+// when every key on it is larger than every key off it (with a tie or a NaN key
+// the full select decides).  slot holds 3 kFWaves words of LDS; a barrier on
+// entry to the reduction and on exit.
+template <class Val>
+__device__ bool fsupport_kept(Val val, int n, const unsigned* mark, unsigned* slot) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  unsigned kmin = 0xffffffffu, kmax = 0u;
+  bool bad = false;
+  for (int j = threadIdx.x; j < n; j += kFThreads) {
+    const unsigned key = __float_as_uint(c_abs2_key(val(j)));
+    bad |= key > 0x7f800000u;
+    if ((mark[j >> 5] >> (j & 31)) & 1u)
+      kmin = min(kmin, key);
+    else
+      kmax = max(kmax, key);
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, o));
+    kmax = max(kmax, __shfl_xor(kmax, o));
+  }
+  const bool wbad = __ballot(bad) != 0ull;
+  if (lane == 0) {
+    slot[3 * wave] = kmin;
+    slot[3 * wave + 1] = kmax;
+    slot[3 * wave + 2] = wbad ? 1u : 0u;
+  }
+  __syncthreads();
+  unsigned mn = 0xffffffffu, mx = 0u, b = 0u;
+#pragma unroll
+  for (int w = 0; w < kFWaves; ++w) {
+    mn = min(mn, slot[3 * w]);
+    mx = max(mx, slot[3 * w + 1]);
+    b |= slot[3 * w + 2];
+  }
+  __syncthreads();
+  return b == 0u && mn > mx;
+}
+
 // Whether any thread of the workgroup has f != 0 (every thread calls it; a
 // barrier on entry and on exit).  slot holds kFWaves ints of LDS.
 __device__ bool fblock_any(int f, int* slot) {
@@ -613,7 +653,9 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
       atomicOr(&mark[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
-    flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
+    // most steps keep T: then sidx (ascending) is already the selection
+    if (!fsupport_kept([&](int j) { return gA[fpos(j)]; }, n, mark, reinterpret_cast<unsigned*>(red)))
+      flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
     int moved = 0;
     for (int e = tid; e < rho; e += kFThreads) {
       const int j = sidx[e];

@@ -52,6 +52,28 @@ def test_init_iht_matches_oracle(lib, torch, q, m, r, rho):
         assert np.linalg.norm(out["S_val"][k] - ref) <= 1e-6 * np.linalg.norm(ref)
 
 
+def test_init_iht_with_all_ties_matches_oracle(lib, torch):
+    """Frames with y_k = 0 make every key tie at zero: HardThreshold keeps 0 .. rho - 1
+    (lower index first), which the kept-support shortcut must leave to the full select."""
+    q, m, r, rho = 8, 700, 3, 40
+    inst = I.make_fourier_instance(N, N, q, m, r, rho, seed=731)
+    Y = inst.Y.copy()
+    Y[[0, 5]] = 0
+    op = F.PartialFourier(N, N, inst.mask)
+    S_ref, idx_ref = F.init_sparse(op, Y, rho)
+    assert np.array_equal(idx_ref[0], np.arange(rho))
+    s = lib.FourierSolver(inst.mask, Y, N, N, r, rho, lib.default_params(power_iters=0, t_max=1)).init()
+    out = s.get()
+    st = s.status()
+    s.close()
+    assert st["error_flags"] == 0
+    assert np.array_equal(out["S_idx"], idx_ref)
+    assert not out["S_val"][[0, 5]].any()
+    for k in range(q):
+        ref = S_ref[k, idx_ref[k]]
+        assert np.linalg.norm(out["S_val"][k] - ref) <= 1e-6 * max(np.linalg.norm(ref), 1e-30)
+
+
 @pytest.mark.parametrize("q,m,r,rho,iters", [(16, 1536, 6, 184, 4), (10, 1000, 4, 60, 3), (64, 1536, 6, 184, 2),
                                              (16, 900, 8, 60, 2), (6, 500, 2, 20, 3), (3, 800, 2, 20, 2)])
 def test_gdmin_trajectory_matches_oracle(lib, torch, q, m, r, rho, iters):
