@@ -397,6 +397,43 @@ static __device__ int block_select(const float* vals, int n, int rho, int* idx, 
   return ctl[2];
 }
 
+// Whether HardThreshold of vals[0..n) keeps the support marked in the bitmap
+// inT: it does when every magnitude on it is larger than every magnitude off it
+// (with a tie or a NaN the full select decides).  slot: 2 kWaves words of LDS;
+// barriers inside, the last one after the slot is read.
+static __device__ bool block_support_kept(const float* vals, int n, const unsigned* inT, unsigned* slot) {
+  const int lane = threadIdx.x & 63, wave = wave_id();
+  unsigned kmin = 0xffffffffu, kmax = 0u;
+  bool bad = false;
+  for (int j = threadIdx.x; j < n; j += kThreads) {
+    const unsigned key = __float_as_uint(vals[j]) & 0x7fffffffu;
+    bad |= key > 0x7f800000u;
+    if ((inT[j >> 5] >> (j & 31)) & 1u)
+      kmin = min(kmin, key);
+    else
+      kmax = max(kmax, key);
+  }
+  if (bad) kmin = 0u;   // fails the test below for the whole block
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    kmin = min(kmin, __shfl_xor(kmin, o));
+    kmax = max(kmax, __shfl_xor(kmax, o));
+  }
+  if (lane == 0) {
+    slot[2 * wave] = kmin;
+    slot[2 * wave + 1] = kmax;
+  }
+  __syncthreads();
+  unsigned mn = 0xffffffffu, mx = 0u;
+#pragma unroll
+  for (int w = 0; w < kWaves; ++w) {
+    mn = min(mn, slot[2 * w]);
+    mx = max(mx, slot[2 * w + 1]);
+  }
+  __syncthreads();
+  return mn > mx;
+}
+
 // ---------------------------------------------------------------- k_col
 
 template <int FMT, int NC, int JU>
@@ -514,14 +551,23 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     // s - mu g, then HardThreshold
     for (int j = tid; j < n; j += kThreads) gl[j] = (float)fma(-mu, (double)gl[j], (double)sd[j]);
     __syncthreads();
-    nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
-    for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
-    for (int wd = tid; wd < nwords; wd += kThreads) inT[wd] = 0u;
-    __syncthreads();
-    for (int t = tid; t < rho; t += kThreads) {
-      const int j = Ti[t];
-      sd[j] = Tv[t];
-      atomicOr(&inT[j >> 5], 1u << (j & 31));
+    if (hasT && block_support_kept(gl, n, inT, reinterpret_cast<unsigned*>(hist))) {
+      // most steps keep T: Ti (ascending) and inT stand, s takes the new values on T
+      for (int t = tid; t < rho; t += kThreads) {
+        const int j = Ti[t];
+        Tv[t] = gl[j];
+        sd[j] = gl[j];
+      }
+    } else {
+      nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
+      for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
+      for (int wd = tid; wd < nwords; wd += kThreads) inT[wd] = 0u;
+      __syncthreads();
+      for (int t = tid; t < rho; t += kThreads) {
+        const int j = Ti[t];
+        sd[j] = Tv[t];
+        atomicOr(&inT[j >> 5], 1u << (j & 31));
+      }
     }
     __syncthreads();
     hasT = true;
