@@ -6,7 +6,8 @@
 // complex64 (float2 = re, im); every transpose of the real path is a conjugate
 // transpose and HardThreshold ranks by modulus.  Per GDmin iteration of Alg. 1:
 //
-//   k_fu   : F U (the DFT of each column of U), one workgroup per column of U;
+//   k_fu   : F U (the DFT of each column of U): a row pass and a column pass,
+//            one 96-point line per 32 lanes;
 //   k_fcol : per column k (one 1024-thread workgroup): P_k = (F U)[mask_k],
 //            G_k = P_k^H P_k and its inverse in FP64, the projected IHT of
 //            Alg. 2 (tau iterations, three 2D FFTs each), b_k by least squares
@@ -755,19 +756,29 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
 
 // ---------------------------------------------------------------- U side
 
-// F U: column c of U (n x r, row-major) transformed by workgroup c.
-__global__ __launch_bounds__(kFThreads) void k_fu(const float2* U, int r, const float2* twg, float2* FU) {
-  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  float2* grid = reinterpret_cast<float2*>(smem);
-  float2* tw = grid + kFGrid;
-  const int c = blockIdx.x, tid = threadIdx.x;
-  for (int t = tid; t < kFN; t += kFThreads) tw[t] = twg[t];
-  zero_grid(grid);
-  __syncthreads();
-  for (int j = tid; j < kFN * kFN; j += kFThreads) grid[fpos(j)] = U[(long long)j * r + c];
-  __syncthreads();
-  fft2_grid<false>(grid, tw);
-  for (int u = tid; u < kFN * kFN; u += kFThreads) FU[(long long)u * r + c] = grid[fpos(u)];
+// F U, the unitary 2D DFT of each of U's r columns (n x r, row-major; frame
+// element (j1, j2) at row j1 * 96 + j2), in two launches that each give one
+// 96-point line to a group of 32 lanes: PASS 0 transforms the rows (j1, c) of U
+// into FU, PASS 1 the columns (u2, c) of FU in place, with the 1/96 scale (the
+// same transform and scaling as fft2_grid).  A group reads its whole line before
+// it writes (the lane exchanges need every lane's loads), and no two groups share
+// an element, so the column pass can run in place.  kFN r is even, so a wave's
+// two groups exit together.
+template <int PASS>
+__global__ __launch_bounds__(64) void k_fu(const float2* U, int r, const float2* tw, float2* FU) {
+  const int gid = blockIdx.x * 2 + (threadIdx.x >> 5), l = threadIdx.x & 31;
+  if (gid >= kFN * r) return;
+  const int line = gid / r, c = gid - line * r;
+  const int k1 = (int)(__builtin_bitreverse32((unsigned)l) >> 27);
+  const long long stride = PASS == 0 ? (long long)r : (long long)kFN * r;
+  const long long base = PASS == 0 ? (long long)line * kFN * r + c : (long long)line * r + c;
+  const float2* src = (PASS == 0 ? U : FU) + base;
+  float2 v[3] = {src[l * stride], src[(l + 32) * stride], src[(l + 64) * stride]};
+  fft96<false>(v, l, tw);
+  float2* dst = FU + base;
+  const float s = 1.0f / kFN;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) dst[(3 * k1 + a) * stride] = PASS == 0 ? v[a] : c_scale(v[a], s);
 }
 
 // Tc[k][c] = sum_j H[k][j] conj(U[j][c]) (so that L_0 (L_0^H U) = sum_k h_k conj(Tc[k]) ^ T).
@@ -1523,15 +1534,10 @@ hipError_t launch_fcol(const FColArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_fu(const float2* U, int r, const float2* tw, float2* FU, hipStream_t st) {
-  const size_t lds = 8 * (size_t)(kFGrid + kFN);
   (void)hipGetLastError();
-  static bool attr_set = false;   // raised once, before any graph capture
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute((const void*)k_fu, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
-  hipLaunchKernelGGL(k_fu, dim3(r), dim3(kFThreads), lds, st, U, r, tw, FU);
+  const int blocks = kFN * r / 2;   // two 32-lane groups per 64-thread workgroup
+  hipLaunchKernelGGL(k_fu<0>, dim3(blocks), dim3(64), 0, st, U, r, tw, FU);
+  hipLaunchKernelGGL(k_fu<1>, dim3(blocks), dim3(64), 0, st, U, r, tw, FU);
   return hipGetLastError();
 }
 
