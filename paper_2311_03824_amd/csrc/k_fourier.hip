@@ -362,7 +362,7 @@ __device__ bool fblock_chol_inverse(const double2* G, double2* L, double2* Ginv,
 
 // LDS layout of the column kernel (bytes)
 struct FColLayout {
-  size_t gridA, gridB, tw, red, gi, dsum, sidx, sval, gT, hist, tmp, total;
+  size_t gridA, gridB, tw, red, gi, dsum, gx, sidx, sval, gT, hist, tmp, total;
   __host__ __device__ FColLayout(int rho, int r) {
     size_t o = 0;
     gridA = o; o = align16(o + 8 * (size_t)kFGrid);
@@ -371,6 +371,7 @@ struct FColLayout {
     red = o;   o = align16(o + 8 * (size_t)kFWaves * (2 * kFRMax + 2));
     gi = o;    o = align16(o + 16 * (size_t)r * r);
     dsum = o;  o = align16(o + 8 * (size_t)(2 * kFRMax + 2));
+    gx = o;    o = align16(o + 16 * (size_t)kFRMax);
     sidx = o;  o = align16(o + 4 * (size_t)rho);
     sval = o;  o = align16(o + 8 * (size_t)rho);
     gT = o;    o = align16(o + 8 * (size_t)rho);
@@ -395,6 +396,7 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
   double* red = reinterpret_cast<double*>(smem + lay.red);
   double2* Gi = reinterpret_cast<double2*>(smem + lay.gi);
   double* dsum = reinterpret_cast<double*>(smem + lay.dsum);
+  double2* gx = reinterpret_cast<double2*>(smem + lay.gx);
   int* sidx = reinterpret_cast<int*>(smem + lay.sidx);
   float2* sval = reinterpret_cast<float2*>(smem + lay.sval);
   float2* gT = reinterpret_cast<float2*>(smem + lay.gT);
@@ -500,6 +502,22 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     if (!fblock_chol_inverse(Gl, Ll, Gi, Yl, r)) flags |= 2;
   }
 
+  // gx = G_k^{-1} x for the complex x in dsum[0 .. 2r), entry ra by thread ra
+  // (one 36-term FP64 chain per workgroup rather than per thread); one barrier.
+  auto ginv_apply = [&]() {
+    if (tid < r) {
+      double dr = 0.0, di = 0.0;
+      for (int cb = 0; cb < r; ++cb) {
+        const double2 g = Gi[tid * r + cb];
+        const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
+        dr += g.x * xr - g.y * xi;
+        di += g.x * xi + g.y * xr;
+      }
+      gx[tid] = make_double2(dr, di);
+    }
+    __syncthreads();
+  };
+
   // v <- v - P_k G_k^{-1} P_k^H v for the two rows of this thread
   auto project = [&](float2 (&v)[2]) {
     double c[2 * R];
@@ -516,19 +534,10 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
       }
     }
     fblock_sum<2 * R>(c, red, dsum);
+    ginv_apply();
     float2 d[R];
 #pragma unroll
-    for (int ra = 0; ra < R; ++ra) {
-      double dr = 0.0, di = 0.0;
-      if (ra < r)
-        for (int cb = 0; cb < r; ++cb) {
-          const double2 g = Gi[ra * r + cb];
-          const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
-          dr += g.x * xr - g.y * xi;
-          di += g.x * xi + g.y * xr;
-        }
-      d[ra] = make_float2((float)dr, (float)di);
-    }
+    for (int ra = 0; ra < R; ++ra) d[ra] = ra < r ? make_float2((float)gx[ra].x, (float)gx[ra].y) : make_float2(0.f, 0.f);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       float2 p[R];
@@ -628,17 +637,9 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
       gg = dsum[2 * R + 1];
       ww = dsum[2 * R];
       if (gd) {
+        ginv_apply();
         double q = 0.0;   // Re(c^H G^{-1} c)
-        for (int ra = 0; ra < r; ++ra) {
-          double dr = 0.0, di = 0.0;
-          for (int cb = 0; cb < r; ++cb) {
-            const double2 g = Gi[ra * r + cb];
-            const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
-            dr += g.x * xr - g.y * xi;
-            di += g.x * xi + g.y * xr;
-          }
-          q += dsum[2 * ra] * dr + dsum[2 * ra + 1] * di;
-        }
+        for (int ra = 0; ra < r; ++ra) q += dsum[2 * ra] * gx[ra].x + dsum[2 * ra + 1] * gx[ra].y;
         ww = fmax(ww - q, 0.0);
       }
     }
@@ -694,19 +695,10 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
       c[2 * R] += (double)ev[e].x * ev[e].x + (double)ev[e].y * ev[e].y;
     }
     fblock_sum<2 * R + 1>(c, red, dsum);
+    ginv_apply();
     float2 b[R];
 #pragma unroll
-    for (int ra = 0; ra < R; ++ra) {
-      double br = 0.0, bi = 0.0;
-      if (ra < r)
-        for (int cb = 0; cb < r; ++cb) {
-          const double2 g = Gi[ra * r + cb];
-          const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
-          br += g.x * xr - g.y * xi;
-          bi += g.x * xi + g.y * xr;
-        }
-      b[ra] = make_float2((float)br, (float)bi);
-    }
+    for (int ra = 0; ra < R; ++ra) b[ra] = ra < r ? make_float2((float)gx[ra].x, (float)gx[ra].y) : make_float2(0.f, 0.f);
     if (tid < r) {
       float2 bo = b[0];
 #pragma unroll
@@ -716,16 +708,7 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     }
     // ||r_k||^2 = ||e_k||^2 - Re(c^H b_k), since G_k b_k = c = P_k^H e_k
     double cb_re = 0.0;
-    for (int ra = 0; ra < r; ++ra) {
-      double br = 0.0, bi = 0.0;
-      for (int cb = 0; cb < r; ++cb) {
-        const double2 g = Gi[ra * r + cb];
-        const double xr = dsum[2 * cb], xi = dsum[2 * cb + 1];
-        br += g.x * xr - g.y * xi;
-        bi += g.x * xi + g.y * xr;
-      }
-      cb_re += dsum[2 * ra] * br + dsum[2 * ra + 1] * bi;
-    }
+    for (int ra = 0; ra < r; ++ra) cb_re += dsum[2 * ra] * gx[ra].x + dsum[2 * ra + 1] * gx[ra].y;
     const double rr = fmax(dsum[2 * R] - cb_re, 0.0);
     if (tid == 0) a.colrr[k] = rr;
     __syncthreads();   // dsum is read above by every thread
