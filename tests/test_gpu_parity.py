@@ -171,6 +171,31 @@ def test_init_iht_matches_oracle(lib, torch, shape):
         assert err.max() <= 1e-4 * max(1.0, np.abs(ref_vals).max())
 
 
+def test_init_iht_all_ties_matches_oracle(lib, torch):
+    """Columns with y_k = 0 make every magnitude tie at zero: HardThreshold keeps 0 .. rho - 1
+    (lower index first), which the kept-support test must leave to the full select."""
+    import dataclasses
+    inst = I.make_instance(n=301, q=16, m=150, r=3, rho=7, seed=19)
+    Y = inst.Y32.copy()
+    Y[[0, 9]] = 0.0
+    inst = dataclasses.replace(inst, Y32=Y)
+    p, keep = problem(lib, torch, inst)
+    q, n, rho = inst.q, inst.n, inst.rho
+    A = inst.A64()
+    Si = torch.zeros((q, rho), dtype=torch.int32, device="cuda")
+    Sv = torch.zeros((q, rho), dtype=torch.float32, device="cuda")
+    fl = torch.zeros(q, dtype=torch.int32, device="cuda")
+    lib.altgdmin_op_iht(p, False, None, None, 3, False, Si, Sv, None, None, fl)
+    torch.cuda.synchronize()
+    S_ref, idx_ref = O.iht(Y.astype(np.float64), lambda S: O.apply_A(A, S), lambda V: O.apply_AT(A, V),
+                           rho, 3, np.zeros((q, n)))
+    assert np.array_equal(idx_ref[[0, 9]], np.tile(np.arange(rho), (2, 1)))
+    assert np.array_equal(host(Si)[[0, 9]], idx_ref[[0, 9]])
+    assert not host(Sv)[[0, 9]].any()
+    assert not host(fl).any()
+    assert _supports_match(host(Si), idx_ref).mean() >= 0.9
+
+
 def _oracle_state_after(inst, iters):
     A = inst.A64()
     Y = inst.Y32.astype(np.float64)
