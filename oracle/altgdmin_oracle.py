@@ -33,6 +33,9 @@ design notes as well):
     before any use) and is skipped.
   * The output pairs U with the B and S fitted to it ("consistent pair").
   * mu = 0 when ||M g|| is 0 or not finite; eta = 0 when grad_U f = 0.
+  * Automatic rank (Sec. 2.6): "energy" is the sum of squared singular values;
+    r is the smallest k whose first k values reach 65 % of the energy of the
+    first floor(min(n, q, m) / 10) (at least one).
 
 Mixed-precision variant (not in the paper; an option of the GPU path whose
 A_k is stored as a BF16 hi + lo pair): every function that takes ``A_t`` uses
@@ -52,6 +55,7 @@ ETA_C = 0.14     # step-size constant of Sec. 2.6
 TAU0 = 10        # IHT iterations in the initialisation (Alg. 1, Sec. 2.6)
 TAU = 3          # IHT iterations per GDmin iteration (Alg. 1, Sec. 2.6)
 T_MAX = 200      # GDmin iterations (Sec. 2.6; Alg. 1 prints 120)
+ENERGY = 0.65    # energy threshold of the automatic rank (Sec. 2.6)
 
 
 # ---------------------------------------------------------------------------
@@ -226,6 +230,29 @@ def spectral_init(L0: np.ndarray, r: int) -> np.ndarray:
     return Uf[:, :r]
 
 
+def rank_budget(n: int, q: int, m: int) -> int:
+    """Sec. 2.6: the energy threshold looks at the first min(n/10, q/10, m/10)
+    singular values of L_0 (rounded down; at least one)."""
+    return max(1, min(n, q, m) // 10)
+
+
+def auto_rank(L0: np.ndarray, m: int, energy: float = ENERGY):
+    """Sec. 2.6, automatic rank: the b% energy threshold on the leading singular
+    values of L_0 (b = 65 in the paper's experiments).
+
+    With sigma_1 >= sigma_2 >= ... the singular values of L_0 (n x q) and
+    K = rank_budget(n, q, m), the rank is the smallest k such that the energy of
+    the first k values, sum_{i <= k} sigma_i^2, is at least `energy` times the
+    energy of the first K.  Returns (r, sigma_1..sigma_K).
+    """
+    n, q = L0.shape
+    K = rank_budget(n, q, m)
+    sv = np.linalg.svd(L0, compute_uv=False)[:K]
+    cum = np.cumsum(sv ** 2)
+    r = int(np.searchsorted(cum, energy * cum[-1], side="left")) + 1
+    return min(r, K), sv
+
+
 @dataclasses.dataclass
 class State:
     U: np.ndarray                 # (n, r) current U (the one the next iteration uses)
@@ -238,9 +265,12 @@ class State:
 
 
 def initialise(A, Y, r, rho, tau0=TAU0, mu_rule="support", A_t=None) -> State:
-    """Initialisation block of Alg. 1 (Sec. 2.3): sparse part first with B = 0, then spectral init."""
+    """Initialisation block of Alg. 1 (Sec. 2.3): sparse part first with B = 0, then
+    spectral init.  r = None takes the automatic rank of Sec. 2.6 from L_0."""
     S, idx = init_sparse(A, Y, rho, tau0, mu_rule, A_t)
     L0 = backprojection(A, Y, S, A_t)
+    if r is None:
+        r = auto_rank(L0, A.shape[1])[0]
     U0 = spectral_init(L0, r)
     return State(U=U0, S=S, idx=idx)
 

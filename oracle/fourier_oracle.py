@@ -39,6 +39,7 @@ ETA_C = 0.14
 TAU0 = 10
 TAU = 3
 T_MAX = 200
+ENERGY = 0.65    # energy threshold of the automatic rank (Sec. 2.6)
 
 
 class PartialFourier:
@@ -182,6 +183,18 @@ def spectral_init(L0, r):
     return Uf[:, :r]
 
 
+def auto_rank(L0, m, energy=ENERGY):
+    """Sec. 2.6 automatic rank on a complex L_0: the smallest k whose leading
+    singular values hold `energy` of the energy sum_i sigma_i^2 of the first
+    K = max(1, floor(min(n, q, m) / 10)).  Returns (r, sigma_1..sigma_K)."""
+    n, q = L0.shape
+    K = max(1, min(n, q, m) // 10)
+    sv = np.linalg.svd(L0, compute_uv=False)[:K]
+    cum = np.cumsum(sv ** 2)
+    r = int(np.searchsorted(cum, energy * cum[-1], side="left")) + 1
+    return min(r, K), sv
+
+
 @dataclasses.dataclass
 class State:
     U: np.ndarray
@@ -194,8 +207,12 @@ class State:
 
 
 def initialise(op, Y, r, rho, tau0=TAU0) -> State:
+    """Initialisation of Alg. 1; r = None takes the automatic rank of Sec. 2.6."""
     S, idx = init_sparse(op, Y, rho, tau0)
-    U0 = spectral_init(backprojection(op, Y, S), r)
+    L0 = backprojection(op, Y, S)
+    if r is None:
+        r = auto_rank(L0, op.m)[0]
+    U0 = spectral_init(L0, r)
     return State(U=U0, S=S, idx=idx)
 
 

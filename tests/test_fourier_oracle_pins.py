@@ -194,3 +194,38 @@ def test_generator_measurements_are_exact():
     assert np.allclose(op.apply(inst.X_star.T), inst.Y, atol=1e-12)
     assert np.all(np.diff(inst.mask, axis=1) > 0)
     assert np.allclose(inst.U_star.conj().T @ inst.U_star, np.eye(2), atol=1e-13)
+
+
+def test_backprojection_is_minus_half_the_gradient_in_s():
+    """Complex l_k = A_k^H (y_k - A_k s_k): for c(s) = ||y_k - A_k s||^2, the central
+    differences of c along Re s_j and Im s_j are -2 Re l_k[j] and -2 Im l_k[j].
+    Only the forward operator (pinned to the DFT definition) builds c."""
+    op = _op(4, 5, 3, 9, seed=21)
+    rng = np.random.default_rng(22)
+    Y = _cn(rng, (3, 9))
+    S = _cn(rng, (3, 20))
+    L0 = F.backprojection(op, Y, S)                  # n x q
+    h = 1e-4
+    for k in range(3):
+        def c(s):
+            Sk = np.zeros((3, 20), np.complex128)
+            Sk[k] = s
+            return float(np.sum(np.abs(Y[k] - op.apply(Sk)[k]) ** 2))
+        for j in range(20):
+            e = np.zeros(20, np.complex128)
+            e[j] = h
+            d_re = (c(S[k] + e) - c(S[k] - e)) / (2 * h)
+            d_im = (c(S[k] + 1j * e) - c(S[k] - 1j * e)) / (2 * h)
+            assert abs(L0[j, k].real + d_re / 2) <= 1e-7 * max(1.0, abs(d_re))
+            assert abs(L0[j, k].imag + d_im / 2) <= 1e-7 * max(1.0, abs(d_im))
+
+
+def test_auto_rank_complex_equal_values():
+    """Complex L_0 with r0 equal singular values: ceil(0.65 r0), as in the real form."""
+    rng = np.random.default_rng(5)
+    for r0, want in [(1, 1), (4, 3), (6, 4)]:
+        Uf = np.linalg.qr(_cn(rng, (300, r0)))[0]
+        Vf = np.linalg.qr(_cn(rng, (120, r0)))[0]
+        L0 = Uf @ Vf.conj().T * 2.0
+        r, sv = F.auto_rank(L0, 200)
+        assert r == want and len(sv) == 12

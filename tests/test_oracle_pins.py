@@ -282,3 +282,110 @@ def test_mixed_variant_recovers_exactly_n100():
     assert np.array_equal(st.idx, inst.supp)
     _, h_hi = O.solve(Ahi, Y, inst.r, inst.rho, t_max=len(h_mix), X_star=inst.X_star)
     assert min(h_hi) > 1e-5
+
+
+# ---------------------------------------------------------------- back-projection (Sec. 2.3)
+
+def test_backprojection_is_minus_half_the_gradient_in_s():
+    """l_k = A_k^T (y_k - A_k s_k) is -1/2 the gradient of c(s) = ||y_k - A_k s||^2 at
+    s = s_k: central differences of c, built from the forward products alone.  Dropping
+    the A_k s_k term, a sign or a transpose fails this."""
+    inst, A, Y = _small(n=25, q=5, m=15, r=2, rho=3, seed=31)
+    rng = np.random.default_rng(8)
+    S = inst.S_star.T + rng.standard_normal((inst.q, inst.n))    # a dense s, away from the truth
+    L0 = O.backprojection(A, Y, S)                               # n x q
+    h = 1e-4
+    for k in range(inst.q):
+        c = lambda s: float(np.sum((Y[k] - A[k] @ s) ** 2))
+        fd = np.empty(inst.n)
+        for j in range(inst.n):
+            e = np.zeros(inst.n)
+            e[j] = h
+            fd[j] = (c(S[k] + e) - c(S[k] - e)) / (2 * h)
+        assert np.abs(L0[:, k] + fd / 2).max() <= 1e-7 * np.abs(fd).max()
+    # at the truth (noise free) every l_k lies in the row space of A_k applied to L*
+    L0_star = O.backprojection(A, Y, inst.S_star.T)
+    want = O.apply_AT(A, O.apply_A(A, (inst.U_star @ inst.B_star).T)).T
+    assert np.allclose(L0_star, want, rtol=1e-10, atol=1e-10 * np.abs(want).max())
+
+
+# ---------------------------------------------------------------- Fig. 1 (Sec. 3)
+
+@pytest.mark.slow
+def test_fig1_exact_recovery_claim():
+    """Sec. 3, Fig. 1: Gaussian A_k, n = q = 600, m = 80, r = 4, S1 values U[-6, 6],
+    threshold budget rho_max = 7, T_max = 200; the paper reports the error reaching
+    about 1e-15 in most cases.  With the restricted normalised step the oracle goes
+    below 1e-10 within the 200 iterations (rho = 2); with the unrestricted step it is
+    still above 1e-2 after 40 iterations, where the restricted one is below 1e-4."""
+    inst = I.make_instance(600, 600, 80, 4, 2, 231103900, s_dist="uniform", s_scale=6.0)
+    A, Y = inst.A64(), inst.Y64
+    st, hist = O.solve(A, Y, 4, 7, t_max=200, X_star=inst.X_star, err_tol=1e-10)
+    assert hist[-1] < 1e-10 and len(hist) <= 200
+    assert hist[39] < 1e-4
+    _, hist_full = O.solve(A, Y, 4, 7, t_max=40, X_star=inst.X_star, mu_rule="full")
+    assert min(hist_full) > 1e-2
+
+
+# ---------------------------------------------------------------- automatic rank (Sec. 2.6)
+
+def _with_spectrum(n, q, sv, seed=0):
+    rng = np.random.default_rng(seed)
+    Uf = O.qr_pos(rng.standard_normal((n, len(sv))))[0]
+    Vf = O.qr_pos(rng.standard_normal((q, len(sv))))[0]
+    return Uf @ np.diag(sv) @ Vf.T
+
+
+def test_rank_budget_is_a_tenth_of_the_smallest_size():
+    assert O.rank_budget(600, 600, 80) == 8          # Fig. 1 and Fig. 2 shapes
+    assert O.rank_budget(400, 400, 40) == 4          # Table 1, m = 40
+    assert O.rank_budget(1000, 1000, 400) == 40
+    assert O.rank_budget(30, 25, 9) == 1             # never below one
+
+
+@pytest.mark.parametrize("r0,want", [(1, 1), (2, 2), (4, 3), (7, 5), (10, 7)])
+def test_auto_rank_equal_singular_values(r0, want):
+    """r0 equal singular values hold k / r0 of the energy after k of them, so the 65 %
+    rule gives ceil(0.65 r0) (budget 10 at n = q = 200, m = 100)."""
+    L0 = _with_spectrum(200, 200, np.full(r0, 3.0), seed=r0)
+    r, sv = O.auto_rank(L0, 100)
+    assert r == want and len(sv) == 10
+
+
+def test_auto_rank_geometric_spectrum_and_budget():
+    # sigma_i^2 = 2^-i: 50 % of the energy after one value, 75 % after two
+    L0 = _with_spectrum(300, 200, np.sqrt(2.0 ** -np.arange(1, 16)), seed=3)
+    assert O.auto_rank(L0, 150)[0] == 2
+    # 30 equal values but a budget of 10: only the first 10 count, so ceil(6.5) = 7
+    L0 = _with_spectrum(300, 200, np.ones(30), seed=4)
+    assert O.auto_rank(L0, 100)[0] == 7
+    # one dominant value: 1 regardless of the small ones
+    L0 = _with_spectrum(300, 200, np.array([10.0, 1.0, 1.0, 1.0, 1.0]), seed=5)
+    assert O.auto_rank(L0, 100)[0] == 1
+
+
+def test_auto_rank_against_eigenvalues_and_invariances():
+    """The singular values are the square roots of the eigenvalues of L_0^T L_0
+    (a library eigen-solver); scaling, transposing and rotating L_0 keep r."""
+    rng = np.random.default_rng(12)
+    L0 = _with_spectrum(250, 180, np.array([9.0, 7.0, 6.0, 2.0, 1.5, 1.0]), seed=6)
+    L0 += 0.05 * rng.standard_normal(L0.shape)
+    r, sv = O.auto_rank(L0, 120)
+    ev = np.sort(np.linalg.eigvalsh(L0.T @ L0))[::-1][: len(sv)]
+    assert np.allclose(sv ** 2, ev, rtol=1e-10)
+    cum = np.cumsum(ev)
+    assert cum[r - 1] >= 0.65 * cum[-1] and (r == 1 or cum[r - 2] < 0.65 * cum[-1])
+    Q = O.qr_pos(rng.standard_normal((250, 250)))[0]
+    assert O.auto_rank(7.5 * L0, 120)[0] == r
+    assert O.auto_rank(L0.T, 120)[0] == r
+    assert O.auto_rank(Q @ L0, 120)[0] == r
+
+
+def test_auto_rank_initialisation_uses_the_chosen_rank():
+    """r = None in the initialisation: U_0 gets auto_rank(L_0) columns."""
+    inst = I.make_instance(200, 150, 100, 3, 2, 41)
+    A, Y = inst.A64(), inst.Y64
+    st = O.initialise(A, Y, None, inst.rho)
+    S, _ = O.init_sparse(A, Y, inst.rho)
+    r, _ = O.auto_rank(O.backprojection(A, Y, S), inst.m)
+    assert st.U.shape == (inst.n, r)
