@@ -336,18 +336,24 @@ def small_configs(lib, torch, np):
     return out
 
 
-def cpu_baseline(inst_args, q_sample: int, iters: int):
-    """FP64 oracle on the first q_sample columns: init + `iters` GDmin iterations, extrapolated to the workload."""
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_sample(inst_args, q_sample: int, iters: int):
+    """Seconds of the FP64 oracle's initialisation and of one GDmin iteration on the first
+    q_sample columns of the workload."""
     import numpy as np
     from oracle import altgdmin_oracle as O
     from paper_2311_03824_amd import instances as I
-    try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
-    except Exception:
-        threads = len(os.sched_getaffinity(0))
     cfg = dict(inst_args)
-    q_full = cfg["q"]
     cfg["q"] = q_sample
     inst = I.make_instance(**cfg)
     A = inst.A64()
@@ -358,10 +364,24 @@ def cpu_baseline(inst_args, q_sample: int, iters: int):
     for _ in range(iters):
         st = O.gdmin_iteration(A, Y, st, inst.rho)
     t2 = time.perf_counter()
-    t_init, t_iter = t1 - t0, (t2 - t1) / iters
+    return t1 - t0, (t2 - t1) / iters
+
+
+def cpu_baseline(inst_args, q_sample: int, iters: int, q_single: int = 25):
+    """FP64 oracle on the first q_sample columns (init + `iters` GDmin iterations) with every
+    BLAS thread the host gives, and on q_single columns with one thread; each extrapolated
+    to the whole workload (per-column work is linear in q)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] or [1])
+    except Exception:
+        threadpool_limits = None
+        threads = len(os.sched_getaffinity(0))
+    q_full = inst_args["q"]
+    t_init, t_iter = _oracle_sample(inst_args, q_sample, iters)
     scale = q_full / q_sample
     solve_s = (t_init + T_ITERS * t_iter) * scale
-    return {
+    out = {
         "value": T_ITERS / solve_s,
         "unit": "iters/s",
         "cores": int(threads),
@@ -370,7 +390,17 @@ def cpu_baseline(inst_args, q_sample: int, iters: int):
                    f"columns of the same instance (init {t_init:.2f} s, {t_iter:.3f} s/iteration); per-column work "
                    f"is linear in q, so a {T_ITERS}-iteration solve is extrapolated as "
                    f"(init + {T_ITERS} x iteration) x {scale:g}"),
+        "cpu_model": cpu_model(),
     }
+    if threadpool_limits is not None and q_single > 0:
+        with threadpool_limits(limits=1):
+            s_init, s_iter = _oracle_sample(inst_args, q_single, 1)
+        s_scale = q_full / q_single
+        out["single_thread"] = {
+            "value": T_ITERS / ((s_init + T_ITERS * s_iter) * s_scale), "unit": "iters/s", "cores": 1,
+            "sample": (f"the same oracle with one BLAS thread: init + 1 GDmin iteration on the first {q_single} "
+                       f"columns (init {s_init:.2f} s, {s_iter:.3f} s/iteration), extrapolated x {s_scale:g}")}
+    return out
 
 
 def main() -> int:
@@ -388,7 +418,7 @@ def main() -> int:
     ap.add_argument("--profile-iters", type=int, default=20)
     ap.add_argument("--no-forms", action="store_true", help="skip the time-to-equal-error comparison of the A forms")
     ap.add_argument("--target-resid", type=float, default=1e-6)
-    ap.add_argument("--serve-requests", type=int, default=128,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the mixed-size serving run (0: skip); arrival rate = 0.8 x closed-loop rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0, help="HBM admission budget of the serving run")
     ap.add_argument("--only", choices=["fourier", "serve"],

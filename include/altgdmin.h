@@ -13,7 +13,8 @@
  *    inputs, the outputs and the workspace, which must outlive every call
  *    that uses them (and the handle).
  *  - Work is enqueued on the caller's HIP stream (`stream`, a hipStream_t
- *    passed as void*; NULL means the legacy default stream).  Calls return as
+ *    passed as void*).  The library never enqueues on the null (legacy default)
+ *    stream: a NULL stream is rejected with ALTGDMIN_EINVAL.  Calls return as
  *    soon as the work is enqueued unless they say they synchronise.
  *  - Layout of A (format ALTGDMIN_A_F32): A_k is column-major with the row
  *    index fastest: element (i, j) of A_k is A[k*a_stride_k + j*lda + i].
@@ -25,14 +26,21 @@
  *  - Y: y_k at Y[k*ldy + i], ldy >= m.
  *  - U: n x r row-major (U[j*r + c]); B is returned transposed, Bt q x r
  *    row-major (Bt[k*r + c] = b_k[c]); S as q x rho arrays of row indices
- *    (int32, ascending within a column) and values (float).
+ *    (int32, strictly ascending within a column) and values (float).  A start
+ *    support handed in by the caller (altgdmin_op_iht, altgdmin_op_lsgrad,
+ *    altgdmin_op_backproject) whose indices are out of range, or not strictly
+ *    ascending (unsorted or repeated), is flagged (error bit 2) and that column
+ *    is treated as having no start (s = 0).
  *  - Partial Fourier form (a_format ALTGDMIN_A_PFOURIER): A_k x = (F x)[mask_k]
  *    with F the unitary 2D DFT, (F x)[u1, u2] = (n1 n2)^(-1/2) sum x[j1, j2]
  *    exp(-2 pi i (u1 j1 / n1 + u2 j2 / n2)); A is never stored (A, A_lo, lda
  *    and a_stride_k are ignored).  Y, U, Bt and S_val hold complex64 values
  *    (interleaved re, im float pairs; ldy counts complex elements), so every
  *    float* output of such a problem receives twice the float count of the
- *    real form.  Limits: n1 = n2 = 96, m <= 2048, r <= 8, rho <= 256.  Every
+ *    real form.  Frames of 96 x 96 run 2D FFTs; other frame sizes with
+ *    n = n1 n2 <= 4096 and n1, n2 <= 1024 (n1 = 1 gives a 1D DFT of length n2)
+ *    run direct line DFTs, as long as the frame and the rows of P_k fit the
+ *    LDS of one CU.  Limits: m <= min(n, 2048), r <= 8, rho <= 256.  Every
  *    transpose of Alg. 1 and Alg. 2 becomes a conjugate transpose and
  *    HardThreshold ranks by the modulus, computed as the FP32 key
  *    fl(fl(re*re) + fl(im*im)) (lower index first on equal keys).
@@ -91,7 +99,11 @@ enum {
 
 /* Problem of Sec. 1.1: sizes, measurement matrices and measurements. */
 typedef struct altgdmin_problem {
-  int32_t n, q, m, r, rho;   /* 1 <= r <= min(m, n), 0 <= rho <= n; rho is the threshold budget (Sec. 2.6) */
+  int32_t n, q, m, r, rho;   /* 1 <= r <= min(m, n), 0 <= rho <= n; rho is the threshold budget (Sec. 2.6).
+                                r = 0 (real A forms): the automatic rank of Sec. 2.6, chosen by altgdmin_init
+                                from L_0 (see altgdmin_params.rank_energy); the workspace is then laid out for
+                                r_cap = min(K, 16, m, n) with K = max(1, floor(min(n, q, m) / 10)), and
+                                altgdmin_report.rank gives the r chosen (outputs have r columns) */
   int32_t a_format;          /* ALTGDMIN_A_* */
   const void* A;             /* F32: const float*; BF16X2: hi plane, const uint16_t* */
   const void* A_lo;          /* BF16X2: lo plane; NULL otherwise */
@@ -103,7 +115,8 @@ typedef struct altgdmin_problem {
                                 basis); complex64 pairs for PFOURIER */
   uint64_t a_seed;           /* PHILOX: 64-bit key of A */
   const float* normal_table; /* PHILOX: device array of ALTGDMIN_NORMAL_TABLE_SIZE FP32 */
-  int32_t n1, n2;            /* PFOURIER: frame size, n = n1 * n2 (x_k flattened row-major); built for 96 x 96 */
+  int32_t n1, n2;            /* PFOURIER: frame size, n = n1 * n2 (x_k flattened row-major): 96 x 96 (FFT), or
+                                n <= 4096 with n1, n2 <= 1024 (direct line DFTs) */
   const int32_t* fourier_mask; /* PFOURIER: q x m frequency indices u = u1 * n2 + u2, ascending per frame */
 } altgdmin_problem;
 
@@ -126,6 +139,10 @@ typedef struct altgdmin_params {
                                 the hi plane alone (2 bytes per element); 0 disables the hi-only phase */
   int32_t pad0;
   double bf16_stall;         /* BF16X2 hi-only phase ends early once resid_t >= bf16_stall * resid_{t-1} */
+  double rank_energy;        /* r = 0: the energy fraction of the automatic rank (paper: 0.65) */
+  int32_t rank_iters;        /* r = 0: steps of the block subspace iteration that estimates the leading
+                                singular values of L_0 (default 30) */
+  int32_t pad1;
 } altgdmin_params;
 
 /* Fills *p with the paper's defaults (tau0 = 10, tau = 3, t_max = 200, eta_c = 0.14). Host call. */
@@ -137,10 +154,11 @@ typedef struct altgdmin_handle altgdmin_handle;
 typedef struct altgdmin_report {
   int32_t iterations;        /* GDmin iterations done */
   int32_t power_iterations;  /* subspace iterations used for U_0 */
-  int32_t error_flags;       /* bit 0: NaN at a selection; bit 1: Gram not positive definite; bit 2: support index out of range */
+  int32_t error_flags;       /* bit 0: NaN at a selection; bit 1: Gram not positive definite; bit 2: invalid start
+                                support (index out of range, unsorted or repeated) or frequency index out of range */
   int32_t converged;         /* 1 when the last residual <= tol_resid */
   int32_t refine_iteration;  /* BF16X2: first GDmin iteration that read hi + lo (-1: still hi-only or no hi-only phase) */
-  int32_t pad0;
+  int32_t rank;              /* the rank r in use (with r = 0 in the problem: the one altgdmin_init chose) */
   double eta;                /* step size (0 before iteration 1) */
   double resid;              /* ||Y - A(U B + S)||_F / ||Y||_F of the last iteration's consistent pair */
   double power_sd;           /* last subspace-iteration change */
@@ -169,6 +187,10 @@ int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float*
 
 /* Synchronises `stream` and reads the device status into *rep (host). */
 int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep);
+
+/* Status of several handles with one synchronisation of `stream` (serving
+ * polls): reps (host, count entries) as altgdmin_status fills them. */
+int altgdmin_status_many(altgdmin_handle* const* hs, int32_t count, void* stream, altgdmin_report* reps);
 
 /* Per-iteration relative residual log, host array of length >= t_max; returns count in *count. Synchronises. */
 int altgdmin_residual_log(altgdmin_handle* h, void* stream, double* host_log, int32_t* count);
@@ -215,13 +237,32 @@ int altgdmin_group_bytes(altgdmin_handle* const* hs, int32_t count, size_t* byte
  * iteration after its residual first reaches tol_resid: its kernels skip it, so
  * its state, report.iterations and report.resid stay those of the first
  * iteration that met the tolerance.  group_ws (device, 256-byte aligned,
- * >= altgdmin_group_bytes) holds the launch tables; it is filled from the host
- * and the stream is synchronised once per call.  The batched launches use the
+ * >= altgdmin_group_bytes) holds the launch tables; each call uploads them on
+ * `stream` from a pinned host buffer the library keeps, without synchronising
+ * the stream (the call returns once the work is enqueued).  The batched launches use the
  * default loads-in-flight instantiations (an autotuned choice applies to
  * altgdmin_step / altgdmin_solve; every variant gives the same bits).  Handles
  * of a BF16X2 problem with a hi-only phase are rejected (EINVAL). */
 int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters, void* group_ws,
                        size_t group_bytes, void* stream);
+
+/* Checkpoint and resume.  Sec. 2.5 lists what the method keeps between
+ * iterations: U (n x r), B (r x q) and the 2 rho q numbers of S; with them a
+ * saved state holds the step size eta (fixed at t = 1), the iteration count
+ * and the rest of the device control block (residual, BF16 phase, error
+ * flags), U_prev (the U that B and S were fitted with) and the residual log.
+ * altgdmin_state_bytes: bytes of a saved state of this handle (host call).
+ * altgdmin_get_state: enqueues device-to-device copies of the state into
+ *   `state` (device, 256-byte aligned, >= altgdmin_state_bytes); asynchronous.
+ * altgdmin_set_state: loads a state saved from a handle of the same problem
+ *   (n, q, m, r, rho, A format and column form) into h, e.g. a fresh handle
+ *   after altgdmin_init; the next altgdmin_step continues from it, giving the
+ *   same bits as iterating on without the save.  Synchronises `stream` once to
+ *   read the saved header; EINVAL if it is not a state of such a problem.  The
+ *   problem arrays (A, Y) must be those of the saved solve. */
+int altgdmin_state_bytes(altgdmin_handle* h, size_t* bytes);
+int altgdmin_get_state(altgdmin_handle* h, void* state, size_t bytes, void* stream);
+int altgdmin_set_state(altgdmin_handle* h, const void* state, size_t bytes, void* stream);
 
 /* Frees the host handle only. */
 int altgdmin_destroy(altgdmin_handle* h);
@@ -314,6 +355,18 @@ int altgdmin_op_grad(const float* H, const float* Bt, int32_t n, int32_t q, int3
 int altgdmin_op_qr_step(const float* U, const float* grad, int32_t n, int32_t r, double eta_c,
                         double* eta_io, float* U_out, void* scratch, size_t scratch_bytes,
                         void* stream);
+
+/* Automatic rank (Sec. 2.6, "b% energy threshold"): with sigma_1 >= sigma_2 >= ...
+ * the singular values of L_0 (n x q, given as L0t q x n row-major) and
+ * K = max(1, floor(min(n, q, m) / 10)), r is the smallest k with
+ * sum_{i<=k} sigma_i^2 >= energy * sum_{i<=K} sigma_i^2.  The K values are Ritz
+ * values of `iters` steps of a block subspace iteration with b = min(K + 8, 88,
+ * n, q) columns (CholeskyQR2 with FP64 Grams), from a fixed orthonormal start;
+ * ENOTBUILT when K > 88.  r_out: device int32; sv_out (optional): device
+ * double[K], descending.  Scratch: altgdmin_op_rank_scratch_bytes.  Asynchronous. */
+int altgdmin_op_rank_scratch_bytes(int32_t n, int32_t q, int32_t m, size_t* bytes);
+int altgdmin_op_rank(const float* L0t, int32_t n, int32_t q, int32_t m, double energy, int32_t iters,
+                     int32_t* r_out, double* sv_out, void* scratch, size_t scratch_bytes, void* stream);
 
 /* Top-r left singular subspace of L0 (n x q, given as L0t q x n) by subspace
  * iteration from U_start (n x r), at most `iters` iterations or until the

@@ -211,12 +211,12 @@ def rel_error(X: np.ndarray, X_star: np.ndarray) -> float:
 # ---------------------------------------------------------------------------
 
 def init_sparse(A: np.ndarray, Y: np.ndarray, rho: int, tau0: int = TAU0, mu_rule="support",
-                A_t: Optional[np.ndarray] = None):
+                A_t: Optional[np.ndarray] = None, trace: Optional[list] = None):
     """Alg. 1 initialisation, first step: s_k = IHT(y_k, A_k, rho, tau0, 0).  Returns (S, idx)."""
     q, m, n = A.shape
     At = A if A_t is None else A_t
     return iht(Y, lambda S: apply_A(A, S), lambda V: apply_AT(At, V), rho, tau0,
-               np.zeros((q, n)), mu_rule=mu_rule, Dop=lambda S: apply_A(At, S))
+               np.zeros((q, n)), mu_rule=mu_rule, trace=trace, Dop=lambda S: apply_A(At, S))
 
 
 def backprojection(A: np.ndarray, Y: np.ndarray, S: np.ndarray, A_t: Optional[np.ndarray] = None) -> np.ndarray:
@@ -276,7 +276,8 @@ def initialise(A, Y, r, rho, tau0=TAU0, mu_rule="support", A_t=None) -> State:
 
 
 def gdmin_iteration(A, Y, st: State, rho: int, tau: int = TAU, eta_c: float = ETA_C,
-                    mu_rule="support", record: Optional[dict] = None, A_t=None) -> State:
+                    mu_rule="support", record: Optional[dict] = None, A_t=None,
+                    trace: Optional[list] = None) -> State:
     """One GDmin iteration of Alg. 1.
 
     z_k, M_k from the current U; warm-started IHT for s_k; LS for b_k
@@ -290,7 +291,7 @@ def gdmin_iteration(A, Y, st: State, rho: int, tau: int = TAU, eta_c: float = ET
     Mop = lambda S: project_out(P, G, apply_A(A, S))         # s -> M_k s
     MTop = lambda V: apply_AT(At, project_out(P, G, V))      # v -> M_k^T v (projector is symmetric)
     Dop = lambda S: project_out(P, G, apply_A(At, S))        # step-length product
-    S, idx = iht(Z, Mop, MTop, rho, tau, st.S, st.idx, mu_rule=mu_rule, Dop=Dop)
+    S, idx = iht(Z, Mop, MTop, rho, tau, st.S, st.idx, mu_rule=mu_rule, trace=trace, Dop=Dop)
     B = pinv_apply(P, G, Y - apply_A(A, S))                  # b_k
     grad = grad_U(A, U, B, S, Y, A_t)
     eta = st.eta

@@ -10,7 +10,9 @@ the problem tensors and the workspace.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
+import functools
 import os
 from typing import Optional
 
@@ -43,12 +45,13 @@ class Problem(ctypes.Structure):
 class Params(ctypes.Structure):
     _fields_ = [("tau0", c_i32), ("tau", c_i32), ("t_max", c_i32), ("power_iters", c_i32),
                 ("poll_every", c_i32), ("flags", c_i32), ("eta_c", c_f64), ("power_tol", c_f64),
-                ("tol_resid", c_f64), ("bf16_hi_max", c_i32), ("pad0", c_i32), ("bf16_stall", c_f64)]
+                ("tol_resid", c_f64), ("bf16_hi_max", c_i32), ("pad0", c_i32), ("bf16_stall", c_f64),
+                ("rank_energy", c_f64), ("rank_iters", c_i32), ("pad1", c_i32)]
 
 
 class Report(ctypes.Structure):
     _fields_ = [("iterations", c_i32), ("power_iterations", c_i32), ("error_flags", c_i32),
-                ("converged", c_i32), ("refine_iteration", c_i32), ("pad0", c_i32), ("eta", c_f64),
+                ("converged", c_i32), ("refine_iteration", c_i32), ("rank", c_i32), ("eta", c_f64),
                 ("resid", c_f64), ("power_sd", c_f64)]
 
     def as_dict(self):
@@ -70,9 +73,13 @@ _SIGS = {
     "altgdmin_step": (c_i32, [c_vp, c_i32, c_vp]),
     "altgdmin_get": (c_i32, [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_status": (c_i32, [c_vp, c_vp, c_vp]),
+    "altgdmin_status_many": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "altgdmin_residual_log": (c_i32, [c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_solve": (c_i32, [c_vp, c_vp, c_vp, c_sz, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "altgdmin_destroy": (c_i32, [c_vp]),
+    "altgdmin_state_bytes": (c_i32, [c_vp, c_vp]),
+    "altgdmin_get_state": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
+    "altgdmin_set_state": (c_i32, [c_vp, c_vp, c_sz, c_vp]),
     "altgdmin_profile_iteration": (c_i32, [c_vp, c_i32, c_vp, c_vp]),
     "altgdmin_group_bytes": (c_i32, [c_vp, c_i32, c_vp]),
     "altgdmin_step_many": (c_i32, [c_vp, c_i32, c_i32, c_vp, c_sz, c_vp]),
@@ -91,6 +98,8 @@ _SIGS = {
     "altgdmin_op_grad": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_sz, c_vp]),
     "altgdmin_op_qr_step": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_f64, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "altgdmin_op_subspace": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_f64, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "altgdmin_op_rank_scratch_bytes": (c_i32, [c_i32, c_i32, c_i32, c_vp]),
+    "altgdmin_op_rank": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_f64, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -142,10 +151,54 @@ def ptr(t) -> Optional[int]:
     return t.data_ptr()
 
 
-def stream_ptr(stream=None) -> int:
+_lib_streams = {}
+
+
+def _library_stream(device):
+    """One created stream per device (default priority) for calls made from torch's
+    null stream: the library never enqueues on the null stream."""
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return s.cuda_stream
+    idx = torch.device(device).index
+    idx = torch.cuda.current_device() if idx is None else idx
+    s = _lib_streams.get(idx)
+    if s is None:
+        s = torch.cuda.Stream(device=idx)
+        _lib_streams[idx] = s
+    return s
+
+
+@contextlib.contextmanager
+def _stream_scope(stream=None):
+    """The stream a call enqueues on: the caller's (or torch's current) stream when it is
+    a created stream; otherwise the library stream, ordered after the work already on
+    the caller's stream and before any work the caller enqueues next."""
+    torch = _torch()
+    caller = stream if stream is not None else torch.cuda.current_stream()
+    if caller.cuda_stream != 0:
+        yield caller
+        return
+    ls = _library_stream(caller.device)
+    ls.wait_stream(caller)
+    try:
+        yield ls
+    finally:
+        caller.wait_stream(ls)
+
+
+def _on_stream(fn):
+    """Entry points taking `stream=`: run `fn` with the stream of _stream_scope."""
+    @functools.wraps(fn)
+    def wrapper(*args, stream=None, **kw):
+        with _stream_scope(stream) as s:
+            return fn(*args, stream=s, **kw)
+    return wrapper
+
+
+def stream_ptr(stream) -> int:
+    p = stream.cuda_stream
+    if not p:
+        raise ValueError("the library never enqueues on the null stream")
+    return p
 
 
 def default_params(**kw) -> Params:
@@ -204,6 +257,7 @@ def altgdmin_workspace_bytes(prob: Problem, par: Params) -> int:
     return b.value
 
 
+@_on_stream
 def altgdmin_init(prob: Problem, par: Params, workspace, stream=None) -> c_vp:
     load()
     h = c_vp()
@@ -213,20 +267,32 @@ def altgdmin_init(prob: Problem, par: Params, workspace, stream=None) -> c_vp:
     return h
 
 
+@_on_stream
 def altgdmin_step(h, iters: int, stream=None) -> None:
     _check(_lib.altgdmin_step(h, iters, stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_get(h, U=None, Bt=None, S_idx=None, S_val=None, U_next=None, stream=None) -> None:
     _check(_lib.altgdmin_get(h, ptr(U), ptr(Bt), ptr(S_idx), ptr(S_val), ptr(U_next), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_status(h, stream=None) -> dict:
     rep = Report()
     _check(_lib.altgdmin_status(h, stream_ptr(stream), ctypes.byref(rep)))
     return rep.as_dict()
 
 
+@_on_stream
+def altgdmin_status_many(hs, stream=None) -> list:
+    """Status of several handles with one synchronisation (serving polls)."""
+    reps = (Report * max(1, len(hs)))()
+    _check(_lib.altgdmin_status_many(_handle_array(hs), len(hs), stream_ptr(stream), reps))
+    return [reps[i].as_dict() for i in range(len(hs))]
+
+
+@_on_stream
 def altgdmin_residual_log(h, t_max: int, stream=None) -> np.ndarray:
     buf = (c_f64 * max(1, t_max))()
     cnt = c_i32(0)
@@ -248,6 +314,7 @@ def altgdmin_group_bytes(hs) -> int:
     return b.value
 
 
+@_on_stream
 def altgdmin_step_many(hs, iters: int, group_ws, stream=None) -> None:
     """One batched launch sequence per iteration over all handles (serving)."""
     _check(_lib.altgdmin_step_many(_handle_array(hs), len(hs), iters, ptr(group_ws),
@@ -257,6 +324,7 @@ def altgdmin_step_many(hs, iters: int, group_ws, stream=None) -> None:
 KERNELS = ("k_au", "k_col", "k_grad", "k_qr")
 
 
+@_on_stream
 def altgdmin_profile_iteration(h, iters: int, stream=None) -> dict:
     """Average per-kernel milliseconds of `iters` eager GDmin iterations (HIP events on the launch stream)."""
     ms = (c_f64 * 4)()
@@ -271,11 +339,31 @@ def altgdmin_tuning(h) -> dict:
     return {"col_unroll": ju.value, "au_depth": aud.value}
 
 
+def altgdmin_state_bytes(h) -> int:
+    load()
+    b = c_sz(0)
+    _check(_lib.altgdmin_state_bytes(h, ctypes.byref(b)))
+    return b.value
+
+
+@_on_stream
+def altgdmin_get_state(h, state, stream=None) -> None:
+    """Save the solver state into the device tensor `state` (uint8, >= altgdmin_state_bytes)."""
+    _check(_lib.altgdmin_get_state(h, ptr(state), state.numel() * state.element_size(), stream_ptr(stream)))
+
+
+@_on_stream
+def altgdmin_set_state(h, state, stream=None) -> None:
+    """Load a state saved from a handle of the same problem into h."""
+    _check(_lib.altgdmin_set_state(h, ptr(state), state.numel() * state.element_size(), stream_ptr(stream)))
+
+
 def altgdmin_destroy(h) -> None:
     if h:
         _lib.altgdmin_destroy(h)
 
 
+@_on_stream
 def altgdmin_solve(prob: Problem, par: Params, workspace, U=None, Bt=None, S_idx=None, S_val=None,
                    stream=None):
     load()
@@ -286,18 +374,21 @@ def altgdmin_solve(prob: Problem, par: Params, workspace, U=None, Bt=None, S_idx
     return rc, rep.as_dict()
 
 
+@_on_stream
 def altgdmin_op_select(V, rho: int, idx, val, flags=None, stream=None) -> None:
     load()
     count, n = V.shape
     _check(_lib.altgdmin_op_select(ptr(V), n, count, n, rho, ptr(idx), ptr(val), ptr(flags), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_philox_fill(seed: int, normal_table, q: int, n: int, m: int, A, stream=None) -> None:
     """Write the Philox form of A (q, n, lda) FP32 into the device tensor A."""
     load()
     _check(_lib.altgdmin_op_philox_fill(int(seed), ptr(normal_table), q, n, m, A.shape[2], ptr(A), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_make_a(seed: int, normal_table, q: int, n: int, m: int, A, A_lo=None, stream=None) -> None:
     """Write the canonical synthetic A: FP32 (q, n, lda) into A, or, with A_lo given,
     the BF16 hi plane into A and the lo plane into A_lo (int16/uint16 (q, n, lda))."""
@@ -307,17 +398,20 @@ def altgdmin_op_make_a(seed: int, normal_table, q: int, n: int, m: int, A, A_lo=
                                    stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_measure(prob: Problem, Xt, Y, stream=None) -> None:
     """Y[k, :m] = A_k x_k with FP64 accumulation; Xt (q, n) float64 on the device."""
     load()
     _check(_lib.altgdmin_op_measure(ctypes.byref(prob), ptr(Xt), ptr(Y), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_au(prob: Problem, U, P, Ginv, flags=None, stream=None) -> None:
     load()
     _check(_lib.altgdmin_op_au(ctypes.byref(prob), ptr(U), ptr(P), ptr(Ginv), ptr(flags), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_iht(prob: Problem, project: bool, P, Ginv, tau: int, has_support: bool, S_idx, S_val,
                     G_out=None, mu_out=None, flags=None, stream=None) -> None:
     load()
@@ -325,12 +419,14 @@ def altgdmin_op_iht(prob: Problem, project: bool, P, Ginv, tau: int, has_support
                                 ptr(S_idx), ptr(S_val), ptr(G_out), ptr(mu_out), ptr(flags), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_lsgrad(prob: Problem, P, Ginv, S_idx, S_val, Bt, H, rr=None, flags=None, stream=None) -> None:
     load()
     _check(_lib.altgdmin_op_lsgrad(ctypes.byref(prob), ptr(P), ptr(Ginv), ptr(S_idx), ptr(S_val), ptr(Bt),
                                    ptr(H), ptr(rr), ptr(flags), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_backproject(prob: Problem, S_idx, S_val, L0t, stream=None) -> None:
     load()
     _check(_lib.altgdmin_op_backproject(ctypes.byref(prob), ptr(S_idx), ptr(S_val), ptr(L0t), stream_ptr(stream)))
@@ -348,6 +444,7 @@ def _scratch(n, q, r):
     return torch.empty(altgdmin_op_scratch_bytes(n, q, r) + 256, dtype=torch.uint8, device="cuda")
 
 
+@_on_stream
 def altgdmin_op_grad(H, Bt, grad, scratch=None, stream=None) -> None:
     load()
     q, n = H.shape
@@ -357,6 +454,7 @@ def altgdmin_op_grad(H, Bt, grad, scratch=None, stream=None) -> None:
                                  stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_qr_step(U, grad, eta_c: float, eta_io, U_out, scratch=None, stream=None) -> None:
     load()
     n, r = U.shape
@@ -365,6 +463,7 @@ def altgdmin_op_qr_step(U, grad, eta_c: float, eta_io, U_out, scratch=None, stre
                                     scratch.numel(), stream_ptr(stream)))
 
 
+@_on_stream
 def altgdmin_op_subspace(L0t, r: int, U_start, iters: int, tol: float, U_out, iters_out=None, scratch=None,
                          stream=None) -> None:
     load()
@@ -372,6 +471,27 @@ def altgdmin_op_subspace(L0t, r: int, U_start, iters: int, tol: float, U_out, it
     scratch = _scratch(n, q, r) if scratch is None else scratch
     _check(_lib.altgdmin_op_subspace(ptr(L0t), n, q, r, ptr(U_start), iters, tol, ptr(U_out), ptr(iters_out),
                                      ptr(scratch), scratch.numel(), stream_ptr(stream)))
+
+
+def altgdmin_op_rank_scratch_bytes(n: int, q: int, m: int) -> int:
+    load()
+    b = c_sz(0)
+    _check(_lib.altgdmin_op_rank_scratch_bytes(n, q, m, ctypes.byref(b)))
+    return b.value
+
+
+@_on_stream
+def altgdmin_op_rank(L0t, m: int, energy: float, iters: int, r_out, sv_out=None, scratch=None,
+                     stream=None) -> None:
+    """Automatic rank of Sec. 2.6 on L_0 (given as L0t, q x n): r into r_out (device int32),
+    the K leading singular-value estimates into sv_out (device float64, optional)."""
+    load()
+    torch = _torch()
+    q, n = L0t.shape
+    if scratch is None:
+        scratch = torch.empty(altgdmin_op_rank_scratch_bytes(n, q, m) + 256, dtype=torch.uint8, device="cuda")
+    _check(_lib.altgdmin_op_rank(ptr(L0t), n, q, m, energy, iters, ptr(r_out), ptr(sv_out), ptr(scratch),
+                                 scratch.numel(), stream_ptr(stream)))
 
 
 # ------------------------------------------------------------------ convenience owner
@@ -412,11 +532,13 @@ class Solver:
     def init(self, stream=None):
         if self.h is not None:
             altgdmin_destroy(self.h)
-        self.h = altgdmin_init(self.prob, self.par, self.ws, stream)
+        self.h = altgdmin_init(self.prob, self.par, self.ws, stream=stream)
+        if self.prob.r == 0:    # automatic rank: the one the initialisation chose
+            self.r = altgdmin_status(self.h, stream=stream)["rank"]
         return self
 
     def step(self, iters: int, stream=None):
-        altgdmin_step(self.h, iters, stream)
+        altgdmin_step(self.h, iters, stream=stream)
         return self
 
     def get(self, stream=None):
@@ -426,13 +548,13 @@ class Solver:
         Bt = torch.empty((self.q, self.r), dtype=torch.float32, device="cuda")
         Si = torch.zeros((self.q, max(self.rho, 1)), dtype=torch.int32, device="cuda")
         Sv = torch.zeros((self.q, max(self.rho, 1)), dtype=torch.float32, device="cuda")
-        altgdmin_get(self.h, U, Bt, Si if self.rho else None, Sv if self.rho else None, Un, stream)
+        altgdmin_get(self.h, U, Bt, Si if self.rho else None, Sv if self.rho else None, Un, stream=stream)
         torch.cuda.synchronize()
         return dict(U=U.cpu().numpy(), U_next=Un.cpu().numpy(), Bt=Bt.cpu().numpy(),
                     S_idx=Si.cpu().numpy()[:, : self.rho], S_val=Sv.cpu().numpy()[:, : self.rho])
 
     def status(self, stream=None) -> dict:
-        return altgdmin_status(self.h, stream)
+        return altgdmin_status(self.h, stream=stream)
 
     def profile_iteration(self, iters: int) -> dict:
         return altgdmin_profile_iteration(self.h, iters)
@@ -473,11 +595,11 @@ class FourierSolver:
     def init(self, stream=None):
         if self.h is not None:
             altgdmin_destroy(self.h)
-        self.h = altgdmin_init(self.prob, self.par, self.ws, stream)
+        self.h = altgdmin_init(self.prob, self.par, self.ws, stream=stream)
         return self
 
     def step(self, iters: int, stream=None):
-        altgdmin_step(self.h, iters, stream)
+        altgdmin_step(self.h, iters, stream=stream)
         return self
 
     def get(self, stream=None):
@@ -487,13 +609,13 @@ class FourierSolver:
         Bt = torch.empty((self.q, self.r), dtype=torch.complex64, device="cuda")
         Si = torch.zeros((self.q, max(self.rho, 1)), dtype=torch.int32, device="cuda")
         Sv = torch.zeros((self.q, max(self.rho, 1)), dtype=torch.complex64, device="cuda")
-        altgdmin_get(self.h, U, Bt, Si if self.rho else None, Sv if self.rho else None, Un, stream)
+        altgdmin_get(self.h, U, Bt, Si if self.rho else None, Sv if self.rho else None, Un, stream=stream)
         torch.cuda.synchronize()
         return dict(U=U.cpu().numpy(), U_next=Un.cpu().numpy(), Bt=Bt.cpu().numpy(),
                     S_idx=Si.cpu().numpy()[:, : self.rho], S_val=Sv.cpu().numpy()[:, : self.rho])
 
     def status(self, stream=None) -> dict:
-        return altgdmin_status(self.h, stream)
+        return altgdmin_status(self.h, stream=stream)
 
     def profile_iteration(self, iters: int) -> dict:
         return altgdmin_profile_iteration(self.h, iters)

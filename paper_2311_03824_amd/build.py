@@ -27,6 +27,7 @@ SOURCES = [
     ("k_small.hip", [], "k_small.o"),
     ("k_gen.hip", [], "k_gen.o"),
     ("k_fourier.hip", [], "k_fourier.o"),
+    ("k_rank.hip", [], "k_rank.o"),
     ("api.hip", [], "api.o"),
 ]
 

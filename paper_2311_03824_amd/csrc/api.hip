@@ -33,6 +33,26 @@ int fail(int code, const std::string& msg) {
     if (e_ != hipSuccess) return fail(ALTGDMIN_EHIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
   } while (0)
 
+// Every entry point that enqueues work takes the caller's stream; the library
+// never enqueues on the null (legacy default) stream.
+#define NEED_STREAM(s)                                                                     \
+  do {                                                                                     \
+    if (!(s)) return fail(ALTGDMIN_EINVAL, "stream is NULL: pass a created HIP stream"); \
+  } while (0)
+
+// Events that are destroyed on every exit path.
+struct EventPair {
+  hipEvent_t e[2] = {nullptr, nullptr};
+  hipError_t create() {
+    hipError_t r = hipEventCreate(&e[0]);
+    return r == hipSuccess ? hipEventCreate(&e[1]) : r;
+  }
+  ~EventPair() {
+    for (hipEvent_t x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
 
@@ -52,6 +72,80 @@ struct Carver {
 // column splits of the gradient reduction: enough workgroups to fill the
 // chip for small n, one split when every split would hold few columns
 int grad_splits(int q) { return q >= 512 ? 4 : (q >= 64 ? 2 : 1); }
+
+// Automatic rank (Sec. 2.6): K = max(1, floor(min(n, q, m) / 10)) leading singular
+// values of L_0 decide r; the block subspace iteration carries b = K + 8 columns
+// (capped by the LDS of its b x b FP64 matrices and by min(n, q)).
+int rank_budget(int n, int q, int m) { return std::max(1, std::min(n, std::min(q, m)) / 10); }
+int rank_block(int n, int q, int m) {
+  return std::min(rank_budget(n, q, m) + 8, std::min(kRankBlockMax, std::min(n, q)));
+}
+// the rank the workspace is laid out for: r, or with r = 0 the largest the automatic rule may pick
+int r_eff(const altgdmin_problem& p) {
+  if (p.r > 0) return p.r;
+  return std::min(std::min(rank_budget(p.n, p.q, p.m), kRMax), std::min(p.m, p.n));
+}
+
+// Scratch of the automatic rank: the block U and Z = L_0 L_0^T U (n x b), T = L_0^T U
+// (q x b), the FP64 Gram and R^{-1} (b x b), R^{-1} in FP32, the K values, r, a flag.
+struct RankScratch {
+  float* Ub;
+  float* Z;
+  float* T;
+  double* W;
+  double* Xinv;
+  float* Xf;
+  double* sv;
+  int* r;
+  int* flag;
+  size_t bytes;
+};
+
+RankScratch rank_scratch(void* base, int n, int q, int m) {
+  const size_t b = rank_block(n, q, m), K = rank_budget(n, q, m);
+  RankScratch s;
+  Carver c(base);
+  s.Ub = c.take<float>((size_t)n * b);
+  s.Z = c.take<float>((size_t)n * b);
+  s.T = c.take<float>((size_t)q * b);
+  s.W = c.take<double>(b * b);
+  s.Xinv = c.take<double>(b * b);
+  s.Xf = c.take<float>(b * b);
+  s.sv = c.take<double>(K);
+  s.r = c.take<int>(1);
+  s.flag = c.take<int>(1);
+  s.bytes = (c.off + kAlign - 1) / kAlign * kAlign;
+  return s;
+}
+
+// Enqueues the automatic rank on L_0 (given as L0t, q x n): `iters` steps of the
+// block subspace iteration from a fixed orthonormal start, each Z = L_0 (L_0^T U)
+// and CholeskyQR2, then the Rayleigh-Ritz values and the rank (device outputs r,
+// sv).  Returns the buffer that holds the final orthonormal block (n x b).
+hipError_t enqueue_rank(const float* L0t, int n, int q, int m, double energy, int iters, RankScratch& s,
+                        float** block, hipStream_t st) {
+  const int b = rank_block(n, q, m), K = rank_budget(n, q, m);
+  float* U = s.Ub;
+  float* Z = s.Z;
+  hipError_t e = launch_fill_int(s.flag, 0, 1, st);
+  if (e == hipSuccess) e = launch_fill_basis(U, n, b, st);
+  for (int it = 0; it < iters && e == hipSuccess; ++it) {
+    e = launch_rank_mm(false, L0t, n, U, b, s.T, b, q, b, n, st);                 // T = L_0^T U
+    if (e == hipSuccess) e = launch_rank_mm(true, L0t, n, s.T, b, Z, b, n, b, q, st);   // Z = L_0 T
+    for (int pass = 0; pass < 2 && e == hipSuccess; ++pass) {                     // CholeskyQR2: Z -> U -> Z
+      e = launch_rank_gram(Z, n, b, s.W, st);
+      if (e == hipSuccess) e = launch_rank_chol(s.W, b, s.Xinv, s.Xf, s.flag, st);
+      if (e == hipSuccess) e = launch_rank_mm(false, Z, b, s.Xf, b, U, b, n, b, b, st);
+      std::swap(U, Z);
+    }
+    std::swap(U, Z);   // after two passes the orthonormal block is in Z: name it U again
+  }
+  if (e == hipSuccess) e = launch_rank_mm(false, L0t, n, U, b, s.T, b, q, b, n, st);   // T = L_0^T U
+  if (e == hipSuccess) e = launch_rank_gram(s.T, q, b, s.W, st);                       // M = T^T T
+  if (e == hipSuccess) e = launch_rank_jacobi(s.W, b, K, energy, s.sv, s.r, st);
+  *block = U;
+  return e;
+}
 
 int fmt_of(const altgdmin_problem* p) {
   switch (p->a_format) {
@@ -91,10 +185,12 @@ struct altgdmin_handle {
   float* tw = nullptr;     // 96 twiddles
   double* fpart = nullptr; // per-256-row-block partial Grams of the GD update
   double* frinv = nullptr; // R1^{-1}, R2^{-1} of the GD update
+  void* rank_ws = nullptr; // r = 0 (automatic rank): scratch of the rank estimate
   int col_unroll = 0;      // autotuned JU of the column kernel (0: the default instantiation)
   int au_depth = 0;        // autotuned AUD of the A_k U kernel (0: the default instantiation)
   int colfmt = 0;          // format of the column kernel: fmt, or the mixed BF16 form
   bool hi_phase = false;   // BF16X2 with a hi-only phase
+  bool auto_rank = false;  // the problem asked for r = 0: r is chosen at init (Sec. 2.6)
   bool have_graph = false;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -124,7 +220,7 @@ size_t carve_fourier(altgdmin_handle* h, void* base) {
   h->Uprev = c.take<float>(2 * n * r);
   h->Utmp = c.take<float>(2 * n * r);
   h->Tpow = c.take<float>(2 * q * r);
-  h->tw = c.take<float>(2 * kFN);
+  h->tw = c.take<float>(2 * (size_t)std::max(kFN, p.n1 + p.n2));
   h->fpart = c.take<double>(2 * 3 * r * r * ((n + 255) / 256));
   h->frinv = c.take<double>(2 * 2 * r * r);
   h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
@@ -136,7 +232,7 @@ size_t carve_fourier(altgdmin_handle* h, void* base) {
 size_t carve(altgdmin_handle* h, void* base) {
   if (h->prob.a_format == ALTGDMIN_A_PFOURIER) return carve_fourier(h, base);
   const altgdmin_problem& p = h->prob;
-  const size_t n = p.n, q = p.q, m = p.m, r = p.r, rho = p.rho;
+  const size_t n = p.n, q = p.q, m = p.m, r = r_eff(p), rho = p.rho;
   Carver c(base);
   h->ctl = c.take<Ctl>(1);
   h->P = c.take<float>(q * m * r);
@@ -155,13 +251,21 @@ size_t carve(altgdmin_handle* h, void* base) {
   h->Tpow = c.take<float>(q * r);
   h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
   h->rlog = c.take<double>(h->rlog_len);
+  if (p.r == 0) h->rank_ws = c.take<unsigned char>(rank_scratch(nullptr, p.n, p.q, p.m).bytes);
   return (c.off + kAlign - 1) / kAlign * kAlign;
 }
 
 int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (!p || !par) return fail(ALTGDMIN_EINVAL, "null problem or params");
   if (p->n < 1 || p->q < 1 || p->m < 1) return fail(ALTGDMIN_EINVAL, "n, q, m must be >= 1");
-  if (p->r < 1 || p->r > p->m || p->r > p->n) return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n)");
+  if (p->r < 0 || (p->r > 0 && (p->r > p->m || p->r > p->n)))
+    return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n), or r = 0 for the automatic rank");
+  if (p->r == 0 && p->a_format == ALTGDMIN_A_PFOURIER)
+    return fail(ALTGDMIN_ENOTBUILT, "the automatic rank is built for the real A forms");
+  if (p->r == 0 && rank_budget(p->n, p->q, p->m) > kRankBlockMax)
+    return fail(ALTGDMIN_ENOTBUILT, "automatic rank: min(n, q, m) / 10 above the largest block of the estimate");
+  if (p->r == 0 && !(par->rank_energy > 0.0 && par->rank_energy <= 1.0 && par->rank_iters >= 1))
+    return fail(ALTGDMIN_EINVAL, "automatic rank needs 0 < rank_energy <= 1 and rank_iters >= 1");
   if (p->rho < 0 || p->rho > p->n) return fail(ALTGDMIN_EINVAL, "need 0 <= rho <= n");
   if (par->tau0 < 0 || par->tau < 0 || par->t_max < 0 || par->power_iters < 0 || par->poll_every < 1 ||
       !(par->eta_c >= 0.0) || par->bf16_hi_max < 0 ||
@@ -171,17 +275,24 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
     return fail(ALTGDMIN_EINVAL, "the mixed BF16 form needs BF16X2 planes and no hi-only phase");
   if (p->a_format == ALTGDMIN_A_PFOURIER) {
     if (p->n1 < 1 || p->n2 < 1 || (int64_t)p->n1 * p->n2 != p->n) return fail(ALTGDMIN_EINVAL, "need n = n1 * n2");
-    if (p->n1 != kFN || p->n2 != kFN) return fail(ALTGDMIN_ENOTBUILT, "the Fourier kernels are built for 96 x 96 frames");
     if (p->m > p->n) return fail(ALTGDMIN_EINVAL, "need m <= n");
+    if (!(p->n1 == kFN && p->n2 == kFN)) {   // generic frames: direct line DFTs in LDS
+      if (p->n > kFGenPer * kFThreads || p->n1 > kFGenLineMax || p->n2 > kFGenLineMax)
+        return fail(ALTGDMIN_ENOTBUILT, "Fourier form: frames other than 96 x 96 are built for n <= 4096 and "
+                                        "n1, n2 <= 1024");
+    }
     if (p->m > 2 * kFThreads) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: m > 2048 has no instantiation");
     if (p->r > kFRMax) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: r > 8 has no instantiation");
     if (p->rho > kFRhoMax) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: rho > 256 has no instantiation");
+    if (fcol_lds_bytes(p->rho, p->r, p->n, p->m, p->n1, p->n2) > kFLdsMax)
+      return fail(ALTGDMIN_ENOTBUILT, "Fourier form: the frame and the rows of P_k need more LDS than a CU has");
     if (!p->fourier_mask || !p->Y) return fail(ALTGDMIN_EINVAL, "Fourier form needs the mask and Y");
     if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
     if (reinterpret_cast<uintptr_t>(p->Y) % 8 != 0) return fail(ALTGDMIN_EINVAL, "Y must be 8-byte aligned");
     return ALTGDMIN_OK;
   }
   if (p->r > kRMax) return fail(ALTGDMIN_ENOTBUILT, "r > 16 has no instantiation");
+  const int re = r_eff(*p);
   if (p->m > 256 * kNCMax) return fail(ALTGDMIN_ENOTBUILT, "m > 1024 has no instantiation");
   if (p->a_format != ALTGDMIN_A_F32 && p->a_format != ALTGDMIN_A_BF16X2 && p->a_format != ALTGDMIN_A_PHILOX)
     return fail(ALTGDMIN_EINVAL, "unknown a_format");
@@ -200,9 +311,9 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
       return fail(ALTGDMIN_EINVAL, "A planes are not aligned to 4 elements");
   }
   if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
-  if (!au_supported(p->m, p->r)) return fail(ALTGDMIN_ENOTBUILT, "no A_k U instantiation for this (m, r)");
+  if (!au_supported(p->m, re)) return fail(ALTGDMIN_ENOTBUILT, "no A_k U instantiation for this (m, r)");
   const int phx = p->a_format == ALTGDMIN_A_PHILOX;
-  if (col_lds_bytes(p->n, p->m, p->r, p->rho, 1, phx) > kMaxLds || au_lds_bytes(p->m, p->r, phx) > kMaxLds)
+  if (col_lds_bytes(p->n, p->m, re, p->rho, 1, phx) > kMaxLds || au_lds_bytes(p->m, re, phx) > kMaxLds)
     return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 64 KiB of LDS per column workgroup");
   return ALTGDMIN_OK;
 }
@@ -336,9 +447,9 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   // an empty support
   ColArgs ca = col_args(h);
   ca.tau = h->par.tau; ca.project = 1; ca.has_support = 0; ca.tail = TAIL_LSGRAD;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
+  EventPair ev;
+  HIPCHK(ev.create());
+  hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
   auto timed = [&](auto launch, float* ms) -> hipError_t {
     hipError_t e = launch();   // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, st);
@@ -369,8 +480,6 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     if (e != hipSuccess) break;
     if (ms < best_col) { best_col = ms; best_ju = ju; }
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("autotune: ") + hipGetErrorString(e));
   h->col_unroll = best_ju;
   h->au_depth = best_aud;
@@ -392,6 +501,8 @@ FColArgs fcol_args(const altgdmin_handle* h, int mode) {
   a.ldy = p.ldy;
   a.FU = reinterpret_cast<const float2*>(h->FU);
   a.tw = reinterpret_cast<const float2*>(h->tw);
+  a.n1 = p.n1;
+  a.n2 = p.n2;
   a.Sidx = h->Tidx;
   a.Sval = reinterpret_cast<float2*>(h->Tval);
   a.Bt = reinterpret_cast<float2*>(h->Bt);
@@ -429,7 +540,9 @@ FQRArgs fqr_args(const altgdmin_handle* h, int mode) {
 hipError_t fourier_launch(altgdmin_handle* h, int which, hipStream_t st) {
   const altgdmin_problem& p = h->prob;
   switch (which) {
-    case 0: return launch_fu(CF2(h->U), p.r, CF2(h->tw), F2(h->FU), st);
+    case 0:
+      if (p.n1 == kFN && p.n2 == kFN) return launch_fu(CF2(h->U), p.r, CF2(h->tw), F2(h->FU), st);
+      return launch_fu_gen(CF2(h->U), p.n, p.r, p.n1, p.n2, CF2(h->tw), F2(h->FU), st);
     case 1: return launch_fcol(fcol_args(h, FCOL_GD), st);
     case 2:
       return launch_fgrad_gd(CF2(h->H), CF2(h->Bt), CF2(h->U), p.n, p.q, p.r, F2(h->gpart),
@@ -485,6 +598,8 @@ void altgdmin_default_params(altgdmin_params* p) {
   p->tol_resid = 0.0;
   p->bf16_hi_max = 0;
   p->bf16_stall = 0.9;
+  p->rank_energy = 0.65;
+  p->rank_iters = 30;
 }
 
 int altgdmin_workspace_bytes(const altgdmin_problem* prob, const altgdmin_params* par, size_t* bytes) {
@@ -503,6 +618,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   int rc = validate(prob, par);
   if (rc) return rc;
   if (!workspace || !out) return fail(ALTGDMIN_EINVAL, "null workspace or out");
+  NEED_STREAM(stream);
   if (reinterpret_cast<uintptr_t>(workspace) % kAlign != 0) return fail(ALTGDMIN_EINVAL, "workspace must be 256-byte aligned");
   altgdmin_handle* h = new altgdmin_handle();
   h->prob = *prob;
@@ -510,7 +626,10 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->fmt = fmt_of(prob);
   h->hi_phase = (h->fmt == FMT_BF16X2 && par->bf16_hi_max > 0);
   h->colfmt = (par->flags & ALTGDMIN_FLAG_BF16_MIXED) ? FMT_BF16MIX : h->fmt;
-  const size_t need = carve(h, workspace);
+  h->auto_rank = prob->r == 0;
+  const size_t need = carve(h, workspace);   // with r = 0, laid out for the largest rank the rule may pick
+  const int r_cap = r_eff(h->prob);
+  if (h->auto_rank) h->prob.r = r_cap;       // until the rank is chosen (the initialisation IHT does not use r)
   if (ws_bytes < need) {
     delete h;
     return fail(ALTGDMIN_ENOWS, "workspace too small: need " + std::to_string(need) + " bytes");
@@ -521,7 +640,8 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
     delete h;
     return fail(ALTGDMIN_EHIP, std::string(what) + ": " + hipGetErrorString(e));
   };
-  if ((par->flags & ALTGDMIN_FLAG_AUTOTUNE) && !h->hi_phase && (h->fmt == FMT_F32 || h->fmt == FMT_BF16X2)) {
+  if ((par->flags & ALTGDMIN_FLAG_AUTOTUNE) && !h->hi_phase && !h->auto_rank &&
+      (h->fmt == FMT_F32 || h->fmt == FMT_BF16X2)) {
     const int trc = autotune(h, st);
     if (trc) {
       delete h;
@@ -534,7 +654,8 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   if ((e = launch_fill_int(h->colflags, 0, p.q, st)) != hipSuccess) return bail(e, "flags");
   if (h->fmt == FMT_PFOURIER) {
     // s_k = IHT(y_k, A_k, rho, tau0, 0), L_0 = [A_k^H (y_k - A_k s_k)], U_0 by subspace iteration
-    if ((e = launch_ftwiddle(F2(h->tw), st)) != hipSuccess) return bail(e, "twiddles");
+    e = (p.n1 == kFN && p.n2 == kFN) ? launch_ftwiddle(F2(h->tw), st) : launch_ftwiddle_gen(F2(h->tw), p.n1, p.n2, st);
+    if (e != hipSuccess) return bail(e, "twiddles");
     if ((e = launch_fcol(fcol_args(h, FCOL_INIT), st)) != hipSuccess) return bail(e, "init column kernel");
     if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
     if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, 2LL * p.n * p.r, st);
@@ -561,9 +682,31 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   ca.tau = par->tau0; ca.project = 0; ca.has_support = 0; ca.tail = TAIL_BACKPROJ;
   if ((e = col_launch(h, h->hi_phase ? FMT_BF16HI : h->colfmt, ca, st)) != hipSuccess) return bail(e, "init column kernel");
   if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
-  // U_0: top-r left singular subspace of L_0 by subspace iteration
-  if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, (long long)p.n * p.r, st);
-  else e = launch_fill_basis(h->Utmp, p.n, p.r, st);
+  if (h->auto_rank) {
+    // r from the energy of the leading singular values of L_0 (Sec. 2.6); the only
+    // synchronisation of the initialisation.  U_0 starts from the first r columns of
+    // the estimate's block, which span the first r columns' subspace iterate.
+    RankScratch rs = rank_scratch(h->rank_ws, p.n, p.q, p.m);
+    float* block = nullptr;
+    if ((e = enqueue_rank(h->H, p.n, p.q, p.m, par->rank_energy, par->rank_iters, rs, &block, st)) != hipSuccess)
+      return bail(e, "automatic rank");
+    int chosen = 0;
+    if ((e = hipMemcpyAsync(&chosen, rs.r, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+      return bail(e, "automatic rank copy");
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "automatic rank");
+    if (chosen < 1 || chosen > r_cap) {
+      delete h;
+      return fail(ALTGDMIN_ENOTBUILT, "automatic rank chose r = " + std::to_string(chosen) + ", above the " +
+                                          std::to_string(r_cap) + " this problem is built for");
+    }
+    h->prob.r = chosen;
+    e = launch_rank_slice(block, p.n, rank_block(p.n, p.q, p.m), chosen, h->Utmp, st);
+  } else if (p.U_start) {
+    // U_0: top-r left singular subspace of L_0 by subspace iteration
+    e = launch_copy_f(h->Utmp, p.U_start, (long long)p.n * p.r, st);
+  } else {
+    e = launch_fill_basis(h->Utmp, p.n, p.r, st);
+  }
   if (e != hipSuccess) return bail(e, "start block");
   if ((e = launch_qr(qr_args(h, QR_ORTH), st)) != hipSuccess) return bail(e, "orth");
   for (int it = 0; it < par->power_iters; ++it) {
@@ -579,6 +722,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
 
 int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
   if (!h || iters < 0) return fail(ALTGDMIN_EINVAL, "null handle or negative iters");
+  NEED_STREAM(stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   if (h->par.flags & ALTGDMIN_FLAG_EAGER) {   // eager launches (no graph)
     for (int i = 0; i < iters; ++i) {
@@ -596,9 +740,17 @@ int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &g);
     (void)hipStreamDestroy(cs);
-    if (rc) return rc;
-    if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("capture: ") + hipGetErrorString(e));
-    HIPCHK(hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0));
+    if (rc || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      if (rc) return rc;
+      return fail(ALTGDMIN_EHIP, std::string("capture: ") + hipGetErrorString(e));
+    }
+    e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(g);
+      h->exec = nullptr;
+      return fail(ALTGDMIN_EHIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
     h->graph = g;
     h->have_graph = true;
   }
@@ -609,10 +761,12 @@ int altgdmin_step(altgdmin_handle* h, int32_t iters, void* stream) {
 
 int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out) {
   if (!h || iters < 1 || !ms_out) return fail(ALTGDMIN_EINVAL, "bad profile arguments");
+  NEED_STREAM(stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const altgdmin_problem& p = h->prob;
-  hipEvent_t ev[5];
-  for (int i = 0; i < 5; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  EventPair evp[3];
+  for (int i = 0; i < 3; ++i) HIPCHK(evp[i].create());
+  const hipEvent_t ev[5] = {evp[0].e[0], evp[0].e[1], evp[1].e[0], evp[1].e[1], evp[2].e[0]};
   double acc[4] = {0, 0, 0, 0};
   int rc = ALTGDMIN_OK;
   for (int it = 0; it < iters && rc == ALTGDMIN_OK && h->fmt == FMT_PFOURIER; ++it) {
@@ -656,7 +810,6 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     }
     if (e != hipSuccess) rc = fail(ALTGDMIN_EHIP, std::string("profile: ") + hipGetErrorString(e));
   }
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
   if (rc) return rc;
   for (int k = 0; k < 4; ++k) ms_out[k] = acc[k] / iters;
   h->t_host += iters;
@@ -666,6 +819,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
 int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float* S_val, float* U_next,
                  void* stream) {
   if (!h) return fail(ALTGDMIN_EINVAL, "null handle");
+  NEED_STREAM(stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const altgdmin_problem& p = h->prob;
   const size_t nr = (size_t)p.n * p.r;
@@ -680,6 +834,7 @@ int altgdmin_get(altgdmin_handle* h, float* U, float* Bt, int32_t* S_idx, float*
 
 int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep) {
   if (!h || !rep) return fail(ALTGDMIN_EINVAL, "null handle or report");
+  NEED_STREAM(stream);
   hipStream_t st = static_cast<hipStream_t>(stream);
   Ctl c;
   HIPCHK(hipMemcpyAsync(&c, h->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
@@ -692,6 +847,33 @@ int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep) {
   rep->power_sd = c.power_sd;
   rep->converged = (h->par.tol_resid > 0.0 && c.t > 0 && c.resid <= h->par.tol_resid) ? 1 : 0;
   rep->refine_iteration = h->hi_phase ? c.refine_t : -1;
+  rep->rank = h->prob.r;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_status_many(altgdmin_handle* const* hs, int32_t count, void* stream, altgdmin_report* reps) {
+  if (!hs || count < 0 || (count > 0 && !reps)) return fail(ALTGDMIN_EINVAL, "bad status_many arguments");
+  NEED_STREAM(stream);
+  for (int i = 0; i < count; ++i)
+    if (!hs[i]) return fail(ALTGDMIN_EINVAL, "null handle");
+  if (count == 0) return ALTGDMIN_OK;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  std::vector<Ctl> c(count);
+  for (int i = 0; i < count; ++i) HIPCHK(hipMemcpyAsync(&c[i], hs[i]->ctl, sizeof(Ctl), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  for (int i = 0; i < count; ++i) {
+    const altgdmin_handle* h = hs[i];
+    altgdmin_report* rep = &reps[i];
+    rep->iterations = c[i].t;
+    rep->power_iterations = c[i].power_it;
+    rep->error_flags = c[i].err;
+    rep->eta = c[i].eta;
+    rep->resid = c[i].resid;
+    rep->power_sd = c[i].power_sd;
+    rep->converged = (h->par.tol_resid > 0.0 && c[i].t > 0 && c[i].resid <= h->par.tol_resid) ? 1 : 0;
+    rep->refine_iteration = h->hi_phase ? c[i].refine_t : -1;
+    rep->rank = h->prob.r;
+  }
   return ALTGDMIN_OK;
 }
 
@@ -701,7 +883,11 @@ int altgdmin_residual_log(altgdmin_handle* h, void* stream, double* host_log, in
   int rc = altgdmin_status(h, stream, &rep);
   if (rc) return rc;
   const int cnt = rep.iterations < h->rlog_len ? rep.iterations : h->rlog_len;
-  if (cnt > 0) HIPCHK(hipMemcpy(host_log, h->rlog, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost));
+  if (cnt > 0) {
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIPCHK(hipMemcpyAsync(host_log, h->rlog, (size_t)cnt * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
   *count = cnt;
   return ALTGDMIN_OK;
 }
@@ -742,6 +928,122 @@ int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, voi
   if (rep) *rep = r;
   if (r.error_flags) return fail(ALTGDMIN_ENONFINITE, "non-finite value or indefinite Gram matrix during the solve");
   if (par->tol_resid > 0.0 && !conv) return ALTGDMIN_ENOTCONV;
+  return ALTGDMIN_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ checkpoint / resume
+
+namespace {
+
+constexpr long long kStateMagic = 0x3130545347544C41LL;   // "ALTGST01"
+
+// A saved state: header words, the control block, U, U_prev (the U that B and S
+// were fitted with), B^T, the support indices and values, the column flags and
+// the residual log, each block at 256-byte alignment.
+struct StateLayout {
+  size_t hdr, ctl, U, Uprev, Bt, Tidx, Tval, flags, rlog, total;
+};
+
+StateLayout state_layout(const altgdmin_handle* h, int rlog_len) {
+  const altgdmin_problem& p = h->prob;
+  const size_t w = h->fmt == FMT_PFOURIER ? 8 : 4;   // bytes per value (complex64 in the Fourier form)
+  const size_t nr = (size_t)p.n * p.r, qr = (size_t)p.q * p.r, qs = (size_t)p.q * p.rho;
+  StateLayout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    o = (o + kAlign - 1) / kAlign * kAlign;
+    const size_t at = o;
+    o += bytes;
+    return at;
+  };
+  L.hdr = take(kStateWords * sizeof(long long));
+  L.ctl = take(sizeof(Ctl));
+  L.U = take(nr * w);
+  L.Uprev = take(nr * w);
+  L.Bt = take(qr * w);
+  L.Tidx = take(qs * sizeof(int));
+  L.Tval = take(qs * w);
+  L.flags = take((size_t)p.q * sizeof(int));
+  L.rlog = take((size_t)rlog_len * sizeof(double));
+  L.total = (o + kAlign - 1) / kAlign * kAlign;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int altgdmin_state_bytes(altgdmin_handle* h, size_t* bytes) {
+  if (!h || !bytes) return fail(ALTGDMIN_EINVAL, "null handle or bytes");
+  *bytes = state_layout(h, h->rlog_len).total;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_get_state(altgdmin_handle* h, void* state, size_t bytes, void* stream) {
+  if (!h || !state) return fail(ALTGDMIN_EINVAL, "null handle or state");
+  NEED_STREAM(stream);
+  if (reinterpret_cast<uintptr_t>(state) % kAlign != 0) return fail(ALTGDMIN_EINVAL, "state must be 256-byte aligned");
+  const StateLayout L = state_layout(h, h->rlog_len);
+  if (bytes < L.total) return fail(ALTGDMIN_ENOWS, "state buffer too small: need " + std::to_string(L.total));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const altgdmin_problem& p = h->prob;
+  const size_t w = h->fmt == FMT_PFOURIER ? 8 : 4;
+  char* d = static_cast<char*>(state);
+  StateWords hw;
+  std::memset(&hw, 0, sizeof(hw));
+  const long long words[] = {kStateMagic, p.n, p.q, p.m, p.r, p.rho, p.a_format, h->colfmt, h->t_host,
+                             h->rlog_len, (long long)L.total};
+  std::memcpy(hw.v, words, sizeof(words));
+  HIPCHK(launch_put_words(reinterpret_cast<long long*>(d + L.hdr), hw, st));
+  auto cp = [&](size_t off, const void* src, size_t n) {
+    return n ? hipMemcpyAsync(d + off, src, n, hipMemcpyDeviceToDevice, st) : hipSuccess;
+  };
+  const size_t nr = (size_t)p.n * p.r;
+  HIPCHK(cp(L.ctl, h->ctl, sizeof(Ctl)));
+  HIPCHK(cp(L.U, h->U, nr * w));
+  HIPCHK(cp(L.Uprev, h->Uprev, nr * w));
+  HIPCHK(cp(L.Bt, h->Bt, (size_t)p.q * p.r * w));
+  HIPCHK(cp(L.Tidx, h->Tidx, (size_t)p.q * p.rho * sizeof(int)));
+  HIPCHK(cp(L.Tval, h->Tval, (size_t)p.q * p.rho * w));
+  HIPCHK(cp(L.flags, h->colflags, (size_t)p.q * sizeof(int)));
+  HIPCHK(cp(L.rlog, h->rlog, (size_t)h->rlog_len * sizeof(double)));
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_set_state(altgdmin_handle* h, const void* state, size_t bytes, void* stream) {
+  if (!h || !state) return fail(ALTGDMIN_EINVAL, "null handle or state");
+  NEED_STREAM(stream);
+  if (reinterpret_cast<uintptr_t>(state) % kAlign != 0) return fail(ALTGDMIN_EINVAL, "state must be 256-byte aligned");
+  if (bytes < kStateWords * sizeof(long long)) return fail(ALTGDMIN_EINVAL, "state buffer too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const char* d = static_cast<const char*>(state);
+  long long hw[kStateWords];
+  HIPCHK(hipMemcpyAsync(hw, d, sizeof(hw), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  const altgdmin_problem& p = h->prob;
+  if (hw[0] != kStateMagic) return fail(ALTGDMIN_EINVAL, "not a saved solver state");
+  if (hw[1] != p.n || hw[2] != p.q || hw[3] != p.m || hw[4] != p.r || hw[5] != p.rho || hw[6] != p.a_format ||
+      hw[7] != h->colfmt)
+    return fail(ALTGDMIN_EINVAL, "saved state is of another problem size or A form");
+  const int saved_len = (int)hw[9];
+  const StateLayout L = state_layout(h, saved_len);
+  if (hw[10] != (long long)L.total || bytes < L.total) return fail(ALTGDMIN_EINVAL, "saved state has an unexpected size");
+  const size_t w = h->fmt == FMT_PFOURIER ? 8 : 4;
+  auto cp = [&](void* dst, size_t off, size_t n) {
+    return n ? hipMemcpyAsync(dst, d + off, n, hipMemcpyDeviceToDevice, st) : hipSuccess;
+  };
+  const size_t nr = (size_t)p.n * p.r;
+  HIPCHK(cp(h->ctl, L.ctl, sizeof(Ctl)));
+  HIPCHK(cp(h->U, L.U, nr * w));
+  HIPCHK(cp(h->Uprev, L.Uprev, nr * w));
+  HIPCHK(cp(h->Bt, L.Bt, (size_t)p.q * p.r * w));
+  HIPCHK(cp(h->Tidx, L.Tidx, (size_t)p.q * p.rho * sizeof(int)));
+  HIPCHK(cp(h->Tval, L.Tval, (size_t)p.q * p.rho * w));
+  HIPCHK(cp(h->colflags, L.flags, (size_t)p.q * sizeof(int)));
+  HIPCHK(cp(h->rlog, L.rlog, (size_t)std::min(saved_len, h->rlog_len) * sizeof(double)));
+  h->t_host = (int)hw[8];
   return ALTGDMIN_OK;
 }
 
@@ -856,6 +1158,40 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
   return ALTGDMIN_OK;
 }
 
+// Host staging of the launch tables of altgdmin_step_many: a pinned host buffer
+// that the library keeps (grown as needed) and an event marking when the last
+// upload from it finished, so an upload needs no stream synchronisation (only a
+// wait for the previous upload, normally long done, before the buffer is reused).
+struct Staging {
+  std::mutex mu;
+  char* host = nullptr;
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  bool pending = false;
+};
+Staging g_stage;
+
+int upload_tables(const std::vector<char>& buf, void* dev, hipStream_t st) {
+  std::lock_guard<std::mutex> lk(g_stage.mu);
+  if (!g_stage.done) HIPCHK(hipEventCreateWithFlags(&g_stage.done, hipEventDisableTiming));
+  if (g_stage.pending) {   // the previous upload still reads the staging buffer
+    HIPCHK(hipEventSynchronize(g_stage.done));
+    g_stage.pending = false;
+  }
+  if (g_stage.cap < buf.size()) {
+    if (g_stage.host) HIPCHK(hipHostFree(g_stage.host));
+    g_stage.host = nullptr;
+    g_stage.cap = 0;
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&g_stage.host), buf.size(), hipHostMallocDefault));
+    g_stage.cap = buf.size();
+  }
+  std::memcpy(g_stage.host, buf.data(), buf.size());
+  HIPCHK(hipMemcpyAsync(dev, g_stage.host, buf.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(g_stage.done, st));
+  g_stage.pending = true;
+  return ALTGDMIN_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -873,6 +1209,7 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
                        void* stream) {
   if (iters < 0 || !group_ws || reinterpret_cast<uintptr_t>(group_ws) % kAlign != 0)
     return fail(ALTGDMIN_EINVAL, "bad step_many arguments");
+  NEED_STREAM(stream);
   GroupPlan g;
   int rc = plan_group(hs, count, g);
   if (rc) return rc;
@@ -892,8 +1229,8 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
   put(g.o_gm, g.grad_map.data(), g.grad_map.size() * sizeof(int4));
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* dev = static_cast<char*>(group_ws);
-  HIPCHK(hipMemcpyAsync(dev, buf.data(), g.total, hipMemcpyHostToDevice, st));
-  HIPCHK(hipStreamSynchronize(st));   // the host staging buffer is released on return
+  rc = upload_tables(buf, dev, st);
+  if (rc) return rc;
   const AUArgs* au_tab = reinterpret_cast<const AUArgs*>(dev + g.o_au);
   const ColArgs* col_tab = reinterpret_cast<const ColArgs*>(dev + g.o_col);
   const GradArgs* grad_tab = reinterpret_cast<const GradArgs*>(dev + g.o_grad);
@@ -927,6 +1264,7 @@ int altgdmin_op_select(const float* V, int32_t n, int32_t count, int64_t ldv, in
   if (!V || n < 1 || count < 0 || ldv < n || rho < 0 || rho > n) return fail(ALTGDMIN_EINVAL, "bad select arguments");
   if (rho > 0 && (!idx || !val)) return fail(ALTGDMIN_EINVAL, "null idx/val");
   if (select_lds_bytes(n, rho) > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "n too large for the select kernel");
+  NEED_STREAM(stream);
   if (count == 0) return ALTGDMIN_OK;
   HIPCHK(launch_select(V, n, count, ldv, rho, idx, val, flags, static_cast<hipStream_t>(stream)));
   return ALTGDMIN_OK;
@@ -939,6 +1277,7 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
   int rc = validate(prob, &par);
   if (rc) return rc;
   if (!U || !P || !Lc) return fail(ALTGDMIN_EINVAL, "null U/P/Ginv");
+  NEED_STREAM(stream);
   AUArgs au;
   au.n = prob->n; au.q = prob->q; au.m = prob->m; au.r = prob->r;
   au.A = prob->A; au.Alo = prob->A_lo; au.lda = prob->lda; au.sA = prob->a_stride_k;
@@ -950,6 +1289,7 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
 }
 
 static int op_col(const altgdmin_problem* prob, ColArgs& a, void* stream) {
+  NEED_STREAM(stream);
   a.n = prob->n; a.q = prob->q; a.m = prob->m; a.r = prob->r; a.rho = prob->rho;
   a.seed = prob->a_seed; a.table = prob->normal_table;
   a.A = prob->A; a.Alo = prob->A_lo; a.lda = prob->lda; a.sA = prob->a_stride_k;
@@ -1007,6 +1347,7 @@ int altgdmin_op_backproject(const altgdmin_problem* prob, const int32_t* S_idx, 
 int altgdmin_op_philox_fill(uint64_t seed, const float* normal_table, int32_t q, int32_t n, int32_t m, int64_t lda,
                             float* A, void* stream) {
   if (!normal_table || !A || q < 1 || n < 1 || m < 1 || lda < m) return fail(ALTGDMIN_EINVAL, "bad philox fill arguments");
+  NEED_STREAM(stream);
   HIPCHK(launch_philox_fill(seed, normal_table, q, n, m, lda, A, static_cast<hipStream_t>(stream)));
   return ALTGDMIN_OK;
 }
@@ -1015,6 +1356,7 @@ int altgdmin_op_make_a(uint64_t seed, const float* normal_table, int32_t q, int3
                        int32_t a_format, void* A, void* A_lo, void* stream) {
   if (!normal_table || !A || q < 1 || n < 1 || m < 1 || lda < m || lda % 4 != 0)
     return fail(ALTGDMIN_EINVAL, "bad make_a arguments");
+  NEED_STREAM(stream);
   if (a_format == ALTGDMIN_A_F32) {
     if (reinterpret_cast<uintptr_t>(A) % 16 != 0) return fail(ALTGDMIN_EINVAL, "A not 16-byte aligned");
     HIPCHK(launch_make_a(seed, normal_table, q, n, m, lda, FMT_F32, static_cast<float*>(A), nullptr, nullptr,
@@ -1032,6 +1374,7 @@ int altgdmin_op_make_a(uint64_t seed, const float* normal_table, int32_t q, int3
 
 int altgdmin_op_measure(const altgdmin_problem* prob, const double* Xt, float* Y, void* stream) {
   if (!prob || !Xt || !Y) return fail(ALTGDMIN_EINVAL, "bad measure arguments");
+  NEED_STREAM(stream);
   const altgdmin_problem& p = *prob;
   if (p.n < 1 || p.q < 1 || p.m < 1 || p.ldy < p.m) return fail(ALTGDMIN_EINVAL, "bad measure sizes");
   MeasureArgs a;
@@ -1084,6 +1427,7 @@ int altgdmin_op_scratch_bytes(int32_t n, int32_t q, int32_t r, size_t* bytes) {
 int altgdmin_op_grad(const float* H, const float* Bt, int32_t n, int32_t q, int32_t r, float* grad, void* scratch,
                      size_t scratch_bytes, void* stream) {
   if (!H || !Bt || !grad || !scratch || n < 1 || q < 1 || r < 1 || r > kRMax) return fail(ALTGDMIN_EINVAL, "bad grad arguments");
+  NEED_STREAM(stream);
   OpScratch s = op_scratch(scratch, n, q, r);
   if (scratch_bytes < s.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1096,6 +1440,7 @@ int altgdmin_op_qr_step(const float* U, const float* grad, int32_t n, int32_t r,
                         float* U_out, void* scratch, size_t scratch_bytes, void* stream) {
   if (!U || !grad || !eta_io || !U_out || !scratch || n < 1 || r < 1 || r > kRMax || r > n)
     return fail(ALTGDMIN_EINVAL, "bad qr arguments");
+  NEED_STREAM(stream);
   OpScratch s = op_scratch(scratch, n, 1, r);
   if (scratch_bytes < s.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1108,11 +1453,13 @@ int altgdmin_op_qr_step(const float* U, const float* grad, int32_t n, int32_t r,
   return ALTGDMIN_OK;
 }
 
-int altgdmin_op_subspace(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start, int32_t iters,
+// The subspace iteration of altgdmin_op_subspace on a given scratch block (the
+// caller's buffer, or the library's static one).  Every scratch word it reads is
+// written first in the same call: the control block is reset by a kernel, the
+// start block is filled, the partial sums and L_0^T U are overwritten.
+static int subspace_body(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start, int32_t iters,
                          double tol, float* U_out, int32_t* iters_out, void* scratch, size_t scratch_bytes,
                          void* stream) {
-  if (!L0t || !U_out || !scratch || n < 1 || q < 1 || r < 1 || r > kRMax || r > n || iters < 0)
-    return fail(ALTGDMIN_EINVAL, "bad subspace arguments");
   OpScratch s = op_scratch(scratch, n, q, r);
   if (scratch_bytes < s.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1135,4 +1482,51 @@ int altgdmin_op_subspace(const float* L0t, int32_t n, int32_t q, int32_t r, cons
   return ALTGDMIN_OK;
 }
 
+static int subspace_args_ok(const float* L0t, int32_t n, int32_t q, int32_t r, int32_t iters, const float* U_out) {
+  if (!L0t || !U_out || n < 1 || q < 1 || r < 1 || r > kRMax || r > n || iters < 0)
+    return fail(ALTGDMIN_EINVAL, "bad subspace arguments");
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_subspace(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start, int32_t iters,
+                         double tol, float* U_out, int32_t* iters_out, void* scratch, size_t scratch_bytes,
+                         void* stream) {
+  int rc = subspace_args_ok(L0t, n, q, r, iters, U_out);
+  if (rc) return rc;
+  if (!scratch) return fail(ALTGDMIN_EINVAL, "null scratch");
+  NEED_STREAM(stream);
+  return subspace_body(L0t, n, q, r, U_start, iters, tol, U_out, iters_out, scratch, scratch_bytes, stream);
+}
+
 }  // extern "C"
+
+extern "C" {
+
+int altgdmin_op_rank_scratch_bytes(int32_t n, int32_t q, int32_t m, size_t* bytes) {
+  if (n < 1 || q < 1 || m < 1 || !bytes) return fail(ALTGDMIN_EINVAL, "bad sizes");
+  if (rank_budget(n, q, m) > kRankBlockMax)
+    return fail(ALTGDMIN_ENOTBUILT, "min(n, q, m) / 10 above the largest block of the estimate");
+  *bytes = rank_scratch(nullptr, n, q, m).bytes;
+  return ALTGDMIN_OK;
+}
+
+int altgdmin_op_rank(const float* L0t, int32_t n, int32_t q, int32_t m, double energy, int32_t iters,
+                     int32_t* r_out, double* sv_out, void* scratch, size_t scratch_bytes, void* stream) {
+  if (!L0t || !r_out || !scratch || n < 1 || q < 1 || m < 1 || iters < 1 || !(energy > 0.0 && energy <= 1.0))
+    return fail(ALTGDMIN_EINVAL, "bad rank arguments");
+  if (rank_budget(n, q, m) > kRankBlockMax)
+    return fail(ALTGDMIN_ENOTBUILT, "min(n, q, m) / 10 above the largest block of the estimate");
+  NEED_STREAM(stream);
+  RankScratch rs = rank_scratch(scratch, n, q, m);
+  if (scratch_bytes < rs.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  float* block = nullptr;
+  HIPCHK(enqueue_rank(L0t, n, q, m, energy, iters, rs, &block, st));
+  HIPCHK(hipMemcpyAsync(r_out, rs.r, sizeof(int), hipMemcpyDeviceToDevice, st));
+  if (sv_out)
+    HIPCHK(hipMemcpyAsync(sv_out, rs.sv, (size_t)rank_budget(n, q, m) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  return ALTGDMIN_OK;
+}
+
+}  // extern "C"
+

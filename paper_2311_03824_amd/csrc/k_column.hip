@@ -489,31 +489,42 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     for (int t = tid; t < r * r; t += kThreads) Gi[t] = Gk[t];
   }
   __syncthreads();
-  int nz = 0;
+  // A start support must hold rho distinct in-range indices in ascending order
+  // (every support this library writes does).  Any other start is invalid caller
+  // state: the column is flagged (bit 2) and starts from s = 0 with no support.
+  int nz = 0, bad = 0;
   if (a.has_support) {
     for (int t = tid; t < rho; t += kThreads) {
-      int j = a.Tidx[(long long)k * rho + t];
-      float v = a.Tval[(long long)k * rho + t];
-      if (j < 0 || j >= n) {   // invalid caller state: flag it and keep every access in bounds
-        if (a.flags) atomicOr(&a.flags[k], 4);
-        j = 0;
-        v = 0.f;
-      }
+      const int j = a.Tidx[(long long)k * rho + t];
+      const int jp = t > 0 ? a.Tidx[(long long)k * rho + t - 1] : -1;
+      const float v = a.Tval[(long long)k * rho + t];
+      bad |= (j < 0 || j >= n || j <= jp) ? 1 : 0;
       Ti[t] = j;
       Tv[t] = v;
-      sd[j] = v;
-      atomicOr(&inT[j >> 5], 1u << (j & 31));
       nz |= v != 0.f;
+    }
+  }
+  // one reduction tells both whether some start value is nonzero and whether the
+  // start is invalid (weights 1 and 64 per wave, at most kWaves waves)
+  const double vote = xwave_sum_scalar((__ballot(nz != 0) != 0ull ? 1.0 : 0.0) + (__ballot(bad != 0) != 0ull ? 64.0 : 0.0),
+                                       redd, lane, wave);
+  const bool invalid = vote >= 64.0;
+  if (a.has_support && !invalid) {
+    for (int t = tid; t < rho; t += kThreads) {   // each thread reads back only its own entries
+      const int j = Ti[t];
+      sd[j] = Tv[t];
+      atomicOr(&inT[j >> 5], 1u << (j & 31));
     }
   } else {
     for (int t = tid; t < rho; t += kThreads) {   // s = 0 on the support 0 .. rho - 1 (kept if tau = 0)
       Ti[t] = t;
       Tv[t] = 0.f;
     }
+    if (invalid && tid == 0 && a.flags) atomicOr(&a.flags[k], 4);
   }
   // a start whose values are all zero (an initialisation with tau0 = 0) is s = 0
   // with no support yet: T then comes from HardThreshold(g), as for no start
-  bool hasT = xwave_sum_scalar(__ballot(nz != 0) != 0ull ? 1.0 : 0.0, redd, lane, wave) > 0.0;
+  bool hasT = !invalid && vote > 0.0;
   int nan_seen = 0;
 
   for (int it = 0; it < a.tau; ++it) {

@@ -27,6 +27,15 @@
 // decimation-in-frequency transform across the lanes (ds_swizzle exchanges), so
 // lane l ends with outputs 3 bitrev5(l) + k2.  Rows first, then columns; the
 // unitary scale 1/96 is applied in the column pass.
+//
+// Other frame sizes (n1 x n2 with n = n1 n2 <= 4096 and lines of at most 1024
+// points; e.g. the 20 x 20 frames or the 1 x 400 rows of a 1D DFT) take the
+// generic instantiation (GEN) of the column kernel: frames are stored unpadded
+// and each 2D DFT is a row pass and a column pass of direct line DFTs, every
+// output a sum over its line in index order with twiddles W_N^((u j) mod N) from
+// a table in LDS (n1 + n2 entries); up to four outputs per thread are held in
+// registers across a barrier, so the passes run in place.  k_fu_gen is the same
+// transform of the columns of U.
 #include "common.h"
 #include "launch.h"
 
@@ -118,8 +127,70 @@ __device__ __attribute__((noinline)) void fft2_grid(float2* grid, const float2* 
   __syncthreads();
 }
 
-__device__ __forceinline__ void zero_grid(float2* grid) {
-  for (int t = threadIdx.x; t < kFGrid; t += kFThreads) grid[t] = make_float2(0.f, 0.f);
+__device__ __forceinline__ void zero_grid(float2* grid, int count = kFGrid) {
+  for (int t = threadIdx.x; t < count; t += kFThreads) grid[t] = make_float2(0.f, 0.f);
+}
+
+// Unitary 2D DFT (INV: inverse) of an unpadded n1 x n2 frame in `grid`, in place,
+// by direct line sums: first X[j1][u2] = sum_j2 x[j1][j2] W_n2^(u2 j2), then
+// X[u1][u2] = scale sum_j1 X[j1][u2] W_n1^(u1 j1), each sum in index order.  tw
+// holds W_n1^t (t < n1) then W_n2^t (t < n2).  All threads of the workgroup call
+// it (blockDim.x = kFThreads, n1 n2 <= kFGenPer kFThreads); it ends with a barrier.
+template <bool INV>
+__device__ __attribute__((noinline)) void dft2_gen(float2* grid, const float2* tw, int n1, int n2, float scale) {
+  const int n = n1 * n2;
+  const float2* tw1 = tw;
+  const float2* tw2 = tw + n1;
+  float2 acc[kFGenPer];
+#pragma unroll
+  for (int e = 0; e < kFGenPer; ++e) {
+    const int t = threadIdx.x + e * kFThreads;
+    float2 sum = make_float2(0.f, 0.f);
+    if (t < n) {
+      const int j1 = t / n2, u2 = t - j1 * n2;
+      const float2* row = grid + j1 * n2;
+      int w = 0;   // (u2 j2) mod n2
+      for (int j2 = 0; j2 < n2; ++j2) {
+        const float2 x = row[j2], tt = twid<INV>(tw2, w);
+        sum.x = fmaf(x.x, tt.x, fmaf(-x.y, tt.y, sum.x));
+        sum.y = fmaf(x.x, tt.y, fmaf(x.y, tt.x, sum.y));
+        w += u2;
+        if (w >= n2) w -= n2;
+      }
+    }
+    acc[e] = sum;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kFGenPer; ++e) {
+    const int t = threadIdx.x + e * kFThreads;
+    if (t < n) grid[t] = acc[e];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kFGenPer; ++e) {
+    const int t = threadIdx.x + e * kFThreads;
+    float2 sum = make_float2(0.f, 0.f);
+    if (t < n) {
+      const int u1 = t / n2, u2 = t - u1 * n2;
+      int w = 0;   // (u1 j1) mod n1
+      for (int j1 = 0; j1 < n1; ++j1) {
+        const float2 x = grid[j1 * n2 + u2], tt = twid<INV>(tw1, w);
+        sum.x = fmaf(x.x, tt.x, fmaf(-x.y, tt.y, sum.x));
+        sum.y = fmaf(x.x, tt.y, fmaf(x.y, tt.x, sum.y));
+        w += u1;
+        if (w >= n1) w -= n1;
+      }
+    }
+    acc[e] = c_scale(sum, scale);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int e = 0; e < kFGenPer; ++e) {
+    const int t = threadIdx.x + e * kFThreads;
+    if (t < n) grid[t] = acc[e];
+  }
+  __syncthreads();
 }
 
 // Sum over the workgroup of NV doubles per thread, in a fixed order (DPP inside
@@ -363,11 +434,12 @@ __device__ bool fblock_chol_inverse(const double2* G, double2* L, double2* Ginv,
 // LDS layout of the column kernel (bytes)
 struct FColLayout {
   size_t gridA, gridB, tw, red, gi, dsum, gx, sidx, sval, gT, hist, tmp, total;
-  __host__ __device__ FColLayout(int rho, int r) {
+  // grid: complex elements of each of the two frame grids; ntw: twiddles
+  __host__ __device__ FColLayout(int rho, int r, int grid = kFGrid, int ntw = kFN) {
     size_t o = 0;
-    gridA = o; o = align16(o + 8 * (size_t)kFGrid);
-    gridB = o; o = align16(o + 8 * (size_t)kFGrid);
-    tw = o;    o = align16(o + 8 * (size_t)kFN);
+    gridA = o; o = align16(o + 8 * (size_t)grid);
+    gridB = o; o = align16(o + 8 * (size_t)grid);
+    tw = o;    o = align16(o + 8 * (size_t)ntw);
     red = o;   o = align16(o + 8 * (size_t)kFWaves * (2 * kFRMax + 2));
     gi = o;    o = align16(o + 16 * (size_t)r * r);
     dsum = o;  o = align16(o + 8 * (size_t)(2 * kFRMax + 2));
@@ -381,15 +453,40 @@ struct FColLayout {
   }
 };
 
-size_t fcol_lds_bytes(int rho, int r) { return FColLayout(rho, r).total; }
+// Grid elements of a generic frame: the frame (n), or the rows of P_k staged for
+// the Gram (m rows of kFRMax + 1 complex values over both grids), whichever is more.
+__host__ __device__ inline int fgen_grid(int n, int m) {
+  int need = (m * (kFRMax + 1) + 1) / 2;
+  if (need < 2 * kFRMax * kFRMax) need = 2 * kFRMax * kFRMax;   // grid B also holds the Cholesky work arrays
+  return ((n > need ? n : need) + 3) / 4 * 4;
+}
 
-template <int R>
+size_t fcol_lds_bytes(int rho, int r, int n, int m, int n1, int n2) {
+  if (n1 == kFN && n2 == kFN) return FColLayout(rho, r).total;
+  return FColLayout(rho, r, fgen_grid(n, m), n1 + n2).total;
+}
+
+template <int R, bool GEN>
 __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int tid = threadIdx.x, k = blockIdx.x;
   const int n = a.n, m = a.m, r = a.r, rho = a.rho;
   const bool gd = a.mode == FCOL_GD;
-  const FColLayout lay(rho, r);
+  const int gsize = GEN ? n : kFGrid;              // grid slots a transform touches
+  const int ntw = GEN ? a.n1 + a.n2 : kFN;
+  const FColLayout lay = GEN ? FColLayout(rho, r, fgen_grid(n, m), ntw) : FColLayout(rho, r);
+  const float gscale = GEN ? (float)(1.0 / sqrt((double)n)) : 0.f;
+  // element j -> grid slot (the 96 x 96 grid has a pad column)
+  auto pos = [&](int j) { return GEN ? j : fpos(j); };
+  auto dft2 = [&](float2* g, const float2* t, bool inv) {
+    if constexpr (GEN) {
+      if (inv) dft2_gen<true>(g, t, a.n1, a.n2, gscale);
+      else dft2_gen<false>(g, t, a.n1, a.n2, gscale);
+    } else {
+      if (inv) fft2_grid<true>(g, t);
+      else fft2_grid<false>(g, t);
+    }
+  };
   float2* gA = reinterpret_cast<float2*>(smem + lay.gridA);
   float2* gB = reinterpret_cast<float2*>(smem + lay.gridB);
   float2* tw = reinterpret_cast<float2*>(smem + lay.tw);
@@ -403,7 +500,7 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
   int* hist = reinterpret_cast<int*>(smem + lay.hist);
   int* tmp = reinterpret_cast<int*>(smem + lay.tmp);
 
-  for (int t = tid; t < kFN; t += kFThreads) tw[t] = a.tw[t];
+  for (int t = tid; t < ntw; t += kFThreads) tw[t] = a.tw[t];
   // the measurement rows i = tid, tid + 1024 of this thread, in registers
   int mi[2];
   bool ok[2];
@@ -433,26 +530,44 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
 #pragma unroll
     for (int c = 0; c < R; ++c) p[c] = Pc[e][c];
   };
-  int nz = 0;
+  // The start support must hold rho distinct in-range indices in ascending order
+  // (every support the library writes does); any other start is invalid caller
+  // state: the frame is flagged (bit 2) and starts from s = 0 with no support.
+  int nz = 0, bad = 0;
   for (int e = tid; e < rho; e += kFThreads) {
     int j = e;   // s = 0 on the support 0 .. rho - 1 when there is no start (kept if tau = 0)
     float2 v = make_float2(0.f, 0.f);
     if (gd) {
       j = a.Sidx[(long long)k * rho + e];
       v = a.Sval[(long long)k * rho + e];
-      if (j < 0 || j >= n) {   // invalid caller state: flag it and keep every access in bounds
-        flags |= 4;
-        j = 0;
-        v = make_float2(0.f, 0.f);
-      }
+      const int jp = e > 0 ? a.Sidx[(long long)k * rho + e - 1] : -1;
+      bad |= (j < 0 || j >= n || j <= jp) ? 1 : 0;
     }
     sidx[e] = j;
     sval[e] = v;
     nz |= v.x != 0.f || v.y != 0.f;
   }
+  int votes = 0;   // bit 0: some start value is nonzero; bit 1: the start is invalid
+  {
+    const int lane = tid & 63, wv = wave_id();
+    const int wb = (__ballot(nz != 0) != 0ull ? 1 : 0) | (__ballot(bad != 0) != 0ull ? 2 : 0);
+    if (lane == 0) tmp[wv] = wb;
+    __syncthreads();
+#pragma unroll
+    for (int w = 0; w < kFWaves; ++w) votes |= tmp[w];
+    __syncthreads();
+  }
+  if (votes & 2) {
+    for (int e = tid; e < rho; e += kFThreads) {
+      sidx[e] = e;
+      sval[e] = make_float2(0.f, 0.f);
+    }
+    if (tid == 0) flags |= 4;
+    __syncthreads();
+  }
   // a start whose values are all zero (an initialisation with tau0 = 0) is s = 0
   // with no support yet: T then comes from HardThreshold(g), as for no start
-  const bool start = fblock_any(nz, tmp);
+  const bool start = votes == 1;
 
   // G_k = P_k^H P_k (FP64) and its inverse.  The rows of P_k are staged in the
   // two grids (free at this point); wave w sums the entries w, w + 16, ... of
@@ -559,24 +674,24 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
 
   // A_k s (the sparse s in sidx/sval) into grid B, gathered at this thread's rows
   auto apply_sparse = [&](const int* id, const float2* vl, int cnt, float2 (&out)[2]) {
-    zero_grid(gB);
+    zero_grid(gB, gsize);
     __syncthreads();
-    for (int e = tid; e < cnt; e += kFThreads) gB[fpos(id[e])] = vl[e];
+    for (int e = tid; e < cnt; e += kFThreads) gB[pos(id[e])] = vl[e];
     __syncthreads();
-    fft2_grid<false>(gB, tw);
+    dft2(gB, tw, false);
 #pragma unroll
-    for (int e = 0; e < 2; ++e) out[e] = ok[e] ? gB[fpos(mi[e])] : make_float2(0.f, 0.f);
+    for (int e = 0; e < 2; ++e) out[e] = ok[e] ? gB[pos(mi[e])] : make_float2(0.f, 0.f);
     __syncthreads();
   };
   // A_k^H v into grid A
   auto apply_adj = [&](float2 (&v)[2]) {
-    zero_grid(gA);
+    zero_grid(gA, gsize);
     __syncthreads();
 #pragma unroll
     for (int e = 0; e < 2; ++e)
-      if (ok[e]) gA[fpos(mi[e])] = v[e];
+      if (ok[e]) gA[pos(mi[e])] = v[e];
     __syncthreads();
-    fft2_grid<true>(gA, tw);
+    dft2(gA, tw, true);
   };
 
   // A_k s at this thread's rows.  When a HardThreshold step keeps the support
@@ -599,13 +714,13 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     apply_adj(u);
     // T: the current support, or that of HardThreshold(g) when s = 0
     if (!have) {
-      flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
+      flags |= fselect([&](int j) { return gA[pos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
       for (int e = tid; e < rho; e += kFThreads) sval[e] = make_float2(0.f, 0.f);
       __syncthreads();
     }
     double gg_part = 0.0;
     for (int e = tid; e < rho; e += kFThreads) {
-      const float2 g = gA[fpos(sidx[e])];
+      const float2 g = gA[pos(sidx[e])];
       gT[e] = g;
       gg_part += (double)g.x * g.x + (double)g.y * g.y;
     }
@@ -646,22 +761,22 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     const bool okmu = ww > 0.0 && isfinite(ww) && isfinite(gg);
     const float mu = okmu ? (float)(gg / ww) : 0.f;
     // v = s - mu g in grid A, then HardThreshold
-    for (int t = tid; t < kFGrid; t += kFThreads) gA[t] = c_scale(gA[t], -mu);
+    for (int t = tid; t < gsize; t += kFThreads) gA[t] = c_scale(gA[t], -mu);
     for (int t = tid; t < words; t += kFThreads) mark[t] = 0u;
     __syncthreads();
     for (int e = tid; e < rho; e += kFThreads) {
       const int j = sidx[e];
-      gA[fpos(j)] = c_add(gA[fpos(j)], sval[e]);
+      gA[pos(j)] = c_add(gA[pos(j)], sval[e]);
       atomicOr(&mark[j >> 5], 1u << (j & 31));
     }
     __syncthreads();
     // most steps keep T: then sidx (ascending) is already the selection
-    if (!fsupport_kept([&](int j) { return gA[fpos(j)]; }, n, mark, reinterpret_cast<unsigned*>(red)))
-      flags |= fselect([&](int j) { return gA[fpos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
+    if (!fsupport_kept([&](int j) { return gA[pos(j)]; }, n, mark, reinterpret_cast<unsigned*>(red)))
+      flags |= fselect([&](int j) { return gA[pos(j)]; }, n, rho, sidx, hist, tmp) ? 1 : 0;
     int moved = 0;
     for (int e = tid; e < rho; e += kFThreads) {
       const int j = sidx[e];
-      sval[e] = gA[fpos(j)];
+      sval[e] = gA[pos(j)];
       moved |= ((mark[j >> 5] >> (j & 31)) & 1u) ^ 1u;
     }
     known = !fblock_any(moved, tmp);
@@ -729,7 +844,7 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     if (tid == 0) a.colrr[k] = yy;
     apply_adj(ev);
   }
-  for (int j = tid; j < n; j += kFThreads) Hk[j] = gA[fpos(j)];
+  for (int j = tid; j < n; j += kFThreads) Hk[j] = gA[pos(j)];
   for (int e = tid; e < rho; e += kFThreads) {
     a.Sidx[(long long)k * rho + e] = sidx[e];
     a.Sval[(long long)k * rho + e] = sval[e];
@@ -762,6 +877,22 @@ __global__ __launch_bounds__(64) void k_fu(const float2* U, int r, const float2*
   const float s = 1.0f / kFN;
 #pragma unroll
   for (int a = 0; a < 3; ++a) dst[(3 * k1 + a) * stride] = PASS == 0 ? v[a] : c_scale(v[a], s);
+}
+
+// F U for a generic frame: one workgroup per column c of U; the column is staged
+// in LDS, transformed by dft2_gen and written back (the same transform and scale
+// as the column kernel's).
+__global__ __launch_bounds__(kFThreads) void k_fu_gen(const float2* U, int n, int r, int n1, int n2,
+                                                      const float2* tw, float2* FU) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  float2* grid = reinterpret_cast<float2*>(smem);
+  float2* twl = grid + n;
+  const int c = blockIdx.x;
+  for (int t = threadIdx.x; t < n1 + n2; t += kFThreads) twl[t] = tw[t];
+  for (int j = threadIdx.x; j < n; j += kFThreads) grid[j] = U[(long long)j * r + c];
+  __syncthreads();
+  dft2_gen<false>(grid, twl, n1, n2, (float)(1.0 / sqrt((double)n)));
+  for (int j = threadIdx.x; j < n; j += kFThreads) FU[(long long)j * r + c] = grid[j];
 }
 
 // Tc[k][c] = sum_j H[k][j] conj(U[j][c]) (so that L_0 (L_0^H U) = sum_k h_k conj(Tc[k]) ^ T).
@@ -1145,6 +1276,16 @@ __global__ void k_ftwiddle(float2* tw) {
   }
 }
 
+// Twiddles of a generic frame: W_n1^t (t < n1), then W_n2^t (t < n2), W_N = exp(-2 pi i / N).
+__global__ void k_ftwiddle_gen(float2* tw, int n1, int n2) {
+  for (int t = threadIdx.x + blockIdx.x * blockDim.x; t < n1 + n2; t += blockDim.x * gridDim.x) {
+    const int N = t < n1 ? n1 : n2, e = t < n1 ? t : t - n1;
+    double s, c;
+    sincospi(-2.0 * e / N, &s, &c);
+    tw[t] = make_float2((float)c, (float)s);
+  }
+}
+
 __global__ void k_fbasis(float2* U, int n, int r) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < (long long)n * r;
        i += (long long)gridDim.x * blockDim.x) {
@@ -1497,22 +1638,43 @@ __global__ void k_fqr_f(FQRArgs a) {
 
 static int fr_bucket(int r) { return r <= 2 ? 2 : (r <= 4 ? 4 : (r <= 6 ? 6 : 8)); }
 
-hipError_t launch_fcol(const FColArgs& a, hipStream_t st) {
-  const size_t lds = fcol_lds_bytes(a.rho, a.r);
-  (void)hipGetLastError();
-#define FCOL_CALL(RR)                                                                                       \
-  {                                                                                                         \
-    static bool attr_set = false;   /* the LDS limit is raised once, before any graph capture */           \
-    if (!attr_set) {                                                                                        \
-      hipError_t e = hipFuncSetAttribute((const void*)k_fcol<RR>, hipFuncAttributeMaxDynamicSharedMemorySize, \
-                                         (int)(163840));                                                    \
-      if (e != hipSuccess) return e;                                                                        \
-      attr_set = true;                                                                                      \
-    }                                                                                                       \
-    hipLaunchKernelGGL(k_fcol<RR>, dim3(a.q), dim3(kFThreads), lds, st, a);                                 \
+template <int RR, bool GEN>
+static hipError_t launch_fcol_inst(const FColArgs& a, size_t lds, hipStream_t st) {
+  static bool attr_set = false;   // the LDS limit is raised once, before any graph capture
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute((const void*)k_fcol<RR, GEN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)kFLdsMax);
+    if (e != hipSuccess) return e;
+    attr_set = true;
   }
+  hipLaunchKernelGGL((k_fcol<RR, GEN>), dim3(a.q), dim3(kFThreads), lds, st, a);
+  return hipSuccess;
+}
+
+hipError_t launch_fcol(const FColArgs& a, hipStream_t st) {
+  const bool gen = !(a.n1 == kFN && a.n2 == kFN);
+  const size_t lds = fcol_lds_bytes(a.rho, a.r, a.n, a.m, a.n1, a.n2);
+  if (lds > kFLdsMax) return hipErrorInvalidValue;
+  (void)hipGetLastError();
+  hipError_t e;
+#define FCOL_CALL(RR) e = gen ? launch_fcol_inst<RR, true>(a, lds, st) : launch_fcol_inst<RR, false>(a, lds, st)
   FR_SWITCH(fr_bucket(a.r), FCOL_CALL)
 #undef FCOL_CALL
+  if (e != hipSuccess) return e;
+  return hipGetLastError();
+}
+
+hipError_t launch_fu_gen(const float2* U, int n, int r, int n1, int n2, const float2* tw, float2* FU,
+                         hipStream_t st) {
+  (void)hipGetLastError();
+  const size_t lds = 8 * (size_t)(n + n1 + n2);
+  hipLaunchKernelGGL(k_fu_gen, dim3(r), dim3(kFThreads), lds, st, U, n, r, n1, n2, tw, FU);
+  return hipGetLastError();
+}
+
+hipError_t launch_ftwiddle_gen(float2* tw, int n1, int n2, hipStream_t st) {
+  (void)hipGetLastError();
+  hipLaunchKernelGGL(k_ftwiddle_gen, dim3((n1 + n2 + 255) / 256), dim3(256), 0, st, tw, n1, n2);
   return hipGetLastError();
 }
 

@@ -451,6 +451,10 @@ __global__ void k_copy_i(int* dst, const int* src, long long count) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
+__global__ void k_put_words(long long* dst, StateWords w) {
+  if (threadIdx.x < kStateWords && blockIdx.x == 0) dst[threadIdx.x] = w.v[threadIdx.x];
+}
+
 __global__ void k_sum_partials(const float* gpart, int KS, long long nr, float* out) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < nr; i += (long long)gridDim.x * blockDim.x) {
     float s = gpart[i];
@@ -542,6 +546,12 @@ hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStrea
 hipError_t launch_sum_partials(const float* gpart, int KS, long long nr, float* out, hipStream_t st) {
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(k_sum_partials, dim3(grid_for(nr, 256)), dim3(256), 0, st, gpart, KS, nr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_put_words(long long* dst, const StateWords& w, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(k_put_words, dim3(1), dim3(64), 0, st, dst, w);
   return hipGetLastError();
 }
 

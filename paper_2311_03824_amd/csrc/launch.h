@@ -69,8 +69,15 @@ hipError_t launch_fill_int(int* p, int v, long long count, hipStream_t st);
 hipError_t launch_fill_basis(float* U, int n, int r, hipStream_t st);
 hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStream_t st);
 hipError_t launch_copy_i(int* dst, const int* src, long long count, hipStream_t st);
+// header words of a saved solver state, written on the stream by a kernel (so the
+// host values are captured at launch, with no host buffer to keep alive)
+constexpr int kStateWords = 16;
+struct StateWords {
+  long long v[kStateWords];
+};
+hipError_t launch_put_words(long long* dst, const StateWords& w, hipStream_t st);
 
-// partial Fourier form (96 x 96 complex frames)
+// partial Fourier form (96 x 96 complex frames by FFT; other frame sizes by direct line DFTs)
 constexpr int kFN = 96;                // 1D transform size
 constexpr int kFP = 97;                // LDS row stride of a frame (complex elements)
 constexpr int kFGrid = kFN * kFP;      // complex elements of a padded frame
@@ -78,6 +85,9 @@ constexpr int kFThreads = 1024;        // workgroup of the Fourier kernels
 constexpr int kFWaves = kFThreads / 64;
 constexpr int kFRMax = 8;              // largest rank of the Fourier kernels
 constexpr int kFRhoMax = 256;          // largest rho of the Fourier column kernel
+constexpr int kFGenPer = 4;            // generic frames: n <= kFGenPer * kFThreads elements
+constexpr int kFGenLineMax = 1024;     // generic frames: n1, n2 <= 1024 (twiddle tables in LDS)
+constexpr size_t kFLdsMax = 160 * 1024;   // LDS of one CU, the most a Fourier column workgroup takes
 enum { FCOL_INIT = 0, FCOL_GD = 1 };
 
 struct FColArgs {
@@ -86,7 +96,8 @@ struct FColArgs {
   const float2* Y;       // y_k at Y[k * ldy]
   long long ldy;
   const float2* FU;      // n x r, the 2D DFT of U's columns (GD)
-  const float2* tw;      // 96 twiddles exp(-2 pi i t / 96)
+  const float2* tw;      // 96 x 96 frames: 96 twiddles exp(-2 pi i t / 96); other frames: W_n1^t, then W_n2^t
+  int n1, n2;            // frame size (n = n1 n2)
   int* Sidx;             // q x rho, in (GD) / out
   float2* Sval;          // q x rho
   float2* Bt;            // q x r (GD)
@@ -113,7 +124,10 @@ struct FQRArgs {
   int nb;                // 256-row blocks of n
 };
 
-size_t fcol_lds_bytes(int rho, int r);
+size_t fcol_lds_bytes(int rho, int r, int n, int m, int n1, int n2);
+hipError_t launch_fu_gen(const float2* U, int n, int r, int n1, int n2, const float2* tw, float2* FU,
+                         hipStream_t st);
+hipError_t launch_ftwiddle_gen(float2* tw, int n1, int n2, hipStream_t st);
 hipError_t launch_fgrad_gd(const float2* H, const float2* B, const float2* U, int n, int q, int r, float2* Gsum,
                            double2* part, const int* skip, hipStream_t st);
 hipError_t launch_fqr_gd(const FQRArgs& a, hipStream_t st);
@@ -124,6 +138,17 @@ hipError_t launch_fltu(const float2* H, const float2* U, int n, int q, int r, fl
 hipError_t launch_fqr(const FQRArgs& a, hipStream_t st);
 hipError_t launch_ftwiddle(float2* tw, hipStream_t st);
 hipError_t launch_fbasis(float2* U, int n, int r, hipStream_t st);
+
+// automatic rank (Sec. 2.6): block subspace iteration, CholeskyQR2, Rayleigh-Ritz by Jacobi
+constexpr int kRankBlockMax = 88;   // block columns b: the b x b FP64 matrices stay under 64 KiB of LDS
+size_t rank_lds_bytes(int b);
+hipError_t launch_rank_mm(bool trans, const float* A, long long lda, const float* B, long long ldb, float* C,
+                          long long ldc, int M, int N, int K, hipStream_t st);
+hipError_t launch_rank_gram(const float* X, int rows, int b, double* W, hipStream_t st);
+hipError_t launch_rank_chol(const double* W, int b, double* Xinv, float* Xf, int* flag, hipStream_t st);
+hipError_t launch_rank_jacobi(const double* M, int b, int K, double energy, double* sv, int* r_out,
+                              hipStream_t st);
+hipError_t launch_rank_slice(const float* Ub, int n, int b, int r, float* U, hipStream_t st);
 
 // synthetic instances on the device
 struct MeasureArgs {

@@ -340,7 +340,19 @@ def poisson_arrivals(count: int, rate: float, seed: int) -> np.ndarray:
     return np.cumsum(gaps) - gaps[0]
 
 
-def request_truth(req: ServeRequest, s_scale: float = 10.0) -> dict:
+def _s_values(rng: np.random.Generator, shape, s_dist: str, s_scale: float) -> np.ndarray:
+    """Nonzero values of S*: N(0, s_scale^2) ("normal"), U[-s_scale, s_scale] ("uniform", the
+    S1 law of Sec. 3) or uniform over {+-1, +-10, +-100} ("pm_powers", the S2 law)."""
+    if s_dist == "normal":
+        return rng.standard_normal(shape) * s_scale
+    if s_dist == "uniform":
+        return rng.uniform(-s_scale, s_scale, shape)
+    if s_dist == "pm_powers":
+        return rng.choice(np.array([-1.0, -10.0, -100.0, 1.0, 10.0, 100.0]), size=shape)
+    raise ValueError(s_dist)
+
+
+def request_truth(req: ServeRequest, s_scale: float = 10.0, s_dist: str = "normal") -> dict:
     """U* (n, r), B* (r, q), the support (q, rho) and values, and Xt = X*^T (q, n) FP64."""
     n, q, r, rho = req.n, req.q, req.r, req.rho
     G = _rng(req.seed, _TAG_U).standard_normal((n, r))
@@ -351,7 +363,7 @@ def request_truth(req: ServeRequest, s_scale: float = 10.0) -> dict:
     B_star = _rng(req.seed, _TAG_B).standard_normal((r, q))
     keys = _rng(req.seed, _TAG_SUPP).random((q, n))
     supp = np.sort(np.argpartition(keys, rho - 1, axis=1)[:, :rho], axis=1) if rho > 0 else np.zeros((q, 0), np.int64)
-    vals = _rng(req.seed, _TAG_SVAL).standard_normal((q, rho)) * s_scale
+    vals = _s_values(_rng(req.seed, _TAG_SVAL), (q, rho), s_dist, s_scale)
     Xt = (U_star @ B_star).T.copy()
     if rho > 0:
         Xt[np.arange(q)[:, None], supp] += vals
@@ -405,19 +417,33 @@ def _complex_normal(rng: np.random.Generator, shape, var: float) -> np.ndarray:
 
 
 def make_fourier_instance(N1: int, N2: int, q: int, m: int, r: int, rho: int, seed: int,
-                          s_var: float = 25.0, s_zero: bool = False) -> FourierInstance:
+                          s_var: float = 25.0, s_zero: bool = False, real_signal: bool = False,
+                          s_dist: str = "normal", s_scale: float = 6.0) -> FourierInstance:
+    """Complex instance (defaults above), or with real_signal=True a real X*: U* the Q factor
+    of a real Gaussian, B* i.i.d. N(0, 1) and S* values by `s_dist` / `s_scale` as in
+    make_instance (the real protocol of Sec. 3 measured through partial Fourier rows)."""
     n = N1 * N2
     if not (1 <= r <= min(m, n)) or not (0 <= rho <= n) or not (1 <= m <= n) or q < 1:
         raise ValueError("invalid sizes")
-    G = _complex_normal(_rng(seed, _TAG_U), (n, r), 1.0)
+    if real_signal:
+        G = _rng(seed, _TAG_U).standard_normal((n, r)).astype(np.complex128)
+    else:
+        G = _complex_normal(_rng(seed, _TAG_U), (n, r), 1.0)
     Q, R = np.linalg.qr(G)
     d = np.diag(R)
     ph = np.where(np.abs(d) > 0, d / np.where(np.abs(d) > 0, np.abs(d), 1.0), 1.0)
     U_star = Q * ph
-    B_star = _complex_normal(_rng(seed, _TAG_B), (r, q), 1.0)
+    if real_signal:
+        U_star = U_star.real.astype(np.complex128)
+        B_star = _rng(seed, _TAG_B).standard_normal((r, q)).astype(np.complex128)
+    else:
+        B_star = _complex_normal(_rng(seed, _TAG_B), (r, q), 1.0)
     keys = _rng(seed, _TAG_SUPP).random((q, n))
     supp = np.sort(np.argsort(keys, axis=1, kind="stable")[:, :rho], axis=1)
-    vals = _complex_normal(_rng(seed, _TAG_SVAL), (q, rho), s_var)
+    if real_signal:
+        vals = _s_values(_rng(seed, _TAG_SVAL), (q, rho), s_dist, s_scale).astype(np.complex128)
+    else:
+        vals = _complex_normal(_rng(seed, _TAG_SVAL), (q, rho), s_var)
     S_star = np.zeros((n, q), np.complex128)
     if not s_zero and rho > 0:
         S_star[supp, np.arange(q)[:, None]] = vals

@@ -106,7 +106,7 @@ def test_workspace_bytes_accepts_the_benchmark_problem(lib):
     (dict(r=17), -5),                   # no instantiation above r = 16
     (dict(n=5600, m=1024, r=16, lda=1024, ldy=1024, a_stride_k=1024 * 5600), -5),   # LDS of a column workgroup
     (dict(m=1025, lda=1028, a_stride_k=1028 * 1000, ldy=1025), -5),
-    (dict(r=0), -1),
+    (dict(r=-1), -1),                   # r = 0 is the automatic rank; negative is invalid
     (dict(q=0), -1),                    # empty problem
     (dict(n=0), -1),
     (dict(m=0, lda=4, ldy=4, a_stride_k=4000), -1),
@@ -178,3 +178,66 @@ def test_fourier_workspace_and_limits(lib):
                      (dict(m=9217), -1)]:
         rc, _, msg = _ws(lib, _fourier_problem(lib, **kw))
         assert rc == code, (kw, msg)
+
+
+def test_null_stream_is_rejected_before_any_gpu_work(lib):
+    """The library never enqueues on the null stream: every entry point that takes a
+    stream returns EINVAL for NULL (checked here with placeholder device pointers,
+    which are validated but never dereferenced)."""
+    so = lib.load()
+    p = _problem(lib)
+    par = lib.default_params()
+    h = ctypes.c_void_p()
+    assert so.altgdmin_init(ctypes.byref(p), ctypes.byref(par), 1 << 30, 1 << 34, None, ctypes.byref(h)) == -1
+    assert "stream" in so.altgdmin_last_error().decode()
+    assert so.altgdmin_op_select(1 << 20, 100, 4, 100, 5, 1 << 21, 1 << 22, None, None) == -1
+    assert so.altgdmin_op_au(ctypes.byref(p), 1 << 20, 1 << 21, 1 << 22, None, None) == -1
+    assert so.altgdmin_op_iht(ctypes.byref(p), 0, None, None, 1, 0, 1 << 20, 1 << 21, None, None, None, None) == -1
+    assert so.altgdmin_op_grad(1 << 20, 1 << 21, 100, 100, 2, 1 << 22, 1 << 23, 1 << 20, None) == -1
+
+
+def test_state_entry_points_validate_arguments(lib):
+    so = lib.load()
+    b = ctypes.c_size_t(0)
+    assert so.altgdmin_state_bytes(None, ctypes.byref(b)) == -1
+    assert so.altgdmin_get_state(None, 1 << 20, 1 << 20, 1 << 12) == -1
+    assert so.altgdmin_set_state(None, 1 << 20, 1 << 20, 1 << 12) == -1
+
+
+def test_automatic_rank_problems(lib):
+    """r = 0 asks for the automatic rank: the workspace is laid out for the largest rank
+    the rule may pick; the Fourier form and K > 88 are not built; bad energies are refused."""
+    rc0, b0, _ = _ws(lib, _problem(lib, r=0))
+    rc16, b16, _ = _ws(lib, _problem(lib, r=16))
+    assert rc0 == 0 and rc16 == 0 and b0 > b16 > 0      # r_cap = 16 plus the estimate's scratch
+    rc, _, msg = _ws(lib, _problem(lib, r=0, n=2000, q=2000, m=1000, lda=1000, ldy=1000,
+                                   a_stride_k=1000 * 2000))
+    assert rc == -5 and "automatic rank" in msg      # K = 100 > 88
+    rc, _, _ = _ws(lib, _fourier_problem(lib, r=0))
+    assert rc == -5
+    rc, _, _ = _ws(lib, _problem(lib, r=0), lib.default_params(rank_energy=1.5))
+    assert rc == -1
+    so = lib.load()
+    b = ctypes.c_size_t(0)
+    assert so.altgdmin_op_rank_scratch_bytes(1000, 1000, 400, ctypes.byref(b)) == 0 and b.value > 0
+    assert so.altgdmin_op_rank_scratch_bytes(2000, 2000, 1000, ctypes.byref(b)) == -5
+
+
+def test_every_binding_call_that_takes_a_stream_is_ordered_on_a_created_stream():
+    """Each binding function with a `stream=` argument is wrapped exactly once by the
+    decorator that moves calls off torch's null stream (the library refuses NULL)."""
+    src = open(os.path.join(ROOT, "paper_2311_03824_amd", "altgdmin.py")).read().split("\n")
+    checked = 0
+    for i, line in enumerate(src):
+        if not line.startswith("def altgdmin_"):
+            continue
+        j, sig = i, line
+        while not sig.rstrip().endswith(":"):
+            j += 1
+            sig += src[j]
+        takes_stream = "stream=None" in sig
+        wrapped = src[i - 1].strip() == "@_on_stream"
+        twice = src[i - 2].strip() == "@_on_stream"
+        assert takes_stream == wrapped and not twice, line
+        checked += takes_stream
+    assert checked >= 20

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 def torch_dev():
     import torch
     if not torch.cuda.is_available():
-        pytest.skip("no GPU")
+        pytest.fail("GPU tests need a ROCm GPU")
     return torch
 
 
