@@ -232,6 +232,47 @@ def philox_form(lib, torch, np, cfg, target):
     return out
 
 
+def philox_beyond_hbm(lib, torch, np, n: int = 2500, q: int = 40001, m: int = 1000, r: int = 4, rho: int = 25,
+                      iters: int = 3):
+    """A problem that cannot be stored: its A would take q n m 4 bytes (about 400 GB as
+    FP32) against 288 GB of HBM.  The Philox form never stores A, so it runs anyway:
+    y_k = A_k x*_k is formed on the device from the same counters (FP64 accumulation),
+    then the initialisation and `iters` GDmin iterations; reported: seconds per
+    iteration, A elements regenerated per second, and the residual after each step."""
+    from paper_2311_03824_amd import instances as I
+    req = I.ServeRequest(idx=0, n=n, q=q, m=m, r=r, rho=rho, a_format="f32", seed=231103829)
+    truth = I.request_truth(req)
+    table = torch.from_numpy(I.normal_table()).cuda()
+    Xt = torch.from_numpy(truth["Xt"]).cuda()
+    Y = torch.empty((q, m), dtype=torch.float32, device="cuda")
+    prob = lib.make_problem(None, Y, r, rho, m=m, philox_seed=req.a_seed, normal_table=table, n=n)
+    lib.altgdmin_op_measure(prob, Xt, Y)
+    del Xt
+    par = lib.default_params(t_max=iters)
+    ws = torch.empty(lib.altgdmin_workspace_bytes(prob, par), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    e0.record()
+    h = lib.altgdmin_init(prob, par, ws)
+    e1.record()
+    lib.altgdmin_step(h, iters)
+    e2.record()
+    torch.cuda.synchronize()
+    log_r = lib.altgdmin_residual_log(h, iters)
+    st = lib.altgdmin_status(h)
+    lib.altgdmin_destroy(h)
+    it_s = e1.elapsed_time(e2) * 1e-3 / iters
+    # elements generated per GDmin iteration: A_k U plus the column kernel's tau + 1 passes
+    # and tau + 1 support gathers (rows rounded up to the generator's groups of four)
+    m4 = 4 * ((m + 3) // 4)
+    elems = q * n * m4 * (1 + par.tau + 1) + q * m4 * rho * (par.tau + 1)
+    return {"workload": f"n={n} q={q} m={m} r={r} rho={rho}, Philox A (never stored)",
+            "fp32_A_bytes_if_stored": 4 * q * n * m, "hbm_bytes": 288 * 10 ** 9,
+            "init_s": round(e0.elapsed_time(e1) * 1e-3, 3), "s_per_gdmin_iteration": round(it_s, 4),
+            "G_elements_per_s": round(elems / it_s / 1e9, 1), "residual_log": [float(x) for x in log_r],
+            "error_flags": st["error_flags"]}
+
+
 def fourier_form(lib, torch, np, iters: int = 200):
     """Partial Fourier form: 64 frames of 96 x 96 (complex64), m = 1536, r = 6, rho = 184."""
     from paper_2311_03824_amd import instances as I
@@ -421,8 +462,10 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the mixed-size serving run (0: skip); arrival rate = 0.8 x closed-loop rate")
     ap.add_argument("--serve-budget-gib", type=float, default=32.0, help="HBM admission budget of the serving run")
-    ap.add_argument("--only", choices=["fourier", "serve"],
-                    help="run only the Fourier form or only the serving run and print its JSON (for profiling)")
+    ap.add_argument("--only", choices=["fourier", "serve", "studies", "philox_big"],
+                    help="run only the Fourier form, the serving run, or the studies of the paper's experiment "
+                         "shapes (Fig. 1, Fig. 2, Table 1) and print its JSON")
+    ap.add_argument("--study-runs", type=int, default=20, help="seeded instances per study cell")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run torch's copy kernel on a 1.6 GB FP32 buffer (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -453,6 +496,13 @@ def main() -> int:
     lib.load()
     if args.only == "fourier":
         print(json.dumps({"fourier_form": fourier_form(lib, torch, np)}), flush=True)
+        return 0
+    if args.only == "philox_big":
+        print(json.dumps({"philox_beyond_hbm": philox_beyond_hbm(lib, torch, np)}), flush=True)
+        return 0
+    if args.only == "studies":
+        from paper_2311_03824_amd import studies
+        print(json.dumps({"studies": studies.run_all(runs=args.study_runs, log=log)}), flush=True)
         return 0
     if args.only == "serve":
         from paper_2311_03824_amd import serve
@@ -560,6 +610,8 @@ def main() -> int:
         log("forms throughput: " + json.dumps(result["forms_throughput"]))
         result["philox_form"] = philox_form(lib, torch, np, cfg, args.target_resid)
         log("philox: " + json.dumps(result["philox_form"]))
+        result["philox_beyond_hbm"] = philox_beyond_hbm(lib, torch, np)
+        log("philox beyond HBM: " + json.dumps(result["philox_beyond_hbm"]))
         result["fourier_form"] = fourier_form(lib, torch, np)
         log("fourier: " + json.dumps(result["fourier_form"]))
         result["other_configs"] = small_configs(lib, torch, np)

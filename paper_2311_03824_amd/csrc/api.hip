@@ -1043,6 +1043,9 @@ int altgdmin_set_state(altgdmin_handle* h, const void* state, size_t bytes, void
   HIPCHK(cp(h->Tval, L.Tval, (size_t)p.q * p.rho * w));
   HIPCHK(cp(h->colflags, L.flags, (size_t)p.q * sizeof(int)));
   HIPCHK(cp(h->rlog, L.rlog, (size_t)std::min(saved_len, h->rlog_len) * sizeof(double)));
+  // the support is the iteration's warm start: a column that is not rho distinct
+  // in-range ascending indices is flagged and restarts from s = 0
+  HIPCHK(launch_check_support(h->Tidx, h->Tval, h->fmt == FMT_PFOURIER ? 2 : 1, p.q, p.rho, p.n, h->colflags, st));
   h->t_host = (int)hw[8];
   return ALTGDMIN_OK;
 }

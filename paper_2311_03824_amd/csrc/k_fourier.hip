@@ -457,7 +457,8 @@ struct FColLayout {
 // the Gram (m rows of kFRMax + 1 complex values over both grids), whichever is more.
 __host__ __device__ inline int fgen_grid(int n, int m) {
   int need = (m * (kFRMax + 1) + 1) / 2;
-  if (need < 2 * kFRMax * kFRMax) need = 2 * kFRMax * kFRMax;   // grid B also holds the Cholesky work arrays
+  // grid B also holds the Cholesky work arrays: 2 kFRMax^2 double2 = 4 kFRMax^2 complex slots
+  if (need < 4 * kFRMax * kFRMax) need = 4 * kFRMax * kFRMax;
   return ((n > need ? n : need) + 3) / 4 * 4;
 }
 
@@ -530,44 +531,26 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
 #pragma unroll
     for (int c = 0; c < R; ++c) p[c] = Pc[e][c];
   };
-  // The start support must hold rho distinct in-range indices in ascending order
-  // (every support the library writes does); any other start is invalid caller
-  // state: the frame is flagged (bit 2) and starts from s = 0 with no support.
-  int nz = 0, bad = 0;
+  int nz = 0;
   for (int e = tid; e < rho; e += kFThreads) {
     int j = e;   // s = 0 on the support 0 .. rho - 1 when there is no start (kept if tau = 0)
     float2 v = make_float2(0.f, 0.f);
     if (gd) {
       j = a.Sidx[(long long)k * rho + e];
       v = a.Sval[(long long)k * rho + e];
-      const int jp = e > 0 ? a.Sidx[(long long)k * rho + e - 1] : -1;
-      bad |= (j < 0 || j >= n || j <= jp) ? 1 : 0;
+      if (j < 0 || j >= n) {   // invalid state: flag it and keep every access in bounds
+        flags |= 4;
+        j = 0;
+        v = make_float2(0.f, 0.f);
+      }
     }
     sidx[e] = j;
     sval[e] = v;
     nz |= v.x != 0.f || v.y != 0.f;
   }
-  int votes = 0;   // bit 0: some start value is nonzero; bit 1: the start is invalid
-  {
-    const int lane = tid & 63, wv = wave_id();
-    const int wb = (__ballot(nz != 0) != 0ull ? 1 : 0) | (__ballot(bad != 0) != 0ull ? 2 : 0);
-    if (lane == 0) tmp[wv] = wb;
-    __syncthreads();
-#pragma unroll
-    for (int w = 0; w < kFWaves; ++w) votes |= tmp[w];
-    __syncthreads();
-  }
-  if (votes & 2) {
-    for (int e = tid; e < rho; e += kFThreads) {
-      sidx[e] = e;
-      sval[e] = make_float2(0.f, 0.f);
-    }
-    if (tid == 0) flags |= 4;
-    __syncthreads();
-  }
   // a start whose values are all zero (an initialisation with tau0 = 0) is s = 0
   // with no support yet: T then comes from HardThreshold(g), as for no start
-  const bool start = votes == 1;
+  const bool start = fblock_any(nz, tmp);
 
   // G_k = P_k^H P_k (FP64) and its inverse.  The rows of P_k are staged in the
   // two grids (free at this point); wave w sums the entries w, w + 16, ... of

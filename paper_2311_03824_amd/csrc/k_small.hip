@@ -451,6 +451,28 @@ __global__ void k_copy_i(int* dst, const int* src, long long count) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < count; i += (long long)gridDim.x * blockDim.x) dst[i] = src[i];
 }
 
+// A support loaded into a solver (altgdmin_set_state) must hold rho distinct
+// in-range indices in ascending order in every column; a column that does not
+// gets the no-start support 0 .. rho - 1 with zero values and error bit 2.
+// One 64-thread workgroup per column; vpe = floats per value (2 for complex).
+__global__ void k_check_support(int* idx, float* val, int vpe, int q, int rho, int n, int* flags) {
+  const int k = blockIdx.x, lane = threadIdx.x;
+  if (k >= q) return;
+  int* ik = idx + (long long)k * rho;
+  float* vk = val + (long long)k * rho * vpe;
+  int bad = 0;
+  for (int t = lane; t < rho; t += 64) {
+    const int j = ik[t];
+    bad |= (j < 0 || j >= n || (t > 0 && j <= ik[t - 1])) ? 1 : 0;
+  }
+  if (__ballot(bad != 0) == 0ull) return;
+  for (int t = lane; t < rho; t += 64) {
+    ik[t] = t;
+    for (int c = 0; c < vpe; ++c) vk[(long long)t * vpe + c] = 0.f;
+  }
+  if (lane == 0) flags[k] |= 4;
+}
+
 __global__ void k_put_words(long long* dst, StateWords w) {
   if (threadIdx.x < kStateWords && blockIdx.x == 0) dst[threadIdx.x] = w.v[threadIdx.x];
 }
@@ -546,6 +568,13 @@ hipError_t launch_copy_f(float* dst, const float* src, long long count, hipStrea
 hipError_t launch_sum_partials(const float* gpart, int KS, long long nr, float* out, hipStream_t st) {
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(k_sum_partials, dim3(grid_for(nr, 256)), dim3(256), 0, st, gpart, KS, nr, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_support(int* idx, float* val, int vpe, int q, int rho, int n, int* flags, hipStream_t st) {
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  if (q < 1 || rho < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_check_support, dim3(q), dim3(64), 0, st, idx, val, vpe, q, rho, n, flags);
   return hipGetLastError();
 }
 

@@ -76,6 +76,7 @@ struct StateWords {
   long long v[kStateWords];
 };
 hipError_t launch_put_words(long long* dst, const StateWords& w, hipStream_t st);
+hipError_t launch_check_support(int* idx, float* val, int vpe, int q, int rho, int n, int* flags, hipStream_t st);
 
 // partial Fourier form (96 x 96 complex frames by FFT; other frame sizes by direct line DFTs)
 constexpr int kFN = 96;                // 1D transform size

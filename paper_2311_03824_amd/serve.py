@@ -13,9 +13,12 @@ the seed of its data.  The scheduler
   * advances every admitted problem together, `poll_every` GDmin iterations per
     round, with altgdmin_step_many (the column, gradient and QR kernels of all
     problems share launches);
-  * after each round reads each problem's relative residual and retires those
-    at or below `tol` or at `max_iters` iterations, recording the latency
-    (completion minus arrival) and the error against X*.
+  * after each round reads every active problem's status with one
+    synchronisation (altgdmin_status_many) and retires those whose relative
+    residual is at or below `tol`, that reached `max_iters` iterations, or whose
+    kernels raised an error flag (a non-finite value, an indefinite Gram
+    matrix, invalid state), recording the latency (completion minus arrival)
+    and the error against X*.
 
 The scheduling logic is host-only and takes an executor object, so it can be
 exercised without a GPU; GpuExecutor is the one that drives the library.
@@ -45,6 +48,7 @@ class Outcome:
     converged: bool
     error: float            # ||X - X*||_F / ||X*||_F of the consistent pair
     rejected: bool = False
+    error_flags: int = 0    # the kernels' error bits when the request was retired
 
     @property
     def latency(self) -> float:
@@ -61,19 +65,28 @@ class ServeReport:
     host_seconds: dict = dataclasses.field(default_factory=dict)
 
     def summary(self, err_bound: float = 1e-6) -> dict:
+        """Counts, throughput and latency.  A completed request is one the scheduler
+        retired (converged, at the iteration cap, or with an error flag); only
+        converged ones count as solves in converged_solves_per_s; error_violations
+        counts every completed request whose error exceeds err_bound, converged or not."""
         done = [o for o in self.outcomes if not o.rejected]
         lat = np.array([o.latency for o in done]) if done else np.zeros(1)
         conv = [o for o in done if o.converged]
+        unconv = [o for o in done if not o.converged]
         return {
             "requests": len(self.outcomes),
             "completed": len(done),
             "rejected": len(self.outcomes) - len(done),
             "solves_per_s": len(done) / self.makespan if self.makespan > 0 else 0.0,
+            "converged_solves_per_s": len(conv) / self.makespan if self.makespan > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)),
             "p99_latency_s": float(np.percentile(lat, 99)),
             "converged_fraction": len(conv) / max(1, len(done)),
             "max_error_converged": max((o.error for o in conv), default=float("nan")),
-            "error_violations": sum(1 for o in conv if not (o.error <= err_bound)),
+            "not_converged": len(unconv),
+            "max_error_not_converged": max((o.error for o in unconv), default=float("nan")),
+            "retired_with_error_flags": sum(1 for o in done if o.error_flags),
+            "error_violations": sum(1 for o in done if not (o.error <= err_bound)),
             "mean_iterations": float(np.mean([o.iterations for o in done])) if done else 0.0,
             "makespan_s": self.makespan,
             "budget_gib": self.budget_bytes / 2**30,
@@ -153,11 +166,13 @@ class Scheduler:
             status = timed("poll", self.ex.poll, [a[1] for a in active])
             keep = []
             for (req, job, fp, adm), st in zip(active, status):
-                iters, resid = st
-                conv = resid <= self.tol
-                if conv or iters >= self.max_iters:
+                iters, resid = st[0], st[1]
+                flags = st[2] if len(st) > 2 else 0
+                conv = resid <= self.tol and not flags
+                if conv or iters >= self.max_iters or flags:
                     err = timed("finish", self.ex.finish, job)
-                    outcomes.append(Outcome(req.idx, req.arrival, adm, now(), iters, resid, conv, err))
+                    outcomes.append(Outcome(req.idx, req.arrival, adm, now(), iters, resid, conv, err,
+                                            error_flags=int(flags)))
                     used -= fp
                 else:
                     keep.append((req, job, fp, adm))
@@ -247,11 +262,9 @@ class GpuExecutor:
         self.lib.altgdmin_step_many(hs, iters, self.group_ws)
 
     def poll(self, jobs):
-        out = []
-        for j in jobs:
-            st = self.lib.altgdmin_status(j["h"])
-            out.append((int(st["iterations"]), float(st["resid"])))
-        return out
+        """(iterations, residual, error flags) of every job, with one synchronisation."""
+        reps = self.lib.altgdmin_status_many([j["h"] for j in jobs])
+        return [(int(st["iterations"]), float(st["resid"]), int(st["error_flags"])) for st in reps]
 
     def finish(self, job) -> float:
         torch, req = self.torch, job["req"]

@@ -186,3 +186,42 @@ def test_load_sweep_runs_each_load_on_the_same_requests():
         assert 0.0 < v["p50_latency_s"] <= v["p99_latency_s"]
     # the caller's requests keep their own arrival times
     assert all(r.arrival == 0.0 for r in reqs)
+
+
+def test_requests_with_error_flags_are_retired_at_once_and_counted():
+    """A job whose kernels report an error flag is retired after the round that
+    raised it (not run to max_iters), counted as not converged and as a violation."""
+    clock = Clock()
+
+    class Flagging(MockExecutor):
+        def poll(self, jobs):
+            out = super().poll(jobs)
+            return [(it, res, 1 if j["req"].idx == 2 else 0) for (it, res), j in zip(out, jobs)]
+
+    ex = Flagging(clock, {i: None for i in range(4)} | {0: 30, 1: 30, 3: 30})
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(4)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-7, max_iters=300,
+                    clock=clock, sleep=clock.sleep).run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert o[2].error_flags == 1 and not o[2].converged and o[2].iterations == 10
+    assert all(o[i].converged and o[i].iterations == 30 for i in (0, 1, 3))
+    s = rep.summary()
+    assert s["retired_with_error_flags"] == 1 and s["not_converged"] == 1
+    assert s["converged_solves_per_s"] < s["solves_per_s"]
+
+
+def test_unconverged_requests_count_as_error_violations():
+    clock = Clock()
+
+    class BadFinish(MockExecutor):
+        def finish(self, job):
+            super().finish(job)
+            return 1e-9 if self.conv_at[job["req"].idx] is not None else 0.5
+
+    ex = BadFinish(clock, {0: 20, 1: None})
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(2)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-7, max_iters=50,
+                    clock=clock, sleep=clock.sleep).run(reqs)
+    s = rep.summary()
+    assert s["not_converged"] == 1 and s["max_error_not_converged"] == 0.5
+    assert s["error_violations"] == 1
