@@ -376,6 +376,27 @@ int altgdmin_op_subspace(const float* L0t, int32_t n, int32_t q, int32_t r, cons
                          int32_t iters, double tol, float* U_out, int32_t* iters_out,
                          void* scratch, size_t scratch_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Allocation-free entry point, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of the library's static device scratch array (one per GPU, held until the process ends). */
+#define ALTGDMIN_STATIC_SCRATCH_BYTES (16u << 20)
+
+/* altgdmin_op_subspace without the scratch argument: its scratch (the
+ * altgdmin_op_scratch_bytes(n, q, r) bytes) is the library's static device
+ * array of ALTGDMIN_STATIC_SCRATCH_BYTES on the current GPU, so the call
+ * allocates nothing; results are those of altgdmin_op_subspace bit for bit.
+ * Sizes whose scratch exceeds the array are rejected (ALTGDMIN_ENOWS).  The
+ * array is shared by every call on that GPU and keeps the last call's contents
+ * (each call rewrites what it reads): calls that overlap on one GPU -- on
+ * different streams, or from host threads without ordering -- race and must
+ * be serialised by the caller.  Asynchronous on `stream`. */
+int altgdmin_op_subspace_noalloc(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start,
+                                 int32_t iters, double tol, float* U_out, int32_t* iters_out, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -98,6 +98,7 @@ _SIGS = {
     "altgdmin_op_grad": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_i32, c_vp, c_vp, c_sz, c_vp]),
     "altgdmin_op_qr_step": (c_i32, [c_vp, c_vp, c_i32, c_i32, c_f64, c_vp, c_vp, c_vp, c_sz, c_vp]),
     "altgdmin_op_subspace": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_f64, c_vp, c_vp, c_vp, c_sz, c_vp]),
+    "altgdmin_op_subspace_noalloc": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_vp, c_i32, c_f64, c_vp, c_vp, c_vp]),
     "altgdmin_op_rank_scratch_bytes": (c_i32, [c_i32, c_i32, c_i32, c_vp]),
     "altgdmin_op_rank": (c_i32, [c_vp, c_i32, c_i32, c_i32, c_f64, c_i32, c_vp, c_vp, c_vp, c_sz, c_vp]),
 }
@@ -492,6 +493,16 @@ def altgdmin_op_rank(L0t, m: int, energy: float, iters: int, r_out, sv_out=None,
         scratch = torch.empty(altgdmin_op_rank_scratch_bytes(n, q, m) + 256, dtype=torch.uint8, device="cuda")
     _check(_lib.altgdmin_op_rank(ptr(L0t), n, q, m, energy, iters, ptr(r_out), ptr(sv_out), ptr(scratch),
                                  scratch.numel(), stream_ptr(stream)))
+
+
+@_on_stream
+def altgdmin_op_subspace_noalloc(L0t, r: int, U_start, iters: int, tol: float, U_out, iters_out=None,
+                                 stream=None) -> None:
+    """altgdmin_op_subspace with the library's static device scratch (no allocation)."""
+    load()
+    q, n = L0t.shape
+    _check(_lib.altgdmin_op_subspace_noalloc(ptr(L0t), n, q, r, ptr(U_start), iters, tol, ptr(U_out),
+                                             ptr(iters_out), stream_ptr(stream)))
 
 
 # ------------------------------------------------------------------ convenience owner

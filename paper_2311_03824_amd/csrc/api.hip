@@ -1533,3 +1533,56 @@ int altgdmin_op_rank(const float* L0t, int32_t n, int32_t q, int32_t m, double e
 
 }  // extern "C"
 
+// ------------------------------------------------------------------ allocation-free entry point
+//
+// For callers that cannot allocate device memory (code under HIP graph capture,
+// tight serving loops, harnesses that forbid hipMalloc): the scratch of the
+// subspace iteration lives in this file-scope device array, one copy per GPU,
+// held until the process ends.  In host code `scratch` only names the symbol;
+// its device address is taken once per device with hipGetSymbolAddress and only
+// that address is handed to kernels and copies.
+
+static __device__ __align__(256) unsigned char scratch[ALTGDMIN_STATIC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on its first use there).
+int static_scratch(void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(ALTGDMIN_EINVAL, "device index beyond the static scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(ALTGDMIN_EHIP, "hipGetSymbolAddress returned no address for the static scratch");
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return ALTGDMIN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int altgdmin_op_subspace_noalloc(const float* L0t, int32_t n, int32_t q, int32_t r, const float* U_start,
+                                 int32_t iters, double tol, float* U_out, int32_t* iters_out, void* stream) {
+  int rc = subspace_args_ok(L0t, n, q, r, iters, U_out);
+  if (rc) return rc;
+  NEED_STREAM(stream);
+  const size_t need = op_scratch(nullptr, n, q, r).bytes;
+  if (need > ALTGDMIN_STATIC_SCRATCH_BYTES)
+    return fail(ALTGDMIN_ENOWS, "sizes need " + std::to_string(need) + " bytes of scratch, more than the " +
+                                    std::to_string((size_t)ALTGDMIN_STATIC_SCRATCH_BYTES) + " of the static array");
+  void* p = nullptr;
+  rc = static_scratch(&p);
+  if (rc) return rc;
+  return subspace_body(L0t, n, q, r, U_start, iters, tol, U_out, iters_out, p, ALTGDMIN_STATIC_SCRATCH_BYTES, stream);
+}
+
+}  // extern "C"

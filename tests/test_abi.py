@@ -204,6 +204,19 @@ def test_state_entry_points_validate_arguments(lib):
     assert so.altgdmin_set_state(None, 1 << 20, 1 << 20, 1 << 12) == -1
 
 
+def test_noalloc_entry_point_checks_sizes_and_stream_on_the_host(lib):
+    """Sizes whose scratch exceeds the static array are refused before any GPU call."""
+    so = lib.load()
+    fake = 1 << 30
+    b = ctypes.c_size_t(0)
+    assert so.altgdmin_op_scratch_bytes(300000, 1000, 16, ctypes.byref(b)) == 0
+    assert b.value > 16 << 20
+    assert so.altgdmin_op_subspace_noalloc(fake, 300000, 1000, 16, None, 5, 1e-7, fake, None, 1 << 12) == -2
+    assert "static" in so.altgdmin_last_error().decode()
+    assert so.altgdmin_op_subspace_noalloc(fake, 1000, 1000, 10, None, 5, 1e-7, fake, None, None) == -1
+    assert so.altgdmin_op_subspace_noalloc(fake, 1000, 1000, 17, None, 5, 1e-7, fake, None, 1 << 12) == -1
+
+
 def test_automatic_rank_problems(lib):
     """r = 0 asks for the automatic rank: the workspace is laid out for the largest rank
     the rule may pick; the Fourier form and K > 88 are not built; bad energies are refused."""
