@@ -233,7 +233,9 @@ int altgdmin_group_bytes(altgdmin_handle* const* hs, int32_t count, size_t* byte
  * columns of those problems; then one gradient-reduction launch and one
  * U-update launch with a workgroup per problem).  Each problem keeps its own
  * U/B/S state in its workspace and follows exactly the arithmetic of
- * altgdmin_step.  A problem whose params have tol_resid > 0 is frozen from the
+ * altgdmin_step (problems are also bucketed by their column-workgroup width, 8
+ * waves for q <= 320 and 4 above: the width sets the order of the kernels'
+ * cross-wave sums).  A problem whose params have tol_resid > 0 is frozen from the
  * iteration after its residual first reaches tol_resid: its kernels skip it, so
  * its state, report.iterations and report.resid stay those of the first
  * iteration that met the tolerance.  group_ws (device, 256-byte aligned,

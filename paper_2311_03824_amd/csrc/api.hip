@@ -186,6 +186,7 @@ struct altgdmin_handle {
   double* fpart = nullptr; // per-256-row-block partial Grams of the GD update
   double* frinv = nullptr; // R1^{-1}, R2^{-1} of the GD update
   void* rank_ws = nullptr; // r = 0 (automatic rank): scratch of the rank estimate
+  int col_waves = kWaves;  // waves of the column workgroup (a property of the problem, see choose_col_waves)
   int col_unroll = 0;      // autotuned JU of the column kernel (0: the default instantiation)
   int au_depth = 0;        // autotuned AUD of the A_k U kernel (0: the default instantiation)
   int colfmt = 0;          // format of the column kernel: fmt, or the mixed BF16 form
@@ -318,6 +319,29 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   return ALTGDMIN_OK;
 }
 
+// Waves of the column workgroup of a problem.  One workgroup per column cannot
+// fill the 256 CUs when q is small, and a CU then streams faster with more
+// waves in flight: 8 waves up to 320 columns, 4 above (at n = 1000, m = 400,
+// r = 10: k_col 31 % faster at q = 125 and 9 % at q = 250 in FP32, 45 % and 42 %
+// in the mixed BF16 form; equal at q = 500; 16 waves measured slower than 8 at
+// every q).  The width sets the order of the cross-wave sums, so it is fixed by
+// the problem, never by timing.  A width not built for m, or whose LDS does not
+// fit, falls back to the next narrower.  ALTGDMIN_COL_WAVES=4|8|16 forces a
+// width (measurements, tests).
+int choose_col_waves(const altgdmin_problem& p) {
+  int w = p.q <= 320 ? 8 : kWaves;
+  if (const char* f = std::getenv("ALTGDMIN_COL_WAVES")) {
+    const int v = std::atoi(f);
+    if (v == 4 || v == 8 || v == 16) w = v;
+  }
+  const int nc = (p.m + 255) / 256;
+  const int phx = p.a_format == ALTGDMIN_A_PHILOX;
+  if (phx) w = std::min(w, nc == 1 ? 16 : (nc == 2 ? 8 : kWaves));   // the generator's registers: wide only at small m
+  while (w > kWaves && (!col_wide_built(w, nc) || col_lds_bytes(p.n, p.m, r_eff(p), p.rho, 1, phx, w) > kMaxLds))
+    w /= 2;
+  return w;
+}
+
 ColArgs col_args(const altgdmin_handle* h) {
   const altgdmin_problem& p = h->prob;
   ColArgs a;
@@ -328,6 +352,7 @@ ColArgs col_args(const altgdmin_handle* h) {
   a.P = h->P; a.Ginv = h->Ginv; a.Tidx = h->Tidx; a.Tval = h->Tval;
   a.H = h->H; a.Bt = h->Bt; a.rr = h->colrr; a.flags = h->colflags;
   a.seed = p.a_seed; a.table = p.normal_table;
+  a.waves = h->col_waves;
   return a;
 }
 
@@ -347,7 +372,7 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
 // The column and A_k U launches of a solve, through the autotuned variant when
 // one was chosen for this problem's format.
 hipError_t col_launch(const altgdmin_handle* h, int fmt, const ColArgs& a, hipStream_t st) {
-  if (h->col_unroll && fmt == h->colfmt) return launch_col_tuned(fmt, h->col_unroll, a, st);
+  if (h->col_unroll && fmt == h->colfmt && a.waves == kWaves) return launch_col_tuned(fmt, h->col_unroll, a, st);
   return launch_col(fmt, a, st);
 }
 hipError_t au_launch(const altgdmin_handle* h, int fmt, const AUArgs& a, hipStream_t st) {
@@ -417,7 +442,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
         (aud != 1 && aud != 2 && aud != 4 && aud != 8))
       return fail(ALTGDMIN_EINVAL, "ALTGDMIN_TUNE_FORCE must be JU,AUD with JU, AUD in {1, 2, 4, 8}");
     if (ju == 8 && p.m > 512) ju = 4;   // JU = 8 is built for at most two row chunks
-    h->col_unroll = ju;
+    h->col_unroll = h->col_waves == kWaves ? ju : 0;   // the unrolls are built for 4-wave workgroups
     h->au_depth = aud;
     return ALTGDMIN_OK;
   }
@@ -470,7 +495,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     if (ms < best_au) { best_au = ms; best_aud = aud; }
   }
   for (int ju : {1, 2, 4, 8}) {
-    if (e != hipSuccess) break;
+    if (e != hipSuccess || h->col_waves != kWaves) break;   // the unrolls are built for 4-wave workgroups
     float ms = 0.f;
     e = timed([&] { return launch_col_tuned(h->colfmt, ju, ca, st); }, &ms);
     if (e == hipErrorNotSupported) {   // no such instantiation for this row count: not a candidate
@@ -627,6 +652,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->hi_phase = (h->fmt == FMT_BF16X2 && par->bf16_hi_max > 0);
   h->colfmt = (par->flags & ALTGDMIN_FLAG_BF16_MIXED) ? FMT_BF16MIX : h->fmt;
   h->auto_rank = prob->r == 0;
+  if (h->fmt != FMT_PFOURIER) h->col_waves = choose_col_waves(h->prob);
   const size_t need = carve(h, workspace);   // with r = 0, laid out for the largest rank the rule may pick
   const int r_cap = r_eff(h->prob);
   if (h->auto_rank) h->prob.r = r_cap;       // until the rank is chosen (the initialisation IHT does not use r)
@@ -1082,7 +1108,7 @@ namespace {
 // an instantiation (NC = ceil(m / 256) for the column kernel, R = r rounded up to
 // even for the A_k U kernel), so no problem runs a wider instantiation than its own.
 struct Bucket {
-  int fmt, inst;
+  int fmt, inst, waves = kWaves;
   std::vector<int2> map;
   size_t lds = 0, off = 0;
 };
@@ -1132,13 +1158,14 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     if (qa.lds) g.qr_lds = std::max(g.qr_lds, (size_t)p.n * p.r * sizeof(float));
     g.qr.push_back(qa);
     const int f = h->fmt, cf = h->colfmt, phx = f == FMT_PHILOX;
-    const int nc = (p.m + 255) / 256, rr = (p.r + 1) / 2 * 2;
+    const int nc = (p.m + 255) / 256, rr = (p.r + 1) / 2 * 2, cw = h->col_waves;
     Bucket& ab = g.au_b[f * 64 + rr];
-    Bucket& cb = g.col_b[cf * 64 + nc];
+    Bucket& cb = g.col_b[(cf * 64 + nc) * 32 + cw];   // problems batch with others of their column width
     ab.fmt = f;
     cb.fmt = cf;
     ab.inst = rr;
     cb.inst = nc;
+    cb.waves = cw;
     for (int k = 0; k < p.q; ++k) {
       ab.map.push_back(make_int2(i, k));
       cb.map.push_back(make_int2(i, k));
@@ -1146,7 +1173,7 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     for (int jb = 0; jb < (p.n + 63) / 64; ++jb)
       for (int ks = 0; ks < h->KS; ++ks) g.grad_map.push_back(make_int4(i, jb, ks, 0));
     ab.lds = std::max(ab.lds, AULayout(p.m, p.r, phx).total);
-    cb.lds = std::max(cb.lds, ColLayout(p.n, p.m, p.r, p.rho, 1, phx).total);
+    cb.lds = std::max(cb.lds, ColLayout(p.n, p.m, p.r, p.rho, 1, phx, cw).total);
   }
   size_t o = 0;
   auto take = [&](size_t bytes) { o = (o + kAlign - 1) / kAlign * kAlign; size_t r = o; o += bytes; return r; };
@@ -1246,8 +1273,8 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
     }
     for (const auto& kv : g.col_b) {
       const Bucket& b = kv.second;
-      HIPCHK(launch_col_grp(b.fmt, b.inst, col_tab, reinterpret_cast<const int2*>(dev + b.off), (int)b.map.size(),
-                            b.lds, st));
+      HIPCHK(launch_col_grp(b.fmt, b.inst, b.waves, col_tab, reinterpret_cast<const int2*>(dev + b.off),
+                            (int)b.map.size(), b.lds, st));
     }
     HIPCHK(launch_grad_grp(grad_tab, reinterpret_cast<const int4*>(dev + g.o_gm), (int)g.grad_map.size(), st));
     HIPCHK(launch_qr_grp(qr_tab, count, g.qr_lds, st));
@@ -1293,6 +1320,7 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
 
 static int op_col(const altgdmin_problem* prob, ColArgs& a, void* stream) {
   NEED_STREAM(stream);
+  a.waves = choose_col_waves(*prob);   // the width the solver takes for this problem
   a.n = prob->n; a.q = prob->q; a.m = prob->m; a.r = prob->r; a.rho = prob->rho;
   a.seed = prob->a_seed; a.table = prob->normal_table;
   a.A = prob->A; a.Alo = prob->A_lo; a.lda = prob->lda; a.sA = prob->a_stride_k;

@@ -66,6 +66,7 @@ struct ColArgs {
   int gate_want;
   unsigned long long seed;  // Philox form: key of A
   const float* table;       // Philox form: normal table (kNormalTable FP32)
+  int waves;                // waves of the column workgroup: 4 (also for 0), 8 or 16
 };
 
 struct AUArgs {
@@ -362,19 +363,20 @@ constexpr size_t kPInLdsMax = 32 * 1024;   // P_k is staged in LDS up to this si
 struct ColLayout {
   size_t ginv, P, wpart, g, sd, inT, Ti, Tv, red, hist, cbuf, tab, total;
   int mq, p_in_lds;
-  __host__ __device__ ColLayout(int n, int m, int r, int rho, int project, int philox = 0) {
+  // waves: waves of the column workgroup (its per-wave partial vectors and sums)
+  __host__ __device__ ColLayout(int n, int m, int r, int rho, int project, int philox = 0, int waves = kWaves) {
     mq = ((m + 3) / 4) * 4;
     p_in_lds = 4 * (size_t)m * r <= kPInLdsMax;
     size_t o = 0;
     ginv = o; o = align16(o + (project ? 8 * (size_t)r * r : 0));
     P = o;    o = align16(o + (project && p_in_lds ? 4 * (size_t)m * r : 0));
-    wpart = o; o = align16(o + 4 * (size_t)kWaves * mq);
+    wpart = o; o = align16(o + 4 * (size_t)waves * mq);
     g = o;    o = align16(o + 4 * (size_t)n);
     sd = o;   o = align16(o + 4 * (size_t)n);
     inT = o;  o = align16(o + 4 * (size_t)((n + 31) / 32));
     Ti = o;   o = align16(o + 4 * (size_t)rho);
     Tv = o;   o = align16(o + 4 * (size_t)rho);
-    red = o;  o = align16(o + 8 * 2 * kWaves);
+    red = o;  o = align16(o + 8 * 2 * (size_t)waves);
     hist = o; o = align16(o + 4 * (256 + 8));
     cbuf = o; o = align16(o + 8 * kRMax);
     tab = o;  o = align16(o + (philox ? 4 * (size_t)kNormalTable : 0));

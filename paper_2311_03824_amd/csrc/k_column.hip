@@ -1,9 +1,12 @@
 // Column kernels of AltGDmin-LR+S for gfx950.
 //
-// One workgroup (4 waves) owns one column k and streams its A_k (m x n,
-// column-major, row index fastest) with coalesced 16-byte loads.  Lane l of
-// every wave holds rows 4*(l + 64c) .. +3 for c < NC, so a column j of A_k is
-// read by one wave as NC contiguous 1 KiB segments.
+// One workgroup owns one column k and streams its A_k (m x n, column-major, row
+// index fastest) with coalesced 16-byte loads.  Lane l of every wave holds rows
+// 4*(l + 64c) .. +3 for c < NC, so a column j of A_k is read by one wave as NC
+// contiguous 1 KiB segments.  The column kernel comes in workgroups of W = 4, 8
+// or 16 waves: the wave count sets the order of the cross-wave sums (and so the
+// bits), so it is a property of the problem; problems with few columns, whose
+// workgroups cannot fill the chip, take the wider ones.
 //
 //  k_au  : P_k = A_k U (m x r), G_k = P_k^T P_k in FP64, G_k^{-1} by Cholesky
 //          (the pieces of (A_k U)^dagger, eq. (bk_LS)).  U is read with
@@ -47,7 +50,7 @@ struct Lane {
 
 // Sum the per-wave partial vectors of all waves (fixed order 0..W-1); every
 // wave ends with the same total.  Two barriers.
-template <int NC>
+template <int NC, int W = kWaves>
 __device__ __forceinline__ void xwave_sum(float4 (&v)[NC], const Lane<NC>& ln, float* wpart, int mq,
                                           int wave) {
 #pragma unroll
@@ -59,19 +62,20 @@ __device__ __forceinline__ void xwave_sum(float4 (&v)[NC], const Lane<NC>& ln, f
     if (ln.nv[c] > 0) {
       float4 s = *reinterpret_cast<const float4*>(wpart + 4 * ln.ch[c]);
 #pragma unroll
-      for (int w = 1; w < kWaves; ++w) s = add4(s, *reinterpret_cast<const float4*>(wpart + w * mq + 4 * ln.ch[c]));
+      for (int w = 1; w < W; ++w) s = add4(s, *reinterpret_cast<const float4*>(wpart + w * mq + 4 * ln.ch[c]));
       v[c] = s;
     }
   }
   __syncthreads();
 }
 
+template <int W = kWaves>
 __device__ __forceinline__ double xwave_sum_scalar(double x, double* redd, int lane, int wave) {
   if (lane == 0) redd[wave] = x;
   __syncthreads();
   double s = redd[0];
 #pragma unroll
-  for (int w = 1; w < kWaves; ++w) s += redd[w];
+  for (int w = 1; w < W; ++w) s += redd[w];
   __syncthreads();
   return s;
 }
@@ -79,7 +83,7 @@ __device__ __forceinline__ double xwave_sum_scalar(double x, double* redd, int l
 // out = sum_{t < cnt} coef[t] * A_k[:, idx[t]]  (idx, coef in LDS), all waves get the total.
 // Each wave keeps up to 8 support columns in flight when A_k has at most 256 rows
 // (4 otherwise, and in the Philox form, where they are generated, not loaded).
-template <int FMT, int NC>
+template <int FMT, int NC, int W = kWaves>
 __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln, const int* idx,
                                        const float* coef, int cnt, float4 (&out)[NC], float* wpart,
                                        int mq, int wave) {
@@ -87,14 +91,14 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
   float4 acc[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) acc[c] = make_float4(0.f, 0.f, 0.f, 0.f);
-  for (int t0 = wave; t0 < cnt; t0 += kWaves * GU) {
+  for (int t0 = wave; t0 < cnt; t0 += W * GU) {
     // every load is issued before any is used: clamped, always legal addresses,
     // invalid rows and slots are zeroed afterwards
     typename ALoader<FMT>::raw_t av[GU][NC];
     float cf[GU];
 #pragma unroll
     for (int g = 0; g < GU; ++g) {
-      const int t = t0 + g * kWaves;
+      const int t = t0 + g * W;
       const int j = idx[t < cnt ? t : t0];
       cf[g] = t < cnt ? coef[t] : 0.f;
 #pragma unroll
@@ -102,13 +106,13 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
     }
 #pragma unroll
     for (int g = 0; g < GU; ++g) {
-      const bool ok = t0 + g * kWaves < cnt;
+      const bool ok = t0 + g * W < cnt;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
         acc[c] = axpy4(cf[g], mask_rows(ALoader<FMT>::expand(av[g][c]), ok ? ln.nv[c] : 0), acc[c]);
     }
   }
-  xwave_sum<NC>(acc, ln, wpart, mq, wave);
+  xwave_sum<NC, W>(acc, ln, wpart, mq, wave);
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[c] = acc[c];
 }
@@ -118,11 +122,11 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
 // (LDS, r doubles); every wave then applies the same d to its own copy of v.
 // If bl != nullptr, lane i < r receives b_i = -d_i (the LS coefficients when
 // v = A_k s_k - y_k).  One barrier; cbuf may be rewritten only after another.
-template <int NC>
+template <int NC, int W = kWaves>
 __device__ __forceinline__ void project(float4 (&v)[NC], const Lane<NC>& ln, const float* Pl,
                                         const double* Gi, int r, int lane, int wave, double* cbuf,
                                         double* bl) {
-  for (int rr = wave; rr < r; rr += kWaves) {
+  for (int rr = wave; rr < r; rr += W) {
     double part = 0.0;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -235,33 +239,37 @@ __device__ __forceinline__ float col_totals(const float (&x)[JU], int lane) {
 
 // Streaming pass over A_k: gl[j] = A_j^T u for every column j; for j in the
 // support bitmap inT (if given) also wacc += gl[j] * A_j and gT2 += gl[j]^2.
-// Wave w takes columns j = w, w + 4, ...; groups of JU columns are loaded one
+// Wave w takes columns j = w, w + W, ...; groups of JU columns are loaded one
 // group ahead of the one being reduced, and reduced together (col_totals).
 // u must be zero on rows >= m (and A finite there): the products are then not
 // masked.  The order in which a wave visits the columns and every column's
 // reduction tree do not depend on JU, so every JU gives the same bits.
-// default loads in flight (autotuned variants pass another JU)
-constexpr int default_ju(int nc) { return nc == 1 ? 4 : 2; }
+// default loads in flight (autotuned variants pass another JU); wider workgroups
+// have more waves in flight and take fewer columns per group
+constexpr int default_ju(int nc, int w = kWaves) { return w >= 16 ? (nc == 1 ? 2 : 1) : (nc == 1 ? 4 : 2); }
 
-template <int FMT, int NC, int JU>
+template <int FMT, int NC, int JU, int W = kWaves>
 __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
                                            int n, float* gl, const unsigned* inT, float4 (&wacc)[NC],
                                            double& gT2, int lane, int wave) {
-  constexpr int step = kWaves * JU;
+  // the support bits of a group's columns j0, j0 + W, ... must lie in the two
+  // bitmap words read per group
+  static_assert((JU - 1) * W <= 32, "a group's support bits span more than two bitmap words");
+  constexpr int step = W * JU;
   // loads are unconditional (column clamped to n-1, chunk clamped to a legal
   // one) so that a whole group is in flight at once; consume() drops them
   typedef typename ALoader<FMT>::raw_t raw_t;
   auto load = [&](int j0, raw_t (&ar)[JU][NC]) {
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
-      const int j = j0 + ju * kWaves;
+      const int j = j0 + ju * W;
       const int jc = j < n ? j : n - 1;
 #pragma unroll
       for (int c = 0; c < NC; ++c) ar[ju][c] = L.fetch(jc, ln.chc[c]);
     }
   };
   auto consume = [&](int j0, const raw_t (&ar)[JU][NC]) {
-    // support bits of columns j0 .. j0 + 4 (JU - 1) (at most 60 bits from
+    // support bits of columns j0 .. j0 + W (JU - 1) (at most 63 bits from
     // j0 - j0 % 32): two bitmap words, read before the reduction hides their latency
     unsigned long long tb = 0ull;
     if (inT) {
@@ -284,13 +292,13 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
       d[ju] = s;
     }
     const float tot = col_totals<JU>(d, lane);
-    const int jl = j0 + lane * kWaves;
+    const int jl = j0 + lane * W;
     if (lane < JU && jl < n) gl[jl] = tot;
     if (inT) {
 #pragma unroll
       for (int ju = 0; ju < JU; ++ju) {
-        const int j = j0 + ju * kWaves;
-        if (j < n && ((tb >> (kWaves * ju)) & 1ull)) {
+        const int j = j0 + ju * W;
+        if (j < n && ((tb >> (W * ju)) & 1ull)) {
           const float dj = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tot), ju));
 #pragma unroll
           for (int c = 0; c < NC; ++c) wacc[c] = axpy4(dj, mask_rows(av[ju][c], ln.nv[c]), wacc[c]);
@@ -324,7 +332,9 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
 // magnitude bits (monotone in |v|), one byte per round from the top, with a
 // 256-bin LDS histogram; ties at T are then resolved in index order by one
 // wave.  hist: 256 + 8 ints of LDS.  Returns the number of NaNs (block-uniform).
+template <int W = kWaves>
 static __device__ int block_select(const float* vals, int n, int rho, int* idx, float* val, int* hist) {
+  constexpr int T = 64 * W;   // threads of the workgroup
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   if (rho <= 0) return 0;
   int* ctl = hist + 256;   // [0] digit, [1] rank left, [2] NaN count
@@ -332,11 +342,11 @@ static __device__ int block_select(const float* vals, int n, int rho, int* idx, 
   int remaining = rho;
   for (int d = 3; d >= 0; --d) {
     const int shift = 8 * d;
-    for (int b = tid; b < 256; b += kThreads) hist[b] = 0;
+    for (int b = tid; b < 256; b += T) hist[b] = 0;
     if (d == 3 && tid == 0) ctl[2] = 0;
     __syncthreads();
     int nanc = 0;
-    for (int j = tid; j < n; j += kThreads) {
+    for (int j = tid; j < n; j += T) {
       const unsigned key = __float_as_uint(vals[j]) & 0x7fffffffu;
       if (d == 3) nanc += key > 0x7f800000u ? 1 : 0;
       if ((key & pmask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1);
@@ -368,7 +378,7 @@ static __device__ int block_select(const float* vals, int n, int rho, int* idx, 
     prefix |= (unsigned)ctl[0] << shift;
     pmask |= 255u << shift;
   }
-  const unsigned T = prefix;
+  const unsigned thr = prefix;
   const int need_eq = remaining;
   if (wave == 0) {
     const unsigned long long lt = (1ull << lane) - 1ull;
@@ -378,8 +388,8 @@ static __device__ int block_select(const float* vals, int n, int rho, int* idx, 
       const bool valid = j < n;
       const float x = valid ? vals[j] : 0.f;
       const unsigned key = __float_as_uint(x) & 0x7fffffffu;
-      const bool eq = valid && key == T;
-      const bool gtb = valid && key > T;
+      const bool eq = valid && key == thr;
+      const bool gtb = valid && key > thr;
       const unsigned long long meq = __ballot(eq);
       const int eq_rank = base_eq + __popcll(meq & lt);
       const bool sel = gtb || (eq && eq_rank < need_eq);
@@ -399,13 +409,14 @@ static __device__ int block_select(const float* vals, int n, int rho, int* idx, 
 
 // Whether HardThreshold of vals[0..n) keeps the support marked in the bitmap
 // inT: it does when every magnitude on it is larger than every magnitude off it
-// (with a tie or a NaN the full select decides).  slot: 2 kWaves words of LDS;
+// (with a tie or a NaN the full select decides).  slot: 2 W words of LDS;
 // barriers inside, the last one after the slot is read.
+template <int W = kWaves>
 static __device__ bool block_support_kept(const float* vals, int n, const unsigned* inT, unsigned* slot) {
   const int lane = threadIdx.x & 63, wave = wave_id();
   unsigned kmin = 0xffffffffu, kmax = 0u;
   bool bad = false;
-  for (int j = threadIdx.x; j < n; j += kThreads) {
+  for (int j = threadIdx.x; j < n; j += 64 * W) {
     const unsigned key = __float_as_uint(vals[j]) & 0x7fffffffu;
     bad |= key > 0x7f800000u;
     if ((inT[j >> 5] >> (j & 31)) & 1u)
@@ -426,7 +437,7 @@ static __device__ bool block_support_kept(const float* vals, int n, const unsign
   __syncthreads();
   unsigned mn = 0xffffffffu, mx = 0u;
 #pragma unroll
-  for (int w = 0; w < kWaves; ++w) {
+  for (int w = 0; w < W; ++w) {
     mn = min(mn, slot[2 * w]);
     mx = max(mx, slot[2 * w + 1]);
   }
@@ -436,11 +447,12 @@ static __device__ bool block_support_kept(const float* vals, int n, const unsign
 
 // ---------------------------------------------------------------- k_col
 
-template <int FMT, int NC, int JU>
+template <int FMT, int NC, int JU, int W>
 __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char* smem) {
+  constexpr int kT = 64 * W;   // threads of the workgroup
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r, rho = a.rho;
-  const ColLayout lay(n, m, r, rho, a.project, FMT == FMT_PHILOX);
+  const ColLayout lay(n, m, r, rho, a.project, FMT == FMT_PHILOX, W);
   double* Gi = reinterpret_cast<double*>(smem + lay.ginv);
   // P_k in LDS when it fits, else read from the workspace copy in global memory
   float* Pl = lay.p_in_lds ? reinterpret_cast<float*>(smem + lay.P) : const_cast<float*>(a.P + (long long)k * m * r);
@@ -461,7 +473,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   ALoader<SF> Ls(a, k);   // A_k^T u and the step length: the streaming view
   if constexpr (FMT == FMT_PHILOX) {
     float* tab = reinterpret_cast<float*>(smem + lay.tab);
-    for (int t = tid; t < kNormalTable; t += kThreads) tab[t] = a.table[t];
+    for (int t = tid; t < kNormalTable; t += kT) tab[t] = a.table[t];
     L.tab = tab;   // read only after the barrier that ends the LDS set-up below
     Ls.tab = tab;
   }
@@ -479,14 +491,14 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     }
   }
 
-  for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
-  for (int w = tid; w < nwords; w += kThreads) inT[w] = 0u;
+  for (int j = tid; j < n; j += kT) sd[j] = 0.f;
+  for (int w = tid; w < nwords; w += kT) inT[w] = 0u;
   if (a.project) {
     const float* Pk = a.P + (long long)k * m * r;
     if (lay.p_in_lds)
-      for (int t = tid; t < m * r; t += kThreads) Pl[t] = Pk[t];
+      for (int t = tid; t < m * r; t += kT) Pl[t] = Pk[t];
     const double* Gk = a.Ginv + (long long)k * r * r;
-    for (int t = tid; t < r * r; t += kThreads) Gi[t] = Gk[t];
+    for (int t = tid; t < r * r; t += kT) Gi[t] = Gk[t];
   }
   __syncthreads();
   // A start support must hold rho distinct in-range indices in ascending order
@@ -494,7 +506,7 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   // state: the column is flagged (bit 2) and starts from s = 0 with no support.
   int nz = 0, bad = 0;
   if (a.has_support) {
-    for (int t = tid; t < rho; t += kThreads) {
+    for (int t = tid; t < rho; t += kT) {
       const int j = a.Tidx[(long long)k * rho + t];
       const int jp = t > 0 ? a.Tidx[(long long)k * rho + t - 1] : -1;
       const float v = a.Tval[(long long)k * rho + t];
@@ -505,18 +517,18 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     }
   }
   // one reduction tells both whether some start value is nonzero and whether the
-  // start is invalid (weights 1 and 64 per wave, at most kWaves waves)
-  const double vote = xwave_sum_scalar((__ballot(nz != 0) != 0ull ? 1.0 : 0.0) + (__ballot(bad != 0) != 0ull ? 64.0 : 0.0),
+  // start is invalid (weights 1 and 64 per wave, at most 16 waves)
+  const double vote = xwave_sum_scalar<W>((__ballot(nz != 0) != 0ull ? 1.0 : 0.0) + (__ballot(bad != 0) != 0ull ? 64.0 : 0.0),
                                        redd, lane, wave);
   const bool invalid = vote >= 64.0;
   if (a.has_support && !invalid) {
-    for (int t = tid; t < rho; t += kThreads) {   // each thread reads back only its own entries
+    for (int t = tid; t < rho; t += kT) {   // each thread reads back only its own entries
       const int j = Ti[t];
       sd[j] = Tv[t];
       atomicOr(&inT[j >> 5], 1u << (j & 31));
     }
   } else {
-    for (int t = tid; t < rho; t += kThreads) {   // s = 0 on the support 0 .. rho - 1 (kept if tau = 0)
+    for (int t = tid; t < rho; t += kT) {   // s = 0 on the support 0 .. rho - 1 (kept if tau = 0)
       Ti[t] = t;
       Tv[t] = 0.f;
     }
@@ -530,51 +542,51 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   for (int it = 0; it < a.tau; ++it) {
     // u = Pi (A_k s - y_k)   (Pi = I in the initialisation)
     float4 v[NC];
-    gather<GF, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
+    gather<GF, NC, W>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);
-    if (a.project) project<NC>(v, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
+    if (a.project) project<NC, W>(v, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
 
     // g = A_k^T u; w = A_k g_T on the current support
     float4 w[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) w[c] = make_float4(0.f, 0.f, 0.f, 0.f);
     double gT2 = 0.0;
-    fused_pass<SF, NC, JU>(Ls, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
+    fused_pass<SF, NC, JU, W>(Ls, ln, v, n, gl, hasT ? inT : nullptr, w, gT2, lane, wave);
     __syncthreads();
     if (hasT) {
-      xwave_sum<NC>(w, ln, wpart, mq, wave);
-      gT2 = xwave_sum_scalar(gT2, redd, lane, wave);
+      xwave_sum<NC, W>(w, ln, wpart, mq, wave);
+      gT2 = xwave_sum_scalar<W>(gT2, redd, lane, wave);
     } else {
       // no support yet (s = 0): restrict to the support of HardThreshold(g, rho)
-      nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
-      gather<SF, NC>(Ls, ln, Ti, Tv, rho, w, wpart, mq, wave);
+      nan_seen += block_select<W>(gl, n, rho, Ti, Tv, hist);
+      gather<SF, NC, W>(Ls, ln, Ti, Tv, rho, w, wpart, mq, wave);
       gT2 = 0.0;
       for (int t = 0; t < rho; ++t) gT2 = fma((double)Tv[t], (double)Tv[t], gT2);
     }
-    if (a.project) project<NC>(w, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
+    if (a.project) project<NC, W>(w, ln, Pl, Gi, r, lane, wave, cbuf, nullptr);
     const double ww = sumsq<NC>(w);
     const double mu = (ww > 0.0 && isfinite(ww) && isfinite(gT2)) ? gT2 / ww : 0.0;
     const bool last = (it == a.tau - 1);
     if (last && a.G_out)
-      for (int j = tid; j < n; j += kThreads) a.G_out[(long long)k * n + j] = gl[j];
+      for (int j = tid; j < n; j += kT) a.G_out[(long long)k * n + j] = gl[j];
     if (last && a.mu_out && tid == 0) a.mu_out[k] = mu;
     // s - mu g, then HardThreshold
-    for (int j = tid; j < n; j += kThreads) gl[j] = (float)fma(-mu, (double)gl[j], (double)sd[j]);
+    for (int j = tid; j < n; j += kT) gl[j] = (float)fma(-mu, (double)gl[j], (double)sd[j]);
     __syncthreads();
-    if (hasT && block_support_kept(gl, n, inT, reinterpret_cast<unsigned*>(hist))) {
+    if (hasT && block_support_kept<W>(gl, n, inT, reinterpret_cast<unsigned*>(hist))) {
       // most steps keep T: Ti (ascending) and inT stand, s takes the new values on T
-      for (int t = tid; t < rho; t += kThreads) {
+      for (int t = tid; t < rho; t += kT) {
         const int j = Ti[t];
         Tv[t] = gl[j];
         sd[j] = gl[j];
       }
     } else {
-      nan_seen += block_select(gl, n, rho, Ti, Tv, hist);
-      for (int j = tid; j < n; j += kThreads) sd[j] = 0.f;
-      for (int wd = tid; wd < nwords; wd += kThreads) inT[wd] = 0u;
+      nan_seen += block_select<W>(gl, n, rho, Ti, Tv, hist);
+      for (int j = tid; j < n; j += kT) sd[j] = 0.f;
+      for (int wd = tid; wd < nwords; wd += kT) inT[wd] = 0u;
       __syncthreads();
-      for (int t = tid; t < rho; t += kThreads) {
+      for (int t = tid; t < rho; t += kT) {
         const int j = Ti[t];
         sd[j] = Tv[t];
         atomicOr(&inT[j >> 5], 1u << (j & 31));
@@ -586,13 +598,13 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
 
   if (a.tail != TAIL_NONE) {
     float4 v[NC];
-    gather<GF, NC>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
+    gather<GF, NC, W>(L, ln, Ti, Tv, hasT ? rho : 0, v, wpart, mq, wave);
 #pragma unroll
     for (int c = 0; c < NC; ++c) v[c] = sub4(v[c], yv[c]);   // A_k s_k - y_k
     if (a.tail == TAIL_LSGRAD) {
       // b_k = G^{-1} P^T (y - A s); r_k = P b + A s - y = Pi (A s - y)
       double b = 0.0;
-      project<NC>(v, ln, Pl, Gi, r, lane, wave, cbuf, &b);
+      project<NC, W>(v, ln, Pl, Gi, r, lane, wave, cbuf, &b);
       const double rr = sumsq<NC>(v);
       if (wave == 0 && lane < r) a.Bt[(long long)k * r + lane] = (float)b;
       if (tid == 0 && a.rr) a.rr[k] = rr;
@@ -604,12 +616,12 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
     }
     float4 w[NC];
     double dummy = 0.0;
-    fused_pass<SF, NC, JU>(Ls, ln, v, n, gl, nullptr, w, dummy, lane, wave);
+    fused_pass<SF, NC, JU, W>(Ls, ln, v, n, gl, nullptr, w, dummy, lane, wave);
     __syncthreads();
-    for (int j = tid; j < n; j += kThreads) a.H[(long long)k * n + j] = gl[j];
+    for (int j = tid; j < n; j += kT) a.H[(long long)k * n + j] = gl[j];
   }
 
-  for (int t = tid; t < rho; t += kThreads) {
+  for (int t = tid; t < rho; t += kT) {
     a.Tidx[(long long)k * rho + t] = Ti[t];
     a.Tval[(long long)k * rho + t] = Tv[t];
   }
@@ -628,22 +640,27 @@ constexpr int col_min_waves(int fmt, int nc, int ju) {
   return ju == 4 ? 1 : 2;
 }
 
-template <int FMT, int NC, int JU = default_ju(NC)>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(col_min_waves(FMT, NC, JU), 8))) void k_col(ColArgs a) {
+// Wider workgroups: W / 4 waves per SIMD at least (the workgroup must fit).
+constexpr int col_min_waves_w(int fmt, int nc, int ju, int w) {
+  return col_min_waves(fmt, nc, ju) > w / 4 ? col_min_waves(fmt, nc, ju) : w / 4;
+}
+
+template <int FMT, int NC, int JU = default_ju(NC), int W = kWaves>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_waves_w(FMT, NC, JU, W), 8))) void k_col(ColArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  col_body<FMT, NC, JU>(a, blockIdx.x, smem);
+  col_body<FMT, NC, JU, W>(a, blockIdx.x, smem);
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
-template <int FMT, int NC>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(col_min_waves(FMT, NC, default_ju(NC)), 8))) void k_col_grp(
+template <int FMT, int NC, int W = kWaves>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_waves_w(FMT, NC, default_ju(NC, W), W), 8))) void k_col_grp(
     const ColArgs* tab, const int2* map) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const ColArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  col_body<FMT, NC, default_ju(NC)>(a, mp.y, smem);
+  col_body<FMT, NC, default_ju(NC, W), W>(a, mp.y, smem);
 }
 
 // ---------------------------------------------------------------- k_au
@@ -921,6 +938,8 @@ bool au_supported(int m, int r) { return m >= 1 && m <= 256 * kNCMax && r >= 1 &
 
 hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX) return hipErrorInvalidValue;
+  if (a.waves == 8 || a.waves == 16) return launch_col_wide(fmt, a, st);
+  if (a.waves != 0 && a.waves != kWaves) return hipErrorInvalidValue;
   const int nc = (a.m + 255) / 256;
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
@@ -937,8 +956,11 @@ hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_col_grp(int fmt, int nc, const ColArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st) {
+hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks, size_t lds,
+                          hipStream_t st) {
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX) return hipErrorInvalidValue;
+  if (waves == 8 || waves == 16) return launch_col_grp_wide(fmt, nc, waves, tab, map, blocks, lds, st);
+  if (waves != kWaves) return hipErrorInvalidValue;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColGrpTable[fmt][nc - 1], dim3(blocks), dim3(kThreads), lds, st, tab, map);
   return hipGetLastError();
@@ -952,8 +974,8 @@ hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, 
   return hipGetLastError();
 }
 
-size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox) {
-  return ColLayout(n, m, r, rho, project, philox).total;
+size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox, int waves) {
+  return ColLayout(n, m, r, rho, project, philox, waves).total;
 }
 size_t au_lds_bytes(int m, int r, int philox) { return AULayout(m, r, philox).total; }
 
@@ -1011,6 +1033,45 @@ static int tuned_slot(int v, const int (&vals)[4]) {
   for (int i = 0; i < 4; ++i)
     if (vals[i] == v) return i;
   return -1;
+}
+
+// Wide column workgroups (8 and 16 waves) with the default loads in flight of
+// their width; 16 waves are built for at most two row chunks (m <= 512).
+#define COLW_F(F, W) {k_col<F, 1, default_ju(1, W), W>, k_col<F, 2, default_ju(2, W), W>, \
+                      k_col<F, 3, default_ju(3, W), W>, k_col<F, 4, default_ju(4, W), W>}
+#define COLW16_F(F) {k_col<F, 1, default_ju(1, 16), 16>, k_col<F, 2, default_ju(2, 16), 16>, nullptr, nullptr}
+static const col_fn2 kColWide[2][5][kNCMax] = {
+    {COLW_F(FMT_F32, 8), COLW_F(FMT_BF16X2, 8), COLW_F(FMT_BF16HI, 8), COLW_F(FMT_PHILOX, 8), COLW_F(FMT_BF16MIX, 8)},
+    {COLW16_F(FMT_F32), COLW16_F(FMT_BF16X2), COLW16_F(FMT_BF16HI), COLW16_F(FMT_PHILOX), COLW16_F(FMT_BF16MIX)}};
+typedef void (*colg_fn2)(const ColArgs*, const int2*);
+#define COLGW_F(F, W) {k_col_grp<F, 1, W>, k_col_grp<F, 2, W>, k_col_grp<F, 3, W>, k_col_grp<F, 4, W>}
+#define COLGW16_F(F) {k_col_grp<F, 1, 16>, k_col_grp<F, 2, 16>, nullptr, nullptr}
+static const colg_fn2 kColGrpWide[2][5][kNCMax] = {
+    {COLGW_F(FMT_F32, 8), COLGW_F(FMT_BF16X2, 8), COLGW_F(FMT_BF16HI, 8), COLGW_F(FMT_PHILOX, 8),
+     COLGW_F(FMT_BF16MIX, 8)},
+    {COLGW16_F(FMT_F32), COLGW16_F(FMT_BF16X2), COLGW16_F(FMT_BF16HI), COLGW16_F(FMT_PHILOX), COLGW16_F(FMT_BF16MIX)}};
+
+bool col_wide_built(int waves, int nc) { return waves == 8 || (waves == 16 && nc <= 2); }
+
+hipError_t launch_col_wide(int fmt, const ColArgs& a, hipStream_t st) {
+  const int nc = (a.m + 255) / 256;
+  const int wi = a.waves == 16 ? 1 : 0;
+  if (fmt < FMT_F32 || fmt > FMT_BF16MIX || nc < 1 || nc > kNCMax || !kColWide[wi][fmt][nc - 1])
+    return hipErrorNotSupported;
+  const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, fmt == FMT_PHILOX, a.waves);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColWide[wi][fmt][nc - 1], dim3(a.q), dim3(64 * a.waves), lay.total, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_grp_wide(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
+                               size_t lds, hipStream_t st) {
+  const int wi = waves == 16 ? 1 : 0;
+  if (fmt < FMT_F32 || fmt > FMT_BF16MIX || nc < 1 || nc > kNCMax || !kColGrpWide[wi][fmt][nc - 1])
+    return hipErrorNotSupported;
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColGrpWide[wi][fmt][nc - 1], dim3(blocks), dim3(64 * waves), lds, st, tab, map);
+  return hipGetLastError();
 }
 
 hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {

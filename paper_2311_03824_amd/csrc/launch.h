@@ -45,9 +45,15 @@ hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st);
 hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st);
 hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
 bool au_supported(int m, int r);
-hipError_t launch_col_grp(int fmt, int nc, const ColArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks, size_t lds,
+                          hipStream_t st);
+// column workgroups of 8 or 16 waves (a.waves); built for 8 waves, and 16 waves at m <= 512
+bool col_wide_built(int waves, int nc);
+hipError_t launch_col_wide(int fmt, const ColArgs& a, hipStream_t st);
+hipError_t launch_col_grp_wide(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
+                               size_t lds, hipStream_t st);
 hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st);
-size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox);
+size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox, int waves = kWaves);
 size_t au_lds_bytes(int m, int r, int philox);
 hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,
                               hipStream_t st);

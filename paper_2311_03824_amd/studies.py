@@ -3,7 +3,8 @@
 Every cell solves `runs` seeded instances with the HIP library and reports the
 error ||X - X*||_F / ||X*||_F of the consistent pair (U, B, S) after T_max GDmin
 iterations: its mean (the statistic the paper plots and tabulates), its median,
-its largest value, and the fraction of runs below 1e-10 (exact recovery).
+its largest value, and the fractions of runs below 1e-6 (the FP32 floor of the
+GPU path: exact recovery in single precision) and below 1e-10.
 
   * Fig. 1: Gaussian A_k, n = q = 600, m = 80, r = 4, rho in {2, 5, 6, 7},
     threshold budget rho_max = 7, S1 values U[-6, 6], T_max = 200.
@@ -45,7 +46,8 @@ SEED = 231103900
 def _summary(errs: Sequence[float]) -> dict:
     e = np.asarray(errs, dtype=np.float64)
     return {"runs": int(e.size), "mean_error": float(e.mean()), "median_error": float(np.median(e)),
-            "max_error": float(e.max()), "fraction_below_1e-10": float(np.mean(e < 1e-10))}
+            "max_error": float(e.max()), "fraction_below_1e-6": float(np.mean(e < 1e-6)),
+            "fraction_below_1e-10": float(np.mean(e < 1e-10))}
 
 
 def gaussian_case(lib, torch, n: int, q: int, m: int, r: int, rho: int, rho_budget: int, s_dist: str,

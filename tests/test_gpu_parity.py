@@ -440,6 +440,25 @@ def test_solve_matches_oracle(lib, torch, shape, iters):
     assert abs(out["status"]["eta"] - st.eta) <= 1e-3 * st.eta
 
 
+@pytest.mark.parametrize("waves", ["4", "8", "16"])
+@pytest.mark.parametrize("shape,iters", [(dict(n=301, q=64, m=150, r=3, rho=7), 60),
+                                         (dict(n=400, q=40, m=300, r=3, rho=8), 40)])   # two row chunks
+def test_every_column_width_matches_oracle(lib, torch, monkeypatch, waves, shape, iters):
+    """Column workgroups of 4, 8 and 16 waves (the width a problem takes is set by
+    its q; forced here): each solve matches the oracle, FP32 and mixed BF16."""
+    monkeypatch.setenv("ALTGDMIN_COL_WAVES", waves)
+    inst = I.make_instance(**shape, seed=231103824, bf16_planes=True)
+    for bf16, flags, A_t in ((False, 0, None), (True, lib.FLAG_BF16_MIXED, inst.A64_hi())):
+        out = _solve(lib, torch, inst, iters, bf16=bf16, flags=flags)
+        st, _ = O.solve(inst.A64(), inst.Y32.astype(np.float64), inst.r, inst.rho, t_max=iters, A_t=A_t)
+        assert out["status"]["error_flags"] == 0
+        assert np.array_equal(out["S_idx"], st.idx)
+        assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+        X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+        X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+        assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+
+
 @pytest.mark.parametrize("shape,iters", [(dict(n=100, q=100, m=40, r=2, rho=2), 120),
                                          (dict(n=301, q=64, m=150, r=3, rho=7), 60),
                                          (dict(n=400, q=64, m=300, r=3, rho=8), 40)])   # two row chunks
@@ -490,9 +509,11 @@ def test_deterministic_and_graph_equals_eager(lib, torch):
 
 @pytest.mark.parametrize("bf16", [False, True])
 def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatch, bf16):
-    """The loads-in-flight variants the autotuner picks among compute the same bits."""
+    """The loads-in-flight variants the autotuner picks among compute the same bits
+    (the unrolls are built for 4-wave column workgroups, which this small q is forced to)."""
     cache = tmp_path / "tune.jsonl"
     monkeypatch.setenv("ALTGDMIN_TUNE_CACHE", str(cache))
+    monkeypatch.setenv("ALTGDMIN_COL_WAVES", "4")
     inst = I.make_instance(n=517, q=40, m=333 + 4 * bf16, r=5, rho=11, seed=12, bf16_planes=bf16)
     a = _solve(lib, torch, inst, 12, bf16=bf16)
     b = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE)
@@ -514,7 +535,9 @@ def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatc
                                    dict(n=260, q=8, m=701, r=8, rho=9)])     # three row chunks
 def test_every_tuned_variant_is_bitwise_the_default(lib, torch, monkeypatch, shape):
     """Each column-pass unroll JU and A_k U depth AUD, forced in turn, gives the bits of
-    the default instantiation (FP32 plane and the mixed BF16 form)."""
+    the default instantiation (FP32 plane and the mixed BF16 form; 4-wave column
+    workgroups, for which the unrolls are built)."""
+    monkeypatch.setenv("ALTGDMIN_COL_WAVES", "4")
     inst = I.make_instance(**shape, seed=21, bf16_planes=True)
     for bf16, extra in ((False, 0), (True, lib.FLAG_BF16_MIXED)):
         monkeypatch.delenv("ALTGDMIN_TUNE_FORCE", raising=False)
@@ -647,9 +670,16 @@ def test_philox_solve_matches_oracle(lib, torch):
     [dict(n=600, q=30, m=250, r=10, rho=12, seed=5, bf16=False),   # the A_k U buckets R = 10, 12, 14
      dict(n=500, q=24, m=300, r=11, rho=10, seed=6, bf16=True, mixed=True),
      dict(n=400, q=20, m=520, r=13, rho=8, seed=7, bf16=False)],
-], ids=["mixed_sizes", "ranks_10_to_14"])
-def test_step_many_equals_solo(lib, torch, specs):
-    """Each problem gives the same result alone and batched with others of other sizes and formats."""
+    [dict(n=300, q=100, m=120, r=2, rho=5, seed=8, bf16=False),    # 8-wave column workgroups
+     dict(n=260, q=400, m=150, r=3, rho=4, seed=9, bf16=True, mixed=True),   # 4-wave
+     dict(n=200, q=330, m=300, r=2, rho=3, seed=10, bf16=False)],  # 4-wave, two row chunks
+], ids=["mixed_sizes", "ranks_10_to_14", "column_widths"])
+@pytest.mark.parametrize("waves", [None, "16"])
+def test_step_many_equals_solo(lib, torch, monkeypatch, specs, waves):
+    """Each problem gives the same result alone and batched with others of other sizes,
+    formats and column-workgroup widths (and with every problem forced to 16 waves)."""
+    if waves:
+        monkeypatch.setenv("ALTGDMIN_COL_WAVES", waves)
     insts = [I.make_instance(n=s["n"], q=s["q"], m=s["m"], r=s["r"], rho=s["rho"], seed=s["seed"],
                              bf16_planes=s["bf16"]) for s in specs]
     iters = 25
