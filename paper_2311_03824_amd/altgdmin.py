@@ -23,6 +23,11 @@ LIB_PATH = os.path.join(_PKG, "libaltgdmin.so")
 
 ALTGDMIN_OK = 0
 ALTGDMIN_ENOTCONV = 1
+ALTGDMIN_EINVAL = -1
+ALTGDMIN_ENOWS = -2
+ALTGDMIN_EHIP = -3
+ALTGDMIN_ENONFINITE = -4
+ALTGDMIN_ENOTBUILT = -5
 ALTGDMIN_A_F32 = 0
 ALTGDMIN_A_BF16X2 = 1
 ALTGDMIN_A_PHILOX = 2

@@ -56,10 +56,12 @@ struct EventPair {
 constexpr size_t kAlign = 256;
 constexpr size_t kMaxLds = 64 * 1024;
 
+// Lays arrays out in the workspace at 256-byte boundaries.  A null base only
+// measures (the addresses are formed as integers, never as offsets of null).
 struct Carver {
-  char* base;
+  uintptr_t base;
   size_t off = 0;
-  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  explicit Carver(void* b) : base(reinterpret_cast<uintptr_t>(b)) {}
   template <class T>
   T* take(size_t count) {
     off = (off + kAlign - 1) / kAlign * kAlign;

@@ -15,10 +15,15 @@ the seed of its data.  The scheduler
     problems share launches);
   * after each round reads every active problem's status with one
     synchronisation (altgdmin_status_many) and retires those whose relative
-    residual is at or below `tol`, that reached `max_iters` iterations, or whose
+    residual is at or below `tol`, that reached `max_iters` iterations, whose
     kernels raised an error flag (a non-finite value, an indefinite Gram
-    matrix, invalid state), recording the latency (completion minus arrival)
-    and the error against X*.
+    matrix, invalid state), or that diverge (the residual, above
+    `diverge_floor`, rose by more than `diverge_rise` at `diverge_polls` polls in
+    a row, or is not finite), recording the latency (completion minus arrival)
+    and the error against X*;
+  * honours cancel(idx), from any thread: a request still waiting is dropped,
+    an admitted one is released (its handle destroyed, its footprint returned to
+    the budget) before the next round.
 
 The scheduling logic is host-only and takes an executor object, so it can be
 exercised without a GPU; GpuExecutor is the one that drives the library.
@@ -29,6 +34,7 @@ import collections
 import concurrent.futures
 import dataclasses
 import itertools
+import threading
 import time
 from typing import Callable, Dict, List, Optional, Sequence
 
@@ -49,6 +55,8 @@ class Outcome:
     error: float            # ||X - X*||_F / ||X*||_F of the consistent pair
     rejected: bool = False
     error_flags: int = 0    # the kernels' error bits when the request was retired
+    cancelled: bool = False
+    diverged: bool = False
 
     @property
     def latency(self) -> float:
@@ -66,17 +74,19 @@ class ServeReport:
 
     def summary(self, err_bound: float = 1e-6) -> dict:
         """Counts, throughput and latency.  A completed request is one the scheduler
-        retired (converged, at the iteration cap, or with an error flag); only
-        converged ones count as solves in converged_solves_per_s; error_violations
-        counts every completed request whose error exceeds err_bound, converged or not."""
-        done = [o for o in self.outcomes if not o.rejected]
+        retired (converged, at the iteration cap, diverged, or with an error flag);
+        rejected and cancelled requests are counted apart.  Only converged ones
+        count as solves in converged_solves_per_s; error_violations counts every
+        completed request whose error exceeds err_bound, converged or not."""
+        done = [o for o in self.outcomes if not o.rejected and not o.cancelled]
         lat = np.array([o.latency for o in done]) if done else np.zeros(1)
         conv = [o for o in done if o.converged]
         unconv = [o for o in done if not o.converged]
         return {
             "requests": len(self.outcomes),
             "completed": len(done),
-            "rejected": len(self.outcomes) - len(done),
+            "rejected": sum(1 for o in self.outcomes if o.rejected),
+            "cancelled": sum(1 for o in self.outcomes if o.cancelled),
             "solves_per_s": len(done) / self.makespan if self.makespan > 0 else 0.0,
             "converged_solves_per_s": len(conv) / self.makespan if self.makespan > 0 else 0.0,
             "p50_latency_s": float(np.percentile(lat, 50)),
@@ -86,6 +96,7 @@ class ServeReport:
             "not_converged": len(unconv),
             "max_error_not_converged": max((o.error for o in unconv), default=float("nan")),
             "retired_with_error_flags": sum(1 for o in done if o.error_flags),
+            "diverged": sum(1 for o in done if o.diverged),
             "error_violations": sum(1 for o in done if not (o.error <= err_bound)),
             "mean_iterations": float(np.mean([o.iterations for o in done])) if done else 0.0,
             "makespan_s": self.makespan,
@@ -96,15 +107,30 @@ class ServeReport:
         }
 
 
+@dataclasses.dataclass
+class _Active:
+    req: object
+    job: object
+    footprint: int
+    admitted: float
+    iterations: int = 0
+    resid: float = float("nan")
+    rises: int = 0          # consecutive polls at which the residual rose
+
+
 class Scheduler:
-    """FIFO admission by footprint, batched stepping, retire on residual or cap."""
+    """FIFO admission by footprint, batched stepping, retire on residual, cap,
+    error flag or divergence; cancellation from any thread."""
 
     def __init__(self, executor, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
                  max_iters: int = 300, clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep, prefetch: int = 16,
-                 max_active: Optional[int] = None):
+                 max_active: Optional[int] = None, diverge_polls: int = 3, diverge_rise: float = 0.01,
+                 diverge_floor: float = 1e-5):
         if poll_every < 1 or max_iters < 1:
             raise ValueError("poll_every and max_iters must be >= 1")
+        if diverge_polls < 0 or diverge_rise < 0:
+            raise ValueError("diverge_polls and diverge_rise must be >= 0")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.poll_every = poll_every
@@ -114,11 +140,38 @@ class Scheduler:
         self.sleep = sleep
         self.prefetch = prefetch
         self.max_active = max_active   # None: limited by the budget only; 1: one request at a time
+        self.diverge_polls = diverge_polls   # 0: never retire for divergence
+        self.diverge_rise = diverge_rise
+        self.diverge_floor = diverge_floor
+        self._lock = threading.Lock()
+        self._cancel = set()
+
+    def cancel(self, idx: int) -> None:
+        """Ask for request `idx` to be dropped (waiting) or released (admitted)
+        before the next round.  Thread-safe; a request already retired, or an
+        unknown index, is ignored."""
+        with self._lock:
+            self._cancel.add(int(idx))
+
+    def _take_cancels(self) -> set:
+        with self._lock:
+            out, self._cancel = self._cancel, set()
+        return out
+
+    def _diverging(self, a: _Active, resid: float) -> bool:
+        """Updates the rise count of `a` with the new residual; True once it diverges."""
+        if not np.isfinite(resid):
+            return True
+        if self.diverge_polls == 0:
+            return False
+        rose = np.isfinite(a.resid) and resid > self.diverge_floor and resid > a.resid * (1.0 + self.diverge_rise)
+        a.rises = a.rises + 1 if rose else 0
+        return a.rises >= self.diverge_polls
 
     def run(self, requests) -> ServeReport:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.idx)))
         waiting = collections.deque()
-        active = []                     # (request, job, footprint, admitted_at)
+        active: List[_Active] = []
         outcomes = []
         used = peak = 0
         rounds = 0
@@ -133,8 +186,33 @@ class Scheduler:
             spent[name] += self.clock() - a
             return out
 
+        def release(a: _Active):
+            rel = getattr(self.ex, "release", None)
+            timed("release", rel if rel is not None else self.ex.finish, a.job)
+
         while pending or waiting or active:
             t = now()
+            cancels = self._take_cancels()
+            if cancels:
+                for q in (pending, waiting):
+                    for req in [r for r in q if r.idx in cancels]:
+                        q.remove(req)
+                        outcomes.append(Outcome(req.idx, req.arrival, t, t, 0, float("nan"), False, float("nan"),
+                                                cancelled=True))
+                        if hasattr(self.ex, "forget"):
+                            self.ex.forget(req)
+                keep = []
+                for a in active:
+                    if a.req.idx in cancels:
+                        release(a)
+                        used -= a.footprint
+                        outcomes.append(Outcome(a.req.idx, a.req.arrival, a.admitted, now(), a.iterations, a.resid,
+                                                False, float("nan"), cancelled=True))
+                    else:
+                        keep.append(a)
+                active = keep
+                if not (pending or waiting or active):
+                    break
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
             if prepare is not None:          # host-side payloads of the next few, made in the background
@@ -156,26 +234,28 @@ class Scheduler:
                 job = timed("start", self.ex.start, req)
                 used += fp
                 peak = max(peak, used)
-                active.append((req, job, fp, now()))
+                active.append(_Active(req, job, fp, now()))
             if not active:
                 if pending:
                     self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
-            timed("step", self.ex.step, [a[1] for a in active], self.poll_every)
+            timed("step", self.ex.step, [a.job for a in active], self.poll_every)
             rounds += 1
-            status = timed("poll", self.ex.poll, [a[1] for a in active])
+            status = timed("poll", self.ex.poll, [a.job for a in active])
             keep = []
-            for (req, job, fp, adm), st in zip(active, status):
+            for a, st in zip(active, status):
                 iters, resid = st[0], st[1]
                 flags = st[2] if len(st) > 2 else 0
                 conv = resid <= self.tol and not flags
-                if conv or iters >= self.max_iters or flags:
-                    err = timed("finish", self.ex.finish, job)
-                    outcomes.append(Outcome(req.idx, req.arrival, adm, now(), iters, resid, conv, err,
-                                            error_flags=int(flags)))
-                    used -= fp
+                diverged = not conv and not flags and self._diverging(a, resid)
+                a.iterations, a.resid = iters, resid
+                if conv or iters >= self.max_iters or flags or diverged:
+                    err = timed("finish", self.ex.finish, a.job)
+                    outcomes.append(Outcome(a.req.idx, a.req.arrival, a.admitted, now(), iters, resid, conv, err,
+                                            error_flags=int(flags), diverged=diverged))
+                    used -= a.footprint
                 else:
-                    keep.append((req, job, fp, adm))
+                    keep.append(a)
             active = keep
         makespan = max((o.done for o in outcomes), default=0.0) - min((o.arrival for o in outcomes), default=0.0)
         outcomes.sort(key=lambda o: o.idx)
@@ -279,9 +359,20 @@ class GpuExecutor:
         if req.rho:
             Xt.scatter_add_(1, Si.long(), Sv.double())
         err = float(torch.linalg.norm(Xt - job["Xt"]) / torch.linalg.norm(job["Xt"]))
-        self.lib.altgdmin_destroy(job["h"])
-        job.clear()
+        self.release(job)
         return err
+
+    def release(self, job) -> None:
+        """Destroy the handle and drop the job's device buffers (cancellation)."""
+        if job.get("h") is not None:
+            self.lib.altgdmin_destroy(job["h"])
+        job.clear()
+
+    def forget(self, req) -> None:
+        """Drop the host-side payload prepared for a request that will not run."""
+        fut = self._truth.pop(req.idx, None)
+        if fut is not None:
+            fut.cancel()
 
 
 def calibrate_rate(executor, requests, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,

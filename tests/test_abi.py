@@ -254,3 +254,13 @@ def test_every_binding_call_that_takes_a_stream_is_ordered_on_a_created_stream()
         assert takes_stream == wrapped and not twice, line
         checked += takes_stream
     assert checked >= 20
+
+
+def test_binding_error_codes_match_the_header():
+    import re
+    from paper_2311_03824_amd import altgdmin as lib
+    hdr = open(os.path.join(ROOT, "include", "altgdmin.h")).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"(ALTGDMIN_E[A-Z]+|ALTGDMIN_OK)\s*=\s*(-?\d+)", hdr))
+    assert len(codes) == 7
+    for name, value in codes.items():
+        assert getattr(lib, name) == value, name

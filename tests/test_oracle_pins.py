@@ -327,6 +327,50 @@ def test_fig1_exact_recovery_claim():
     assert min(hist_full) > 1e-2
 
 
+# ---------------------------------------------------------------- the fixed step size (Sec. 2.6)
+
+def _first_eta_and_errors(inst, c, iters):
+    A, Y = inst.A64(), inst.Y64
+    st = O.initialise(A, Y, inst.r, inst.rho)
+    errs = []
+    for _ in range(iters):
+        st = O.gdmin_iteration(A, Y, st, inst.rho, eta_c=c)
+        errs.append(O.rel_error(O.estimate(st), inst.X_star))
+    return st.eta, np.array(errs)
+
+
+def test_fixed_step_contracts_by_one_minus_eta_m_sigma_squared():
+    """Near the solution, with B refitted by least squares and E[A_k^T A_k] = m I,
+    one projected GD step scales the error of U along the i-th direction by about
+    1 - eta m sigma_i(B*)^2 (the gradient of Sec. 2.1 without its factor 2).  The
+    fixed eta = c / ||grad_U f(U_0, B_1, S_1)||_2 is proportional to 1 / SD(U_0),
+    so with the paper's c = 0.14 a start that is already accurate (here SD(U_0) =
+    0.06, from q = 3000 columns) gives eta m sigma^2 near 3 > 2: the error doubles
+    per step instead of shrinking.  With c = 0.05 the same start gives about 1.1
+    and the error falls by the predicted factor.  On the paper's own shapes (the
+    n = q = 100 instance below; also the Fig. 1 shape and n = q = 1000, m = 400)
+    eta m sigma^2 lies in [0.5, 0.92]."""
+    inst = I.make_instance(60, 3000, 60, 2, 1, 5)
+    sv = np.linalg.svd(inst.B_star, compute_uv=False)
+    m = inst.m
+    eta, e = _first_eta_and_errors(inst, 0.14, 4)
+    lo, hi = eta * m * sv[-1] ** 2, eta * m * sv[0] ** 2
+    assert 2.5 < lo <= hi < 3.5
+    ratios = e[1:] / e[:-1]
+    assert np.all(ratios > 1.5)                                        # diverges
+    assert ratios[0] == pytest.approx(lo - 1.0, rel=0.15)              # |1 - eta m sigma^2|, slowest mode
+    eta, e = _first_eta_and_errors(inst, 0.05, 8)
+    lo, hi = eta * m * sv[-1] ** 2, eta * m * sv[0] ** 2
+    assert 0.9 < lo <= hi < 1.3
+    ratios = e[1:] / e[:-1]
+    assert np.all(ratios < 1.1 * max(abs(1 - lo), abs(1 - hi)))
+    assert e[-1] < 1e-8
+    paper = I.make_instance(100, 100, 40, 2, 2, 231103824)
+    eta, _ = _first_eta_and_errors(paper, 0.14, 1)
+    svp = np.linalg.svd(paper.B_star, compute_uv=False)
+    assert 0.4 < eta * paper.m * svp[-1] ** 2 <= eta * paper.m * svp[0] ** 2 < 1.0
+
+
 # ---------------------------------------------------------------- automatic rank (Sec. 2.6)
 
 def _with_spectrum(n, q, sv, seed=0):

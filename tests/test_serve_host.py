@@ -225,3 +225,154 @@ def test_unconverged_requests_count_as_error_violations():
     s = rep.summary()
     assert s["not_converged"] == 1 and s["max_error_not_converged"] == 0.5
     assert s["error_violations"] == 1
+
+
+class Releasing(MockExecutor):
+    """Counts releases apart from finishes (a cancelled job is released, not finished)."""
+
+    def __init__(self, *a, **k):
+        super().__init__(*a, **k)
+        self.released, self.finished = [], []
+
+    def release(self, job):
+        self.in_use -= self.fp(job["req"])
+        self.released.append(job["req"].idx)
+
+    def finish(self, job):
+        self.finished.append(job["req"].idx)
+        return super().finish(job)
+
+
+def test_cancel_drops_waiting_and_releases_active_requests():
+    """cancel(idx) before the run drops a request that never starts; cancel during
+    the run releases an admitted job before the next round and returns its
+    footprint to the budget; the rest complete as usual."""
+    clock = Clock()
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(5)]
+    sched = None
+
+    class CancelMid(Releasing):
+        def step(self, jobs, iters):
+            super().step(jobs, iters)
+            if len(self.rounds) == 2:
+                sched.cancel(1)       # an active request, after two rounds
+                sched.cancel(99)      # unknown: ignored
+
+    ex = CancelMid(clock, {i: 40 for i in range(5)} | {1: None})
+    sched = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-7, max_iters=300,
+                      clock=clock, sleep=clock.sleep)
+    sched.cancel(3)                   # waiting: never admitted
+    rep = sched.run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert len(o) == 5
+    assert o[3].cancelled and 3 not in ex.admit_order and o[3].iterations == 0
+    assert o[1].cancelled and o[1].iterations == 20 and np.isnan(o[1].error)
+    assert ex.released == [1] and 1 not in ex.finished and 3 not in ex.finished
+    assert ex.rounds == [4, 4, 3, 3]                 # request 1 is gone from the third round on
+    assert all(o[i].converged and not o[i].cancelled for i in (0, 2, 4))
+    assert ex.in_use == 0
+    s = rep.summary()
+    assert s["cancelled"] == 2 and s["completed"] == 3 and s["rejected"] == 0
+    assert s["converged_fraction"] == 1.0 and s["error_violations"] == 0
+
+
+def test_cancel_from_another_thread():
+    import threading
+
+    clock = Clock()
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(3)]
+    started = threading.Event()
+    sched = None
+
+    def canceller():
+        started.wait(10)
+        sched.cancel(0)
+
+    th = threading.Thread(target=canceller)
+
+    class Signal(Releasing):
+        def step(self, jobs, iters):
+            super().step(jobs, iters)
+            if len(self.rounds) == 1:
+                started.set()
+                th.join(10)
+
+    ex = Signal(clock, {0: None, 1: 30, 2: 30})
+    sched = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, clock=clock, sleep=clock.sleep)
+    th.start()
+    rep = sched.run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert o[0].cancelled and o[0].iterations == 10 and ex.released == [0]
+    assert o[1].converged and o[2].converged
+
+
+def test_cancelling_the_last_request_ends_the_run():
+    clock = Clock()
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(1)]
+    sched = None
+
+    class CancelFirst(Releasing):
+        def step(self, jobs, iters):
+            super().step(jobs, iters)
+            sched.cancel(0)
+
+    ex = CancelFirst(clock, {0: None})
+    sched = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, max_iters=10**6, clock=clock, sleep=clock.sleep)
+    rep = sched.run(reqs)
+    assert rep.outcomes[0].cancelled and ex.rounds == [1] and ex.in_use == 0
+
+
+class Trajectory(MockExecutor):
+    """Residual of request idx at its p-th poll: traj[idx](p)."""
+
+    def __init__(self, clock, traj):
+        super().__init__(clock, {i: None for i in traj})
+        self.traj = traj
+        self.polls = {}
+
+    def poll(self, jobs):
+        out = []
+        for j in jobs:
+            i = j["req"].idx
+            p = self.polls.get(i, 0) + 1
+            self.polls[i] = p
+            out.append((j["it"], self.traj[i](p)))
+        return out
+
+
+def test_diverging_requests_are_retired():
+    """A residual that rises by more than diverge_rise at diverge_polls polls in a row
+    retires the request as diverged; one that rises only below diverge_floor, or
+    rises and falls again, runs to the cap; a NaN residual retires at once."""
+    clock = Clock()
+    traj = {
+        0: lambda p: 1e-3 * 1.5 ** p,                          # grows: rises at polls 2, 3, 4
+        1: lambda p: 1e-8 * 1.5 ** p,                          # grows, but below the floor up to poll 12
+        2: lambda p: 1e-3 * (1.5 if p % 3 else 0.5),           # two rises, then a fall, repeating
+        3: lambda p: float("nan") if p == 2 else 1e-3,
+        4: lambda p: 1e-3 * 1.005 ** p,                        # rises by less than 1 %
+    }
+    ex = Trajectory(clock, traj)
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(5)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-12, max_iters=100,
+                    clock=clock, sleep=clock.sleep).run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert o[0].diverged and o[0].iterations == 40 and not o[0].converged
+    assert o[3].diverged and o[3].iterations == 20
+    for i in (1, 2, 4):
+        assert not o[i].diverged and o[i].iterations == 100
+    s = rep.summary()
+    assert s["diverged"] == 2 and s["completed"] == 5 and s["not_converged"] == 5
+
+
+def test_divergence_check_can_be_switched_off():
+    clock = Clock()
+    ex = Trajectory(clock, {0: lambda p: 1e-3 * 2.0 ** p, 1: lambda p: float("inf")})
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(2)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-12, max_iters=60, diverge_polls=0,
+                    clock=clock, sleep=clock.sleep).run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert not o[0].diverged and o[0].iterations == 60
+    assert o[1].diverged and o[1].iterations == 10        # a non-finite residual always ends the request
+    with pytest.raises(ValueError):
+        Scheduler(None, 1, diverge_polls=-1)
