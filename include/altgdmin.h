@@ -156,11 +156,13 @@ typedef struct altgdmin_report {
   int32_t power_iterations;  /* subspace iterations used for U_0 */
   int32_t error_flags;       /* bit 0: NaN at a selection; bit 1: Gram not positive definite; bit 2: invalid start
                                 support (index out of range, unsorted or repeated) or frequency index out of range */
-  int32_t converged;         /* 1 when the last residual <= tol_resid */
+  int32_t converged;         /* 1 when the last residual <= tol_resid and no error flag is set */
   int32_t refine_iteration;  /* BF16X2: first GDmin iteration that read hi + lo (-1: still hi-only or no hi-only phase) */
   int32_t rank;              /* the rank r in use (with r = 0 in the problem: the one altgdmin_init chose) */
   double eta;                /* step size (0 before iteration 1) */
-  double resid;              /* ||Y - A(U B + S)||_F / ||Y||_F of the last iteration's consistent pair */
+  double resid;              /* ||Y - A(U B + S)||_F / ||Y||_F of the last iteration's consistent pair (NaN once a
+                                non-finite value reached a residual); an iteration whose QR step failed (error bit
+                                1) is still counted and leaves U unchanged */
   double power_sd;           /* last subspace-iteration change */
 } altgdmin_report;
 

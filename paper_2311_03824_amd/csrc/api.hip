@@ -873,7 +873,7 @@ int altgdmin_status(altgdmin_handle* h, void* stream, altgdmin_report* rep) {
   rep->eta = c.eta;
   rep->resid = c.resid;
   rep->power_sd = c.power_sd;
-  rep->converged = (h->par.tol_resid > 0.0 && c.t > 0 && c.resid <= h->par.tol_resid) ? 1 : 0;
+  rep->converged = (h->par.tol_resid > 0.0 && c.t > 0 && c.err == 0 && c.resid <= h->par.tol_resid) ? 1 : 0;
   rep->refine_iteration = h->hi_phase ? c.refine_t : -1;
   rep->rank = h->prob.r;
   return ALTGDMIN_OK;
@@ -898,7 +898,7 @@ int altgdmin_status_many(altgdmin_handle* const* hs, int32_t count, void* stream
     rep->eta = c[i].eta;
     rep->resid = c[i].resid;
     rep->power_sd = c[i].power_sd;
-    rep->converged = (h->par.tol_resid > 0.0 && c[i].t > 0 && c[i].resid <= h->par.tol_resid) ? 1 : 0;
+    rep->converged = (h->par.tol_resid > 0.0 && c[i].t > 0 && c[i].err == 0 && c[i].resid <= h->par.tol_resid) ? 1 : 0;
     rep->refine_iteration = h->hi_phase ? c[i].refine_t : -1;
     rep->rank = h->prob.r;
   }

@@ -807,7 +807,8 @@ __global__ __launch_bounds__(kFThreads) void k_fcol(FColArgs a) {
     // ||r_k||^2 = ||e_k||^2 - Re(c^H b_k), since G_k b_k = c = P_k^H e_k
     double cb_re = 0.0;
     for (int ra = 0; ra < r; ++ra) cb_re += dsum[2 * ra] * gx[ra].x + dsum[2 * ra + 1] * gx[ra].y;
-    const double rr = fmax(dsum[2 * R] - cb_re, 0.0);
+    const double d_rr = dsum[2 * R] - cb_re;
+    const double rr = d_rr < 0.0 ? 0.0 : d_rr;   // rounding below zero clamped; a NaN stays NaN
     if (tid == 0) a.colrr[k] = rr;
     __syncthreads();   // dsum is read above by every thread
     float2 rv[2];
@@ -1244,7 +1245,7 @@ __global__ __launch_bounds__(kFThreads) void k_fqr(FQRArgs a) {
   bool ok = fcholqr_pass<R>(X, n, r, stage, W, Lm, &okf);
   if (ok) ok = fcholqr_pass<R>(X, n, r, stage, W, Lm, &okf);
   if (!ok) {
-    if (tid == 0) a.ctl->err |= 2;
+    if (tid == 0) atomicOr(&a.ctl->err, 2);
     return;
   }
   block_copy_c(a.U, X, nr);
@@ -1436,7 +1437,7 @@ __global__ __launch_bounds__(256) void k_fqr_a(FQRArgs a) {
     const bool ok = wave_chol_c(W, Lm, r);
     if (ok) wave_rinv_c<kFRMax>(Lm, a.rinv, r);
     if (!ok && tid == 0) {
-      a.ctl->err |= 2;
+      atomicOr(&a.ctl->err, 2);
       for (int e = 0; e < rr; ++e) a.rinv[e] = make_double2((e % (r + 1) == 0) ? 1.0 : 0.0, 0.0);
     }
   }
@@ -1509,7 +1510,7 @@ __global__ __launch_bounds__(256) void k_fqr_c(FQRArgs a) {
     const bool ok = wave_chol_c(W, Lm, a.r);
     if (ok) wave_rinv_c<kFRMax>(Lm, a.rinv + rr, a.r);
     if (!ok && tid == 0) {
-      a.ctl->err |= 2;
+      atomicOr(&a.ctl->err, 2);
       for (int e = 0; e < rr; ++e) a.rinv[rr + e] = make_double2((e % (a.r + 1) == 0) ? 1.0 : 0.0, 0.0);
     }
   }

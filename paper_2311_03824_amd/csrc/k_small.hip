@@ -301,14 +301,16 @@ __device__ __forceinline__ void qr_body(const QRArgs& a, unsigned char* dsm, QRS
     for (int idx = tid; idx < nr; idx += kQRThreads) X[idx] = (float)fma(-eta, (double)X[idx], (double)a.U[idx]);
     __syncthreads();
   }
-  // CholeskyQR2
+  // CholeskyQR2.  A Gram that is not positive definite (a non-finite step, or a
+  // rank-deficient block) raises error bit 1 and leaves U as it was; a GD step
+  // still records the iteration below (its residual, the column flags, the count).
   bool ok = block_cholqr_pass(X, n, r, sh, W, Lf, &okflag);
   if (ok) ok = block_cholqr_pass(X, n, r, sh, W, Lf, &okflag);
   if (!ok) {
-    if (tid == 0 && a.ctl) a.ctl->err |= 2;
-    return;
+    if (tid == 0 && a.ctl) atomicOr(&a.ctl->err, 2);
+    if (a.mode != QR_GD) return;
   }
-  if (a.mode == QR_POWER) {
+  if (ok && a.mode == QR_POWER) {
     // subspace change ||U_new - U_old (U_old^T U_new)||_F, summed directly from the
     // residual entries (r - ||U_old^T U_new||_F^2 cancels below angles of ~3e-4 in FP32)
     block_gram(a.U, X, n, r, W, false);   // U_old^T U_new
@@ -344,7 +346,7 @@ __device__ __forceinline__ void qr_body(const QRArgs& a, unsigned char* dsm, QRS
   }
   for (int idx = tid; idx < nr; idx += kQRThreads) {
     if (a.mode == QR_GD && a.Uprev) a.Uprev[idx] = a.U[idx];
-    a.U[idx] = X[idx];
+    if (ok) a.U[idx] = X[idx];
   }
   if (a.mode == QR_GD && a.ctl) {
     double s = 0.0;

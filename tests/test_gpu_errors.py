@@ -2,9 +2,10 @@
 still runs to its normal end; all loops in the kernels have fixed trip counts):
 
   * a NaN in the measurements reaches the HardThreshold selection; the kernels
-    raise error bit 0, the residual is not finite, and altgdmin_solve returns
-    ALTGDMIN_ENONFINITE instead of a result (FP32 plane, mixed BF16, partial
-    Fourier);
+    raise error bit 0 (and bit 1 once the non-finite gradient reaches the QR
+    step, which then leaves U unchanged), the residual is NaN, `converged` stays
+    0, and altgdmin_solve returns ALTGDMIN_ENONFINITE instead of a result (FP32
+    plane, mixed BF16, partial Fourier);
   * a tolerance that cannot be reached exhausts t_max: altgdmin_solve returns
     the ALTGDMIN_ENOTCONV warning with the iterate of the last iteration in the
     outputs (the binding passes the warning through);
@@ -52,7 +53,7 @@ def _problem(lib, torch, inst, form, Y32):
 
 @pytest.mark.parametrize("form", ["f32", "bf16_mixed"])
 def test_nan_in_measurements_is_reported(lib, torch, form):
-    inst = I.make_instance(**SHAPE, seed=231103824)
+    inst = I.make_instance(**SHAPE, seed=231103824, bf16_planes=(form != "f32"))
     Y32 = inst.Y32.copy()
     Y32[3, 5] = np.nan
     print(f"\ncase: NaN in y_3, {form}", flush=True)
@@ -68,8 +69,13 @@ def test_nan_in_measurements_is_reported(lib, torch, form):
     try:
         lib.altgdmin_step(h, 2)
         st = lib.altgdmin_status(h)
-        assert st["error_flags"] & 1
-        assert st["converged"] == 0 and not np.isfinite(st["resid"])
+        assert st["error_flags"] & 1 and st["iterations"] == 2
+        assert st["converged"] == 0 and np.isnan(st["resid"])
+        # the failed QR steps left U as it was: finite, orthonormal
+        U = torch.empty((inst.n, inst.r), dtype=torch.float32, device="cuda")
+        lib.altgdmin_get(h, U)
+        Uh = U.double().cpu().numpy()
+        assert np.all(np.isfinite(Uh)) and np.abs(Uh.T @ Uh - np.eye(inst.r)).max() < 1e-5
     finally:
         lib.altgdmin_destroy(h)
 
@@ -83,7 +89,7 @@ def test_nan_in_fourier_measurements_is_reported(lib, torch):
     try:
         s.step(3)
         st = s.status()
-        assert st["error_flags"] & 1 and not np.isfinite(st["resid"])
+        assert st["error_flags"] & 1 and np.isnan(st["resid"]) and st["iterations"] == 3
     finally:
         s.close()
 
@@ -98,7 +104,7 @@ def test_tmax_exhaustion_returns_the_warning_and_the_last_iterate(lib, torch):
     rc, rep = lib.altgdmin_solve(p, par, ws, U, Bt, Si, Sv)
     assert rc == lib.ALTGDMIN_ENOTCONV
     assert rep["iterations"] == 7 and rep["converged"] == 0 and rep["error_flags"] == 0
-    assert 0.0 < rep["resid"] < 1e-2
+    assert 0.0 < rep["resid"] < 0.1
     # the outputs hold the iterate of iteration 7: the same as stepping a handle 7 times
     h = lib.altgdmin_init(p, par, ws)
     try:
