@@ -298,6 +298,7 @@ class ServeRequest:
     a_format: str          # "f32" or "bf16x2"
     seed: int              # seed of this request's U*, B*, S* and A key
     arrival: float = 0.0   # seconds after the start of the run
+    eta_scale: float = 1.0  # multiplies the step constant eta_c (a serving retry sets it below 1)
 
     @property
     def lda(self) -> int:

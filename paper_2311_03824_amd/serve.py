@@ -17,10 +17,22 @@ the seed of its data.  The scheduler
     synchronisation (altgdmin_status_many) and retires those whose relative
     residual is at or below `tol`, that reached `max_iters` iterations, whose
     kernels raised an error flag (a non-finite value, an indefinite Gram
-    matrix, invalid state), or that diverge (the residual, above
-    `diverge_floor`, rose by more than `diverge_rise` at `diverge_polls` polls in
-    a row, or is not finite), recording the latency (completion minus arrival)
-    and the error against X*;
+    matrix, invalid state), that diverge (the residual, above `diverge_floor`,
+    rose by more than `diverge_rise` at `diverge_polls` polls in a row, or is not
+    finite), or that stall (no new minimum by 1 % for `stall_polls` polls: above
+    `diverge_floor` a failure -- the period-2 oscillation of a step that is too
+    long looks flat when the polls fall on iterations of one parity -- and at or
+    below it the FP32 rounding floor of a request whose `tol` sits just under
+    it, retired as `at_floor`), recording the latency (completion minus
+    arrival) and the error against X*;
+  * optionally (`retry_step_limit`) re-queues a diverged or stalled request, at
+    the head of the queue, when its step is too long: the fixed step of Sec. 2.6
+    scales the error along direction i by about 1 - eta m sigma_i(B)^2 (Gaussian
+    A_k, E[A_k^T A_k] = m I), so with an initialisation that is already accurate
+    eta m sigma_max^2 exceeds 2 and the iteration cannot settle.  The executor's
+    step_diagnostic(job) gives eta m sigma_max(B_t)^2 from the current iterate
+    (no knowledge of X*); above the limit, the retry scales eta_c by 1 over it.
+    Requests that stall for other reasons are not retried;
   * honours cancel(idx), from any thread: a request still waiting is dropped,
     an admitted one is released (its handle destroyed, its footprint returned to
     the budget) before the next round.
@@ -57,6 +69,11 @@ class Outcome:
     error_flags: int = 0    # the kernels' error bits when the request was retired
     cancelled: bool = False
     diverged: bool = False
+    stalled: bool = False
+    at_floor: bool = False  # stalled at or below diverge_floor: the rounding floor, not a failure
+    attempts: int = 1       # 1 + retries with a shorter step
+    eta_m_sigma2: float = float("nan")   # eta m sigma_max(B*)^2 of the last attempt, when the executor reports it
+    step_diag: float = float("nan")      # eta m sigma_max(B_t)^2 from the iterate, when a failure was checked
 
     @property
     def latency(self) -> float:
@@ -97,6 +114,16 @@ class ServeReport:
             "max_error_not_converged": max((o.error for o in unconv), default=float("nan")),
             "retired_with_error_flags": sum(1 for o in done if o.error_flags),
             "diverged": sum(1 for o in done if o.diverged),
+            "stalled": sum(1 for o in done if o.stalled),
+            "at_floor": sum(1 for o in done if o.at_floor),
+            "retried": sum(1 for o in done if o.attempts > 1),
+            "converged_after_retry": sum(1 for o in done if o.attempts > 1 and o.converged),
+            "not_converged_detail": [{"idx": o.idx, "iterations": o.iterations, "resid": o.resid, "error": o.error,
+                                      "attempts": o.attempts, "eta_m_sigma2": o.eta_m_sigma2,
+                                      "step_diag": o.step_diag,
+                                      "why": "diverged" if o.diverged else "stalled" if o.stalled else
+                                      "at floor" if o.at_floor else "error flag" if o.error_flags else
+                                      "iteration cap"} for o in unconv][:16],
             "error_violations": sum(1 for o in done if not (o.error <= err_bound)),
             "mean_iterations": float(np.mean([o.iterations for o in done])) if done else 0.0,
             "makespan_s": self.makespan,
@@ -116,6 +143,8 @@ class _Active:
     iterations: int = 0
     resid: float = float("nan")
     rises: int = 0          # consecutive polls at which the residual rose
+    best: float = float("inf")
+    since_best: int = 0     # polls since the residual last reached a new minimum (by 1 %)
 
 
 class Scheduler:
@@ -126,11 +155,14 @@ class Scheduler:
                  max_iters: int = 300, clock: Callable[[], float] = time.perf_counter,
                  sleep: Callable[[float], None] = time.sleep, prefetch: int = 16,
                  max_active: Optional[int] = None, diverge_polls: int = 3, diverge_rise: float = 0.01,
-                 diverge_floor: float = 1e-5):
+                 diverge_floor: float = 1e-5, stall_polls: int = 6, retry_step_limit: Optional[float] = None,
+                 max_retries: int = 1):
         if poll_every < 1 or max_iters < 1:
             raise ValueError("poll_every and max_iters must be >= 1")
-        if diverge_polls < 0 or diverge_rise < 0:
-            raise ValueError("diverge_polls and diverge_rise must be >= 0")
+        if diverge_polls < 0 or diverge_rise < 0 or stall_polls < 0 or max_retries < 0:
+            raise ValueError("diverge_polls, diverge_rise, stall_polls and max_retries must be >= 0")
+        if retry_step_limit is not None and not retry_step_limit >= 1.0:
+            raise ValueError("retry_step_limit must be >= 1")
         self.ex = executor
         self.budget = int(budget_bytes)
         self.poll_every = poll_every
@@ -143,6 +175,9 @@ class Scheduler:
         self.diverge_polls = diverge_polls   # 0: never retire for divergence
         self.diverge_rise = diverge_rise
         self.diverge_floor = diverge_floor
+        self.stall_polls = stall_polls       # 0: never retire for a stall
+        self.retry_step_limit = retry_step_limit
+        self.max_retries = max_retries
         self._lock = threading.Lock()
         self._cancel = set()
 
@@ -168,6 +203,14 @@ class Scheduler:
         a.rises = a.rises + 1 if rose else 0
         return a.rises >= self.diverge_polls
 
+    def _stalled(self, a: _Active, resid: float) -> bool:
+        """Updates the poll count since the last new minimum; True once it reaches stall_polls."""
+        if resid < a.best * 0.99:
+            a.best, a.since_best = resid, 0
+            return False
+        a.since_best += 1
+        return self.stall_polls > 0 and a.since_best >= self.stall_polls
+
     def run(self, requests) -> ServeReport:
         pending = collections.deque(sorted(requests, key=lambda r: (r.arrival, r.idx)))
         waiting = collections.deque()
@@ -176,6 +219,7 @@ class Scheduler:
         used = peak = 0
         rounds = 0
         spent = collections.Counter()     # wall time inside each executor call
+        attempts = collections.defaultdict(lambda: 1)
         prepare = getattr(self.ex, "prepare", None)
         t0 = self.clock()
         now = lambda: self.clock() - t0  # noqa: E731
@@ -243,20 +287,38 @@ class Scheduler:
             rounds += 1
             status = timed("poll", self.ex.poll, [a.job for a in active])
             keep = []
+            retry = []
             for a, st in zip(active, status):
                 iters, resid = st[0], st[1]
                 flags = st[2] if len(st) > 2 else 0
                 conv = resid <= self.tol and not flags
                 diverged = not conv and not flags and self._diverging(a, resid)
+                stalled = not conv and not flags and not diverged and self._stalled(a, resid)
+                at_floor = stalled and resid <= self.diverge_floor
+                stalled = stalled and not at_floor
                 a.iterations, a.resid = iters, resid
-                if conv or iters >= self.max_iters or flags or diverged:
-                    err = timed("finish", self.ex.finish, a.job)
+                diag = float("nan")
+                if (diverged or stalled) and self.retry_step_limit and attempts[a.req.idx] <= self.max_retries \
+                        and hasattr(self.ex, "step_diagnostic"):
+                    diag = timed("diagnose", self.ex.step_diagnostic, a.job)
+                if diag > (self.retry_step_limit or float("inf")):
+                    release(a)
+                    used -= a.footprint
+                    attempts[a.req.idx] += 1
+                    retry.append(dataclasses.replace(a.req, eta_scale=a.req.eta_scale / diag))
+                elif conv or iters >= self.max_iters or flags or diverged or stalled or at_floor:
+                    out = timed("finish", self.ex.finish, a.job)
+                    err, info = out if isinstance(out, tuple) else (out, {})
                     outcomes.append(Outcome(a.req.idx, a.req.arrival, a.admitted, now(), iters, resid, conv, err,
-                                            error_flags=int(flags), diverged=diverged))
+                                            error_flags=int(flags), diverged=diverged, stalled=stalled,
+                                            at_floor=at_floor,
+                                            attempts=attempts[a.req.idx], step_diag=diag,
+                                            eta_m_sigma2=info.get("eta_m_sigma2", float("nan"))))
                     used -= a.footprint
                 else:
                     keep.append(a)
             active = keep
+            waiting.extendleft(reversed(retry))     # retries go first, in their original order
         makespan = max((o.done for o in outcomes), default=0.0) - min((o.arrival for o in outcomes), default=0.0)
         outcomes.sort(key=lambda o: o.idx)
         return ServeReport(outcomes, makespan, self.budget, peak, rounds, dict(spent))
@@ -287,8 +349,18 @@ class GpuExecutor:
         self._truth = {}
 
     def _make_truth(self, req):
-        Xt = self.torch.from_numpy(inst.request_truth(req)["Xt"])
-        return Xt.pin_memory()
+        """X*^T, pinned for the upload, and sigma_min(B*)^2, sigma_max(B*)^2 (step diagnostic)."""
+        t = inst.request_truth(req)
+        sv = np.linalg.svd(t["B_star"], compute_uv=False)
+        return self.torch.from_numpy(t["Xt"]).pin_memory(), (float(sv[-1]) ** 2, float(sv[0]) ** 2)
+
+    def _params(self, req):
+        base = self.params if req.a_format == "f32" else self.params_bf16
+        if req.eta_scale == 1.0:
+            return base
+        par = self.lib.Params.from_buffer_copy(base)
+        par.eta_c = base.eta_c * req.eta_scale
+        return par
 
     def prepare(self, req) -> None:
         """Start drawing X* of a request on a host thread (pinned for the upload)."""
@@ -318,7 +390,7 @@ class GpuExecutor:
     def start(self, req):
         torch, lib = self.torch, self.lib
         fut = self._truth.pop(req.idx, None)
-        Xt_host = fut.result() if fut is not None else self._make_truth(req)
+        Xt_host, sv2 = fut.result() if fut is not None else self._make_truth(req)
         Xt = Xt_host.to(self.device, non_blocking=True)
         shape = (req.q, req.n, req.lda)
         if req.a_format == "f32":
@@ -331,8 +403,8 @@ class GpuExecutor:
         prob = lib.make_problem(A, Y, req.r, req.rho, A_lo=A_lo, m=req.m)
         lib.altgdmin_op_measure(prob, Xt, Y)
         ws = torch.empty(self.workspace_bytes(req), dtype=torch.uint8, device=self.device)
-        h = lib.altgdmin_init(prob, self.params if req.a_format == "f32" else self.params_bf16, ws)
-        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, Xt_host=Xt_host, ws=ws, prob=prob, h=h)
+        h = lib.altgdmin_init(prob, self._params(req), ws)
+        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, Xt_host=Xt_host, ws=ws, prob=prob, h=h, sv2=sv2)
 
     def step(self, jobs, iters: int) -> None:
         hs = [j["h"] for j in jobs]
@@ -346,7 +418,8 @@ class GpuExecutor:
         reps = self.lib.altgdmin_status_many([j["h"] for j in jobs])
         return [(int(st["iterations"]), float(st["resid"]), int(st["error_flags"])) for st in reps]
 
-    def finish(self, job) -> float:
+    def finish(self, job):
+        """(error against X*, {"eta_m_sigma2": eta m sigma_max(B*)^2}) of a retired job."""
         torch, req = self.torch, job["req"]
         U = torch.empty((req.n, req.r), dtype=torch.float32, device=self.device)
         Bt = torch.empty((req.q, req.r), dtype=torch.float32, device=self.device)
@@ -359,8 +432,20 @@ class GpuExecutor:
         if req.rho:
             Xt.scatter_add_(1, Si.long(), Sv.double())
         err = float(torch.linalg.norm(Xt - job["Xt"]) / torch.linalg.norm(job["Xt"]))
+        eta = self.lib.altgdmin_status(job["h"])["eta"]
+        diag = eta * req.m * job["sv2"][1]
         self.release(job)
-        return err
+        return err, {"eta_m_sigma2": diag}
+
+    def step_diagnostic(self, job) -> float:
+        """eta m sigma_max(B_t)^2 from the iterate's B_t (an estimate of B*); above 2 the
+        fixed step is too long (Gaussian A_k, E[A_k^T A_k] = m I)."""
+        req = job["req"]
+        Bt = self.torch.empty((req.q, req.r), dtype=self.torch.float32, device=self.device)
+        self.lib.altgdmin_get(job["h"], None, Bt)
+        eta = self.lib.altgdmin_status(job["h"])["eta"]
+        sv = np.linalg.svd(Bt.double().cpu().numpy(), compute_uv=False)
+        return float(eta * req.m * sv[0] ** 2)
 
     def release(self, job) -> None:
         """Destroy the handle and drop the job's device buffers (cancellation)."""
@@ -376,18 +461,19 @@ class GpuExecutor:
 
 
 def calibrate_rate(executor, requests, budget_bytes: int, poll_every: int = 10, tol: float = 1e-7,
-                   max_iters: int = 300, max_active: Optional[int] = None) -> float:
+                   max_iters: int = 300, max_active: Optional[int] = None, **policy) -> float:
     """Closed-loop throughput (all requests present at t = 0), in solves/s.  With
-    max_active = 1 the requests are solved one after the other (no batching)."""
+    max_active = 1 the requests are solved one after the other (no batching).
+    `policy`: the Scheduler's retirement and retry arguments."""
     reqs = [dataclasses.replace(r, arrival=0.0) for r in requests]
-    rep = Scheduler(executor, budget_bytes, poll_every, tol, max_iters, max_active=max_active).run(reqs)
+    rep = Scheduler(executor, budget_bytes, poll_every, tol, max_iters, max_active=max_active, **policy).run(reqs)
     return rep.summary()["solves_per_s"]
 
 
 def load_sweep(executor, requests, saturated: float, loads: Sequence[float], budget_bytes: int, seed: int,
                poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
                clock: Callable[[], float] = time.perf_counter, sleep: Callable[[float], None] = time.sleep,
-               log=None) -> Dict[str, dict]:
+               log=None, **policy) -> Dict[str, dict]:
     """The same requests under seeded Poisson arrivals at each load x the closed-loop
     throughput `saturated`; per load: the rate, solves/s, p50 / p99 latency and the
     converged fraction."""
@@ -396,7 +482,8 @@ def load_sweep(executor, requests, saturated: float, loads: Sequence[float], bud
         rate = ld * saturated
         arr = inst.poisson_arrivals(len(requests), rate, seed)
         reqs = [dataclasses.replace(r, arrival=float(a)) for r, a in zip(requests, arr)]
-        s = Scheduler(executor, budget_bytes, poll_every, tol, max_iters, clock=clock, sleep=sleep).run(reqs).summary()
+        s = Scheduler(executor, budget_bytes, poll_every, tol, max_iters, clock=clock, sleep=sleep,
+                      **policy).run(reqs).summary()
         out[f"{ld:g}"] = {"arrival_rate_per_s": rate, "solves_per_s": s["solves_per_s"],
                           "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
                           "converged_fraction": s["converged_fraction"], "error_violations": s["error_violations"]}
@@ -409,38 +496,43 @@ def load_sweep(executor, requests, saturated: float, loads: Sequence[float], bud
 def serve(count: int = 512, seed: int = 231103828, budget_gib: float = 32.0, load: float = 0.8,
           rate: Optional[float] = None, poll_every: int = 10, tol: float = 1e-7, max_iters: int = 300,
           calibration_count: Optional[int] = None, sequential: bool = True, bf16_mixed: bool = True,
-          sweep: Sequence[float] = (), log=None) -> dict:
+          sweep: Sequence[float] = (), log=None, retry_step_limit: Optional[float] = 2.0) -> dict:
     """Serve `count` seeded requests on the GPU and return the summary.
 
     Without an explicit `rate`, the arrival rate is `load` times the closed-loop
     throughput of the first `calibration_count` requests (default: all of them);
-    `sweep` adds runs at those other multiples of it.
+    `sweep` adds runs at those other multiples of it.  A request that diverges or
+    stalls with a step diagnostic above retry_step_limit is retried once with the
+    step scaled to a diagnostic of 1 (None: no retries).
     """
+    policy = {"retry_step_limit": retry_step_limit}
     ex = GpuExecutor(tol=tol, max_iters=max_iters, bf16_mixed=bf16_mixed)
     reqs = inst.serving_requests(count, seed)
     budget = int(budget_gib * 2**30)
     sat = None
     if rate is None:
         cal = reqs[: calibration_count or count]
-        sat = calibrate_rate(ex, cal, budget, poll_every, tol, max_iters)
+        sat = calibrate_rate(ex, cal, budget, poll_every, tol, max_iters, **policy)
         rate = load * sat
         if log:
             log(f"closed-loop throughput {sat:.2f} solves/s over {len(cal)} requests; arrival rate {rate:.2f}/s")
     arr = inst.poisson_arrivals(count, rate, seed)
     for r, a in zip(reqs, arr):
         r.arrival = float(a)
-    rep = Scheduler(ex, budget, poll_every, tol, max_iters).run(reqs)
+    rep = Scheduler(ex, budget, poll_every, tol, max_iters, **policy).run(reqs)
     out = rep.summary()
     out.update({"arrival_rate_per_s": rate, "closed_loop_solves_per_s": sat, "load": load if sat else None,
                 "tol_resid": tol, "max_iters": max_iters, "poll_every": poll_every, "seed": seed,
-                "bf16_form": "mixed" if bf16_mixed else "hi+lo"})
+                "bf16_form": "mixed" if bf16_mixed else "hi+lo", "retry_step_limit": retry_step_limit})
     if sequential and sat:
         # the same requests solved one at a time through the same executor (no batching)
-        seq = calibrate_rate(ex, reqs[: calibration_count or count], budget, poll_every, tol, max_iters, max_active=1)
+        seq = calibrate_rate(ex, reqs[: calibration_count or count], budget, poll_every, tol, max_iters, max_active=1,
+                             **policy)
         out["sequential_solves_per_s"] = seq
         out["batching_speedup"] = sat / seq if seq > 0 else None
         if log:
             log(f"one request at a time: {seq:.2f} solves/s (batching speedup {sat / seq:.2f}x)")
     if sweep and sat:
-        out["load_sweep"] = load_sweep(ex, reqs, sat, sweep, budget, seed, poll_every, tol, max_iters, log=log)
+        out["load_sweep"] = load_sweep(ex, reqs, sat, sweep, budget, seed, poll_every, tol, max_iters, log=log,
+                                       **policy)
     return out

@@ -103,3 +103,26 @@ def test_small_serving_run(lib, torch_dev):
     mixed = [o for o in rep.outcomes if o.idx == reqs[3].idx][0]
     assert rep1.outcomes[0].iterations == mixed.iterations
     assert rep1.outcomes[0].error == mixed.error
+
+
+def test_too_long_step_is_caught_and_retried(lib, torch_dev):
+    """A request whose initialisation is so accurate that the fixed step of Sec. 2.6 is
+    too long (n = 128, q = 2048, m = 128, r = 2: eta m sigma_max(B*)^2 near 3, so the
+    error grows and then oscillates) is retired as diverged or stalled; the retry, with
+    the step scaled by the diagnostic read from the iterate, converges."""
+    from paper_2311_03824_amd.serve import GpuExecutor, Scheduler
+    req = inst.ServeRequest(idx=0, n=128, q=2048, m=128, r=2, rho=1, a_format="f32", seed=20231103)
+    ex = GpuExecutor(tol=1e-7, max_iters=300)
+    budget = 2 * ex.footprint(req)
+    print("\ncase: one request, no retry", flush=True)
+    rep = Scheduler(ex, budget, poll_every=10, tol=1e-7, max_iters=300).run([req])
+    o = rep.outcomes[0]
+    print(o, flush=True)
+    assert not o.converged and (o.diverged or o.stalled) and o.eta_m_sigma2 > 2.0
+    assert o.iterations < 300
+    print("case: one request, retry when the step diagnostic exceeds 2", flush=True)
+    rep = Scheduler(ex, budget, poll_every=10, tol=1e-7, max_iters=300, retry_step_limit=2.0).run([req])
+    o = rep.outcomes[0]
+    print(o, flush=True)
+    # the retry scales the step by 1 / (eta m sigma_max(B_t)^2), B_t from the stalled iterate
+    assert o.converged and o.attempts == 2 and 0.5 < o.eta_m_sigma2 < 1.5 and o.error <= 1e-6

@@ -130,7 +130,8 @@ def test_scheduler_caps_iterations_and_reports_non_convergence():
     reqs = _reqs(6)
     conv = {r.idx: (None if r.idx == 2 else 20) for r in reqs}
     ex = MockExecutor(clk, conv)
-    rep = Scheduler(ex, 1 << 50, poll_every=7, tol=1e-7, max_iters=50, clock=clk, sleep=clk.sleep).run(reqs)
+    rep = Scheduler(ex, 1 << 50, poll_every=7, tol=1e-7, max_iters=50, clock=clk, sleep=clk.sleep,
+                    stall_polls=0).run(reqs)
     o = {x.idx: x for x in rep.outcomes}
     assert not o[2].converged and o[2].iterations == 56          # first poll at or past the cap
     assert all(o[i].converged and o[i].iterations == 21 for i in o if i != 2)
@@ -354,7 +355,7 @@ def test_diverging_requests_are_retired():
     }
     ex = Trajectory(clock, traj)
     reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(5)]
-    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-12, max_iters=100,
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-12, max_iters=100, stall_polls=0,
                     clock=clock, sleep=clock.sleep).run(reqs)
     o = {x.idx: x for x in rep.outcomes}
     assert o[0].diverged and o[0].iterations == 40 and not o[0].converged
@@ -370,9 +371,94 @@ def test_divergence_check_can_be_switched_off():
     ex = Trajectory(clock, {0: lambda p: 1e-3 * 2.0 ** p, 1: lambda p: float("inf")})
     reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(2)]
     rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-12, max_iters=60, diverge_polls=0,
-                    clock=clock, sleep=clock.sleep).run(reqs)
+                    stall_polls=0, clock=clock, sleep=clock.sleep).run(reqs)
     o = {x.idx: x for x in rep.outcomes}
     assert not o[0].diverged and o[0].iterations == 60
     assert o[1].diverged and o[1].iterations == 10        # a non-finite residual always ends the request
     with pytest.raises(ValueError):
         Scheduler(None, 1, diverge_polls=-1)
+
+
+def test_stalled_requests_are_retired():
+    """A residual that reaches no new minimum (by 1 %) for stall_polls polls retires the
+    request: as stalled above diverge_floor (a flat residual, and an oscillation whose
+    polls see one phase only), as at_floor below it (the rounding floor); a slow but
+    steady decrease runs on."""
+    clock = Clock()
+    traj = {
+        0: lambda p: 3e-2,                                     # flat
+        1: lambda p: 3e-2 * (1.0 if p % 2 else 0.9),           # oscillates: best at poll 2, then never beaten
+        2: lambda p: 1e-2 * 0.98 ** p,                         # 2 % per poll: keeps going
+        3: lambda p: 1e-6,                                     # flat below the floor
+    }
+    ex = Trajectory(clock, traj)
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(4)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-12, max_iters=200, stall_polls=6,
+                    clock=clock, sleep=clock.sleep).run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert o[0].stalled and o[0].iterations == 70            # best at poll 1, six polls without a new one
+    assert o[1].stalled and o[1].iterations == 80            # best at poll 2
+    assert not o[2].stalled and o[2].iterations == 200
+    assert not o[3].stalled and o[3].at_floor and o[3].iterations == 70
+    s = rep.summary()
+    assert s["stalled"] == 2 and s["at_floor"] == 1 and s["not_converged"] == 4
+    assert {d["idx"]: d["why"] for d in s["not_converged_detail"]} == {0: "stalled", 1: "stalled", 2: "iteration cap",
+                                                                      3: "at floor"}
+
+
+class StepSensitive(MockExecutor):
+    """Requests with an odd index start with a step diagnostic of 3 (too long): they
+    oscillate until the step is scaled below 2 / 3 of the original; every request with a
+    diagnostic below 2 converges after 30 iterations, except index 2, which stalls
+    whatever its step (a failure the retry cannot mend)."""
+
+    def __init__(self, clock):
+        super().__init__(clock, {})
+        self.started = []
+
+    def _diag(self, req):
+        return (3.0 if req.idx % 2 else 0.8) * req.eta_scale
+
+    def start(self, req):
+        self.started.append((req.idx, req.eta_scale))
+        return super().start(req)
+
+    def poll(self, jobs):
+        out = []
+        for j in jobs:
+            ok = self._diag(j["req"]) < 2.0 and j["req"].idx != 2
+            out.append((j["it"], 1e-9 if ok and j["it"] >= 30 else (3e-2 if (j["it"] // 10) % 2 else 2e-2)))
+        return out
+
+    def step_diagnostic(self, job):
+        return self._diag(job["req"])
+
+    def finish(self, job):
+        super().finish(job)
+        return 1e-9, {"eta_m_sigma2": self._diag(job["req"])}
+
+
+def test_too_long_steps_are_retried_with_a_shorter_step():
+    clock = Clock()
+    ex = StepSensitive(clock)
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(4)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, tol=1e-7, max_iters=300, stall_polls=4,
+                    retry_step_limit=2.0, clock=clock, sleep=clock.sleep).run(reqs)
+    o = {x.idx: x for x in rep.outcomes}
+    assert len(o) == 4 and o[0].converged and o[0].attempts == 1
+    assert o[1].converged and o[3].converged and o[1].attempts == 2 and o[3].attempts == 2
+    assert o[1].iterations == 30 and o[1].eta_m_sigma2 == pytest.approx(1.0)    # scaled by 1 / 3
+    assert (1, pytest.approx(1 / 3)) in ex.started and (3, pytest.approx(1 / 3)) in ex.started
+    # index 2 stalls with a diagnostic of 0.8: not a long step, so no retry
+    assert o[2].stalled and o[2].attempts == 1 and o[2].step_diag == pytest.approx(0.8)
+    assert ex.in_use == 0
+    s = rep.summary()
+    assert s["retried"] == 2 and s["converged_after_retry"] == 2 and s["stalled"] == 1
+    # without retries the odd requests end as stalled too
+    ex2 = StepSensitive(Clock())
+    rep2 = Scheduler(ex2, budget_bytes=1 << 50, poll_every=10, tol=1e-7, max_iters=300, stall_polls=4,
+                     clock=ex2.clock, sleep=ex2.clock.sleep).run(reqs)
+    s2 = rep2.summary()
+    assert s2["stalled"] == 3 and s2["converged_fraction"] == 0.25 and s2["retried"] == 0
+    with pytest.raises(ValueError):
+        Scheduler(None, 1, retry_step_limit=0.5)
