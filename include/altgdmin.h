@@ -214,15 +214,24 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
 
 /* Autotuner (with ALTGDMIN_FLAG_AUTOTUNE): the column-kernel unroll JU (columns
  * per load group, 1, 2, 4 or 8) and the A_k U pipeline depth AUD (1, 2, 4 or 8) chosen for
- * this handle; 0 means the default instantiation.  The choice is made once per
+ * this handle; 0 means the default instantiation, -1 the default instantiation
+ * with cached loads of A.  Without the autotuner every handle reports 0, or -1
+ * when the plane of A that the column passes stream (4 bytes per element, 2 in
+ * the mixed BF16 form) takes at most 200 MiB, so that the Infinity Cache keeps
+ * it between passes; otherwise A is read with non-temporal loads.  With the
+ * autotuner the cached default is one more timed candidate.  The environment
+ * variable ALTGDMIN_LOAD_POLICY=stream|cached forces the load policy of the
+ * default instantiations (for tests; the batched altgdmin_step_many applies the
+ * same 200 MiB rule to all its problems together).  The choice is made once per
  * (GPU architecture, A format, n, q, m, r, rho) in a process by timing each
  * variant three times on the problem's own data (A_k U from a fixed orthonormal
  * U; the column kernel as in a GDmin iteration, from an empty support) before
  * the initialisation; with the environment variable ALTGDMIN_TUNE_CACHE naming
  * a file, choices are read from and appended to it as JSON lines keyed by the
  * architecture.  ALTGDMIN_TUNE_FORCE="JU,AUD" takes the given variants without
- * timing (JU = 8 falls back to 4 above 512 rows).  Every variant computes the
- * same bits.  Host call. */
+ * timing (JU = 8 falls back to 4 above 512 rows; -1 selects the cached
+ * default).  Every variant and both load policies compute the same bits.  Host
+ * call. */
 int altgdmin_tuning(altgdmin_handle* h, int32_t* col_unroll, int32_t* au_depth);
 
 /* Device bytes of the launch tables altgdmin_step_many needs for these handles (host call). */

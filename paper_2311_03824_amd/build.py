@@ -19,11 +19,13 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libaltgdmin.so")
 ARCH = os.environ.get("ALTGDMIN_ARCH", "gfx950")
-# (source, extra flags, object): k_column.hip is compiled twice, the second time
-# for the autotuned kernel variants only, so the two halves build in parallel.
+# (source, extra flags, object): k_column.hip is compiled three times, the second
+# time for the autotuned kernel variants only and the third for the cached-load
+# instantiations, so the parts build in parallel.
 SOURCES = [
     ("k_column.hip", ["-DALTG_PART=1"], "k_column.o"),
     ("k_column.hip", ["-DALTG_PART=2"], "k_column_tuned.o"),
+    ("k_column.hip", ["-DALTG_PART=3"], "k_column_cached.o"),
     ("k_small.hip", [], "k_small.o"),
     ("k_gen.hip", [], "k_gen.o"),
     ("k_fourier.hip", [], "k_fourier.o"),

@@ -374,12 +374,12 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
 // The column and A_k U launches of a solve, through the autotuned variant when
 // one was chosen for this problem's format.
 hipError_t col_launch(const altgdmin_handle* h, int fmt, const ColArgs& a, hipStream_t st) {
-  if (h->col_unroll && fmt == h->colfmt && a.waves == kWaves) return launch_col_tuned(fmt, h->col_unroll, a, st);
-  return launch_col(fmt, a, st);
+  if (h->col_unroll > 0 && fmt == h->colfmt && a.waves == kWaves) return launch_col_tuned(fmt, h->col_unroll, a, st);
+  return launch_col(fmt, a, st, h->col_unroll < 0 ? POL_CACHED : POL_STREAM);
 }
 hipError_t au_launch(const altgdmin_handle* h, int fmt, const AUArgs& a, hipStream_t st) {
-  if (h->au_depth && fmt == h->fmt) return launch_au_tuned(fmt, h->au_depth, a, st);
-  return launch_au(fmt, a, st);
+  if (h->au_depth > 0 && fmt == h->fmt) return launch_au_tuned(fmt, h->au_depth, a, st);
+  return launch_au(fmt, a, st, h->au_depth < 0 ? POL_CACHED : POL_STREAM);
 }
 
 // ---- autotuner: the loads in flight of the two streaming kernels, per
@@ -435,16 +435,34 @@ void tune_cache_append(const TuneKey& k, int ju, int aud, float col_ms, float au
 
 ColArgs col_args(const altgdmin_handle* h);
 
+// Load policy of A (the same bits either way): ordinary loads, which the 256 MB
+// Infinity Cache keeps between the passes, when the plane the column passes
+// stream fits in kCacheBudget; non-temporal loads otherwise.  The environment
+// variable ALTGDMIN_LOAD_POLICY=stream|cached forces one.
+constexpr size_t kCacheBudget = 200ull << 20;
+size_t streamed_plane_bytes(const altgdmin_problem& p, int colfmt) {
+  const size_t eb = colfmt == FMT_F32 || colfmt == FMT_BF16X2 ? 4 : colfmt == FMT_BF16MIX ? 2 : 0;
+  return eb * (size_t)p.q * (size_t)p.n * (size_t)p.lda;
+}
+int load_policy(size_t bytes) {
+  if (const char* f = std::getenv("ALTGDMIN_LOAD_POLICY")) {
+    if (!std::strcmp(f, "stream")) return POL_STREAM;
+    if (!std::strcmp(f, "cached")) return POL_CACHED;
+  }
+  return bytes > 0 && bytes <= kCacheBudget ? POL_CACHED : POL_STREAM;
+}
+
 int autotune(altgdmin_handle* h, hipStream_t st) {
   const altgdmin_problem& p = h->prob;
   // ALTGDMIN_TUNE_FORCE="JU,AUD" skips the timing and takes these variants (tests)
   if (const char* force = std::getenv("ALTGDMIN_TUNE_FORCE")) {
     int ju = 0, aud = 0;
-    if (std::sscanf(force, "%d,%d", &ju, &aud) != 2 || (ju != 1 && ju != 2 && ju != 4 && ju != 8) ||
-        (aud != 1 && aud != 2 && aud != 4 && aud != 8))
-      return fail(ALTGDMIN_EINVAL, "ALTGDMIN_TUNE_FORCE must be JU,AUD with JU, AUD in {1, 2, 4, 8}");
+    auto ok = [](int v) { return v == -1 || v == 1 || v == 2 || v == 4 || v == 8; };
+    if (std::sscanf(force, "%d,%d", &ju, &aud) != 2 || !ok(ju) || !ok(aud))
+      return fail(ALTGDMIN_EINVAL, "ALTGDMIN_TUNE_FORCE must be JU,AUD with JU, AUD in {-1, 1, 2, 4, 8}");
     if (ju == 8 && p.m > 512) ju = 4;   // JU = 8 is built for at most two row chunks
-    h->col_unroll = h->col_waves == kWaves ? ju : 0;   // the unrolls are built for 4-wave workgroups
+    // the unrolls are built for 4-wave workgroups; -1 (the cached default) for every width
+    h->col_unroll = ju < 0 || h->col_waves == kWaves ? ju : 0;
     h->au_depth = aud;
     return ALTGDMIN_OK;
   }
@@ -487,19 +505,28 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     *ms /= 3.f;
     return e;
   };
+  // candidates: the unrolls (4-wave column workgroups only; the default alone at
+  // other widths), and, when the streamed plane fits in the cache, the default
+  // instantiation with cached loads (-1)
+  const bool cached = load_policy(streamed_plane_bytes(p, h->colfmt)) == POL_CACHED;
   int best_aud = 0, best_ju = 0;
   float best_au = 1e30f, best_col = 1e30f;
   hipError_t e = hipSuccess;
-  for (int aud : {1, 2, 4, 8}) {
+  for (int aud : {1, 2, 4, 8, -1}) {
+    if (aud < 0 && !cached) break;
     float ms = 0.f;
-    e = timed([&] { return launch_au_tuned(h->fmt, aud, au, st); }, &ms);
+    e = timed([&] { return aud > 0 ? launch_au_tuned(h->fmt, aud, au, st) : launch_au(h->fmt, au, st, POL_CACHED); },
+              &ms);
     if (e != hipSuccess) break;
     if (ms < best_au) { best_au = ms; best_aud = aud; }
   }
-  for (int ju : {1, 2, 4, 8}) {
-    if (e != hipSuccess || h->col_waves != kWaves) break;   // the unrolls are built for 4-wave workgroups
+  for (int ju : {1, 2, 4, 8, 0, -1}) {
+    if (e != hipSuccess) break;
+    if ((ju > 0 && h->col_waves != kWaves) || (ju == 0 && (h->col_waves == kWaves || !cached)) || (ju < 0 && !cached))
+      continue;
     float ms = 0.f;
-    e = timed([&] { return launch_col_tuned(h->colfmt, ju, ca, st); }, &ms);
+    e = timed([&] { return ju > 0 ? launch_col_tuned(h->colfmt, ju, ca, st)
+                                  : launch_col(h->colfmt, ca, st, ju < 0 ? POL_CACHED : POL_STREAM); }, &ms);
     if (e == hipErrorNotSupported) {   // no such instantiation for this row count: not a candidate
       e = hipSuccess;
       continue;
@@ -654,7 +681,12 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->hi_phase = (h->fmt == FMT_BF16X2 && par->bf16_hi_max > 0);
   h->colfmt = (par->flags & ALTGDMIN_FLAG_BF16_MIXED) ? FMT_BF16MIX : h->fmt;
   h->auto_rank = prob->r == 0;
-  if (h->fmt != FMT_PFOURIER) h->col_waves = choose_col_waves(h->prob);
+  if (h->fmt != FMT_PFOURIER) {
+    h->col_waves = choose_col_waves(h->prob);
+    // the default instantiations with cached loads when the streamed plane fits in
+    // the Infinity Cache (the autotuner, when on, times them against the unrolls)
+    if (load_policy(streamed_plane_bytes(h->prob, h->colfmt)) == POL_CACHED) h->col_unroll = h->au_depth = -1;
+  }
   const size_t need = carve(h, workspace);   // with r = 0, laid out for the largest rank the rule may pick
   const int r_cap = r_eff(h->prob);
   if (h->auto_rank) h->prob.r = r_cap;       // until the rank is chosen (the initialisation IHT does not use r)
@@ -1267,16 +1299,22 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
   const ColArgs* col_tab = reinterpret_cast<const ColArgs*>(dev + g.o_col);
   const GradArgs* grad_tab = reinterpret_cast<const GradArgs*>(dev + g.o_grad);
   const QRArgs* qr_tab = reinterpret_cast<const QRArgs*>(dev + g.o_qr);
+  // one load policy for the round: cached loads when the planes streamed by all
+  // the problems together fit in the Infinity Cache
+  size_t plane_bytes = 0;
+  for (int i = 0; i < count; ++i)
+    if (hs[i]->fmt != FMT_PFOURIER) plane_bytes += streamed_plane_bytes(hs[i]->prob, hs[i]->colfmt);
+  const int pol = load_policy(plane_bytes);
   for (int it = 0; it < iters; ++it) {
     for (const auto& kv : g.au_b) {
       const Bucket& b = kv.second;
       HIPCHK(launch_au_grp(b.fmt, b.inst, au_tab, reinterpret_cast<const int2*>(dev + b.off), (int)b.map.size(),
-                           b.lds, st));
+                           b.lds, st, pol));
     }
     for (const auto& kv : g.col_b) {
       const Bucket& b = kv.second;
       HIPCHK(launch_col_grp(b.fmt, b.inst, b.waves, col_tab, reinterpret_cast<const int2*>(dev + b.off),
-                            (int)b.map.size(), b.lds, st));
+                            (int)b.map.size(), b.lds, st, pol));
     }
     HIPCHK(launch_grad_grp(grad_tab, reinterpret_cast<const int4*>(dev + g.o_gm), (int)g.grad_map.size(), st));
     HIPCHK(launch_qr_grp(qr_tab, count, g.qr_lds, st));

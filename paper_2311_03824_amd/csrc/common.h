@@ -150,24 +150,36 @@ __device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane
 __device__ __forceinline__ float bf16_to_f32(uint32_t bits16) { return __uint_as_float(bits16 << 16); }
 
 // ---------------------------------------------------------------- A_k loaders
-// load(j, ch) returns rows 4*ch .. 4*ch+3 of column j of A_k.  A is streamed
-// with the non-temporal load policy: each element is read once per pass, and
-// keeping it out of the caches lets the stream run at 7.0 TB/s instead of
-// 6.15 TB/s (one 256-thread workgroup per 1.6 MB column block, measured).
+// load(j, ch) returns rows 4*ch .. 4*ch+3 of column j of A_k.  Two load
+// policies, the same values (so the same bits) either way:
+//   POL_STREAM: non-temporal loads.  Each element is read once per pass, and
+//     keeping A out of the caches lets a large A stream at 7.0 TB/s instead of
+//     6.15 TB/s (one 256-thread workgroup per 1.6 MB column block, measured).
+//   POL_CACHED: ordinary loads.  When the plane a pass streams fits in the
+//     256 MB Infinity Cache, the passes after the first (and the next
+//     iteration's) hit it: at n = 1000, m = 400, q = 125 (200 MB) the column
+//     kernel takes 0.175 instead of 0.216 ms.
+enum { POL_STREAM = 0, POL_CACHED = 1 };
 typedef float f32x4_nt __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x2_nt __attribute__((ext_vector_type(2)));
-__device__ __forceinline__ float4 ld_stream(const float* p) {
-  const f32x4_nt v = __builtin_nontemporal_load(reinterpret_cast<const f32x4_nt*>(p));
+template <int POL>
+__device__ __forceinline__ float4 ld_a(const float* p) {
+  f32x4_nt v;
+  if constexpr (POL == POL_CACHED) v = *reinterpret_cast<const f32x4_nt*>(p);
+  else v = __builtin_nontemporal_load(reinterpret_cast<const f32x4_nt*>(p));
   return make_float4(v.x, v.y, v.z, v.w);
 }
-__device__ __forceinline__ uint2 ld_stream(const uint16_t* p) {
-  const u32x2_nt v = __builtin_nontemporal_load(reinterpret_cast<const u32x2_nt*>(p));
+template <int POL>
+__device__ __forceinline__ uint2 ld_a(const uint16_t* p) {
+  u32x2_nt v;
+  if constexpr (POL == POL_CACHED) v = *reinterpret_cast<const u32x2_nt*>(p);
+  else v = __builtin_nontemporal_load(reinterpret_cast<const u32x2_nt*>(p));
   return make_uint2(v.x, v.y);
 }
 
-template <int FMT> struct ALoader;
+template <int FMT, int POL = POL_STREAM> struct ALoader;
 
-template <> struct ALoader<FMT_F32> {
+template <int POL> struct ALoader<FMT_F32, POL> {
   const float* base;
   long long lda;
   __device__ ALoader(const ColArgs& a, int k)
@@ -178,12 +190,12 @@ template <> struct ALoader<FMT_F32> {
   // FP32.  Pipelined loops keep raw_t in flight and expand at the point of use,
   // so that a conversion never waits for loads issued after it.
   typedef float4 raw_t;
-  __device__ __forceinline__ raw_t fetch(int j, int ch) const { return ld_stream(base + (long long)j * lda + 4 * ch); }
+  __device__ __forceinline__ raw_t fetch(int j, int ch) const { return ld_a<POL>(base + (long long)j * lda + 4 * ch); }
   __device__ static __forceinline__ float4 expand(raw_t v) { return v; }
   __device__ __forceinline__ float4 load(int j, int ch) const { return fetch(j, ch); }
 };
 
-template <> struct ALoader<FMT_BF16X2> {
+template <int POL> struct ALoader<FMT_BF16X2, POL> {
   const uint16_t* hi;
   const uint16_t* lo;
   long long lda;
@@ -195,8 +207,8 @@ template <> struct ALoader<FMT_BF16X2> {
         lo(static_cast<const uint16_t*>(a.Alo) + (long long)k * a.sA), lda(a.lda) {}
   typedef uint4 raw_t;   // (hi pair, lo pair)
   __device__ __forceinline__ raw_t fetch(int j, int ch) const {
-    const uint2 h = ld_stream(hi + (long long)j * lda + 4 * ch);
-    const uint2 l = ld_stream(lo + (long long)j * lda + 4 * ch);
+    const uint2 h = ld_a<POL>(hi + (long long)j * lda + 4 * ch);
+    const uint2 l = ld_a<POL>(lo + (long long)j * lda + 4 * ch);
     return make_uint4(h.x, h.y, l.x, l.y);
   }
   __device__ static __forceinline__ float4 expand(raw_t v) {
@@ -211,7 +223,7 @@ template <> struct ALoader<FMT_BF16X2> {
   __device__ __forceinline__ float4 load(int j, int ch) const { return expand(fetch(j, ch)); }
 };
 
-template <> struct ALoader<FMT_BF16HI> {
+template <int POL> struct ALoader<FMT_BF16HI, POL> {
   const uint16_t* hi;
   long long lda;
   __device__ ALoader(const ColArgs& a, int k)
@@ -219,7 +231,7 @@ template <> struct ALoader<FMT_BF16HI> {
   __device__ ALoader(const AUArgs& a, int k)
       : hi(static_cast<const uint16_t*>(a.A) + (long long)k * a.sA), lda(a.lda) {}
   typedef uint2 raw_t;
-  __device__ __forceinline__ raw_t fetch(int j, int ch) const { return ld_stream(hi + (long long)j * lda + 4 * ch); }
+  __device__ __forceinline__ raw_t fetch(int j, int ch) const { return ld_a<POL>(hi + (long long)j * lda + 4 * ch); }
   __device__ static __forceinline__ float4 expand(raw_t h) {
     return make_float4(bf16_to_f32(h.x & 0xffffu), bf16_to_f32(h.x >> 16),
                        bf16_to_f32(h.y & 0xffffu), bf16_to_f32(h.y >> 16));
@@ -266,7 +278,7 @@ __device__ __forceinline__ float word_to_normal(uint32_t x, const float* tab) {
   return (x >> 31) ? -z : z;
 }
 
-template <> struct ALoader<FMT_PHILOX> {
+template <int POL> struct ALoader<FMT_PHILOX, POL> {   // generated, not loaded: POL has no effect
   uint32_t k0, k1, col;
   const float* tab;   // LDS copy of the normal table, set by the kernel
   __device__ ALoader(const ColArgs& a, int k)

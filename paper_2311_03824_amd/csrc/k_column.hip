@@ -83,8 +83,8 @@ __device__ __forceinline__ double xwave_sum_scalar(double x, double* redd, int l
 // out = sum_{t < cnt} coef[t] * A_k[:, idx[t]]  (idx, coef in LDS), all waves get the total.
 // Each wave keeps up to 8 support columns in flight when A_k has at most 256 rows
 // (4 otherwise, and in the Philox form, where they are generated, not loaded).
-template <int FMT, int NC, int W = kWaves>
-__device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln, const int* idx,
+template <int FMT, int NC, int W = kWaves, int POL = POL_STREAM>
+__device__ __forceinline__ void gather(const ALoader<FMT, POL>& L, const Lane<NC>& ln, const int* idx,
                                        const float* coef, int cnt, float4 (&out)[NC], float* wpart,
                                        int mq, int wave) {
   constexpr int GU = (NC == 1 && FMT != FMT_PHILOX) ? 8 : 4;   // support columns in flight per wave
@@ -94,7 +94,7 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
   for (int t0 = wave; t0 < cnt; t0 += W * GU) {
     // every load is issued before any is used: clamped, always legal addresses,
     // invalid rows and slots are zeroed afterwards
-    typename ALoader<FMT>::raw_t av[GU][NC];
+    typename ALoader<FMT, POL>::raw_t av[GU][NC];
     float cf[GU];
 #pragma unroll
     for (int g = 0; g < GU; ++g) {
@@ -109,7 +109,7 @@ __device__ __forceinline__ void gather(const ALoader<FMT>& L, const Lane<NC>& ln
       const bool ok = t0 + g * W < cnt;
 #pragma unroll
       for (int c = 0; c < NC; ++c)
-        acc[c] = axpy4(cf[g], mask_rows(ALoader<FMT>::expand(av[g][c]), ok ? ln.nv[c] : 0), acc[c]);
+        acc[c] = axpy4(cf[g], mask_rows(ALoader<FMT, POL>::expand(av[g][c]), ok ? ln.nv[c] : 0), acc[c]);
     }
   }
   xwave_sum<NC, W>(acc, ln, wpart, mq, wave);
@@ -246,10 +246,15 @@ __device__ __forceinline__ float col_totals(const float (&x)[JU], int lane) {
 // reduction tree do not depend on JU, so every JU gives the same bits.
 // default loads in flight (autotuned variants pass another JU); wider workgroups
 // have more waves in flight and take fewer columns per group
-constexpr int default_ju(int nc, int w = kWaves) { return w >= 16 ? (nc == 1 ? 2 : 1) : (nc == 1 ? 4 : 2); }
+// Default loads in flight of the column passes (columns per wave per group).
+// The mixed BF16 form streams 2-byte elements, so its 8-wave workgroups keep
+// twice the columns in flight at two row chunks (0.191 -> 0.180 ms at q = 125).
+constexpr int default_ju(int nc, int w = kWaves, int fmt = FMT_F32) {
+  return w >= 16 ? (nc == 1 ? 2 : 1) : (w == 8 && nc == 2 && fmt == FMT_BF16MIX ? 4 : (nc == 1 ? 4 : 2));
+}
 
-template <int FMT, int NC, int JU, int W = kWaves>
-__device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>& ln, const float4 (&u)[NC],
+template <int FMT, int NC, int JU, int W = kWaves, int POL = POL_STREAM>
+__device__ __forceinline__ void fused_pass(const ALoader<FMT, POL>& L, const Lane<NC>& ln, const float4 (&u)[NC],
                                            int n, float* gl, const unsigned* inT, float4 (&wacc)[NC],
                                            double& gT2, int lane, int wave) {
   // the support bits of a group's columns j0, j0 + W, ... must lie in the two
@@ -258,7 +263,7 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
   constexpr int step = W * JU;
   // loads are unconditional (column clamped to n-1, chunk clamped to a legal
   // one) so that a whole group is in flight at once; consume() drops them
-  typedef typename ALoader<FMT>::raw_t raw_t;
+  typedef typename ALoader<FMT, POL>::raw_t raw_t;
   auto load = [&](int j0, raw_t (&ar)[JU][NC]) {
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
@@ -282,11 +287,11 @@ __device__ __forceinline__ void fused_pass(const ALoader<FMT>& L, const Lane<NC>
     float d[JU];
 #pragma unroll
     for (int ju = 0; ju < JU; ++ju) {
-      av[ju][0] = ALoader<FMT>::expand(ar[ju][0]);
+      av[ju][0] = ALoader<FMT, POL>::expand(ar[ju][0]);
       float s = dot4(av[ju][0], u[0]);
 #pragma unroll
       for (int c = 1; c < NC; ++c) {
-        av[ju][c] = ALoader<FMT>::expand(ar[ju][c]);
+        av[ju][c] = ALoader<FMT, POL>::expand(ar[ju][c]);
         s += dot4(av[ju][c], u[c]);
       }
       d[ju] = s;
@@ -447,7 +452,7 @@ static __device__ bool block_support_kept(const float* vals, int n, const unsign
 
 // ---------------------------------------------------------------- k_col
 
-template <int FMT, int NC, int JU, int W>
+template <int FMT, int NC, int JU, int W, int POL = POL_STREAM>
 __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char* smem) {
   constexpr int kT = 64 * W;   // threads of the workgroup
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
@@ -469,8 +474,8 @@ __device__ __forceinline__ void col_body(const ColArgs& a, int k, unsigned char*
   const int nwords = (n + 31) >> 5;
 
   constexpr int GF = gather_fmt(FMT), SF = stream_fmt(FMT);
-  ALoader<GF> L(a, k);    // A_k s_k: exact
-  ALoader<SF> Ls(a, k);   // A_k^T u and the step length: the streaming view
+  ALoader<GF, POL> L(a, k);    // A_k s_k: exact
+  ALoader<SF, POL> Ls(a, k);   // A_k^T u and the step length: the streaming view
   if constexpr (FMT == FMT_PHILOX) {
     float* tab = reinterpret_cast<float*>(smem + lay.tab);
     for (int t = tid; t < kNormalTable; t += kT) tab[t] = a.table[t];
@@ -645,22 +650,22 @@ constexpr int col_min_waves_w(int fmt, int nc, int ju, int w) {
   return col_min_waves(fmt, nc, ju) > w / 4 ? col_min_waves(fmt, nc, ju) : w / 4;
 }
 
-template <int FMT, int NC, int JU = default_ju(NC), int W = kWaves>
+template <int FMT, int NC, int JU = default_ju(NC), int W = kWaves, int POL = POL_STREAM>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_waves_w(FMT, NC, JU, W), 8))) void k_col(ColArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  col_body<FMT, NC, JU, W>(a, blockIdx.x, smem);
+  col_body<FMT, NC, JU, W, POL>(a, blockIdx.x, smem);
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
-template <int FMT, int NC, int W = kWaves>
-__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_waves_w(FMT, NC, default_ju(NC, W), W), 8))) void k_col_grp(
+template <int FMT, int NC, int W = kWaves, int POL = POL_STREAM>
+__global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_waves_w(FMT, NC, default_ju(NC, W, FMT), W), 8))) void k_col_grp(
     const ColArgs* tab, const int2* map) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const ColArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  col_body<FMT, NC, default_ju(NC, W), W>(a, mp.y, smem);
+  col_body<FMT, NC, default_ju(NC, W, FMT), W, POL>(a, mp.y, smem);
 }
 
 // ---------------------------------------------------------------- k_au
@@ -670,7 +675,7 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_
 // and columns j = w % js, w % js + js, ... where js = 4 / nch (1 when nch > 2);
 // each lane holds 4 rows x R accumulators.  Partial P_k of the waves sharing a
 // chunk are added in a fixed order (in LDS when P_k fits, else in global memory).
-template <int FMT, int R, int AUD>
+template <int FMT, int R, int AUD, int POL = POL_STREAM>
 __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* smem) {
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r;
@@ -682,7 +687,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   double* Ll = reinterpret_cast<double*>(smem + lay.L);
   double* Gil = reinterpret_cast<double*>(smem + lay.Gi);
   double* yl = reinterpret_cast<double*>(smem + lay.y);
-  ALoader<FMT> L(a, k);
+  ALoader<FMT, POL> L(a, k);
   if constexpr (FMT == FMT_PHILOX) {
     float* tab = reinterpret_cast<float*>(smem + lay.tab);
     for (int t = tid; t < kNormalTable; t += kThreads) tab[t] = a.table[t];
@@ -713,7 +718,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   constexpr int RP = (R + 3) / 4 * 4;
   float* Uw = reinterpret_cast<float*>(smem + lay.P) + wave * 64 * RP;   // shares the P region
   const float* U = a.U;
-  typedef typename ALoader<FMT>::raw_t raw_t;
+  typedef typename ALoader<FMT, POL>::raw_t raw_t;
   auto fetch = [&](int j, raw_t& a4) {
     const int jc = j < n ? j : n - 1;   // clamped: always a legal address
     a4 = L.fetch(jc, chc);
@@ -767,7 +772,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
         const int tt = t + d;
         if ((tt & 63) == 0) stage(tt);
         fetch(jw + (tt + AUD) * js, buf[(d + AUD) % NB]);
-        fma_col(ALoader<FMT>::expand(buf[d]), tt & 63);
+        fma_col(ALoader<FMT, POL>::expand(buf[d]), tt & 63);
       }
     }
 #pragma unroll
@@ -776,7 +781,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
       if (tt < cols) {
         if ((tt & 63) == 0) stage(tt);
         if (d + AUD < NB) fetch(jw + (tt + AUD) * js, buf[d + AUD]);
-        fma_col(ALoader<FMT>::expand(buf[d]), tt & 63);
+        fma_col(ALoader<FMT, POL>::expand(buf[d]), tt & 63);
       }
     }
   }
@@ -867,21 +872,21 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
 
 constexpr int kDefaultAUD = 2;   // A_k loads of the next AUD columns in flight per wave (autotuned variants differ)
 
-template <int FMT, int R, int AUD = kDefaultAUD>
+template <int FMT, int R, int AUD = kDefaultAUD, int POL = POL_STREAM>
 __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  au_body<FMT, R, AUD>(a, blockIdx.x, smem);
+  au_body<FMT, R, AUD, POL>(a, blockIdx.x, smem);
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
-template <int FMT, int R>
+template <int FMT, int R, int POL = POL_STREAM>
 __global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const int2* map) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  au_body<FMT, R, kDefaultAUD>(a, mp.y, smem);
+  au_body<FMT, R, kDefaultAUD, POL>(a, mp.y, smem);
 }
 
 #if !defined(ALTG_PART) || ALTG_PART == 1
@@ -936,8 +941,12 @@ static const aug_fn kAUGrpTable[4][kRMax / 2] = {AUG_ROW(FMT_F32), AUG_ROW(FMT_B
 
 bool au_supported(int m, int r) { return m >= 1 && m <= 256 * kNCMax && r >= 1 && r <= kRMax; }
 
-hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
+hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st, int pol) {
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX) return hipErrorInvalidValue;
+  if (pol == POL_CACHED) {   // the cached-load instantiation when one is built, else the streaming one
+    const hipError_t e = launch_col_cached(fmt, a, st);
+    if (e != hipErrorNotSupported) return e;
+  }
   if (a.waves == 8 || a.waves == 16) return launch_col_wide(fmt, a, st);
   if (a.waves != 0 && a.waves != kWaves) return hipErrorInvalidValue;
   const int nc = (a.m + 255) / 256;
@@ -947,8 +956,12 @@ hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
+hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st, int pol) {
   if (fmt < FMT_F32 || fmt > FMT_PHILOX) return hipErrorInvalidValue;   // A_k U is exact in every form
+  if (pol == POL_CACHED) {
+    const hipError_t e = launch_au_cached(fmt, a, st);
+    if (e != hipErrorNotSupported) return e;
+  }
   const int ri = (a.r + 1) / 2 - 1;
   const AULayout lay(a.m, a.r, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
@@ -957,8 +970,12 @@ hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks, size_t lds,
-                          hipStream_t st) {
+                          hipStream_t st, int pol) {
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX) return hipErrorInvalidValue;
+  if (pol == POL_CACHED) {
+    const hipError_t e = launch_col_grp_cached(fmt, nc, waves, tab, map, blocks, lds, st);
+    if (e != hipErrorNotSupported) return e;
+  }
   if (waves == 8 || waves == 16) return launch_col_grp_wide(fmt, nc, waves, tab, map, blocks, lds, st);
   if (waves != kWaves) return hipErrorInvalidValue;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
@@ -966,8 +983,13 @@ hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const 
   return hipGetLastError();
 }
 
-hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st) {
+hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st,
+                         int pol) {
   if (fmt < FMT_F32 || fmt > FMT_PHILOX) return hipErrorInvalidValue;
+  if (pol == POL_CACHED) {
+    const hipError_t e = launch_au_grp_cached(fmt, rmax, tab, map, blocks, lds, st);
+    if (e != hipErrorNotSupported) return e;
+  }
   const int ri = (rmax + 1) / 2 - 1;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kAUGrpTable[fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab, map);
@@ -1037,8 +1059,8 @@ static int tuned_slot(int v, const int (&vals)[4]) {
 
 // Wide column workgroups (8 and 16 waves) with the default loads in flight of
 // their width; 16 waves are built for at most two row chunks (m <= 512).
-#define COLW_F(F, W) {k_col<F, 1, default_ju(1, W), W>, k_col<F, 2, default_ju(2, W), W>, \
-                      k_col<F, 3, default_ju(3, W), W>, k_col<F, 4, default_ju(4, W), W>}
+#define COLW_F(F, W) {k_col<F, 1, default_ju(1, W, F), W>, k_col<F, 2, default_ju(2, W, F), W>, \
+                      k_col<F, 3, default_ju(3, W, F), W>, k_col<F, 4, default_ju(4, W, F), W>}
 #define COLW16_F(F) {k_col<F, 1, default_ju(1, 16), 16>, k_col<F, 2, default_ju(2, 16), 16>, nullptr, nullptr}
 static const col_fn2 kColWide[2][5][kNCMax] = {
     {COLW_F(FMT_F32, 8), COLW_F(FMT_BF16X2, 8), COLW_F(FMT_BF16HI, 8), COLW_F(FMT_PHILOX, 8), COLW_F(FMT_BF16MIX, 8)},
@@ -1098,5 +1120,77 @@ hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st) {
   return hipGetLastError();
 }
 #endif  // ALTG_PART == 2
+
+#if ALTG_PART == 3
+// Cached-load (POL_CACHED) instantiations of the default column and A_k U
+// kernels, for problems whose streamed plane fits in the Infinity Cache: 4- and
+// 8-wave column workgroups, the single-problem and the batched launches.  The
+// Philox form loads no A and has none (its launches take the streaming kernels).
+typedef void (*col_fn3)(ColArgs);
+typedef void (*colg_fn3)(const ColArgs*, const int2*);
+typedef void (*au_fn3)(AUArgs);
+typedef void (*aug_fn3)(const AUArgs*, const int2*);
+#define COLC_F(F, W) {k_col<F, 1, default_ju(1, W, F), W, POL_CACHED>, k_col<F, 2, default_ju(2, W, F), W, POL_CACHED>, \
+                      k_col<F, 3, default_ju(3, W, F), W, POL_CACHED>, k_col<F, 4, default_ju(4, W, F), W, POL_CACHED>}
+#define COLC_NONE {nullptr, nullptr, nullptr, nullptr}
+static const col_fn3 kColCached[2][5][kNCMax] = {
+    {COLC_F(FMT_F32, 4), COLC_F(FMT_BF16X2, 4), COLC_F(FMT_BF16HI, 4), COLC_NONE, COLC_F(FMT_BF16MIX, 4)},
+    {COLC_F(FMT_F32, 8), COLC_F(FMT_BF16X2, 8), COLC_F(FMT_BF16HI, 8), COLC_NONE, COLC_F(FMT_BF16MIX, 8)}};
+#define COLGC_F(F, W) {k_col_grp<F, 1, W, POL_CACHED>, k_col_grp<F, 2, W, POL_CACHED>, \
+                       k_col_grp<F, 3, W, POL_CACHED>, k_col_grp<F, 4, W, POL_CACHED>}
+static const colg_fn3 kColGrpCached[2][5][kNCMax] = {
+    {COLGC_F(FMT_F32, 4), COLGC_F(FMT_BF16X2, 4), COLGC_F(FMT_BF16HI, 4), COLC_NONE, COLGC_F(FMT_BF16MIX, 4)},
+    {COLGC_F(FMT_F32, 8), COLGC_F(FMT_BF16X2, 8), COLGC_F(FMT_BF16HI, 8), COLC_NONE, COLGC_F(FMT_BF16MIX, 8)}};
+#define AUC_F(F) {k_au<F, 2, kDefaultAUD, POL_CACHED>, k_au<F, 4, kDefaultAUD, POL_CACHED>, \
+                  k_au<F, 6, kDefaultAUD, POL_CACHED>, k_au<F, 8, kDefaultAUD, POL_CACHED>, \
+                  k_au<F, 10, kDefaultAUD, POL_CACHED>, k_au<F, 12, kDefaultAUD, POL_CACHED>, \
+                  k_au<F, 14, kDefaultAUD, POL_CACHED>, k_au<F, 16, kDefaultAUD, POL_CACHED>}
+static const au_fn3 kAUCached[3][kRMax / 2] = {AUC_F(FMT_F32), AUC_F(FMT_BF16X2), AUC_F(FMT_BF16HI)};
+#define AUGC_F(F) {k_au_grp<F, 2, POL_CACHED>, k_au_grp<F, 4, POL_CACHED>, k_au_grp<F, 6, POL_CACHED>, \
+                   k_au_grp<F, 8, POL_CACHED>, k_au_grp<F, 10, POL_CACHED>, k_au_grp<F, 12, POL_CACHED>, \
+                   k_au_grp<F, 14, POL_CACHED>, k_au_grp<F, 16, POL_CACHED>}
+static const aug_fn3 kAUGrpCached[3][kRMax / 2] = {AUGC_F(FMT_F32), AUGC_F(FMT_BF16X2), AUGC_F(FMT_BF16HI)};
+
+static int cached_width_row(int waves) { return waves == 8 ? 1 : (waves == 0 || waves == kWaves ? 0 : -1); }
+
+hipError_t launch_col_cached(int fmt, const ColArgs& a, hipStream_t st) {
+  const int nc = (a.m + 255) / 256, wi = cached_width_row(a.waves);
+  if (fmt < FMT_F32 || fmt > FMT_BF16MIX || wi < 0 || nc < 1 || nc > kNCMax || !kColCached[wi][fmt][nc - 1])
+    return hipErrorNotSupported;
+  const int w = wi ? 8 : kWaves;
+  const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, 0, w);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColCached[wi][fmt][nc - 1], dim3(a.q), dim3(64 * w), lay.total, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_col_grp_cached(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
+                                 size_t lds, hipStream_t st) {
+  const int wi = cached_width_row(waves);
+  if (fmt < FMT_F32 || fmt > FMT_BF16MIX || wi < 0 || nc < 1 || nc > kNCMax || !kColGrpCached[wi][fmt][nc - 1])
+    return hipErrorNotSupported;
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kColGrpCached[wi][fmt][nc - 1], dim3(blocks), dim3(64 * (wi ? 8 : kWaves)), lds, st, tab, map);
+  return hipGetLastError();
+}
+
+hipError_t launch_au_cached(int fmt, const AUArgs& a, hipStream_t st) {
+  if (fmt < FMT_F32 || fmt > FMT_BF16HI) return hipErrorNotSupported;
+  const int ri = (a.r + 1) / 2 - 1;
+  const AULayout lay(a.m, a.r, 0);
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kAUCached[fmt][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_au_grp_cached(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds,
+                                hipStream_t st) {
+  if (fmt < FMT_F32 || fmt > FMT_BF16HI) return hipErrorNotSupported;
+  const int ri = (rmax + 1) / 2 - 1;
+  (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
+  hipLaunchKernelGGL(kAUGrpCached[fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab, map);
+  return hipGetLastError();
+}
+#endif  // ALTG_PART == 3
 
 }  // namespace altg

@@ -39,20 +39,31 @@ struct GradArgs {
   const int* skip;   // if non-null and *skip != 0, the workgroup does nothing
 };
 
-hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st);
+// pol: POL_STREAM (non-temporal loads of A) or POL_CACHED (ordinary loads; for a
+// streamed plane that fits in the Infinity Cache).  The same bits either way;
+// a form without a cached instantiation (Philox, 16-wave columns) streams.
+hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st, int pol = 0);
 // autotuned variants (FP32 and BF16X2 planes): JU in {1, 2, 3}, AUD in {1, 2, 4}
 hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st);
 hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st);
-hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st);
+hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st, int pol = 0);
 bool au_supported(int m, int r);
 hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks, size_t lds,
-                          hipStream_t st);
+                          hipStream_t st, int pol = 0);
+// the cached-load instantiations (hipErrorNotSupported where none is built)
+hipError_t launch_col_cached(int fmt, const ColArgs& a, hipStream_t st);
+hipError_t launch_col_grp_cached(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
+                                 size_t lds, hipStream_t st);
+hipError_t launch_au_cached(int fmt, const AUArgs& a, hipStream_t st);
+hipError_t launch_au_grp_cached(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds,
+                                hipStream_t st);
 // column workgroups of 8 or 16 waves (a.waves); built for 8 waves, and 16 waves at m <= 512
 bool col_wide_built(int waves, int nc);
 hipError_t launch_col_wide(int fmt, const ColArgs& a, hipStream_t st);
 hipError_t launch_col_grp_wide(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
                                size_t lds, hipStream_t st);
-hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st);
+hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st,
+                         int pol = 0);
 size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox, int waves = kWaves);
 size_t au_lds_bytes(int m, int r, int philox);
 hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,

@@ -17,7 +17,7 @@ import pytest
 
 from paper_2311_03824_amd import build as B
 
-OBJS = ["k_column.o", "k_column_tuned.o", "k_small.o", "k_gen.o", "k_fourier.o", "k_rank.o"]
+OBJS = ["k_column.o", "k_column_tuned.o", "k_column_cached.o", "k_small.o", "k_gen.o", "k_fourier.o", "k_rank.o"]
 SAN = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined"]
 
 

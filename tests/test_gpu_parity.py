@@ -518,8 +518,9 @@ def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatc
     a = _solve(lib, torch, inst, 12, bf16=bf16)
     b = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE)
     c = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE | lib.FLAG_EAGER)
-    assert a["tuning"] == {"col_unroll": 0, "au_depth": 0}
-    assert b["tuning"]["col_unroll"] in (1, 2, 4, 8) and b["tuning"]["au_depth"] in (1, 2, 4, 8)
+    # a small A (the streamed plane fits in the cache): the defaults with cached loads
+    assert a["tuning"] == {"col_unroll": -1, "au_depth": -1}
+    assert b["tuning"]["col_unroll"] in (-1, 1, 2, 4, 8) and b["tuning"]["au_depth"] in (-1, 1, 2, 4, 8)
     assert c["tuning"] == b["tuning"]              # the second init reuses the process-wide choice
     for key in ("U", "Bt", "S_idx", "S_val"):
         assert np.array_equal(a[key], b[key]), key
@@ -542,7 +543,7 @@ def test_every_tuned_variant_is_bitwise_the_default(lib, torch, monkeypatch, sha
     for bf16, extra in ((False, 0), (True, lib.FLAG_BF16_MIXED)):
         monkeypatch.delenv("ALTGDMIN_TUNE_FORCE", raising=False)
         ref = _solve(lib, torch, inst, 6, bf16=bf16, flags=extra)
-        for ju, aud in ((1, 1), (2, 2), (4, 4), (8, 8), (1, 8), (8, 1)):
+        for ju, aud in ((1, 1), (2, 2), (4, 4), (8, 8), (1, 8), (8, 1), (-1, -1), (-1, 2), (4, -1)):
             monkeypatch.setenv("ALTGDMIN_TUNE_FORCE", f"{ju},{aud}")
             out = _solve(lib, torch, inst, 6, bf16=bf16, flags=extra | lib.FLAG_AUTOTUNE)
             for key in ("U", "Bt", "S_idx", "S_val"):
@@ -661,6 +662,64 @@ def test_philox_solve_matches_oracle(lib, torch):
 
 
 # ---------------------------------------------------------------- serving: batched launches
+
+@pytest.mark.parametrize("waves", ["4", "8"])
+def test_load_policies_give_the_same_bits(lib, torch, monkeypatch, waves):
+    """Non-temporal and cached loads of A compute the same bits: every form (FP32
+    plane, BF16 hi + lo, the hi-only phase, the mixed form) at 4- and 8-wave
+    column workgroups, one and two row chunks; a small A takes the cached default
+    (tuning -1), a forced stream the non-temporal one (0)."""
+    monkeypatch.setenv("ALTGDMIN_COL_WAVES", waves)
+    for shape in (dict(n=300, q=40, m=120, r=2, rho=5), dict(n=517, q=24, m=333, r=5, rho=11)):
+        inst = I.make_instance(**shape, seed=31, bf16_planes=True)
+        for bf16, extra in ((False, {}), (True, {}), (True, {"bf16_hi_max": 4}),
+                            (True, {"flags": lib.FLAG_BF16_MIXED})):
+            outs = {}
+            for pol in ("stream", "cached"):
+                monkeypatch.setenv("ALTGDMIN_LOAD_POLICY", pol)
+                outs[pol] = _solve(lib, torch, inst, 8, bf16=bf16, **extra)
+            assert outs["stream"]["tuning"] == {"col_unroll": 0, "au_depth": 0}
+            assert outs["cached"]["tuning"] == {"col_unroll": -1, "au_depth": -1}
+            for key in ("U", "Bt", "S_idx", "S_val", "log"):
+                assert np.array_equal(outs["stream"][key], outs["cached"][key]), (shape, bf16, extra, key)
+    monkeypatch.delenv("ALTGDMIN_LOAD_POLICY")
+
+
+def test_batched_cached_equals_solo_streamed(lib, torch, monkeypatch):
+    """The batched launches with cached loads (small planes) give the bits of solo
+    solves with non-temporal loads."""
+    specs = [dict(n=300, q=100, m=120, r=2, rho=5, seed=8, bf16=False),
+             dict(n=260, q=60, m=150, r=3, rho=4, seed=9, bf16=True),
+             dict(n=200, q=330, m=300, r=2, rho=3, seed=10, bf16=False)]
+    insts = [I.make_instance(n=s["n"], q=s["q"], m=s["m"], r=s["r"], rho=s["rho"], seed=s["seed"],
+                             bf16_planes=s["bf16"]) for s in specs]
+    iters = 20
+
+    def solver(inst, sp):
+        par = lib.default_params(t_max=iters, flags=lib.FLAG_BF16_MIXED if sp["bf16"] else 0)
+        if sp["bf16"]:
+            return lib.Solver(None, inst.Y32, inst.m, inst.r, inst.rho, par, A_hi=inst.A_hi, A_lo=inst.A_lo)
+        return lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, par)
+
+    monkeypatch.setenv("ALTGDMIN_LOAD_POLICY", "stream")
+    solo = []
+    for inst, sp in zip(insts, specs):
+        s = solver(inst, sp)
+        s.init().step(iters)
+        solo.append(s.get())
+        s.close()
+    monkeypatch.delenv("ALTGDMIN_LOAD_POLICY")
+    group = [solver(inst, sp).init() for inst, sp in zip(insts, specs)]
+    hs = [s.h for s in group]
+    assert all(lib.altgdmin_tuning(h)["col_unroll"] == -1 for h in hs)
+    gws = torch.empty(lib.altgdmin_group_bytes(hs) + 256, dtype=torch.uint8, device="cuda")
+    lib.altgdmin_step_many(hs, iters, gws)
+    for s, ref in zip(group, solo):
+        out = s.get()
+        for key in ("U", "Bt", "S_idx", "S_val"):
+            assert np.array_equal(out[key], ref[key]), key
+        s.close()
+
 
 @pytest.mark.parametrize("specs", [
     [dict(n=300, q=40, m=120, r=2, rho=5, seed=1, bf16=False),
