@@ -27,6 +27,8 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2311_03824_amd.roofline import au_kernel_bytes, column_kernel_bytes  # noqa: E402
+
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
 WORKLOAD = "gauss_n1000_q1000_m400_r10_rho50"
 T_ITERS = 200
@@ -34,27 +36,6 @@ T_ITERS = 200
 
 def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
-
-
-def column_kernel_bytes(n, q, m, r, rho, tau, a_bytes=4.0, gather_bytes=None):
-    """Algorithmic HBM bytes of one launch of the column kernel (tau IHT iterations + LS/gradient tail).
-
-    Per column: (tau + 1) streaming passes over A_k (m n elements), (tau + 1)
-    gathers of the rho support columns (rho m elements), y_k, P_k (m r FP32),
-    G_k^{-1} (r^2 FP64), the support in and out (2 rho (4 + 4) bytes), h_k
-    (n FP32), b_k (r FP32) and ||r_k||^2.  a_bytes: bytes per element of the
-    streaming passes; gather_bytes: of the support gathers (default a_bytes;
-    the mixed BF16 form streams 2 bytes and gathers 4).
-    """
-    gb = a_bytes if gather_bytes is None else gather_bytes
-    per_col = ((tau + 1) * m * n * a_bytes + (tau + 1) * rho * m * gb + 4 * m + 4 * m * r
-               + 8 * r * r + 16 * rho + 4 * n + 4 * r + 8)
-    return per_col * q
-
-
-def au_kernel_bytes(n, q, m, r, a_bytes=4.0):
-    """Per column: one pass over A_k, U (n r, L2-resident after the first column), P_k written, G^{-1} written."""
-    return q * (m * n * a_bytes + 4 * m * r + 8 * r * r) + 4 * n * r
 
 
 def source_hash(paths) -> str:

@@ -316,8 +316,8 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
   if (!au_supported(p->m, re)) return fail(ALTGDMIN_ENOTBUILT, "no A_k U instantiation for this (m, r)");
   const int phx = p->a_format == ALTGDMIN_A_PHILOX;
-  if (col_lds_bytes(p->n, p->m, re, p->rho, 1, phx) > kMaxLds || au_lds_bytes(p->m, re, phx) > kMaxLds)
-    return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 64 KiB of LDS per column workgroup");
+  if (col_lds_bytes(p->n, p->m, re, p->rho, 1, phx) > kColLdsMax || au_lds_bytes(p->m, re, phx) > kMaxLds)
+    return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 160 KiB of LDS per column workgroup");
   return ALTGDMIN_OK;
 }
 
@@ -331,15 +331,19 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
 // fit, falls back to the next narrower.  ALTGDMIN_COL_WAVES=4|8|16 forces a
 // width (measurements, tests).
 int choose_col_waves(const altgdmin_problem& p) {
-  int w = p.q <= 320 ? 8 : kWaves;
+  const int phx = p.a_format == ALTGDMIN_A_PHILOX;
+  // above 64 KiB of LDS (large n) a CU holds one column workgroup: 8 waves keep
+  // more loads in flight whatever q
+  const bool big = col_lds_bytes(p.n, p.m, r_eff(p), p.rho, 1, phx) > kColLdsDefault;
+  int w = p.q <= 320 || big ? 8 : kWaves;
   if (const char* f = std::getenv("ALTGDMIN_COL_WAVES")) {
     const int v = std::atoi(f);
     if (v == 4 || v == 8 || v == 16) w = v;
   }
   const int nc = (p.m + 255) / 256;
-  const int phx = p.a_format == ALTGDMIN_A_PHILOX;
   if (phx) w = std::min(w, nc == 1 ? 16 : (nc == 2 ? 8 : kWaves));   // the generator's registers: wide only at small m
-  while (w > kWaves && (!col_wide_built(w, nc) || col_lds_bytes(p.n, p.m, r_eff(p), p.rho, 1, phx, w) > kMaxLds))
+  const size_t cap = big ? kColLdsMax : kColLdsDefault;
+  while (w > kWaves && (!col_wide_built(w, nc) || col_lds_bytes(p.n, p.m, r_eff(p), p.rho, 1, phx, w) > cap))
     w /= 2;
   return w;
 }
@@ -1281,7 +1285,7 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
   for (const auto& kv : g.au_b)
     if (kv.second.lds > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
   for (const auto& kv : g.col_b)
-    if (kv.second.lds > kMaxLds) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
+    if (kv.second.lds > kColLdsMax) return fail(ALTGDMIN_ENOTBUILT, "group needs too much LDS");
   std::vector<char> buf(g.total, 0);
   auto put = [&](size_t off, const void* src, size_t bytes) { if (bytes) std::memcpy(buf.data() + off, src, bytes); };
   put(g.o_au, g.au.data(), g.au.size() * sizeof(AUArgs));

@@ -25,6 +25,8 @@
 // Pi_k v = v - P_k G_k^{-1} P_k^T v supplies z_k and M_k = Pi_k A_k of Sec. 2.2
 // without forming M_k; since Pi_k is symmetric and idempotent,
 // M_k^T (M_k s - z_k) = A_k^T Pi_k (A_k s - y_k).
+#include <mutex>
+
 #include "launch.h"
 
 namespace altg {
@@ -951,6 +953,10 @@ hipError_t launch_col(int fmt, const ColArgs& a, hipStream_t st, int pol) {
   if (a.waves != 0 && a.waves != kWaves) return hipErrorInvalidValue;
   const int nc = (a.m + 255) / 256;
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, fmt == FMT_PHILOX);
+  if (lay.total > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColTable[fmt][nc - 1], dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
@@ -978,6 +984,10 @@ hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const 
   }
   if (waves == 8 || waves == 16) return launch_col_grp_wide(fmt, nc, waves, tab, map, blocks, lds, st);
   if (waves != kWaves) return hipErrorInvalidValue;
+  if (lds > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColGrpTable[fmt][nc - 1], dim3(blocks), dim3(kThreads), lds, st, tab, map);
   return hipGetLastError();
@@ -998,6 +1008,31 @@ hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, 
 
 size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox, int waves) {
   return ColLayout(n, m, r, rho, project, philox, waves).total;
+}
+
+// Raise the dynamic LDS limit of each kernel in `fns` to kColLdsMax (null entries skipped).
+template <class F>
+static hipError_t raise_lds(const F* fns, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (fns[i]) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fns[i]),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kColLdsMax);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+hipError_t col_allow_big_lds() {
+  static std::mutex mu;
+  static bool done = false;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done) return hipSuccess;
+  hipError_t e = raise_lds(&kColTable[0][0], sizeof(kColTable) / sizeof(kColTable[0][0]));
+  if (e == hipSuccess) e = raise_lds(&kColGrpTable[0][0], sizeof(kColGrpTable) / sizeof(kColGrpTable[0][0]));
+  if (e == hipSuccess) e = col_allow_big_lds_tuned();
+  if (e == hipSuccess) e = col_allow_big_lds_cached();
+  if (e == hipSuccess) done = true;
+  return e;
 }
 size_t au_lds_bytes(int m, int r, int philox) { return AULayout(m, r, philox).total; }
 
@@ -1081,6 +1116,10 @@ hipError_t launch_col_wide(int fmt, const ColArgs& a, hipStream_t st) {
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX || nc < 1 || nc > kNCMax || !kColWide[wi][fmt][nc - 1])
     return hipErrorNotSupported;
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, fmt == FMT_PHILOX, a.waves);
+  if (lay.total > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColWide[wi][fmt][nc - 1], dim3(a.q), dim3(64 * a.waves), lay.total, st, a);
   return hipGetLastError();
@@ -1091,9 +1130,31 @@ hipError_t launch_col_grp_wide(int fmt, int nc, int waves, const ColArgs* tab, c
   const int wi = waves == 16 ? 1 : 0;
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX || nc < 1 || nc > kNCMax || !kColGrpWide[wi][fmt][nc - 1])
     return hipErrorNotSupported;
+  if (lds > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColGrpWide[wi][fmt][nc - 1], dim3(blocks), dim3(64 * waves), lds, st, tab, map);
   return hipGetLastError();
+}
+
+template <class F>
+static hipError_t raise_lds(const F* fns, size_t count) {
+  for (size_t i = 0; i < count; ++i)
+    if (fns[i]) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fns[i]),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)kColLdsMax);
+      if (e != hipSuccess) return e;
+    }
+  return hipSuccess;
+}
+
+hipError_t col_allow_big_lds_tuned() {
+  hipError_t e = raise_lds(&kColTuned[0][0][0], sizeof(kColTuned) / sizeof(kColTuned[0][0][0]));
+  if (e == hipSuccess) e = raise_lds(&kColWide[0][0][0], sizeof(kColWide) / sizeof(kColWide[0][0][0]));
+  if (e == hipSuccess) e = raise_lds(&kColGrpWide[0][0][0], sizeof(kColGrpWide) / sizeof(kColGrpWide[0][0][0]));
+  return e;
 }
 
 hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
@@ -1104,6 +1165,10 @@ hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
   const int nc = (a.m + 255) / 256;
   if (!kColTuned[row][nc - 1][slot]) return hipErrorNotSupported;   // variant not built
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, 0);
+  if (lay.total > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColTuned[row][nc - 1][slot], dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
@@ -1153,12 +1218,34 @@ static const aug_fn3 kAUGrpCached[3][kRMax / 2] = {AUGC_F(FMT_F32), AUGC_F(FMT_B
 
 static int cached_width_row(int waves) { return waves == 8 ? 1 : (waves == 0 || waves == kWaves ? 0 : -1); }
 
+hipError_t col_allow_big_lds_cached() {
+  for (size_t i = 0; i < sizeof(kColCached) / sizeof(kColCached[0][0][0]); ++i) {
+    const col_fn3 f = (&kColCached[0][0][0])[i];
+    if (!f) continue;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kColLdsMax);
+    if (e != hipSuccess) return e;
+  }
+  for (size_t i = 0; i < sizeof(kColGrpCached) / sizeof(kColGrpCached[0][0][0]); ++i) {
+    const colg_fn3 f = (&kColGrpCached[0][0][0])[i];
+    if (!f) continue;
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(f),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kColLdsMax);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_col_cached(int fmt, const ColArgs& a, hipStream_t st) {
   const int nc = (a.m + 255) / 256, wi = cached_width_row(a.waves);
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX || wi < 0 || nc < 1 || nc > kNCMax || !kColCached[wi][fmt][nc - 1])
     return hipErrorNotSupported;
   const int w = wi ? 8 : kWaves;
   const ColLayout lay(a.n, a.m, a.r, a.rho, a.project, 0, w);
+  if (lay.total > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColCached[wi][fmt][nc - 1], dim3(a.q), dim3(64 * w), lay.total, st, a);
   return hipGetLastError();
@@ -1169,6 +1256,10 @@ hipError_t launch_col_grp_cached(int fmt, int nc, int waves, const ColArgs* tab,
   const int wi = cached_width_row(waves);
   if (fmt < FMT_F32 || fmt > FMT_BF16MIX || wi < 0 || nc < 1 || nc > kNCMax || !kColGrpCached[wi][fmt][nc - 1])
     return hipErrorNotSupported;
+  if (lds > kColLdsDefault) {
+    const hipError_t e = col_allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(kColGrpCached[wi][fmt][nc - 1], dim3(blocks), dim3(64 * (wi ? 8 : kWaves)), lds, st, tab, map);
   return hipGetLastError();

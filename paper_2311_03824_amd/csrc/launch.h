@@ -65,6 +65,16 @@ hipError_t launch_col_grp_wide(int fmt, int nc, int waves, const ColArgs* tab, c
 hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st,
                          int pol = 0);
 size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox, int waves = kWaves);
+// A column workgroup takes at most 64 KiB of LDS by default and up to the CU's
+// 160 KiB for large n (g, the step and the support bitmap are n-long LDS arrays;
+// a CU then holds one column workgroup).  col_allow_big_lds() raises the dynamic
+// LDS limit of every column kernel once; call it before the first launch that
+// needs more than 64 KiB and before any graph capture.
+constexpr size_t kColLdsDefault = 64 * 1024;
+constexpr size_t kColLdsMax = 160 * 1024;
+hipError_t col_allow_big_lds();
+hipError_t col_allow_big_lds_tuned();    // the autotuned and wide variants
+hipError_t col_allow_big_lds_cached();   // the cached-load variants
 size_t au_lds_bytes(int m, int r, int philox);
 hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,
                               hipStream_t st);

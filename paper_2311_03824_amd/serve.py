@@ -53,6 +53,7 @@ from typing import Callable, Dict, List, Optional, Sequence
 import numpy as np
 
 from . import instances as inst
+from . import roofline
 
 
 @dataclasses.dataclass
@@ -74,6 +75,7 @@ class Outcome:
     attempts: int = 1       # 1 + retries with a shorter step
     eta_m_sigma2: float = float("nan")   # eta m sigma_max(B*)^2 of the last attempt, when the executor reports it
     step_diag: float = float("nan")      # eta m sigma_max(B_t)^2 from the iterate, when a failure was checked
+    bytes_per_iteration: float = 0.0     # algorithmic HBM bytes of one GDmin iteration (A_k U + column kernel)
 
     @property
     def latency(self) -> float:
@@ -126,6 +128,10 @@ class ServeReport:
                                       "iteration cap"} for o in unconv][:16],
             "error_violations": sum(1 for o in done if not (o.error <= err_bound)),
             "mean_iterations": float(np.mean([o.iterations for o in done])) if done else 0.0,
+            # algorithmic bytes of the GDmin iterations run (last attempt of each request;
+            # initialisations not counted) over the makespan: a lower bound of the HBM rate
+            "iteration_GBps": (sum(o.iterations * o.bytes_per_iteration for o in done) / self.makespan / 1e9
+                               if self.makespan > 0 else 0.0),
             "makespan_s": self.makespan,
             "budget_gib": self.budget_bytes / 2**30,
             "peak_admitted_gib": self.peak_bytes / 2**30,
@@ -309,11 +315,13 @@ class Scheduler:
                 elif conv or iters >= self.max_iters or flags or diverged or stalled or at_floor:
                     out = timed("finish", self.ex.finish, a.job)
                     err, info = out if isinstance(out, tuple) else (out, {})
+                    bpi = self.ex.iteration_bytes(a.req) if hasattr(self.ex, "iteration_bytes") else 0.0
                     outcomes.append(Outcome(a.req.idx, a.req.arrival, a.admitted, now(), iters, resid, conv, err,
                                             error_flags=int(flags), diverged=diverged, stalled=stalled,
                                             at_floor=at_floor,
                                             attempts=attempts[a.req.idx], step_diag=diag,
-                                            eta_m_sigma2=info.get("eta_m_sigma2", float("nan"))))
+                                            eta_m_sigma2=info.get("eta_m_sigma2", float("nan")),
+                                            bytes_per_iteration=bpi))
                     used -= a.footprint
                 else:
                     keep.append(a)
@@ -385,6 +393,11 @@ class GpuExecutor:
 
     def footprint(self, req) -> int:
         return req.a_bytes() + 4 * req.q * req.m + 8 * req.q * req.n + self.workspace_bytes(req)
+
+    def iteration_bytes(self, req) -> float:
+        """Algorithmic HBM bytes of one GDmin iteration of the request (its form's A reads)."""
+        return roofline.iteration_bytes(req.n, req.q, req.m, req.r, req.rho, 3,
+                                        mixed=req.a_format != "f32" and self.bf16_mixed)
 
     # -- lifecycle
     def start(self, req):

@@ -94,6 +94,18 @@ def test_default_params_are_the_papers(lib):
     assert par.tol_resid == 0.0 and par.flags == 0
 
 
+@pytest.mark.parametrize("n, m, r", [(17688, 1024, 16), (17104, 400, 10), (19692, 64, 4), (16384, 400, 10)])
+def test_large_n_is_accepted_up_to_the_lds_of_a_cu(lib, n, m, r):
+    """g, the step and the support bitmap of a column are n-long LDS arrays; up to the
+    CU's 160 KiB (one column workgroup per CU) every n up to these is built, which
+    includes 128 x 128 frames (n = 16384) at the benchmark's m and r."""
+    lda = (m + 7) // 8 * 8
+    rc, b, _ = _ws(lib, _problem(lib, n=n, m=m, r=r, lda=lda, ldy=m, a_stride_k=lda * n))
+    assert rc == 0 and b > 0
+    rc, _, _ = _ws(lib, _problem(lib, n=n + 1, m=m, r=r, lda=lda, ldy=m, a_stride_k=lda * (n + 1)))
+    assert rc == (-5 if n != 16384 else 0)
+
+
 def test_workspace_bytes_accepts_the_benchmark_problem(lib):
     rc, b, _ = _ws(lib, _problem(lib))
     assert rc == 0 and b > 0
@@ -104,7 +116,7 @@ def test_workspace_bytes_accepts_the_benchmark_problem(lib):
 
 @pytest.mark.parametrize("kw, code", [
     (dict(r=17), -5),                   # no instantiation above r = 16
-    (dict(n=5600, m=1024, r=16, lda=1024, ldy=1024, a_stride_k=1024 * 5600), -5),   # LDS of a column workgroup
+    (dict(n=17689, m=1024, r=16, lda=1024, ldy=1024, a_stride_k=1024 * 17689), -5),   # 160 KiB LDS of a column workgroup
     (dict(m=1025, lda=1028, a_stride_k=1028 * 1000, ldy=1025), -5),
     (dict(r=-1), -1),                   # r = 0 is the automatic rank; negative is invalid
     (dict(q=0), -1),                    # empty problem

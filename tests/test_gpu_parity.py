@@ -732,7 +732,9 @@ def test_batched_cached_equals_solo_streamed(lib, torch, monkeypatch):
     [dict(n=300, q=100, m=120, r=2, rho=5, seed=8, bf16=False),    # 8-wave column workgroups
      dict(n=260, q=400, m=150, r=3, rho=4, seed=9, bf16=True, mixed=True),   # 4-wave
      dict(n=200, q=330, m=300, r=2, rho=3, seed=10, bf16=False)],  # 4-wave, two row chunks
-], ids=["mixed_sizes", "ranks_10_to_14", "column_widths"])
+    [dict(n=12000, q=10, m=64, r=3, rho=20, seed=11, bf16=False),  # ~100 KiB of LDS per column workgroup
+     dict(n=300, q=40, m=120, r=2, rho=5, seed=12, bf16=False)],   # in the same launch bucket
+], ids=["mixed_sizes", "ranks_10_to_14", "column_widths", "large_n"])
 @pytest.mark.parametrize("waves", [None, "16"])
 def test_step_many_equals_solo(lib, torch, monkeypatch, specs, waves):
     """Each problem gives the same result alone and batched with others of other sizes,
@@ -905,10 +907,35 @@ def test_degenerate_first_iteration_matches_oracle(lib, torch, shape):
     assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-4
 
 
+@pytest.mark.parametrize("shape", [dict(n=19692, q=20, m=64, r=4, rho=30),     # the largest n at m = 64
+                                   dict(n=16384, q=12, m=400, r=10, rho=50)])  # 128 x 128 frames, benchmark m, r
+def test_largest_n_matches_oracle(lib, torch, shape):
+    """n beyond 64 KiB of LDS per column workgroup (up to the CU's 160 KiB: one column
+    workgroup per CU, the kernels' LDS limit raised): three GDmin iterations from the
+    oracle's exact U_0 give its supports, subspace and estimate."""
+    inst = I.make_instance(**shape, seed=43)
+    A, Y = inst.A64(), inst.Y32.astype(np.float64)
+    st = O.initialise(A, Y, inst.r, inst.rho)
+    U0 = st.U.copy()
+    for _ in range(3):
+        st = O.gdmin_iteration(A, Y, st, inst.rho)
+    print(f"\ncase: n = {inst.n}, m = {inst.m}, r = {inst.r}", flush=True)
+    s = lib.Solver(inst.At, inst.Y32, inst.m, inst.r, inst.rho, lib.default_params(t_max=3), U_start=U0)
+    s.init().step(3)
+    out = s.get()
+    out["status"] = s.status()
+    s.close()
+    assert out["status"]["error_flags"] == 0
+    assert np.array_equal(out["S_idx"], st.idx)
+    assert O.subspace_distance(st.U_fit, out["U"].astype(np.float64)) <= 1e-5
+    X_gpu = out["U"].astype(np.float64) @ out["Bt"].T.astype(np.float64)
+    X_gpu[out["S_idx"], np.arange(inst.q)[:, None]] += out["S_val"]
+    assert O.rel_error(X_gpu, O.estimate(st)) <= 1e-5
+
+
 def test_largest_supported_shape_matches_oracle(lib, torch):
-    """Largest instantiation along every axis at once: m = 1024 rows (four row chunks,
-    P_k in global memory), r = 16, and n = 5500 columns, just under the 64 KiB of LDS
-    a column workgroup may take (n = 5600 is rejected, see test_abi)."""
+    """Largest instantiation along the m and r axes with a large n: m = 1024 rows (four
+    row chunks, P_k in global memory), r = 16, and n = 5500 columns."""
     inst = I.make_instance(n=5500, q=20, m=1024, r=16, rho=50, seed=41)
     A, Y = inst.A64(), inst.Y32.astype(np.float64)
     st = O.initialise(A, Y, inst.r, inst.rho)

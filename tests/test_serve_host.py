@@ -462,3 +462,31 @@ def test_too_long_steps_are_retried_with_a_shorter_step():
     assert s2["stalled"] == 3 and s2["converged_fraction"] == 0.25 and s2["retried"] == 0
     with pytest.raises(ValueError):
         Scheduler(None, 1, retry_step_limit=0.5)
+
+
+def test_iteration_bytes_enter_the_summary():
+    """The summary's iteration_GBps is the sum over completed requests of iterations x
+    bytes per iteration, over the makespan."""
+    clock = Clock()
+
+    class Sized(MockExecutor):
+        def iteration_bytes(self, req):
+            return 1e9 * (1 + req.idx)
+
+    ex = Sized(clock, {0: 20, 1: 30}, cost=0.01)
+    reqs = [dataclasses.replace(r, arrival=0.0) for r in _reqs(2)]
+    rep = Scheduler(ex, budget_bytes=1 << 50, poll_every=10, clock=clock, sleep=clock.sleep).run(reqs)
+    s = rep.summary()
+    want = (20 * 1e9 + 30 * 2e9) / rep.makespan / 1e9
+    assert s["iteration_GBps"] == pytest.approx(want)
+    assert {o.idx: o.bytes_per_iteration for o in rep.outcomes} == {0: 1e9, 1: 2e9}
+
+
+def test_iteration_bytes_formula():
+    from paper_2311_03824_amd import roofline
+    # the benchmark workload: 6.743e9 B in the column kernel, 1.6 GB + P_k, G^{-1} in A_k U
+    assert roofline.column_kernel_bytes(1000, 1000, 400, 10, 50, 3) == 6743248000.0
+    assert roofline.au_kernel_bytes(1000, 1000, 400, 10) == 1000 * (1.6e6 + 16000 + 800) + 40000
+    full = roofline.iteration_bytes(1000, 1000, 400, 10, 50)
+    mixed = roofline.iteration_bytes(1000, 1000, 400, 10, 50, mixed=True)
+    assert full == pytest.approx(8.36e9, rel=1e-3) and mixed == pytest.approx(5.16e9, rel=2e-3)
