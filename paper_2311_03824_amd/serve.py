@@ -12,7 +12,9 @@ the seed of its data.  The scheduler
     Alg. 1 (altgdmin_init);
   * advances every admitted problem together, `poll_every` GDmin iterations per
     round, with altgdmin_step_many (the column, gradient and QR kernels of all
-    problems share launches);
+    problems share launches); the round's launches go out before the host
+    admits new requests, so admission overlaps the GPU work, and a request
+    admitted during a round joins the next one;
   * after each round reads every active problem's status with one
     synchronisation (altgdmin_status_many) and retires those whose relative
     residual is at or below `tol`, that reached `max_iters` iterations, whose
@@ -265,6 +267,12 @@ class Scheduler:
                     break
             while pending and pending[0].arrival <= t:
                 waiting.append(pending.popleft())
+            # the round's batched step goes out first (asynchronous on the GPU), and the
+            # host admits waiting requests while it runs; they join the next round
+            stepped = list(active)
+            if stepped:
+                timed("step", self.ex.step, [a.job for a in stepped], self.poll_every)
+                rounds += 1
             if prepare is not None:          # host-side payloads of the next few, made in the background
                 for req in itertools.islice(waiting, self.prefetch):
                     prepare(req)
@@ -285,16 +293,15 @@ class Scheduler:
                 used += fp
                 peak = max(peak, used)
                 active.append(_Active(req, job, fp, now()))
-            if not active:
-                if pending:
+            if not stepped:
+                if not active and pending:
                     self.sleep(max(0.0, pending[0].arrival - now()))
                 continue
-            timed("step", self.ex.step, [a.job for a in active], self.poll_every)
-            rounds += 1
-            status = timed("poll", self.ex.poll, [a.job for a in active])
+            admitted = active[len(stepped):]
+            status = timed("poll", self.ex.poll, [a.job for a in stepped])
             keep = []
             retry = []
-            for a, st in zip(active, status):
+            for a, st in zip(stepped, status):
                 iters, resid = st[0], st[1]
                 flags = st[2] if len(st) > 2 else 0
                 conv = resid <= self.tol and not flags
@@ -325,7 +332,7 @@ class Scheduler:
                     used -= a.footprint
                 else:
                     keep.append(a)
-            active = keep
+            active = keep + admitted
             waiting.extendleft(reversed(retry))     # retries go first, in their original order
         makespan = max((o.done for o in outcomes), default=0.0) - min((o.arrival for o in outcomes), default=0.0)
         outcomes.sort(key=lambda o: o.idx)
@@ -333,10 +340,15 @@ class Scheduler:
 
 
 class GpuExecutor:
-    """Runs requests through the HIP library (one stream, torch for device memory).
+    """Runs requests through the HIP library (torch for device memory).
 
-    BF16 requests run the mixed form (hi plane for the transposed products,
-    hi + lo for every residual) unless bf16_mixed is False.
+    Two streams of default priority: a request's data (A, y) and its
+    initialisation -- the tau_0 IHT iterations and the subspace iteration, mostly
+    small latency-bound launches -- go on the init stream, so they overlap the
+    batched GDmin iterations of the admitted problems on the step stream; the
+    step stream waits on an event recorded after a request's initialisation
+    before its first step.  BF16 requests run the mixed form (hi plane for the
+    transposed products, hi + lo for every residual) unless bf16_mixed is False.
     """
 
     def __init__(self, tol: float = 1e-7, max_iters: int = 300, device: str = "cuda", bf16_mixed: bool = True):
@@ -352,6 +364,8 @@ class GpuExecutor:
                                               flags=lib.FLAG_BF16_MIXED if bf16_mixed else 0)
         self.bf16_mixed = bf16_mixed
         self.group_ws = None
+        self.init_stream = torch.cuda.Stream(device=device)
+        self.step_stream = torch.cuda.Stream(device=device)
         self._ws_cache = {}
         self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=4)
         self._truth = {}
@@ -404,48 +418,64 @@ class GpuExecutor:
         torch, lib = self.torch, self.lib
         fut = self._truth.pop(req.idx, None)
         Xt_host, sv2 = fut.result() if fut is not None else self._make_truth(req)
-        Xt = Xt_host.to(self.device, non_blocking=True)
-        shape = (req.q, req.n, req.lda)
-        if req.a_format == "f32":
-            A, A_lo = torch.empty(shape, dtype=torch.float32, device=self.device), None
-        else:
-            A = torch.empty(shape, dtype=torch.int16, device=self.device)
-            A_lo = torch.empty(shape, dtype=torch.int16, device=self.device)
-        Y = torch.empty((req.q, req.m), dtype=torch.float32, device=self.device)
-        lib.altgdmin_op_make_a(req.a_seed, self.table, req.q, req.n, req.m, A, A_lo)
-        prob = lib.make_problem(A, Y, req.r, req.rho, A_lo=A_lo, m=req.m)
-        lib.altgdmin_op_measure(prob, Xt, Y)
-        ws = torch.empty(self.workspace_bytes(req), dtype=torch.uint8, device=self.device)
-        h = lib.altgdmin_init(prob, self._params(req), ws)
-        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, Xt_host=Xt_host, ws=ws, prob=prob, h=h, sv2=sv2)
+        with torch.cuda.stream(self.init_stream):
+            Xt = Xt_host.to(self.device, non_blocking=True)
+            shape = (req.q, req.n, req.lda)
+            if req.a_format == "f32":
+                A, A_lo = torch.empty(shape, dtype=torch.float32, device=self.device), None
+            else:
+                A = torch.empty(shape, dtype=torch.int16, device=self.device)
+                A_lo = torch.empty(shape, dtype=torch.int16, device=self.device)
+            Y = torch.empty((req.q, req.m), dtype=torch.float32, device=self.device)
+            lib.altgdmin_op_make_a(req.a_seed, self.table, req.q, req.n, req.m, A, A_lo)
+            prob = lib.make_problem(A, Y, req.r, req.rho, A_lo=A_lo, m=req.m)
+            lib.altgdmin_op_measure(prob, Xt, Y)
+            ws = torch.empty(self.workspace_bytes(req), dtype=torch.uint8, device=self.device)
+            h = lib.altgdmin_init(prob, self._params(req), ws)
+            ready = torch.cuda.Event()
+            ready.record(self.init_stream)
+        # the step stream reads these too: the allocator must not reuse them before it is done
+        for t in (Xt, A, A_lo, Y, ws):
+            if t is not None:
+                t.record_stream(self.step_stream)
+        return dict(req=req, A=A, A_lo=A_lo, Y=Y, Xt=Xt, Xt_host=Xt_host, ws=ws, prob=prob, h=h, sv2=sv2,
+                    ready=ready)
 
     def step(self, jobs, iters: int) -> None:
+        torch = self.torch
         hs = [j["h"] for j in jobs]
-        need = self.lib.altgdmin_group_bytes(hs)
-        if self.group_ws is None or self.group_ws.numel() < need:
-            self.group_ws = self.torch.empty(max(need, 1 << 20), dtype=self.torch.uint8, device=self.device)
-        self.lib.altgdmin_step_many(hs, iters, self.group_ws)
+        with torch.cuda.stream(self.step_stream):
+            for j in jobs:   # a newly admitted job: its initialisation first
+                ev = j.pop("ready", None)
+                if ev is not None:
+                    self.step_stream.wait_event(ev)
+            need = self.lib.altgdmin_group_bytes(hs)
+            if self.group_ws is None or self.group_ws.numel() < need:
+                self.group_ws = torch.empty(max(need, 1 << 20), dtype=torch.uint8, device=self.device)
+            self.lib.altgdmin_step_many(hs, iters, self.group_ws)
 
     def poll(self, jobs):
         """(iterations, residual, error flags) of every job, with one synchronisation."""
-        reps = self.lib.altgdmin_status_many([j["h"] for j in jobs])
+        with self.torch.cuda.stream(self.step_stream):
+            reps = self.lib.altgdmin_status_many([j["h"] for j in jobs])
         return [(int(st["iterations"]), float(st["resid"]), int(st["error_flags"])) for st in reps]
 
     def finish(self, job):
         """(error against X*, {"eta_m_sigma2": eta m sigma_max(B*)^2}) of a retired job."""
         torch, req = self.torch, job["req"]
-        U = torch.empty((req.n, req.r), dtype=torch.float32, device=self.device)
-        Bt = torch.empty((req.q, req.r), dtype=torch.float32, device=self.device)
-        rho = max(req.rho, 1)
-        Si = torch.zeros((req.q, rho), dtype=torch.int32, device=self.device)
-        Sv = torch.zeros((req.q, rho), dtype=torch.float32, device=self.device)
-        self.lib.altgdmin_get(job["h"], U, Bt, Si if req.rho else None, Sv if req.rho else None)
-        # error of the consistent pair in FP64 (measurement harness, not the method)
-        Xt = Bt.double() @ U.double().T
-        if req.rho:
-            Xt.scatter_add_(1, Si.long(), Sv.double())
-        err = float(torch.linalg.norm(Xt - job["Xt"]) / torch.linalg.norm(job["Xt"]))
-        eta = self.lib.altgdmin_status(job["h"])["eta"]
+        with torch.cuda.stream(self.step_stream):
+            U = torch.empty((req.n, req.r), dtype=torch.float32, device=self.device)
+            Bt = torch.empty((req.q, req.r), dtype=torch.float32, device=self.device)
+            rho = max(req.rho, 1)
+            Si = torch.zeros((req.q, rho), dtype=torch.int32, device=self.device)
+            Sv = torch.zeros((req.q, rho), dtype=torch.float32, device=self.device)
+            self.lib.altgdmin_get(job["h"], U, Bt, Si if req.rho else None, Sv if req.rho else None)
+            # error of the consistent pair in FP64 (measurement harness, not the method)
+            Xt = Bt.double() @ U.double().T
+            if req.rho:
+                Xt.scatter_add_(1, Si.long(), Sv.double())
+            err = float(torch.linalg.norm(Xt - job["Xt"]) / torch.linalg.norm(job["Xt"]))
+            eta = self.lib.altgdmin_status(job["h"])["eta"]
         diag = eta * req.m * job["sv2"][1]
         self.release(job)
         return err, {"eta_m_sigma2": diag}
@@ -454,14 +484,18 @@ class GpuExecutor:
         """eta m sigma_max(B_t)^2 from the iterate's B_t (an estimate of B*); above 2 the
         fixed step is too long (Gaussian A_k, E[A_k^T A_k] = m I)."""
         req = job["req"]
-        Bt = self.torch.empty((req.q, req.r), dtype=self.torch.float32, device=self.device)
-        self.lib.altgdmin_get(job["h"], None, Bt)
-        eta = self.lib.altgdmin_status(job["h"])["eta"]
+        with self.torch.cuda.stream(self.step_stream):
+            Bt = self.torch.empty((req.q, req.r), dtype=self.torch.float32, device=self.device)
+            self.lib.altgdmin_get(job["h"], None, Bt)
+            eta = self.lib.altgdmin_status(job["h"])["eta"]
         sv = np.linalg.svd(Bt.double().cpu().numpy(), compute_uv=False)
         return float(eta * req.m * sv[0] ** 2)
 
     def release(self, job) -> None:
         """Destroy the handle and drop the job's device buffers (cancellation)."""
+        ready = job.get("ready")
+        if ready is not None:   # never stepped: its initialisation may still be running
+            ready.synchronize()
         if job.get("h") is not None:
             self.lib.altgdmin_destroy(job["h"])
         job.clear()
