@@ -872,9 +872,14 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   for (int t = tid; t < r * r; t += kThreads) Gk[t] = Gil[t];
 }
 
-constexpr int kDefaultAUD = 2;   // A_k loads of the next AUD columns in flight per wave (autotuned variants differ)
+// A_k loads of the next AUD columns in flight per wave (autotuned variants differ).
+// The r accumulators per row compete with the loads for registers: at R = 14 one
+// column in flight keeps four waves per SIMD (0.311 against 0.377 ms with two at
+// n = q = 1000, m = 400, FP32), at R = 16 four in flight hide the latency best
+// (0.382 against 0.409 ms); two elsewhere.
+constexpr int default_aud(int R) { return R == 14 ? 1 : (R == 16 ? 4 : 2); }
 
-template <int FMT, int R, int AUD = kDefaultAUD, int POL = POL_STREAM>
+template <int FMT, int R, int AUD = default_aud(R), int POL = POL_STREAM>
 __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -888,7 +893,7 @@ __global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const in
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  au_body<FMT, R, kDefaultAUD, POL>(a, mp.y, smem);
+  au_body<FMT, R, default_aud(R), POL>(a, mp.y, smem);
 }
 
 #if !defined(ALTG_PART) || ALTG_PART == 1
@@ -1206,10 +1211,10 @@ static const col_fn3 kColCached[2][5][kNCMax] = {
 static const colg_fn3 kColGrpCached[2][5][kNCMax] = {
     {COLGC_F(FMT_F32, 4), COLGC_F(FMT_BF16X2, 4), COLGC_F(FMT_BF16HI, 4), COLC_NONE, COLGC_F(FMT_BF16MIX, 4)},
     {COLGC_F(FMT_F32, 8), COLGC_F(FMT_BF16X2, 8), COLGC_F(FMT_BF16HI, 8), COLC_NONE, COLGC_F(FMT_BF16MIX, 8)}};
-#define AUC_F(F) {k_au<F, 2, kDefaultAUD, POL_CACHED>, k_au<F, 4, kDefaultAUD, POL_CACHED>, \
-                  k_au<F, 6, kDefaultAUD, POL_CACHED>, k_au<F, 8, kDefaultAUD, POL_CACHED>, \
-                  k_au<F, 10, kDefaultAUD, POL_CACHED>, k_au<F, 12, kDefaultAUD, POL_CACHED>, \
-                  k_au<F, 14, kDefaultAUD, POL_CACHED>, k_au<F, 16, kDefaultAUD, POL_CACHED>}
+#define AUC_F(F) {k_au<F, 2, default_aud(2), POL_CACHED>, k_au<F, 4, default_aud(4), POL_CACHED>, \
+                  k_au<F, 6, default_aud(6), POL_CACHED>, k_au<F, 8, default_aud(8), POL_CACHED>, \
+                  k_au<F, 10, default_aud(10), POL_CACHED>, k_au<F, 12, default_aud(12), POL_CACHED>, \
+                  k_au<F, 14, default_aud(14), POL_CACHED>, k_au<F, 16, default_aud(16), POL_CACHED>}
 static const au_fn3 kAUCached[3][kRMax / 2] = {AUC_F(FMT_F32), AUC_F(FMT_BF16X2), AUC_F(FMT_BF16HI)};
 #define AUGC_F(F) {k_au_grp<F, 2, POL_CACHED>, k_au_grp<F, 4, POL_CACHED>, k_au_grp<F, 6, POL_CACHED>, \
                    k_au_grp<F, 8, POL_CACHED>, k_au_grp<F, 10, POL_CACHED>, k_au_grp<F, 12, POL_CACHED>, \

@@ -9,6 +9,8 @@
 //            CholeskyQR2 (FP64 Gram and Cholesky, positive-diagonal R), the QR of
 //            the projected GD step in Alg. 1; also the subspace-iteration
 //            orthonormalisation and the residual monitor.
+#include <mutex>
+
 #include "launch.h"
 
 namespace altg {
@@ -510,10 +512,32 @@ hipError_t launch_ltu(const float* L0t, const float* U, int n, int q, int r, flo
   return hipGetLastError();
 }
 
+// Raise the dynamic LDS limit of the QR kernels to kQRLdsMax, once, before the
+// first launch whose n x r block needs more than the default.  The block in LDS
+// or in global memory goes through the same arithmetic in the same order.
+static hipError_t qr_allow_lds(size_t bytes) {
+  if (bytes <= kQRLdsDefault) return hipSuccess;
+  static std::mutex mu;
+  static bool done = false;
+  std::lock_guard<std::mutex> lk(mu);
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_qr), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kQRLdsMax);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_qr_grp), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kQRLdsMax);
+  done = e == hipSuccess;
+  return e;
+}
+
 hipError_t launch_qr(const QRArgs& a_in, hipStream_t st) {
   QRArgs a = a_in;
   const size_t bytes = (size_t)a.n * a.r * sizeof(float);
   a.lds = bytes <= kQRLdsMax ? 1 : 0;
+  if (a.lds) {
+    const hipError_t e = qr_allow_lds(bytes);
+    if (e != hipSuccess) return e;
+  }
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(k_qr, dim3(1), dim3(kQRThreads), a.lds ? bytes : 0, st, a);
   return hipGetLastError();
@@ -526,6 +550,8 @@ hipError_t launch_grad_grp(const GradArgs* tab, const int4* map, int blocks, hip
 }
 
 hipError_t launch_qr_grp(const QRArgs* tab, int count, size_t lds, hipStream_t st) {
+  const hipError_t ea = qr_allow_lds(lds);
+  if (ea != hipSuccess) return ea;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
   hipLaunchKernelGGL(k_qr_grp, dim3(count), dim3(kQRThreads), lds, st, tab);
   return hipGetLastError();

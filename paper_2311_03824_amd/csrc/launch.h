@@ -28,7 +28,10 @@ struct QRArgs {
   int gate_done;           // GD: skip the update when ctl->done is set (batched stepping)
 };
 
-constexpr size_t kQRLdsMax = 48 * 1024;   // dynamic LDS for the n x r block of k_qr
+// dynamic LDS for the n x r block of k_qr (with its 10 KiB of static LDS, up to the
+// CU's 160 KiB; above the default 48 KiB the kernels' limit is raised on first use)
+constexpr size_t kQRLdsMax = 144 * 1024;
+constexpr size_t kQRLdsDefault = 48 * 1024;
 constexpr int kGradWaves = 16;             // waves of a gradient-reduction workgroup
 
 struct GradArgs {
