@@ -379,6 +379,12 @@ QRArgs qr_args(const altgdmin_handle* h, int mode) {
 // one was chosen for this problem's format.
 hipError_t col_launch(const altgdmin_handle* h, int fmt, const ColArgs& a, hipStream_t st) {
   if (h->col_unroll > 0 && fmt == h->colfmt && a.waves == kWaves) return launch_col_tuned(fmt, h->col_unroll, a, st);
+  // the FP32 default at two row chunks keeps one column per group in flight; when
+  // its LDS leaves a CU three 4-wave workgroups instead of four (r >= 15 at m = 400)
+  // two in flight win (1.16 against 1.42 ms at n = q = 1000, m = 400, r = 16)
+  if (h->col_unroll == 0 && fmt == FMT_F32 && a.waves == kWaves && (a.m + 255) / 256 == 2 &&
+      col_lds_bytes(a.n, a.m, a.r, a.rho, a.project, 0) > 160 * 1024 / 4)
+    return launch_col_tuned(fmt, 2, a, st);
   return launch_col(fmt, a, st, h->col_unroll < 0 ? POL_CACHED : POL_STREAM);
 }
 hipError_t au_launch(const altgdmin_handle* h, int fmt, const AUArgs& a, hipStream_t st) {

@@ -251,8 +251,13 @@ __device__ __forceinline__ float col_totals(const float (&x)[JU], int lane) {
 // Default loads in flight of the column passes (columns per wave per group).
 // The mixed BF16 form streams 2-byte elements, so its 8-wave workgroups keep
 // twice the columns in flight at two row chunks (0.191 -> 0.180 ms at q = 125).
+// The FP32 plane at two row chunks in 4-wave workgroups takes one column per
+// group: with two it needs a 16-byte spill under its 128-register cap (0.982
+// against 1.02 ms at n = q = 1000, m = 400, r = 10).
 constexpr int default_ju(int nc, int w = kWaves, int fmt = FMT_F32) {
-  return w >= 16 ? (nc == 1 ? 2 : 1) : (w == 8 && nc == 2 && fmt == FMT_BF16MIX ? 4 : (nc == 1 ? 4 : 2));
+  return w >= 16 ? (nc == 1 ? 2 : 1)
+                 : (w == 8 && nc == 2 && fmt == FMT_BF16MIX ? 4
+                                                            : (nc == 1 ? 4 : (w == 4 && nc == 2 && fmt == FMT_F32 ? 1 : 2)));
 }
 
 template <int FMT, int NC, int JU, int W = kWaves, int POL = POL_STREAM>
@@ -652,7 +657,7 @@ constexpr int col_min_waves_w(int fmt, int nc, int ju, int w) {
   return col_min_waves(fmt, nc, ju) > w / 4 ? col_min_waves(fmt, nc, ju) : w / 4;
 }
 
-template <int FMT, int NC, int JU = default_ju(NC), int W = kWaves, int POL = POL_STREAM>
+template <int FMT, int NC, int JU = default_ju(NC, kWaves, FMT), int W = kWaves, int POL = POL_STREAM>
 __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_waves_w(FMT, NC, JU, W), 8))) void k_col(ColArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
