@@ -100,10 +100,13 @@ enum {
 /* Problem of Sec. 1.1: sizes, measurement matrices and measurements. */
 typedef struct altgdmin_problem {
   int32_t n, q, m, r, rho;   /* 1 <= r <= min(m, n), 0 <= rho <= n; rho is the threshold budget (Sec. 2.6).
-                                r = 0 (real A forms): the automatic rank of Sec. 2.6, chosen by altgdmin_init
-                                from L_0 (see altgdmin_params.rank_energy); the workspace is then laid out for
-                                r_cap = min(K, 16, m, n) with K = max(1, floor(min(n, q, m) / 10)), and
-                                altgdmin_report.rank gives the r chosen (outputs have r columns) */
+                                r = 0: the automatic rank of Sec. 2.6, chosen by altgdmin_init from L_0 (see
+                                altgdmin_params.rank_energy); the workspace is then laid out for r_cap =
+                                min(K, 16, m, n) (min(K, 8, m, n) in the Fourier form) with K = max(1,
+                                floor(min(n, q, m) / 10)), U_start is not used, and altgdmin_report.rank gives
+                                the r chosen (outputs have r columns).  The Fourier form estimates the values
+                                on the real embedding [[X, -Y], [Y, X]] of L_0 = X + iY (each value twice);
+                                K <= 88 (44 in the Fourier form), else ALTGDMIN_ENOTBUILT */
   int32_t a_format;          /* ALTGDMIN_A_* */
   const void* A;             /* F32: const float*; BF16X2: hi plane, const uint16_t* */
   const void* A_lo;          /* BF16X2: lo plane; NULL otherwise */

@@ -612,6 +612,8 @@ class FourierSolver:
         if self.h is not None:
             altgdmin_destroy(self.h)
         self.h = altgdmin_init(self.prob, self.par, self.ws, stream=stream)
+        if self.prob.r == 0:    # automatic rank: the one the initialisation chose
+            self.r = altgdmin_status(self.h, stream=stream)["rank"]
         return self
 
     def step(self, iters: int, stream=None):

@@ -85,7 +85,21 @@ int rank_block(int n, int q, int m) {
 // the rank the workspace is laid out for: r, or with r = 0 the largest the automatic rule may pick
 int r_eff(const altgdmin_problem& p) {
   if (p.r > 0) return p.r;
-  return std::min(std::min(rank_budget(p.n, p.q, p.m), kRMax), std::min(p.m, p.n));
+  const int cap = p.a_format == ALTGDMIN_A_PFOURIER ? kFRMax : kRMax;
+  return std::min(std::min(rank_budget(p.n, p.q, p.m), cap), std::min(p.m, p.n));
+}
+
+// The matrix the rank estimate runs on and its sizes: L_0 itself for the real
+// forms (n x q; K values, a block of b columns); for the Fourier form the real
+// embedding [[X, -Y], [Y, X]] of L_0 = X + iY (2n x 2q), whose singular values are
+// those of L_0 twice each, so K and the block double.
+struct RankShape {
+  int n, q, K, b;
+};
+RankShape rank_shape(int n, int q, int m) { return {n, q, rank_budget(n, q, m), rank_block(n, q, m)}; }
+RankShape rank_shape_complex(int n, int q, int m) {
+  const int K = rank_budget(n, q, m);
+  return {2 * n, 2 * q, 2 * K, std::min(2 * K + 8, std::min(kRankBlockMax, std::min(2 * n, 2 * q)))};
 }
 
 // Scratch of the automatic rank: the block U and Z = L_0 L_0^T U (n x b), T = L_0^T U
@@ -103,8 +117,8 @@ struct RankScratch {
   size_t bytes;
 };
 
-RankScratch rank_scratch(void* base, int n, int q, int m) {
-  const size_t b = rank_block(n, q, m), K = rank_budget(n, q, m);
+RankScratch rank_scratch(void* base, const RankShape& sh) {
+  const size_t n = sh.n, q = sh.q, b = sh.b, K = sh.K;
   RankScratch s;
   Carver c(base);
   s.Ub = c.take<float>((size_t)n * b);
@@ -124,9 +138,9 @@ RankScratch rank_scratch(void* base, int n, int q, int m) {
 // block subspace iteration from a fixed orthonormal start, each Z = L_0 (L_0^T U)
 // and CholeskyQR2, then the Rayleigh-Ritz values and the rank (device outputs r,
 // sv).  Returns the buffer that holds the final orthonormal block (n x b).
-hipError_t enqueue_rank(const float* L0t, int n, int q, int m, double energy, int iters, RankScratch& s,
+hipError_t enqueue_rank(const float* L0t, const RankShape& sh, double energy, int iters, RankScratch& s,
                         float** block, hipStream_t st) {
-  const int b = rank_block(n, q, m), K = rank_budget(n, q, m);
+  const int n = sh.n, q = sh.q, b = sh.b, K = sh.K;
   float* U = s.Ub;
   float* Z = s.Z;
   hipError_t e = launch_fill_int(s.flag, 0, 1, st);
@@ -188,6 +202,7 @@ struct altgdmin_handle {
   double* fpart = nullptr; // per-256-row-block partial Grams of the GD update
   double* frinv = nullptr; // R1^{-1}, R2^{-1} of the GD update
   void* rank_ws = nullptr; // r = 0 (automatic rank): scratch of the rank estimate
+  float* rank_embed = nullptr;  // Fourier form, r = 0: the real embedding of L_0 (2q x 2n)
   int col_waves = kWaves;  // waves of the column workgroup (a property of the problem, see choose_col_waves)
   int col_unroll = 0;      // autotuned JU of the column kernel (0: the default instantiation)
   int au_depth = 0;        // autotuned AUD of the A_k U kernel (0: the default instantiation)
@@ -205,7 +220,7 @@ namespace {
 // Workspace of the partial Fourier form (complex values as float pairs).
 size_t carve_fourier(altgdmin_handle* h, void* base) {
   const altgdmin_problem& p = h->prob;
-  const size_t n = p.n, q = p.q, r = p.r, rho = p.rho;
+  const size_t n = p.n, q = p.q, r = r_eff(p), rho = p.rho;
   Carver c(base);
   h->ctl = c.take<Ctl>(1);
   h->P = nullptr;
@@ -228,6 +243,10 @@ size_t carve_fourier(altgdmin_handle* h, void* base) {
   h->frinv = c.take<double>(2 * 2 * r * r);
   h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
   h->rlog = c.take<double>(h->rlog_len);
+  if (p.r == 0) {   // automatic rank: the real embedding of L_0 and the estimate's scratch
+    h->rank_embed = c.take<float>(4 * q * n);
+    h->rank_ws = c.take<unsigned char>(rank_scratch(nullptr, rank_shape_complex(p.n, p.q, p.m)).bytes);
+  }
   return (c.off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -254,7 +273,7 @@ size_t carve(altgdmin_handle* h, void* base) {
   h->Tpow = c.take<float>(q * r);
   h->rlog_len = h->par.t_max > 0 ? h->par.t_max : 1;
   h->rlog = c.take<double>(h->rlog_len);
-  if (p.r == 0) h->rank_ws = c.take<unsigned char>(rank_scratch(nullptr, p.n, p.q, p.m).bytes);
+  if (p.r == 0) h->rank_ws = c.take<unsigned char>(rank_scratch(nullptr, rank_shape(p.n, p.q, p.m)).bytes);
   return (c.off + kAlign - 1) / kAlign * kAlign;
 }
 
@@ -263,9 +282,7 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (p->n < 1 || p->q < 1 || p->m < 1) return fail(ALTGDMIN_EINVAL, "n, q, m must be >= 1");
   if (p->r < 0 || (p->r > 0 && (p->r > p->m || p->r > p->n)))
     return fail(ALTGDMIN_EINVAL, "need 1 <= r <= min(m, n), or r = 0 for the automatic rank");
-  if (p->r == 0 && p->a_format == ALTGDMIN_A_PFOURIER)
-    return fail(ALTGDMIN_ENOTBUILT, "the automatic rank is built for the real A forms");
-  if (p->r == 0 && rank_budget(p->n, p->q, p->m) > kRankBlockMax)
+  if (p->r == 0 && (p->a_format == ALTGDMIN_A_PFOURIER ? 2 : 1) * rank_budget(p->n, p->q, p->m) > kRankBlockMax)
     return fail(ALTGDMIN_ENOTBUILT, "automatic rank: min(n, q, m) / 10 above the largest block of the estimate");
   if (p->r == 0 && !(par->rank_energy > 0.0 && par->rank_energy <= 1.0 && par->rank_iters >= 1))
     return fail(ALTGDMIN_EINVAL, "automatic rank needs 0 < rank_energy <= 1 and rank_iters >= 1");
@@ -287,7 +304,7 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
     if (p->m > 2 * kFThreads) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: m > 2048 has no instantiation");
     if (p->r > kFRMax) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: r > 8 has no instantiation");
     if (p->rho > kFRhoMax) return fail(ALTGDMIN_ENOTBUILT, "Fourier form: rho > 256 has no instantiation");
-    if (fcol_lds_bytes(p->rho, p->r, p->n, p->m, p->n1, p->n2) > kFLdsMax)
+    if (fcol_lds_bytes(p->rho, r_eff(*p), p->n, p->m, p->n1, p->n2) > kFLdsMax)
       return fail(ALTGDMIN_ENOTBUILT, "Fourier form: the frame and the rows of P_k need more LDS than a CU has");
     if (!p->fourier_mask || !p->Y) return fail(ALTGDMIN_EINVAL, "Fourier form needs the mask and Y");
     if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
@@ -728,7 +745,29 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
     if (e != hipSuccess) return bail(e, "twiddles");
     if ((e = launch_fcol(fcol_args(h, FCOL_INIT), st)) != hipSuccess) return bail(e, "init column kernel");
     if ((e = launch_sum_ctl(h->colrr, p.q, h->ctl, st)) != hipSuccess) return bail(e, "ynorm");
-    if (p.U_start) e = launch_copy_f(h->Utmp, p.U_start, 2LL * p.n * p.r, st);
+    if (h->auto_rank) {
+      // r from the energy of the leading singular values of L_0 (Sec. 2.6), estimated on
+      // its real embedding, where each value appears twice: the smallest k' of the
+      // doubled sequence is 2r - 1 or 2r.  The only synchronisation of the initialisation.
+      const RankShape rsh = rank_shape_complex(p.n, p.q, p.m);
+      RankScratch rs = rank_scratch(h->rank_ws, rsh);
+      float* block = nullptr;
+      if ((e = launch_rank_embed(h->H, p.q, p.n, h->rank_embed, st)) != hipSuccess) return bail(e, "embedding");
+      if ((e = enqueue_rank(h->rank_embed, rsh, par->rank_energy, par->rank_iters, rs, &block, st)) != hipSuccess)
+        return bail(e, "automatic rank");
+      int chosen2 = 0;
+      if ((e = hipMemcpyAsync(&chosen2, rs.r, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return bail(e, "automatic rank copy");
+      if ((e = hipStreamSynchronize(st)) != hipSuccess) return bail(e, "automatic rank");
+      const int chosen = (chosen2 + 1) / 2;
+      if (chosen < 1 || chosen > r_cap) {
+        delete h;
+        return fail(ALTGDMIN_ENOTBUILT, "automatic rank chose r = " + std::to_string(chosen) + ", above the " +
+                                            std::to_string(r_cap) + " this problem is built for");
+      }
+      h->prob.r = chosen;
+    }
+    if (p.U_start && !h->auto_rank) e = launch_copy_f(h->Utmp, p.U_start, 2LL * p.n * p.r, st);
     else e = launch_fbasis(F2(h->Utmp), p.n, p.r, st);
     if (e != hipSuccess) return bail(e, "start block");
     if ((e = launch_fqr(fqr_args(h, QR_ORTH), st)) != hipSuccess) return bail(e, "orth");
@@ -756,9 +795,10 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
     // r from the energy of the leading singular values of L_0 (Sec. 2.6); the only
     // synchronisation of the initialisation.  U_0 starts from the first r columns of
     // the estimate's block, which span the first r columns' subspace iterate.
-    RankScratch rs = rank_scratch(h->rank_ws, p.n, p.q, p.m);
+    RankScratch rs = rank_scratch(h->rank_ws, rank_shape(p.n, p.q, p.m));
     float* block = nullptr;
-    if ((e = enqueue_rank(h->H, p.n, p.q, p.m, par->rank_energy, par->rank_iters, rs, &block, st)) != hipSuccess)
+    if ((e = enqueue_rank(h->H, rank_shape(p.n, p.q, p.m), par->rank_energy, par->rank_iters, rs, &block, st)) !=
+        hipSuccess)
       return bail(e, "automatic rank");
     int chosen = 0;
     if ((e = hipMemcpyAsync(&chosen, rs.r, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess)
@@ -1587,7 +1627,7 @@ int altgdmin_op_rank_scratch_bytes(int32_t n, int32_t q, int32_t m, size_t* byte
   if (n < 1 || q < 1 || m < 1 || !bytes) return fail(ALTGDMIN_EINVAL, "bad sizes");
   if (rank_budget(n, q, m) > kRankBlockMax)
     return fail(ALTGDMIN_ENOTBUILT, "min(n, q, m) / 10 above the largest block of the estimate");
-  *bytes = rank_scratch(nullptr, n, q, m).bytes;
+  *bytes = rank_scratch(nullptr, rank_shape(n, q, m)).bytes;
   return ALTGDMIN_OK;
 }
 
@@ -1598,11 +1638,11 @@ int altgdmin_op_rank(const float* L0t, int32_t n, int32_t q, int32_t m, double e
   if (rank_budget(n, q, m) > kRankBlockMax)
     return fail(ALTGDMIN_ENOTBUILT, "min(n, q, m) / 10 above the largest block of the estimate");
   NEED_STREAM(stream);
-  RankScratch rs = rank_scratch(scratch, n, q, m);
+  RankScratch rs = rank_scratch(scratch, rank_shape(n, q, m));
   if (scratch_bytes < rs.bytes) return fail(ALTGDMIN_ENOWS, "scratch too small");
   hipStream_t st = static_cast<hipStream_t>(stream);
   float* block = nullptr;
-  HIPCHK(enqueue_rank(L0t, n, q, m, energy, iters, rs, &block, st));
+  HIPCHK(enqueue_rank(L0t, rank_shape(n, q, m), energy, iters, rs, &block, st));
   HIPCHK(hipMemcpyAsync(r_out, rs.r, sizeof(int), hipMemcpyDeviceToDevice, st));
   if (sv_out)
     HIPCHK(hipMemcpyAsync(sv_out, rs.sv, (size_t)rank_budget(n, q, m) * sizeof(double), hipMemcpyDeviceToDevice, st));

@@ -272,6 +272,23 @@ __global__ __launch_bounds__(256) void k_rank_jacobi(const double* __restrict__ 
   }
 }
 
+// The real embedding of a complex L_0 = X + iY (n x q), given as L0t (q x n
+// complex, L0t[k][j] = L_0[j][k]): E = [[X, -Y], [Y, X]] (2n x 2q), written as its
+// transpose Et (2q x 2n, row-major).  The singular values of E are those of L_0,
+// each twice.
+__global__ void k_rank_embed(const float2* __restrict__ L0t, int q, int n, float* __restrict__ Et) {
+  const long long n2 = 2LL * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)q * n;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long k = e / n, j = e % n;
+    const float2 v = L0t[e];
+    Et[k * n2 + j] = v.x;
+    Et[k * n2 + n + j] = v.y;
+    Et[(q + k) * n2 + j] = -v.y;
+    Et[(q + k) * n2 + n + j] = v.x;
+  }
+}
+
 // U (n x r, row-major) = the first r columns of Ub (n x b, row-major).
 __global__ void k_rank_slice(const float* __restrict__ Ub, int n, int b, int r, float* __restrict__ U) {
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < (long long)n * r;
@@ -312,6 +329,15 @@ hipError_t launch_rank_jacobi(const double* M, int b, int K, double energy, doub
                               hipStream_t st) {
   (void)hipGetLastError();
   hipLaunchKernelGGL(k_rank_jacobi, dim3(1), dim3(256), rank_lds_bytes(b), st, M, b, K, energy, sv, r_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_rank_embed(const float* L0t, int q, int n, float* Et, hipStream_t st) {
+  (void)hipGetLastError();
+  long long g = ((long long)q * n + 255) / 256;
+  if (g > 4096) g = 4096;
+  if (g < 1) g = 1;
+  hipLaunchKernelGGL(k_rank_embed, dim3((unsigned)g), dim3(256), 0, st, reinterpret_cast<const float2*>(L0t), q, n, Et);
   return hipGetLastError();
 }
 

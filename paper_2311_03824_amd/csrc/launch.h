@@ -180,6 +180,9 @@ hipError_t launch_rank_chol(const double* W, int b, double* Xinv, float* Xf, int
 hipError_t launch_rank_jacobi(const double* M, int b, int K, double energy, double* sv, int* r_out,
                               hipStream_t st);
 hipError_t launch_rank_slice(const float* Ub, int n, int b, int r, float* U, hipStream_t st);
+// Et (2q x 2n real) = the transpose of the real embedding [[X, -Y], [Y, X]] of the
+// complex L_0 = X + iY given as L0t (q x n complex64)
+hipError_t launch_rank_embed(const float* L0t, int q, int n, float* Et, hipStream_t st);
 
 // synthetic instances on the device
 struct MeasureArgs {

@@ -231,15 +231,22 @@ def test_noalloc_entry_point_checks_sizes_and_stream_on_the_host(lib):
 
 def test_automatic_rank_problems(lib):
     """r = 0 asks for the automatic rank: the workspace is laid out for the largest rank
-    the rule may pick; the Fourier form and K > 88 are not built; bad energies are refused."""
+    the rule may pick (plus, in the Fourier form, the real embedding of L_0); K > 88 (44
+    in the Fourier form) is not built; bad energies are refused."""
     rc0, b0, _ = _ws(lib, _problem(lib, r=0))
     rc16, b16, _ = _ws(lib, _problem(lib, r=16))
     assert rc0 == 0 and rc16 == 0 and b0 > b16 > 0      # r_cap = 16 plus the estimate's scratch
     rc, _, msg = _ws(lib, _problem(lib, r=0, n=2000, q=2000, m=1000, lda=1000, ldy=1000,
                                    a_stride_k=1000 * 2000))
     assert rc == -5 and "automatic rank" in msg      # K = 100 > 88
-    rc, _, _ = _ws(lib, _fourier_problem(lib, r=0))
-    assert rc == -5
+    rc0, b0, _ = _ws(lib, _fourier_problem(lib, r=0))
+    rc6, b6, _ = _ws(lib, _fourier_problem(lib, r=6))
+    assert rc0 == 0 and rc6 == 0 and b0 >= b6 + 4 * 4 * 64 * 96 * 96   # K = 6 = r_cap, plus the 2q x 2n embedding
+    # 96 x 96 frames, q = 450, m = 900: K = min(n, q, m) / 10 = 45, so 2K = 90 > 88
+    rc, _, msg = _ws(lib, _fourier_problem(lib, r=0, q=450, m=900, ldy=900))
+    assert rc == -5 and "automatic rank" in msg
+    rc, _, _ = _ws(lib, _fourier_problem(lib, r=0, q=440, m=900, ldy=900))   # K = 44
+    assert rc == 0
     rc, _, _ = _ws(lib, _problem(lib, r=0), lib.default_params(rank_energy=1.5))
     assert rc == -1
     so = lib.load()
