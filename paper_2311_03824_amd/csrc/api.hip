@@ -710,6 +710,16 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->auto_rank = prob->r == 0;
   if (h->fmt != FMT_PFOURIER) {
     h->col_waves = choose_col_waves(h->prob);
+    // a GDmin iteration's column workgroup (with P_k) may need more LDS than the
+    // initialisation's: raise the kernels' limit now, before any graph capture
+    if (col_lds_bytes(prob->n, prob->m, r_eff(*prob), prob->rho, 1, prob->a_format == ALTGDMIN_A_PHILOX,
+                      h->col_waves) > kColLdsDefault) {
+      const hipError_t le = col_allow_big_lds();
+      if (le != hipSuccess) {
+        delete h;
+        return fail(ALTGDMIN_EHIP, std::string("column kernels' LDS limit: ") + hipGetErrorString(le));
+      }
+    }
     // the default instantiations with cached loads when the streamed plane fits in
     // the Infinity Cache (the autotuner, when on, times them against the unrolls)
     if (load_policy(streamed_plane_bytes(h->prob, h->colfmt)) == POL_CACHED) h->col_unroll = h->au_depth = -1;

@@ -908,7 +908,9 @@ def test_degenerate_first_iteration_matches_oracle(lib, torch, shape):
 
 
 @pytest.mark.parametrize("shape", [dict(n=19692, q=20, m=64, r=4, rho=30),     # the largest n at m = 64
-                                   dict(n=16384, q=12, m=400, r=10, rho=50)])  # 128 x 128 frames, benchmark m, r
+                                   dict(n=16384, q=12, m=400, r=10, rho=50),   # 128 x 128 frames, benchmark m, r
+                                   # ~55 KiB in the initialisation, ~72 KiB (with P_k) in the captured iterations
+                                   dict(n=5000, q=20, m=400, r=10, rho=50)])
 def test_largest_n_matches_oracle(lib, torch, shape):
     """n beyond 64 KiB of LDS per column workgroup (up to the CU's 160 KiB: one column
     workgroup per CU, the kernels' LDS limit raised): three GDmin iterations from the
