@@ -216,7 +216,7 @@ int altgdmin_solve(const altgdmin_problem* prob, const altgdmin_params* par, voi
 int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, double* ms_out);
 
 /* Autotuner (with ALTGDMIN_FLAG_AUTOTUNE): the column-kernel unroll JU (columns
- * per load group, 1, 2, 4 or 8) and the A_k U pipeline depth AUD (1, 2, 4 or 8) chosen for
+ * per load group, 1, 2, 4 or 8) and the A_k U pipeline depth AUD (1, 2, 3, 4 or 8) chosen for
  * this handle; 0 means the default instantiation, -1 the default instantiation
  * with cached loads of A.  Without the autotuner every handle reports 0, or -1
  * when the plane of A that the column passes stream (4 bytes per element, 2 in

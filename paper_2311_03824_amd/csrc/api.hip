@@ -485,8 +485,9 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   if (const char* force = std::getenv("ALTGDMIN_TUNE_FORCE")) {
     int ju = 0, aud = 0;
     auto ok = [](int v) { return v == -1 || v == 1 || v == 2 || v == 4 || v == 8; };
-    if (std::sscanf(force, "%d,%d", &ju, &aud) != 2 || !ok(ju) || !ok(aud))
-      return fail(ALTGDMIN_EINVAL, "ALTGDMIN_TUNE_FORCE must be JU,AUD with JU, AUD in {-1, 1, 2, 4, 8}");
+    if (std::sscanf(force, "%d,%d", &ju, &aud) != 2 || !ok(ju) || !(ok(aud) || aud == 3))
+      return fail(ALTGDMIN_EINVAL,
+                  "ALTGDMIN_TUNE_FORCE must be JU,AUD with JU in {-1, 1, 2, 4, 8}, AUD in {-1, 1, 2, 3, 4, 8}");
     if (ju == 8 && p.m > 512) ju = 4;   // JU = 8 is built for at most two row chunks
     // the unrolls are built for 4-wave workgroups; -1 (the cached default) for every width
     h->col_unroll = ju < 0 || h->col_waves == kWaves ? ju : 0;
@@ -539,7 +540,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   int best_aud = 0, best_ju = 0;
   float best_au = 1e30f, best_col = 1e30f;
   hipError_t e = hipSuccess;
-  for (int aud : {1, 2, 4, 8, -1}) {
+  for (int aud : {1, 2, 3, 4, 8, -1}) {
     if (aud < 0 && !cached) break;
     float ms = 0.f;
     e = timed([&] { return aud > 0 ? launch_au_tuned(h->fmt, aud, au, st) : launch_au(h->fmt, au, st, POL_CACHED); },

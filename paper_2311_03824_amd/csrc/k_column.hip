@@ -734,8 +734,12 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   auto load_rows = [&](int t0) {        // rows of columns jw + js (t0 + t), t = lane
     const int jrow = jw + js * (t0 + lane);
     const int jr = jrow < n ? jrow : n - 1;
+    const float* row = U + (long long)jr * r;
+    // r is R - 1 or R: the entries below R - 1 sit at fixed offsets (one address
+    // register for the row); entry R - 1 reads the row's last entry, a duplicate
+    // when r = R - 1 that store_rows zeroes
 #pragma unroll
-    for (int rr = 0; rr < RP; ++rr) un[rr] = U[(long long)jr * r + (rr < r ? rr : 0)];
+    for (int rr = 0; rr < RP; ++rr) un[rr] = rr < R - 1 ? row[rr] : (rr == R - 1 ? row[r - 1] : 0.f);
   };
   auto store_rows = [&](int t0) {
     const int jrow = jw + js * (t0 + lane);
@@ -878,11 +882,17 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
 }
 
 // A_k loads of the next AUD columns in flight per wave (autotuned variants differ).
-// The r accumulators per row compete with the loads for registers: at R = 14 one
-// column in flight keeps four waves per SIMD (0.311 against 0.377 ms with two at
-// n = q = 1000, m = 400, FP32), at R = 16 four in flight hide the latency best
-// (0.382 against 0.409 ms); two elsewhere.
-constexpr int default_aud(int R) { return R == 14 ? 1 : (R == 16 ? 4 : 2); }
+// Streamed loads: the r accumulators per row compete with the loads for registers:
+// at R = 14 one column in flight keeps four waves per SIMD (0.311 against 0.377 ms
+// with two at n = q = 1000, m = 400, FP32), at R = 16 four in flight hide the
+// latency best (0.382 against 0.409 ms); two elsewhere.  Cached loads (a plane that
+// fits in the Infinity Cache, typically few columns and so one workgroup per CU):
+// three in flight at every rank, four at R <= 4 (q = 125, n = 1000, m = 400, FP32:
+// 0.091 against 0.105 ms at r = 10, 0.121 against 0.149 at r = 14, 0.068 against
+// 0.081 at r = 4).  The depth only moves loads: the arithmetic is the same.
+constexpr int default_aud(int R, int POL = POL_STREAM) {
+  return POL == POL_CACHED ? (R <= 4 ? 4 : 3) : (R == 14 ? 1 : (R == 16 ? 4 : 2));
+}
 
 template <int FMT, int R, int AUD = default_aud(R), int POL = POL_STREAM>
 __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
@@ -898,7 +908,7 @@ __global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const in
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  au_body<FMT, R, default_aud(R), POL>(a, mp.y, smem);
+  au_body<FMT, R, default_aud(R, POL), POL>(a, mp.y, smem);
 }
 
 #if !defined(ALTG_PART) || ALTG_PART == 1
@@ -1081,7 +1091,7 @@ hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q
 
 #if ALTG_PART == 2
 // Autotuned variants of the plane formats: k_col with JU in {1, 2, 4, 8} (FP32,
-// BF16X2 and the mixed BF16 form) and k_au with AUD in {1, 2, 4, 8} (FP32,
+// BF16X2 and the mixed BF16 form) and k_au with AUD in {1, 2, 3, 4, 8} (FP32,
 // BF16X2).  JU = 8 and AUD = 8 keep many loads in flight per wave at one or two
 // waves per SIMD: for problems with few columns, where each CU holds one or two
 // column workgroups.  Every variant gives the same bits as the default one.
@@ -1092,12 +1102,13 @@ typedef void (*au_fn2)(AUArgs);
 #define COLT_NC4(F, NC) {k_col<F, NC, 1>, k_col<F, NC, 2>, k_col<F, NC, 4>, nullptr}
 #define COLT_F(F) {COLT_NC(F, 1), COLT_NC(F, 2), COLT_NC4(F, 3), COLT_NC4(F, 4)}
 static const col_fn2 kColTuned[3][kNCMax][4] = {COLT_F(FMT_F32), COLT_F(FMT_BF16X2), COLT_F(FMT_BF16MIX)};
-#define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 4>, k_au<F, R, 8>}
+#define AUT_R(F, R) {k_au<F, R, 1>, k_au<F, R, 2>, k_au<F, R, 3>, k_au<F, R, 4>, k_au<F, R, 8>}
 #define AUT_F(F) {AUT_R(F, 2), AUT_R(F, 4), AUT_R(F, 6), AUT_R(F, 8), AUT_R(F, 10), AUT_R(F, 12), AUT_R(F, 14), AUT_R(F, 16)}
-static const au_fn2 kAUTuned[2][kRMax / 2][4] = {AUT_F(FMT_F32), AUT_F(FMT_BF16X2)};
+static const au_fn2 kAUTuned[2][kRMax / 2][5] = {AUT_F(FMT_F32), AUT_F(FMT_BF16X2)};
 
-static int tuned_slot(int v, const int (&vals)[4]) {
-  for (int i = 0; i < 4; ++i)
+template <int N>
+static int tuned_slot(int v, const int (&vals)[N]) {
+  for (int i = 0; i < N; ++i)
     if (vals[i] == v) return i;
   return -1;
 }
@@ -1185,7 +1196,7 @@ hipError_t launch_col_tuned(int fmt, int ju, const ColArgs& a, hipStream_t st) {
 }
 
 hipError_t launch_au_tuned(int fmt, int aud, const AUArgs& a, hipStream_t st) {
-  static const int kAUD[4] = {1, 2, 4, 8};
+  static const int kAUD[5] = {1, 2, 3, 4, 8};
   const int slot = tuned_slot(aud, kAUD);
   if ((fmt != FMT_F32 && fmt != FMT_BF16X2) || slot < 0) return hipErrorInvalidValue;
   const int ri = (a.r + 1) / 2 - 1;
@@ -1216,10 +1227,12 @@ static const col_fn3 kColCached[2][5][kNCMax] = {
 static const colg_fn3 kColGrpCached[2][5][kNCMax] = {
     {COLGC_F(FMT_F32, 4), COLGC_F(FMT_BF16X2, 4), COLGC_F(FMT_BF16HI, 4), COLC_NONE, COLGC_F(FMT_BF16MIX, 4)},
     {COLGC_F(FMT_F32, 8), COLGC_F(FMT_BF16X2, 8), COLGC_F(FMT_BF16HI, 8), COLC_NONE, COLGC_F(FMT_BF16MIX, 8)}};
-#define AUC_F(F) {k_au<F, 2, default_aud(2), POL_CACHED>, k_au<F, 4, default_aud(4), POL_CACHED>, \
-                  k_au<F, 6, default_aud(6), POL_CACHED>, k_au<F, 8, default_aud(8), POL_CACHED>, \
-                  k_au<F, 10, default_aud(10), POL_CACHED>, k_au<F, 12, default_aud(12), POL_CACHED>, \
-                  k_au<F, 14, default_aud(14), POL_CACHED>, k_au<F, 16, default_aud(16), POL_CACHED>}
+#define AUC_F(F) {k_au<F, 2, default_aud(2, POL_CACHED), POL_CACHED>, k_au<F, 4, default_aud(4, POL_CACHED), POL_CACHED>, \
+                  k_au<F, 6, default_aud(6, POL_CACHED), POL_CACHED>, k_au<F, 8, default_aud(8, POL_CACHED), POL_CACHED>, \
+                  k_au<F, 10, default_aud(10, POL_CACHED), POL_CACHED>,                                     \
+                  k_au<F, 12, default_aud(12, POL_CACHED), POL_CACHED>,                                     \
+                  k_au<F, 14, default_aud(14, POL_CACHED), POL_CACHED>,                                     \
+                  k_au<F, 16, default_aud(16, POL_CACHED), POL_CACHED>}
 static const au_fn3 kAUCached[3][kRMax / 2] = {AUC_F(FMT_F32), AUC_F(FMT_BF16X2), AUC_F(FMT_BF16HI)};
 #define AUGC_F(F) {k_au_grp<F, 2, POL_CACHED>, k_au_grp<F, 4, POL_CACHED>, k_au_grp<F, 6, POL_CACHED>, \
                    k_au_grp<F, 8, POL_CACHED>, k_au_grp<F, 10, POL_CACHED>, k_au_grp<F, 12, POL_CACHED>, \
