@@ -27,9 +27,11 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+from paper_2311_03824_amd import roofline  # noqa: E402
 from paper_2311_03824_amd.roofline import au_kernel_bytes, column_kernel_bytes  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E peak
+FP32_VECTOR_TFLOPS = 157.3      # MI355X FP32 vector peak (256 CUs at 2.4 GHz)
 WORKLOAD = "gauss_n1000_q1000_m400_r10_rho50"
 T_ITERS = 200
 
@@ -295,7 +297,14 @@ def fourier_form(lib, torch, np, iters: int = 200):
     err = float(np.linalg.norm(X - inst.X_star) / np.linalg.norm(inst.X_star))
     kms = s.profile_iteration(20)
     s.close()
+    flops = roofline.fourier_column_flops(96, 96, cfg["q"], cfg["m"], cfg["r"])
+    tflops = flops / (kms["k_col"] * 1e-3) / 1e12
     return {"workload": "fourier_96x96_q64_m1536_r6_rho184 (complex64, 2D FFTs in LDS)",
+            "k_fcol_roofline": {"bound": "latency", "flops_per_launch": flops, "achieved": round(tflops, 3),
+                                "peak": FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                                "frac": round(tflops / FP32_VECTOR_TFLOPS, 4),
+                                "frac_of_busy_cus": round(tflops / (FP32_VECTOR_TFLOPS * cfg["q"] / 256), 4),
+                                "note": "one 1024-thread workgroup per frame: 64 of 256 CUs; FFT and Gram flops"},
             "gdmin_iters_per_s": round(iters / (it_ms * 1e-3), 1), "solve_ms": round(init_ms + it_ms, 2),
             "init_ms": round(init_ms, 2), "iterations": iters,
             "kernels_ms": {"k_fu": round(kms["k_au"], 4), "k_fcol": round(kms["k_col"], 4),

@@ -1,4 +1,5 @@
-"""Algorithmic HBM bytes of the two streaming kernels of a GDmin iteration.
+"""Algorithmic HBM bytes of the two streaming kernels of a GDmin iteration, and the
+algorithmic FLOPs of the partial Fourier column kernel.
 
 These are the bytes the algorithm must move (each element of A read once per
 pass, the small per-column vectors once), not what the hardware moved; the
@@ -35,3 +36,19 @@ def iteration_bytes(n, q, m, r, rho, tau=3, mixed=False):
     4 bytes per element everywhere; the mixed BF16 form: 2 in the column passes."""
     return (au_kernel_bytes(n, q, m, r, 4.0)
             + column_kernel_bytes(n, q, m, r, rho, tau, 2.0 if mixed else 4.0, 4.0))
+
+
+def fourier_column_flops(n1, n2, q, m, r, transforms=8):
+    """Algorithmic FLOPs of one launch of the partial Fourier column kernel (real
+    flops, a complex multiply-add counted as 8).
+
+    Per frame: `transforms` unitary 2D DFTs of n = n1 n2 points at the
+    conventional 5 n log2 n of a radix-2 FFT (8 per GDmin call once the supports
+    hold: per IHT step the adjoint of the residual and the forward transform of
+    the step on the support, plus the LS / gradient tail), and the Gram
+    G_k = P_k^H P_k (m r^2 multiply-adds).  The projections and the IHT updates
+    (O(m r) and O(n) per step) are left out: under 2 % of the total here.
+    """
+    import math
+    n = n1 * n2
+    return q * (transforms * 5.0 * n * math.log2(n) + 8.0 * m * r * r)

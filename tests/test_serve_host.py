@@ -490,3 +490,12 @@ def test_iteration_bytes_formula():
     full = roofline.iteration_bytes(1000, 1000, 400, 10, 50)
     mixed = roofline.iteration_bytes(1000, 1000, 400, 10, 50, mixed=True)
     assert full == pytest.approx(8.36e9, rel=1e-3) and mixed == pytest.approx(5.16e9, rel=2e-3)
+
+
+def test_fourier_column_flops_formula():
+    from paper_2311_03824_amd import roofline
+    # a 2 x 2 frame: one transform is 5 * 4 * log2(4) = 40 flops; the Gram 8 m r^2
+    assert roofline.fourier_column_flops(2, 2, 1, 3, 1, transforms=1) == 40.0 + 24.0
+    # the benchmark's 64 frames of 96 x 96, m = 1536, r = 6: 8 transforms each
+    f = roofline.fourier_column_flops(96, 96, 64, 1536, 6)
+    assert f == pytest.approx(64 * (8 * 5 * 9216 * 13.1699 + 8 * 1536 * 36), rel=1e-5)
