@@ -222,16 +222,19 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
  * when the plane of A that the column passes stream (4 bytes per element, 2 in
  * the mixed BF16 form) takes at most 200 MiB, so that the Infinity Cache keeps
  * it between passes; otherwise A is read with non-temporal loads.  With the
- * autotuner the cached default is one more timed candidate.  The environment
+ * autotuner that default (0 or -1) is the baseline the variants are timed
+ * against.  The default A_k U kernels keep deeper load pipelines for launches of
+ * at most 256 columns (one workgroup per CU).  The environment
  * variable ALTGDMIN_LOAD_POLICY=stream|cached forces the load policy of the
  * default instantiations (for tests; the batched altgdmin_step_many applies the
  * same 200 MiB rule to all its problems together).  The choice is made once per
- * (GPU architecture, A format, n, q, m, r, rho) in a process by timing each
- * variant three times on the problem's own data (A_k U from a fixed orthonormal
- * U; the column kernel as in a GDmin iteration, from an empty support) before
- * the initialisation; with the environment variable ALTGDMIN_TUNE_CACHE naming
- * a file, choices are read from and appended to it as JSON lines keyed by the
- * architecture.  ALTGDMIN_TUNE_FORCE="JU,AUD" takes the given variants without
+ * (GPU architecture, A format, n, q, m, r, rho) in a process by timing the
+ * default and each variant five times on the problem's own data (A_k U from a
+ * fixed orthonormal U; the column kernel as in a GDmin iteration, from an empty
+ * support) before the initialisation; a variant replaces the default only when
+ * it is at least 2 % faster than the best so far.  With the environment variable
+ * ALTGDMIN_TUNE_CACHE naming a file, choices are read from and appended to it as
+ * JSON lines keyed by the architecture.  ALTGDMIN_TUNE_FORCE="JU,AUD" takes the given variants without
  * timing (JU = 8 falls back to 4 above 512 rows; -1 selects the cached
  * default).  Every variant and both load policies compute the same bits.  Host
  * call. */

@@ -523,44 +523,48 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   EventPair ev;
   HIPCHK(ev.create());
   hipEvent_t e0 = ev.e[0], e1 = ev.e[1];
+  constexpr int kReps = 5;
   auto timed = [&](auto launch, float* ms) -> hipError_t {
     hipError_t e = launch();   // warm-up
     if (e == hipSuccess) e = hipEventRecord(e0, st);
-    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch();
+    for (int rep = 0; rep < kReps && e == hipSuccess; ++rep) e = launch();
     if (e == hipSuccess) e = hipEventRecord(e1, st);
     if (e == hipSuccess) e = hipEventSynchronize(e1);
     if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
-    *ms /= 3.f;
+    *ms /= (float)kReps;
     return e;
   };
-  // candidates: the unrolls (4-wave column workgroups only; the default alone at
-  // other widths), and, when the streamed plane fits in the cache, the default
-  // instantiation with cached loads (-1)
+  // The default instantiation under the load policy's rule (0: streamed, -1:
+  // cached) is timed first and kept unless a variant beats the best so far by
+  // kMargin: the candidates run from an empty support, which is not the state of
+  // the iterations they are picked for, so near-equal times are not a reason to
+  // leave the default.  Candidates: the unrolls (4-wave column workgroups only)
+  // and the A_k U depths.
+  constexpr float kMargin = 0.02f;
   const bool cached = load_policy(streamed_plane_bytes(p, h->colfmt)) == POL_CACHED;
-  int best_aud = 0, best_ju = 0;
-  float best_au = 1e30f, best_col = 1e30f;
-  hipError_t e = hipSuccess;
-  for (int aud : {1, 2, 3, 4, 8, -1}) {
-    if (aud < 0 && !cached) break;
-    float ms = 0.f;
-    e = timed([&] { return aud > 0 ? launch_au_tuned(h->fmt, aud, au, st) : launch_au(h->fmt, au, st, POL_CACHED); },
-              &ms);
+  const int base = cached ? -1 : 0;
+  const int pol = cached ? POL_CACHED : POL_STREAM;
+  int best_aud = base, best_ju = base;
+  float best_au = 0.f, best_col = 0.f;
+  hipError_t e = timed([&] { return launch_au(h->fmt, au, st, pol); }, &best_au);
+  for (int aud : {1, 2, 3, 4, 8}) {
     if (e != hipSuccess) break;
-    if (ms < best_au) { best_au = ms; best_aud = aud; }
+    float ms = 0.f;
+    e = timed([&] { return launch_au_tuned(h->fmt, aud, au, st); }, &ms);
+    if (e != hipSuccess) break;
+    if (ms < (1.f - kMargin) * best_au) { best_au = ms; best_aud = aud; }
   }
-  for (int ju : {1, 2, 4, 8, 0, -1}) {
-    if (e != hipSuccess) break;
-    if ((ju > 0 && h->col_waves != kWaves) || (ju == 0 && (h->col_waves == kWaves || !cached)) || (ju < 0 && !cached))
-      continue;
+  if (e == hipSuccess) e = timed([&] { return launch_col(h->colfmt, ca, st, pol); }, &best_col);
+  for (int ju : {1, 2, 4, 8}) {
+    if (e != hipSuccess || h->col_waves != kWaves) break;
     float ms = 0.f;
-    e = timed([&] { return ju > 0 ? launch_col_tuned(h->colfmt, ju, ca, st)
-                                  : launch_col(h->colfmt, ca, st, ju < 0 ? POL_CACHED : POL_STREAM); }, &ms);
+    e = timed([&] { return launch_col_tuned(h->colfmt, ju, ca, st); }, &ms);
     if (e == hipErrorNotSupported) {   // no such instantiation for this row count: not a candidate
       e = hipSuccess;
       continue;
     }
     if (e != hipSuccess) break;
-    if (ms < best_col) { best_col = ms; best_ju = ju; }
+    if (ms < (1.f - kMargin) * best_col) { best_col = ms; best_ju = ju; }
   }
   if (e != hipSuccess) return fail(ALTGDMIN_EHIP, std::string("autotune: ") + hipGetErrorString(e));
   h->col_unroll = best_ju;

@@ -735,11 +735,11 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
     const int jrow = jw + js * (t0 + lane);
     const int jr = jrow < n ? jrow : n - 1;
     const float* row = U + (long long)jr * r;
-    // r is R - 1 or R: the entries below R - 1 sit at fixed offsets (one address
-    // register for the row); entry R - 1 reads the row's last entry, a duplicate
-    // when r = R - 1 that store_rows zeroes
+    // one address register for the row and fixed offsets; r is uniform over the
+    // wave (a batched launch's R is its largest rank, so r may be far below R),
+    // and entries at or beyond r are never read
 #pragma unroll
-    for (int rr = 0; rr < RP; ++rr) un[rr] = rr < R - 1 ? row[rr] : (rr == R - 1 ? row[r - 1] : 0.f);
+    for (int rr = 0; rr < RP; ++rr) un[rr] = rr < r ? row[rr] : 0.f;
   };
   auto store_rows = [&](int t0) {
     const int jrow = jw + js * (t0 + lane);
@@ -882,19 +882,29 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
 }
 
 // A_k loads of the next AUD columns in flight per wave (autotuned variants differ).
-// Streamed loads: the r accumulators per row compete with the loads for registers:
-// at R = 14 one column in flight keeps four waves per SIMD (0.311 against 0.377 ms
-// with two at n = q = 1000, m = 400, FP32), at R = 16 four in flight hide the
-// latency best (0.382 against 0.409 ms); two elsewhere.  Cached loads (a plane that
-// fits in the Infinity Cache, typically few columns and so one workgroup per CU):
-// three in flight at every rank, four at R <= 4 (q = 125, n = 1000, m = 400, FP32:
-// 0.091 against 0.105 ms at r = 10, 0.121 against 0.149 at r = 14, 0.068 against
-// 0.081 at r = 4).  The depth only moves loads: the arithmetic is the same.
-constexpr int default_aud(int R, int POL = POL_STREAM) {
-  return POL == POL_CACHED ? (R <= 4 ? 4 : 3) : (R == 14 ? 1 : (R == 16 ? 4 : 2));
+// The r accumulators per row compete with the loads for registers: at R = 14 one
+// column in flight keeps four waves per SIMD (0.311 against 0.377 ms with two at
+// n = q = 1000, m = 400, FP32), at R = 16 four in flight hide the latency best
+// (0.382 against 0.409 ms); two elsewhere.  The BF16 hi + lo planes take two loads
+// per group of elements and one group in flight is best up to R = 14 (0.308
+// against 0.319 ms at r = 10, 0.273 against 0.292 at r = 4), three at R = 16
+// (0.423 against 0.457 with two).
+constexpr int default_aud(int R, int FMT = FMT_F32) {
+  if (FMT == FMT_BF16X2) return R == 16 ? 3 : 1;
+  return R == 14 ? 1 : (R == 16 ? 4 : 2);
 }
 
-template <int FMT, int R, int AUD = default_aud(R), int POL = POL_STREAM>
+// Launches of at most kDeepAuColumns columns (the MI355X's 256 CUs: one column
+// workgroup per CU, one wave per SIMD) take the deep variants: three loads in
+// flight at every rank, four at R <= 4 (cached loads at q = 125, n = 1000,
+// m = 400, FP32: 0.091 against 0.105 ms at r = 10, 0.121 against 0.149 at
+// r = 14, 0.068 against 0.081 at r = 4).  With several workgroups per CU the
+// default depths keep more waves resident.  The depth only moves loads: the
+// arithmetic, and so every bit, is the same.
+constexpr int deep_aud(int R, int = FMT_F32) { return R <= 4 ? 4 : 3; }
+constexpr int kDeepAuColumns = 256;
+
+template <int FMT, int R, int AUD = default_aud(R, FMT), int POL = POL_STREAM>
 __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
@@ -902,13 +912,13 @@ __global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
-template <int FMT, int R, int POL = POL_STREAM>
+template <int FMT, int R, int POL = POL_STREAM, int AUD = default_aud(R, FMT)>
 __global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const int2* map) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  au_body<FMT, R, default_aud(R, POL), POL>(a, mp.y, smem);
+  au_body<FMT, R, AUD, POL>(a, mp.y, smem);
 }
 
 #if !defined(ALTG_PART) || ALTG_PART == 1
@@ -960,6 +970,17 @@ static const au_fn kAUTable[4][kRMax / 2] = {AU_ROW(FMT_F32), AU_ROW(FMT_BF16X2)
                     k_au_grp<F, 14>, k_au_grp<F, 16>}
 static const aug_fn kAUGrpTable[4][kRMax / 2] = {AUG_ROW(FMT_F32), AUG_ROW(FMT_BF16X2), AUG_ROW(FMT_BF16HI),
                                                  AUG_ROW(FMT_PHILOX)};
+// the deep depths of the plane formats, for launches of at most kDeepAuColumns columns
+// (the Philox form regenerates A and is bound by its ALU work: it keeps the defaults)
+#define AUD_ROW(F) {k_au<F, 2, deep_aud(2)>, k_au<F, 4, deep_aud(4)>, k_au<F, 6, deep_aud(6)>, k_au<F, 8, deep_aud(8)>, \
+                    k_au<F, 10, deep_aud(10)>, k_au<F, 12, deep_aud(12)>, k_au<F, 14, deep_aud(14)>,              \
+                    k_au<F, 16, deep_aud(16)>}
+static const au_fn kAUDeep[3][kRMax / 2] = {AUD_ROW(FMT_F32), AUD_ROW(FMT_BF16X2), AUD_ROW(FMT_BF16HI)};
+#define AUGD_ROW(F) {k_au_grp<F, 2, POL_STREAM, deep_aud(2)>, k_au_grp<F, 4, POL_STREAM, deep_aud(4)>,   \
+                     k_au_grp<F, 6, POL_STREAM, deep_aud(6)>, k_au_grp<F, 8, POL_STREAM, deep_aud(8)>,   \
+                     k_au_grp<F, 10, POL_STREAM, deep_aud(10)>, k_au_grp<F, 12, POL_STREAM, deep_aud(12)>, \
+                     k_au_grp<F, 14, POL_STREAM, deep_aud(14)>, k_au_grp<F, 16, POL_STREAM, deep_aud(16)>}
+static const aug_fn kAUGrpDeep[3][kRMax / 2] = {AUGD_ROW(FMT_F32), AUGD_ROW(FMT_BF16X2), AUGD_ROW(FMT_BF16HI)};
 
 bool au_supported(int m, int r) { return m >= 1 && m <= 256 * kNCMax && r >= 1 && r <= kRMax; }
 
@@ -991,7 +1012,8 @@ hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st, int pol) {
   const int ri = (a.r + 1) / 2 - 1;
   const AULayout lay(a.m, a.r, fmt == FMT_PHILOX);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUTable[fmt][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  const au_fn f = (fmt != FMT_PHILOX && a.q <= kDeepAuColumns) ? kAUDeep[fmt][ri] : kAUTable[fmt][ri];
+  hipLaunchKernelGGL(f, dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
 }
 
@@ -1022,7 +1044,8 @@ hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, 
   }
   const int ri = (rmax + 1) / 2 - 1;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUGrpTable[fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab, map);
+  const aug_fn f = (fmt != FMT_PHILOX && blocks <= kDeepAuColumns) ? kAUGrpDeep[fmt][ri] : kAUGrpTable[fmt][ri];
+  hipLaunchKernelGGL(f, dim3(blocks), dim3(kThreads), lds, st, tab, map);
   return hipGetLastError();
 }
 
@@ -1227,17 +1250,20 @@ static const col_fn3 kColCached[2][5][kNCMax] = {
 static const colg_fn3 kColGrpCached[2][5][kNCMax] = {
     {COLGC_F(FMT_F32, 4), COLGC_F(FMT_BF16X2, 4), COLGC_F(FMT_BF16HI, 4), COLC_NONE, COLGC_F(FMT_BF16MIX, 4)},
     {COLGC_F(FMT_F32, 8), COLGC_F(FMT_BF16X2, 8), COLGC_F(FMT_BF16HI, 8), COLC_NONE, COLGC_F(FMT_BF16MIX, 8)}};
-#define AUC_F(F) {k_au<F, 2, default_aud(2, POL_CACHED), POL_CACHED>, k_au<F, 4, default_aud(4, POL_CACHED), POL_CACHED>, \
-                  k_au<F, 6, default_aud(6, POL_CACHED), POL_CACHED>, k_au<F, 8, default_aud(8, POL_CACHED), POL_CACHED>, \
-                  k_au<F, 10, default_aud(10, POL_CACHED), POL_CACHED>,                                     \
-                  k_au<F, 12, default_aud(12, POL_CACHED), POL_CACHED>,                                     \
-                  k_au<F, 14, default_aud(14, POL_CACHED), POL_CACHED>,                                     \
-                  k_au<F, 16, default_aud(16, POL_CACHED), POL_CACHED>}
-static const au_fn3 kAUCached[3][kRMax / 2] = {AUC_F(FMT_F32), AUC_F(FMT_BF16X2), AUC_F(FMT_BF16HI)};
-#define AUGC_F(F) {k_au_grp<F, 2, POL_CACHED>, k_au_grp<F, 4, POL_CACHED>, k_au_grp<F, 6, POL_CACHED>, \
-                   k_au_grp<F, 8, POL_CACHED>, k_au_grp<F, 10, POL_CACHED>, k_au_grp<F, 12, POL_CACHED>, \
-                   k_au_grp<F, 14, POL_CACHED>, k_au_grp<F, 16, POL_CACHED>}
-static const aug_fn3 kAUGrpCached[3][kRMax / 2] = {AUGC_F(FMT_F32), AUGC_F(FMT_BF16X2), AUGC_F(FMT_BF16HI)};
+// [0]: the default depths; [1]: the deep ones, for launches of at most kDeepAuColumns columns
+#define AUC_F(F, D) {k_au<F, 2, D(2, F), POL_CACHED>, k_au<F, 4, D(4, F), POL_CACHED>, k_au<F, 6, D(6, F), POL_CACHED>,     \
+                     k_au<F, 8, D(8, F), POL_CACHED>, k_au<F, 10, D(10, F), POL_CACHED>, k_au<F, 12, D(12, F), POL_CACHED>, \
+                     k_au<F, 14, D(14, F), POL_CACHED>, k_au<F, 16, D(16, F), POL_CACHED>}
+static const au_fn3 kAUCached[2][3][kRMax / 2] = {
+    {AUC_F(FMT_F32, default_aud), AUC_F(FMT_BF16X2, default_aud), AUC_F(FMT_BF16HI, default_aud)},
+    {AUC_F(FMT_F32, deep_aud), AUC_F(FMT_BF16X2, deep_aud), AUC_F(FMT_BF16HI, deep_aud)}};
+#define AUGC_F(F, D) {k_au_grp<F, 2, POL_CACHED, D(2, F)>, k_au_grp<F, 4, POL_CACHED, D(4, F)>,   \
+                      k_au_grp<F, 6, POL_CACHED, D(6, F)>, k_au_grp<F, 8, POL_CACHED, D(8, F)>,   \
+                      k_au_grp<F, 10, POL_CACHED, D(10, F)>, k_au_grp<F, 12, POL_CACHED, D(12, F)>, \
+                      k_au_grp<F, 14, POL_CACHED, D(14, F)>, k_au_grp<F, 16, POL_CACHED, D(16, F)>}
+static const aug_fn3 kAUGrpCached[2][3][kRMax / 2] = {
+    {AUGC_F(FMT_F32, default_aud), AUGC_F(FMT_BF16X2, default_aud), AUGC_F(FMT_BF16HI, default_aud)},
+    {AUGC_F(FMT_F32, deep_aud), AUGC_F(FMT_BF16X2, deep_aud), AUGC_F(FMT_BF16HI, deep_aud)}};
 
 static int cached_width_row(int waves) { return waves == 8 ? 1 : (waves == 0 || waves == kWaves ? 0 : -1); }
 
@@ -1293,7 +1319,7 @@ hipError_t launch_au_cached(int fmt, const AUArgs& a, hipStream_t st) {
   const int ri = (a.r + 1) / 2 - 1;
   const AULayout lay(a.m, a.r, 0);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUCached[fmt][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  hipLaunchKernelGGL(kAUCached[a.q <= kDeepAuColumns][fmt][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
   return hipGetLastError();
 }
 
@@ -1302,7 +1328,8 @@ hipError_t launch_au_grp_cached(int fmt, int rmax, const AUArgs* tab, const int2
   if (fmt < FMT_F32 || fmt > FMT_BF16HI) return hipErrorNotSupported;
   const int ri = (rmax + 1) / 2 - 1;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUGrpCached[fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab, map);
+  hipLaunchKernelGGL(kAUGrpCached[blocks <= kDeepAuColumns][fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab,
+                     map);
   return hipGetLastError();
 }
 #endif  // ALTG_PART == 3
