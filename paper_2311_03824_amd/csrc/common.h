@@ -321,49 +321,54 @@ __device__ __forceinline__ float get4(float4 v, int e) {
   return e == 0 ? v.x : (e == 1 ? v.y : (e == 2 ? v.z : v.w));
 }
 
-// Lower Cholesky factor L of an SPD r x r FP64 matrix G (row-major), then
-// G^{-1} = L^{-T} L^{-1} into Ginv, for an SPD r x r matrix G (r <= 64), by the
-// whole workgroup (every thread calls it).  Cholesky G = L L^T column by column:
-// thread j + 1 + t computes L[j + 1 + t][j]; then thread c solves L y = e_c and
-// L^T x = y for column c of G^{-1} (y in Y, column c at Y[i * r + c]).  G, L,
-// Ginv, Y live in LDS.  Returns false, with the identity in Ginv, if a pivot is
-// not positive; the result is the same on every thread.
-__device__ inline bool block_chol_inverse(const double* G, double* L, double* Ginv, double* Y, int r) {
-  const int tid = threadIdx.x;
-  for (int j = 0; j < r; ++j) {
-    double s = G[j * r + j];
-    for (int p = 0; p < j; ++p) s -= L[j * r + p] * L[j * r + p];
-    if (!(s > 0.0)) {   // every thread computed the same s
-      for (int i = tid; i < r * r; i += blockDim.x) Ginv[i] = (i % (r + 1) == 0) ? 1.0 : 0.0;
-      __syncthreads();
-      return false;
-    }
-    const double d = sqrt(s);
-    const int i = j + 1 + tid;
-    if (i < r) {
-      double t = G[i * r + j];
-      for (int p = 0; p < j; ++p) t -= L[i * r + p] * L[j * r + p];
-      L[i * r + j] = t / d;
-    }
-    if (tid == 0) L[j * r + j] = d;
-    if (tid < j) L[tid * r + j] = 0.0;
-    __syncthreads();
+// G^{-1} of an SPD r x r FP64 matrix G (row-major, r <= 16) by Gauss-Jordan
+// elimination without pivoting (an SPD matrix has positive pivots and needs
+// none), by one wave with no barriers: the wave's LDS accesses complete in
+// order, and each step reads every entry it needs before it writes.  W (LDS,
+// 2 r^2 doubles) holds [G | I]; step k scales row k by 1 / W[k][k] and takes
+// W[i][k] times it from every other row; the right half ends as G^{-1}, copied
+// to Ginv.  Returns false, with the identity in Ginv, when a pivot is not
+// positive (or not a number); the result is the same on every lane.  One
+// reciprocal per step and a chain of r steps, with the other waves idle: the
+// A_k U launch at n = q = 1000, m = 400, r = 10 went from 0.269 to 0.262 ms
+// against a workgroup-wide Cholesky with two triangular solves (which chain r
+// square roots and 3r divisions under barriers).
+__device__ inline bool wave_spd_inverse(const double* G, double* W, double* Ginv, int r) {
+  const int lane = threadIdx.x & 63, w2 = 2 * r, ne = r * w2;   // ne <= 512: at most 8 entries per lane
+  for (int e = lane; e < ne; e += 64) {
+    const int i = e / w2, c = e - i * w2;
+    W[e] = c < r ? G[i * r + c] : (c - r == i ? 1.0 : 0.0);
   }
-  if (tid < r) {
-    const int c = tid;
-    for (int i = c; i < r; ++i) {           // rows above c of y are zero
-      double t = (i == c) ? 1.0 : 0.0;
-      for (int p = c; p < i; ++p) t -= L[i * r + p] * Y[p * r + c];
-      Y[i * r + c] = t / L[i * r + i];
+  bool ok = true;
+  for (int k = 0; k < r && ok; ++k) {
+    const double piv = W[k * w2 + k];
+    if (!(piv > 0.0)) {
+      ok = false;
+      break;
     }
-    for (int i = r - 1; i >= 0; --i) {
-      double t = i >= c ? Y[i * r + c] : 0.0;
-      for (int p = i + 1; p < r; ++p) t -= L[p * r + i] * Ginv[p * r + c];
-      Ginv[i * r + c] = t / L[i * r + i];
+    const double inv = 1.0 / piv;
+    double nv[8];
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = lane + 64 * t;
+      nv[t] = 0.0;
+      if (e < ne) {
+        const int i = e / w2, c = e - i * w2;
+        const double rk = W[k * w2 + c] * inv;   // the new row k
+        nv[t] = i == k ? rk : fma(-W[i * w2 + k], rk, W[e]);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+      const int e = lane + 64 * t;
+      if (e < ne) W[e] = nv[t];
     }
   }
-  __syncthreads();
-  return true;
+  for (int e = lane; e < r * r; e += 64) {
+    const int i = e / r, c = e - i * r;
+    Ginv[e] = ok ? W[i * w2 + r + c] : (i == c ? 1.0 : 0.0);
+  }
+  return ok;
 }
 
 __host__ __device__ inline size_t align16(size_t x) { return (x + 15) & ~size_t(15); }
@@ -398,7 +403,7 @@ struct ColLayout {
 
 // LDS layout of the A_k U kernel.
 struct AULayout {
-  size_t P, gpart, G, L, Gi, y, tab, total;
+  size_t P, gpart, G, W, Gi, tab, total;
   int p_in_lds, mp;
   __host__ __device__ AULayout(int m, int r, int philox = 0) {
     mp = ((m + 3) / 4) * 4 + 4;                     // LDS row stride of the column-major P
@@ -409,9 +414,8 @@ struct AULayout {
     P = o;     o = align16(o + (pb > ust ? pb : ust));
     gpart = o; o = align16(o + 4 * 8 * (size_t)kThreads);
     G = o;     o = align16(o + 8 * (size_t)r * r);
-    L = o;     o = align16(o + 8 * (size_t)r * r);
+    W = o;     o = align16(o + 16 * (size_t)r * r);   // [G | I], r x 2r, for the inverse
     Gi = o;    o = align16(o + 8 * (size_t)r * r);
-    y = o;     o = align16(o + 8 * (size_t)r * r);
     tab = o;   o = align16(o + (philox ? 4 * (size_t)kNormalTable : 0));
     total = o;
   }

@@ -8,10 +8,11 @@
 // bits), so it is a property of the problem; problems with few columns, whose
 // workgroups cannot fill the chip, take the wider ones.
 //
-//  k_au  : P_k = A_k U (m x r), G_k = P_k^T P_k in FP64, G_k^{-1} by Cholesky
-//          (the pieces of (A_k U)^dagger, eq. (bk_LS)).  U is read with
-//          wave-uniform (scalar) loads; waves split the columns j of A_k and
-//          their partial P_k are summed in LDS in a fixed order.
+//  k_au  : P_k = A_k U (m x r), G_k = P_k^T P_k in FP64, G_k^{-1} by Gauss-Jordan in one wave
+//          (the pieces of (A_k U)^dagger, eq. (bk_LS)).  The rows of U are
+//          staged in LDS 64 at a time and read back as broadcasts; waves split
+//          the columns j of A_k and their partial P_k are summed in LDS in a
+//          fixed order.
 //  k_col : tau iterations of IHT (Alg. 2) on column k, then the LS solve for
 //          b_k (eq. (bk_LS)), the residual r_k = A_k(U b_k + s_k) - y_k and
 //          h_k = A_k^T r_k for grad_U f (Sec. 2.1), or the back-projection
@@ -691,9 +692,8 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   float* Pp = lay.p_in_lds ? reinterpret_cast<float*>(smem + lay.P) : Pk;
   double* gpart = reinterpret_cast<double*>(smem + lay.gpart);
   double* Gl = reinterpret_cast<double*>(smem + lay.G);
-  double* Ll = reinterpret_cast<double*>(smem + lay.L);
+  double* Wl = reinterpret_cast<double*>(smem + lay.W);
   double* Gil = reinterpret_cast<double*>(smem + lay.Gi);
-  double* yl = reinterpret_cast<double*>(smem + lay.y);
   ALoader<FMT, POL> L(a, k);
   if constexpr (FMT == FMT_PHILOX) {
     float* tab = reinterpret_cast<float*>(smem + lay.tab);
@@ -875,8 +875,12 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
     }
   }
   __syncthreads();
-  const bool spd = block_chol_inverse(Gl, Ll, Gil, yl, r);
-  if (!spd && tid == 0 && a.flags) a.flags[k] |= 2;
+  // G^{-1} by wave 0 (tid 0, which raises the flag, is in it)
+  if (wave == 0) {
+    const bool spd = wave_spd_inverse(Gl, Wl, Gil, r);
+    if (!spd && tid == 0 && a.flags) a.flags[k] |= 2;
+  }
+  __syncthreads();
   double* Gk = a.Ginv + (long long)k * r * r;
   for (int t = tid; t < r * r; t += kThreads) Gk[t] = Gil[t];
 }
