@@ -333,7 +333,7 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
   if (p->ldy < p->m) return fail(ALTGDMIN_EINVAL, "ldy must be >= m");
   if (!au_supported(p->m, re)) return fail(ALTGDMIN_ENOTBUILT, "no A_k U instantiation for this (m, r)");
   const int phx = p->a_format == ALTGDMIN_A_PHILOX;
-  if (col_lds_bytes(p->n, p->m, re, p->rho, 1, phx) > kColLdsMax || au_lds_bytes(p->m, re, phx) > kMaxLds)
+  if (col_lds_bytes(p->n, p->m, re, p->rho, 1, phx) > kColLdsMax || au_lds_bytes(p->m, re, phx, 8) > kMaxLds)
     return fail(ALTGDMIN_ENOTBUILT, "problem needs more than 160 KiB of LDS per column workgroup");
   return ALTGDMIN_OK;
 }
@@ -364,6 +364,12 @@ int choose_col_waves(const altgdmin_problem& p) {
     w /= 2;
   return w;
 }
+
+// Waves of the A_k U workgroup: 8 for problems whose column kernel takes 8 or
+// more (few columns: more loads in flight per CU), else 4.  It sets the order of
+// the cross-wave sums of P_k, so, like the column width, it is a property of the
+// problem (not of its A format), the same in solo and batched launches.
+int au_waves(int col_waves, int /*fmt*/) { return col_waves >= 8 ? 8 : kWaves; }
 
 ColArgs col_args(const altgdmin_handle* h) {
   const altgdmin_problem& p = h->prob;
@@ -405,7 +411,8 @@ hipError_t col_launch(const altgdmin_handle* h, int fmt, const ColArgs& a, hipSt
   return launch_col(fmt, a, st, h->col_unroll < 0 ? POL_CACHED : POL_STREAM);
 }
 hipError_t au_launch(const altgdmin_handle* h, int fmt, const AUArgs& a, hipStream_t st) {
-  if (h->au_depth > 0 && fmt == h->fmt) return launch_au_tuned(fmt, h->au_depth, a, st);
+  // the tuned depths are built for 4-wave workgroups
+  if (h->au_depth > 0 && fmt == h->fmt && a.waves != 8) return launch_au_tuned(fmt, h->au_depth, a, st);
   return launch_au(fmt, a, st, h->au_depth < 0 ? POL_CACHED : POL_STREAM);
 }
 
@@ -491,7 +498,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     if (ju == 8 && p.m > 512) ju = 4;   // JU = 8 is built for at most two row chunks
     // the unrolls are built for 4-wave workgroups; -1 (the cached default) for every width
     h->col_unroll = ju < 0 || h->col_waves == kWaves ? ju : 0;
-    h->au_depth = aud;
+    h->au_depth = aud < 0 || au_waves(h->col_waves, h->fmt) == kWaves ? aud : 0;
     return ALTGDMIN_OK;
   }
   const std::string arch = device_arch();
@@ -515,6 +522,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
   au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
   au.U = h->Utmp; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
+  au.waves = au_waves(h->col_waves, h->fmt);
   // the column kernel in its GDmin configuration (projection by the P_k, G_k^{-1}
   // the A_k U runs just wrote, tau IHT iterations, the LS / gradient tail), from
   // an empty support
@@ -548,7 +556,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   float best_au = 0.f, best_col = 0.f;
   hipError_t e = timed([&] { return launch_au(h->fmt, au, st, pol); }, &best_au);
   for (int aud : {1, 2, 3, 4, 8}) {
-    if (e != hipSuccess) break;
+    if (e != hipSuccess || au.waves != kWaves) break;   // the tuned depths are built for 4 waves
     float ms = 0.f;
     e = timed([&] { return launch_au_tuned(h->fmt, aud, au, st); }, &ms);
     if (e != hipSuccess) break;
@@ -650,6 +658,7 @@ int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
   au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
   au.gate = nullptr; au.gate_want = 0;
   au.seed = p.a_seed; au.table = p.normal_table;
+  au.waves = au_waves(h->col_waves, h->fmt);
   ColArgs ca = col_args(h);
   ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
   if (h->hi_phase) {
@@ -916,6 +925,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
     au.gate = nullptr; au.gate_want = 0;
     au.seed = p.a_seed; au.table = p.normal_table;
+    au.waves = au_waves(h->col_waves, h->fmt);
     ColArgs ca = col_args(h);
     ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
     hipError_t e = hipEventRecord(ev[0], st);
@@ -1238,6 +1248,7 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
     au.seed = p.a_seed; au.table = p.normal_table;
+    au.waves = au_waves(h->col_waves, h->fmt);
     // with tol_resid > 0 a problem whose residual reached it is frozen (every kernel skips it)
     const int* done = h->par.tol_resid > 0.0 ? &h->ctl->done : nullptr;
     au.gate = done; au.gate_want = 0;
@@ -1258,11 +1269,13 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     g.qr.push_back(qa);
     const int f = h->fmt, cf = h->colfmt, phx = f == FMT_PHILOX;
     const int nc = (p.m + 255) / 256, rr = (p.r + 1) / 2 * 2, cw = h->col_waves;
-    Bucket& ab = g.au_b[f * 64 + rr];
+    const int aw = au_waves(cw, f);
+    Bucket& ab = g.au_b[(f * 64 + rr) * 32 + aw];   // and with others of their A_k U width
     Bucket& cb = g.col_b[(cf * 64 + nc) * 32 + cw];   // problems batch with others of their column width
     ab.fmt = f;
     cb.fmt = cf;
     ab.inst = rr;
+    ab.waves = aw;
     cb.inst = nc;
     cb.waves = cw;
     for (int k = 0; k < p.q; ++k) {
@@ -1271,7 +1284,7 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     }
     for (int jb = 0; jb < (p.n + 63) / 64; ++jb)
       for (int ks = 0; ks < h->KS; ++ks) g.grad_map.push_back(make_int4(i, jb, ks, 0));
-    ab.lds = std::max(ab.lds, AULayout(p.m, p.r, phx).total);
+    ab.lds = std::max(ab.lds, AULayout(p.m, p.r, phx, aw).total);
     cb.lds = std::max(cb.lds, ColLayout(p.n, p.m, p.r, p.rho, 1, phx, cw).total);
   }
   size_t o = 0;
@@ -1373,7 +1386,7 @@ int altgdmin_step_many(altgdmin_handle* const* hs, int32_t count, int32_t iters,
   for (int it = 0; it < iters; ++it) {
     for (const auto& kv : g.au_b) {
       const Bucket& b = kv.second;
-      HIPCHK(launch_au_grp(b.fmt, b.inst, au_tab, reinterpret_cast<const int2*>(dev + b.off), (int)b.map.size(),
+      HIPCHK(launch_au_grp(b.fmt, b.inst, b.waves, au_tab, reinterpret_cast<const int2*>(dev + b.off), (int)b.map.size(),
                            b.lds, st, pol));
     }
     for (const auto& kv : g.col_b) {
@@ -1419,6 +1432,7 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
   au.U = U; au.P = P; au.Ginv = Lc; au.flags = flags;
   au.gate = nullptr; au.gate_want = 0;
   au.seed = prob->a_seed; au.table = prob->normal_table;
+  au.waves = au_waves(choose_col_waves(*prob), fmt_of(prob));   // the width the solver takes for this problem
   HIPCHK(launch_au(fmt_of(prob), au, static_cast<hipStream_t>(stream)));
   return ALTGDMIN_OK;
 }

@@ -82,6 +82,7 @@ struct AUArgs {
   int gate_want;
   unsigned long long seed;  // Philox form: key of A
   const float* table;       // Philox form: normal table (kNormalTable FP32)
+  int waves;                // waves per workgroup: 8 (plane formats, few columns) or 4 (0 reads as 4)
 };
 
 // ---------------------------------------------------------------- wave reductions
@@ -405,10 +406,10 @@ struct ColLayout {
 struct AULayout {
   size_t P, gpart, G, W, Gi, tab, total;
   int p_in_lds, mp;
-  __host__ __device__ AULayout(int m, int r, int philox = 0) {
+  __host__ __device__ AULayout(int m, int r, int philox = 0, int waves = kWaves) {
     mp = ((m + 3) / 4) * 4 + 4;                     // LDS row stride of the column-major P
     p_in_lds = 4 * (size_t)mp * r <= kPInLdsMax;
-    const size_t ust = 4 * (size_t)kWaves * 64 * ((((r + 1) / 2 * 2) + 3) / 4 * 4);   // staged rows of U
+    const size_t ust = 4 * (size_t)waves * 64 * ((((r + 1) / 2 * 2) + 3) / 4 * 4);   // staged rows of U
     const size_t pb = p_in_lds ? 4 * (size_t)mp * r : 0;
     size_t o = 0;
     P = o;     o = align16(o + (pb > ust ? pb : ust));

@@ -678,16 +678,21 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_
 
 // ---------------------------------------------------------------- k_au
 
-// One column k of A_k U.  Waves split the 256-row chunks of A_k first and the
-// columns j second: with nch = ceil(m / 256) chunks, wave w takes chunk w / js
-// and columns j = w % js, w % js + js, ... where js = 4 / nch (1 when nch > 2);
-// each lane holds 4 rows x R accumulators.  Partial P_k of the waves sharing a
-// chunk are added in a fixed order (in LDS when P_k fits, else in global memory).
-template <int FMT, int R, int AUD, int POL = POL_STREAM>
+// One column k of A_k U by a workgroup of W waves.  Waves split the 256-row
+// chunks of A_k first and the columns j second: with nch = ceil(m / 256) chunks,
+// wave w takes chunk w / js and columns j = w % js, w % js + js, ... where
+// js = max(1, W / nch); each lane holds 4 rows x R accumulators.  Partial P_k of
+// the waves sharing a chunk are added in a fixed order (in LDS when P_k fits,
+// else in global memory), so W sets the summation order: it is a property of the
+// problem (8 waves where the column kernel takes 8 or more, for the plane
+// formats), the same in a solo and a batched launch.  The Gram and the inverse
+// use the first 4 waves whatever W.
+template <int FMT, int R, int AUD, int POL = POL_STREAM, int W = kWaves>
 __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* smem) {
+  constexpr int kT = 64 * W;
   const int tid = threadIdx.x, lane = tid & 63, wave = wave_id();
   const int n = a.n, m = a.m, r = a.r;
-  const AULayout lay(m, r, FMT == FMT_PHILOX);
+  const AULayout lay(m, r, FMT == FMT_PHILOX, W);
   float* Pk = a.P + (long long)k * m * r;
   float* Pp = lay.p_in_lds ? reinterpret_cast<float*>(smem + lay.P) : Pk;
   double* gpart = reinterpret_cast<double*>(smem + lay.gpart);
@@ -697,12 +702,12 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   ALoader<FMT, POL> L(a, k);
   if constexpr (FMT == FMT_PHILOX) {
     float* tab = reinterpret_cast<float*>(smem + lay.tab);
-    for (int t = tid; t < kNormalTable; t += kThreads) tab[t] = a.table[t];
+    for (int t = tid; t < kNormalTable; t += kT) tab[t] = a.table[t];
     L.tab = tab;
     __syncthreads();
   }
   const int nch = (m + 255) >> 8;
-  const int js = nch == 1 ? 4 : (nch == 2 ? 2 : 1);
+  const int js = W / nch > 1 ? W / nch : 1;
   const int cs = wave / js, jw = wave % js;
   const bool active = cs < nch;
   const int ch = lane + 64 * cs;
@@ -830,7 +835,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
     __syncthreads();
   }
   if (lay.p_in_lds)
-    for (int t = tid; t < m * r; t += kThreads) {
+    for (int t = tid; t < m * r; t += kT) {
       const int i = t / r, rr = t - i * r;
       Pk[t] = Pp[rr * mp + i];
     }
@@ -844,7 +849,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   const int RB = (r + 1) >> 1;
   const int nb = RB * (RB + 1) / 2;
   const int parts = kThreads / nb;
-  {
+  if (tid < kThreads) {
     const int blk = tid % nb, part = tid / nb;
     int ba = 0, base = 0;
     while (blk >= base + (RB - ba)) { base += RB - ba; ++ba; }
@@ -882,7 +887,7 @@ __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* s
   }
   __syncthreads();
   double* Gk = a.Ginv + (long long)k * r * r;
-  for (int t = tid; t < r * r; t += kThreads) Gk[t] = Gil[t];
+  for (int t = tid; t < r * r; t += kT) Gk[t] = Gil[t];
 }
 
 // A_k loads of the next AUD columns in flight per wave (autotuned variants differ).
@@ -908,21 +913,21 @@ constexpr int default_aud(int R, int FMT = FMT_F32) {
 constexpr int deep_aud(int R, int = FMT_F32) { return R <= 4 ? 4 : 3; }
 constexpr int kDeepAuColumns = 256;
 
-template <int FMT, int R, int AUD = default_aud(R, FMT), int POL = POL_STREAM>
-__global__ __launch_bounds__(kThreads) void k_au(AUArgs a) {
+template <int FMT, int R, int AUD = default_aud(R, FMT), int POL = POL_STREAM, int W = kWaves>
+__global__ __launch_bounds__(64 * W) void k_au(AUArgs a) {
   if (a.gate && *a.gate != a.gate_want) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  au_body<FMT, R, AUD, POL>(a, blockIdx.x, smem);
+  au_body<FMT, R, AUD, POL, W>(a, blockIdx.x, smem);
 }
 
 // Several problems in one launch: block b works on column map[b].y of problem map[b].x.
-template <int FMT, int R, int POL = POL_STREAM, int AUD = default_aud(R, FMT)>
-__global__ __launch_bounds__(kThreads) void k_au_grp(const AUArgs* tab, const int2* map) {
+template <int FMT, int R, int POL = POL_STREAM, int AUD = default_aud(R, FMT), int W = kWaves>
+__global__ __launch_bounds__(64 * W) void k_au_grp(const AUArgs* tab, const int2* map) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const int2 mp = map[blockIdx.x];
   const AUArgs a = tab[mp.x];
   if (a.gate && *a.gate != a.gate_want) return;
-  au_body<FMT, R, AUD, POL>(a, mp.y, smem);
+  au_body<FMT, R, AUD, POL, W>(a, mp.y, smem);
 }
 
 #if !defined(ALTG_PART) || ALTG_PART == 1
@@ -985,6 +990,23 @@ static const au_fn kAUDeep[3][kRMax / 2] = {AUD_ROW(FMT_F32), AUD_ROW(FMT_BF16X2
                      k_au_grp<F, 10, POL_STREAM, deep_aud(10)>, k_au_grp<F, 12, POL_STREAM, deep_aud(12)>, \
                      k_au_grp<F, 14, POL_STREAM, deep_aud(14)>, k_au_grp<F, 16, POL_STREAM, deep_aud(16)>}
 static const aug_fn kAUGrpDeep[3][kRMax / 2] = {AUGD_ROW(FMT_F32), AUGD_ROW(FMT_BF16X2), AUGD_ROW(FMT_BF16HI)};
+// 8-wave workgroups (problems whose column kernel takes 8 or more waves: few
+// columns, so the deep depths; every format, so that the width, and with it the
+// bits, do not depend on how A is held)
+#define AU8_ROW(F) {k_au<F, 2, deep_aud(2), POL_STREAM, 8>, k_au<F, 4, deep_aud(4), POL_STREAM, 8>,     \
+                    k_au<F, 6, deep_aud(6), POL_STREAM, 8>, k_au<F, 8, deep_aud(8), POL_STREAM, 8>,     \
+                    k_au<F, 10, deep_aud(10), POL_STREAM, 8>, k_au<F, 12, deep_aud(12), POL_STREAM, 8>, \
+                    k_au<F, 14, deep_aud(14), POL_STREAM, 8>, k_au<F, 16, deep_aud(16), POL_STREAM, 8>}
+static const au_fn kAU8[4][kRMax / 2] = {AU8_ROW(FMT_F32), AU8_ROW(FMT_BF16X2), AU8_ROW(FMT_BF16HI), AU8_ROW(FMT_PHILOX)};
+#define AUG8_ROW(F) {k_au_grp<F, 2, POL_STREAM, deep_aud(2), 8>, k_au_grp<F, 4, POL_STREAM, deep_aud(4), 8>,     \
+                     k_au_grp<F, 6, POL_STREAM, deep_aud(6), 8>, k_au_grp<F, 8, POL_STREAM, deep_aud(8), 8>,     \
+                     k_au_grp<F, 10, POL_STREAM, deep_aud(10), 8>, k_au_grp<F, 12, POL_STREAM, deep_aud(12), 8>, \
+                     k_au_grp<F, 14, POL_STREAM, deep_aud(14), 8>, k_au_grp<F, 16, POL_STREAM, deep_aud(16), 8>}
+static const aug_fn kAUGrp8[4][kRMax / 2] = {AUG8_ROW(FMT_F32), AUG8_ROW(FMT_BF16X2), AUG8_ROW(FMT_BF16HI),
+                                             AUG8_ROW(FMT_PHILOX)};
+
+// the workgroup width of the A_k U kernels for a launch: 8 waves when asked for, else 4
+static inline int au_width(int waves) { return waves == 8 ? 8 : kWaves; }
 
 bool au_supported(int m, int r) { return m >= 1 && m <= 256 * kNCMax && r >= 1 && r <= kRMax; }
 
@@ -1013,11 +1035,12 @@ hipError_t launch_au(int fmt, const AUArgs& a, hipStream_t st, int pol) {
     const hipError_t e = launch_au_cached(fmt, a, st);
     if (e != hipErrorNotSupported) return e;
   }
-  const int ri = (a.r + 1) / 2 - 1;
-  const AULayout lay(a.m, a.r, fmt == FMT_PHILOX);
+  const int ri = (a.r + 1) / 2 - 1, w = au_width(a.waves);
+  const AULayout lay(a.m, a.r, fmt == FMT_PHILOX, w);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  const au_fn f = (fmt != FMT_PHILOX && a.q <= kDeepAuColumns) ? kAUDeep[fmt][ri] : kAUTable[fmt][ri];
-  hipLaunchKernelGGL(f, dim3(a.q), dim3(kThreads), lay.total, st, a);
+  const au_fn f = w == 8 ? kAU8[fmt][ri]
+                         : ((fmt != FMT_PHILOX && a.q <= kDeepAuColumns) ? kAUDeep[fmt][ri] : kAUTable[fmt][ri]);
+  hipLaunchKernelGGL(f, dim3(a.q), dim3(64 * w), lay.total, st, a);
   return hipGetLastError();
 }
 
@@ -1039,17 +1062,19 @@ hipError_t launch_col_grp(int fmt, int nc, int waves, const ColArgs* tab, const 
   return hipGetLastError();
 }
 
-hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st,
-                         int pol) {
+hipError_t launch_au_grp(int fmt, int rmax, int waves, const AUArgs* tab, const int2* map, int blocks, size_t lds,
+                         hipStream_t st, int pol) {
   if (fmt < FMT_F32 || fmt > FMT_PHILOX) return hipErrorInvalidValue;
   if (pol == POL_CACHED) {
-    const hipError_t e = launch_au_grp_cached(fmt, rmax, tab, map, blocks, lds, st);
+    const hipError_t e = launch_au_grp_cached(fmt, rmax, waves, tab, map, blocks, lds, st);
     if (e != hipErrorNotSupported) return e;
   }
-  const int ri = (rmax + 1) / 2 - 1;
+  const int ri = (rmax + 1) / 2 - 1, w = au_width(waves);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  const aug_fn f = (fmt != FMT_PHILOX && blocks <= kDeepAuColumns) ? kAUGrpDeep[fmt][ri] : kAUGrpTable[fmt][ri];
-  hipLaunchKernelGGL(f, dim3(blocks), dim3(kThreads), lds, st, tab, map);
+  const aug_fn f = w == 8 ? kAUGrp8[fmt][ri]
+                          : ((fmt != FMT_PHILOX && blocks <= kDeepAuColumns) ? kAUGrpDeep[fmt][ri]
+                                                                              : kAUGrpTable[fmt][ri]);
+  hipLaunchKernelGGL(f, dim3(blocks), dim3(64 * w), lds, st, tab, map);
   return hipGetLastError();
 }
 
@@ -1081,7 +1106,7 @@ hipError_t col_allow_big_lds() {
   if (e == hipSuccess) done = true;
   return e;
 }
-size_t au_lds_bytes(int m, int r, int philox) { return AULayout(m, r, philox).total; }
+size_t au_lds_bytes(int m, int r, int philox, int waves) { return AULayout(m, r, philox, waves).total; }
 
 // Materialises the Philox form of A into the FP32 layout (one thread per 4-row chunk).
 __global__ __launch_bounds__(256) void k_philox_fill(unsigned long long seed, const float* table, int q, int n, int m,
@@ -1268,6 +1293,17 @@ static const au_fn3 kAUCached[2][3][kRMax / 2] = {
 static const aug_fn3 kAUGrpCached[2][3][kRMax / 2] = {
     {AUGC_F(FMT_F32, default_aud), AUGC_F(FMT_BF16X2, default_aud), AUGC_F(FMT_BF16HI, default_aud)},
     {AUGC_F(FMT_F32, deep_aud), AUGC_F(FMT_BF16X2, deep_aud), AUGC_F(FMT_BF16HI, deep_aud)}};
+// 8-wave workgroups (deep depths), as in the streaming tables
+#define AUC8_F(F) {k_au<F, 2, deep_aud(2), POL_CACHED, 8>, k_au<F, 4, deep_aud(4), POL_CACHED, 8>,     \
+                   k_au<F, 6, deep_aud(6), POL_CACHED, 8>, k_au<F, 8, deep_aud(8), POL_CACHED, 8>,     \
+                   k_au<F, 10, deep_aud(10), POL_CACHED, 8>, k_au<F, 12, deep_aud(12), POL_CACHED, 8>, \
+                   k_au<F, 14, deep_aud(14), POL_CACHED, 8>, k_au<F, 16, deep_aud(16), POL_CACHED, 8>}
+static const au_fn3 kAUCached8[3][kRMax / 2] = {AUC8_F(FMT_F32), AUC8_F(FMT_BF16X2), AUC8_F(FMT_BF16HI)};
+#define AUGC8_F(F) {k_au_grp<F, 2, POL_CACHED, deep_aud(2), 8>, k_au_grp<F, 4, POL_CACHED, deep_aud(4), 8>,     \
+                    k_au_grp<F, 6, POL_CACHED, deep_aud(6), 8>, k_au_grp<F, 8, POL_CACHED, deep_aud(8), 8>,     \
+                    k_au_grp<F, 10, POL_CACHED, deep_aud(10), 8>, k_au_grp<F, 12, POL_CACHED, deep_aud(12), 8>, \
+                    k_au_grp<F, 14, POL_CACHED, deep_aud(14), 8>, k_au_grp<F, 16, POL_CACHED, deep_aud(16), 8>}
+static const aug_fn3 kAUGrpCached8[3][kRMax / 2] = {AUGC8_F(FMT_F32), AUGC8_F(FMT_BF16X2), AUGC8_F(FMT_BF16HI)};
 
 static int cached_width_row(int waves) { return waves == 8 ? 1 : (waves == 0 || waves == kWaves ? 0 : -1); }
 
@@ -1320,20 +1356,21 @@ hipError_t launch_col_grp_cached(int fmt, int nc, int waves, const ColArgs* tab,
 
 hipError_t launch_au_cached(int fmt, const AUArgs& a, hipStream_t st) {
   if (fmt < FMT_F32 || fmt > FMT_BF16HI) return hipErrorNotSupported;
-  const int ri = (a.r + 1) / 2 - 1;
-  const AULayout lay(a.m, a.r, 0);
+  const int ri = (a.r + 1) / 2 - 1, w = a.waves == 8 ? 8 : kWaves;
+  const AULayout lay(a.m, a.r, 0, w);
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUCached[a.q <= kDeepAuColumns][fmt][ri], dim3(a.q), dim3(kThreads), lay.total, st, a);
+  const au_fn3 f = w == 8 ? kAUCached8[fmt][ri] : kAUCached[a.q <= kDeepAuColumns][fmt][ri];
+  hipLaunchKernelGGL(f, dim3(a.q), dim3(64 * w), lay.total, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_au_grp_cached(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds,
-                                hipStream_t st) {
+hipError_t launch_au_grp_cached(int fmt, int rmax, int waves, const AUArgs* tab, const int2* map, int blocks,
+                                size_t lds, hipStream_t st) {
   if (fmt < FMT_F32 || fmt > FMT_BF16HI) return hipErrorNotSupported;
-  const int ri = (rmax + 1) / 2 - 1;
+  const int ri = (rmax + 1) / 2 - 1, w = waves == 8 ? 8 : kWaves;
   (void)hipGetLastError();   // clear a stale error of an earlier, unrelated call
-  hipLaunchKernelGGL(kAUGrpCached[blocks <= kDeepAuColumns][fmt][ri], dim3(blocks), dim3(kThreads), lds, st, tab,
-                     map);
+  const aug_fn3 f = w == 8 ? kAUGrpCached8[fmt][ri] : kAUGrpCached[blocks <= kDeepAuColumns][fmt][ri];
+  hipLaunchKernelGGL(f, dim3(blocks), dim3(64 * w), lds, st, tab, map);
   return hipGetLastError();
 }
 #endif  // ALTG_PART == 3

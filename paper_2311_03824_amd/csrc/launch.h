@@ -58,15 +58,16 @@ hipError_t launch_col_cached(int fmt, const ColArgs& a, hipStream_t st);
 hipError_t launch_col_grp_cached(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
                                  size_t lds, hipStream_t st);
 hipError_t launch_au_cached(int fmt, const AUArgs& a, hipStream_t st);
-hipError_t launch_au_grp_cached(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds,
-                                hipStream_t st);
+hipError_t launch_au_grp_cached(int fmt, int rmax, int waves, const AUArgs* tab, const int2* map, int blocks,
+                                size_t lds, hipStream_t st);
 // column workgroups of 8 or 16 waves (a.waves); built for 8 waves, and 16 waves at m <= 512
 bool col_wide_built(int waves, int nc);
 hipError_t launch_col_wide(int fmt, const ColArgs& a, hipStream_t st);
 hipError_t launch_col_grp_wide(int fmt, int nc, int waves, const ColArgs* tab, const int2* map, int blocks,
                                size_t lds, hipStream_t st);
-hipError_t launch_au_grp(int fmt, int rmax, const AUArgs* tab, const int2* map, int blocks, size_t lds, hipStream_t st,
-                         int pol = 0);
+// A_k U over several problems; waves: the problems' A_k U width (8 or 4, see AUArgs::waves)
+hipError_t launch_au_grp(int fmt, int rmax, int waves, const AUArgs* tab, const int2* map, int blocks, size_t lds,
+                         hipStream_t st, int pol = 0);
 size_t col_lds_bytes(int n, int m, int r, int rho, int project, int philox, int waves = kWaves);
 // A column workgroup takes at most 64 KiB of LDS by default and up to the CU's
 // 160 KiB for large n (g, the step and the support bitmap are n-long LDS arrays;
@@ -78,7 +79,7 @@ constexpr size_t kColLdsMax = 160 * 1024;
 hipError_t col_allow_big_lds();
 hipError_t col_allow_big_lds_tuned();    // the autotuned and wide variants
 hipError_t col_allow_big_lds_cached();   // the cached-load variants
-size_t au_lds_bytes(int m, int r, int philox);
+size_t au_lds_bytes(int m, int r, int philox, int waves = kWaves);
 hipError_t launch_philox_fill(unsigned long long seed, const float* table, int q, int n, int m, long long lda, float* A,
                               hipStream_t st);
 size_t select_lds_bytes(int n, int rho);
