@@ -330,9 +330,10 @@ int altgdmin_op_make_a(uint64_t seed, const float* normal_table, int32_t q, int3
  * in FP64 over j = 0..n-1 in order and rounded once.  Asynchronous. */
 int altgdmin_op_measure(const altgdmin_problem* prob, const double* Xt, float* Y, void* stream);
 
-/* P_k = A_k U (m x r, row-major per k at P[k*m*r]) and the Cholesky factor
- * L_k (lower, r x r row-major FP64 at Lc[k*r*r]) of G_k = P_k^T P_k, the pieces
- * of (A_k U)^dagger in eq. (bk_LS).  flags[k] gets bit 1 if G_k is not positive definite. */
+/* P_k = A_k U (m x r, row-major per k at P[k*m*r]) and the inverse Gram
+ * G_k^{-1} = (P_k^T P_k)^{-1} (r x r row-major FP64 at Lc[k*r*r]), the pieces of
+ * (A_k U)^dagger in eq. (bk_LS).  flags[k] gets bit 1 (value 2) if G_k is not
+ * positive definite; Lc then holds the identity for that k.  Asynchronous. */
 int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, double* Lc,
                    int32_t* flags, void* stream);
 
