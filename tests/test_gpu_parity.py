@@ -115,11 +115,12 @@ AU_SHAPES = SHAPES + [
     dict(n=1000, q=8, m=400, r=10, rho=50),     # the benchmark's n, m, r (two row chunks)
     dict(n=700, q=6, m=300, r=11, rho=20),      # r rounded up to the R = 12 instantiation
     dict(n=500, q=6, m=520, r=14, rho=9),       # three chunks, P_k in global memory
-    # more than 256 columns: the default pipeline depths of each format (fewer
-    # columns take the deep ones)
-    dict(n=300, q=300, m=120, r=10, rho=6),
-    dict(n=200, q=280, m=90, r=14, rho=4),
-    dict(n=200, q=270, m=90, r=16, rho=4),
+    # more than 320 columns: 4-wave workgroups with the default pipeline depths
+    # of each format (fewer columns take 8 waves and the deep depths)
+    dict(n=300, q=330, m=120, r=10, rho=6),
+    dict(n=200, q=340, m=90, r=14, rho=4),
+    dict(n=200, q=350, m=90, r=16, rho=4),
+    dict(n=200, q=300, m=90, r=10, rho=4),      # 8 waves above 256 columns
 ]
 
 
