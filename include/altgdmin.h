@@ -224,7 +224,10 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
  * it between passes; otherwise A is read with non-temporal loads.  With the
  * autotuner that default (0 or -1) is the baseline the variants are timed
  * against.  The default A_k U kernels keep deeper load pipelines for launches of
- * at most 256 columns (one workgroup per CU).  The environment
+ * at most 256 columns (one workgroup per CU), and problems of at most 512 columns
+ * run A_k U in 8-wave workgroups, whose partial sums, and so bits, differ from
+ * the 4-wave ones (ALTGDMIN_AU_WAVES=4|8 forces the width; the depth variants are
+ * built for 4 waves).  The environment
  * variable ALTGDMIN_LOAD_POLICY=stream|cached forces the load policy of the
  * default instantiations (for tests; the batched altgdmin_step_many applies the
  * same 200 MiB rule to all its problems together).  The choice is made once per

@@ -340,19 +340,23 @@ int validate(const altgdmin_problem* p, const altgdmin_params* par) {
 
 // Waves of the column workgroup of a problem.  One workgroup per column cannot
 // fill the 256 CUs when q is small, and a CU then streams faster with more
-// waves in flight: 8 waves up to 320 columns, 4 above (at n = 1000, m = 400,
-// r = 10: k_col 31 % faster at q = 125 and 9 % at q = 250 in FP32, 45 % and 42 %
-// in the mixed BF16 form; equal at q = 500; 16 waves measured slower than 8 at
-// every q).  The width sets the order of the cross-wave sums, so it is fixed by
-// the problem, never by timing.  A width not built for m, or whose LDS does not
-// fit, falls back to the next narrower.  ALTGDMIN_COL_WAVES=4|8|16 forces a
-// width (measurements, tests).
-int choose_col_waves(const altgdmin_problem& p) {
+// waves in flight: 8 waves up to 512 columns, 4 above; the mixed BF16 form
+// (mixed) takes 8 only up to 320.  At n = 1000, m = 400, r = 10: k_col 31 %
+// faster at q = 125 and 9 % at q = 250 in FP32, 45 % and 42 % in the mixed form;
+// at q = 330 / 400 / 500 FP32 0.420 / 0.446 / 0.521 ms against 0.474 / 0.494 /
+// 0.534 with 4, the mixed form 0.367 / 0.376 / 0.395 against 0.321 / 0.328 /
+// 0.340; at q = 700 4 waves win (0.696 against 0.748); 16 waves measured slower
+// than 8 at every q.  The width sets the order of the cross-wave sums, so it is
+// fixed by the problem, never by timing (the FP32 plane, the exact BF16 split and
+// the Philox form share it and so their bits).  A width not built for m, or
+// whose LDS does not fit, falls back to the next narrower.
+// ALTGDMIN_COL_WAVES=4|8|16 forces a width (measurements, tests).
+int choose_col_waves(const altgdmin_problem& p, bool mixed) {
   const int phx = p.a_format == ALTGDMIN_A_PHILOX;
   // above 64 KiB of LDS (large n) a CU holds one column workgroup: 8 waves keep
   // more loads in flight whatever q
   const bool big = col_lds_bytes(p.n, p.m, r_eff(p), p.rho, 1, phx) > kColLdsDefault;
-  int w = p.q <= 320 || big ? 8 : kWaves;
+  int w = p.q <= 320 || big || (!mixed && p.q <= 512) ? 8 : kWaves;
   if (const char* f = std::getenv("ALTGDMIN_COL_WAVES")) {
     const int v = std::atoi(f);
     if (v == 4 || v == 8 || v == 16) w = v;
@@ -365,11 +369,21 @@ int choose_col_waves(const altgdmin_problem& p) {
   return w;
 }
 
-// Waves of the A_k U workgroup: 8 for problems whose column kernel takes 8 or
-// more (few columns: more loads in flight per CU), else 4.  It sets the order of
-// the cross-wave sums of P_k, so, like the column width, it is a property of the
-// problem (not of its A format), the same in solo and batched launches.
-int au_waves(int col_waves, int /*fmt*/) { return col_waves >= 8 ? 8 : kWaves; }
+// Waves of the A_k U workgroup: 8 up to 512 columns, 4 above (n = 1000, m = 400,
+// r = 10: 0.065 against 0.094 ms at q = 125, 0.134 against 0.147 at q = 330 in
+// FP32 and 0.159 against 0.204 with BF16 hi + lo planes, 0.157 against 0.161 at
+// q = 500; 0.223 against 0.192 at q = 700).  It sets the order of the cross-wave
+// sums of P_k, so, like the column width, it is a property of the problem (of q,
+// not of the A format), the same in solo and batched launches.
+// ALTGDMIN_AU_WAVES=4|8 forces a width (tests of the 4-wave tuned depths).
+int au_waves(const altgdmin_problem& p) {
+  int w = p.q <= 512 ? 8 : kWaves;
+  if (const char* f = std::getenv("ALTGDMIN_AU_WAVES")) {
+    const int v = std::atoi(f);
+    if (v == 4 || v == 8) w = v;
+  }
+  return w;
+}
 
 ColArgs col_args(const altgdmin_handle* h) {
   const altgdmin_problem& p = h->prob;
@@ -498,7 +512,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
     if (ju == 8 && p.m > 512) ju = 4;   // JU = 8 is built for at most two row chunks
     // the unrolls are built for 4-wave workgroups; -1 (the cached default) for every width
     h->col_unroll = ju < 0 || h->col_waves == kWaves ? ju : 0;
-    h->au_depth = aud < 0 || au_waves(h->col_waves, h->fmt) == kWaves ? aud : 0;
+    h->au_depth = aud < 0 || au_waves(h->prob) == kWaves ? aud : 0;
     return ALTGDMIN_OK;
   }
   const std::string arch = device_arch();
@@ -522,7 +536,7 @@ int autotune(altgdmin_handle* h, hipStream_t st) {
   au.n = p.n; au.q = p.q; au.m = p.m; au.r = p.r;
   au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
   au.U = h->Utmp; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
-  au.waves = au_waves(h->col_waves, h->fmt);
+  au.waves = au_waves(h->prob);
   // the column kernel in its GDmin configuration (projection by the P_k, G_k^{-1}
   // the A_k U runs just wrote, tau IHT iterations, the LS / gradient tail), from
   // an empty support
@@ -658,7 +672,7 @@ int enqueue_iteration(altgdmin_handle* h, hipStream_t st) {
   au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
   au.gate = nullptr; au.gate_want = 0;
   au.seed = p.a_seed; au.table = p.normal_table;
-  au.waves = au_waves(h->col_waves, h->fmt);
+  au.waves = au_waves(h->prob);
   ColArgs ca = col_args(h);
   ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
   if (h->hi_phase) {
@@ -723,7 +737,7 @@ int altgdmin_init(const altgdmin_problem* prob, const altgdmin_params* par, void
   h->colfmt = (par->flags & ALTGDMIN_FLAG_BF16_MIXED) ? FMT_BF16MIX : h->fmt;
   h->auto_rank = prob->r == 0;
   if (h->fmt != FMT_PFOURIER) {
-    h->col_waves = choose_col_waves(h->prob);
+    h->col_waves = choose_col_waves(h->prob, h->colfmt == FMT_BF16MIX);
     // a GDmin iteration's column workgroup (with P_k) may need more LDS than the
     // initialisation's: raise the kernels' limit now, before any graph capture
     if (col_lds_bytes(prob->n, prob->m, r_eff(*prob), prob->rho, 1, prob->a_format == ALTGDMIN_A_PHILOX,
@@ -925,7 +939,7 @@ int altgdmin_profile_iteration(altgdmin_handle* h, int32_t iters, void* stream, 
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
     au.gate = nullptr; au.gate_want = 0;
     au.seed = p.a_seed; au.table = p.normal_table;
-    au.waves = au_waves(h->col_waves, h->fmt);
+    au.waves = au_waves(h->prob);
     ColArgs ca = col_args(h);
     ca.tau = h->par.tau; ca.project = 1; ca.has_support = 1; ca.tail = TAIL_LSGRAD;
     hipError_t e = hipEventRecord(ev[0], st);
@@ -1248,7 +1262,7 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     au.A = p.A; au.Alo = p.A_lo; au.lda = p.lda; au.sA = p.a_stride_k;
     au.U = h->U; au.P = h->P; au.Ginv = h->Ginv; au.flags = h->colflags;
     au.seed = p.a_seed; au.table = p.normal_table;
-    au.waves = au_waves(h->col_waves, h->fmt);
+    au.waves = au_waves(h->prob);
     // with tol_resid > 0 a problem whose residual reached it is frozen (every kernel skips it)
     const int* done = h->par.tol_resid > 0.0 ? &h->ctl->done : nullptr;
     au.gate = done; au.gate_want = 0;
@@ -1269,7 +1283,7 @@ int plan_group(altgdmin_handle* const* hs, int count, GroupPlan& g) {
     g.qr.push_back(qa);
     const int f = h->fmt, cf = h->colfmt, phx = f == FMT_PHILOX;
     const int nc = (p.m + 255) / 256, rr = (p.r + 1) / 2 * 2, cw = h->col_waves;
-    const int aw = au_waves(cw, f);
+    const int aw = au_waves(p);
     Bucket& ab = g.au_b[(f * 64 + rr) * 32 + aw];   // and with others of their A_k U width
     Bucket& cb = g.col_b[(cf * 64 + nc) * 32 + cw];   // problems batch with others of their column width
     ab.fmt = f;
@@ -1432,14 +1446,14 @@ int altgdmin_op_au(const altgdmin_problem* prob, const float* U, float* P, doubl
   au.U = U; au.P = P; au.Ginv = Lc; au.flags = flags;
   au.gate = nullptr; au.gate_want = 0;
   au.seed = prob->a_seed; au.table = prob->normal_table;
-  au.waves = au_waves(choose_col_waves(*prob), fmt_of(prob));   // the width the solver takes for this problem
+  au.waves = au_waves(*prob);   // the width the solver takes for this problem
   HIPCHK(launch_au(fmt_of(prob), au, static_cast<hipStream_t>(stream)));
   return ALTGDMIN_OK;
 }
 
 static int op_col(const altgdmin_problem* prob, ColArgs& a, void* stream) {
   NEED_STREAM(stream);
-  a.waves = choose_col_waves(*prob);   // the width the solver takes for this problem
+  a.waves = choose_col_waves(*prob, false);   // the width the solver takes for this problem
   a.n = prob->n; a.q = prob->q; a.m = prob->m; a.r = prob->r; a.rho = prob->rho;
   a.seed = prob->a_seed; a.table = prob->normal_table;
   a.A = prob->A; a.Alo = prob->A_lo; a.lda = prob->lda; a.sA = prob->a_stride_k;

@@ -82,7 +82,7 @@ struct AUArgs {
   int gate_want;
   unsigned long long seed;  // Philox form: key of A
   const float* table;       // Philox form: normal table (kNormalTable FP32)
-  int waves;                // waves per workgroup: 8 (plane formats, few columns) or 4 (0 reads as 4)
+  int waves;                // waves per workgroup: 8 (at most 512 columns) or 4 (0 reads as 4)
 };
 
 // ---------------------------------------------------------------- wave reductions

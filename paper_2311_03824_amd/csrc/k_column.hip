@@ -684,9 +684,8 @@ __global__ __launch_bounds__(64 * W) __attribute__((amdgpu_waves_per_eu(col_min_
 // js = max(1, W / nch); each lane holds 4 rows x R accumulators.  Partial P_k of
 // the waves sharing a chunk are added in a fixed order (in LDS when P_k fits,
 // else in global memory), so W sets the summation order: it is a property of the
-// problem (8 waves where the column kernel takes 8 or more, for the plane
-// formats), the same in a solo and a batched launch.  The Gram and the inverse
-// use the first 4 waves whatever W.
+// problem (8 waves up to 512 columns), the same in a solo and a batched launch.
+// The Gram and the inverse use the first 4 waves whatever W.
 template <int FMT, int R, int AUD, int POL = POL_STREAM, int W = kWaves>
 __device__ __forceinline__ void au_body(const AUArgs& a, int k, unsigned char* smem) {
   constexpr int kT = 64 * W;
@@ -990,9 +989,8 @@ static const au_fn kAUDeep[3][kRMax / 2] = {AUD_ROW(FMT_F32), AUD_ROW(FMT_BF16X2
                      k_au_grp<F, 10, POL_STREAM, deep_aud(10)>, k_au_grp<F, 12, POL_STREAM, deep_aud(12)>, \
                      k_au_grp<F, 14, POL_STREAM, deep_aud(14)>, k_au_grp<F, 16, POL_STREAM, deep_aud(16)>}
 static const aug_fn kAUGrpDeep[3][kRMax / 2] = {AUGD_ROW(FMT_F32), AUGD_ROW(FMT_BF16X2), AUGD_ROW(FMT_BF16HI)};
-// 8-wave workgroups (problems whose column kernel takes 8 or more waves: few
-// columns, so the deep depths; every format, so that the width, and with it the
-// bits, do not depend on how A is held)
+// 8-wave workgroups (problems of at most 512 columns, with the deep depths; every
+// format, so that the width, and with it the bits, do not depend on how A is held)
 #define AU8_ROW(F) {k_au<F, 2, deep_aud(2), POL_STREAM, 8>, k_au<F, 4, deep_aud(4), POL_STREAM, 8>,     \
                     k_au<F, 6, deep_aud(6), POL_STREAM, 8>, k_au<F, 8, deep_aud(8), POL_STREAM, 8>,     \
                     k_au<F, 10, deep_aud(10), POL_STREAM, 8>, k_au<F, 12, deep_aud(12), POL_STREAM, 8>, \

@@ -115,11 +115,11 @@ AU_SHAPES = SHAPES + [
     dict(n=1000, q=8, m=400, r=10, rho=50),     # the benchmark's n, m, r (two row chunks)
     dict(n=700, q=6, m=300, r=11, rho=20),      # r rounded up to the R = 12 instantiation
     dict(n=500, q=6, m=520, r=14, rho=9),       # three chunks, P_k in global memory
-    # more than 320 columns: 4-wave workgroups with the default pipeline depths
+    # more than 512 columns: 4-wave workgroups with the default pipeline depths
     # of each format (fewer columns take 8 waves and the deep depths)
-    dict(n=300, q=330, m=120, r=10, rho=6),
-    dict(n=200, q=340, m=90, r=14, rho=4),
-    dict(n=200, q=350, m=90, r=16, rho=4),
+    dict(n=150, q=600, m=70, r=10, rho=3),
+    dict(n=120, q=560, m=60, r=14, rho=3),
+    dict(n=120, q=530, m=60, r=16, rho=3),
     dict(n=200, q=300, m=90, r=10, rho=4),      # 8 waves above 256 columns
 ]
 
@@ -520,6 +520,7 @@ def test_autotuned_solve_is_bitwise_the_default(lib, torch, tmp_path, monkeypatc
     cache = tmp_path / "tune.jsonl"
     monkeypatch.setenv("ALTGDMIN_TUNE_CACHE", str(cache))
     monkeypatch.setenv("ALTGDMIN_COL_WAVES", "4")
+    monkeypatch.setenv("ALTGDMIN_AU_WAVES", "4")   # the tuned A_k U depths are built for 4 waves
     inst = I.make_instance(n=517, q=40, m=333 + 4 * bf16, r=5, rho=11, seed=12, bf16_planes=bf16)
     a = _solve(lib, torch, inst, 12, bf16=bf16)
     b = _solve(lib, torch, inst, 12, bf16=bf16, flags=lib.FLAG_AUTOTUNE)
@@ -546,6 +547,7 @@ def test_every_tuned_variant_is_bitwise_the_default(lib, torch, monkeypatch, sha
     the default instantiation (FP32 plane and the mixed BF16 form; 4-wave column
     workgroups, for which the unrolls are built)."""
     monkeypatch.setenv("ALTGDMIN_COL_WAVES", "4")
+    monkeypatch.setenv("ALTGDMIN_AU_WAVES", "4")
     inst = I.make_instance(**shape, seed=21, bf16_planes=True)
     for bf16, extra in ((False, 0), (True, lib.FLAG_BF16_MIXED)):
         monkeypatch.delenv("ALTGDMIN_TUNE_FORCE", raising=False)
