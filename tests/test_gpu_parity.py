@@ -446,13 +446,16 @@ def test_solve_matches_oracle(lib, torch, shape, iters):
     assert abs(out["status"]["eta"] - st.eta) <= 1e-3 * st.eta
 
 
+@pytest.mark.parametrize("au_waves", ["4", "8"])
 @pytest.mark.parametrize("waves", ["4", "8", "16"])
 @pytest.mark.parametrize("shape,iters", [(dict(n=301, q=64, m=150, r=3, rho=7), 60),
                                          (dict(n=400, q=40, m=300, r=3, rho=8), 40)])   # two row chunks
-def test_every_column_width_matches_oracle(lib, torch, monkeypatch, waves, shape, iters):
-    """Column workgroups of 4, 8 and 16 waves (the width a problem takes is set by
-    its q; forced here): each solve matches the oracle, FP32 and mixed BF16."""
+def test_every_column_width_matches_oracle(lib, torch, monkeypatch, waves, au_waves, shape, iters):
+    """Column workgroups of 4, 8 and 16 waves and A_k U workgroups of 4 and 8 (the
+    widths a problem takes are set by its q; forced here): each solve matches the
+    oracle, FP32 and mixed BF16."""
     monkeypatch.setenv("ALTGDMIN_COL_WAVES", waves)
+    monkeypatch.setenv("ALTGDMIN_AU_WAVES", au_waves)
     inst = I.make_instance(**shape, seed=231103824, bf16_planes=True)
     for bf16, flags, A_t in ((False, 0, None), (True, lib.FLAG_BF16_MIXED, inst.A64_hi())):
         out = _solve(lib, torch, inst, iters, bf16=bf16, flags=flags)
