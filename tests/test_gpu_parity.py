@@ -741,9 +741,10 @@ def test_batched_cached_equals_solo_streamed(lib, torch, monkeypatch):
     [dict(n=600, q=30, m=250, r=10, rho=12, seed=5, bf16=False),   # the A_k U buckets R = 10, 12, 14
      dict(n=500, q=24, m=300, r=11, rho=10, seed=6, bf16=True, mixed=True),
      dict(n=400, q=20, m=520, r=13, rho=8, seed=7, bf16=False)],
-    [dict(n=300, q=100, m=120, r=2, rho=5, seed=8, bf16=False),    # 8-wave column workgroups
-     dict(n=260, q=400, m=150, r=3, rho=4, seed=9, bf16=True, mixed=True),   # 4-wave
-     dict(n=200, q=330, m=300, r=2, rho=3, seed=10, bf16=False)],  # 4-wave, two row chunks
+    [dict(n=300, q=100, m=120, r=2, rho=5, seed=8, bf16=False),    # 8-wave column and A_k U workgroups
+     dict(n=260, q=400, m=150, r=3, rho=4, seed=9, bf16=True, mixed=True),   # 4-wave column, 8-wave A_k U
+     dict(n=200, q=330, m=300, r=2, rho=3, seed=10, bf16=False),   # 8 waves (q <= 512), two row chunks
+     dict(n=150, q=560, m=90, r=2, rho=3, seed=13, bf16=False)],   # 4-wave column and A_k U
     [dict(n=12000, q=10, m=64, r=3, rho=20, seed=11, bf16=False),  # ~100 KiB of LDS per column workgroup
      dict(n=300, q=40, m=120, r=2, rho=5, seed=12, bf16=False)],   # in the same launch bucket
 ], ids=["mixed_sizes", "ranks_10_to_14", "column_widths", "large_n"])
